@@ -1,0 +1,176 @@
+/*
+ * oc.h -- C ABI of the MI355X overset connectivity library.
+ *
+ * The library computes the two data-parallel steps of overset domain
+ * connectivity for curved quadratic grids (Crabill, Witherden & Jameson,
+ * "A Parallel Direct Cut Algorithm for High-Order Overset Methods"):
+ *
+ *   hole cutting      Sec. 4.2 (Parallel Direct Cut) and Sec. 2.1 step 1:
+ *                     every element of a grid is classified against closed
+ *                     cutting surfaces as hole, fringe or field;
+ *   point connectivity Sec. 4.3 and Sec. 2.1 step 2: each receptor point is
+ *                     located in a donor element and its reference
+ *                     coordinates are found by Newton inversion of the
+ *                     isoparametric map (eq. reftophys, eq. ref-update).
+ *
+ * General rules
+ *   - Every function returns an oc_status (0 = OC_OK, < 0 = error) and never
+ *     aborts; oc_last_error() returns a thread-local message for the last
+ *     failure of the calling thread.
+ *   - Registration calls take HOST pointers; the library copies what it needs
+ *     to device memory and the caller keeps ownership of its arrays.
+ *   - Compute calls (oc_cut*, oc_fringe_points, oc_donor_search) take DEVICE
+ *     pointers for bulk inputs and outputs and are ordered on the context's
+ *     stream (oc_set_stream).  Poses are 12 host doubles
+ *     {R00,R01,R02,R10,R11,R12,R20,R21,R22,tx,ty,tz} applied as x' = R x + t.
+ *   - Results are deterministic: identical inputs give identical bits.
+ *   - Floating point: element/face/donor boxes, bins and the box filter are
+ *     FP32 with outward rounding (no true candidate is ever dropped); every
+ *     decision (intersection, side, containment) is taken in FP64.
+ *   - One context owns one device; a context is not thread safe.
+ */
+#ifndef OC_H
+#define OC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct oc_ctx oc_ctx;
+typedef int32_t oc_status;
+
+enum {
+    OC_OK = 0,
+    OC_EINVAL = -1,    /* bad handle, size, pointer or argument */
+    OC_ENOMEM = -2,    /* device or host allocation failed */
+    OC_EDEVICE = -3,   /* HIP runtime error */
+    OC_ENOTFOUND = -4, /* unknown grid / surface id */
+    OC_EBUDGET = -5,   /* the context's HBM budget would be exceeded */
+    OC_EGEOM = -6,     /* invalid geometry (open or inverted surface, inverted element) */
+    OC_ECAPACITY = -7  /* an output buffer is too small */
+};
+
+/* int8 blanking values (hole map values are not reused: hole 0, field 1,
+ * fringe -1; fringe = artificial-boundary element of Sec. 4.2) */
+enum { OC_HOLE = 0, OC_FIELD = 1, OC_FRINGE = -1 };
+
+/* Cutting-surface kinds (Sec. 3 and Sec. 4: near-body grids are cut by
+ * solid walls, off-body grids by overset boundaries).  Elements intersected
+ * by a WALL surface become holes; elements intersected by an OVERSET surface
+ * stay field (they are needed for overlap). */
+enum { OC_SURF_WALL = 0, OC_SURF_OVERSET = 1 };
+
+/* Per-element face tags, face order (-xi, +xi, -eta, +eta, -zeta, +zeta). */
+enum { OC_FACE_INTERIOR = 0, OC_FACE_WALL = 1, OC_FACE_OVERSET = 2, OC_FACE_FARFIELD = 3 };
+
+/* Fixed constants of the method (not configurable: results depend on them). */
+#define OC_TOL_HIT 1e-7      /* triangle pairs closer than this intersect (Alg. cp1/cp2) */
+#define OC_NEWTON_MAXIT 10   /* Newton iteration limit (Sec. 4.3) */
+#define OC_NEWTON_CLAMP 0.01 /* iterates clamped to [-1-c, 1+c] (Sec. 4.3) */
+#define OC_CONTAIN_TOL 1e-10 /* contained if max|xi| <= 1 + tol */
+
+typedef struct oc_config {
+    int32_t device;         /* HIP device ordinal */
+    int32_t surf_bins;      /* cut-surface bins per axis; 0 = automatic */
+    double donor_bin_scale; /* donor bin edge / mean element extent; 0 = 1 */
+    int64_t hbm_budget;     /* device bytes the context may hold; 0 = no limit */
+} oc_config;
+
+/* Statistics of the last oc_cut / oc_cut_multi call (host copy; the call
+ * synchronises the context stream). */
+typedef struct oc_cut_info {
+    int64_t n_elem;       /* elements classified */
+    int64_t n_inbox;      /* elements whose box meets a surface box */
+    int64_t n_near;       /* elements with at least one candidate face */
+    int64_t n_far;        /* in-box elements without candidates (ray parity) */
+    int64_t n_hit;        /* elements intersected by a surface */
+    int64_t n_hole;       /* hole elements */
+    int64_t n_cand_pairs; /* element x face pairs passing the FP32 box filter */
+} oc_cut_info;
+
+/* Create / destroy a context on cfg->device (cfg may be NULL: device 0,
+ * automatic bins, no budget).  *ctx receives an opaque handle. */
+oc_status oc_create(oc_ctx **ctx, const oc_config *cfg);
+oc_status oc_destroy(oc_ctx *ctx);
+const char *oc_last_error(void);
+
+/* Stream for all later compute calls (a hipStream_t; NULL = default stream). */
+oc_status oc_set_stream(oc_ctx *ctx, void *hip_stream);
+
+/* Register a grid of quadratic 27-node hexahedra (eq. reftophys with K = 2).
+ *   nodes     [n_nodes*3] FP64 xyz, host
+ *   conn      [n_elem*27] int32, lexicographic a+3b+9c over reference nodes
+ *             {-1,0,1}^3, host; every id in [0, n_nodes)
+ *   face_tags [n_elem*6] int8 OC_FACE_* or NULL (all interior/boundary)
+ * Face adjacency is derived from shared corner node ids.  The grid is fixed
+ * in its registration frame; motion is given per call by a pose.
+ * Errors: OC_EINVAL (sizes, ids), OC_EGEOM (non-positive Jacobian at an
+ * element centre), OC_ENOMEM / OC_EBUDGET. */
+oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, const int32_t *conn,
+                           int64_t n_elem, const int8_t *face_tags, int32_t *grid_id);
+
+/* Register a closed cutting surface of 9-node quadratic quads (Sec. 4.2:
+ * each face is split into 2x2 linear quads of two triangles each, along the
+ * diagonal from lattice node (m,n) to (m+1,n+1)).
+ *   nodes [n_nodes*3] FP64 host, conn [n_face*9] int32 host (a+3b),
+ *   outward normal = d/dxi x d/deta.
+ *   kind  OC_SURF_WALL or OC_SURF_OVERSET
+ * Errors: OC_EGEOM if the triangulation is not closed and consistently
+ * oriented or encloses a non-positive volume. */
+oc_status oc_register_cut_surface(oc_ctx *ctx, const double *nodes, int64_t n_nodes, const int32_t *conn,
+                                  int64_t n_face, int32_t kind, int32_t *surf_id);
+
+/* Direct cut of a grid by one posed surface (Sec. 4.2).  iblank_out: device
+ * int8 [n_elem] receiving OC_HOLE / OC_FIELD / OC_FRINGE.  An element is a
+ * hole if the surface (wall) intersects it -- some element/surface triangle
+ * pair closer than OC_TOL_HIT -- or if it lies inside the surface.  Fringe =
+ * field element sharing a face with a hole, or carrying an OVERSET face tag
+ * (artificial boundary of Sec. 4.2). */
+oc_status oc_cut(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pose[12], int8_t *iblank_out);
+
+/* Union of holes over n_surf posed surfaces (Sec. 4.2: union over cutting
+ * boundaries), then one fringe layer.  poses: n_surf*12 host doubles.
+ * n_surf = 0 gives the fringe layer of OVERSET-tagged faces only. */
+oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses,
+                       int32_t n_surf, int8_t *iblank_out);
+
+oc_status oc_last_cut_info(oc_ctx *ctx, oc_cut_info *info);
+
+/* Receptor points: 27 Gauss-Legendre points (3x3x3 tensor, order a+3b+9c)
+ * per FRINGE element of iblank, in ascending element id, mapped by
+ * eq. reftophys and posed by grid_pose into the world frame.
+ *   iblank      device int8 [n_elem]
+ *   points_out  device FP64 [cap*3] xyz
+ *   src_out     device int32 [cap] source element of each point (may be NULL)
+ *   n_out       host: number of points (27 * fringe elements)
+ * Synchronises the stream.  OC_ECAPACITY if cap is too small (n_out is set). */
+oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int8_t *iblank,
+                           double *points_out, int64_t cap, int64_t *n_out, int32_t *src_out);
+
+/* Donor search (Sec. 4.3).  points: device FP64 [n*3] world frame.  Each
+ * point is mapped into the donor grid's registration frame by the inverse
+ * of grid_pose, candidates are the elements whose Bernstein control-net box
+ * contains it, and Newton iterations from xi = 0 (at most OC_NEWTON_MAXIT,
+ * clamped to [-1-OC_NEWTON_CLAMP, 1+OC_NEWTON_CLAMP]) decide containment;
+ * the lowest-id containing element is the donor.
+ *   donor_out device int32 [n]   (-1 = orphan)
+ *   ref_out   device FP64 [n*3]  reference coordinates (NaN for orphans) */
+oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12], const double *points,
+                          int64_t n, int32_t *donor_out, double *ref_out);
+
+/* Per-kernel device timing with HIP events recorded on the context stream.
+ * oc_timing(ctx, 1) starts collecting (and clears), oc_timing(ctx, 0) stops.
+ * oc_timing_report writes a JSON object {"kernel": [total_ms, launches], ...}
+ * into buf (synchronises the stream). */
+oc_status oc_timing(oc_ctx *ctx, int32_t enable);
+oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len);
+
+/* Device bytes currently held by the context. */
+oc_status oc_memory_used(oc_ctx *ctx, int64_t *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OC_H */

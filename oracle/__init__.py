@@ -63,11 +63,13 @@ def lib():
         L.orc_newton.argtypes = [dp, dp, C.c_int, dp, C.POINTER(C.c_int)]
         L.orc_face_neighbors.restype = C.c_int
         L.orc_face_neighbors.argtypes = [ip, C.c_int64, ip]
+        L.orc_element_winding.restype = C.c_double
+        L.orc_element_winding.argtypes = [dp, ip, C.c_int64, dp]
         L.orc_element_tris.restype = None
         L.orc_element_tris.argtypes = [dp, ip, C.c_int64, dp]
         L.orc_cut_surface.restype = C.c_int
         L.orc_cut_surface.argtypes = [dp, ip, C.c_int64, i64p, C.c_int64, dp, C.c_int64, ip, C.c_int64,
-                                      dp, C.c_int, C.c_int, C.c_int, i8p, i8p, dp, i8p, dp]
+                                      dp, C.c_int, C.c_int, C.c_int, i8p, i8p, dp, i8p, dp, i8p]
         L.orc_fringe_points.restype = C.c_int
         L.orc_fringe_points.argtypes = [dp, ip, i64p, C.c_int64, dp, dp]
         L.orc_donor_search.restype = C.c_int
@@ -138,6 +140,13 @@ def element_tris(nodes, conn, e):
     return out.reshape(48, 3, 3)
 
 
+def element_winding(nodes, conn, e, p):
+    nodes = _f64(nodes)
+    conn = _i32(conn)
+    p = _f64(p).reshape(3)
+    return lib().orc_element_winding(_p(nodes, C.c_double), _p(conn, C.c_int32), int(e), _p(p, C.c_double))
+
+
 def face_neighbors(conn):
     conn = _i32(conn)
     n = conn.shape[0]
@@ -157,8 +166,10 @@ def cut_surface(grid, surf, pose=IDENTITY, kind=SURF_WALL, sel=None, brute=False
     """Per-surface status of the selected elements (0 hole / 1 field).
 
     With ``diagnostics`` also returns hit flags, the global nearest distance,
-    the nearest-face side (+1 outside / -1 inside) and the winding number at
-    each element's first node."""
+    the nearest-face side (+1 outside / -1 inside) from the element-surface
+    nearest triangle pair, the winding number at each element's first node
+    and the nearest-face side of that node (``psign``).  ``diagnostics`` may
+    be "point" to skip the element-pair search."""
     gn = _f64(grid.nodes)
     gc = _i32(grid.conn)
     sn = _f64(surf.nodes)
@@ -169,16 +180,18 @@ def cut_surface(grid, surf, pose=IDENTITY, kind=SURF_WALL, sel=None, brute=False
     n = gc.shape[0] if sel is None else sel.shape[0]
     status = np.empty(n, dtype=np.int8)
     hit = np.empty(n, dtype=np.int8)
-    dstar = np.empty(n) if diagnostics else None
-    nsign = np.empty(n, dtype=np.int8) if diagnostics else None
+    pair = diagnostics is True
+    dstar = np.empty(n) if pair else None
+    nsign = np.empty(n, dtype=np.int8) if pair else None
     wind = np.empty(n) if diagnostics else None
+    psign = np.empty(n, dtype=np.int8) if diagnostics else None
     lib().orc_cut_surface(_p(gn, C.c_double), _p(gc, C.c_int32), gc.shape[0], _p(sel, C.c_int64),
                           0 if sel is None else sel.shape[0], _p(sn, C.c_double), sn.shape[0],
                           _p(sc, C.c_int32), sc.shape[0], _p(pose, C.c_double), int(kind), int(bool(brute)),
                           int(threads), _p(status, C.c_int8), _p(hit, C.c_int8), _p(dstar, C.c_double),
-                          _p(nsign, C.c_int8), _p(wind, C.c_double))
+                          _p(nsign, C.c_int8), _p(wind, C.c_double), _p(psign, C.c_int8))
     if diagnostics:
-        return dict(status=status, hit=hit, dstar=dstar, nsign=nsign, wind=wind)
+        return dict(status=status, hit=hit, dstar=dstar, nsign=nsign, wind=wind, psign=psign)
     return status
 
 

@@ -832,6 +832,99 @@ static double winding(const surf_t *S, const double *p)
     return w / (4.0 * M_PI);
 }
 
+/* Nearest-face side of a point (the rule of Sec. 4.1 applied to the
+ * nearest surface point of one node): global nearest distance, then among
+ * the triangles within best*(1+1e-9) the largest |dot| of the unit
+ * point-to-surface vector with the outward normal decides; normals are
+ * averaged only when the two most visible disagree in sign. */
+static int point_side(const surf_t *S, const double *p, int brute, ivec *cand, ivec *stack, double *dout)
+{
+    double pb[6] = {p[0], p[1], p[2], p[0], p[1], p[2]};
+    double best = INFINITY;
+    if (brute) {
+        for (int64_t f = 0; f < S->n_face; ++f)
+            for (int t = 0; t < 8; ++t) {
+                const double *T = S->tris + 72 * f + 9 * t;
+                double q[3];
+                pt_tri(p, T, T + 3, T + 6, q);
+                best = fmin(best, sqrt(v_dist2(p, q)));
+            }
+    } else {
+        int leaf = bvh_greedy_leaf(&S->tree, pb);
+        const bnode *nd = &S->tree.node[leaf];
+        for (int k = 0; k < nd->count; ++k) {
+            int64_t f = S->tree.idx[nd->start + k];
+            for (int t = 0; t < 8; ++t) {
+                const double *T = S->tris + 72 * f + 9 * t;
+                double q[3];
+                pt_tri(p, T, T + 3, T + 6, q);
+                best = fmin(best, sqrt(v_dist2(p, q)));
+            }
+        }
+        bvh_near_box(&S->tree, pb, best, cand, stack);
+        for (int k = 0; k < cand->n; ++k)
+            for (int t = 0; t < 8; ++t) {
+                const double *T = S->tris + 72 * (int64_t)cand->v[k] + 9 * t;
+                if (box_dist(S->tbox + 48 * (int64_t)cand->v[k] + 6 * t, pb) > best) continue;
+                double q[3];
+                pt_tri(p, T, T + 3, T + 6, q);
+                best = fmin(best, sqrt(v_dist2(p, q)));
+            }
+    }
+    double thr = best * (1.0 + TIE_REL);
+    tie_rec b1, b2;
+    b1.valid = b2.valid = 0;
+    if (!brute) bvh_near_box(&S->tree, pb, thr, cand, stack);
+    int64_t nf = brute ? S->n_face : cand->n;
+    for (int64_t k = 0; k < nf; ++k) {
+        int64_t f = brute ? k : cand->v[k];
+        for (int t = 0; t < 8; ++t) {
+            const double *T = S->tris + 72 * f + 9 * t;
+            double q[3];
+            pt_tri(p, T, T + 3, T + 6, q);
+            double d = sqrt(v_dist2(p, q));
+            if (d > thr) continue;
+            tie_rec r;
+            v_sub(p, q, r.v);
+            v_copy(r.n, S->tnrm + 24 * f + 3 * t);
+            r.dot = d > 0.0 ? v_dot(r.v, r.n) / d : 0.0;
+            r.absdot = fabs(r.dot);
+            r.f = f;
+            r.s = t;
+            r.t = 0;
+            r.valid = 1;
+            tie_offer(&b1, &b2, &r);
+        }
+    }
+    double sgn = b1.dot;
+    if (b2.valid && b1.absdot - b2.absdot <= TIE_DOT && (b1.dot > 0.0) != (b2.dot > 0.0)) {
+        double nn[3] = {b1.n[0] + b2.n[0], b1.n[1] + b2.n[1], b1.n[2] + b2.n[2]};
+        sgn = v_dot(b1.v, nn);
+    }
+    if (dout) *dout = best;
+    return sgn < 0.0 ? -1 : 1;
+}
+
+/* Winding number of an element's closed boundary at p.  The face lattices
+ * of -xi, +eta and -zeta run clockwise seen from outside, so their
+ * triangles count with the opposite sign. */
+static double elem_winding(const double *et, const double *p)
+{
+    static const double face_sign[6] = {-1.0, 1.0, 1.0, -1.0, -1.0, 1.0};
+    double w = 0.0;
+    for (int t = 0; t < 48; ++t)
+        w += face_sign[t / 8] * orc_solid_angle(p, et + 9 * t, et + 9 * t + 3, et + 9 * t + 6);
+    return w / (4.0 * M_PI);
+}
+
+double orc_element_winding(const double *nodes, const int32_t *conn, int64_t e, const double *p)
+{
+    double X[81], et[48 * 9];
+    elem_nodes(nodes, conn, e, X);
+    tris_from_elem(X, et);
+    return elem_winding(et, p);
+}
+
 static int in_box(const double *b, const double *p)
 {
     return p[0] >= b[0] && p[1] >= b[1] && p[2] >= b[2] && p[0] <= b[3] && p[1] <= b[4] && p[2] <= b[5];
@@ -839,7 +932,7 @@ static int in_box(const double *b, const double *p)
 
 static void classify_one(const double *gnodes, const int32_t *gconn, int64_t e, const surf_t *S, int kind,
                          int brute, ivec *cand, ivec *stack, int8_t *status, int8_t *hit_out,
-                         double *dstar_out, int8_t *nsign_out, double *wind_out)
+                         double *dstar_out, int8_t *nsign_out, double *wind_out, int8_t *psign_out)
 {
     double X[81], et[48 * 9], ebox[48 * 6], box[6];
     elem_nodes(gnodes, gconn, e, X);
@@ -862,9 +955,7 @@ static void classify_one(const double *gnodes, const int32_t *gconn, int64_t e, 
     }
     /* surface enclosed by the element */
     if (!hit && (brute || in_box(box, S->first))) {
-        double w = 0.0;
-        for (int t = 0; t < 48; ++t) w += orc_solid_angle(S->first, et + 9 * t, et + 9 * t + 3, et + 9 * t + 6);
-        if (fabs(w / (4.0 * M_PI)) > 0.5) hit = 1;
+        if (fabs(elem_winding(et, S->first)) > 0.5) hit = 1;
     }
     /* winding number at the first node (zero outside the surface's box) */
     double w = 0.0;
@@ -915,6 +1006,8 @@ static void classify_one(const double *gnodes, const int32_t *gconn, int64_t e, 
         nsign = sgn < 0.0 ? -1 : 1;
     }
 
+    if (psign_out) *psign_out = hit ? 0 : (int8_t)point_side(S, X, brute, cand, stack, NULL);
+
     int hole;
     if (kind == 0) hole = hit || inside;  /* wall */
     else hole = inside && !hit;           /* overset */
@@ -928,7 +1021,7 @@ static void classify_one(const double *gnodes, const int32_t *gconn, int64_t e, 
 int orc_cut_surface(const double *gnodes, const int32_t *gconn, int64_t n_elem, const int64_t *sel,
                     int64_t n_sel, const double *snodes, int64_t n_snodes, const int32_t *sconn,
                     int64_t n_face, const double *pose, int kind, int brute, int n_threads, int8_t *status,
-                    int8_t *hit, double *dstar, int8_t *nsign, double *wind)
+                    int8_t *hit, double *dstar, int8_t *nsign, double *wind, int8_t *psign)
 {
     surf_t S;
     surf_build(&S, snodes, n_snodes, sconn, n_face, pose, !brute);
@@ -946,7 +1039,7 @@ int orc_cut_surface(const double *gnodes, const int32_t *gconn, int64_t n_elem, 
             int64_t e = sel ? sel[i] : i;
             classify_one(gnodes, gconn, e, &S, kind, brute, &cand, &stack, status ? status + i : NULL,
                          hit ? hit + i : NULL, dstar ? dstar + i : NULL, nsign ? nsign + i : NULL,
-                         wind ? wind + i : NULL);
+                         wind ? wind + i : NULL, psign ? psign + i : NULL);
         }
         free(cand.v);
         free(stack.v);

@@ -30,6 +30,8 @@ void orc_q2_eval(const double *X, const double *xi, double *x, double *J);
 int orc_newton(const double *X, const double *xp, int maxit, double *xi_out, int *iters_out);
 /* Face neighbours from shared corner ids: nbr[e*6+f] = element or -1. */
 int orc_face_neighbors(const int32_t *conn, int64_t n_elem, int32_t *nbr);
+/* Winding number of element e's closed boundary at point p. */
+double orc_element_winding(const double *nodes, const int32_t *conn, int64_t e, const double *p);
 /* The 48 boundary triangles of element e (48*9 doubles). */
 void orc_element_tris(const double *nodes, const int32_t *conn, int64_t e, double *tris);
 
@@ -40,12 +42,13 @@ void orc_element_tris(const double *nodes, const int32_t *conn, int64_t e, doubl
  *   hit     1 if the element intersects (or encloses) the surface
  *   dstar   global minimum element-surface distance (0 when hit)
  *   nsign   nearest-face side: +1 outside, -1 inside, 0 when hit
- *   wind    generalised winding number at the element's first node      */
+ *   wind    generalised winding number at the element's first node
+ *   psign   nearest-face side of the element's first node (0 when hit) */
 int orc_cut_surface(const double *gnodes, const int32_t *gconn, int64_t n_elem,
                     const int64_t *sel, int64_t n_sel,
                     const double *snodes, int64_t n_snodes, const int32_t *sconn, int64_t n_face,
                     const double *pose, int kind, int brute, int n_threads,
-                    int8_t *status, int8_t *hit, double *dstar, int8_t *nsign, double *wind);
+                    int8_t *status, int8_t *hit, double *dstar, int8_t *nsign, double *wind, int8_t *psign);
 
 /* 27 Gauss points per listed element, mapped and posed (n*27*3 doubles). */
 int orc_fringe_points(const double *gnodes, const int32_t *gconn, const int64_t *elems, int64_t n,

@@ -1,0 +1,140 @@
+// Device-wide exclusive prefix sum of int32 counts (reduce, scan of tile
+// sums, scan-and-apply).  The item count may live in device memory so the
+// scan can follow kernels whose output size is only known on the device.
+#include "dev_common.h"
+
+namespace oc {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+constexpr int kScanMaxTiles = 1024 * 64;
+
+__device__ inline int wave_incl_scan(int v)
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// exclusive scan of one value per thread over a block of kScanThreads
+__device__ inline int block_excl_scan(int v, int *total)
+{
+    __shared__ int wsum[kScanThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = wave_incl_scan(v);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t *__restrict__ in, const int *n_dev,
+                                                              int64_t n_host, int32_t *__restrict__ tsum)
+{
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int s = 0;
+    if (base < n) {
+#pragma unroll
+        for (int k = 0; k < kScanItems; ++k) {
+            int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+            if (i < n) s += in[i];
+        }
+    }
+    int tot;
+    (void)block_excl_scan(s, &tot);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of the tile sums in place, total at tsum[nt]
+__global__ __launch_bounds__(1024) void k_scan_tiles(int32_t *tsum, int nt)
+{
+    __shared__ int wsum[16];
+    const int per = (nt + 1023) / 1024;
+    const int lo = threadIdx.x * per;
+    int loc = 0;
+    for (int k = 0; k < per; ++k)
+        if (lo + k < nt) loc += tsum[lo + k];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = wave_incl_scan(loc);
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+    }
+    int run = off + inc - loc;
+    for (int k = 0; k < per; ++k)
+        if (lo + k < nt) {
+            int v = tsum[lo + k];
+            tsum[lo + k] = run;
+            run += v;
+        }
+    if (threadIdx.x == 0) tsum[nt] = tot;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *__restrict__ in,
+                                                             int32_t *__restrict__ out, const int *n_dev,
+                                                             int64_t n_host, const int32_t *__restrict__ tsum,
+                                                             int nt)
+{
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tsum[nt];
+    if (base >= n) return;
+    // each thread owns kScanItems consecutive items
+    int v[kScanItems];
+    int s = 0;
+    const int64_t my = base + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = my + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    int tot;
+    int run = block_excl_scan(s, &tot) + tsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = my + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+}
+
+int64_t scan_tmp_ints(int64_t cap) { return (cap + kScanTile - 1) / kScanTile + 1; }
+
+oc_status scan_exclusive(oc_ctx *ctx, const int32_t *in, int32_t *out, int64_t cap, const int *n_dev,
+                         int32_t *tmp)
+{
+    int64_t nt = (cap + kScanTile - 1) / kScanTile;
+    if (nt < 1) nt = 1;
+    if (nt > kScanMaxTiles) {
+        set_error("scan: too many items");
+        return OC_EINVAL;
+    }
+    size_t slot;
+    time_begin(ctx, "scan", &slot);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nt), dim3(kScanThreads), 0, ctx->stream, in, n_dev, cap, tmp);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, ctx->stream, tmp, (int)nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(kScanThreads), 0, ctx->stream, in, out, n_dev, cap,
+                       tmp, (int)nt);
+    time_end(ctx, slot);
+    OC_HIP(hipGetLastError());
+    return OC_OK;
+}
+
+}  // namespace oc

@@ -1,0 +1,541 @@
+// C ABI entry points, context, validation and registration.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <unordered_map>
+
+#include "dev_common.h"
+
+namespace oc {
+
+static thread_local std::string g_error;
+void set_error(const std::string &msg) { g_error = msg; }
+
+oc_status dev_alloc(oc_ctx *ctx, std::vector<DevBuf> &owner, size_t bytes, void **out)
+{
+    if (bytes == 0) bytes = 256;
+    if (ctx->budget > 0 && ctx->used + (int64_t)bytes > ctx->budget) {
+        set_error("HBM budget exceeded: " + std::to_string(ctx->used + bytes) + " > " + std::to_string(ctx->budget));
+        return OC_EBUDGET;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        return OC_ENOMEM;
+    }
+    owner.push_back(DevBuf{p, bytes});
+    ctx->used += (int64_t)bytes;
+    *out = p;
+    return OC_OK;
+}
+
+void dev_free_all(oc_ctx *ctx, std::vector<DevBuf> &owner)
+{
+    for (auto &b : owner) {
+        (void)hipFree(b.p);
+        ctx->used -= (int64_t)b.bytes;
+    }
+    owner.clear();
+}
+
+void time_begin(oc_ctx *ctx, const char *name, size_t *slot)
+{
+    *slot = std::numeric_limits<size_t>::max();
+    if (!ctx->timing) return;
+    while (ctx->event_pool.size() < ctx->event_next + 2) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) return;
+        ctx->event_pool.push_back(ev);
+    }
+    TimingRec r{ctx->event_pool[ctx->event_next], ctx->event_pool[ctx->event_next + 1], name};
+    ctx->event_next += 2;
+    (void)hipEventRecord(r.a, ctx->stream);
+    *slot = ctx->trecs.size();
+    ctx->trecs.push_back(r);
+}
+
+void time_end(oc_ctx *ctx, size_t slot)
+{
+    if (slot == std::numeric_limits<size_t>::max()) return;
+    (void)hipEventRecord(ctx->trecs[slot].b, ctx->stream);
+}
+
+static Pose to_pose(const double *p)
+{
+    Pose q;
+    for (int i = 0; i < 9; ++i) q.r[i] = p[i];
+    for (int i = 0; i < 3; ++i) q.t[i] = p[9 + i];
+    return q;
+}
+
+static bool pose_ok(const double *p)
+{
+    if (!p) return false;
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// face corner local indices, order -xi,+xi,-eta,+eta,-zeta,+zeta
+static const int kFaceCorners[6][4] = {{0, 6, 18, 24}, {2, 8, 20, 26}, {0, 2, 18, 20},
+                                       {6, 8, 24, 26}, {0, 2, 6, 8},   {18, 20, 24, 26}};
+
+// Face adjacency from shared corner ids: bucket every face by its smallest
+// corner id (counting sort), then match the remaining three ids inside a
+// bucket.  Returns false for a face shared by more than two elements.
+static bool face_neighbors(const int32_t *conn, int64_t n_elem, int64_t n_nodes, std::vector<int32_t> &nbr)
+{
+    const int64_t nf = n_elem * 6;
+    nbr.assign((size_t)nf, -1);
+    std::vector<std::array<int32_t, 4>> key((size_t)nf);
+    std::vector<int32_t> cnt((size_t)n_nodes + 1, 0);
+    for (int64_t e = 0; e < n_elem; ++e)
+        for (int f = 0; f < 6; ++f) {
+            std::array<int32_t, 4> k;
+            for (int i = 0; i < 4; ++i) k[i] = conn[e * 27 + kFaceCorners[f][i]];
+            std::sort(k.begin(), k.end());
+            key[(size_t)(e * 6 + f)] = k;
+            cnt[(size_t)k[0] + 1]++;
+        }
+    for (int64_t i = 0; i < n_nodes; ++i) cnt[(size_t)i + 1] += cnt[(size_t)i];
+    std::vector<int32_t> order((size_t)nf);
+    {
+        std::vector<int32_t> cur(cnt.begin(), cnt.end() - 1);
+        for (int64_t i = 0; i < nf; ++i) order[(size_t)cur[(size_t)key[(size_t)i][0]]++] = (int32_t)i;
+    }
+    for (int64_t v = 0; v < n_nodes; ++v) {
+        const int32_t b0 = cnt[(size_t)v], b1 = cnt[(size_t)v + 1];
+        for (int32_t i = b0; i < b1; ++i) {
+            const int32_t fi = order[(size_t)i];
+            for (int32_t j = i + 1; j < b1; ++j) {
+                const int32_t fj = order[(size_t)j];
+                if (key[(size_t)fi] != key[(size_t)fj]) continue;
+                if (nbr[(size_t)fi] >= 0 || nbr[(size_t)fj] >= 0) return false;
+                nbr[(size_t)fi] = fj / 6;
+                nbr[(size_t)fj] = fi / 6;
+            }
+        }
+    }
+    return true;
+}
+
+template <class T>
+static oc_status upload(oc_ctx *ctx, std::vector<DevBuf> &owner, const T *src, size_t n, T **dst)
+{
+    OC_TRY(dev_alloc(ctx, owner, sizeof(T) * std::max<size_t>(n, 1), (void **)dst));
+    if (n) OC_HIP(hipMemcpy(*dst, src, sizeof(T) * n, hipMemcpyHostToDevice));
+    return OC_OK;
+}
+
+}  // namespace oc
+
+using namespace oc;
+
+extern "C" {
+
+const char *oc_last_error(void) { return g_error.c_str(); }
+
+oc_status oc_create(oc_ctx **out, const oc_config *cfg)
+{
+    if (!out) {
+        set_error("oc_create: null output");
+        return OC_EINVAL;
+    }
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        set_error("oc_create: no HIP device");
+        return OC_EDEVICE;
+    }
+    oc_ctx *ctx = new oc_ctx();
+    if (cfg) {
+        ctx->device = cfg->device;
+        ctx->surf_bins = cfg->surf_bins;
+        ctx->donor_bin_scale = cfg->donor_bin_scale > 0 ? cfg->donor_bin_scale : 1.0;
+        ctx->budget = cfg->hbm_budget;
+    }
+    if (ctx->device < 0 || ctx->device >= ndev || hipSetDevice(ctx->device) != hipSuccess) {
+        delete ctx;
+        set_error("oc_create: invalid device");
+        return OC_EINVAL;
+    }
+    if (hipMalloc(&ctx->counters, sizeof(CutCounters)) != hipSuccess ||
+        hipMalloc(&ctx->dev_scalar, 64) != hipSuccess) {
+        delete ctx;
+        set_error("oc_create: allocation failed");
+        return OC_ENOMEM;
+    }
+    (void)hipMemset(ctx->counters, 0, sizeof(CutCounters));
+    *out = ctx;
+    return OC_OK;
+}
+
+oc_status oc_destroy(oc_ctx *ctx)
+{
+    if (!ctx) return OC_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &g : ctx->grids)
+        if (g) dev_free_all(ctx, g->owned);
+    for (auto &s : ctx->surfs)
+        if (s) dev_free_all(ctx, s->owned);
+    (void)hipFree(ctx->counters);
+    (void)hipFree(ctx->dev_scalar);
+    for (auto ev : ctx->event_pool) (void)hipEventDestroy(ev);
+    delete ctx;
+    return OC_OK;
+}
+
+oc_status oc_set_stream(oc_ctx *ctx, void *stream)
+{
+    if (!ctx) {
+        set_error("oc_set_stream: null context");
+        return OC_EINVAL;
+    }
+    ctx->stream = (hipStream_t)stream;
+    return OC_OK;
+}
+
+oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, const int32_t *conn, int64_t n_elem,
+                           const int8_t *face_tags, int32_t *grid_id)
+{
+    if (!ctx || !nodes || !conn || !grid_id || n_nodes <= 0 || n_elem <= 0 || n_elem > (1ll << 31) / 32 ||
+        n_nodes >= (1ll << 31)) {
+        set_error("oc_register_grid: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    for (int64_t i = 0; i < n_elem * 27; ++i)
+        if (conn[i] < 0 || conn[i] >= n_nodes) {
+            set_error("oc_register_grid: node id out of range at conn[" + std::to_string(i) + "]");
+            return OC_EINVAL;
+        }
+    for (int64_t i = 0; i < n_nodes * 3; ++i)
+        if (!std::isfinite(nodes[i])) {
+            set_error("oc_register_grid: non-finite node coordinate");
+            return OC_EINVAL;
+        }
+    std::vector<int32_t> nbr;
+    if (!face_neighbors(conn, n_elem, n_nodes, nbr)) {
+        set_error("oc_register_grid: a face is shared by more than two elements");
+        return OC_EGEOM;
+    }
+    std::vector<int32_t> overset;
+    if (face_tags)
+        for (int64_t e = 0; e < n_elem; ++e)
+            for (int f = 0; f < 6; ++f)
+                if (face_tags[e * 6 + f] == OC_FACE_OVERSET) {
+                    overset.push_back((int32_t)e);
+                    break;
+                }
+
+    auto g = std::make_unique<Grid>();
+    g->n_elem = n_elem;
+    g->n_nodes = n_nodes;
+    g->ebox_stride = (n_elem + 63) / 64 * 64;
+    oc_status st = OC_OK;
+    double *nodes_dev = nullptr;
+    int32_t *conn_dev = nullptr;
+    std::vector<DevBuf> tmp;
+    auto fail = [&](oc_status s) {
+        dev_free_all(ctx, tmp);
+        dev_free_all(ctx, g->owned);
+        return s;
+    };
+    if ((st = upload(ctx, tmp, nodes, (size_t)n_nodes * 3, &nodes_dev)) != OC_OK) return fail(st);
+    if ((st = upload(ctx, tmp, conn, (size_t)n_elem * 27, &conn_dev)) != OC_OK) return fail(st);
+    const size_t ne = (size_t)n_elem;
+    if ((st = dev_alloc(ctx, g->owned, sizeof(double) * ne * 81, (void **)&g->enodes)) != OC_OK) return fail(st);
+    if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 6 * (size_t)g->ebox_stride, (void **)&g->ebox)) != OC_OK)
+        return fail(st);
+    if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 6 * ne, (void **)&g->cbox)) != OC_OK) return fail(st);
+    if ((st = dev_alloc(ctx, g->owned, sizeof(double) * ne, (void **)&g->ediam)) != OC_OK) return fail(st);
+    if ((st = upload(ctx, g->owned, nbr.data(), nbr.size(), &g->nbr)) != OC_OK) return fail(st);
+    g->n_overset = (int64_t)overset.size();
+    if ((st = upload(ctx, g->owned, overset.data(), overset.size(), &g->overset)) != OC_OK) return fail(st);
+    int32_t **lists[5] = {&g->list_inbox, &g->list_near, &g->list_far, &g->list_hole, &g->list_fringe};
+    for (auto l : lists)
+        if ((st = dev_alloc(ctx, g->owned, sizeof(int32_t) * ne, (void **)l)) != OC_OK) return fail(st);
+    g->n_fr_blocks = (n_elem + 4095) / 4096;
+    if ((st = dev_alloc(ctx, g->owned, sizeof(int32_t) * (2 * (g->n_fr_blocks + 1) + scan_tmp_ints(g->n_fr_blocks) + 8),
+                        (void **)&g->fr_blocksum)) != OC_OK)
+        return fail(st);
+    if ((st = grid_build_device(ctx, *g, conn_dev, nodes_dev)) != OC_OK) return fail(st);
+    dev_free_all(ctx, tmp);
+    if ((st = grid_build_donor_bins(ctx, *g)) != OC_OK) return fail(st);
+    ctx->grids.push_back(std::move(g));
+    *grid_id = (int32_t)ctx->grids.size() - 1;
+    return OC_OK;
+}
+
+oc_status oc_register_cut_surface(oc_ctx *ctx, const double *nodes, int64_t n_nodes, const int32_t *conn,
+                                  int64_t n_face, int32_t kind, int32_t *surf_id)
+{
+    if (!ctx || !nodes || !conn || !surf_id || n_nodes <= 0 || n_face <= 0 || n_face > (1ll << 26) ||
+        n_nodes >= (1ll << 31) || (kind != OC_SURF_WALL && kind != OC_SURF_OVERSET)) {
+        set_error("oc_register_cut_surface: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    for (int64_t i = 0; i < n_face * 9; ++i)
+        if (conn[i] < 0 || conn[i] >= n_nodes) {
+            set_error("oc_register_cut_surface: node id out of range");
+            return OC_EINVAL;
+        }
+    for (int64_t i = 0; i < n_nodes * 3; ++i)
+        if (!std::isfinite(nodes[i])) {
+            set_error("oc_register_cut_surface: non-finite node coordinate");
+            return OC_EINVAL;
+        }
+    // closed and consistently oriented: every directed boundary segment of a
+    // face lattice appears once, and its reverse once
+    static const int loop[9] = {0, 1, 2, 5, 8, 7, 6, 3, 0};
+    std::unordered_map<uint64_t, int> seg;
+    seg.reserve((size_t)n_face * 16);
+    for (int64_t f = 0; f < n_face; ++f)
+        for (int k = 0; k < 8; ++k) {
+            uint32_t a = (uint32_t)conn[f * 9 + loop[k]], b = (uint32_t)conn[f * 9 + loop[k + 1]];
+            if (a == b) {
+                set_error("oc_register_cut_surface: degenerate face edge");
+                return OC_EGEOM;
+            }
+            seg[((uint64_t)a << 32) | b]++;
+        }
+    for (auto &kv : seg) {
+        uint64_t rev = (kv.first << 32) | (kv.first >> 32);
+        auto it = seg.find(rev);
+        if (kv.second != 1 || it == seg.end() || it->second != 1) {
+            set_error("oc_register_cut_surface: surface is not closed and consistently oriented");
+            return OC_EGEOM;
+        }
+    }
+    // enclosed volume (divergence theorem on the triangulation) and face size
+    double vol = 0.0, dmax = 0.0;
+    double c[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n_nodes; ++i)
+        for (int d = 0; d < 3; ++d) c[d] += nodes[3 * i + d] / (double)n_nodes;
+    double rb = 0.0;
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) s += (nodes[3 * i + d] - c[d]) * (nodes[3 * i + d] - c[d]);
+        rb = std::max(rb, std::sqrt(s));
+    }
+    static const int tri[8][3] = {{0, 1, 4}, {0, 4, 3}, {1, 2, 5}, {1, 5, 4}, {3, 4, 7}, {3, 7, 6}, {4, 5, 8}, {4, 8, 7}};
+    for (int64_t f = 0; f < n_face; ++f) {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int k = 0; k < 9; ++k)
+            for (int d = 0; d < 3; ++d) {
+                double v = nodes[3 * (int64_t)conn[f * 9 + k] + d];
+                lo[d] = std::min(lo[d], v);
+                hi[d] = std::max(hi[d], v);
+            }
+        dmax = std::max(dmax, std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                        (hi[2] - lo[2]) * (hi[2] - lo[2])));
+        for (auto &t : tri) {
+            const double *A = nodes + 3 * (int64_t)conn[f * 9 + t[0]];
+            const double *B = nodes + 3 * (int64_t)conn[f * 9 + t[1]];
+            const double *C = nodes + 3 * (int64_t)conn[f * 9 + t[2]];
+            vol += (A[0] * (B[1] * C[2] - B[2] * C[1]) - A[1] * (B[0] * C[2] - B[2] * C[0]) +
+                    A[2] * (B[0] * C[1] - B[1] * C[0])) / 6.0;
+        }
+    }
+    if (!(vol > 0.0)) {
+        set_error("oc_register_cut_surface: enclosed volume is not positive (inward orientation?)");
+        return OC_EGEOM;
+    }
+    auto s = std::make_unique<Surf>();
+    s->n_face = n_face;
+    s->n_nodes = n_nodes;
+    s->kind = kind;
+    s->dmax = f32_up(dmax);
+    int nb = (int)std::ceil(2.0 * rb / std::max(dmax, 1e-30)) + 1;
+    nb = std::max(1, std::min(nb, 160));
+    if (ctx->surf_bins > 0) nb = std::min(nb, ctx->surf_bins);
+    s->nb_max = nb;
+    for (int d = 0; d < 3; ++d) s->first[d] = nodes[d];
+    std::vector<double> soa((size_t)n_nodes * 3);
+    for (int64_t i = 0; i < n_nodes; ++i)
+        for (int d = 0; d < 3; ++d) soa[(size_t)(d * n_nodes + i)] = nodes[3 * i + d];
+    oc_status st = OC_OK;
+    auto fail = [&](oc_status e) {
+        dev_free_all(ctx, s->owned);
+        return e;
+    };
+    const int64_t bcap = (int64_t)nb * nb * nb + 1;
+    if ((st = upload(ctx, s->owned, soa.data(), soa.size(), &s->nodes)) != OC_OK) return fail(st);
+    if ((st = upload(ctx, s->owned, conn, (size_t)n_face * 9, &s->conn)) != OC_OK) return fail(st);
+    if ((st = dev_alloc(ctx, s->owned, sizeof(double) * 27 * n_face, (void **)&s->pnodes)) != OC_OK) return fail(st);
+    if ((st = dev_alloc(ctx, s->owned, sizeof(float) * 6 * n_face, (void **)&s->fbox)) != OC_OK) return fail(st);
+    if ((st = dev_alloc(ctx, s->owned, sizeof(int32_t) * bcap, (void **)&s->bin_count)) != OC_OK) return fail(st);
+    if ((st = dev_alloc(ctx, s->owned, sizeof(int32_t) * bcap, (void **)&s->bin_start)) != OC_OK) return fail(st);
+    if ((st = dev_alloc(ctx, s->owned, sizeof(int32_t) * 8 * n_face, (void **)&s->bin_items)) != OC_OK)
+        return fail(st);
+    if ((st = dev_alloc(ctx, s->owned, sizeof(int32_t) * scan_tmp_ints(bcap), (void **)&s->scan_tmp)) != OC_OK)
+        return fail(st);
+    if ((st = dev_alloc(ctx, s->owned, sizeof(SurfParams), (void **)&s->params)) != OC_OK) return fail(st);
+    OC_HIP(hipMemset(s->bin_count, 0, sizeof(int32_t) * bcap));
+    ctx->surfs.push_back(std::move(s));
+    *surf_id = (int32_t)ctx->surfs.size() - 1;
+    return OC_OK;
+}
+
+static oc_status get_grid(oc_ctx *ctx, int32_t id, Grid **g)
+{
+    if (id < 0 || id >= (int32_t)ctx->grids.size() || !ctx->grids[id]) {
+        set_error("unknown grid id " + std::to_string(id));
+        return OC_ENOTFOUND;
+    }
+    *g = ctx->grids[id].get();
+    return OC_OK;
+}
+
+oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
+                       int8_t *iblank_out)
+{
+    if (!ctx || !iblank_out || n_surf < 0 || (n_surf > 0 && (!surf_ids || !poses))) {
+        set_error("oc_cut: invalid arguments");
+        return OC_EINVAL;
+    }
+    if (((uintptr_t)iblank_out & 3) != 0) {
+        set_error("oc_cut: iblank_out must be 4-byte aligned");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    std::vector<Pose> ps;
+    for (int k = 0; k < n_surf; ++k) {
+        if (surf_ids[k] < 0 || surf_ids[k] >= (int32_t)ctx->surfs.size() || !ctx->surfs[surf_ids[k]]) {
+            set_error("unknown surface id " + std::to_string(surf_ids[k]));
+            return OC_ENOTFOUND;
+        }
+        if (!pose_ok(poses + 12 * k)) {
+            set_error("oc_cut: non-finite pose");
+            return OC_EINVAL;
+        }
+        ss.push_back(ctx->surfs[surf_ids[k]].get());
+        ps.push_back(to_pose(poses + 12 * k));
+    }
+    ctx->last_n_elem = g->n_elem;
+    return cut_run(ctx, *g, ss.data(), ps.data(), n_surf, iblank_out);
+}
+
+oc_status oc_cut(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pose[12], int8_t *iblank_out)
+{
+    return oc_cut_multi(ctx, grid_id, &surf_id, pose, 1, iblank_out);
+}
+
+oc_status oc_last_cut_info(oc_ctx *ctx, oc_cut_info *info)
+{
+    if (!ctx || !info) {
+        set_error("oc_last_cut_info: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    CutCounters c;
+    OC_HIP(hipMemcpyAsync(&c, ctx->counters, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
+    OC_HIP(hipStreamSynchronize(ctx->stream));
+    info->n_elem = ctx->last_n_elem;
+    info->n_inbox = c.n_inbox;
+    info->n_near = c.n_near;
+    info->n_far = c.n_far;
+    info->n_hit = c.n_hit;
+    info->n_hole = c.n_hole;
+    info->n_cand_pairs = (int64_t)c.n_cand_pairs;
+    return OC_OK;
+}
+
+oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int8_t *iblank,
+                           double *points_out, int64_t cap, int64_t *n_out, int32_t *src_out)
+{
+    if (!ctx || !iblank || !n_out || cap < 0 || (cap > 0 && !points_out) || !pose_ok(grid_pose)) {
+        set_error("oc_fringe_points: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    return fringe_points_run(ctx, *g, to_pose(grid_pose), iblank, points_out, cap, n_out, src_out);
+}
+
+oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12], const double *points,
+                          int64_t n, int32_t *donor_out, double *ref_out)
+{
+    if (!ctx || n < 0 || (n > 0 && (!points || !donor_out || !ref_out)) || !pose_ok(grid_pose)) {
+        set_error("oc_donor_search: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, donor_grid_id, &g));
+    return donor_run(ctx, *g, to_pose(grid_pose), points, n, donor_out, ref_out);
+}
+
+oc_status oc_timing(oc_ctx *ctx, int32_t enable)
+{
+    if (!ctx) {
+        set_error("oc_timing: null context");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->timing = enable != 0;
+    ctx->trecs.clear();
+    ctx->event_next = 0;
+    return OC_OK;
+}
+
+oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len)
+{
+    if (!ctx || !buf || buf_len <= 0) {
+        set_error("oc_timing_report: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipStreamSynchronize(ctx->stream));
+    std::map<std::string, std::pair<double, int>> acc;
+    for (auto &r : ctx->trecs) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+            (void)hipGetLastError();
+            continue;
+        }
+        auto &a = acc[r.name];
+        a.first += ms;
+        a.second += 1;
+    }
+    std::string js = "{";
+    bool firstk = true;
+    for (auto &kv : acc) {
+        char tmp[256];
+        snprintf(tmp, sizeof tmp, "%s\"%s\": [%.9g, %d]", firstk ? "" : ", ", kv.first.c_str(), kv.second.first,
+                 kv.second.second);
+        js += tmp;
+        firstk = false;
+    }
+    js += "}";
+    if ((int64_t)js.size() + 1 > buf_len) {
+        set_error("oc_timing_report: buffer too small");
+        return OC_ECAPACITY;
+    }
+    memcpy(buf, js.c_str(), js.size() + 1);
+    ctx->trecs.clear();
+    ctx->event_next = 0;
+    return OC_OK;
+}
+
+oc_status oc_memory_used(oc_ctx *ctx, int64_t *bytes)
+{
+    if (!ctx || !bytes) {
+        set_error("oc_memory_used: invalid arguments");
+        return OC_EINVAL;
+    }
+    *bytes = ctx->used;
+    return OC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/oc.h"
+
+namespace oc {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string &msg);
+#define OC_HIP(call)                                                                             \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) {                                                                  \
+            ::oc::set_error(std::string(#call) + ": " + hipGetErrorString(e_));                  \
+            return OC_EDEVICE;                                                                   \
+        }                                                                                        \
+    } while (0)
+#define OC_TRY(call)                                                                             \
+    do {                                                                                         \
+        oc_status s_ = (call);                                                                   \
+        if (s_ != OC_OK) return s_;                                                              \
+    } while (0)
+
+// ------------------------------------------------------------- bin grids --
+// Uniform bins over a box: bin index of coordinate v along an axis is
+// clamp(floor((v - o) * inv), 0, n - 1), evaluated in FP32.  The function is
+// monotone in v, so a box [lo, hi] inserted into bins [bin(lo), bin(hi)] is
+// found from any query box that overlaps it.
+struct BinGrid {
+    float o[3];
+    float inv[3];
+    int n[3];
+    int pad;
+};
+
+// Per-cut device state of a cutting surface.
+struct SurfParams {
+    int sbox_ord[6];   // surface box as order-preserving ints (atomic min/max)
+    float sbox[6];     // surface box (lo xyz, hi xyz), FP32, outward
+    BinGrid grid;      // bins over the surface box
+    int n_bins;        // grid.n[0]*n[1]*n[2]
+    int pad[3];
+};
+
+// Per-cut counters (device).
+struct CutCounters {
+    int n_inbox, n_near, n_far, n_hit, n_hole, pad0;
+    unsigned long long n_cand_pairs;
+};
+
+// -------------------------------------------------------- device buffers --
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Grid {
+    int64_t n_elem = 0, n_nodes = 0;
+    double *enodes = nullptr;   // [n_elem][81]: x[27], y[27], z[27]
+    float *ebox = nullptr;      // [6][ebox_stride] SoA: xlo ylo zlo xhi yhi zhi (outward FP32)
+    int64_t ebox_stride = 0;    // plane stride, n_elem rounded up to 64
+    int32_t *nbr = nullptr;     // [n_elem][6], -1 = boundary
+    int32_t *overset = nullptr; // elements with an OVERSET-tagged face (ascending)
+    int64_t n_overset = 0;
+    // donor search structure (registration frame)
+    float *cbox = nullptr;      // [n_elem][6] control-net boxes, outward FP32
+    double *ediam = nullptr;    // [n_elem] node-box diagonal
+    BinGrid dgrid{};
+    int32_t *dbin_start = nullptr; // [n_dbins + 1]
+    int32_t *dbin_items = nullptr; // element ids, ascending within a bin
+    int64_t n_dbins = 0, n_ditems = 0;
+    // workspace of cuts on this grid
+    int32_t *list_inbox = nullptr, *list_near = nullptr, *list_far = nullptr, *list_hole = nullptr;
+    int32_t *list_fringe = nullptr;
+    int32_t *fr_blocksum = nullptr;  // fringe compaction block sums
+    int64_t n_fr_blocks = 0;
+    std::vector<DevBuf> owned;
+};
+
+struct Surf {
+    int64_t n_face = 0, n_nodes = 0;
+    int kind = OC_SURF_WALL;
+    int nb_max = 4;
+    float dmax = 0.f;            // largest face-box diagonal (pose invariant bound)
+    double *nodes = nullptr;     // [3][n_nodes] SoA registration frame
+    int32_t *conn = nullptr;     // [n_face][9]
+    double first[3] = {0, 0, 0}; // first node (registration frame)
+    // per-cut workspace
+    double *pnodes = nullptr;    // [n_face][27]: x[9], y[9], z[9] posed
+    float *fbox = nullptr;       // [n_face][6] inflated outward FP32 boxes
+    int32_t *bin_count = nullptr;  // [nb_max^3 + 1]
+    int32_t *bin_start = nullptr;  // [nb_max^3 + 1]
+    int32_t *bin_items = nullptr;  // [8 * n_face]
+    int32_t *scan_tmp = nullptr;
+    SurfParams *params = nullptr;
+    std::vector<DevBuf> owned;
+};
+
+// Pose passed by value to kernels.
+struct Pose {
+    double r[9];
+    double t[3];
+};
+
+struct TimingRec {
+    hipEvent_t a, b;
+    const char *name;
+};
+
+}  // namespace oc
+
+struct oc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int surf_bins = 0;
+    double donor_bin_scale = 1.0;
+    int64_t budget = 0;
+    int64_t used = 0;
+    std::vector<std::unique_ptr<oc::Grid>> grids;
+    std::vector<std::unique_ptr<oc::Surf>> surfs;
+    oc::CutCounters *counters = nullptr;  // device
+    oc::CutCounters last{};
+    int64_t last_n_elem = 0;
+    int32_t *dev_scalar = nullptr;        // device scratch int (fringe count)
+    // timing
+    bool timing = false;
+    std::vector<oc::TimingRec> trecs;
+    std::vector<hipEvent_t> event_pool;
+    size_t event_next = 0;
+};
+
+namespace oc {
+
+oc_status dev_alloc(oc_ctx *ctx, std::vector<DevBuf> &owner, size_t bytes, void **out);
+void dev_free_all(oc_ctx *ctx, std::vector<DevBuf> &owner);
+
+// Launch bracketing for per-kernel timing.
+void time_begin(oc_ctx *ctx, const char *name, size_t *slot);
+void time_end(oc_ctx *ctx, size_t slot);
+
+// exclusive scan of n (device count n_dev if non-null, else n_host) int32
+// values; out[n] receives the total.  tmp must hold scan_tmp_ints(cap) ints.
+int64_t scan_tmp_ints(int64_t cap);
+oc_status scan_exclusive(oc_ctx *ctx, const int32_t *in, int32_t *out, int64_t cap, const int *n_dev,
+                         int32_t *tmp);
+
+// registration-time device work
+oc_status grid_build_device(oc_ctx *ctx, Grid &g, const int32_t *conn_dev, const double *nodes_dev);
+oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g);
+
+// cut pipeline
+oc_status cut_run(oc_ctx *ctx, Grid &g, Surf **surfs, const Pose *poses, int n_surf, int8_t *iblank);
+oc_status fringe_points_run(oc_ctx *ctx, Grid &g, const Pose &pose, const int8_t *iblank, double *pts,
+                            int64_t cap, int64_t *n_out, int32_t *src);
+oc_status donor_run(oc_ctx *ctx, Grid &g, const Pose &pose, const double *pts, int64_t n, int32_t *donor,
+                    double *ref);
+
+}  // namespace oc

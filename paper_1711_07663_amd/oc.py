@@ -1,0 +1,214 @@
+"""ctypes binding of the C ABI declared in include/oc.h.
+
+Argument marshalling only: every step of the method runs in the HIP library
+``liboc.so``.  Bulk inputs/outputs of compute calls are device tensors
+(PyTorch is used for device memory and streams); registration takes host
+arrays.  There is no CPU fallback: importing this module without the built
+library raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboc.so")
+
+OC_OK, OC_EINVAL, OC_ENOMEM, OC_EDEVICE, OC_ENOTFOUND, OC_EBUDGET, OC_EGEOM, OC_ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
+OC_HOLE, OC_FIELD, OC_FRINGE = 0, 1, -1
+OC_SURF_WALL, OC_SURF_OVERSET = 0, 1
+OC_FACE_INTERIOR, OC_FACE_WALL, OC_FACE_OVERSET, OC_FACE_FARFIELD = 0, 1, 2, 3
+
+EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_register_grid",
+           "oc_register_cut_surface", "oc_cut", "oc_cut_multi", "oc_last_cut_info", "oc_fringe_points",
+           "oc_donor_search", "oc_timing", "oc_timing_report", "oc_memory_used"]
+
+
+class OcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("oc status %d: %s" % (status, msg))
+        self.status = status
+
+
+class oc_config(C.Structure):
+    _fields_ = [("device", C.c_int32), ("surf_bins", C.c_int32), ("donor_bin_scale", C.c_double),
+                ("hbm_budget", C.c_int64)]
+
+
+class oc_cut_info(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_elem", "n_inbox", "n_near", "n_far", "n_hit", "n_hole",
+                                         "n_cand_pairs")]
+
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load liboc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("HIP library %s is missing: build it with paper_1711_07663_amd/build.py "
+                          "(no CPU fallback exists)" % path)
+    L = C.CDLL(path)
+    vp, dp, i32p, i8p, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int32), C.c_void_p, C.POINTER(C.c_int64)
+    sig = {
+        "oc_create": ([C.POINTER(C.c_void_p), C.POINTER(oc_config)]),
+        "oc_destroy": ([vp]),
+        "oc_set_stream": ([vp, vp]),
+        "oc_register_grid": ([vp, dp, C.c_int64, i32p, C.c_int64, C.POINTER(C.c_int8), i32p]),
+        "oc_register_cut_surface": ([vp, dp, C.c_int64, i32p, C.c_int64, C.c_int32, i32p]),
+        "oc_cut": ([vp, C.c_int32, C.c_int32, dp, vp]),
+        "oc_cut_multi": ([vp, C.c_int32, i32p, dp, C.c_int32, vp]),
+        "oc_last_cut_info": ([vp, C.POINTER(oc_cut_info)]),
+        "oc_fringe_points": ([vp, C.c_int32, dp, vp, vp, C.c_int64, i64p, vp]),
+        "oc_donor_search": ([vp, C.c_int32, dp, vp, C.c_int64, vp, vp]),
+        "oc_timing": ([vp, C.c_int32]),
+        "oc_timing_report": ([vp, C.c_char_p, C.c_int64]),
+        "oc_memory_used": ([vp, i64p]),
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int32
+    L.oc_last_error.argtypes = []
+    L.oc_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st):
+    if st != OC_OK:
+        raise OcError(st, load().oc_last_error().decode())
+
+
+def _pose(p):
+    a = np.ascontiguousarray(p, dtype=np.float64).reshape(-1)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _dptr(t, dtype, n=None):
+    """Device pointer of a contiguous CUDA tensor of the given dtype."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous() or t.dtype != dtype:
+        raise TypeError("expected a contiguous %s CUDA tensor" % dtype)
+    if n is not None and t.numel() < n:
+        raise ValueError("tensor too small: %d < %d" % (t.numel(), n))
+    return C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns one oc_ctx on one device; all compute calls run on ``stream``
+    (torch's current stream of that device when not given)."""
+
+    def __init__(self, device=0, surf_bins=0, donor_bin_scale=0.0, hbm_budget=0, stream=None):
+        L = load()
+        cfg = oc_config(device, surf_bins, donor_bin_scale, hbm_budget)
+        h = C.c_void_p()
+        _check(L.oc_create(C.byref(h), C.byref(cfg)))
+        self._h = h
+        self.device = device
+        self.grids = {}
+        self.surfs = {}
+        self.set_stream(stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().oc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        self.stream = stream
+        _check(load().oc_set_stream(self._h, C.c_void_p(handle)))
+
+    # -------------------------------------------------------- registration --
+    def register_grid(self, nodes, conn, face_tags=None):
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        tags_p = None
+        if face_tags is not None:
+            face_tags = np.ascontiguousarray(face_tags, dtype=np.int8)
+            tags_p = face_tags.ctypes.data_as(C.POINTER(C.c_int8))
+        gid = C.c_int32(-1)
+        _check(load().oc_register_grid(self._h, nodes.ctypes.data_as(C.POINTER(C.c_double)), nodes.shape[0],
+                                       conn.ctypes.data_as(C.POINTER(C.c_int32)), conn.shape[0], tags_p,
+                                       C.byref(gid)))
+        self.grids[gid.value] = int(conn.shape[0])
+        return gid.value
+
+    def register_cut_surface(self, nodes, conn, kind=OC_SURF_WALL):
+        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        sid = C.c_int32(-1)
+        _check(load().oc_register_cut_surface(self._h, nodes.ctypes.data_as(C.POINTER(C.c_double)), nodes.shape[0],
+                                              conn.ctypes.data_as(C.POINTER(C.c_int32)), conn.shape[0], int(kind),
+                                              C.byref(sid)))
+        self.surfs[sid.value] = int(conn.shape[0])
+        return sid.value
+
+    # -------------------------------------------------------------- compute --
+    def cut(self, grid_id, surf_id, pose, iblank):
+        import torch
+        _, pp = _pose(pose)
+        _check(load().oc_cut(self._h, grid_id, surf_id, pp, _dptr(iblank, torch.int8, self.grids[grid_id])))
+        return iblank
+
+    def cut_multi(self, grid_id, surf_ids, poses, iblank):
+        import torch
+        ids = np.ascontiguousarray(surf_ids, dtype=np.int32)
+        pa, pp = _pose(np.asarray(poses, dtype=np.float64).reshape(-1) if len(ids) else np.zeros(12))
+        _check(load().oc_cut_multi(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
+                                   _dptr(iblank, torch.int8, self.grids[grid_id])))
+        return iblank
+
+    def last_cut_info(self):
+        info = oc_cut_info()
+        _check(load().oc_last_cut_info(self._h, C.byref(info)))
+        return {n: getattr(info, n) for n, _ in oc_cut_info._fields_}
+
+    def fringe_points(self, grid_id, pose, iblank, points, src=None):
+        """Fills ``points`` (float64 [cap,3]) and ``src`` (int32 [cap]);
+        returns the number of points written."""
+        import torch
+        _, pp = _pose(pose)
+        n = C.c_int64(0)
+        cap = points.numel() // 3
+        _check(load().oc_fringe_points(self._h, grid_id, pp, _dptr(iblank, torch.int8), _dptr(points, torch.float64),
+                                       cap, C.byref(n), None if src is None else _dptr(src, torch.int32, cap)))
+        return n.value
+
+    def donor_search(self, grid_id, pose, points, n, donor, ref):
+        import torch
+        _, pp = _pose(pose)
+        if n == 0:
+            return
+        _check(load().oc_donor_search(self._h, grid_id, pp, _dptr(points, torch.float64, 3 * n), int(n),
+                                      _dptr(donor, torch.int32, n), _dptr(ref, torch.float64, 3 * n)))
+
+    # ------------------------------------------------------------- timing ---
+    def timing(self, enable):
+        _check(load().oc_timing(self._h, 1 if enable else 0))
+
+    def timing_report(self):
+        buf = C.create_string_buffer(1 << 16)
+        _check(load().oc_timing_report(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def memory_used(self):
+        v = C.c_int64(0)
+        _check(load().oc_memory_used(self._h, C.byref(v)))
+        return v.value

@@ -1,0 +1,92 @@
+"""Helpers for comparing the HIP path with the oracle on the same seeded case."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as O
+
+XI_TOL = 1e-10      # donor reference coordinates (FP64 path)
+PT_TOL = 1e-12      # receptor point coordinates
+
+
+def pose_inverse(p):
+    R = np.asarray(p[:9]).reshape(3, 3)
+    t = np.asarray(p[9:12])
+    return np.concatenate([R.T.ravel(), -R.T @ t])
+
+
+def pose_compose(a, b):
+    Ra = np.asarray(a[:9]).reshape(3, 3)
+    Rb = np.asarray(b[:9]).reshape(3, 3)
+    return np.concatenate([(Ra @ Rb).ravel(), Ra @ np.asarray(b[9:12]) + np.asarray(a[9:12])])
+
+
+def oracle_step(case, poses, threads=0):
+    """The connectivity step computed by the oracle alone."""
+    bg = case["bg"]
+    walls = [b["surface"] for b in case["bodies"]]
+    out = {}
+    out["ib_bg"] = O.cut(bg, walls, poses, threads=threads)
+    fe = O.fringe_elements(out["ib_bg"])
+    out["pts_bg"] = O.fringe_points(bg, fe)
+    out["src_bg"] = np.repeat(fe, 27)
+    out["bodies"] = []
+    for i, b in enumerate(case["bodies"]):
+        others = [j for j in range(len(walls)) if j != i]
+        inv = pose_inverse(poses[i])
+        ib = O.cut(b["shell"], [walls[j] for j in others], [pose_compose(inv, poses[j]) for j in others],
+                   threads=threads)
+        fs = O.fringe_elements(ib)
+        pts = O.fringe_points(b["shell"], fs, poses[i])
+        d_bg, r_bg, _ = O.donor_search(b["shell"], out["pts_bg"], poses[i], threads=threads)
+        d, r, _ = O.donor_search(bg, pts, threads=threads)
+        out["bodies"].append(dict(ib=ib, pts=pts, src=np.repeat(fs, 27), donor_bg=d_bg, ref_bg=r_bg, donor=d, ref=r))
+    return out
+
+
+def gpu_step(system, poses):
+    """The same step through the HIP library (pipeline.OversetSystem)."""
+    import torch
+    c = system.step(poses)
+    torch.cuda.synchronize()
+    n_bg = c["n_bg_points"]
+    out = dict(ib_bg=system.ib_bg.cpu().numpy(), pts_bg=system.pts_bg[:n_bg].cpu().numpy(),
+               src_bg=system.src_bg[:n_bg].cpu().numpy(), bodies=[])
+    for b, n in zip(system.bodies, c["n_shell_points"]):
+        out["bodies"].append(dict(ib=b["ib"].cpu().numpy(), pts=b["pts"][:n].cpu().numpy(),
+                                  src=b["src"][:n].cpu().numpy(), donor_bg=b["donor_bg"][:n_bg].cpu().numpy(),
+                                  ref_bg=b["ref_bg"][:n_bg].cpu().numpy(), donor=b["donor"][:n].cpu().numpy(),
+                                  ref=b["ref"][:n].cpu().numpy()))
+    return out
+
+
+def _cmp_donors(d_g, r_g, d_o, r_o, what):
+    assert d_g.shape == d_o.shape, what
+    bad = np.nonzero(d_g != d_o)[0]
+    assert bad.size == 0, "%s: %d donor ids differ, first %s: gpu %s oracle %s" % (
+        what, bad.size, bad[:5], d_g[bad[:5]], d_o[bad[:5]])
+    ok = d_o >= 0
+    if ok.any():
+        err = np.abs(r_g[ok] - r_o[ok]).max()
+        assert err <= XI_TOL, "%s: max |xi_gpu - xi_oracle| = %g" % (what, err)
+    assert np.all(np.isnan(r_g[~ok])), what + ": orphan reference coordinates must be NaN"
+
+
+def compare(g, o):
+    """Bit-exact iblank and donor ids, reference coordinates within XI_TOL."""
+    bad = np.nonzero(g["ib_bg"] != o["ib_bg"])[0]
+    assert bad.size == 0, "background iblank: %d elements differ, first %s: gpu %s oracle %s" % (
+        bad.size, bad[:8], g["ib_bg"][bad[:8]], o["ib_bg"][bad[:8]])
+    assert np.array_equal(g["src_bg"], o["src_bg"])
+    if o["pts_bg"].size:
+        assert np.abs(g["pts_bg"] - o["pts_bg"]).max() <= PT_TOL
+    for k, (gb, ob) in enumerate(zip(g["bodies"], o["bodies"])):
+        assert np.array_equal(gb["ib"], ob["ib"]), "shell %d iblank" % k
+        assert np.array_equal(gb["src"], ob["src"])
+        if ob["pts"].size:
+            assert np.abs(gb["pts"] - ob["pts"]).max() <= PT_TOL
+        # both directions searched from the oracle's own points would hide
+        # point differences; the points agree to PT_TOL, so search results of
+        # each side's own points are compared
+        _cmp_donors(gb["donor_bg"], gb["ref_bg"], ob["donor_bg"], ob["ref_bg"], "bg->shell %d" % k)
+        _cmp_donors(gb["donor"], gb["ref"], ob["donor"], ob["ref"], "shell %d->bg" % k)

@@ -1,0 +1,185 @@
+"""HIP path against the oracle, element by element and point by point, through
+the C ABI.  Bar: bit-exact iblank and donor ids, reference coordinates within
+1e-10, receptor points within 1e-12."""
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import configs as CF
+from workloads import meshes as M
+
+from parity_util import compare, gpu_step, oracle_step
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1711_07663_amd import oc
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    c = oc.Context(device=0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _system(ctx, case):
+    from paper_1711_07663_amd.pipeline import OversetSystem
+    return OversetSystem(ctx, case)
+
+
+def test_tiny_case_parity(ctx, orc):
+    _note("tiny: 16^3 background, 96-face sphere, 4-layer shell")
+    case = CF.tiny()
+    sysm = _system(ctx, case)
+    g = gpu_step(sysm, case["poses"])
+    o = oracle_step(case, case["poses"])
+    compare(g, o)
+    assert (g["ib_bg"] == 0).sum() == 88 and (g["ib_bg"] == -1).sum() == 96
+    info = ctx.last_cut_info()
+    assert info["n_elem"] > 0
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_small_posed_dimpled_parity(ctx, orc, seed):
+    rng = np.random.default_rng(100 + seed)
+    n = int(rng.integers(9, 19))
+    m = int(rng.integers(3, 7))
+    _note("small dimpled seed %d: bg %d^3, m %d" % (seed, n, m))
+    bg = M.background_grid(n, -1.3, 1.3, amp=0.03)
+    s = M.cube_sphere(m, R=0.5, dimples=20, dimple_a=0.09, dimple_k=0.025)
+    sh = M.shell_grid(s, 3, r_out=0.9)
+    case = dict(bg=bg, bodies=[dict(surface=s, shell=sh)])
+    poses = [M.random_pose(rng, 0.2)]
+    sysm = _system(ctx, case)
+    compare(gpu_step(sysm, poses), oracle_step(case, poses))
+
+
+def test_box_closed_form_gpu(ctx, orc):
+    import torch
+    _note("box surface on an undisplaced 12^3 grid")
+    n, lo, hi = 12, -1.5, 1.5
+    g = M.background_grid(n, lo, hi, amp=0.0)
+    a, b = (-0.41, 0.63, -0.2), (0.37, 0.88, 0.61)
+    s = M.box_surface(3, a, b)
+    gid = ctx.register_grid(g.nodes, g.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    ib = torch.empty(g.n_elem, dtype=torch.int8, device="cuda")
+    ctx.cut(gid, sid, M.IDENTITY_POSE, ib)
+    ib = ib.cpu().numpy()
+    e = np.linspace(lo, hi, n + 1)
+    cnt = [int(((e[1:] >= a[k]) & (e[:-1] <= b[k])).sum()) for k in range(3)]
+    assert (ib == 0).sum() == cnt[0] * cnt[1] * cnt[2]
+    assert (ib == -1).sum() == 2 * (cnt[0] * cnt[1] + cnt[1] * cnt[2] + cnt[0] * cnt[2])
+
+
+def test_mid_dimpled_parity(ctx, orc):
+    _note("mid dimpled: bg 40^3 on [-3,3], m 16, 120 dimples, 4-layer shell, rotated")
+    bg = M.background_grid(40, -3.0, 3.0, amp=0.02)
+    s = M.cube_sphere(16, R=0.5, dimples=120, dimple_a=0.04, dimple_k=0.008)
+    sh = M.shell_grid(s, 4, r_out=1.0)
+    case = dict(bg=bg, bodies=[dict(surface=s, shell=sh)])
+    poses = [M.pose_rz(0.7, (0.01, -0.02, 0.005))]
+    sysm = _system(ctx, case)
+    compare(gpu_step(sysm, poses), oracle_step(case, poses))
+
+
+def test_two_body_small_parity(ctx, orc):
+    _note("two bodies: bg 32^3 on [-3,3], m 8 dimpled spheres 1.5 apart, opposite spins")
+    bg = M.background_grid(32, -3.0, 3.0, amp=0.02)
+    s = M.cube_sphere(8, R=0.5, dimples=40, dimple_a=0.06, dimple_k=0.012)
+    sh = M.shell_grid(s, 3, r_out=1.0)
+    case = dict(bg=bg, bodies=[dict(surface=s, shell=sh), dict(surface=s, shell=sh)])
+    poses = CF.two_body_poses(7)
+    sysm = _system(ctx, case)
+    compare(gpu_step(sysm, poses), oracle_step(case, poses))
+
+
+def test_edge_cases(ctx, orc):
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("edge cases: ragged grid, surface outside the grid, empty point set")
+    # ragged element count (not a multiple of 4 or 64) and a surface that
+    # misses the grid entirely
+    g = M.background_grid((7, 5, 3), -1.0, 1.0, amp=0.05)
+    s = M.cube_sphere(2, R=0.3)
+    gid = ctx.register_grid(g.nodes, g.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    ib = torch.empty(g.n_elem, dtype=torch.int8, device="cuda")
+    far = M.pose_rz(0.0, (5.0, 0.0, 0.0))
+    ctx.cut(gid, sid, far, ib)
+    assert np.all(ib.cpu().numpy() == 1)
+    for p in (M.IDENTITY_POSE, M.pose_rz(0.4, (0.12, -0.05, 0.02))):
+        ctx.cut(gid, sid, p, ib)
+        assert np.array_equal(ib.cpu().numpy(), orc.cut(g, [s], [p]))
+    # one-element grid enclosing a small surface: the element is hit
+    g1 = M.background_grid(1, -1.0, 1.0, amp=0.0)
+    g1id = ctx.register_grid(g1.nodes, g1.conn)
+    ib1 = torch.empty(1, dtype=torch.int8, device="cuda")
+    ctx.cut(g1id, sid, M.IDENTITY_POSE, ib1)
+    assert ib1.cpu().numpy()[0] == orc.cut(g1, [s], [M.IDENTITY_POSE])[0] == 0
+    # empty point set and a single point
+    pts = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    don = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+    ref = torch.zeros((1, 3), dtype=torch.float64, device="cuda")
+    ctx.donor_search(gid, M.IDENTITY_POSE, pts, 0, don, ref)
+    assert int(don.cpu()[0]) == 7
+    ctx.donor_search(gid, M.IDENTITY_POSE, pts, 1, don, ref)
+    d_o, r_o, _ = orc.donor_search(g, np.zeros((1, 3)))
+    assert int(don.cpu()[0]) == int(d_o[0])
+    # capacity too small for the fringe points
+    ctx.cut(gid, sid, M.IDENTITY_POSE, ib)
+    small = torch.empty((1, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(oc.OcError) as ei:
+        ctx.fringe_points(gid, M.IDENTITY_POSE, ib, small)
+    assert ei.value.status == oc.OC_ECAPACITY
+
+
+def test_error_paths(ctx):
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("error paths")
+    s = M.cube_sphere(2, R=0.3)
+    # open surface (one face removed)
+    with pytest.raises(oc.OcError) as ei:
+        ctx.register_cut_surface(s.nodes, s.conn[1:])
+    assert ei.value.status == oc.OC_EGEOM
+    # inward orientation
+    flipped = s.conn.reshape(-1, 3, 3)[:, :, ::-1].reshape(-1, 9)
+    with pytest.raises(oc.OcError) as ei:
+        ctx.register_cut_surface(s.nodes, flipped)
+    assert ei.value.status == oc.OC_EGEOM
+    ib = torch.empty(8, dtype=torch.int8, device="cuda")
+    with pytest.raises(oc.OcError) as ei:
+        oc._check(oc.load().oc_cut(ctx._h, 999, 0, oc._pose(M.IDENTITY_POSE)[1], oc.C.c_void_p(ib.data_ptr())))
+    assert ei.value.status == oc.OC_ENOTFOUND
+    g = M.background_grid(2, -1, 1, amp=0.0)
+    bad = g.conn.copy()
+    bad[0, 0] = 10 ** 6
+    with pytest.raises(oc.OcError) as ei:
+        ctx.register_grid(g.nodes, bad)
+    assert ei.value.status == oc.OC_EINVAL
+    tiny_budget = oc.Context(device=0, hbm_budget=1 << 16)
+    gb = M.background_grid(8, -1, 1)
+    with pytest.raises(oc.OcError) as ei:
+        tiny_budget.register_grid(gb.nodes, gb.conn)
+    assert ei.value.status == oc.OC_EBUDGET
+    tiny_budget.close()
+
+
+def test_deterministic(ctx, orc):
+    _note("determinism: same case twice")
+    case = CF.tiny()
+    sysm = _system(ctx, case)
+    a = gpu_step(sysm, case["poses"])
+    b = gpu_step(sysm, case["poses"])
+    assert np.array_equal(a["ib_bg"], b["ib_bg"])
+    for x, y in zip(a["bodies"], b["bodies"]):
+        assert np.array_equal(x["donor"], y["donor"]) and np.array_equal(x["ref"], y["ref"], equal_nan=True)

@@ -137,6 +137,7 @@ def test_brute_force_equals_accelerated(orc, seed):
     assert np.array_equal(rb["status"], ra["status"])
     assert np.array_equal(rb["hit"], ra["hit"])
     assert np.array_equal(rb["nsign"], ra["nsign"])
+    assert np.array_equal(rb["psign"], ra["psign"])
     np.testing.assert_allclose(rb["dstar"], ra["dstar"], rtol=0, atol=0)
     assert 0 < (ra["status"] == 0).sum() < g.n_elem
 
@@ -153,6 +154,7 @@ def test_nearest_sign_agrees_with_winding(orc):
         r = orc.cut_surface(g, s, p, diagnostics=True)
         nh = r["hit"] == 0
         assert np.array_equal(r["nsign"][nh] < 0, r["wind"][nh] > 0.5)
+        assert np.array_equal(r["psign"][nh] < 0, r["wind"][nh] > 0.5)
         assert np.all(np.abs(r["wind"][nh] - np.round(r["wind"][nh])) < 1e-9)
 
 
@@ -182,3 +184,17 @@ def test_relabeling_and_union(orc):
     nbr = orc.face_neighbors(g.conn)
     ib = orc.cut(g, [s, s3], [pose, p3], nbr=nbr)
     assert np.array_equal(ib == orc.HOLE, (st == 0) | (st3 == 0))
+
+
+def test_element_winding_and_enclosed_surface(orc):
+    """The element boundary is a closed surface: winding 1 at interior points
+    (positive Jacobian), 0 outside; a surface lying inside one element makes
+    that element hit."""
+    g = M.background_grid(1, -1.0, 1.0, amp=0.0)
+    g.nodes[:] += 0.07 * np.sin(3.0 * g.nodes[:, [1, 2, 0]])
+    for p, w in (([0.05, -0.1, 0.2], 1.0), ([0.7, 0.6, -0.65], 1.0), ([1.6, 0, 0], 0.0), ([0, -2, 0.3], 0.0)):
+        assert orc.element_winding(g.nodes, g.conn, 0, p) == pytest.approx(w, abs=1e-12)
+    s = M.cube_sphere(2, R=0.3)
+    r = orc.cut_surface(g, s, diagnostics="point")
+    assert r["hit"][0] == 1 and r["status"][0] == 0
+    assert orc.cut_surface(g, s, kind=orc.SURF_OVERSET)[0] == 1
