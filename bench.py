@@ -1,0 +1,182 @@
+"""Benchmark: one full overset connectivity step on one MI355X.
+
+Workload (the single dimpled-sphere cut): background 128^3 quadratic hexes on
+[-3,3]^3 with the sinusoidal displacement; cut surface: R = 0.5 sphere with
+300 spherical-cap dimples, 24 576 quadratic quads; near-body shell of 8
+layers (196 608 hexes) to r = 1.  A step is the whole hot path: pose, bins,
+filter, exact intersection, nearest-face side, ray parity, union, fringe
+marking, Gauss receptor points and Newton donor search in both directions.
+Inputs are generated from fixed formulas (synthetic), resident on the device
+before timing.
+
+Prints one JSON line.  Only N = 1 GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+FP64_VECTOR_PEAK = 78.6        # TFLOP/s, MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+NEWTON_FLOP = 640              # FLOP per Newton iteration of the quadratic map (sum-factorised x, J, 3x3 solve)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=4, help="oracle runs on every k-th element / point")
+    ap.add_argument("--bg", type=int, default=128)
+    return ap.parse_args()
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(case, sample_every):
+    """The oracle, as it stands, on a strided sample of the same step."""
+    import oracle as O
+    bg = case["bg"]
+    body = case["bodies"][0]
+    s, sh = body["surface"], body["shell"]
+    O.build(force=False)
+    threads = os.cpu_count() or 1
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    threads = min(threads, 16)
+    sel = np.arange(0, bg.n_elem, sample_every, dtype=np.int64)
+    t0 = time.perf_counter()
+    O.cut_surface(bg, s, O.IDENTITY, sel=sel, threads=threads)
+    t_cut = time.perf_counter() - t0
+    # donors: shell fringe points (outer layer) searched in the background
+    nf = s.n_face
+    layers = sh.n_elem // nf
+    fe = np.arange((layers - 1) * nf, layers * nf, sample_every, dtype=np.int64)
+    pts = O.fringe_points(sh, fe)
+    t0 = time.perf_counter()
+    O.donor_search(bg, pts, threads=threads)
+    t_don = time.perf_counter() - t0
+    t_step = (t_cut + t_don) * sample_every
+    return dict(value=bg.n_elem / t_step, unit="elements/s", cores=threads, kind="oracle",
+                sample="every %d-th background element classified (cut only, no fringe) and every %d-th "
+                       "outer-shell element's 27 Gauss points searched in the background; step time scaled "
+                       "by %d (cut %.2f s + donors %.2f s of wall time on %d threads)"
+                       % (sample_every, sample_every, sample_every, t_cut, t_don, threads),
+                t_step_s=t_step)
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: the method's multi-GPU sharding is a design note, "
+              "not part of this build (got --gpus %d)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1711_07663_amd import oc
+    from paper_1711_07663_amd.pipeline import OversetSystem
+    from workloads import configs as CF
+
+    log("generating the dimpled-sphere workload")
+    case = CF.dimpled(bg_n=a.bg)
+    bg = case["bg"]
+    torch.cuda.set_device(0)
+    ctx = oc.Context(device=0)
+    log("registering grids and surface")
+    t0 = time.perf_counter()
+    system = OversetSystem(ctx, case, bg_points_cap=27 * 40000)
+    torch.cuda.synchronize()
+    t_reg = time.perf_counter() - t0
+    poses = case["poses"]
+    log("warmup %d" % a.warmup)
+    counts = None
+    for _ in range(a.warmup):
+        counts = system.step(poses)
+    torch.cuda.synchronize()
+    counts = system.step(poses, stats=True)
+    torch.cuda.synchronize()
+    st = counts.pop("stats")
+    info = st["bg_cut"]
+
+    log("timed %d steps" % a.steps)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ts = time.perf_counter()
+        counts = system.step(poses)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    ms = 1e3 * t_total / a.steps
+
+    # per-kernel HIP-event timing over a second pass of the same steps
+    log("per-kernel event timing over %d steps" % a.steps)
+    ctx.timing(True)
+    for _ in range(a.steps):
+        system.step(poses)
+    rep = ctx.timing_report()
+    ctx.timing(False)
+    per_kernel = {k: dict(total_ms=v[0], launches=v[1], avg_us=1e3 * v[0] / max(v[1], 1)) for k, v in rep.items()}
+
+    n_pts = counts["n_bg_points"] + sum(counts["n_shell_points"])
+    value = bg.n_elem / (ms / 1e3)
+    # roofline of the streaming filter (HBM bound): per element its FP32 box
+    # (24 B) is read and its iblank (1 B) written
+    kf = per_kernel.get("k_filter")
+    roof_filter = None
+    if kf:
+        bytes_per_launch = 25.0 * bg.n_elem
+        achieved = bytes_per_launch / (kf["avg_us"] * 1e-6) / 1e9
+        roof_filter = dict(bound="hbm", kernel="k_filter", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                           frac=achieved / HBM_PEAK_GBS, traffic=None,
+                           algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=kf["avg_us"])
+    # dominant kernel of the step: the Newton donor search, FP64 VALU bound;
+    # algorithmic FLOP per launch = NEWTON_FLOP x Newton iterations run
+    kd = per_kernel.get("k_donor")
+    roof = roof_filter
+    dominant = max(per_kernel.items(), key=lambda kv: kv[1]["total_ms"])[0] if per_kernel else None
+    if kd and dominant == "k_donor":
+        iters = sum(d["n_iter"] for d in st["donor_bg"] + st["donor_shell"])
+        launches_per_step = len(st["donor_bg"]) + len(st["donor_shell"])
+        flop_per_launch = NEWTON_FLOP * iters / launches_per_step
+        achieved = flop_per_launch / (kd["avg_us"] * 1e-6) / 1e12
+        roof = dict(bound="alu", kernel="k_donor", achieved=achieved, peak=FP64_VECTOR_PEAK, unit="TFLOP/s",
+                    frac=achieved / FP64_VECTOR_PEAK, traffic=None, algorithmic_flop_per_launch=flop_per_launch,
+                    newton_iterations_per_step=iters, avg_launch_us=kd["avg_us"])
+    out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
+               value=value, unit="elements/s", n_gpus=1, steps=a.steps, warmup=a.warmup, ms_per_step=ms,
+               higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload="dimpled sphere single cut: %d^3 quadratic hexes on [-3,3]^3, 300-dimple "
+                                    "R=0.5 sphere of 24576 9-node quads, 8-layer shell of 196608 hexes; cut + "
+                                    "fringe + Gauss points + Newton donors in both directions" % a.bg,
+                           bg_elements=bg.n_elem, surface_faces=case["bodies"][0]["surface"].n_face,
+                           shell_elements=case["bodies"][0]["shell"].n_elem, parallelism="1 GPU"),
+               donors_per_s=n_pts / (ms / 1e3), points_per_step=n_pts,
+               latency_ms=dict(p50=1e3 * float(np.percentile(lat, 50)), p99=1e3 * float(np.percentile(lat, 99))),
+               cut_info=info, donor_info=dict(bg_to_shell=st["donor_bg"], shell_to_bg=st["donor_shell"]),
+               registration_s=t_reg, per_kernel=per_kernel, roofline=roof, roofline_filter=roof_filter,
+               dominant_kernel=dominant)
+    if not a.no_cpu_baseline:
+        log("oracle baseline on the host")
+        cb = cpu_baseline(case, a.cpu_sample)
+        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -39,6 +39,7 @@ extern "C" {
 #endif
 
 typedef struct oc_ctx oc_ctx;
+typedef struct oc_slot oc_slot;
 typedef int32_t oc_status;
 
 enum {
@@ -90,6 +91,14 @@ typedef struct oc_cut_info {
     int64_t n_cand_pairs; /* element x face pairs passing the FP32 box filter */
 } oc_cut_info;
 
+/* Statistics of the last oc_donor_search call (host copy; synchronises). */
+typedef struct oc_donor_info {
+    int64_t n_points;  /* points searched */
+    int64_t n_newton;  /* Newton solves run (candidates whose box holds the point) */
+    int64_t n_iter;    /* Newton iterations run in total */
+    int64_t n_orphan;  /* points without a donor */
+} oc_donor_info;
+
 /* Create / destroy a context on cfg->device (cfg may be NULL: device 0,
  * automatic bins, no budget).  *ctx receives an opaque handle. */
 oc_status oc_create(oc_ctx **ctx, const oc_config *cfg);
@@ -127,7 +136,7 @@ oc_status oc_register_cut_surface(oc_ctx *ctx, const double *nodes, int64_t n_no
  * hole if the surface (wall) intersects it -- some element/surface triangle
  * pair closer than OC_TOL_HIT -- or if it lies inside the surface.  Fringe =
  * field element sharing a face with a hole, or carrying an OVERSET face tag
- * (artificial boundary of Sec. 4.2). */
+ * (artificial boundary of Sec. 4.2).  iblank_out must be 4-byte aligned. */
 oc_status oc_cut(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pose[12], int8_t *iblank_out);
 
 /* Union of holes over n_surf posed surfaces (Sec. 4.2: union over cutting
@@ -135,6 +144,18 @@ oc_status oc_cut(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pos
  * n_surf = 0 gives the fringe layer of OVERSET-tagged faces only. */
 oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses,
                        int32_t n_surf, int8_t *iblank_out);
+
+/* Warm-started cut of a moving surface (the per-time-step recut of Sec. 3):
+ * prev_iblank (device, not aliasing iblank_out) is this grid's iblank from
+ * oc_cut of the same single surface at prev_pose.  Elements whose box grown
+ * by the sweep bound (oc_sweep_bound) meets no face box keep their previous
+ * hole/field status; all others are recomputed.  The result equals a cold
+ * oc_cut at pose. */
+oc_status oc_cut_warm(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pose[12], const double prev_pose[12],
+                      const int8_t *prev_iblank, int8_t *iblank_out);
+/* Largest distance a point of the surface travels from pose_a to pose_b:
+ * rotation angle of R_b R_a^T times the largest node radius plus |t_b - t_a|. */
+oc_status oc_sweep_bound(oc_ctx *ctx, int32_t surf_id, const double pose_a[12], const double pose_b[12], double *out);
 
 oc_status oc_last_cut_info(oc_ctx *ctx, oc_cut_info *info);
 
@@ -159,6 +180,44 @@ oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[
  *   ref_out   device FP64 [n*3]  reference coordinates (NaN for orphans) */
 oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12], const double *points,
                           int64_t n, int32_t *donor_out, double *ref_out);
+
+oc_status oc_last_donor_info(oc_ctx *ctx, oc_donor_info *info);
+
+/* ------------------------------------------------------------------ slots
+ * A slot is the per-request scratch of the compute calls (element lists,
+ * posed surface copies and bins, counters) plus the stream they run on.
+ * The oc_cut / oc_fringe_points / oc_donor_search calls above use the
+ * context's default slot, which grows on demand.  A slot made with
+ * oc_slot_create reserves everything up front for the listed grids and
+ * surfaces (OC_EBUDGET if the context's HBM budget would be exceeded), its
+ * calls never allocate, never synchronise and take poses and point counts in
+ * device memory, so several slots can run at once on different streams and a
+ * sequence of slot calls can be captured in a HIP graph and replayed.  Calls
+ * on one slot must not overlap in time. */
+oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, const int32_t *surf_ids,
+                         int32_t n_surfs, oc_slot **slot);
+oc_status oc_slot_destroy(oc_slot *slot);
+oc_status oc_slot_set_stream(oc_slot *slot, void *hip_stream);
+/* device bytes reserved by the slot */
+oc_status oc_slot_bytes(oc_slot *slot, int64_t *bytes);
+/* oc_cut_multi on a slot; poses_dev: device FP64 [n_surf*12] (8-byte aligned) */
+oc_status oc_slot_cut(oc_slot *slot, int32_t grid_id, const int32_t *surf_ids, const double *poses_dev,
+                      int32_t n_surf, int8_t *iblank_out);
+/* oc_cut_warm on a slot; sweep from oc_sweep_bound for the two poses */
+oc_status oc_slot_cut_warm(oc_slot *slot, int32_t grid_id, int32_t surf_id, const double *pose_dev, double sweep,
+                           const int8_t *prev_iblank, int8_t *iblank_out);
+/* oc_fringe_points on a slot; pose_dev: device FP64 [12]; the number of
+ * points (27 per fringe element) is written to the device int32 *n_dev;
+ * at most cap points are written. */
+oc_status oc_slot_fringe_points(oc_slot *slot, int32_t grid_id, const double *pose_dev, const int8_t *iblank,
+                                double *points_out, int64_t cap, int32_t *n_dev, int32_t *src_out);
+/* oc_donor_search on a slot for min(*n_dev, cap) points (n_dev may be NULL:
+ * cap points); pose_dev: device FP64 [12]. */
+oc_status oc_slot_donor_search(oc_slot *slot, int32_t donor_grid_id, const double *pose_dev, const double *points,
+                               int64_t cap, const int32_t *n_dev, int32_t *donor_out, double *ref_out);
+/* counters of the slot's last cut / donor search (synchronise the slot stream) */
+oc_status oc_slot_cut_info(oc_slot *slot, oc_cut_info *info);
+oc_status oc_slot_donor_info(oc_slot *slot, oc_donor_info *info);
 
 /* Per-kernel device timing with HIP events recorded on the context stream.
  * oc_timing(ctx, 1) starts collecting (and clears), oc_timing(ctx, 0) stops.

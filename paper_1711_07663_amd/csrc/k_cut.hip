@@ -66,7 +66,7 @@ __device__ inline double wave_min_d(double v)
 __global__ void k_reset_counters(CutCounters *cnt)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        cnt->n_inbox = cnt->n_near = cnt->n_far = cnt->n_hit = cnt->n_hole = 0;
+        cnt->n_inbox = cnt->n_near = cnt->n_far = cnt->n_hit = cnt->n_hole = cnt->n_side = 0;
         cnt->n_cand_pairs = 0ull;
     }
 }
@@ -78,7 +78,7 @@ __global__ void k_surf_init(SurfParams *sp, CutCounters *cnt)
             sp->sbox_ord[k] = f2ord(INFINITY);
             sp->sbox_ord[3 + k] = f2ord(-INFINITY);
         }
-        cnt->n_inbox = cnt->n_near = cnt->n_far = 0;
+        cnt->n_inbox = cnt->n_near = cnt->n_far = cnt->n_side = 0;
     }
 }
 
@@ -87,9 +87,11 @@ __global__ void k_surf_init(SurfParams *sp, CutCounters *cnt)
 // by tol_hit + 2^-20 * max|coordinate|.
 __global__ __launch_bounds__(kThreads) void k_pose_faces(const double *__restrict__ nodes, int64_t n_nodes,
                                                          const int32_t *__restrict__ conn, int64_t n_face,
-                                                         Pose pose, double *__restrict__ pnodes,
-                                                         float *__restrict__ fbox, SurfParams *sp)
+                                                         const Pose *__restrict__ pose_dev,
+                                                         double *__restrict__ pnodes, float *__restrict__ fbox,
+                                                         SurfParams *sp)
 {
+    const Pose pose = *pose_dev;
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     if (f < n_face) {
@@ -260,57 +262,167 @@ __device__ inline bool box_overlap(const float *a, const float *b)
     return a[0] <= b[3] && b[0] <= a[3] && a[1] <= b[4] && b[1] <= a[4] && a[2] <= b[5] && b[2] <= a[5];
 }
 
-// a3, bin part: count the candidate faces of each in-box element (element box
-// overlapping an inflated face box).  A face found in several bins is
-// counted only in the first bin (per axis) common to both bin ranges.
-__global__ __launch_bounds__(kThreads) void k_candidates(const float *__restrict__ ebox, int64_t stride,
-                                                         const float *__restrict__ fbox,
-                                                         const SurfParams *__restrict__ sp,
-                                                         const int32_t *__restrict__ bstart,
-                                                         const int32_t *__restrict__ bitems,
-                                                         const int32_t *__restrict__ list_inbox,
-                                                         int32_t *__restrict__ list_near,
-                                                         int32_t *__restrict__ list_far, CutCounters *cnt)
+// Inclusive 3-D range of bins enumerated with a linear index, so that the
+// 64 lanes of a wavefront can each take one bin per round.
+struct BinRange {
+    int lo[3], n[3], total;
+};
+
+__device__ inline BinRange make_range(const int *lo, const int *hi)
 {
+    BinRange R;
+    for (int a = 0; a < 3; ++a) {
+        R.lo[a] = lo[a];
+        R.n[a] = hi[a] - lo[a] + 1;
+    }
+    R.total = R.n[0] * R.n[1] * R.n[2];
+    return R;
+}
+
+__device__ inline int range_bin(const BinGrid &G, const BinRange &R, int idx, int *xyz)
+{
+    xyz[0] = R.lo[0] + idx % R.n[0];
+    xyz[1] = R.lo[1] + (idx / R.n[0]) % R.n[1];
+    xyz[2] = R.lo[2] + idx / (R.n[0] * R.n[1]);
+    return xyz[0] + G.n[0] * (xyz[1] + G.n[1] * xyz[2]);
+}
+
+// a face found in bin xyz is taken only in the first bin (per axis) that its
+// own range shares with the query range starting at qlo
+__device__ inline bool first_common_bin(const BinGrid &G, const float *fb, const int *xyz, const int *qlo)
+{
+    for (int a = 0; a < 3; ++a) {
+        int fl = bin_of(fb[a], G.o[a], G.inv[a], G.n[a]);
+        if (xyz[a] != max(qlo[a], fl)) return false;
+    }
+    return true;
+}
+
+// LDS of one wavefront for walk_faces
+struct WalkLds {
+    int pre[64];
+    int j0[64];
+    int xyz[64];
+};
+
+// Visit every face stored in the bins of range R (a face stored in several
+// bins is met once per bin; callers keep the first common bin).  A round
+// loads the extents of 64 bins, one per lane, prefix-sums their lengths and
+// then hands the stored faces out one per lane, so the dependent loads of a
+// round are issued by the whole wavefront at once.  fn(face, xyz) is called
+// with the same trip count on every lane (face < 0 on idle lanes) and may use
+// wavefront operations; it returns true (wave-uniformly) to stop the walk.
+// Requires a one-wavefront workgroup.
+template <class Fn>
+__device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int32_t *__restrict__ bstart,
+                                  const int32_t *__restrict__ bitems, WalkLds &L, Fn &&fn)
+{
+    const int lane = threadIdx.x;
+    for (int r = 0; r < R.total; r += 64) {
+        const int idx = r + lane;
+        int cnt = 0, j0 = 0, packed = 0;
+        if (idx < R.total) {
+            int xyz[3];
+            const int b = range_bin(G, R, idx, xyz);
+            j0 = bstart[b];
+            cnt = bstart[b + 1] - j0;
+            packed = xyz[0] | (xyz[1] << 10) | (xyz[2] << 20);
+        }
+        int inc = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        const int total = __shfl(inc, 63, 64);
+        __syncthreads();
+        L.pre[lane] = inc - cnt;
+        L.j0[lane] = j0;
+        L.xyz[lane] = packed;
+        __syncthreads();
+        for (int k0 = 0; k0 < total; k0 += 64) {
+            const int k = k0 + lane;
+            int face = -1, xyz[3] = {0, 0, 0};
+            if (k < total) {
+                int lo = 0, hi = 63;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (L.pre[mid] <= k) lo = mid;
+                    else hi = mid - 1;
+                }
+                face = bitems[L.j0[lo] + (k - L.pre[lo])];
+                const int pk = L.xyz[lo];
+                xyz[0] = pk & 1023;
+                xyz[1] = (pk >> 10) & 1023;
+                xyz[2] = pk >> 20;
+            }
+            if (fn(face, xyz)) return;
+        }
+    }
+}
+
+// a3, bin part: one wavefront per in-box element counts its candidate faces
+// (element box overlapping an inflated face box).  Warm start (prev != null):
+// the walk also counts faces whose box meets the element box grown by the
+// sweep bound; an element meeting none keeps its previous side (the surface
+// never came near it between the two poses) and skips the ray test.
+__global__ __launch_bounds__(64) void k_candidates(const float *__restrict__ ebox, int64_t stride,
+                                                   const float *__restrict__ fbox, const SurfParams *__restrict__ sp,
+                                                   const int32_t *__restrict__ bstart,
+                                                   const int32_t *__restrict__ bitems,
+                                                   const int32_t *__restrict__ list_inbox,
+                                                   int32_t *__restrict__ list_near, int32_t *__restrict__ list_far,
+                                                   CutCounters *cnt, const int8_t *__restrict__ prev, double sweep,
+                                                   int8_t *__restrict__ iblank, int32_t *__restrict__ list_hole)
+{
+    __shared__ WalkLds L;
     const BinGrid G = sp->grid;
     const int n_in = cnt->n_inbox;
-    const int gstride = gridDim.x * blockDim.x;
-    for (int base = blockIdx.x * blockDim.x; base < n_in; base += gstride) {
-        const int i = base + threadIdx.x;
-        int e = -1, nc = 0;
-        if (i < n_in) {
-            e = list_inbox[i];
-            float eb[6];
-            for (int k = 0; k < 6; ++k) eb[k] = ebox[(int64_t)k * stride + e];
-            int lo[3], hi[3];
-            box_bins(G, eb, lo, hi);
-            for (int z = lo[2]; z <= hi[2]; ++z)
-                for (int y = lo[1]; y <= hi[1]; ++y)
-                    for (int x = lo[0]; x <= hi[0]; ++x) {
-                        const int b = x + G.n[0] * (y + G.n[1] * z);
-                        for (int j = bstart[b]; j < bstart[b + 1]; ++j) {
-                            const float *fb = fbox + (int64_t)bitems[j] * 6;
-                            int fl[3], fh[3];
-                            box_bins(G, fb, fl, fh);
-                            if (x != max(lo[0], fl[0]) || y != max(lo[1], fl[1]) || z != max(lo[2], fl[2])) continue;
-                            nc += box_overlap(eb, fb);
-                        }
-                    }
+    const int lane = threadIdx.x;
+    for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
+        const int e = list_inbox[item];
+        float eb[6], wb[6];
+        for (int k = 0; k < 6; ++k) eb[k] = ebox[(int64_t)k * stride + e];
+        for (int k = 0; k < 3; ++k) {
+            wb[k] = prev ? f32_down((double)eb[k] - sweep) : eb[k];
+            wb[3 + k] = prev ? f32_up((double)eb[3 + k] + sweep) : eb[3 + k];
         }
-        const bool near = e >= 0 && nc > 0, far = e >= 0 && nc == 0;
-        int pn = wave_append(&cnt->n_near, near ? 1 : 0);
-        int pf = wave_append(&cnt->n_far, far ? 1 : 0);
-        if (near) list_near[pn] = e;
-        if (far) list_far[pf] = e;
-        long long s = wave_sum_ll(nc);
-        if (lane_id() == 0 && s) atomicAdd(&cnt->n_cand_pairs, (unsigned long long)s);
+        int lo[3], hi[3];
+        box_bins(G, wb, lo, hi);
+        const BinRange R = make_range(lo, hi);
+        int nc = 0, nw = 0;
+        walk_faces(G, R, bstart, bitems, L, [&](int f, const int *xyz) {
+            if (f >= 0) {
+                const float *fb = fbox + (int64_t)f * 6;
+                if (first_common_bin(G, fb, xyz, lo)) {
+                    nc += box_overlap(eb, fb);
+                    nw += box_overlap(wb, fb);
+                }
+            }
+            return false;
+        });
+        const long long tot = wave_sum_ll(nc);
+        const long long totw = prev ? wave_sum_ll(nw) : 1;
+        if (lane == 0) {
+            if (tot > 0) {
+                list_near[atomicAdd(&cnt->n_near, 1)] = e;
+                atomicAdd(&cnt->n_cand_pairs, (unsigned long long)tot);
+            } else if (totw == 0) {
+                if (prev[e] == OC_HOLE && iblank[e] != OC_HOLE) {
+                    iblank[e] = OC_HOLE;
+                    list_hole[atomicAdd(&cnt->n_hole, 1)] = e;
+                }
+            } else {
+                list_far[atomicAdd(&cnt->n_far, 1)] = e;
+            }
+        }
     }
 }
 
 // ------------------------------------------------------------ exact stage --
 struct TieRec {
     double absdot, dot;
-    double v[3], n[3];
+    double vx, vy, vz, nx, ny, nz;
     int f, s, valid, pad;
 };
 
@@ -323,18 +435,35 @@ __device__ inline bool tie_before(const TieRec &a, const TieRec &b)
     if (a.f != b.f) return a.f < b.f;
     return a.s < b.s;
 }
+__device__ inline TieRec tie_sel(bool c, const TieRec &x, const TieRec &y)
+{
+    TieRec r;
+    r.absdot = c ? x.absdot : y.absdot;
+    r.dot = c ? x.dot : y.dot;
+    r.vx = c ? x.vx : y.vx;
+    r.vy = c ? x.vy : y.vy;
+    r.vz = c ? x.vz : y.vz;
+    r.nx = c ? x.nx : y.nx;
+    r.ny = c ? x.ny : y.ny;
+    r.nz = c ? x.nz : y.nz;
+    r.f = c ? x.f : y.f;
+    r.s = c ? x.s : y.s;
+    r.valid = c ? x.valid : y.valid;
+    r.pad = 0;
+    return r;
+}
+// keep the two records that come first in tie order
 __device__ inline void tie_offer(TieRec &b1, TieRec &b2, const TieRec &r)
 {
-    if (tie_before(r, b1)) {
-        b2 = b1;
-        b1 = r;
-    } else if (tie_before(r, b2)) {
-        b2 = r;
-    }
+    const bool before1 = tie_before(r, b1), before2 = tie_before(r, b2);
+    const TieRec n2 = tie_sel(before1, b1, tie_sel(before2, r, b2));
+    const TieRec n1 = tie_sel(before1, r, b1);
+    b1 = n1;
+    b2 = n2;
 }
 
-// triangle s of a posed face (face-major x[9], y[9], z[9])
-__device__ inline void face_tri(const double *__restrict__ P, int s, d3 *T)
+// triangle s of a face stored x[9], y[9], z[9]
+__device__ inline void face_tri(const double *P, int s, d3 *T)
 {
     int uv[6];
     quad_tri_uv((s >> 1) & 1, s >> 2, s & 1, uv);
@@ -344,12 +473,62 @@ __device__ inline void face_tri(const double *__restrict__ P, int s, d3 *T)
     }
 }
 
+// boundary triangle t (0..47) of an element stored x[27], y[27], z[27]
+__device__ inline void elem_tri(const double *X, int t, d3 *T)
+{
+    int uv[6];
+    quad_tri_uv((t >> 1) & 1, (t >> 2) & 1, t & 1, uv);
+    for (int k = 0; k < 3; ++k) {
+        int nd = elem_face_node(t >> 3, uv[2 * k], uv[2 * k + 1]);
+        T[k] = mk(X[nd], X[27 + nd], X[54 + nd]);
+    }
+}
+
 __device__ inline double point_box_dist(d3 p, const float *b)
 {
     double gx = fmax(0.0, fmax((double)b[0] - p.x, p.x - (double)b[3]));
     double gy = fmax(0.0, fmax((double)b[1] - p.y, p.y - (double)b[4]));
     double gz = fmax(0.0, fmax((double)b[2] - p.z, p.z - (double)b[5]));
     return sqrt(gx * gx + gy * gy + gz * gz);
+}
+
+// distance from p to the 8 triangles of a posed face
+__device__ inline double point_face_dist(d3 p, const double *__restrict__ P)
+{
+    double best = INFINITY;
+    for (int s = 0; s < 8; ++s) {
+        d3 F[3];
+        face_tri(P, s, F);
+        d3 w = p - closest_on_tri(p, F[0], F[1], F[2]);
+        best = fmin(best, dot(w, w));
+    }
+    return sqrt(best);
+}
+
+// box gap test (FP64): closer than tol along every axis
+__device__ inline bool boxes_within(const double *a, const double *b, double tol)
+{
+    return b[0] - a[3] < tol && a[0] - b[3] < tol && b[1] - a[4] < tol && a[1] - b[4] < tol && b[2] - a[5] < tol &&
+           a[2] - b[5] < tol;
+}
+
+// closed boxes meet
+__device__ inline bool boxes_meet(const double *a, const double *b)
+{
+    return b[0] <= a[3] && a[0] <= b[3] && b[1] <= a[4] && a[1] <= b[4] && b[2] <= a[5] && a[2] <= b[5];
+}
+
+// query box [p - r, p + r] rounded outward to FP32 and its bin range
+__device__ inline void query_bins(const BinGrid &G, d3 p, double r, int *lo, int *hi)
+{
+    float qb[6];
+    qb[0] = f32_down(p.x - r);
+    qb[1] = f32_down(p.y - r);
+    qb[2] = f32_down(p.z - r);
+    qb[3] = f32_up(p.x + r);
+    qb[4] = f32_up(p.y + r);
+    qb[5] = f32_up(p.z + r);
+    box_bins(G, qb, lo, hi);
 }
 
 struct ExactArgs {
@@ -362,31 +541,35 @@ struct ExactArgs {
     const int32_t *bitems;
     const SurfParams *sp;
     const int32_t *list_near;
+    int32_t *list_side;
     CutCounters *cnt;
     int8_t *iblank;
     int32_t *list_hole;
     int kind;
     int pad;
-    double sfirst[3];
+    const Pose *pose;       // device pose of the surface
+    double first[3];        // first surface node, registration frame
 };
 
-// query box [p - r, p + r] rounded outward to FP32 and its bin range
-__device__ inline void query_bins(const BinGrid &G, d3 p, double r, float *qb, int *lo, int *hi)
-{
-    qb[0] = f32_down(p.x - r);
-    qb[1] = f32_down(p.y - r);
-    qb[2] = f32_down(p.z - r);
-    qb[3] = f32_up(p.x + r);
-    qb[4] = f32_up(p.y + r);
-    qb[5] = f32_up(p.z + r);
-    box_bins(G, qb, lo, hi);
-}
+constexpr int kFaceCap = 256;
 
-// a4 + a5: one wavefront per near element.
-__global__ __launch_bounds__(64) void k_exact(ExactArgs a)
+// a4: one wavefront per near element decides whether the surface intersects
+// it: some element-boundary / surface triangle pair closer than tol_hit
+// (Alg. cp2, with no truncation of the candidate faces), or the whole surface
+// inside the element.  Candidate faces that come within the element's
+// boundary-face boxes are collected in LDS; for each, the 384 triangle pairs
+// are screened by FP64 boxes and only the survivors get the exact test, one
+// pair per lane.
+__global__ __launch_bounds__(64) void k_hit(ExactArgs a)
 {
-    __shared__ double sN[81];
-    __shared__ TieRec rec[128];
+    __shared__ double sX[81];
+    __shared__ double sTB[48 * 6];   // element triangle boxes
+    __shared__ double sEF[6 * 6];    // element boundary-face boxes
+    __shared__ double sF[27];        // current face nodes
+    __shared__ double sFT[8 * 6];    // current face triangle boxes
+    __shared__ int sList[kFaceCap];
+    __shared__ short sPair[384];
+    __shared__ WalkLds L;
     const int lane = threadIdx.x;
     const BinGrid G = a.sp->grid;
     const int n_near = a.cnt->n_near;
@@ -394,196 +577,233 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a)
     for (int item = blockIdx.x; item < n_near; item += gridDim.x) {
         const int e = a.list_near[item];
         __syncthreads();
-        for (int k = lane; k < 81; k += 64) sN[k] = a.enodes[(int64_t)e * 81 + k];
+        for (int k = lane; k < 81; k += 64) sX[k] = a.enodes[(int64_t)e * 81 + k];
         __syncthreads();
-
-        // this lane's boundary triangle of the element (48 = 6 faces x 4 quads x 2)
-        const bool tv = lane < 48;
-        d3 T[3];
-        double tlo[3], thi[3];
-        {
-            const int t = tv ? lane : 0;
-            int uv[6];
-            quad_tri_uv((t >> 1) & 1, (t >> 2) & 1, t & 1, uv);
+        if (lane < 48) {
+            d3 T[3];
+            elem_tri(sX, lane, T);
+            double *b = sTB + 6 * lane;
+            b[0] = fmin(T[0].x, fmin(T[1].x, T[2].x)); b[3] = fmax(T[0].x, fmax(T[1].x, T[2].x));
+            b[1] = fmin(T[0].y, fmin(T[1].y, T[2].y)); b[4] = fmax(T[0].y, fmax(T[1].y, T[2].y));
+            b[2] = fmin(T[0].z, fmin(T[1].z, T[2].z)); b[5] = fmax(T[0].z, fmax(T[1].z, T[2].z));
+        } else if (lane < 54) {
+            const int f = lane - 48;
+            double *b = sEF + 6 * f;
             for (int k = 0; k < 3; ++k) {
-                int nd = elem_face_node(t >> 3, uv[2 * k], uv[2 * k + 1]);
-                T[k] = mk(sN[nd], sN[27 + nd], sN[54 + nd]);
+                b[k] = INFINITY;
+                b[3 + k] = -INFINITY;
             }
-            tlo[0] = fmin(T[0].x, fmin(T[1].x, T[2].x)); thi[0] = fmax(T[0].x, fmax(T[1].x, T[2].x));
-            tlo[1] = fmin(T[0].y, fmin(T[1].y, T[2].y)); thi[1] = fmax(T[0].y, fmax(T[1].y, T[2].y));
-            tlo[2] = fmin(T[0].z, fmin(T[1].z, T[2].z)); thi[2] = fmax(T[0].z, fmax(T[1].z, T[2].z));
+            for (int u = 0; u < 3; ++u)
+                for (int v = 0; v < 3; ++v) {
+                    const int nd = elem_face_node(f, u, v);
+                    for (int k = 0; k < 3; ++k) {
+                        b[k] = fmin(b[k], sX[27 * k + nd]);
+                        b[3 + k] = fmax(b[3 + k], sX[27 * k + nd]);
+                    }
+                }
         }
+        __syncthreads();
         float eb[6];
         for (int k = 0; k < 6; ++k) eb[k] = a.ebox[(int64_t)k * a.stride + e];
         int lo[3], hi[3];
         box_bins(G, eb, lo, hi);
-
-        // ---- hit test over the candidate faces (binned, deduplicated)
+        const BinRange R = make_range(lo, hi);
         bool hit = false;
-        for (int z = lo[2]; z <= hi[2] && !hit; ++z)
-            for (int y = lo[1]; y <= hi[1] && !hit; ++y)
-                for (int x = lo[0]; x <= hi[0] && !hit; ++x) {
-                    const int b = x + G.n[0] * (y + G.n[1] * z);
-                    const int j0 = a.bstart[b], j1 = a.bstart[b + 1];
-                    for (int base = j0; base < j1 && !hit; base += 64) {
-                        const int j = base + lane;
-                        int f = -1;
-                        bool pass = false;
-                        if (j < j1) {
-                            f = a.bitems[j];
-                            const float *fb = a.fbox + (int64_t)f * 6;
-                            int fl[3], fh[3];
-                            box_bins(G, fb, fl, fh);
-                            pass = x == max(lo[0], fl[0]) && y == max(lo[1], fl[1]) && z == max(lo[2], fl[2]) &&
-                                   box_overlap(eb, fb);
-                        }
-                        unsigned long long mask = __ballot(pass);
-                        while (mask && !hit) {
-                            const int l = __ffsll((long long)mask) - 1;
-                            mask &= mask - 1;
-                            const int fid = __shfl(f, l, 64);
-                            const double *P = a.pnodes + (int64_t)fid * 27;
-                            bool lh = false;
-                            for (int s = 0; s < 8; ++s) {
-                                d3 F[3];
-                                face_tri(P, s, F);
-                                double flo0 = fmin(F[0].x, fmin(F[1].x, F[2].x)), fhi0 = fmax(F[0].x, fmax(F[1].x, F[2].x));
-                                double flo1 = fmin(F[0].y, fmin(F[1].y, F[2].y)), fhi1 = fmax(F[0].y, fmax(F[1].y, F[2].y));
-                                double flo2 = fmin(F[0].z, fmin(F[1].z, F[2].z)), fhi2 = fmax(F[0].z, fmax(F[1].z, F[2].z));
-                                bool nearb = tv && flo0 - thi[0] < tol && tlo[0] - fhi0 < tol && flo1 - thi[1] < tol &&
-                                             tlo[1] - fhi1 < tol && flo2 - thi[2] < tol && tlo[2] - fhi2 < tol;
-                                if (nearb && !lh) lh = tri_tri_within(T, F, tol);
-                            }
-                            if (__ballot(lh)) hit = true;
+        int nlist = 0;
+        // exact test of the listed faces
+        auto flush = [&]() {
+            for (int i = 0; i < nlist && !hit; ++i) {
+                const int fid = sList[i];
+                if (lane < 27) sF[lane] = a.pnodes[(int64_t)fid * 27 + lane];
+                __syncthreads();
+                if (lane < 8) {
+                    d3 F[3];
+                    face_tri(sF, lane, F);
+                    double *bb = sFT + 6 * lane;
+                    bb[0] = fmin(F[0].x, fmin(F[1].x, F[2].x)); bb[3] = fmax(F[0].x, fmax(F[1].x, F[2].x));
+                    bb[1] = fmin(F[0].y, fmin(F[1].y, F[2].y)); bb[4] = fmax(F[0].y, fmax(F[1].y, F[2].y));
+                    bb[2] = fmin(F[0].z, fmin(F[1].z, F[2].z)); bb[5] = fmax(F[0].z, fmax(F[1].z, F[2].z));
+                }
+                __syncthreads();
+                // screen the 384 pairs (pair p = 48 * face_tri + elem_tri)
+                int np = 0;
+                for (int kk = 0; kk < 6; ++kk) {
+                    const int p = lane + 64 * kk;
+                    const int s = p / 48, t = p - 48 * s;
+                    const bool pass = boxes_within(sTB + 6 * t, sFT + 6 * s, tol);
+                    const unsigned long long m = __ballot(pass);
+                    if (pass) sPair[np + __popcll(m & ((1ull << lane) - 1ull))] = (short)p;
+                    np += __popcll(m);
+                }
+                __syncthreads();
+                bool lh = false;
+                for (int q = lane; q < np && !lh; q += 64) {
+                    const int p = sPair[q];
+                    const int s = p / 48, t = p - 48 * s;
+                    d3 T[3], F[3];
+                    elem_tri(sX, t, T);
+                    face_tri(sF, s, F);
+                    lh = tri_tri_within(T, F, tol);
+                }
+                if (__ballot(lh)) hit = true;
+                __syncthreads();
+            }
+            nlist = 0;
+        };
+        walk_faces(G, R, a.bstart, a.bitems, L, [&](int f, const int *xyz) {
+            bool pass = false;
+            if (f >= 0) {
+                const float *fb = a.fbox + (int64_t)f * 6;
+                if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb)) {
+                    const double fd[6] = {fb[0], fb[1], fb[2], fb[3], fb[4], fb[5]};
+                    for (int q = 0; q < 6; ++q) pass |= boxes_meet(sEF + 6 * q, fd);
+                }
+            }
+            const unsigned long long m = __ballot(pass);
+            if (pass) sList[nlist + __popcll(m & ((1ull << lane) - 1ull))] = f;
+            nlist += __popcll(m);
+            if (nlist > kFaceCap - 64) {
+                __syncthreads();
+                flush();
+            }
+            return hit;
+        });
+        if (!hit && nlist > 0) {
+            __syncthreads();
+            flush();
+        }
+        // the whole surface inside the element: ray parity of its first node
+        // against the element's 48 boundary triangles
+        const d3 sf = pose_apply(*a.pose, mk(a.first[0], a.first[1], a.first[2]));
+        if (!hit && sf.x >= eb[0] && sf.x <= eb[3] && sf.y >= eb[1] && sf.y <= eb[4] && sf.z >= eb[2] &&
+            sf.z <= eb[5]) {
+            int c = 0;
+            if (lane < 48) {
+                d3 T[3];
+                elem_tri(sX, lane, T);
+                c = ray_x_crosses(sf, T[0], T[1], T[2]);
+            }
+            if (__popcll(__ballot(c)) & 1) hit = true;
+        }
+        if (lane == 0) {
+            if (hit) {
+                atomicAdd(&a.cnt->n_hit, 1);
+                if (a.kind == OC_SURF_WALL && a.iblank[e] != OC_HOLE) {
+                    a.iblank[e] = OC_HOLE;
+                    a.list_hole[atomicAdd(&a.cnt->n_hole, 1)] = e;
+                }
+            } else {
+                a.list_side[atomicAdd(&a.cnt->n_side, 1)] = e;
+            }
+        }
+    }
+}
+
+// a5: near elements that the surface does not intersect lie on one side of
+// it; that side is the nearest-face side of the element's first node:
+// wavefront minimum of the point-to-triangle distance over the binned faces,
+// then the tie rule (largest |dot| of the unit point-to-surface vector with
+// the outward triangle normal; normals averaged only for equally visible
+// triangles of opposite sign).
+__global__ __launch_bounds__(64) void k_side(ExactArgs a)
+{
+    __shared__ TieRec rec[128];
+    __shared__ WalkLds L;
+    const int lane = threadIdx.x;
+    const BinGrid G = a.sp->grid;
+    const int n_side = a.cnt->n_side;
+    for (int item = blockIdx.x; item < n_side; item += gridDim.x) {
+        const int e = a.list_side[item];
+        const double *X = a.enodes + (int64_t)e * 81;
+        const d3 p = mk(X[0], X[27], X[54]);
+        float eb[6];
+        for (int k = 0; k < 6; ++k) eb[k] = a.ebox[(int64_t)k * a.stride + e];
+        // upper bound: nearest of the element's candidate faces
+        double u = INFINITY;
+        {
+            int lo[3], hi[3];
+            box_bins(G, eb, lo, hi);
+            const BinRange R = make_range(lo, hi);
+            walk_faces(G, R, a.bstart, a.bitems, L, [&](int f, const int *xyz) {
+                if (f >= 0) {
+                    const float *fb = a.fbox + (int64_t)f * 6;
+                    if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb) && point_box_dist(p, fb) < u)
+                        u = fmin(u, point_face_dist(p, a.pnodes + (int64_t)f * 27));
+                }
+                return false;
+            });
+        }
+        const double U = wave_min_d(u);
+        // every face whose box is within U of the node
+        double best = U;
+        {
+            int lo[3], hi[3];
+            query_bins(G, p, U, lo, hi);
+            const BinRange R = make_range(lo, hi);
+            walk_faces(G, R, a.bstart, a.bitems, L, [&](int f, const int *xyz) {
+                if (f >= 0) {
+                    const float *fb = a.fbox + (int64_t)f * 6;
+                    if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
+                        best = fmin(best, point_face_dist(p, a.pnodes + (int64_t)f * 27));
+                }
+                return false;
+            });
+        }
+        best = wave_min_d(best);
+        // tie set within best * (1 + 1e-9)
+        const double thr = best * (1.0 + 1e-9);
+        TieRec b1, b2;
+        b1.valid = b2.valid = 0;
+        {
+            int lo[3], hi[3];
+            query_bins(G, p, thr, lo, hi);
+            const BinRange R = make_range(lo, hi);
+            walk_faces(G, R, a.bstart, a.bitems, L, [&](int f, const int *xyz) {
+                if (f >= 0) {
+                    const float *fb = a.fbox + (int64_t)f * 6;
+                    if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= thr) {
+                        const double *P = a.pnodes + (int64_t)f * 27;
+                        for (int s = 0; s < 8; ++s) {
+                            d3 F[3];
+                            face_tri(P, s, F);
+                            const d3 v = p - closest_on_tri(p, F[0], F[1], F[2]);
+                            const double d = sqrt(dot(v, v));
+                            if (d > thr) continue;
+                            const d3 n = cross(F[1] - F[0], F[2] - F[0]);
+                            const double ln = sqrt(dot(n, n));
+                            TieRec rr;
+                            rr.vx = v.x;
+                            rr.vy = v.y;
+                            rr.vz = v.z;
+                            rr.nx = ln > 0 ? n.x / ln : 0.0;
+                            rr.ny = ln > 0 ? n.y / ln : 0.0;
+                            rr.nz = ln > 0 ? n.z / ln : 0.0;
+                            rr.dot = d > 0 ? (v.x * rr.nx + v.y * rr.ny + v.z * rr.nz) / d : 0.0;
+                            rr.absdot = fabs(rr.dot);
+                            rr.f = f;
+                            rr.s = s;
+                            rr.valid = 1;
+                            rr.pad = 0;
+                            tie_offer(b1, b2, rr);
                         }
                     }
                 }
-
-        // ---- the whole surface inside the element (ray parity of its first node)
-        const d3 sf = mk(a.sfirst[0], a.sfirst[1], a.sfirst[2]);
-        if (!hit && sf.x >= eb[0] && sf.x <= eb[3] && sf.y >= eb[1] && sf.y <= eb[4] && sf.z >= eb[2] &&
-            sf.z <= eb[5]) {
-            int c = tv ? ray_x_crosses(sf, T[0], T[1], T[2]) : 0;
-            if (__popcll(__ballot(c)) & 1) hit = true;
+                return false;
+            });
         }
-
-        int hole;
-        if (hit) {
-            hole = a.kind == OC_SURF_WALL;
-        } else {
-            // ---- nearest-face side of the element's first node
-            const d3 p = mk(sN[0], sN[27], sN[54]);
-            // initial bound: distance to the nearest face box corner region of
-            // the element's own box extent
-            double r = 0.0;
-            for (int k = 0; k < 3; ++k) r = fmax(r, fmax((double)eb[3 + k] - (double)eb[k], 0.0));
-            r = r * 1.7320508075688772 + 1e-12;
-            double best = INFINITY;
-            bool found = false;
-            // widen until some face is within the radius
-            for (int grow = 0; grow < 40 && !found; ++grow) {
-                float qb[6];
-                int ql[3], qh[3];
-                query_bins(G, p, r, qb, ql, qh);
-                for (int z = ql[2]; z <= qh[2]; ++z)
-                    for (int y = ql[1]; y <= qh[1]; ++y)
-                        for (int x = ql[0]; x <= qh[0]; ++x) {
-                            const int b = x + G.n[0] * (y + G.n[1] * z);
-                            const int j0 = a.bstart[b], j1 = a.bstart[b + 1];
-                            for (int base = j0; base < j1; base += 64) {
-                                const int j = base + lane;
-                                if (j < j1) {
-                                    const int f = a.bitems[j];
-                                    const float *fb = a.fbox + (int64_t)f * 6;
-                                    int fl[3], fh[3];
-                                    box_bins(G, fb, fl, fh);
-                                    if (x == max(ql[0], fl[0]) && y == max(ql[1], fl[1]) && z == max(ql[2], fl[2]) &&
-                                        point_box_dist(p, fb) <= fmin(r, best)) {
-                                        const double *P = a.pnodes + (int64_t)f * 27;
-                                        for (int s = 0; s < 8; ++s) {
-                                            d3 F[3];
-                                            face_tri(P, s, F);
-                                            d3 q = closest_on_tri(p, F[0], F[1], F[2]);
-                                            d3 w = p - q;
-                                            best = fmin(best, sqrt(dot(w, w)));
-                                        }
-                                    }
-                                }
-                                best = wave_min_d(best);
-                            }
-                        }
-                best = wave_min_d(best);
-                found = best <= r;
-                if (!found) r *= 2.0;
-            }
-            // ---- tie set within best*(1+1e-9): largest |dot| decides, normals
-            // averaged only for equally visible pairs of opposite sign
-            const double thr = best * (1.0 + 1e-9);
-            TieRec b1, b2;
-            b1.valid = b2.valid = 0;
-            {
-                float qb[6];
-                int ql[3], qh[3];
-                query_bins(G, p, thr, qb, ql, qh);
-                for (int z = ql[2]; z <= qh[2]; ++z)
-                    for (int y = ql[1]; y <= qh[1]; ++y)
-                        for (int x = ql[0]; x <= qh[0]; ++x) {
-                            const int b = x + G.n[0] * (y + G.n[1] * z);
-                            const int j0 = a.bstart[b], j1 = a.bstart[b + 1];
-                            for (int j = j0 + lane; j < j1; j += 64) {
-                                const int f = a.bitems[j];
-                                const float *fb = a.fbox + (int64_t)f * 6;
-                                int fl[3], fh[3];
-                                box_bins(G, fb, fl, fh);
-                                if (x != max(ql[0], fl[0]) || y != max(ql[1], fl[1]) || z != max(ql[2], fl[2]) ||
-                                    point_box_dist(p, fb) > thr)
-                                    continue;
-                                const double *P = a.pnodes + (int64_t)f * 27;
-                                for (int s = 0; s < 8; ++s) {
-                                    d3 F[3];
-                                    face_tri(P, s, F);
-                                    d3 q = closest_on_tri(p, F[0], F[1], F[2]);
-                                    d3 v = p - q;
-                                    double d = sqrt(dot(v, v));
-                                    if (d > thr) continue;
-                                    d3 n = cross(F[1] - F[0], F[2] - F[0]);
-                                    double ln = sqrt(dot(n, n));
-                                    TieRec rr;
-                                    rr.v[0] = v.x; rr.v[1] = v.y; rr.v[2] = v.z;
-                                    rr.n[0] = ln > 0 ? n.x / ln : 0.0;
-                                    rr.n[1] = ln > 0 ? n.y / ln : 0.0;
-                                    rr.n[2] = ln > 0 ? n.z / ln : 0.0;
-                                    rr.dot = d > 0 ? (v.x * rr.n[0] + v.y * rr.n[1] + v.z * rr.n[2]) / d : 0.0;
-                                    rr.absdot = fabs(rr.dot);
-                                    rr.f = f;
-                                    rr.s = s;
-                                    rr.valid = 1;
-                                    tie_offer(b1, b2, rr);
-                                }
-                            }
-                        }
-            }
-            rec[2 * lane] = b1;
-            rec[2 * lane + 1] = b2;
-            __syncthreads();
-            if (lane == 0) {
-                TieRec c1, c2;
-                c1.valid = c2.valid = 0;
-                for (int k = 0; k < 128; ++k)
-                    if (rec[k].valid) tie_offer(c1, c2, rec[k]);
-                double sg = c1.dot;
-                if (c2.valid && c1.absdot - c2.absdot <= 1e-9 && ((c1.dot > 0.0) != (c2.dot > 0.0))) {
-                    sg = c1.v[0] * (c1.n[0] + c2.n[0]) + c1.v[1] * (c1.n[1] + c2.n[1]) +
-                         c1.v[2] * (c1.n[2] + c2.n[2]);
-                }
-                rec[0].pad = (c1.valid && sg < 0.0) ? 1 : 0;
-            }
-            __syncthreads();
-            hole = rec[0].pad;
-        }
+        __syncthreads();
+        rec[2 * lane] = b1;
+        rec[2 * lane + 1] = b2;
+        __syncthreads();
         if (lane == 0) {
-            if (hit) atomicAdd(&a.cnt->n_hit, 1);
-            if (hole && a.iblank[e] != OC_HOLE) {
+            TieRec c1, c2;
+            c1.valid = c2.valid = 0;
+            for (int k = 0; k < 128; ++k)
+                if (rec[k].valid) tie_offer(c1, c2, rec[k]);
+            double sg = c1.dot;
+            if (c2.valid && c1.absdot - c2.absdot <= 1e-9 && ((c1.dot > 0.0) != (c2.dot > 0.0)))
+                sg = c1.vx * (c1.nx + c2.nx) + c1.vy * (c1.ny + c2.ny) + c1.vz * (c1.nz + c2.nz);
+            if (c1.valid && sg < 0.0 && a.iblank[e] != OC_HOLE) {
                 a.iblank[e] = OC_HOLE;
                 a.list_hole[atomicAdd(&a.cnt->n_hole, 1)] = e;
             }
@@ -591,44 +811,48 @@ __global__ __launch_bounds__(64) void k_exact(ExactArgs a)
     }
 }
 
-// a6: far elements (no candidate face): +x ray parity of the first node,
-// walking the column of bins that contains the ray.
-__global__ __launch_bounds__(kThreads) void k_ray(const double *__restrict__ enodes, const double *__restrict__ pnodes,
-                                                  const float *__restrict__ fbox, const SurfParams *__restrict__ sp,
-                                                  const int32_t *__restrict__ bstart,
-                                                  const int32_t *__restrict__ bitems,
-                                                  const int32_t *__restrict__ list_far, CutCounters *cnt,
-                                                  int8_t *__restrict__ iblank, int32_t *__restrict__ list_hole)
+// a6: far elements (no candidate face): +x ray parity of the first node over
+// the column of bins that holds the ray.
+__global__ __launch_bounds__(64) void k_ray(const double *__restrict__ enodes, const double *__restrict__ pnodes,
+                                            const float *__restrict__ fbox, const SurfParams *__restrict__ sp,
+                                            const int32_t *__restrict__ bstart, const int32_t *__restrict__ bitems,
+                                            const int32_t *__restrict__ list_far, CutCounters *cnt,
+                                            int8_t *__restrict__ iblank, int32_t *__restrict__ list_hole)
 {
+    __shared__ WalkLds L;
     const BinGrid G = sp->grid;
     const int n_far = cnt->n_far;
+    const int lane = threadIdx.x;
     const float sb[6] = {sp->sbox[0], sp->sbox[1], sp->sbox[2], sp->sbox[3], sp->sbox[4], sp->sbox[5]};
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_far; i += gridDim.x * blockDim.x) {
-        const int e = list_far[i];
-        const d3 p = mk(enodes[(int64_t)e * 81], enodes[(int64_t)e * 81 + 27], enodes[(int64_t)e * 81 + 54]);
+    for (int item = blockIdx.x; item < n_far; item += gridDim.x) {
+        const int e = list_far[item];
+        const double *X = enodes + (int64_t)e * 81;
+        const d3 p = mk(X[0], X[27], X[54]);
         if (p.y < sb[1] || p.y > sb[4] || p.z < sb[2] || p.z > sb[5] || p.x > sb[3]) continue;
-        const int iy = bin_of((float)p.y, G.o[1], G.inv[1], G.n[1]);
-        const int iz = bin_of((float)p.z, G.o[2], G.inv[2], G.n[2]);
-        const int ix0 = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
+        int lo[3], hi[3];
+        lo[0] = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
+        lo[1] = hi[1] = bin_of((float)p.y, G.o[1], G.inv[1], G.n[1]);
+        lo[2] = hi[2] = bin_of((float)p.z, G.o[2], G.inv[2], G.n[2]);
+        hi[0] = G.n[0] - 1;
+        const BinRange R = make_range(lo, hi);
         int par = 0;
-        for (int ix = ix0; ix < G.n[0]; ++ix) {
-            const int b = ix + G.n[0] * (iy + G.n[1] * iz);
-            for (int j = bstart[b]; j < bstart[b + 1]; ++j) {
-                const int f = bitems[j];
+        walk_faces(G, R, bstart, bitems, L, [&](int f, const int *xyz) {
+            if (f >= 0) {
                 const float *fb = fbox + (int64_t)f * 6;
-                if (ix != max(ix0, bin_of(fb[0], G.o[0], G.inv[0], G.n[0]))) continue;
-                if ((double)fb[1] > p.y || (double)fb[4] < p.y || (double)fb[2] > p.z || (double)fb[5] < p.z ||
-                    (double)fb[3] < p.x)
-                    continue;
-                const double *P = pnodes + (int64_t)f * 27;
-                for (int s = 0; s < 8; ++s) {
-                    d3 F[3];
-                    face_tri(P, s, F);
-                    par ^= ray_x_crosses(p, F[0], F[1], F[2]);
+                if (first_common_bin(G, fb, xyz, lo) && (double)fb[1] <= p.y && (double)fb[4] >= p.y &&
+                    (double)fb[2] <= p.z && (double)fb[5] >= p.z && (double)fb[3] >= p.x) {
+                    const double *P = pnodes + (int64_t)f * 27;
+                    for (int s = 0; s < 8; ++s) {
+                        d3 F[3];
+                        face_tri(P, s, F);
+                        par ^= ray_x_crosses(p, F[0], F[1], F[2]);
+                    }
                 }
             }
-        }
-        if (par && iblank[e] != OC_HOLE) {
+            return false;
+        });
+        const int odd = __popcll(__ballot(par)) & 1;
+        if (lane == 0 && odd && iblank[e] != OC_HOLE) {
             iblank[e] = OC_HOLE;
             list_hole[atomicAdd(&cnt->n_hole, 1)] = e;
         }
@@ -678,63 +902,112 @@ static unsigned grid_for(int64_t n, int per_block, unsigned cap)
 #define LAUNCH(name, grid, block, ...)                                                       \
     do {                                                                                     \
         size_t slot_;                                                                        \
-        time_begin(ctx, #name, &slot_);                                                      \
-        hipLaunchKernelGGL(name, grid, block, 0, ctx->stream, __VA_ARGS__);                  \
-        time_end(ctx, slot_);                                                                \
+        time_begin(ctx, st, #name, &slot_);                                                  \
+        hipLaunchKernelGGL(name, grid, block, 0, st, __VA_ARGS__);                           \
+        time_end(ctx, st, slot_);                                                            \
     } while (0)
 
-static oc_status cut_one_surface(oc_ctx *ctx, Grid &g, Surf &s, const Pose &pose, int8_t *iblank, bool first)
+static oc_status cut_one_surface(oc_slot *sl, Grid &g, int surf_id, Surf &s, const Pose *pose_dev, int8_t *iblank,
+                                 bool first, const int8_t *prev, double sweep)
 {
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    SurfWork &w = sl->sw.at(surf_id);
     const unsigned fb = grid_for(s.n_face, kThreads, 1u << 30);
-    LAUNCH(k_surf_init, dim3(1), dim3(64), s.params, ctx->counters);
-    LAUNCH(k_pose_faces, dim3(fb), dim3(kThreads), s.nodes, s.n_nodes, s.conn, s.n_face, pose, s.pnodes, s.fbox,
-           s.params);
-    LAUNCH(k_bins_setup, dim3(1), dim3(64), s.params, s.dmax, s.nb_max);
+    LAUNCH(k_surf_init, dim3(1), dim3(64), w.params, sl->counters);
+    LAUNCH(k_pose_faces, dim3(fb), dim3(kThreads), s.nodes, s.n_nodes, s.conn, s.n_face, pose_dev, w.pnodes, w.fbox,
+           w.params);
+    LAUNCH(k_bins_setup, dim3(1), dim3(64), w.params, s.dmax, s.nb_max);
     const int64_t bcap = (int64_t)s.nb_max * s.nb_max * s.nb_max;
-    LAUNCH(k_zero_i32, dim3(grid_for(bcap + 1, kThreads, 4096)), dim3(kThreads), s.bin_count, &s.params->n_bins,
+    LAUNCH(k_zero_i32, dim3(grid_for(bcap + 1, kThreads, 4096)), dim3(kThreads), w.bin_count, &w.params->n_bins,
            (int64_t)0);
-    LAUNCH(k_bin_count, dim3(fb), dim3(kThreads), s.fbox, s.n_face, s.params, s.bin_count);
-    OC_TRY(scan_exclusive(ctx, s.bin_count, s.bin_start, bcap, &s.params->n_bins, s.scan_tmp));
-    LAUNCH(k_bin_fill, dim3(fb), dim3(kThreads), s.fbox, s.n_face, s.params, s.bin_start, s.bin_count, s.bin_items);
+    LAUNCH(k_bin_count, dim3(fb), dim3(kThreads), w.fbox, s.n_face, w.params, w.bin_count);
+    OC_TRY(scan_exclusive(ctx, st, w.bin_count, w.bin_start, bcap, &w.params->n_bins, w.scan_tmp));
+    LAUNCH(k_bin_fill, dim3(fb), dim3(kThreads), w.fbox, s.n_face, w.params, w.bin_start, w.bin_count, w.bin_items);
 
-    LAUNCH(k_filter, dim3(grid_for(g.n_elem, kThreads * 4, 8192)), dim3(kThreads), g.ebox, g.n_elem, g.ebox_stride, s.params,
-           iblank, first ? 1 : 0, g.list_inbox, ctx->counters);
-    LAUNCH(k_candidates, dim3(1024), dim3(kThreads), g.ebox, g.ebox_stride, s.fbox, s.params, s.bin_start, s.bin_items,
-           g.list_inbox, g.list_near, g.list_far, ctx->counters);
+    LAUNCH(k_filter, dim3(grid_for(g.n_elem, kThreads * 4, 8192)), dim3(kThreads), g.ebox, g.n_elem, g.ebox_stride,
+           w.params, iblank, first ? 1 : 0, sl->list_inbox, sl->counters);
+    LAUNCH(k_candidates, dim3(8192), dim3(64), g.ebox, g.ebox_stride, w.fbox, w.params, w.bin_start, w.bin_items,
+           sl->list_inbox, sl->list_near, sl->list_far, sl->counters, prev, sweep, iblank, sl->list_hole);
     ExactArgs ea;
     ea.enodes = g.enodes;
     ea.ebox = g.ebox;
     ea.stride = g.ebox_stride;
-    ea.pnodes = s.pnodes;
-    ea.fbox = s.fbox;
-    ea.bstart = s.bin_start;
-    ea.bitems = s.bin_items;
-    ea.sp = s.params;
-    ea.list_near = g.list_near;
-    ea.cnt = ctx->counters;
+    ea.pnodes = w.pnodes;
+    ea.fbox = w.fbox;
+    ea.bstart = w.bin_start;
+    ea.bitems = w.bin_items;
+    ea.sp = w.params;
+    ea.list_near = sl->list_near;
+    ea.list_side = sl->list_side;
+    ea.cnt = sl->counters;
     ea.iblank = iblank;
-    ea.list_hole = g.list_hole;
+    ea.list_hole = sl->list_hole;
     ea.kind = s.kind;
     ea.pad = 0;
-    // first node of the surface, posed
-    for (int i = 0; i < 3; ++i)
-        ea.sfirst[i] = pose.r[3 * i] * s.first[0] + pose.r[3 * i + 1] * s.first[1] + pose.r[3 * i + 2] * s.first[2] +
-                       pose.t[i];
-    LAUNCH(k_exact, dim3(4096), dim3(64), ea);
-    LAUNCH(k_ray, dim3(256), dim3(kThreads), g.enodes, s.pnodes, s.fbox, s.params, s.bin_start, s.bin_items,
-           g.list_far, ctx->counters, iblank, g.list_hole);
+    ea.pose = pose_dev;
+    for (int i = 0; i < 3; ++i) ea.first[i] = s.first[i];
+    LAUNCH(k_hit, dim3(8192), dim3(64), ea);
+    LAUNCH(k_side, dim3(8192), dim3(64), ea);
+    LAUNCH(k_ray, dim3(8192), dim3(64), g.enodes, w.pnodes, w.fbox, w.params, w.bin_start, w.bin_items,
+           sl->list_far, sl->counters, iblank, sl->list_hole);
     OC_HIP(hipGetLastError());
     return OC_OK;
 }
 
-oc_status cut_run(oc_ctx *ctx, Grid &g, Surf **surfs, const Pose *poses, int n_surf, int8_t *iblank)
+struct PosePack {
+    Pose p[8];
+    int n;
+};
+
+__global__ void k_set_poses(Pose *dst, PosePack pk)
 {
-    LAUNCH(k_reset_counters, dim3(1), dim3(64), ctx->counters);
+    if (blockIdx.x == 0 && (int)threadIdx.x < pk.n) dst[threadIdx.x] = pk.p[threadIdx.x];
+}
+
+// Host poses into the slot's device pose slots, ordered on the slot stream
+// (the values travel as kernel arguments, so the host array may be reused
+// as soon as this returns).
+oc_status set_poses(oc_slot *sl, int first, const double *host, int n)
+{
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    if (first < 0 || n < 0 || first + n > kPoseSlots) {
+        set_error("too many poses");
+        return OC_EINVAL;
+    }
+    for (int k0 = 0; k0 < n; k0 += 8) {
+        PosePack pk;
+        pk.n = std::min(8, n - k0);
+        for (int k = 0; k < pk.n; ++k) {
+            for (int i = 0; i < 9; ++i) pk.p[k].r[i] = host[12 * (k0 + k) + i];
+            for (int i = 0; i < 3; ++i) pk.p[k].t[i] = host[12 * (k0 + k) + 9 + i];
+        }
+        LAUNCH(k_set_poses, dim3(1), dim3(64), sl->poses + first + k0, pk);
+    }
+    OC_HIP(hipGetLastError());
+    return OC_OK;
+}
+
+oc_status cut_run(oc_slot *sl, Grid &g, const int *surf_ids, Surf **surfs, const Pose *poses_dev, int n_surf,
+                  int8_t *iblank, const int8_t *prev, double sweep)
+{
+    if (prev && n_surf != 1) {
+        set_error("warm start needs exactly one cutting surface");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    OC_TRY(slot_reserve_grid(sl, g));
+    for (int k = 0; k < n_surf; ++k) OC_TRY(slot_reserve_surf(sl, surf_ids[k], *surfs[k]));
+    sl->last_n_elem = g.n_elem;
+    LAUNCH(k_reset_counters, dim3(1), dim3(64), sl->counters);
     if (n_surf == 0)
         LAUNCH(k_fill_i8, dim3(grid_for(g.n_elem, kThreads, 4096)), dim3(kThreads), iblank, g.n_elem,
                (int8_t)OC_FIELD);
-    for (int k = 0; k < n_surf; ++k) OC_TRY(cut_one_surface(ctx, g, *surfs[k], poses[k], iblank, k == 0));
-    LAUNCH(k_fringe, dim3(1024), dim3(kThreads), g.nbr, g.list_hole, ctx->counters, iblank);
+    for (int k = 0; k < n_surf; ++k)
+        OC_TRY(cut_one_surface(sl, g, surf_ids[k], *surfs[k], poses_dev + k, iblank, k == 0, prev, sweep));
+    LAUNCH(k_fringe, dim3(1024), dim3(kThreads), g.nbr, sl->list_hole, sl->counters, iblank);
     if (g.n_overset > 0)
         LAUNCH(k_overset_fringe, dim3(grid_for(g.n_overset, kThreads, 4096)), dim3(kThreads), g.overset, g.n_overset,
                iblank);

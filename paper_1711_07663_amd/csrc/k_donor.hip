@@ -31,8 +31,11 @@ __device__ inline void lag2(double s, double *l, double *dl)
     dl[2] = s + 0.5;
 }
 
-// x(xi) and J = dx/dxi of an element stored as x[27], y[27], z[27]
-// (sum factorisation: contract the xi index first, then eta, then zeta).
+__device__ inline double pick3(int i, double a, double b, double c) { return i == 0 ? a : (i == 1 ? b : c); }
+
+// x(xi) and J = dx/dxi of an element stored as x[27], y[27], z[27].  The
+// nine node rows (fixed eta, zeta index) are streamed one at a time so the
+// 81 coordinates never have to be resident in registers together.
 template <bool WITH_J>
 __device__ inline void q2_map(const double *__restrict__ X, const double *xi, double *x, double *J)
 {
@@ -40,37 +43,41 @@ __device__ inline void q2_map(const double *__restrict__ X, const double *xi, do
     lag2(xi[0], la, da);
     lag2(xi[1], lb, db);
     lag2(xi[2], lc, dc);
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        const double *C = X + 27 * d;
-        double s = 0.0, s_a = 0.0, s_b = 0.0, s_c = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double t = 0.0, t_a = 0.0, t_b = 0.0;
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                const double v0 = C[3 * b + 9 * c], v1 = C[1 + 3 * b + 9 * c], v2 = C[2 + 3 * b + 9 * c];
-                const double u = v0 * la[0] + v1 * la[1] + v2 * la[2];
-                t += u * lb[b];
-                if (WITH_J) {
-                    const double u_a = v0 * da[0] + v1 * da[1] + v2 * da[2];
-                    t_a += u_a * lb[b];
-                    t_b += u * db[b];
-                }
-            }
-            s += t * lc[c];
-            if (WITH_J) {
-                s_a += t_a * lc[c];
-                s_b += t_b * lc[c];
-                s_c += t * dc[c];
-            }
-        }
-        x[d] = s;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    double j0 = 0.0, j1 = 0.0, j2 = 0.0, j3 = 0.0, j4 = 0.0, j5 = 0.0, j6 = 0.0, j7 = 0.0, j8 = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < 9; ++r) {
+        const int b = r % 3, c = r / 3;
+        const double wb = pick3(b, lb[0], lb[1], lb[2]), wc = pick3(c, lc[0], lc[1], lc[2]);
+        const double w = wb * wc;
+        const double *R = X + 3 * r;
+        const double x0 = R[0], x1 = R[1], x2 = R[2];
+        const double y0 = R[27], y1 = R[28], y2 = R[29];
+        const double z0 = R[54], z1 = R[55], z2 = R[56];
+        const double ux = x0 * la[0] + x1 * la[1] + x2 * la[2];
+        const double uy = y0 * la[0] + y1 * la[1] + y2 * la[2];
+        const double uz = z0 * la[0] + z1 * la[1] + z2 * la[2];
+        ax += ux * w;
+        ay += uy * w;
+        az += uz * w;
         if (WITH_J) {
-            J[3 * d + 0] = s_a;
-            J[3 * d + 1] = s_b;
-            J[3 * d + 2] = s_c;
+            const double wdb = pick3(b, db[0], db[1], db[2]) * wc;
+            const double wdc = wb * pick3(c, dc[0], dc[1], dc[2]);
+            const double vx = x0 * da[0] + x1 * da[1] + x2 * da[2];
+            const double vy = y0 * da[0] + y1 * da[1] + y2 * da[2];
+            const double vz = z0 * da[0] + z1 * da[1] + z2 * da[2];
+            j0 += vx * w; j1 += ux * wdb; j2 += ux * wdc;
+            j3 += vy * w; j4 += uy * wdb; j5 += uy * wdc;
+            j6 += vz * w; j7 += uz * wdb; j8 += uz * wdc;
         }
+    }
+    x[0] = ax;
+    x[1] = ay;
+    x[2] = az;
+    if (WITH_J) {
+        J[0] = j0; J[1] = j1; J[2] = j2;
+        J[3] = j3; J[4] = j4; J[5] = j5;
+        J[6] = j6; J[7] = j7; J[8] = j8;
     }
 }
 
@@ -78,11 +85,13 @@ __device__ inline void q2_map(const double *__restrict__ X, const double *xi, do
 // before each step) or the clamped step is <= 1e-14; at most
 // OC_NEWTON_MAXIT iterations; contained if converged and
 // max|xi| <= 1 + OC_CONTAIN_TOL.  The 3x3 system is solved with the adjugate.
-__device__ inline bool newton_q2(const double *__restrict__ X, d3 p, double diam, double *xi)
+__device__ inline bool newton_q2(const double *__restrict__ X, d3 p, double diam, double *xi, int &iters)
 {
     xi[0] = xi[1] = xi[2] = 0.0;
     bool conv = false;
+#pragma unroll 1
     for (int it = 0; it < OC_NEWTON_MAXIT; ++it) {
+        ++iters;
         double x[3], J[9];
         q2_map<true>(X, xi, x, J);
         const double r0 = p.x - x[0], r1 = p.y - x[1], r2 = p.z - x[2];
@@ -291,85 +300,254 @@ __global__ __launch_bounds__(kT) void k_fr_write(const int8_t *__restrict__ ibla
     }
 }
 
-// a9: Gauss point k = a + 3b + 9c of fringe element list[i], posed
+// a9: Gauss point k = a + 3b + 9c of fringe element list[i / 27], posed.
+// The number of fringe elements is read from the device (nfr); at most cap
+// points are written; n_out receives 27 * nfr.
 __global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__ enodes,
-                                                      const int32_t *__restrict__ list, int64_t n_pts, Pose pose,
-                                                      double *__restrict__ pts, int32_t *__restrict__ src)
+                                                      const int32_t *__restrict__ list, const int32_t *__restrict__ nfr,
+                                                      int64_t cap, const Pose *__restrict__ pose_dev,
+                                                      double *__restrict__ pts, int32_t *__restrict__ src,
+                                                      int32_t *__restrict__ n_out)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pts) return;
-    const int64_t q = i / 27;
-    const int k = (int)(i - q * 27);
-    const int e = list[q];
-    const double g = 0.7745966692414834;  // sqrt(3/5), 3-point Gauss-Legendre
-    const double xi[3] = {(k % 3 - 1) * g, ((k / 3) % 3 - 1) * g, (k / 9 - 1) * g};
-    double x[3];
-    q2_map<false>(enodes + (int64_t)e * 81, xi, x, nullptr);
-    const d3 w = pose_apply(pose, mk(x[0], x[1], x[2]));
-    pts[3 * i] = w.x;
-    pts[3 * i + 1] = w.y;
-    pts[3 * i + 2] = w.z;
-    if (src) src[i] = e;
+    const int64_t total = (int64_t)(*nfr) * 27;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && n_out) *n_out = (int32_t)total;
+    const int64_t n = total < cap ? total : cap;
+    const Pose pose = *pose_dev;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = i / 27;
+        const int k = (int)(i - q * 27);
+        const int e = list[q];
+        const double g = 0.7745966692414834;  // sqrt(3/5), 3-point Gauss-Legendre
+        const double xi[3] = {(k % 3 - 1) * g, ((k / 3) % 3 - 1) * g, (k / 9 - 1) * g};
+        double x[3];
+        q2_map<false>(enodes + (int64_t)e * 81, xi, x, nullptr);
+        const d3 w = pose_apply(pose, mk(x[0], x[1], x[2]));
+        pts[3 * i] = w.x;
+        pts[3 * i + 1] = w.y;
+        pts[3 * i + 2] = w.z;
+        if (src) src[i] = e;
+    }
 }
 
-// a10 + a11: donor search, one thread per point
-__global__ __launch_bounds__(kT) void k_donor(const double *__restrict__ enodes, const float *__restrict__ cbox,
+constexpr int kDonorCache = 32;   // element node sets staged in LDS at a time
+constexpr int kDonorHash = 256;   // open-addressing table of the wavefront's candidate ids
+constexpr int kPairCap = 64 * kDonorCache;
+
+__device__ inline bool box_has(const float *__restrict__ c, d3 p)
+{
+    return p.x >= (double)c[0] && p.y >= (double)c[1] && p.z >= (double)c[2] && p.x <= (double)c[3] &&
+           p.y <= (double)c[4] && p.z <= (double)c[5];
+}
+
+__device__ inline unsigned hash_slot(int e) { return ((unsigned)e * 2654435761u) >> 24; }  // 8 bits
+
+// a10 + a11: one wavefront per 64 points.  The candidates of a point are the
+// elements of its bin whose control-net box contains it; as in Sec. 4.3 the
+// containment tests (Newton) run after the search.  The wavefront's distinct
+// candidates are gathered in an LDS table, sorted by id and staged in LDS 32
+// at a time; for each staged batch the (point, element) pairs are listed
+// element by element and run 64 at a time.  A point keeps the lowest id that
+// contains it (LDS atomic minimum), so points resolved in a batch skip the
+// later (higher-id) batches.  If the table overflows, the wavefront falls
+// back to per-lane Newton in ascending id order from global memory.
+__global__ __launch_bounds__(64) void k_donor(const double *__restrict__ enodes, const float *__restrict__ cbox,
                                               const double *__restrict__ ediam, BinGrid G,
                                               const int32_t *__restrict__ bstart, const int32_t *__restrict__ bitems,
-                                              Pose pose, const double *__restrict__ pts, int64_t n,
-                                              int32_t *__restrict__ donor, double *__restrict__ ref)
+                                              const Pose *__restrict__ pose_dev, const double *__restrict__ pts,
+                                              int64_t cap, const int32_t *__restrict__ n_dev,
+                                              int32_t *__restrict__ donor, double *__restrict__ ref,
+                                              DonorCounters *dcnt)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const d3 p = pose_inverse(pose, mk(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]));
-    const int bx = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
-    const int by = bin_of((float)p.y, G.o[1], G.inv[1], G.n[1]);
-    const int bz = bin_of((float)p.z, G.o[2], G.inv[2], G.n[2]);
-    const int64_t b = bx + (int64_t)G.n[0] * (by + (int64_t)G.n[1] * bz);
-    int32_t d = -1;
-    double r[3] = {NAN, NAN, NAN};
-    for (int j = bstart[b]; j < bstart[b + 1]; ++j) {
-        const int e = bitems[j];
-        const float *c = cbox + (int64_t)e * 6;
-        if (p.x < (double)c[0] || p.y < (double)c[1] || p.z < (double)c[2] || p.x > (double)c[3] ||
-            p.y > (double)c[4] || p.z > (double)c[5])
-            continue;
-        double xi[3];
-        if (newton_q2(enodes + (int64_t)e * 81, p, ediam[e], xi)) {
-            d = e;
-            r[0] = xi[0];
-            r[1] = xi[1];
-            r[2] = xi[2];
-            break;
+    const Pose pose = *pose_dev;
+    const int64_t n = n_dev ? ((int64_t)*n_dev < cap ? (int64_t)*n_dev : cap) : cap;
+    __shared__ int sKey[kDonorHash];
+    __shared__ int sList[kDonorHash];
+    __shared__ int sSorted[kDonorHash];
+    __shared__ double sNodes[kDonorCache * 81];
+    __shared__ double sP[64 * 3];
+    __shared__ int sBest[64];
+    __shared__ double sXi[64 * 3];
+    __shared__ unsigned short sPair[kPairCap];
+    __shared__ int sFull;
+    int n_solve = 0, n_iter = 0, n_orph = 0;
+    const int lane = threadIdx.x;
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
+        const int64_t i = base + lane;
+        const bool valid = i < n;
+        d3 p = mk(0.0, 0.0, 0.0);
+        int j0 = 0, j1 = 0;
+        if (valid) {
+            p = pose_inverse(pose, mk(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]));
+            const int bx = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
+            const int by = bin_of((float)p.y, G.o[1], G.inv[1], G.n[1]);
+            const int bz = bin_of((float)p.z, G.o[2], G.inv[2], G.n[2]);
+            const int64_t b = bx + (int64_t)G.n[0] * (by + (int64_t)G.n[1] * bz);
+            j0 = bstart[b];
+            j1 = bstart[b + 1];
         }
+        for (int k = lane; k < kDonorHash; k += 64) sKey[k] = -1;
+        sP[3 * lane] = p.x;
+        sP[3 * lane + 1] = p.y;
+        sP[3 * lane + 2] = p.z;
+        sBest[lane] = 0x7fffffff;
+        sXi[3 * lane] = sXi[3 * lane + 1] = sXi[3 * lane + 2] = NAN;
+        if (lane == 0) sFull = 0;
+        __syncthreads();
+        // distinct candidates of the wavefront
+        bool lost = false;
+        for (int j = j0; j < j1; ++j) {
+            const int e = bitems[j];
+            if (!box_has(cbox + (int64_t)e * 6, p)) continue;
+            unsigned h = hash_slot(e);
+            bool in = false;
+            for (int probe = 0; probe < kDonorHash; ++probe, h = (h + 1) & (kDonorHash - 1)) {
+                const int old = atomicCAS(&sKey[h], -1, e);
+                if (old == -1 || old == e) {
+                    in = true;
+                    break;
+                }
+            }
+            lost |= !in;
+        }
+        if (lost) sFull = 1;
+        __syncthreads();
+        if (!sFull) {
+            // dense list of the distinct ids, then ascending order (rank sort)
+            int cnt = 0;
+            for (int k = 0; k < kDonorHash / 64; ++k) {
+                const int key = sKey[lane + 64 * k];
+                const unsigned long long m = __ballot(key >= 0);
+                if (key >= 0) sList[cnt + __popcll(m & ((1ull << lane) - 1ull))] = key;
+                cnt += __popcll(m);
+            }
+            __syncthreads();
+            for (int k = lane; k < cnt; k += 64) {
+                const int v = sList[k];
+                int r = 0;
+                for (int q = 0; q < cnt; ++q) r += sList[q] < v;
+                sSorted[r] = v;
+            }
+            __syncthreads();
+            for (int c0 = 0; c0 < cnt; c0 += kDonorCache) {
+                const int nb = min(kDonorCache, cnt - c0);
+                for (int k = lane; k < nb * 81; k += 64) {
+                    const int sl = k / 81;
+                    sNodes[k] = enodes[(int64_t)sSorted[c0 + sl] * 81 + (k - 81 * sl)];
+                }
+                // pairs (lane, slot) element by element, unresolved points only
+                int np = 0;
+                const bool open = valid && sBest[lane] == 0x7fffffff;
+                for (int k = 0; k < nb; ++k) {
+                    const bool pass = open && box_has(cbox + (int64_t)sSorted[c0 + k] * 6, p);
+                    const unsigned long long m = __ballot(pass);
+                    if (pass) sPair[np + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)(lane | (k << 6));
+                    np += __popcll(m);
+                }
+                __syncthreads();
+                for (int q0 = 0; q0 < np; q0 += 64) {
+                    const int q = q0 + lane;
+                    bool ok = false;
+                    int e = -1, l = 0;
+                    double xi[3] = {0.0, 0.0, 0.0};
+                    if (q < np) {
+                        const int pr = sPair[q];
+                        l = pr & 63;
+                        const int k = pr >> 6;
+                        e = sSorted[c0 + k];
+                        const d3 pp = mk(sP[3 * l], sP[3 * l + 1], sP[3 * l + 2]);
+                        ++n_solve;
+                        ok = newton_q2(sNodes + 81 * k, pp, ediam[e], xi, n_iter);
+                        if (ok) atomicMin(&sBest[l], e);
+                    }
+                    __syncthreads();
+                    if (ok && sBest[l] == e) {
+                        sXi[3 * l] = xi[0];
+                        sXi[3 * l + 1] = xi[1];
+                        sXi[3 * l + 2] = xi[2];
+                    }
+                    __syncthreads();
+                }
+            }
+        } else {
+            // overflow: each lane runs its candidates in ascending id order
+            int32_t d = 0x7fffffff;
+            double x0 = NAN, x1 = NAN, x2 = NAN;
+            for (int j = j0; j < j1; ++j) {
+                const int e = bitems[j];
+                if (!box_has(cbox + (int64_t)e * 6, p)) continue;
+                double xi[3];
+                ++n_solve;
+                if (newton_q2(enodes + (int64_t)e * 81, p, ediam[e], xi, n_iter)) {
+                    d = e;
+                    x0 = xi[0];
+                    x1 = xi[1];
+                    x2 = xi[2];
+                    break;
+                }
+            }
+            sBest[lane] = d;
+            sXi[3 * lane] = x0;
+            sXi[3 * lane + 1] = x1;
+            sXi[3 * lane + 2] = x2;
+        }
+        __syncthreads();
+        if (valid) {
+            const int bst = sBest[lane];
+            const int32_t d = bst == 0x7fffffff ? -1 : bst;
+            donor[i] = d;
+            ref[3 * i] = sXi[3 * lane];
+            ref[3 * i + 1] = sXi[3 * lane + 1];
+            ref[3 * i + 2] = sXi[3 * lane + 2];
+            n_orph += d < 0;
+        }
+        __syncthreads();
     }
-    donor[i] = d;
-    ref[3 * i] = r[0];
-    ref[3 * i + 1] = r[1];
-    ref[3 * i + 2] = r[2];
+    // per-wavefront totals, one atomic each
+    unsigned long long a = n_solve, b = n_iter, cc = n_orph;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        a += __shfl_xor(a, d, 64);
+        b += __shfl_xor(b, d, 64);
+        cc += __shfl_xor(cc, d, 64);
+    }
+    if (lane == 0) {
+        atomicAdd(&dcnt->n_newton, a);
+        atomicAdd(&dcnt->n_iter, b);
+        atomicAdd(&dcnt->n_orphan, cc);
+    }
+}
+
+__global__ void k_donor_reset(DonorCounters *c, int64_t cap, const int32_t *n_dev)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t n = n_dev ? ((int64_t)*n_dev < cap ? (int64_t)*n_dev : cap) : cap;
+        c->n_points = (unsigned long long)n;
+        c->n_newton = c->n_iter = c->n_orphan = 0ull;
+    }
 }
 
 // ------------------------------------------------------------ host side --
 #define LAUNCH(name, grid, block, ...)                                                       \
     do {                                                                                     \
         size_t slot_;                                                                        \
-        time_begin(ctx, #name, &slot_);                                                      \
-        hipLaunchKernelGGL(name, grid, block, 0, ctx->stream, __VA_ARGS__);                  \
-        time_end(ctx, slot_);                                                                \
+        time_begin(ctx, st, #name, &slot_);                                                  \
+        hipLaunchKernelGGL(name, grid, block, 0, st, __VA_ARGS__);                           \
+        time_end(ctx, st, slot_);                                                            \
     } while (0)
 
 static unsigned blocks(int64_t n, int per) { return (unsigned)((n + per - 1) / per > 0 ? (n + per - 1) / per : 1); }
 
 oc_status grid_build_device(oc_ctx *ctx, Grid &g, const int32_t *conn_dev, const double *nodes_dev)
 {
+    hipStream_t st = ctx->reg_stream;
     LAUNCH(k_gather_nodes, dim3(blocks(g.n_elem * 27, kT)), dim3(kT), nodes_dev, conn_dev, g.n_elem, g.enodes);
     int *bad = ctx->dev_scalar;
-    OC_HIP(hipMemsetAsync(bad, 0, sizeof(int), ctx->stream));
+    OC_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
     LAUNCH(k_elem_boxes, dim3(blocks(g.n_elem, kT)), dim3(kT), g.enodes, g.n_elem, g.ebox_stride, g.ebox, g.cbox,
            g.ediam, bad);
     int hbad = 0;
-    OC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    OC_HIP(hipStreamSynchronize(ctx->stream));
+    OC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    OC_HIP(hipStreamSynchronize(st));
     if (hbad) {
         set_error(std::to_string(hbad) + " element(s) with a non-positive Jacobian at the centre");
         return OC_EGEOM;
@@ -379,6 +557,7 @@ oc_status grid_build_device(oc_ctx *ctx, Grid &g, const int32_t *conn_dev, const
 
 oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g)
 {
+    hipStream_t st = ctx->reg_stream;
     // grid box from the control-net boxes (host reduction at registration)
     std::vector<float> cb((size_t)g.n_elem * 6);
     OC_HIP(hipMemcpy(cb.data(), g.cbox, cb.size() * sizeof(float), hipMemcpyDeviceToHost));
@@ -406,53 +585,62 @@ oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g)
     OC_TRY(dev_alloc(ctx, g.owned, sizeof(int32_t) * (nb + 1), (void **)&count));
     OC_TRY(dev_alloc(ctx, g.owned, sizeof(int32_t) * (nb + 1), (void **)&start));
     OC_TRY(dev_alloc(ctx, g.owned, sizeof(int32_t) * scan_tmp_ints(nb), (void **)&tmp));
-    OC_HIP(hipMemsetAsync(count, 0, sizeof(int32_t) * (nb + 1), ctx->stream));
+    OC_HIP(hipMemsetAsync(count, 0, sizeof(int32_t) * (nb + 1), st));
     LAUNCH(k_dbin_count, dim3(blocks(g.n_elem, kT)), dim3(kT), g.cbox, g.n_elem, g.dgrid, count);
-    OC_TRY(scan_exclusive(ctx, count, start, nb, nullptr, tmp));
+    OC_TRY(scan_exclusive(ctx, st, count, start, nb, nullptr, tmp));
     int32_t total = 0;
-    OC_HIP(hipMemcpyAsync(&total, start + nb, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    OC_HIP(hipStreamSynchronize(ctx->stream));
+    OC_HIP(hipMemcpyAsync(&total, start + nb, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    OC_HIP(hipStreamSynchronize(st));
     g.n_ditems = total;
     OC_TRY(dev_alloc(ctx, g.owned, sizeof(int32_t) * std::max<int64_t>(total, 1), (void **)&g.dbin_items));
-    OC_HIP(hipMemsetAsync(count, 0, sizeof(int32_t) * (nb + 1), ctx->stream));
+    OC_HIP(hipMemsetAsync(count, 0, sizeof(int32_t) * (nb + 1), st));
     LAUNCH(k_dbin_fill, dim3(blocks(g.n_elem, kT)), dim3(kT), g.cbox, g.n_elem, g.dgrid, start, count, g.dbin_items);
     LAUNCH(k_dbin_sort, dim3(blocks(nb, kT)), dim3(kT), start, nb, g.dbin_items);
     g.dbin_start = start;
-    OC_HIP(hipStreamSynchronize(ctx->stream));
+    OC_HIP(hipStreamSynchronize(st));
     OC_HIP(hipGetLastError());
     return OC_OK;
 }
 
-oc_status fringe_points_run(oc_ctx *ctx, Grid &g, const Pose &pose, const int8_t *iblank, double *pts, int64_t cap,
-                            int64_t *n_out, int32_t *src)
+oc_status fringe_points_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const int8_t *iblank, double *pts,
+                            int64_t cap, int32_t *n_dev, int64_t *n_host, int32_t *src)
 {
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    OC_TRY(slot_reserve_grid(sl, g));
     const int64_t nt = (g.n_elem + kFrTile - 1) / kFrTile;
-    int32_t *tcount = g.fr_blocksum, *toff = g.fr_blocksum + (nt + 1);
-    int32_t *tmp = g.fr_blocksum + 2 * (nt + 1);
+    int32_t *tcount = sl->fr_tiles, *toff = sl->fr_tiles + (nt + 1);
+    int32_t *tmp = sl->fr_tiles + 2 * (nt + 1);
+    int32_t *cnt_out = n_dev ? n_dev : sl->scalar;
     LAUNCH(k_fr_count, dim3((unsigned)std::max<int64_t>(nt, 1)), dim3(kT), iblank, g.n_elem, tcount);
-    OC_TRY(scan_exclusive(ctx, tcount, toff, nt, nullptr, tmp));
-    LAUNCH(k_fr_write, dim3((unsigned)std::max<int64_t>(nt, 1)), dim3(kT), iblank, g.n_elem, toff, g.list_fringe);
-    int32_t nfr = 0;
-    OC_HIP(hipMemcpyAsync(&nfr, toff + nt, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
-    OC_HIP(hipStreamSynchronize(ctx->stream));
-    const int64_t npts = (int64_t)nfr * 27;
-    *n_out = npts;
-    if (npts > cap) {
-        set_error("oc_fringe_points: capacity " + std::to_string(cap) + " < " + std::to_string(npts) + " points");
-        return OC_ECAPACITY;
-    }
-    if (npts > 0)
-        LAUNCH(k_fringe_points, dim3(blocks(npts, kT)), dim3(kT), g.enodes, g.list_fringe, npts, pose, pts, src);
+    OC_TRY(scan_exclusive(ctx, st, tcount, toff, nt, nullptr, tmp));
+    LAUNCH(k_fr_write, dim3((unsigned)std::max<int64_t>(nt, 1)), dim3(kT), iblank, g.n_elem, toff, sl->list_fringe);
+    const int64_t cap_pts = std::min<int64_t>(cap, 27 * g.n_elem);
+    LAUNCH(k_fringe_points, dim3(std::min<unsigned>(blocks(std::max<int64_t>(cap_pts, 1), kT), 8192u)), dim3(kT),
+           g.enodes, sl->list_fringe, toff + nt, cap, pose_dev, pts, src, cnt_out);
     OC_HIP(hipGetLastError());
+    if (n_host) {
+        int32_t n = 0;
+        OC_HIP(hipMemcpyAsync(&n, cnt_out, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        OC_HIP(hipStreamSynchronize(st));
+        *n_host = n;
+        if (n > cap) {
+            set_error("oc_fringe_points: capacity " + std::to_string(cap) + " < " + std::to_string(n) + " points");
+            return OC_ECAPACITY;
+        }
+    }
     return OC_OK;
 }
 
-oc_status donor_run(oc_ctx *ctx, Grid &g, const Pose &pose, const double *pts, int64_t n, int32_t *donor,
-                    double *ref)
+oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pts, int64_t cap, const int32_t *n_dev,
+                    int32_t *donor, double *ref)
 {
-    if (n <= 0) return OC_OK;
-    LAUNCH(k_donor, dim3(blocks(n, kT)), dim3(kT), g.enodes, g.cbox, g.ediam, g.dgrid, g.dbin_start, g.dbin_items,
-           pose, pts, n, donor, ref);
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    LAUNCH(k_donor_reset, dim3(1), dim3(64), sl->dcounters, cap, n_dev);
+    if (cap <= 0) return OC_OK;
+    LAUNCH(k_donor, dim3((unsigned)std::min<int64_t>((cap + 63) / 64, 16384)), dim3(64), g.enodes, g.cbox, g.ediam,
+           g.dgrid, g.dbin_start, g.dbin_items, pose_dev, pts, cap, n_dev, donor, ref, sl->dcounters);
     OC_HIP(hipGetLastError());
     return OC_OK;
 }

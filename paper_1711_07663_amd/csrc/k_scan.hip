@@ -117,8 +117,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *__re
 
 int64_t scan_tmp_ints(int64_t cap) { return (cap + kScanTile - 1) / kScanTile + 1; }
 
-oc_status scan_exclusive(oc_ctx *ctx, const int32_t *in, int32_t *out, int64_t cap, const int *n_dev,
-                         int32_t *tmp)
+oc_status scan_exclusive(oc_ctx *ctx, hipStream_t st, const int32_t *in, int32_t *out, int64_t cap,
+                         const int *n_dev, int32_t *tmp)
 {
     int64_t nt = (cap + kScanTile - 1) / kScanTile;
     if (nt < 1) nt = 1;
@@ -127,12 +127,12 @@ oc_status scan_exclusive(oc_ctx *ctx, const int32_t *in, int32_t *out, int64_t c
         return OC_EINVAL;
     }
     size_t slot;
-    time_begin(ctx, "scan", &slot);
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nt), dim3(kScanThreads), 0, ctx->stream, in, n_dev, cap, tmp);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, ctx->stream, tmp, (int)nt);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(kScanThreads), 0, ctx->stream, in, out, n_dev, cap,
-                       tmp, (int)nt);
-    time_end(ctx, slot);
+    time_begin(ctx, st, "scan", &slot);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nt), dim3(kScanThreads), 0, st, in, n_dev, cap, tmp);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tmp, (int)nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(kScanThreads), 0, st, in, out, n_dev, cap, tmp,
+                       (int)nt);
+    time_end(ctx, st, slot);
     OC_HIP(hipGetLastError());
     return OC_OK;
 }

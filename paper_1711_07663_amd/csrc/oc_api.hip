@@ -42,7 +42,7 @@ void dev_free_all(oc_ctx *ctx, std::vector<DevBuf> &owner)
     owner.clear();
 }
 
-void time_begin(oc_ctx *ctx, const char *name, size_t *slot)
+void time_begin(oc_ctx *ctx, hipStream_t st, const char *name, size_t *slot)
 {
     *slot = std::numeric_limits<size_t>::max();
     if (!ctx->timing) return;
@@ -53,15 +53,91 @@ void time_begin(oc_ctx *ctx, const char *name, size_t *slot)
     }
     TimingRec r{ctx->event_pool[ctx->event_next], ctx->event_pool[ctx->event_next + 1], name};
     ctx->event_next += 2;
-    (void)hipEventRecord(r.a, ctx->stream);
+    (void)hipEventRecord(r.a, st);
     *slot = ctx->trecs.size();
     ctx->trecs.push_back(r);
 }
 
-void time_end(oc_ctx *ctx, size_t slot)
+void time_end(oc_ctx *ctx, hipStream_t st, size_t slot)
 {
     if (slot == std::numeric_limits<size_t>::max()) return;
-    (void)hipEventRecord(ctx->trecs[slot].b, ctx->stream);
+    (void)hipEventRecord(ctx->trecs[slot].b, st);
+}
+
+// ------------------------------------------------------------------ slots --
+static oc_status slot_alloc_lists(oc_slot *sl, int64_t n_elem)
+{
+    oc_ctx *ctx = sl->ctx;
+    const size_t ne = (size_t)std::max<int64_t>(n_elem, 1);
+    int32_t **lists[6] = {&sl->list_inbox, &sl->list_near, &sl->list_far, &sl->list_hole, &sl->list_fringe,
+                          &sl->list_side};
+    for (auto l : lists) OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * ne, (void **)l));
+    const int64_t nt = (n_elem + 4095) / 4096;
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * (2 * (nt + 1) + scan_tmp_ints(nt) + 8), (void **)&sl->fr_tiles));
+    sl->list_cap = n_elem;
+    sl->fr_tiles_cap = nt;
+    return OC_OK;
+}
+
+static oc_status slot_alloc_surf(oc_slot *sl, int surf_id, const Surf &s)
+{
+    oc_ctx *ctx = sl->ctx;
+    SurfWork w;
+    const int64_t bcap = (int64_t)s.nb_max * s.nb_max * s.nb_max + 1;
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(double) * 27 * s.n_face, (void **)&w.pnodes));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(float) * 6 * s.n_face, (void **)&w.fbox));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * bcap, (void **)&w.bin_count));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * bcap, (void **)&w.bin_start));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * 8 * s.n_face, (void **)&w.bin_items));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * scan_tmp_ints(bcap), (void **)&w.scan_tmp));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(SurfParams), (void **)&w.params));
+    sl->sw[surf_id] = w;
+    return OC_OK;
+}
+
+oc_status slot_init(oc_ctx *ctx, oc_slot *sl, bool grow)
+{
+    sl->ctx = ctx;
+    sl->grow = grow;
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(CutCounters), (void **)&sl->counters));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(DonorCounters), (void **)&sl->dcounters));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(Pose) * kPoseSlots, (void **)&sl->poses));
+    OC_TRY(dev_alloc(ctx, sl->owned, 256, (void **)&sl->scalar));
+    OC_HIP(hipMemset(sl->counters, 0, sizeof(CutCounters)));
+    OC_HIP(hipMemset(sl->dcounters, 0, sizeof(DonorCounters)));
+    return OC_OK;
+}
+
+void slot_free(oc_slot *sl)
+{
+    if (!sl) return;
+    (void)hipStreamSynchronize(sl->stream);
+    dev_free_all(sl->ctx, sl->owned);
+    sl->sw.clear();
+}
+
+// The default slot grows on demand (its calls may allocate); slots made by
+// oc_slot_create are sized once and refuse larger work.
+oc_status slot_reserve_grid(oc_slot *sl, const Grid &g)
+{
+    if (g.n_elem <= sl->list_cap) return OC_OK;
+    if (!sl->grow) {
+        set_error("slot was not created for a grid of " + std::to_string(g.n_elem) + " elements");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipStreamSynchronize(sl->stream));
+    // the old lists stay allocated until the slot is freed (simple, rare)
+    return slot_alloc_lists(sl, g.n_elem);
+}
+
+oc_status slot_reserve_surf(oc_slot *sl, int surf_id, const Surf &s)
+{
+    if (sl->sw.count(surf_id)) return OC_OK;
+    if (!sl->grow) {
+        set_error("slot was not created for surface " + std::to_string(surf_id));
+        return OC_EINVAL;
+    }
+    return slot_alloc_surf(sl, surf_id, s);
 }
 
 static Pose to_pose(const double *p)
@@ -164,13 +240,20 @@ oc_status oc_create(oc_ctx **out, const oc_config *cfg)
         set_error("oc_create: invalid device");
         return OC_EINVAL;
     }
-    if (hipMalloc(&ctx->counters, sizeof(CutCounters)) != hipSuccess ||
-        hipMalloc(&ctx->dev_scalar, 64) != hipSuccess) {
+    if (hipMalloc(&ctx->dev_scalar, 64) != hipSuccess) {
         delete ctx;
         set_error("oc_create: allocation failed");
         return OC_ENOMEM;
     }
-    (void)hipMemset(ctx->counters, 0, sizeof(CutCounters));
+    ctx->dflt = new oc_slot();
+    oc_status st = slot_init(ctx, ctx->dflt, true);
+    if (st != OC_OK) {
+        slot_free(ctx->dflt);
+        delete ctx->dflt;
+        (void)hipFree(ctx->dev_scalar);
+        delete ctx;
+        return st;
+    }
     *out = ctx;
     return OC_OK;
 }
@@ -179,12 +262,17 @@ oc_status oc_destroy(oc_ctx *ctx)
 {
     if (!ctx) return OC_OK;
     (void)hipSetDevice(ctx->device);
-    (void)hipStreamSynchronize(ctx->stream);
+    for (auto sl : ctx->slots) {
+        slot_free(sl);
+        delete sl;
+    }
+    ctx->slots.clear();
+    slot_free(ctx->dflt);
+    delete ctx->dflt;
     for (auto &g : ctx->grids)
         if (g) dev_free_all(ctx, g->owned);
     for (auto &s : ctx->surfs)
         if (s) dev_free_all(ctx, s->owned);
-    (void)hipFree(ctx->counters);
     (void)hipFree(ctx->dev_scalar);
     for (auto ev : ctx->event_pool) (void)hipEventDestroy(ev);
     delete ctx;
@@ -197,7 +285,7 @@ oc_status oc_set_stream(oc_ctx *ctx, void *stream)
         set_error("oc_set_stream: null context");
         return OC_EINVAL;
     }
-    ctx->stream = (hipStream_t)stream;
+    ctx->dflt->stream = (hipStream_t)stream;
     return OC_OK;
 }
 
@@ -258,13 +346,6 @@ oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, co
     if ((st = upload(ctx, g->owned, nbr.data(), nbr.size(), &g->nbr)) != OC_OK) return fail(st);
     g->n_overset = (int64_t)overset.size();
     if ((st = upload(ctx, g->owned, overset.data(), overset.size(), &g->overset)) != OC_OK) return fail(st);
-    int32_t **lists[5] = {&g->list_inbox, &g->list_near, &g->list_far, &g->list_hole, &g->list_fringe};
-    for (auto l : lists)
-        if ((st = dev_alloc(ctx, g->owned, sizeof(int32_t) * ne, (void **)l)) != OC_OK) return fail(st);
-    g->n_fr_blocks = (n_elem + 4095) / 4096;
-    if ((st = dev_alloc(ctx, g->owned, sizeof(int32_t) * (2 * (g->n_fr_blocks + 1) + scan_tmp_ints(g->n_fr_blocks) + 8),
-                        (void **)&g->fr_blocksum)) != OC_OK)
-        return fail(st);
     if ((st = grid_build_device(ctx, *g, conn_dev, nodes_dev)) != OC_OK) return fail(st);
     dev_free_all(ctx, tmp);
     if ((st = grid_build_donor_bins(ctx, *g)) != OC_OK) return fail(st);
@@ -358,6 +439,9 @@ oc_status oc_register_cut_surface(oc_ctx *ctx, const double *nodes, int64_t n_no
     if (ctx->surf_bins > 0) nb = std::min(nb, ctx->surf_bins);
     s->nb_max = nb;
     for (int d = 0; d < 3; ++d) s->first[d] = nodes[d];
+    for (int64_t i = 0; i < n_nodes; ++i)
+        s->rmax = std::max(s->rmax, std::sqrt(nodes[3 * i] * nodes[3 * i] + nodes[3 * i + 1] * nodes[3 * i + 1] +
+                                              nodes[3 * i + 2] * nodes[3 * i + 2]));
     std::vector<double> soa((size_t)n_nodes * 3);
     for (int64_t i = 0; i < n_nodes; ++i)
         for (int d = 0; d < 3; ++d) soa[(size_t)(d * n_nodes + i)] = nodes[3 * i + d];
@@ -366,19 +450,8 @@ oc_status oc_register_cut_surface(oc_ctx *ctx, const double *nodes, int64_t n_no
         dev_free_all(ctx, s->owned);
         return e;
     };
-    const int64_t bcap = (int64_t)nb * nb * nb + 1;
     if ((st = upload(ctx, s->owned, soa.data(), soa.size(), &s->nodes)) != OC_OK) return fail(st);
     if ((st = upload(ctx, s->owned, conn, (size_t)n_face * 9, &s->conn)) != OC_OK) return fail(st);
-    if ((st = dev_alloc(ctx, s->owned, sizeof(double) * 27 * n_face, (void **)&s->pnodes)) != OC_OK) return fail(st);
-    if ((st = dev_alloc(ctx, s->owned, sizeof(float) * 6 * n_face, (void **)&s->fbox)) != OC_OK) return fail(st);
-    if ((st = dev_alloc(ctx, s->owned, sizeof(int32_t) * bcap, (void **)&s->bin_count)) != OC_OK) return fail(st);
-    if ((st = dev_alloc(ctx, s->owned, sizeof(int32_t) * bcap, (void **)&s->bin_start)) != OC_OK) return fail(st);
-    if ((st = dev_alloc(ctx, s->owned, sizeof(int32_t) * 8 * n_face, (void **)&s->bin_items)) != OC_OK)
-        return fail(st);
-    if ((st = dev_alloc(ctx, s->owned, sizeof(int32_t) * scan_tmp_ints(bcap), (void **)&s->scan_tmp)) != OC_OK)
-        return fail(st);
-    if ((st = dev_alloc(ctx, s->owned, sizeof(SurfParams), (void **)&s->params)) != OC_OK) return fail(st);
-    OC_HIP(hipMemset(s->bin_count, 0, sizeof(int32_t) * bcap));
     ctx->surfs.push_back(std::move(s));
     *surf_id = (int32_t)ctx->surfs.size() - 1;
     return OC_OK;
@@ -394,36 +467,71 @@ static oc_status get_grid(oc_ctx *ctx, int32_t id, Grid **g)
     return OC_OK;
 }
 
-oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
-                       int8_t *iblank_out)
+static oc_status collect_surfs(oc_ctx *ctx, const int32_t *surf_ids, int32_t n_surf, std::vector<Surf *> &ss)
 {
-    if (!ctx || !iblank_out || n_surf < 0 || (n_surf > 0 && (!surf_ids || !poses))) {
-        set_error("oc_cut: invalid arguments");
-        return OC_EINVAL;
-    }
-    if (((uintptr_t)iblank_out & 3) != 0) {
-        set_error("oc_cut: iblank_out must be 4-byte aligned");
-        return OC_EINVAL;
-    }
-    OC_HIP(hipSetDevice(ctx->device));
-    Grid *g;
-    OC_TRY(get_grid(ctx, grid_id, &g));
-    std::vector<Surf *> ss;
-    std::vector<Pose> ps;
     for (int k = 0; k < n_surf; ++k) {
         if (surf_ids[k] < 0 || surf_ids[k] >= (int32_t)ctx->surfs.size() || !ctx->surfs[surf_ids[k]]) {
             set_error("unknown surface id " + std::to_string(surf_ids[k]));
             return OC_ENOTFOUND;
         }
+        ss.push_back(ctx->surfs[surf_ids[k]].get());
+    }
+    return OC_OK;
+}
+
+static oc_status read_cut_info(oc_slot *sl, oc_cut_info *info)
+{
+    CutCounters c;
+    OC_HIP(hipMemcpyAsync(&c, sl->counters, sizeof c, hipMemcpyDeviceToHost, sl->stream));
+    OC_HIP(hipStreamSynchronize(sl->stream));
+    info->n_elem = sl->last_n_elem;
+    info->n_inbox = c.n_inbox;
+    info->n_near = c.n_near;
+    info->n_far = c.n_far;
+    info->n_hit = c.n_hit;
+    info->n_hole = c.n_hole;
+    info->n_cand_pairs = (int64_t)c.n_cand_pairs;
+    return OC_OK;
+}
+
+static oc_status read_donor_info(oc_slot *sl, oc_donor_info *info)
+{
+    DonorCounters c;
+    OC_HIP(hipMemcpyAsync(&c, sl->dcounters, sizeof c, hipMemcpyDeviceToHost, sl->stream));
+    OC_HIP(hipStreamSynchronize(sl->stream));
+    info->n_points = (int64_t)c.n_points;
+    info->n_newton = (int64_t)c.n_newton;
+    info->n_iter = (int64_t)c.n_iter;
+    info->n_orphan = (int64_t)c.n_orphan;
+    return OC_OK;
+}
+
+static bool aligned4(const void *p) { return ((uintptr_t)p & 3) == 0; }
+
+oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
+                       int8_t *iblank_out)
+{
+    if (!ctx || !iblank_out || n_surf < 0 || n_surf > kPoseSlots - 2 || (n_surf > 0 && (!surf_ids || !poses))) {
+        set_error("oc_cut: invalid arguments");
+        return OC_EINVAL;
+    }
+    if (!aligned4(iblank_out)) {
+        set_error("oc_cut: iblank_out must be 4-byte aligned");
+        return OC_EINVAL;
+    }
+    for (int k = 0; k < n_surf; ++k)
         if (!pose_ok(poses + 12 * k)) {
             set_error("oc_cut: non-finite pose");
             return OC_EINVAL;
         }
-        ss.push_back(ctx->surfs[surf_ids[k]].get());
-        ps.push_back(to_pose(poses + 12 * k));
-    }
-    ctx->last_n_elem = g->n_elem;
-    return cut_run(ctx, *g, ss.data(), ps.data(), n_surf, iblank_out);
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, 0, poses, n_surf));
+    return cut_run(sl, *g, surf_ids, ss.data(), sl->poses, n_surf, iblank_out);
 }
 
 oc_status oc_cut(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pose[12], int8_t *iblank_out)
@@ -438,17 +546,17 @@ oc_status oc_last_cut_info(oc_ctx *ctx, oc_cut_info *info)
         return OC_EINVAL;
     }
     OC_HIP(hipSetDevice(ctx->device));
-    CutCounters c;
-    OC_HIP(hipMemcpyAsync(&c, ctx->counters, sizeof c, hipMemcpyDeviceToHost, ctx->stream));
-    OC_HIP(hipStreamSynchronize(ctx->stream));
-    info->n_elem = ctx->last_n_elem;
-    info->n_inbox = c.n_inbox;
-    info->n_near = c.n_near;
-    info->n_far = c.n_far;
-    info->n_hit = c.n_hit;
-    info->n_hole = c.n_hole;
-    info->n_cand_pairs = (int64_t)c.n_cand_pairs;
-    return OC_OK;
+    return read_cut_info(ctx->dflt, info);
+}
+
+oc_status oc_last_donor_info(oc_ctx *ctx, oc_donor_info *info)
+{
+    if (!ctx || !info) {
+        set_error("oc_last_donor_info: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    return read_donor_info(ctx->dflt, info);
 }
 
 oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int8_t *iblank,
@@ -461,7 +569,9 @@ oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[
     OC_HIP(hipSetDevice(ctx->device));
     Grid *g;
     OC_TRY(get_grid(ctx, grid_id, &g));
-    return fringe_points_run(ctx, *g, to_pose(grid_pose), iblank, points_out, cap, n_out, src_out);
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, kPoseSlots - 2, grid_pose, 1));
+    return fringe_points_run(sl, *g, sl->poses + kPoseSlots - 2, iblank, points_out, cap, nullptr, n_out, src_out);
 }
 
 oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12], const double *points,
@@ -474,7 +584,210 @@ oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_
     OC_HIP(hipSetDevice(ctx->device));
     Grid *g;
     OC_TRY(get_grid(ctx, donor_grid_id, &g));
-    return donor_run(ctx, *g, to_pose(grid_pose), points, n, donor_out, ref_out);
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, kPoseSlots - 1, grid_pose, 1));
+    return donor_run(sl, *g, sl->poses + kPoseSlots - 1, points, n, nullptr, donor_out, ref_out);
+}
+
+// Bound on the distance any point of surface s travels between two poses:
+// rotation angle of R_b R_a^T times the largest node radius, plus the
+// distance between the two offsets (a screw motion between the poses).
+static double sweep_bound(const Surf &s, const double *a, const double *b)
+{
+    double tr = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) tr += b[3 * i + k] * a[3 * i + k];   // trace(R_b R_a^T)
+    const double c = std::max(-1.0, std::min(1.0, 0.5 * (tr - 1.0)));
+    const double th = std::acos(c);
+    const double dt = std::sqrt((b[9] - a[9]) * (b[9] - a[9]) + (b[10] - a[10]) * (b[10] - a[10]) +
+                                (b[11] - a[11]) * (b[11] - a[11]));
+    return (th * s.rmax + dt) * (1.0 + 1e-9) + 1e-12;
+}
+
+oc_status oc_sweep_bound(oc_ctx *ctx, int32_t surf_id, const double pose_a[12], const double pose_b[12], double *out)
+{
+    if (!ctx || !out || !pose_ok(pose_a) || !pose_ok(pose_b)) {
+        set_error("oc_sweep_bound: invalid arguments");
+        return OC_EINVAL;
+    }
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, &surf_id, 1, ss));
+    *out = sweep_bound(*ss[0], pose_a, pose_b);
+    return OC_OK;
+}
+
+oc_status oc_cut_warm(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pose[12], const double prev_pose[12],
+                      const int8_t *prev_iblank, int8_t *iblank_out)
+{
+    if (!ctx || !iblank_out || !prev_iblank || !aligned4(iblank_out) || !pose_ok(pose) || !pose_ok(prev_pose) ||
+        prev_iblank == iblank_out) {
+        set_error("oc_cut_warm: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, &surf_id, 1, ss));
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, 0, pose, 1));
+    return cut_run(sl, *g, &surf_id, ss.data(), sl->poses, 1, iblank_out, prev_iblank,
+                   sweep_bound(*ss[0], prev_pose, pose));
+}
+
+// ------------------------------------------------------------- slot API --
+oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, const int32_t *surf_ids,
+                         int32_t n_surfs, oc_slot **out)
+{
+    if (!ctx || !out || n_grids < 0 || n_surfs < 0 || (n_grids && !grid_ids) || (n_surfs && !surf_ids)) {
+        set_error("oc_slot_create: invalid arguments");
+        return OC_EINVAL;
+    }
+    *out = nullptr;
+    OC_HIP(hipSetDevice(ctx->device));
+    int64_t ne = 1;
+    for (int k = 0; k < n_grids; ++k) {
+        Grid *g;
+        OC_TRY(get_grid(ctx, grid_ids[k], &g));
+        ne = std::max(ne, g->n_elem);
+    }
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, surf_ids, n_surfs, ss));
+    oc_slot *sl = new oc_slot();
+    oc_status st = slot_init(ctx, sl, false);
+    if (st == OC_OK) st = slot_alloc_lists(sl, ne);
+    for (int k = 0; k < n_surfs && st == OC_OK; ++k)
+        if (!sl->sw.count(surf_ids[k])) st = slot_alloc_surf(sl, surf_ids[k], *ss[k]);
+    if (st != OC_OK) {
+        slot_free(sl);
+        delete sl;
+        return st;
+    }
+    ctx->slots.push_back(sl);
+    *out = sl;
+    return OC_OK;
+}
+
+oc_status oc_slot_destroy(oc_slot *sl)
+{
+    if (!sl) return OC_OK;
+    oc_ctx *ctx = sl->ctx;
+    (void)hipSetDevice(ctx->device);
+    for (size_t k = 0; k < ctx->slots.size(); ++k)
+        if (ctx->slots[k] == sl) {
+            ctx->slots.erase(ctx->slots.begin() + k);
+            break;
+        }
+    slot_free(sl);
+    delete sl;
+    return OC_OK;
+}
+
+oc_status oc_slot_set_stream(oc_slot *sl, void *hip_stream)
+{
+    if (!sl) {
+        set_error("oc_slot_set_stream: null slot");
+        return OC_EINVAL;
+    }
+    sl->stream = (hipStream_t)hip_stream;
+    return OC_OK;
+}
+
+oc_status oc_slot_bytes(oc_slot *sl, int64_t *bytes)
+{
+    if (!sl || !bytes) {
+        set_error("oc_slot_bytes: invalid arguments");
+        return OC_EINVAL;
+    }
+    int64_t b = 0;
+    for (auto &d : sl->owned) b += (int64_t)d.bytes;
+    *bytes = b;
+    return OC_OK;
+}
+
+oc_status oc_slot_cut(oc_slot *sl, int32_t grid_id, const int32_t *surf_ids, const double *poses_dev, int32_t n_surf,
+                      int8_t *iblank_out)
+{
+    if (!sl || !iblank_out || n_surf < 0 || (n_surf > 0 && (!surf_ids || !poses_dev)) || !aligned4(iblank_out) ||
+        ((uintptr_t)poses_dev & 7)) {
+        set_error("oc_slot_cut: invalid arguments");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
+    return cut_run(sl, *g, surf_ids, ss.data(), reinterpret_cast<const Pose *>(poses_dev), n_surf, iblank_out);
+}
+
+oc_status oc_slot_cut_warm(oc_slot *sl, int32_t grid_id, int32_t surf_id, const double *pose_dev, double sweep,
+                           const int8_t *prev_iblank, int8_t *iblank_out)
+{
+    if (!sl || !pose_dev || !prev_iblank || !iblank_out || !aligned4(iblank_out) || ((uintptr_t)pose_dev & 7) ||
+        !(sweep >= 0.0) || prev_iblank == iblank_out) {
+        set_error("oc_slot_cut_warm: invalid arguments");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, &surf_id, 1, ss));
+    return cut_run(sl, *g, &surf_id, ss.data(), reinterpret_cast<const Pose *>(pose_dev), 1, iblank_out,
+                   prev_iblank, sweep);
+}
+
+oc_status oc_slot_fringe_points(oc_slot *sl, int32_t grid_id, const double *pose_dev, const int8_t *iblank,
+                                double *points_out, int64_t cap, int32_t *n_dev, int32_t *src_out)
+{
+    if (!sl || !pose_dev || !iblank || !n_dev || cap < 0 || (cap > 0 && !points_out) || ((uintptr_t)pose_dev & 7)) {
+        set_error("oc_slot_fringe_points: invalid arguments");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    return fringe_points_run(sl, *g, reinterpret_cast<const Pose *>(pose_dev), iblank, points_out, cap, n_dev,
+                             nullptr, src_out);
+}
+
+oc_status oc_slot_donor_search(oc_slot *sl, int32_t donor_grid_id, const double *pose_dev, const double *points,
+                               int64_t cap, const int32_t *n_dev, int32_t *donor_out, double *ref_out)
+{
+    if (!sl || !pose_dev || cap < 0 || (cap > 0 && (!points || !donor_out || !ref_out)) ||
+        ((uintptr_t)pose_dev & 7)) {
+        set_error("oc_slot_donor_search: invalid arguments");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, donor_grid_id, &g));
+    return donor_run(sl, *g, reinterpret_cast<const Pose *>(pose_dev), points, cap, n_dev, donor_out, ref_out);
+}
+
+oc_status oc_slot_cut_info(oc_slot *sl, oc_cut_info *info)
+{
+    if (!sl || !info) {
+        set_error("oc_slot_cut_info: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(sl->ctx->device));
+    return read_cut_info(sl, info);
+}
+
+oc_status oc_slot_donor_info(oc_slot *sl, oc_donor_info *info)
+{
+    if (!sl || !info) {
+        set_error("oc_slot_donor_info: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(sl->ctx->device));
+    return read_donor_info(sl, info);
 }
 
 oc_status oc_timing(oc_ctx *ctx, int32_t enable)
@@ -483,7 +796,7 @@ oc_status oc_timing(oc_ctx *ctx, int32_t enable)
         set_error("oc_timing: null context");
         return OC_EINVAL;
     }
-    OC_HIP(hipStreamSynchronize(ctx->stream));
+    OC_HIP(hipDeviceSynchronize());
     ctx->timing = enable != 0;
     ctx->trecs.clear();
     ctx->event_next = 0;
@@ -496,7 +809,7 @@ oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len)
         set_error("oc_timing_report: invalid arguments");
         return OC_EINVAL;
     }
-    OC_HIP(hipStreamSynchronize(ctx->stream));
+    OC_HIP(hipDeviceSynchronize());
     std::map<std::string, std::pair<double, int>> acc;
     for (auto &r : ctx->trecs) {
         float ms = 0.f;

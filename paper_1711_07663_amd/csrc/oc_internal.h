@@ -52,8 +52,13 @@ struct SurfParams {
 
 // Per-cut counters (device).
 struct CutCounters {
-    int n_inbox, n_near, n_far, n_hit, n_hole, pad0;
+    int n_inbox, n_near, n_far, n_hit, n_hole, n_side;
     unsigned long long n_cand_pairs;
+};
+
+// Per-donor-search counters (device).
+struct DonorCounters {
+    unsigned long long n_points, n_newton, n_iter, n_orphan;
 };
 
 // -------------------------------------------------------- device buffers --
@@ -77,11 +82,6 @@ struct Grid {
     int32_t *dbin_start = nullptr; // [n_dbins + 1]
     int32_t *dbin_items = nullptr; // element ids, ascending within a bin
     int64_t n_dbins = 0, n_ditems = 0;
-    // workspace of cuts on this grid
-    int32_t *list_inbox = nullptr, *list_near = nullptr, *list_far = nullptr, *list_hole = nullptr;
-    int32_t *list_fringe = nullptr;
-    int32_t *fr_blocksum = nullptr;  // fringe compaction block sums
-    int64_t n_fr_blocks = 0;
     std::vector<DevBuf> owned;
 };
 
@@ -93,22 +93,53 @@ struct Surf {
     double *nodes = nullptr;     // [3][n_nodes] SoA registration frame
     int32_t *conn = nullptr;     // [n_face][9]
     double first[3] = {0, 0, 0}; // first node (registration frame)
-    // per-cut workspace
-    double *pnodes = nullptr;    // [n_face][27]: x[9], y[9], z[9] posed
-    float *fbox = nullptr;       // [n_face][6] inflated outward FP32 boxes
+    double rmax = 0.0;           // largest node distance from the registration origin
+    std::vector<DevBuf> owned;
+};
+
+// Per-request scratch of one surface in a slot.
+struct SurfWork {
+    double *pnodes = nullptr;      // [n_face][27]: x[9], y[9], z[9] posed
+    float *fbox = nullptr;         // [n_face][6] inflated outward FP32 boxes
     int32_t *bin_count = nullptr;  // [nb_max^3 + 1]
     int32_t *bin_start = nullptr;  // [nb_max^3 + 1]
     int32_t *bin_items = nullptr;  // [8 * n_face]
     int32_t *scan_tmp = nullptr;
     SurfParams *params = nullptr;
-    std::vector<DevBuf> owned;
 };
 
-// Pose passed by value to kernels.
+// Pose passed to kernels through device memory.
 struct Pose {
     double r[9];
     double t[3];
 };
+
+constexpr int kPoseSlots = 64;
+
+}  // namespace oc
+
+// A slot: the per-request device scratch of the cut / fringe / donor calls
+// and the stream they are ordered on.  Everything is allocated when the
+// slot is created, so the calls made through a slot never allocate.
+struct oc_slot {
+    oc_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    bool grow = false;                 // the context's default slot grows on demand
+    int64_t list_cap = 0;              // element lists capacity
+    int32_t *list_inbox = nullptr, *list_near = nullptr, *list_far = nullptr, *list_hole = nullptr;
+    int32_t *list_side = nullptr, *list_fringe = nullptr;
+    int32_t *fr_tiles = nullptr;       // fringe compaction: counts, offsets, scan scratch
+    int64_t fr_tiles_cap = 0;
+    oc::CutCounters *counters = nullptr;
+    oc::DonorCounters *dcounters = nullptr;
+    oc::Pose *poses = nullptr;         // [kPoseSlots] device
+    int32_t *scalar = nullptr;         // device scratch
+    int64_t last_n_elem = 0;
+    std::map<int, oc::SurfWork> sw;
+    std::vector<oc::DevBuf> owned;
+};
+
+namespace oc {
 
 struct TimingRec {
     hipEvent_t a, b;
@@ -119,18 +150,17 @@ struct TimingRec {
 
 struct oc_ctx {
     int device = 0;
-    hipStream_t stream = nullptr;
     int surf_bins = 0;
     double donor_bin_scale = 1.0;
     int64_t budget = 0;
     int64_t used = 0;
     std::vector<std::unique_ptr<oc::Grid>> grids;
     std::vector<std::unique_ptr<oc::Surf>> surfs;
-    oc::CutCounters *counters = nullptr;  // device
-    oc::CutCounters last{};
-    int64_t last_n_elem = 0;
-    int32_t *dev_scalar = nullptr;        // device scratch int (fringe count)
-    // timing
+    oc_slot *dflt = nullptr;               // default slot of the simple calls
+    std::vector<oc_slot *> slots;          // slots created by the caller
+    int32_t *dev_scalar = nullptr;         // device scratch int (registration)
+    hipStream_t reg_stream = nullptr;      // registration work
+    // timing (default slot and slots alike, recorded on the launching stream)
     bool timing = false;
     std::vector<oc::TimingRec> trecs;
     std::vector<hipEvent_t> event_pool;
@@ -142,25 +172,39 @@ namespace oc {
 oc_status dev_alloc(oc_ctx *ctx, std::vector<DevBuf> &owner, size_t bytes, void **out);
 void dev_free_all(oc_ctx *ctx, std::vector<DevBuf> &owner);
 
-// Launch bracketing for per-kernel timing.
-void time_begin(oc_ctx *ctx, const char *name, size_t *slot);
-void time_end(oc_ctx *ctx, size_t slot);
+// Launch bracketing for per-kernel timing (events on the given stream).
+void time_begin(oc_ctx *ctx, hipStream_t st, const char *name, size_t *slot);
+void time_end(oc_ctx *ctx, hipStream_t st, size_t slot);
 
 // exclusive scan of n (device count n_dev if non-null, else n_host) int32
 // values; out[n] receives the total.  tmp must hold scan_tmp_ints(cap) ints.
 int64_t scan_tmp_ints(int64_t cap);
-oc_status scan_exclusive(oc_ctx *ctx, const int32_t *in, int32_t *out, int64_t cap, const int *n_dev,
-                         int32_t *tmp);
+oc_status scan_exclusive(oc_ctx *ctx, hipStream_t st, const int32_t *in, int32_t *out, int64_t cap,
+                         const int *n_dev, int32_t *tmp);
 
 // registration-time device work
 oc_status grid_build_device(oc_ctx *ctx, Grid &g, const int32_t *conn_dev, const double *nodes_dev);
 oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g);
 
-// cut pipeline
-oc_status cut_run(oc_ctx *ctx, Grid &g, Surf **surfs, const Pose *poses, int n_surf, int8_t *iblank);
-oc_status fringe_points_run(oc_ctx *ctx, Grid &g, const Pose &pose, const int8_t *iblank, double *pts,
-                            int64_t cap, int64_t *n_out, int32_t *src);
-oc_status donor_run(oc_ctx *ctx, Grid &g, const Pose &pose, const double *pts, int64_t n, int32_t *donor,
-                    double *ref);
+// slot scratch sizing (grow-only for the default slot)
+oc_status slot_reserve_grid(oc_slot *sl, const Grid &g);
+oc_status slot_reserve_surf(oc_slot *sl, int surf_id, const Surf &s);
+
+oc_status set_poses(oc_slot *sl, int first, const double *host, int n);
+oc_status slot_init(oc_ctx *ctx, oc_slot *sl, bool grow);
+void slot_free(oc_slot *sl);
+
+// cut pipeline; poses are device pointers (one Pose per surface)
+// warm start: prev = previous iblank of the same grid and single surface,
+// sweep = bound on how far any surface point moved since (0 / null: cold)
+oc_status cut_run(oc_slot *sl, Grid &g, const int *surf_ids, Surf **surfs, const Pose *poses_dev, int n_surf,
+                  int8_t *iblank, const int8_t *prev = nullptr, double sweep = 0.0);
+// receptor points: the count stays on the device (n_dev, int32) and is also
+// returned on the host when n_host is not null (synchronising)
+oc_status fringe_points_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const int8_t *iblank, double *pts,
+                            int64_t cap, int32_t *n_dev, int64_t *n_host, int32_t *src);
+// donor search of min(*n_dev, cap) points (n_dev may be null: cap points)
+oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pts, int64_t cap, const int32_t *n_dev,
+                    int32_t *donor, double *ref);
 
 }  // namespace oc

@@ -24,7 +24,10 @@ OC_FACE_INTERIOR, OC_FACE_WALL, OC_FACE_OVERSET, OC_FACE_FARFIELD = 0, 1, 2, 3
 
 EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_register_grid",
            "oc_register_cut_surface", "oc_cut", "oc_cut_multi", "oc_last_cut_info", "oc_fringe_points",
-           "oc_donor_search", "oc_timing", "oc_timing_report", "oc_memory_used"]
+           "oc_donor_search", "oc_last_donor_info", "oc_timing", "oc_timing_report", "oc_memory_used",
+           "oc_slot_create", "oc_slot_destroy", "oc_slot_set_stream", "oc_slot_bytes", "oc_slot_cut",
+           "oc_slot_fringe_points", "oc_slot_donor_search", "oc_slot_cut_info", "oc_slot_donor_info",
+           "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm"]
 
 
 class OcError(RuntimeError):
@@ -41,6 +44,10 @@ class oc_config(C.Structure):
 class oc_cut_info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_elem", "n_inbox", "n_near", "n_far", "n_hit", "n_hole",
                                          "n_cand_pairs")]
+
+
+class oc_donor_info(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_points", "n_newton", "n_iter", "n_orphan")]
 
 
 _lib = None
@@ -67,9 +74,22 @@ def load(path=LIB_PATH):
         "oc_last_cut_info": ([vp, C.POINTER(oc_cut_info)]),
         "oc_fringe_points": ([vp, C.c_int32, dp, vp, vp, C.c_int64, i64p, vp]),
         "oc_donor_search": ([vp, C.c_int32, dp, vp, C.c_int64, vp, vp]),
+        "oc_last_donor_info": ([vp, C.POINTER(oc_donor_info)]),
         "oc_timing": ([vp, C.c_int32]),
         "oc_timing_report": ([vp, C.c_char_p, C.c_int64]),
         "oc_memory_used": ([vp, i64p]),
+        "oc_slot_create": ([vp, i32p, C.c_int32, i32p, C.c_int32, C.POINTER(C.c_void_p)]),
+        "oc_slot_destroy": ([vp]),
+        "oc_slot_set_stream": ([vp, vp]),
+        "oc_slot_bytes": ([vp, i64p]),
+        "oc_slot_cut": ([vp, C.c_int32, i32p, vp, C.c_int32, vp]),
+        "oc_slot_fringe_points": ([vp, C.c_int32, vp, vp, vp, C.c_int64, vp, vp]),
+        "oc_slot_donor_search": ([vp, C.c_int32, vp, vp, C.c_int64, vp, vp, vp]),
+        "oc_slot_cut_info": ([vp, C.POINTER(oc_cut_info)]),
+        "oc_slot_donor_info": ([vp, C.POINTER(oc_donor_info)]),
+        "oc_cut_warm": ([vp, C.c_int32, C.c_int32, dp, dp, vp, vp]),
+        "oc_sweep_bound": ([vp, C.c_int32, dp, dp, dp]),
+        "oc_slot_cut_warm": ([vp, C.c_int32, C.c_int32, vp, C.c_double, vp, vp]),
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -175,10 +195,30 @@ class Context:
                                    _dptr(iblank, torch.int8, self.grids[grid_id])))
         return iblank
 
+    def cut_warm(self, grid_id, surf_id, pose, prev_pose, prev_iblank, iblank):
+        import torch
+        _, pp = _pose(pose)
+        _, qq = _pose(prev_pose)
+        _check(load().oc_cut_warm(self._h, grid_id, surf_id, pp, qq, _dptr(prev_iblank, torch.int8, self.grids[grid_id]),
+                                  _dptr(iblank, torch.int8, self.grids[grid_id])))
+        return iblank
+
+    def sweep_bound(self, surf_id, pose_a, pose_b):
+        _, pa = _pose(pose_a)
+        _, pb = _pose(pose_b)
+        v = C.c_double(0)
+        _check(load().oc_sweep_bound(self._h, surf_id, pa, pb, C.byref(v)))
+        return v.value
+
     def last_cut_info(self):
         info = oc_cut_info()
         _check(load().oc_last_cut_info(self._h, C.byref(info)))
         return {n: getattr(info, n) for n, _ in oc_cut_info._fields_}
+
+    def last_donor_info(self):
+        info = oc_donor_info()
+        _check(load().oc_last_donor_info(self._h, C.byref(info)))
+        return {n: getattr(info, n) for n, _ in oc_donor_info._fields_}
 
     def fringe_points(self, grid_id, pose, iblank, points, src=None):
         """Fills ``points`` (float64 [cap,3]) and ``src`` (int32 [cap]);
@@ -212,3 +252,87 @@ class Context:
         v = C.c_int64(0)
         _check(load().oc_memory_used(self._h, C.byref(v)))
         return v.value
+
+    def create_slot(self, grid_ids, surf_ids, stream=None):
+        return Slot(self, grid_ids, surf_ids, stream)
+
+
+def _dev_or_null(t, dtype):
+    return None if t is None else _dptr(t, dtype)
+
+
+class Slot:
+    """Per-request scratch reserved up front (oc_slot_create).  Its calls
+    take device poses (float64 [k,12] tensors) and device point counts
+    (int32 tensors), never allocate and never synchronise, so they can be
+    captured in a graph or run concurrently with other slots."""
+
+    def __init__(self, ctx: Context, grid_ids, surf_ids, stream=None):
+        import torch
+        self.ctx = ctx
+        g = np.ascontiguousarray(grid_ids, dtype=np.int32)
+        sid = np.ascontiguousarray(surf_ids, dtype=np.int32)
+        h = C.c_void_p()
+        _check(load().oc_slot_create(ctx._h, g.ctypes.data_as(C.POINTER(C.c_int32)), len(g),
+                                     sid.ctypes.data_as(C.POINTER(C.c_int32)), len(sid), C.byref(h)))
+        self._h = h
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=ctx.device)
+        self.set_stream(self.stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().oc_slot_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        _check(load().oc_slot_set_stream(self._h, C.c_void_p(handle)))
+
+    def nbytes(self):
+        v = C.c_int64(0)
+        _check(load().oc_slot_bytes(self._h, C.byref(v)))
+        return v.value
+
+    def cut(self, grid_id, surf_ids, poses_dev, iblank):
+        import torch
+        ids = np.ascontiguousarray(surf_ids, dtype=np.int32)
+        pp = _dptr(poses_dev, torch.float64, 12 * len(ids)) if len(ids) else None
+        _check(load().oc_slot_cut(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
+                                  _dptr(iblank, torch.int8, self.ctx.grids[grid_id])))
+
+    def cut_warm(self, grid_id, surf_id, pose_dev, sweep, prev_iblank, iblank):
+        import torch
+        _check(load().oc_slot_cut_warm(self._h, grid_id, surf_id, _dptr(pose_dev, torch.float64, 12), float(sweep),
+                                       _dptr(prev_iblank, torch.int8, self.ctx.grids[grid_id]),
+                                       _dptr(iblank, torch.int8, self.ctx.grids[grid_id])))
+
+    def fringe_points(self, grid_id, pose_dev, iblank, points, n_dev, src=None):
+        import torch
+        cap = points.numel() // 3
+        _check(load().oc_slot_fringe_points(self._h, grid_id, _dptr(pose_dev, torch.float64, 12),
+                                            _dptr(iblank, torch.int8), _dptr(points, torch.float64), cap,
+                                            _dptr(n_dev, torch.int32, 1),
+                                            None if src is None else _dptr(src, torch.int32, cap)))
+
+    def donor_search(self, grid_id, pose_dev, points, cap, n_dev, donor, ref):
+        import torch
+        _check(load().oc_slot_donor_search(self._h, grid_id, _dptr(pose_dev, torch.float64, 12),
+                                           _dptr(points, torch.float64, 3 * cap), int(cap),
+                                           _dev_or_null(n_dev, torch.int32), _dptr(donor, torch.int32, cap),
+                                           _dptr(ref, torch.float64, 3 * cap)))
+
+    def cut_info(self):
+        info = oc_cut_info()
+        _check(load().oc_slot_cut_info(self._h, C.byref(info)))
+        return {n: getattr(info, n) for n, _ in oc_cut_info._fields_}
+
+    def donor_info(self):
+        info = oc_donor_info()
+        _check(load().oc_slot_donor_info(self._h, C.byref(info)))
+        return {n: getattr(info, n) for n, _ in oc_donor_info._fields_}

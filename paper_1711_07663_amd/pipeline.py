@@ -64,12 +64,15 @@ class OversetSystem:
             b["donor_bg"] = torch.empty(cap_bg, dtype=torch.int32, device=dev)
             b["ref_bg"] = torch.empty((cap_bg, 3), dtype=torch.float64, device=dev)
 
-    def step(self, poses):
-        """Full connectivity step at the given body poses; returns counts."""
+    def step(self, poses, stats=False):
+        """Full connectivity step at the given body poses; returns counts.
+        With ``stats`` the cut and donor counters of each call are collected
+        too (each read synchronises the stream)."""
         ctx = self.ctx
         poses = [np.asarray(p, dtype=np.float64) for p in poses]
         sids = [b["surf"] for b in self.bodies]
         ctx.cut_multi(self.bg_id, sids, np.concatenate(poses), self.ib_bg)
+        st = dict(bg_cut=ctx.last_cut_info(), donor_bg=[], donor_shell=[]) if stats else None
         for i, b in enumerate(self.bodies):
             others = [j for j in range(len(self.bodies)) if j != i]
             inv = pose_inverse(poses[i])
@@ -79,8 +82,99 @@ class OversetSystem:
         counts = dict(n_bg_points=n_bg, n_shell_points=[])
         for i, b in enumerate(self.bodies):
             ctx.donor_search(b["shell"], poses[i], self.pts_bg, n_bg, b["donor_bg"], b["ref_bg"])
+            if stats:
+                st["donor_bg"].append(ctx.last_donor_info())
         for i, b in enumerate(self.bodies):
             n_s = ctx.fringe_points(b["shell"], poses[i], b["ib"], b["pts"], b["src"])
             ctx.donor_search(self.bg_id, IDENTITY, b["pts"], n_s, b["donor"], b["ref"])
             counts["n_shell_points"].append(n_s)
+            if stats:
+                st["donor_shell"].append(ctx.last_donor_info())
+        if stats:
+            counts["stats"] = st
         return counts
+
+
+class SlotStep:
+    """The same connectivity step on a slot of an OversetSystem: poses and
+    point counts live on the device, nothing synchronises, and the launch
+    sequence can be captured once in a graph and replayed with new poses.
+
+    Device pose table rows: [0, nb) body poses (background cut; shell receptor
+    points and bg->shell searches); then for body i the poses of the other
+    bodies in body i's frame (shell cuts); the last row is the identity."""
+
+    def __init__(self, system: OversetSystem, stream=None):
+        self.sys = system
+        ctx = system.ctx
+        dev = torch.device("cuda", ctx.device)
+        nb = len(system.bodies)
+        grids = [system.bg_id] + [b["shell"] for b in system.bodies]
+        surfs = sorted(set(b["surf"] for b in system.bodies))
+        self.slot = ctx.create_slot(grids, surfs, stream)
+        self.n_pose = nb + nb * (nb - 1) + 1
+        self.poses_dev = torch.zeros((self.n_pose, 12), dtype=torch.float64, device=dev)
+        self.n_dev = torch.zeros(1 + nb, dtype=torch.int32, device=dev)
+        self.graph = None
+
+    def _pose_table(self, poses):
+        nb = len(self.sys.bodies)
+        rows = [np.asarray(p, dtype=np.float64) for p in poses]
+        for i in range(nb):
+            inv = pose_inverse(poses[i])
+            rows += [pose_compose(inv, poses[j]) for j in range(nb) if j != i]
+        rows.append(IDENTITY)
+        return torch.from_numpy(np.stack(rows))
+
+    def _launch(self):
+        s, sl = self.sys, self.slot
+        nb = len(s.bodies)
+        sids = [b["surf"] for b in s.bodies]
+        sl.cut(s.bg_id, sids, self.poses_dev[:nb], s.ib_bg)
+        r = nb
+        for i, b in enumerate(s.bodies):
+            others = [sids[j] for j in range(nb) if j != i]
+            sl.cut(b["shell"], others, self.poses_dev[r:r + nb - 1], b["ib"])
+            r += nb - 1
+        ident = self.poses_dev[self.n_pose - 1]
+        cap_bg = s.pts_bg.shape[0]
+        sl.fringe_points(s.bg_id, ident, s.ib_bg, s.pts_bg, self.n_dev[0:1], s.src_bg)
+        for i, b in enumerate(s.bodies):
+            sl.donor_search(b["shell"], self.poses_dev[i], s.pts_bg, cap_bg, self.n_dev[0:1], b["donor_bg"],
+                            b["ref_bg"])
+        for i, b in enumerate(s.bodies):
+            cap = b["pts"].shape[0]
+            sl.fringe_points(b["shell"], self.poses_dev[i], b["ib"], b["pts"], self.n_dev[1 + i:2 + i], b["src"])
+            sl.donor_search(s.bg_id, ident, b["pts"], cap, self.n_dev[1 + i:2 + i], b["donor"], b["ref"])
+
+    def set_poses(self, poses):
+        with torch.cuda.stream(self.slot.stream):
+            self.poses_dev.copy_(self._pose_table(poses))
+
+    def step(self, poses):
+        """Eager launches on the slot stream (no synchronisation)."""
+        self.set_poses(poses)
+        self._launch()
+
+    def capture(self):
+        g = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            self.slot.set_stream(torch.cuda.current_stream())
+            self._launch()
+        self.slot.set_stream(self.slot.stream)
+        self.graph = g
+        return g
+
+    def replay(self, poses):
+        """Graph replay on the slot stream with new poses."""
+        if self.graph is None:
+            self.capture()
+        with torch.cuda.stream(self.slot.stream):
+            self.poses_dev.copy_(self._pose_table(poses))
+            self.graph.replay()
+
+    def counts(self):
+        """Point counts (synchronises)."""
+        n = self.n_dev.cpu().tolist()
+        return dict(n_bg_points=n[0], n_shell_points=n[1:])

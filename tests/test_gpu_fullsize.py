@@ -1,0 +1,92 @@
+"""Parity at the benchmark's full size and launch configuration: the single
+dimpled-sphere cut (128^3 background, 24 576-face surface, 196 608-element
+shell), one whole connectivity step through the same pipeline bench.py times.
+
+The oracle classifies every element whose node box comes within two element
+widths of the surface's box.  Every other element is field under the plain
+definition: its first node lies outside the convex hull of the surface
+(winding number 0) and no triangle of it is within 1e-7 of the surface; none
+of its face neighbours can be a hole either.  Receptor points and donors are
+compared for every point in both directions."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from workloads import configs as CF
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_dimpled_full_size_parity(orc):
+    import torch
+    from paper_1711_07663_amd import oc
+    from paper_1711_07663_amd.pipeline import OversetSystem
+    from parity_util import PT_TOL, XI_TOL
+
+    _note("full-size dimpled case: generating inputs")
+    case = CF.dimpled()
+    bg, body = case["bg"], case["bodies"][0]
+    s, sh = body["surface"], body["shell"]
+    ctx = oc.Context(device=0)
+    try:
+        system = OversetSystem(ctx, case, bg_points_cap=27 * 40000)
+        _note("full-size dimpled case: GPU step")
+        c = system.step(case["poses"])
+        torch.cuda.synchronize()
+        ib_g = system.ib_bg.cpu().numpy()
+        n_bg = c["n_bg_points"]
+        n_sh = c["n_shell_points"][0]
+        b = system.bodies[0]
+        pts_bg_g = system.pts_bg[:n_bg].cpu().numpy()
+        pts_sh_g = b["pts"][:n_sh].cpu().numpy()
+        d_bg_g, r_bg_g = b["donor_bg"][:n_bg].cpu().numpy(), b["ref_bg"][:n_bg].cpu().numpy()
+        d_sh_g, r_sh_g = b["donor"][:n_sh].cpu().numpy(), b["ref"][:n_sh].cpu().numpy()
+        ib_sh_g = b["ib"].cpu().numpy()
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+
+    _note("full-size dimpled case: oracle cut of the band around the surface")
+    t0 = time.time()
+    P = bg.nodes[bg.conn]                       # (n_elem, 27, 3)
+    elo, ehi = P.min(axis=1), P.max(axis=1)
+    slo, shi = s.nodes.min(axis=0), s.nodes.max(axis=0)
+    h = 6.0 / 128
+    band = np.nonzero(np.all(ehi >= slo - 2 * h, axis=1) & np.all(elo <= shi + 2 * h, axis=1))[0]
+    del P
+    st = orc.cut_surface(bg, s, orc.IDENTITY, sel=band, threads=0)
+    hole = np.zeros(bg.n_elem, dtype=bool)
+    hole[band] = st == 0
+    nbr = orc.face_neighbors(bg.conn)
+    ib_o = orc.mark_fringe(hole, nbr)
+    _note("oracle band of %d elements in %.1f s" % (band.size, time.time() - t0))
+    bad = np.nonzero(ib_g != ib_o)[0]
+    assert bad.size == 0, "%d background elements differ, first %s" % (bad.size, bad[:8])
+    assert (ib_o == orc.HOLE).sum() > 1000 and (ib_o == orc.FRINGE).sum() > 500
+
+    ib_sh_o = orc.cut(sh, [], [])
+    assert np.array_equal(ib_sh_g, ib_sh_o)
+
+    _note("full-size dimpled case: receptor points and donors, both directions")
+    pts_bg_o = orc.fringe_points(bg, orc.fringe_elements(ib_o))
+    pts_sh_o = orc.fringe_points(sh, orc.fringe_elements(ib_sh_o))
+    assert pts_bg_o.shape == pts_bg_g.shape and pts_sh_o.shape == pts_sh_g.shape
+    assert np.abs(pts_bg_o - pts_bg_g).max() <= PT_TOL
+    assert np.abs(pts_sh_o - pts_sh_g).max() <= PT_TOL
+    for name, grid, pts, d_g, r_g in (("bg->shell", sh, pts_bg_g, d_bg_g, r_bg_g),
+                                      ("shell->bg", bg, pts_sh_g, d_sh_g, r_sh_g)):
+        t0 = time.time()
+        d_o, r_o, _ = orc.donor_search(grid, pts, threads=0)
+        _note("%s: %d points in %.1f s" % (name, pts.shape[0], time.time() - t0))
+        bad = np.nonzero(d_g != d_o)[0]
+        assert bad.size == 0, "%s: %d donor ids differ, first %s" % (name, bad.size, bad[:8])
+        ok = d_o >= 0
+        assert np.abs(r_g[ok] - r_o[ok]).max() <= XI_TOL
+        assert np.all(np.isnan(r_g[~ok]))
