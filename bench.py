@@ -144,17 +144,18 @@ def main():
         roof_filter = dict(bound="hbm", kernel="k_filter", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                            frac=achieved / HBM_PEAK_GBS, traffic=None,
                            algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=kf["avg_us"])
-    # dominant kernel of the step: the Newton donor search, FP64 VALU bound;
-    # algorithmic FLOP per launch = NEWTON_FLOP x Newton iterations run
-    kd = per_kernel.get("k_donor")
+    # dominant kernel of the step; when it is the Newton kernel of the donor
+    # search (FP64 VALU bound) its algorithmic FLOP per launch is
+    # NEWTON_FLOP x the Newton iterations it ran
     roof = roof_filter
     dominant = max(per_kernel.items(), key=lambda kv: kv[1]["total_ms"])[0] if per_kernel else None
-    if kd and dominant == "k_donor":
+    kd = per_kernel.get(dominant)
+    if kd and dominant == "k_dp_newton":
         iters = sum(d["n_iter"] for d in st["donor_bg"] + st["donor_shell"])
         launches_per_step = len(st["donor_bg"]) + len(st["donor_shell"])
         flop_per_launch = NEWTON_FLOP * iters / launches_per_step
         achieved = flop_per_launch / (kd["avg_us"] * 1e-6) / 1e12
-        roof = dict(bound="alu", kernel="k_donor", achieved=achieved, peak=FP64_VECTOR_PEAK, unit="TFLOP/s",
+        roof = dict(bound="alu", kernel=dominant, achieved=achieved, peak=FP64_VECTOR_PEAK, unit="TFLOP/s",
                     frac=achieved / FP64_VECTOR_PEAK, traffic=None, algorithmic_flop_per_launch=flop_per_launch,
                     newton_iterations_per_step=iters, avg_launch_us=kd["avg_us"])
     out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",

@@ -194,8 +194,9 @@ oc_status oc_last_donor_info(oc_ctx *ctx, oc_donor_info *info);
  * device memory, so several slots can run at once on different streams and a
  * sequence of slot calls can be captured in a HIP graph and replayed.  Calls
  * on one slot must not overlap in time. */
+/* points_cap: largest point count of one donor search on this slot */
 oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, const int32_t *surf_ids,
-                         int32_t n_surfs, oc_slot **slot);
+                         int32_t n_surfs, int64_t points_cap, oc_slot **slot);
 oc_status oc_slot_destroy(oc_slot *slot);
 oc_status oc_slot_set_stream(oc_slot *slot, void *hip_stream);
 /* device bytes reserved by the slot */

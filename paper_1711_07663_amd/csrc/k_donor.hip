@@ -329,199 +329,168 @@ __global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__
     }
 }
 
-constexpr int kDonorCache = 32;   // element node sets staged in LDS at a time
-constexpr int kDonorHash = 256;   // open-addressing table of the wavefront's candidate ids
-constexpr int kPairCap = 64 * kDonorCache;
-
 __device__ inline bool box_has(const float *__restrict__ c, d3 p)
 {
     return p.x >= (double)c[0] && p.y >= (double)c[1] && p.z >= (double)c[2] && p.x <= (double)c[3] &&
            p.y <= (double)c[4] && p.z <= (double)c[5];
 }
 
-__device__ inline unsigned hash_slot(int e) { return ((unsigned)e * 2654435761u) >> 24; }  // 8 bits
-
-// a10 + a11: one wavefront per 64 points.  The candidates of a point are the
-// elements of its bin whose control-net box contains it; as in Sec. 4.3 the
-// containment tests (Newton) run after the search.  The wavefront's distinct
-// candidates are gathered in an LDS table, sorted by id and staged in LDS 32
-// at a time; for each staged batch the (point, element) pairs are listed
-// element by element and run 64 at a time.  A point keeps the lowest id that
-// contains it (LDS atomic minimum), so points resolved in a batch skip the
-// later (higher-id) batches.  If the table overflows, the wavefront falls
-// back to per-lane Newton in ascending id order from global memory.
-__global__ __launch_bounds__(64) void k_donor(const double *__restrict__ enodes, const float *__restrict__ cbox,
-                                              const double *__restrict__ ediam, BinGrid G,
-                                              const int32_t *__restrict__ bstart, const int32_t *__restrict__ bitems,
-                                              const Pose *__restrict__ pose_dev, const double *__restrict__ pts,
-                                              int64_t cap, const int32_t *__restrict__ n_dev,
-                                              int32_t *__restrict__ donor, double *__restrict__ ref,
-                                              DonorCounters *dcnt)
+__device__ inline int64_t point_bin(const BinGrid &G, d3 p)
 {
-    const Pose pose = *pose_dev;
-    const int64_t n = n_dev ? ((int64_t)*n_dev < cap ? (int64_t)*n_dev : cap) : cap;
-    __shared__ int sKey[kDonorHash];
-    __shared__ int sList[kDonorHash];
-    __shared__ int sSorted[kDonorHash];
-    __shared__ double sNodes[kDonorCache * 81];
-    __shared__ double sP[64 * 3];
-    __shared__ int sBest[64];
-    __shared__ double sXi[64 * 3];
-    __shared__ unsigned short sPair[kPairCap];
-    __shared__ int sFull;
-    int n_solve = 0, n_iter = 0, n_orph = 0;
-    const int lane = threadIdx.x;
-    for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
-        const int64_t i = base + lane;
-        const bool valid = i < n;
-        d3 p = mk(0.0, 0.0, 0.0);
-        int j0 = 0, j1 = 0;
-        if (valid) {
-            p = pose_inverse(pose, mk(pts[3 * i], pts[3 * i + 1], pts[3 * i + 2]));
-            const int bx = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
-            const int by = bin_of((float)p.y, G.o[1], G.inv[1], G.n[1]);
-            const int bz = bin_of((float)p.z, G.o[2], G.inv[2], G.n[2]);
-            const int64_t b = bx + (int64_t)G.n[0] * (by + (int64_t)G.n[1] * bz);
-            j0 = bstart[b];
-            j1 = bstart[b + 1];
-        }
-        for (int k = lane; k < kDonorHash; k += 64) sKey[k] = -1;
-        sP[3 * lane] = p.x;
-        sP[3 * lane + 1] = p.y;
-        sP[3 * lane + 2] = p.z;
-        sBest[lane] = 0x7fffffff;
-        sXi[3 * lane] = sXi[3 * lane + 1] = sXi[3 * lane + 2] = NAN;
-        if (lane == 0) sFull = 0;
-        __syncthreads();
-        // distinct candidates of the wavefront
-        bool lost = false;
-        for (int j = j0; j < j1; ++j) {
-            const int e = bitems[j];
-            if (!box_has(cbox + (int64_t)e * 6, p)) continue;
-            unsigned h = hash_slot(e);
-            bool in = false;
-            for (int probe = 0; probe < kDonorHash; ++probe, h = (h + 1) & (kDonorHash - 1)) {
-                const int old = atomicCAS(&sKey[h], -1, e);
-                if (old == -1 || old == e) {
-                    in = true;
-                    break;
-                }
-            }
-            lost |= !in;
-        }
-        if (lost) sFull = 1;
-        __syncthreads();
-        if (!sFull) {
-            // dense list of the distinct ids, then ascending order (rank sort)
-            int cnt = 0;
-            for (int k = 0; k < kDonorHash / 64; ++k) {
-                const int key = sKey[lane + 64 * k];
-                const unsigned long long m = __ballot(key >= 0);
-                if (key >= 0) sList[cnt + __popcll(m & ((1ull << lane) - 1ull))] = key;
-                cnt += __popcll(m);
-            }
-            __syncthreads();
-            for (int k = lane; k < cnt; k += 64) {
-                const int v = sList[k];
-                int r = 0;
-                for (int q = 0; q < cnt; ++q) r += sList[q] < v;
-                sSorted[r] = v;
-            }
-            __syncthreads();
-            for (int c0 = 0; c0 < cnt; c0 += kDonorCache) {
-                const int nb = min(kDonorCache, cnt - c0);
-                for (int k = lane; k < nb * 81; k += 64) {
-                    const int sl = k / 81;
-                    sNodes[k] = enodes[(int64_t)sSorted[c0 + sl] * 81 + (k - 81 * sl)];
-                }
-                // pairs (lane, slot) element by element, unresolved points only
-                int np = 0;
-                const bool open = valid && sBest[lane] == 0x7fffffff;
-                for (int k = 0; k < nb; ++k) {
-                    const bool pass = open && box_has(cbox + (int64_t)sSorted[c0 + k] * 6, p);
-                    const unsigned long long m = __ballot(pass);
-                    if (pass) sPair[np + __popcll(m & ((1ull << lane) - 1ull))] = (unsigned short)(lane | (k << 6));
-                    np += __popcll(m);
-                }
-                __syncthreads();
-                for (int q0 = 0; q0 < np; q0 += 64) {
-                    const int q = q0 + lane;
-                    bool ok = false;
-                    int e = -1, l = 0;
-                    double xi[3] = {0.0, 0.0, 0.0};
-                    if (q < np) {
-                        const int pr = sPair[q];
-                        l = pr & 63;
-                        const int k = pr >> 6;
-                        e = sSorted[c0 + k];
-                        const d3 pp = mk(sP[3 * l], sP[3 * l + 1], sP[3 * l + 2]);
-                        ++n_solve;
-                        ok = newton_q2(sNodes + 81 * k, pp, ediam[e], xi, n_iter);
-                        if (ok) atomicMin(&sBest[l], e);
-                    }
-                    __syncthreads();
-                    if (ok && sBest[l] == e) {
-                        sXi[3 * l] = xi[0];
-                        sXi[3 * l + 1] = xi[1];
-                        sXi[3 * l + 2] = xi[2];
-                    }
-                    __syncthreads();
-                }
-            }
-        } else {
-            // overflow: each lane runs its candidates in ascending id order
-            int32_t d = 0x7fffffff;
-            double x0 = NAN, x1 = NAN, x2 = NAN;
-            for (int j = j0; j < j1; ++j) {
-                const int e = bitems[j];
-                if (!box_has(cbox + (int64_t)e * 6, p)) continue;
-                double xi[3];
-                ++n_solve;
-                if (newton_q2(enodes + (int64_t)e * 81, p, ediam[e], xi, n_iter)) {
-                    d = e;
-                    x0 = xi[0];
-                    x1 = xi[1];
-                    x2 = xi[2];
-                    break;
-                }
-            }
-            sBest[lane] = d;
-            sXi[3 * lane] = x0;
-            sXi[3 * lane + 1] = x1;
-            sXi[3 * lane + 2] = x2;
-        }
-        __syncthreads();
-        if (valid) {
-            const int bst = sBest[lane];
-            const int32_t d = bst == 0x7fffffff ? -1 : bst;
-            donor[i] = d;
-            ref[3 * i] = sXi[3 * lane];
-            ref[3 * i + 1] = sXi[3 * lane + 1];
-            ref[3 * i + 2] = sXi[3 * lane + 2];
-            n_orph += d < 0;
-        }
-        __syncthreads();
-    }
-    // per-wavefront totals, one atomic each
-    unsigned long long a = n_solve, b = n_iter, cc = n_orph;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) {
-        a += __shfl_xor(a, d, 64);
-        b += __shfl_xor(b, d, 64);
-        cc += __shfl_xor(cc, d, 64);
-    }
-    if (lane == 0) {
-        atomicAdd(&dcnt->n_newton, a);
-        atomicAdd(&dcnt->n_iter, b);
-        atomicAdd(&dcnt->n_orphan, cc);
+    const int bx = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
+    const int by = bin_of((float)p.y, G.o[1], G.inv[1], G.n[1]);
+    const int bz = bin_of((float)p.z, G.o[2], G.inv[2], G.n[2]);
+    return bx + (int64_t)G.n[0] * (by + (int64_t)G.n[1] * bz);
+}
+
+struct DonorArgs {
+    const double *enodes;
+    const float *cbox;
+    const double *ediam;
+    BinGrid G;
+    const int32_t *bstart;
+    const int32_t *bitems;
+    const Pose *pose;
+    const double *pts;
+    int64_t cap;           // point capacity
+    const int32_t *n_dev;  // point count on the device (null: cap)
+    int32_t *n_eff;        // min(*n_dev, cap), written by k_dp_count
+    double *plocal;        // [cap][3] points in the grid's registration frame
+    int32_t *cnt;          // [cap + 1] candidates per point
+    int32_t *off;          // [cap + 1] exclusive scan of cnt
+    int32_t *best;         // [cap] lowest containing element id
+    int32_t *pair_pt;      // [pair_cap]
+    int32_t *pair_el;      // [pair_cap]
+    int64_t pair_cap;
+    int32_t *donor;
+    double *ref;
+    DonorCounters *dcnt;
+};
+
+__device__ inline int64_t donor_points(const DonorArgs &a)
+{
+    return a.n_dev ? ((int64_t)*a.n_dev < a.cap ? (int64_t)*a.n_dev : a.cap) : a.cap;
+}
+
+// a10: per point, the registration-frame position (inverse pose, the rigid
+// motion of Sec. 4.3), its bin, and the number of elements of the bin whose
+// control-net box contains it.
+__global__ __launch_bounds__(kT) void k_dp_count(DonorArgs a)
+{
+    const int64_t n = donor_points(a);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_eff = (int32_t)n;
+    const Pose pose = *a.pose;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const d3 p = pose_inverse(pose, mk(a.pts[3 * i], a.pts[3 * i + 1], a.pts[3 * i + 2]));
+        a.plocal[3 * i] = p.x;
+        a.plocal[3 * i + 1] = p.y;
+        a.plocal[3 * i + 2] = p.z;
+        const int64_t b = point_bin(a.G, p);
+        int c = 0;
+        for (int j = a.bstart[b]; j < a.bstart[b + 1]; ++j) c += box_has(a.cbox + (int64_t)a.bitems[j] * 6, p);
+        a.cnt[i] = c;
+        a.best[i] = 0x7fffffff;
     }
 }
 
-__global__ void k_donor_reset(DonorCounters *c, int64_t cap, const int32_t *n_dev)
+// a10: the candidates as (point, element) pairs (the containment tests are
+// deferred to the next kernel, as in Sec. 4.3); pairs past the capacity are
+// dropped and their points searched one by one in k_dp_final.
+__global__ __launch_bounds__(kT) void k_dp_fill(DonorArgs a)
+{
+    const int64_t n = donor_points(a);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
+        const int64_t b = point_bin(a.G, p);
+        int64_t q = a.off[i];
+        for (int j = a.bstart[b]; j < a.bstart[b + 1] && q < a.pair_cap; ++j) {
+            const int e = a.bitems[j];
+            if (!box_has(a.cbox + (int64_t)e * 6, p)) continue;
+            a.pair_pt[q] = (int32_t)i;
+            a.pair_el[q] = e;
+            ++q;
+        }
+    }
+}
+
+// a11: Newton on every pair, one thread each; a point keeps the lowest
+// element id that contains it.
+__global__ __launch_bounds__(kT) void k_dp_newton(DonorArgs a)
+{
+    const int64_t n = *a.n_eff;
+    const int64_t tot = a.off[n] < a.pair_cap ? (int64_t)a.off[n] : a.pair_cap;
+    int iters = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
+        const int i = a.pair_pt[q], e = a.pair_el[q];
+        const d3 p = mk(a.plocal[3 * (int64_t)i], a.plocal[3 * (int64_t)i + 1], a.plocal[3 * (int64_t)i + 2]);
+        double xi[3];
+        if (newton_q2(a.enodes + (int64_t)e * 81, p, a.ediam[e], xi, iters)) atomicMin(&a.best[i], e);
+    }
+    unsigned long long s = iters;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&a.dcnt->n_iter, s);
+}
+
+// donor id and reference coordinates per point: Newton is rerun on the
+// winning element (same code, same inputs, same result) for its xi.  Points
+// whose pairs did not all fit take their candidates in ascending id order.
+__global__ __launch_bounds__(kT) void k_dp_final(DonorArgs a)
+{
+    const int64_t n = *a.n_eff;
+    int orph = 0, extra = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
+        int32_t d = -1;
+        double xi[3] = {NAN, NAN, NAN};
+        int scratch = 0;
+        if ((int64_t)a.off[i + 1] > a.pair_cap) {
+            const int64_t b = point_bin(a.G, p);
+            for (int j = a.bstart[b]; j < a.bstart[b + 1]; ++j) {
+                const int e = a.bitems[j];
+                if (!box_has(a.cbox + (int64_t)e * 6, p)) continue;
+                ++extra;
+                if (newton_q2(a.enodes + (int64_t)e * 81, p, a.ediam[e], xi, scratch)) {
+                    d = e;
+                    break;
+                }
+                xi[0] = xi[1] = xi[2] = NAN;
+            }
+        } else if (a.best[i] != 0x7fffffff) {
+            d = a.best[i];
+            (void)newton_q2(a.enodes + (int64_t)d * 81, p, a.ediam[d], xi, scratch);
+        }
+        a.donor[i] = d;
+        a.ref[3 * i] = xi[0];
+        a.ref[3 * i + 1] = xi[1];
+        a.ref[3 * i + 2] = xi[2];
+        orph += d < 0;
+    }
+    unsigned long long so = orph, sx = extra;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        so += __shfl_xor(so, d, 64);
+        sx += __shfl_xor(sx, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (so) atomicAdd(&a.dcnt->n_orphan, so);
+        if (sx) atomicAdd(&a.dcnt->n_newton, sx);
+    }
+}
+
+__global__ void k_dp_newton_count(DonorArgs a)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t n = *a.n_eff;
+        a.dcnt->n_points = (unsigned long long)n;
+        a.dcnt->n_newton += (unsigned long long)(a.off[n] < a.pair_cap ? (int64_t)a.off[n] : a.pair_cap);
+    }
+}
+
+__global__ void k_donor_reset(DonorCounters *c)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
-        const int64_t n = n_dev ? ((int64_t)*n_dev < cap ? (int64_t)*n_dev : cap) : cap;
-        c->n_points = (unsigned long long)n;
+        c->n_points = 0ull;
         c->n_newton = c->n_iter = c->n_orphan = 0ull;
     }
 }
@@ -637,10 +606,38 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
 {
     oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
-    LAUNCH(k_donor_reset, dim3(1), dim3(64), sl->dcounters, cap, n_dev);
+    LAUNCH(k_donor_reset, dim3(1), dim3(64), sl->dcounters);
     if (cap <= 0) return OC_OK;
-    LAUNCH(k_donor, dim3((unsigned)std::min<int64_t>((cap + 63) / 64, 16384)), dim3(64), g.enodes, g.cbox, g.ediam,
-           g.dgrid, g.dbin_start, g.dbin_items, pose_dev, pts, cap, n_dev, donor, ref, sl->dcounters);
+    OC_TRY(slot_reserve_points(sl, cap));
+    DonorArgs a;
+    a.enodes = g.enodes;
+    a.cbox = g.cbox;
+    a.ediam = g.ediam;
+    a.G = g.dgrid;
+    a.bstart = g.dbin_start;
+    a.bitems = g.dbin_items;
+    a.pose = pose_dev;
+    a.pts = pts;
+    a.cap = cap;
+    a.n_dev = n_dev;
+    a.n_eff = sl->scalar + 1;
+    a.plocal = sl->dp_local;
+    a.cnt = sl->dp_cnt;
+    a.off = sl->dp_off;
+    a.best = sl->dp_best;
+    a.pair_pt = sl->dpair_pt;
+    a.pair_el = sl->dpair_el;
+    a.pair_cap = sl->dpair_cap;
+    a.donor = donor;
+    a.ref = ref;
+    a.dcnt = sl->dcounters;
+    const unsigned gp = std::min<unsigned>(blocks(cap, kT), 8192u);
+    LAUNCH(k_dp_count, dim3(gp), dim3(kT), a);
+    OC_TRY(scan_exclusive(ctx, st, sl->dp_cnt, sl->dp_off, cap, a.n_eff, sl->dp_scan_tmp));
+    LAUNCH(k_dp_fill, dim3(gp), dim3(kT), a);
+    LAUNCH(k_dp_newton_count, dim3(1), dim3(64), a);
+    LAUNCH(k_dp_newton, dim3(std::min<unsigned>(blocks(sl->dpair_cap, kT), 16384u)), dim3(kT), a);
+    LAUNCH(k_dp_final, dim3(gp), dim3(kT), a);
     OC_HIP(hipGetLastError());
     return OC_OK;
 }

@@ -130,6 +130,33 @@ oc_status slot_reserve_grid(oc_slot *sl, const Grid &g)
     return slot_alloc_lists(sl, g.n_elem);
 }
 
+static oc_status slot_alloc_points(oc_slot *sl, int64_t cap)
+{
+    oc_ctx *ctx = sl->ctx;
+    const int64_t pc = cap * kPairsPerPoint;
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(double) * 3 * cap, (void **)&sl->dp_local));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * (cap + 1), (void **)&sl->dp_cnt));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * (cap + 1), (void **)&sl->dp_off));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * cap, (void **)&sl->dp_best));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * scan_tmp_ints(cap), (void **)&sl->dp_scan_tmp));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * pc, (void **)&sl->dpair_pt));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * pc, (void **)&sl->dpair_el));
+    sl->dpt_cap = cap;
+    sl->dpair_cap = pc;
+    return OC_OK;
+}
+
+oc_status slot_reserve_points(oc_slot *sl, int64_t cap)
+{
+    if (cap <= sl->dpt_cap) return OC_OK;
+    if (!sl->grow) {
+        set_error("slot was not created for " + std::to_string(cap) + " points");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipStreamSynchronize(sl->stream));
+    return slot_alloc_points(sl, cap);
+}
+
 oc_status slot_reserve_surf(oc_slot *sl, int surf_id, const Surf &s)
 {
     if (sl->sw.count(surf_id)) return OC_OK;
@@ -637,9 +664,10 @@ oc_status oc_cut_warm(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const doubl
 
 // ------------------------------------------------------------- slot API --
 oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, const int32_t *surf_ids,
-                         int32_t n_surfs, oc_slot **out)
+                         int32_t n_surfs, int64_t points_cap, oc_slot **out)
 {
-    if (!ctx || !out || n_grids < 0 || n_surfs < 0 || (n_grids && !grid_ids) || (n_surfs && !surf_ids)) {
+    if (!ctx || !out || n_grids < 0 || n_surfs < 0 || (n_grids && !grid_ids) || (n_surfs && !surf_ids) ||
+        points_cap < 0) {
         set_error("oc_slot_create: invalid arguments");
         return OC_EINVAL;
     }
@@ -656,6 +684,7 @@ oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, 
     oc_slot *sl = new oc_slot();
     oc_status st = slot_init(ctx, sl, false);
     if (st == OC_OK) st = slot_alloc_lists(sl, ne);
+    if (st == OC_OK && points_cap > 0) st = slot_alloc_points(sl, points_cap);
     for (int k = 0; k < n_surfs && st == OC_OK; ++k)
         if (!sl->sw.count(surf_ids[k])) st = slot_alloc_surf(sl, surf_ids[k], *ss[k]);
     if (st != OC_OK) {

@@ -135,6 +135,11 @@ struct oc_slot {
     oc::Pose *poses = nullptr;         // [kPoseSlots] device
     int32_t *scalar = nullptr;         // device scratch
     int64_t last_n_elem = 0;
+    // donor search scratch: per point and per (point, candidate) pair
+    int64_t dpt_cap = 0, dpair_cap = 0;
+    double *dp_local = nullptr;
+    int32_t *dp_cnt = nullptr, *dp_off = nullptr, *dp_best = nullptr, *dp_scan_tmp = nullptr;
+    int32_t *dpair_pt = nullptr, *dpair_el = nullptr;
     std::map<int, oc::SurfWork> sw;
     std::vector<oc::DevBuf> owned;
 };
@@ -189,6 +194,8 @@ oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g);
 // slot scratch sizing (grow-only for the default slot)
 oc_status slot_reserve_grid(oc_slot *sl, const Grid &g);
 oc_status slot_reserve_surf(oc_slot *sl, int surf_id, const Surf &s);
+oc_status slot_reserve_points(oc_slot *sl, int64_t cap);
+constexpr int kPairsPerPoint = 8;   // pair capacity per point capacity
 
 oc_status set_poses(oc_slot *sl, int first, const double *host, int n);
 oc_status slot_init(oc_ctx *ctx, oc_slot *sl, bool grow);

@@ -78,7 +78,7 @@ def load(path=LIB_PATH):
         "oc_timing": ([vp, C.c_int32]),
         "oc_timing_report": ([vp, C.c_char_p, C.c_int64]),
         "oc_memory_used": ([vp, i64p]),
-        "oc_slot_create": ([vp, i32p, C.c_int32, i32p, C.c_int32, C.POINTER(C.c_void_p)]),
+        "oc_slot_create": ([vp, i32p, C.c_int32, i32p, C.c_int32, C.c_int64, C.POINTER(C.c_void_p)]),
         "oc_slot_destroy": ([vp]),
         "oc_slot_set_stream": ([vp, vp]),
         "oc_slot_bytes": ([vp, i64p]),
@@ -253,8 +253,8 @@ class Context:
         _check(load().oc_memory_used(self._h, C.byref(v)))
         return v.value
 
-    def create_slot(self, grid_ids, surf_ids, stream=None):
-        return Slot(self, grid_ids, surf_ids, stream)
+    def create_slot(self, grid_ids, surf_ids, points_cap=0, stream=None):
+        return Slot(self, grid_ids, surf_ids, points_cap, stream)
 
 
 def _dev_or_null(t, dtype):
@@ -267,14 +267,15 @@ class Slot:
     (int32 tensors), never allocate and never synchronise, so they can be
     captured in a graph or run concurrently with other slots."""
 
-    def __init__(self, ctx: Context, grid_ids, surf_ids, stream=None):
+    def __init__(self, ctx: Context, grid_ids, surf_ids, points_cap=0, stream=None):
         import torch
         self.ctx = ctx
         g = np.ascontiguousarray(grid_ids, dtype=np.int32)
         sid = np.ascontiguousarray(surf_ids, dtype=np.int32)
         h = C.c_void_p()
         _check(load().oc_slot_create(ctx._h, g.ctypes.data_as(C.POINTER(C.c_int32)), len(g),
-                                     sid.ctypes.data_as(C.POINTER(C.c_int32)), len(sid), C.byref(h)))
+                                     sid.ctypes.data_as(C.POINTER(C.c_int32)), len(sid), int(points_cap),
+                                     C.byref(h)))
         self._h = h
         self.stream = stream if stream is not None else torch.cuda.Stream(device=ctx.device)
         self.set_stream(self.stream)

@@ -111,7 +111,8 @@ class SlotStep:
         nb = len(system.bodies)
         grids = [system.bg_id] + [b["shell"] for b in system.bodies]
         surfs = sorted(set(b["surf"] for b in system.bodies))
-        self.slot = ctx.create_slot(grids, surfs, stream)
+        cap = max([system.pts_bg.shape[0]] + [b["pts"].shape[0] for b in system.bodies])
+        self.slot = ctx.create_slot(grids, surfs, cap, stream)
         self.n_pose = nb + nb * (nb - 1) + 1
         self.poses_dev = torch.zeros((self.n_pose, 12), dtype=torch.float64, device=dev)
         self.n_dev = torch.zeros(1 + nb, dtype=torch.int32, device=dev)
