@@ -159,6 +159,28 @@ oc_status oc_sweep_bound(oc_ctx *ctx, int32_t surf_id, const double pose_a[12], 
 
 oc_status oc_last_cut_info(oc_ctx *ctx, oc_cut_info *info);
 
+/* One request of a cut batch: grid grid_id cut by n_surf posed surfaces
+ * (union of holes, as oc_cut_multi) into its own iblank_out (device int8
+ * [n_elem], 4-byte aligned; no two requests of a batch may share one). */
+typedef struct oc_cut_req {
+    int32_t grid_id;
+    int32_t n_surf;
+    const int32_t *surf_ids; /* host [n_surf] */
+    const double *poses;     /* [n_surf*12]: host memory for oc_cut_batch,
+                                device memory (8-byte aligned) for oc_slot_cut_batch */
+    int8_t *iblank_out;
+} oc_cut_req;
+
+/* Cut a batch of independent requests (Sec. 4.2 applied to many grids and
+ * bodies at once).  Every stage of the cut is one launch for the whole
+ * batch: face and element launches are flattened over the requests, the
+ * exact stages take work items from batch-wide lists, so instances of very
+ * different sizes share the device.  Each request's iblank equals what
+ * oc_cut_multi gives for it alone.  At most 254 poses per batch (no limit
+ * on a slot, oc_slot_cut_batch).
+ * oc_last_cut_info then reports totals over the batch. */
+oc_status oc_cut_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req);
+
 /* Receptor points: 27 Gauss-Legendre points (3x3x3 tensor, order a+3b+9c)
  * per FRINGE element of iblank, in ascending element id, mapped by
  * eq. reftophys and posed by grid_pose into the world frame.
@@ -197,6 +219,11 @@ oc_status oc_last_donor_info(oc_ctx *ctx, oc_donor_info *info);
 /* points_cap: largest point count of one donor search on this slot */
 oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, const int32_t *surf_ids,
                          int32_t n_surfs, int64_t points_cap, oc_slot **slot);
+/* A slot sized for batches shaped like reqs (grid and surface ids are read;
+ * poses and outputs are ignored): any batch whose summed grid elements x
+ * surfaces, faces, bins, cuts and requests do not exceed those of reqs. */
+oc_status oc_slot_create_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req, int64_t points_cap,
+                               oc_slot **slot);
 oc_status oc_slot_destroy(oc_slot *slot);
 oc_status oc_slot_set_stream(oc_slot *slot, void *hip_stream);
 /* device bytes reserved by the slot */
@@ -204,6 +231,8 @@ oc_status oc_slot_bytes(oc_slot *slot, int64_t *bytes);
 /* oc_cut_multi on a slot; poses_dev: device FP64 [n_surf*12] (8-byte aligned) */
 oc_status oc_slot_cut(oc_slot *slot, int32_t grid_id, const int32_t *surf_ids, const double *poses_dev,
                       int32_t n_surf, int8_t *iblank_out);
+/* oc_cut_batch on a slot; every request's poses are in device memory */
+oc_status oc_slot_cut_batch(oc_slot *slot, const oc_cut_req *reqs, int32_t n_req);
 /* oc_cut_warm on a slot; sweep from oc_sweep_bound for the two poses */
 oc_status oc_slot_cut_warm(oc_slot *slot, int32_t grid_id, int32_t surf_id, const double *pose_dev, double sweep,
                            const int8_t *prev_iblank, int8_t *iblank_out);

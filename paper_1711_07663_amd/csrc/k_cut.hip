@@ -1,26 +1,31 @@
-// Direct cut of a curved quadratic grid by closed cutting surfaces
-// (Sec. 4.2 "Parallel Direct Cut Algorithm"): every element decides on its
-// own whether it is intersected by, inside or outside the surface, so no
-// paint-fill is needed.
+// Direct cut of curved quadratic grids by closed cutting surfaces
+// (Sec. 4.2, parallel direct cut): every element decides on its own whether
+// it is intersected by, inside or outside the surface, so no paint-fill is
+// needed.
 //
-// Pipeline per surface (all on the context stream):
-//   k_surf_init / k_pose_faces      pose the surface nodes, FP32 face boxes
+// A call cuts a batch: one or more requests, each a grid cut by one or more
+// surfaces into its own iblank.  Each (grid, surface, pose) is a "cut" with
+// a descriptor (CutInst); every stage is one launch for the whole batch:
+//   k_reset_counters                batch counters, surface boxes
+//   k_pose_faces                    pose the surface nodes, FP32 face boxes
 //                                   inflated by the hit tolerance, surface box
-//   k_bins_setup / k_bin_count /    uniform bins over the surface box:
-//   scan / k_bin_fill               count, exclusive scan, fill (CSR)
+//   k_bins_setup / k_bin_count /    uniform bins over each surface box, packed
+//   scan / k_bin_fill               one after another: count, scan, fill (CSR)
 //   k_filter                        stream every element's FP32 box; boxes
 //                                   meeting the surface box go to a list
 //   k_candidates                    element box x binned face boxes: elements
 //                                   with a candidate face are "near", others
 //                                   "far"
-//   k_exact                         one wavefront per near element: FP64
-//                                   triangle-pair intersection (hit), else the
-//                                   nearest-face side of the element's first
-//                                   node (wavefront minimum + tie rule)
+//   k_hit                           one wavefront per near element: FP64
+//                                   triangle-pair intersection
+//   k_side                          near elements not hit: nearest-face side of
+//                                   the first node (wavefront minimum + tie rule)
 //   k_ray                           far elements: +x ray parity of the first
 //                                   node against the surface triangles
-// then once per cut:
 //   k_fringe / k_overset_fringe     one fringe layer around holes, overset faces
+#include <algorithm>
+#include <cstring>
+
 #include "dev_geom.h"
 
 namespace oc {
@@ -62,37 +67,57 @@ __device__ inline double wave_min_d(double v)
     return v;
 }
 
-// ------------------------------------------------------- surface stage ----
-__global__ void k_reset_counters(CutCounters *cnt)
+// Owner of block b in a launch flattened over several entries: the number
+// of entries k >= 1 whose first block is <= b (first blocks never decrease,
+// entries with no block share their successor's first block).  Called by
+// every thread of the block.
+template <class F>
+__device__ inline int block_owner(int n, int b, F first)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    int c = 0;
+    for (int k0 = 1; k0 < n; k0 += blockDim.x) {
+        const int k = k0 + (int)threadIdx.x;
+        c += __syncthreads_count(k < n && first(k) <= b);
+    }
+    return c;
+}
+
+__device__ inline uint64_t pack_item(int cut, int e) { return ((uint64_t)(uint32_t)cut << 32) | (uint32_t)e; }
+__device__ inline int item_cut(uint64_t v) { return (int)(v >> 32); }
+__device__ inline int item_elem(uint64_t v) { return (int)(uint32_t)v; }
+
+// ------------------------------------------------------- surface stage ----
+// counters of the batch and the surface box of every cut
+__global__ __launch_bounds__(kThreads) void k_reset_counters(CutCounters *cnt, const CutInst *__restrict__ I, int n)
+{
+    if (threadIdx.x == 0) {
         cnt->n_inbox = cnt->n_near = cnt->n_far = cnt->n_hit = cnt->n_hole = cnt->n_side = 0;
         cnt->n_cand_pairs = 0ull;
     }
-}
-
-__global__ void k_surf_init(SurfParams *sp, CutCounters *cnt)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        SurfParams *sp = I[i].params;
         for (int k = 0; k < 3; ++k) {
             sp->sbox_ord[k] = f2ord(INFINITY);
             sp->sbox_ord[3 + k] = f2ord(-INFINITY);
         }
-        cnt->n_inbox = cnt->n_near = cnt->n_far = cnt->n_side = 0;
     }
 }
 
 // a1 + a2 (face boxes): pose the 9 nodes of every face (x' = R x + t), store
 // them face-major, and build the face's FP32 box rounded outward and inflated
-// by tol_hit + 2^-20 * max|coordinate|.
-__global__ __launch_bounds__(kThreads) void k_pose_faces(const double *__restrict__ nodes, int64_t n_nodes,
-                                                         const int32_t *__restrict__ conn, int64_t n_face,
-                                                         const Pose *__restrict__ pose_dev,
-                                                         double *__restrict__ pnodes, float *__restrict__ fbox,
-                                                         SurfParams *sp)
+// by tol_hit + 2^-20 * max|coordinate|.  Blocks are flattened over the cuts.
+__global__ __launch_bounds__(kThreads) void k_pose_faces(const CutInst *__restrict__ I, int n_cut)
 {
-    const Pose pose = *pose_dev;
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].fblk0; });
+    const CutInst &c = I[ci];
+    const double *__restrict__ nodes = c.snodes;
+    const int32_t *__restrict__ conn = c.conn;
+    const int64_t n_nodes = c.n_nodes, n_face = c.n_face;
+    double *__restrict__ pnodes = c.pnodes;
+    float *__restrict__ fbox = c.fbox;
+    SurfParams *sp = c.params;
+    const Pose pose = *c.pose;
+    const int64_t f = (int64_t)(blockIdx.x - c.fblk0) * blockDim.x + threadIdx.x;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     if (f < n_face) {
         double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -131,32 +156,73 @@ __global__ __launch_bounds__(kThreads) void k_pose_faces(const double *__restric
     }
 }
 
-// Bin grid over the surface box.  The bin edge is at least the largest face
-// box extent (dmax + 2 delta, pose invariant), so a face spans at most two
-// bins per axis and at most 8 bins in total.
-__global__ void k_bins_setup(SurfParams *sp, float dmax, int nb_max)
+// exclusive scan over a block of kThreads (one value per thread)
+__device__ inline int block_scan_excl(int v, int *total)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    float L = 0.f;
-    for (int k = 0; k < 6; ++k) {
-        sp->sbox[k] = ord2f(sp->sbox_ord[k]);
-        L = fmaxf(L, fabsf(sp->sbox[k]));
+    __shared__ int wsum[kThreads / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
     }
-    const float w = (dmax + 2.0f * (1e-7f + ldexpf(L, -20)) + ldexpf(L, -18)) * 1.001f;
-    int nb = 1;
-    for (int a = 0; a < 3; ++a) {
-        float ext = sp->sbox[3 + a] - sp->sbox[a];
-        int n = 1;
-        if (ext > 0.f) {
-            float q = fminf(floorf(ext / w), (float)nb_max);
-            n = q < 1.f ? 1 : (int)q;
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+// Bin grid over each cut's surface box, and the cut's first bin in the
+// batch's bin arrays.  The bin edge is at least the largest face box extent
+// (dmax + 2 delta, pose invariant), so a face spans at most two bins per axis
+// and at most 8 bins in total.  One block; the batch's bin total goes to
+// *total.
+__global__ __launch_bounds__(kThreads) void k_bins_setup(const CutInst *__restrict__ I, int n_cut, int *total)
+{
+    int carry = 0;
+    for (int i0 = 0; i0 < n_cut; i0 += kThreads) {
+        const int i = i0 + (int)threadIdx.x;
+        int nb = 0;
+        SurfParams *sp = nullptr;
+        if (i < n_cut) {
+            sp = I[i].params;
+            const float dmax = I[i].dmax;
+            const int nb_max = I[i].nb_max;
+            float L = 0.f;
+            for (int k = 0; k < 6; ++k) {
+                sp->sbox[k] = ord2f(sp->sbox_ord[k]);
+                L = fmaxf(L, fabsf(sp->sbox[k]));
+            }
+            const float w = (dmax + 2.0f * (1e-7f + ldexpf(L, -20)) + ldexpf(L, -18)) * 1.001f;
+            nb = 1;
+            for (int a = 0; a < 3; ++a) {
+                float ext = sp->sbox[3 + a] - sp->sbox[a];
+                int n = 1;
+                if (ext > 0.f) {
+                    float q = fminf(floorf(ext / w), (float)nb_max);
+                    n = q < 1.f ? 1 : (int)q;
+                }
+                sp->grid.o[a] = sp->sbox[a];
+                sp->grid.n[a] = n;
+                sp->grid.inv[a] = ext > 0.f ? (float)n / ext : 0.f;
+                nb *= n;
+            }
+            sp->n_bins = nb;
         }
-        sp->grid.o[a] = sp->sbox[a];
-        sp->grid.n[a] = n;
-        sp->grid.inv[a] = ext > 0.f ? (float)n / ext : 0.f;
-        nb *= n;
+        int tot;
+        const int off = block_scan_excl(nb, &tot);
+        if (sp) sp->bin_off = carry + off;
+        carry += tot;
     }
-    sp->n_bins = nb;
+    if (threadIdx.x == 0) *total = carry;
 }
 
 __global__ __launch_bounds__(kThreads) void k_zero_i32(int32_t *p, const int *n_dev, int64_t n_host)
@@ -174,87 +240,96 @@ __device__ inline void box_bins(const BinGrid &G, const float *b, int *lo, int *
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_bin_count(const float *__restrict__ fbox, int64_t n_face,
-                                                        const SurfParams *__restrict__ sp,
+__global__ __launch_bounds__(kThreads) void k_bin_count(const CutInst *__restrict__ I, int n_cut,
                                                         int32_t *__restrict__ count)
 {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n_face) return;
-    const BinGrid G = sp->grid;
+    const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].fblk0; });
+    const CutInst &c = I[ci];
+    const int64_t f = (int64_t)(blockIdx.x - c.fblk0) * blockDim.x + threadIdx.x;
+    if (f >= c.n_face) return;
+    const BinGrid G = c.params->grid;
+    int32_t *cnt = count + c.params->bin_off;
     int lo[3], hi[3];
-    box_bins(G, fbox + f * 6, lo, hi);
+    box_bins(G, c.fbox + f * 6, lo, hi);
     for (int z = lo[2]; z <= hi[2]; ++z)
         for (int y = lo[1]; y <= hi[1]; ++y)
-            for (int x = lo[0]; x <= hi[0]; ++x) atomicAdd(&count[x + G.n[0] * (y + G.n[1] * z)], 1);
+            for (int x = lo[0]; x <= hi[0]; ++x) atomicAdd(&cnt[x + G.n[0] * (y + G.n[1] * z)], 1);
 }
 
-// fill: the count array doubles as the per-bin cursor and ends at zero
-__global__ __launch_bounds__(kThreads) void k_bin_fill(const float *__restrict__ fbox, int64_t n_face,
-                                                       const SurfParams *__restrict__ sp,
+// fill: the count array doubles as the per-bin cursor and ends at zero;
+// items hold face ids local to their cut
+__global__ __launch_bounds__(kThreads) void k_bin_fill(const CutInst *__restrict__ I, int n_cut,
                                                        const int32_t *__restrict__ start, int32_t *count,
                                                        int32_t *__restrict__ items)
 {
-    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n_face) return;
-    const BinGrid G = sp->grid;
+    const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].fblk0; });
+    const CutInst &c = I[ci];
+    const int64_t f = (int64_t)(blockIdx.x - c.fblk0) * blockDim.x + threadIdx.x;
+    if (f >= c.n_face) return;
+    const BinGrid G = c.params->grid;
+    const int off = c.params->bin_off;
     int lo[3], hi[3];
-    box_bins(G, fbox + f * 6, lo, hi);
+    box_bins(G, c.fbox + f * 6, lo, hi);
     for (int z = lo[2]; z <= hi[2]; ++z)
         for (int y = lo[1]; y <= hi[1]; ++y)
             for (int x = lo[0]; x <= hi[0]; ++x) {
-                int b = x + G.n[0] * (y + G.n[1] * z);
-                int pos = atomicSub(&count[b], 1) - 1;
+                const int b = off + x + G.n[0] * (y + G.n[1] * z);
+                const int pos = atomicSub(&count[b], 1) - 1;
                 items[start[b] + pos] = (int32_t)f;
             }
 }
 
 // ---------------------------------------------------------- element stage --
 // a3, streaming part: every element's FP32 box (SoA planes, 4 elements per
-// thread) is tested against the surface box.  Optionally initialises iblank
-// to field.
-__global__ __launch_bounds__(kThreads) void k_filter(const float *__restrict__ ebox, int64_t n_elem, int64_t stride_e,
-                                                     const SurfParams *__restrict__ sp, int8_t *__restrict__ iblank,
-                                                     int write_field, int32_t *__restrict__ list_inbox,
-                                                     CutCounters *cnt)
+// thread) is tested against its cut's surface box.  The first cut of an
+// output also initialises its iblank to field.  Blocks are flattened over
+// the cuts, 1024 elements per block.
+__global__ __launch_bounds__(kThreads) void k_filter(const CutInst *__restrict__ I, int n_cut,
+                                                     uint64_t *__restrict__ list_inbox, CutCounters *cnt)
 {
+    const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].eblk0; });
+    const CutInst &c = I[ci];
+    const float *__restrict__ ebox = c.ebox;
+    const int64_t stride_e = c.stride, n_elem = c.n_elem;
+    int8_t *__restrict__ iblank = c.iblank;
+    const int write_field = c.write_field;
+    const SurfParams *sp = c.params;
     const float s0 = sp->sbox[0], s1 = sp->sbox[1], s2 = sp->sbox[2];
     const float s3 = sp->sbox[3], s4 = sp->sbox[4], s5 = sp->sbox[5];
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 4;
-    for (int64_t e0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-         e0 - (int64_t)lane_id() * 4 < n_elem; e0 += stride) {
-        int flags = 0, c = 0;
-        if (e0 + 3 < n_elem) {
-            const float4 xl = *reinterpret_cast<const float4 *>(ebox + e0);
-            const float4 yl = *reinterpret_cast<const float4 *>(ebox + stride_e + e0);
-            const float4 zl = *reinterpret_cast<const float4 *>(ebox + 2 * stride_e + e0);
-            const float4 xh = *reinterpret_cast<const float4 *>(ebox + 3 * stride_e + e0);
-            const float4 yh = *reinterpret_cast<const float4 *>(ebox + 4 * stride_e + e0);
-            const float4 zh = *reinterpret_cast<const float4 *>(ebox + 5 * stride_e + e0);
-            const float L0[4] = {xl.x, xl.y, xl.z, xl.w}, L1[4] = {yl.x, yl.y, yl.z, yl.w};
-            const float L2[4] = {zl.x, zl.y, zl.z, zl.w}, H0[4] = {xh.x, xh.y, xh.z, xh.w};
-            const float H1[4] = {yh.x, yh.y, yh.z, yh.w}, H2[4] = {zh.x, zh.y, zh.z, zh.w};
+    const int64_t e0 = ((int64_t)(blockIdx.x - c.eblk0) * blockDim.x + threadIdx.x) * 4;
+    if (e0 - (int64_t)lane_id() * 4 >= n_elem) return;   // whole wavefront past the end
+    int flags = 0, cn = 0;
+    if (e0 + 3 < n_elem) {
+        const float4 xl = *reinterpret_cast<const float4 *>(ebox + e0);
+        const float4 yl = *reinterpret_cast<const float4 *>(ebox + stride_e + e0);
+        const float4 zl = *reinterpret_cast<const float4 *>(ebox + 2 * stride_e + e0);
+        const float4 xh = *reinterpret_cast<const float4 *>(ebox + 3 * stride_e + e0);
+        const float4 yh = *reinterpret_cast<const float4 *>(ebox + 4 * stride_e + e0);
+        const float4 zh = *reinterpret_cast<const float4 *>(ebox + 5 * stride_e + e0);
+        const float L0[4] = {xl.x, xl.y, xl.z, xl.w}, L1[4] = {yl.x, yl.y, yl.z, yl.w};
+        const float L2[4] = {zl.x, zl.y, zl.z, zl.w}, H0[4] = {xh.x, xh.y, xh.z, xh.w};
+        const float H1[4] = {yh.x, yh.y, yh.z, yh.w}, H2[4] = {zh.x, zh.y, zh.z, zh.w};
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                bool in = L0[k] <= s3 && H0[k] >= s0 && L1[k] <= s4 && H1[k] >= s1 && L2[k] <= s5 && H2[k] >= s2;
-                flags |= (int)in << k;
-                c += in;
-            }
-            if (write_field) *reinterpret_cast<uint32_t *>(iblank + e0) = 0x01010101u;
-        } else {
-            for (int k = 0; k < 4; ++k) {
-                int64_t e = e0 + k;
-                if (e >= n_elem) break;
-                bool in = ebox[e] <= s3 && ebox[3 * stride_e + e] >= s0 && ebox[stride_e + e] <= s4 &&
-                          ebox[4 * stride_e + e] >= s1 && ebox[2 * stride_e + e] <= s5 && ebox[5 * stride_e + e] >= s2;
-                flags |= (int)in << k;
-                c += in;
-                if (write_field) iblank[e] = OC_FIELD;
-            }
+        for (int k = 0; k < 4; ++k) {
+            bool in = L0[k] <= s3 && H0[k] >= s0 && L1[k] <= s4 && H1[k] >= s1 && L2[k] <= s5 && H2[k] >= s2;
+            flags |= (int)in << k;
+            cn += in;
         }
-        int pos = wave_append(&cnt->n_inbox, c);
-        for (int k = 0; k < 4; ++k)
-            if (flags >> k & 1) list_inbox[pos++] = (int32_t)(e0 + k);
+        if (write_field) *reinterpret_cast<uint32_t *>(iblank + e0) = 0x01010101u;
+    } else {
+        for (int k = 0; k < 4; ++k) {
+            int64_t e = e0 + k;
+            if (e >= n_elem) break;
+            bool in = ebox[e] <= s3 && ebox[3 * stride_e + e] >= s0 && ebox[stride_e + e] <= s4 &&
+                      ebox[4 * stride_e + e] >= s1 && ebox[2 * stride_e + e] <= s5 && ebox[5 * stride_e + e] >= s2;
+            flags |= (int)in << k;
+            cn += in;
+            if (write_field) iblank[e] = OC_FIELD;
+        }
     }
+    int pos = wave_append(&cnt->n_inbox, cn);
+    for (int k = 0; k < 4; ++k)
+        if (flags >> k & 1) list_inbox[pos++] = pack_item(ci, (int)(e0 + k));
 }
 
 __device__ inline bool box_overlap(const float *a, const float *b)
@@ -366,23 +441,26 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
 // the walk also counts faces whose box meets the element box grown by the
 // sweep bound; an element meeting none keeps its previous side (the surface
 // never came near it between the two poses) and skips the ray test.
-__global__ __launch_bounds__(64) void k_candidates(const float *__restrict__ ebox, int64_t stride,
-                                                   const float *__restrict__ fbox, const SurfParams *__restrict__ sp,
-                                                   const int32_t *__restrict__ bstart,
+__global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I, const int32_t *__restrict__ bin_start,
                                                    const int32_t *__restrict__ bitems,
-                                                   const int32_t *__restrict__ list_inbox,
-                                                   int32_t *__restrict__ list_near, int32_t *__restrict__ list_far,
-                                                   CutCounters *cnt, const int8_t *__restrict__ prev, double sweep,
-                                                   int8_t *__restrict__ iblank, int32_t *__restrict__ list_hole)
+                                                   const uint64_t *__restrict__ list_inbox,
+                                                   uint64_t *__restrict__ list_near, uint64_t *__restrict__ list_far,
+                                                   uint64_t *__restrict__ list_hole, CutCounters *cnt)
 {
     __shared__ WalkLds L;
-    const BinGrid G = sp->grid;
     const int n_in = cnt->n_inbox;
     const int lane = threadIdx.x;
     for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
-        const int e = list_inbox[item];
+        const uint64_t it = list_inbox[item];
+        const int ci = item_cut(it), e = item_elem(it);
+        const CutInst &c = I[ci];
+        const float *__restrict__ fbox = c.fbox;
+        const int8_t *prev = c.prev;
+        const double sweep = c.sweep;
+        const BinGrid G = c.params->grid;
+        const int32_t *bstart = bin_start + c.params->bin_off;
         float eb[6], wb[6];
-        for (int k = 0; k < 6; ++k) eb[k] = ebox[(int64_t)k * stride + e];
+        for (int k = 0; k < 6; ++k) eb[k] = c.ebox[(int64_t)k * c.stride + e];
         for (int k = 0; k < 3; ++k) {
             wb[k] = prev ? f32_down((double)eb[k] - sweep) : eb[k];
             wb[3 + k] = prev ? f32_up((double)eb[3 + k] + sweep) : eb[3 + k];
@@ -405,15 +483,15 @@ __global__ __launch_bounds__(64) void k_candidates(const float *__restrict__ ebo
         const long long totw = prev ? wave_sum_ll(nw) : 1;
         if (lane == 0) {
             if (tot > 0) {
-                list_near[atomicAdd(&cnt->n_near, 1)] = e;
+                list_near[atomicAdd(&cnt->n_near, 1)] = it;
                 atomicAdd(&cnt->n_cand_pairs, (unsigned long long)tot);
             } else if (totw == 0) {
-                if (prev[e] == OC_HOLE && iblank[e] != OC_HOLE) {
-                    iblank[e] = OC_HOLE;
-                    list_hole[atomicAdd(&cnt->n_hole, 1)] = e;
+                if (prev[e] == OC_HOLE && c.iblank[e] != OC_HOLE) {
+                    c.iblank[e] = OC_HOLE;
+                    list_hole[atomicAdd(&cnt->n_hole, 1)] = it;
                 }
             } else {
-                list_far[atomicAdd(&cnt->n_far, 1)] = e;
+                list_far[atomicAdd(&cnt->n_far, 1)] = it;
             }
         }
     }
@@ -532,23 +610,13 @@ __device__ inline void query_bins(const BinGrid &G, d3 p, double r, int *lo, int
 }
 
 struct ExactArgs {
-    const double *enodes;
-    const float *ebox;
-    int64_t stride;
-    const double *pnodes;
-    const float *fbox;
-    const int32_t *bstart;
+    const CutInst *insts;
+    const int32_t *bin_start;
     const int32_t *bitems;
-    const SurfParams *sp;
-    const int32_t *list_near;
-    int32_t *list_side;
+    const uint64_t *list_in;    // near (k_hit) or side (k_side) elements
+    uint64_t *list_side;
+    uint64_t *list_hole;
     CutCounters *cnt;
-    int8_t *iblank;
-    int32_t *list_hole;
-    int kind;
-    int pad;
-    const Pose *pose;       // device pose of the surface
-    double first[3];        // first surface node, registration frame
 };
 
 constexpr int kFaceCap = 256;
@@ -571,13 +639,18 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
     __shared__ short sPair[384];
     __shared__ WalkLds L;
     const int lane = threadIdx.x;
-    const BinGrid G = a.sp->grid;
     const int n_near = a.cnt->n_near;
     const double tol = kTolHit;
     for (int item = blockIdx.x; item < n_near; item += gridDim.x) {
-        const int e = a.list_near[item];
+        const uint64_t it = a.list_in[item];
+        const int ci = item_cut(it), e = item_elem(it);
+        const CutInst &c = a.insts[ci];
+        const BinGrid G = c.params->grid;
+        const int32_t *bstart = a.bin_start + c.params->bin_off;
+        const float *__restrict__ fboxc = c.fbox;
+        const double *__restrict__ pnodes = c.pnodes;
         __syncthreads();
-        for (int k = lane; k < 81; k += 64) sX[k] = a.enodes[(int64_t)e * 81 + k];
+        for (int k = lane; k < 81; k += 64) sX[k] = c.enodes[(int64_t)e * 81 + k];
         __syncthreads();
         if (lane < 48) {
             d3 T[3];
@@ -604,7 +677,7 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         }
         __syncthreads();
         float eb[6];
-        for (int k = 0; k < 6; ++k) eb[k] = a.ebox[(int64_t)k * a.stride + e];
+        for (int k = 0; k < 6; ++k) eb[k] = c.ebox[(int64_t)k * c.stride + e];
         int lo[3], hi[3];
         box_bins(G, eb, lo, hi);
         const BinRange R = make_range(lo, hi);
@@ -614,7 +687,7 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         auto flush = [&]() {
             for (int i = 0; i < nlist && !hit; ++i) {
                 const int fid = sList[i];
-                if (lane < 27) sF[lane] = a.pnodes[(int64_t)fid * 27 + lane];
+                if (lane < 27) sF[lane] = pnodes[(int64_t)fid * 27 + lane];
                 __syncthreads();
                 if (lane < 8) {
                     d3 F[3];
@@ -650,10 +723,10 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
             }
             nlist = 0;
         };
-        walk_faces(G, R, a.bstart, a.bitems, L, [&](int f, const int *xyz) {
+        walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
             bool pass = false;
             if (f >= 0) {
-                const float *fb = a.fbox + (int64_t)f * 6;
+                const float *fb = fboxc + (int64_t)f * 6;
                 if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb)) {
                     const double fd[6] = {fb[0], fb[1], fb[2], fb[3], fb[4], fb[5]};
                     for (int q = 0; q < 6; ++q) pass |= boxes_meet(sEF + 6 * q, fd);
@@ -674,7 +747,7 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         }
         // the whole surface inside the element: ray parity of its first node
         // against the element's 48 boundary triangles
-        const d3 sf = pose_apply(*a.pose, mk(a.first[0], a.first[1], a.first[2]));
+        const d3 sf = pose_apply(*c.pose, mk(c.first[0], c.first[1], c.first[2]));
         if (!hit && sf.x >= eb[0] && sf.x <= eb[3] && sf.y >= eb[1] && sf.y <= eb[4] && sf.z >= eb[2] &&
             sf.z <= eb[5]) {
             int c = 0;
@@ -688,12 +761,12 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         if (lane == 0) {
             if (hit) {
                 atomicAdd(&a.cnt->n_hit, 1);
-                if (a.kind == OC_SURF_WALL && a.iblank[e] != OC_HOLE) {
-                    a.iblank[e] = OC_HOLE;
-                    a.list_hole[atomicAdd(&a.cnt->n_hole, 1)] = e;
+                if (c.kind == OC_SURF_WALL && c.iblank[e] != OC_HOLE) {
+                    c.iblank[e] = OC_HOLE;
+                    a.list_hole[atomicAdd(&a.cnt->n_hole, 1)] = it;
                 }
             } else {
-                a.list_side[atomicAdd(&a.cnt->n_side, 1)] = e;
+                a.list_side[atomicAdd(&a.cnt->n_side, 1)] = it;
             }
         }
     }
@@ -710,25 +783,30 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
     __shared__ TieRec rec[128];
     __shared__ WalkLds L;
     const int lane = threadIdx.x;
-    const BinGrid G = a.sp->grid;
     const int n_side = a.cnt->n_side;
     for (int item = blockIdx.x; item < n_side; item += gridDim.x) {
-        const int e = a.list_side[item];
-        const double *X = a.enodes + (int64_t)e * 81;
+        const uint64_t it = a.list_in[item];
+        const int ci = item_cut(it), e = item_elem(it);
+        const CutInst &c = a.insts[ci];
+        const BinGrid G = c.params->grid;
+        const int32_t *bstart = a.bin_start + c.params->bin_off;
+        const float *__restrict__ fboxc = c.fbox;
+        const double *__restrict__ pnodes = c.pnodes;
+        const double *X = c.enodes + (int64_t)e * 81;
         const d3 p = mk(X[0], X[27], X[54]);
         float eb[6];
-        for (int k = 0; k < 6; ++k) eb[k] = a.ebox[(int64_t)k * a.stride + e];
+        for (int k = 0; k < 6; ++k) eb[k] = c.ebox[(int64_t)k * c.stride + e];
         // upper bound: nearest of the element's candidate faces
         double u = INFINITY;
         {
             int lo[3], hi[3];
             box_bins(G, eb, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, a.bstart, a.bitems, L, [&](int f, const int *xyz) {
+            walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
                 if (f >= 0) {
-                    const float *fb = a.fbox + (int64_t)f * 6;
+                    const float *fb = fboxc + (int64_t)f * 6;
                     if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb) && point_box_dist(p, fb) < u)
-                        u = fmin(u, point_face_dist(p, a.pnodes + (int64_t)f * 27));
+                        u = fmin(u, point_face_dist(p, pnodes + (int64_t)f * 27));
                 }
                 return false;
             });
@@ -740,11 +818,11 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
             int lo[3], hi[3];
             query_bins(G, p, U, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, a.bstart, a.bitems, L, [&](int f, const int *xyz) {
+            walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
                 if (f >= 0) {
-                    const float *fb = a.fbox + (int64_t)f * 6;
+                    const float *fb = fboxc + (int64_t)f * 6;
                     if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
-                        best = fmin(best, point_face_dist(p, a.pnodes + (int64_t)f * 27));
+                        best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
                 }
                 return false;
             });
@@ -758,11 +836,11 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
             int lo[3], hi[3];
             query_bins(G, p, thr, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, a.bstart, a.bitems, L, [&](int f, const int *xyz) {
+            walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
                 if (f >= 0) {
-                    const float *fb = a.fbox + (int64_t)f * 6;
+                    const float *fb = fboxc + (int64_t)f * 6;
                     if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= thr) {
-                        const double *P = a.pnodes + (int64_t)f * 27;
+                        const double *P = pnodes + (int64_t)f * 27;
                         for (int s = 0; s < 8; ++s) {
                             d3 F[3];
                             face_tri(P, s, F);
@@ -803,9 +881,9 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
             double sg = c1.dot;
             if (c2.valid && c1.absdot - c2.absdot <= 1e-9 && ((c1.dot > 0.0) != (c2.dot > 0.0)))
                 sg = c1.vx * (c1.nx + c2.nx) + c1.vy * (c1.ny + c2.ny) + c1.vz * (c1.nz + c2.nz);
-            if (c1.valid && sg < 0.0 && a.iblank[e] != OC_HOLE) {
-                a.iblank[e] = OC_HOLE;
-                a.list_hole[atomicAdd(&a.cnt->n_hole, 1)] = e;
+            if (c1.valid && sg < 0.0 && c.iblank[e] != OC_HOLE) {
+                c.iblank[e] = OC_HOLE;
+                a.list_hole[atomicAdd(&a.cnt->n_hole, 1)] = it;
             }
         }
     }
@@ -813,22 +891,27 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
 
 // a6: far elements (no candidate face): +x ray parity of the first node over
 // the column of bins that holds the ray.
-__global__ __launch_bounds__(64) void k_ray(const double *__restrict__ enodes, const double *__restrict__ pnodes,
-                                            const float *__restrict__ fbox, const SurfParams *__restrict__ sp,
-                                            const int32_t *__restrict__ bstart, const int32_t *__restrict__ bitems,
-                                            const int32_t *__restrict__ list_far, CutCounters *cnt,
-                                            int8_t *__restrict__ iblank, int32_t *__restrict__ list_hole)
+__global__ __launch_bounds__(64) void k_ray(const CutInst *__restrict__ I, const int32_t *__restrict__ bin_start,
+                                            const int32_t *__restrict__ bitems,
+                                            const uint64_t *__restrict__ list_far, uint64_t *__restrict__ list_hole,
+                                            CutCounters *cnt)
 {
     __shared__ WalkLds L;
-    const BinGrid G = sp->grid;
     const int n_far = cnt->n_far;
     const int lane = threadIdx.x;
-    const float sb[6] = {sp->sbox[0], sp->sbox[1], sp->sbox[2], sp->sbox[3], sp->sbox[4], sp->sbox[5]};
     for (int item = blockIdx.x; item < n_far; item += gridDim.x) {
-        const int e = list_far[item];
-        const double *X = enodes + (int64_t)e * 81;
+        const uint64_t it = list_far[item];
+        const int ci = item_cut(it), e = item_elem(it);
+        const CutInst &c = I[ci];
+        const SurfParams *sp = c.params;
+        const double *X = c.enodes + (int64_t)e * 81;
         const d3 p = mk(X[0], X[27], X[54]);
-        if (p.y < sb[1] || p.y > sb[4] || p.z < sb[2] || p.z > sb[5] || p.x > sb[3]) continue;
+        if (p.y < sp->sbox[1] || p.y > sp->sbox[4] || p.z < sp->sbox[2] || p.z > sp->sbox[5] || p.x > sp->sbox[3])
+            continue;
+        const BinGrid G = sp->grid;
+        const int32_t *bstart = bin_start + sp->bin_off;
+        const float *__restrict__ fbox = c.fbox;
+        const double *__restrict__ pnodes = c.pnodes;
         int lo[3], hi[3];
         lo[0] = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
         lo[1] = hi[1] = bin_of((float)p.y, G.o[1], G.inv[1], G.n[1]);
@@ -852,21 +935,25 @@ __global__ __launch_bounds__(64) void k_ray(const double *__restrict__ enodes, c
             return false;
         });
         const int odd = __popcll(__ballot(par)) & 1;
-        if (lane == 0 && odd && iblank[e] != OC_HOLE) {
-            iblank[e] = OC_HOLE;
-            list_hole[atomicAdd(&cnt->n_hole, 1)] = e;
+        if (lane == 0 && odd && c.iblank[e] != OC_HOLE) {
+            c.iblank[e] = OC_HOLE;
+            list_hole[atomicAdd(&cnt->n_hole, 1)] = it;
         }
     }
 }
 
 // a8: fringe layer (field elements sharing a face with a hole)
-__global__ __launch_bounds__(kThreads) void k_fringe(const int32_t *__restrict__ nbr,
-                                                     const int32_t *__restrict__ list_hole,
-                                                     const CutCounters *__restrict__ cnt, int8_t *iblank)
+__global__ __launch_bounds__(kThreads) void k_fringe(const CutInst *__restrict__ I,
+                                                     const uint64_t *__restrict__ list_hole,
+                                                     const CutCounters *__restrict__ cnt)
 {
     const int n = cnt->n_hole;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int e = list_hole[i];
+        const uint64_t it = list_hole[i];
+        const int e = item_elem(it);
+        const CutInst &c = I[item_cut(it)];
+        const int32_t *nbr = c.nbr;
+        int8_t *iblank = c.iblank;
         for (int f = 0; f < 6; ++f) {
             const int q = nbr[(int64_t)e * 6 + f];
             if (q >= 0 && iblank[q] != OC_HOLE) iblank[q] = OC_FRINGE;
@@ -874,20 +961,27 @@ __global__ __launch_bounds__(kThreads) void k_fringe(const int32_t *__restrict__
     }
 }
 
-// elements carrying an overset-tagged face are fringe unless hole
-__global__ __launch_bounds__(kThreads) void k_overset_fringe(const int32_t *__restrict__ list, int64_t n,
-                                                             int8_t *iblank)
+// outputs with no cutting surface: every element field (blocks flattened
+// over those outputs, kThreads elements per block)
+__global__ __launch_bounds__(kThreads) void k_fill_field(const CutOut *__restrict__ O, int n_out)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const int e = list[i];
-        if (iblank[e] != OC_HOLE) iblank[e] = OC_FRINGE;
-    }
+    const int oi = block_owner(n_out, blockIdx.x, [&](int k) { return O[k].fblk0; });
+    const CutOut &o = O[oi];
+    const int64_t e = (int64_t)(blockIdx.x - o.fblk0) * blockDim.x + threadIdx.x;
+    if (e < o.n_elem) o.iblank[e] = OC_FIELD;
 }
 
-__global__ void k_fill_i8(int8_t *p, int64_t n, int8_t v)
+// elements carrying an overset-tagged face are fringe unless hole (blocks
+// flattened over the outputs' overset lists)
+__global__ __launch_bounds__(kThreads) void k_overset_fringe(const CutOut *__restrict__ O, int n_out)
 {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+    const int oi = block_owner(n_out, blockIdx.x, [&](int k) { return O[k].oblk0; });
+    const CutOut &o = O[oi];
+    const int64_t i = (int64_t)(blockIdx.x - o.oblk0) * blockDim.x + threadIdx.x;
+    if (i < o.n_overset) {
+        const int e = o.overset[i];
+        if (o.iblank[e] != OC_HOLE) o.iblank[e] = OC_FRINGE;
+    }
 }
 
 // -------------------------------------------------------------- host side --
@@ -907,110 +1001,182 @@ static unsigned grid_for(int64_t n, int per_block, unsigned cap)
         time_end(ctx, st, slot_);                                                            \
     } while (0)
 
-static oc_status cut_one_surface(oc_slot *sl, Grid &g, int surf_id, Surf &s, const Pose *pose_dev, int8_t *iblank,
-                                 bool first, const int8_t *prev, double sweep)
+static int64_t blocks_of(int64_t n, int64_t per_block) { return (n + per_block - 1) / per_block; }
+
+CutCaps cut_caps(const CutReq *reqs, int n)
+{
+    CutCaps c;
+    for (int r = 0; r < n; ++r) {
+        const CutReq &q = reqs[r];
+        c.outs += 1;
+        for (int k = 0; k < q.n_surf; ++k) {
+            const Surf &s = *q.surfs[k];
+            c.elem_inst += q.g->n_elem;
+            c.faces += s.n_face;
+            c.bins += (int64_t)s.nb_max * s.nb_max * s.nb_max;
+            c.cuts += 1;
+        }
+    }
+    return c;
+}
+
+// Host bytes travel to the device as kernel arguments, in stream order: the
+// copy is captured by graph capture like any launch and the host array may
+// be reused as soon as the call returns.
+struct BytePack {
+    unsigned char b[2048];
+    int n;
+    int pad;
+};
+
+__global__ void k_put_bytes(unsigned char *dst, BytePack pk)
+{
+    for (int i = threadIdx.x; i < pk.n; i += blockDim.x) dst[i] = pk.b[i];
+}
+
+oc_status put_bytes(oc_slot *sl, void *dst, const void *src, size_t n)
 {
     oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
-    SurfWork &w = sl->sw.at(surf_id);
-    const unsigned fb = grid_for(s.n_face, kThreads, 1u << 30);
-    LAUNCH(k_surf_init, dim3(1), dim3(64), w.params, sl->counters);
-    LAUNCH(k_pose_faces, dim3(fb), dim3(kThreads), s.nodes, s.n_nodes, s.conn, s.n_face, pose_dev, w.pnodes, w.fbox,
-           w.params);
-    LAUNCH(k_bins_setup, dim3(1), dim3(64), w.params, s.dmax, s.nb_max);
-    const int64_t bcap = (int64_t)s.nb_max * s.nb_max * s.nb_max;
-    LAUNCH(k_zero_i32, dim3(grid_for(bcap + 1, kThreads, 4096)), dim3(kThreads), w.bin_count, &w.params->n_bins,
-           (int64_t)0);
-    LAUNCH(k_bin_count, dim3(fb), dim3(kThreads), w.fbox, s.n_face, w.params, w.bin_count);
-    OC_TRY(scan_exclusive(ctx, st, w.bin_count, w.bin_start, bcap, &w.params->n_bins, w.scan_tmp));
-    LAUNCH(k_bin_fill, dim3(fb), dim3(kThreads), w.fbox, s.n_face, w.params, w.bin_start, w.bin_count, w.bin_items);
-
-    LAUNCH(k_filter, dim3(grid_for(g.n_elem, kThreads * 4, 8192)), dim3(kThreads), g.ebox, g.n_elem, g.ebox_stride,
-           w.params, iblank, first ? 1 : 0, sl->list_inbox, sl->counters);
-    LAUNCH(k_candidates, dim3(8192), dim3(64), g.ebox, g.ebox_stride, w.fbox, w.params, w.bin_start, w.bin_items,
-           sl->list_inbox, sl->list_near, sl->list_far, sl->counters, prev, sweep, iblank, sl->list_hole);
-    ExactArgs ea;
-    ea.enodes = g.enodes;
-    ea.ebox = g.ebox;
-    ea.stride = g.ebox_stride;
-    ea.pnodes = w.pnodes;
-    ea.fbox = w.fbox;
-    ea.bstart = w.bin_start;
-    ea.bitems = w.bin_items;
-    ea.sp = w.params;
-    ea.list_near = sl->list_near;
-    ea.list_side = sl->list_side;
-    ea.cnt = sl->counters;
-    ea.iblank = iblank;
-    ea.list_hole = sl->list_hole;
-    ea.kind = s.kind;
-    ea.pad = 0;
-    ea.pose = pose_dev;
-    for (int i = 0; i < 3; ++i) ea.first[i] = s.first[i];
-    LAUNCH(k_hit, dim3(8192), dim3(64), ea);
-    LAUNCH(k_side, dim3(8192), dim3(64), ea);
-    LAUNCH(k_ray, dim3(8192), dim3(64), g.enodes, w.pnodes, w.fbox, w.params, w.bin_start, w.bin_items,
-           sl->list_far, sl->counters, iblank, sl->list_hole);
+    const unsigned char *p = static_cast<const unsigned char *>(src);
+    for (size_t k0 = 0; k0 < n; k0 += sizeof(BytePack::b)) {
+        BytePack pk;
+        pk.n = (int)std::min(sizeof pk.b, n - k0);
+        pk.pad = 0;
+        memcpy(pk.b, p + k0, (size_t)pk.n);
+        LAUNCH(k_put_bytes, dim3(1), dim3(256), static_cast<unsigned char *>(dst) + k0, pk);
+    }
     OC_HIP(hipGetLastError());
     return OC_OK;
 }
 
-struct PosePack {
-    Pose p[8];
-    int n;
-};
-
-__global__ void k_set_poses(Pose *dst, PosePack pk)
-{
-    if (blockIdx.x == 0 && (int)threadIdx.x < pk.n) dst[threadIdx.x] = pk.p[threadIdx.x];
-}
-
-// Host poses into the slot's device pose slots, ordered on the slot stream
-// (the values travel as kernel arguments, so the host array may be reused
-// as soon as this returns).
+// Host poses into the slot's device pose slots.
 oc_status set_poses(oc_slot *sl, int first, const double *host, int n)
 {
-    oc_ctx *ctx = sl->ctx;
-    hipStream_t st = sl->stream;
     if (first < 0 || n < 0 || first + n > kPoseSlots) {
         set_error("too many poses");
         return OC_EINVAL;
     }
-    for (int k0 = 0; k0 < n; k0 += 8) {
-        PosePack pk;
-        pk.n = std::min(8, n - k0);
-        for (int k = 0; k < pk.n; ++k) {
-            for (int i = 0; i < 9; ++i) pk.p[k].r[i] = host[12 * (k0 + k) + i];
-            for (int i = 0; i < 3; ++i) pk.p[k].t[i] = host[12 * (k0 + k) + 9 + i];
-        }
-        LAUNCH(k_set_poses, dim3(1), dim3(64), sl->poses + first + k0, pk);
+    if (n == 0) return OC_OK;
+    std::vector<Pose> P((size_t)n);
+    for (int k = 0; k < n; ++k) {
+        for (int i = 0; i < 9; ++i) P[k].r[i] = host[12 * k + i];
+        for (int i = 0; i < 3; ++i) P[k].t[i] = host[12 * k + 9 + i];
     }
-    OC_HIP(hipGetLastError());
-    return OC_OK;
+    return put_bytes(sl, sl->poses + first, P.data(), sizeof(Pose) * (size_t)n);
 }
 
-oc_status cut_run(oc_slot *sl, Grid &g, const int *surf_ids, Surf **surfs, const Pose *poses_dev, int n_surf,
-                  int8_t *iblank, const int8_t *prev, double sweep)
+// Every request's cuts run together, one launch per stage: launches over
+// faces or elements are flattened over the cuts (each block finds its cut
+// from the cuts' first blocks), the later stages take (cut, element) items
+// from batch-wide lists, so instances of very different sizes share the
+// device without one launch sequence per instance.
+oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
 {
-    if (prev && n_surf != 1) {
-        set_error("warm start needs exactly one cutting surface");
-        return OC_EINVAL;
-    }
     oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
-    OC_TRY(slot_reserve_grid(sl, g));
-    for (int k = 0; k < n_surf; ++k) OC_TRY(slot_reserve_surf(sl, surf_ids[k], *surfs[k]));
-    sl->last_n_elem = g.n_elem;
-    LAUNCH(k_reset_counters, dim3(1), dim3(64), sl->counters);
-    if (n_surf == 0)
-        LAUNCH(k_fill_i8, dim3(grid_for(g.n_elem, kThreads, 4096)), dim3(kThreads), iblank, g.n_elem,
-               (int8_t)OC_FIELD);
-    for (int k = 0; k < n_surf; ++k)
-        OC_TRY(cut_one_surface(sl, g, surf_ids[k], *surfs[k], poses_dev + k, iblank, k == 0, prev, sweep));
-    LAUNCH(k_fringe, dim3(1024), dim3(kThreads), g.nbr, sl->list_hole, sl->counters, iblank);
-    if (g.n_overset > 0)
-        LAUNCH(k_overset_fringe, dim3(grid_for(g.n_overset, kThreads, 4096)), dim3(kThreads), g.overset, g.n_overset,
-               iblank);
+    const CutCaps need = cut_caps(reqs, n_req);
+    OC_TRY(slot_reserve_cut(sl, need));
+    for (int r = 0; r < n_req; ++r) {
+        if (reqs[r].prev && reqs[r].n_surf != 1) {
+            set_error("warm start needs exactly one cutting surface");
+            return OC_EINVAL;
+        }
+        for (int q = 0; q < r; ++q)
+            if (reqs[q].iblank == reqs[r].iblank) {
+                set_error("two requests of one batch write the same iblank");
+                return OC_EINVAL;
+            }
+    }
+    std::vector<CutInst> I;
+    std::vector<CutOut> O;
+    int64_t fblk = 0, eblk = 0, face_off = 0, fill_blk = 0, ov_blk = 0, n_elem_total = 0;
+    for (int r = 0; r < n_req; ++r) {
+        const CutReq &q = reqs[r];
+        const Grid &g = *q.g;
+        CutOut o{};
+        o.iblank = q.iblank;
+        o.overset = g.overset;
+        o.n_elem = g.n_elem;
+        o.n_overset = g.n_overset;
+        o.fblk0 = (int)fill_blk;
+        o.oblk0 = (int)ov_blk;
+        if (q.n_surf == 0) fill_blk += blocks_of(g.n_elem, kThreads);
+        ov_blk += blocks_of(g.n_overset, kThreads);
+        O.push_back(o);
+        n_elem_total += g.n_elem;
+        for (int k = 0; k < q.n_surf; ++k) {
+            const Surf &s = *q.surfs[k];
+            CutInst c{};
+            c.enodes = g.enodes;
+            c.ebox = g.ebox;
+            c.nbr = g.nbr;
+            c.snodes = s.nodes;
+            c.conn = s.conn;
+            c.pose = q.poses + k;
+            c.pnodes = sl->pnodes + 27 * face_off;
+            c.fbox = sl->fbox + 6 * face_off;
+            c.params = sl->params + I.size();
+            c.iblank = q.iblank;
+            c.prev = q.prev;
+            c.sweep = q.sweep;
+            c.stride = g.ebox_stride;
+            c.n_elem = g.n_elem;
+            c.n_nodes = s.n_nodes;
+            c.n_face = s.n_face;
+            for (int d = 0; d < 3; ++d) c.first[d] = s.first[d];
+            c.dmax = s.dmax;
+            c.nb_max = s.nb_max;
+            c.kind = s.kind;
+            c.write_field = k == 0;
+            c.fblk0 = (int)fblk;
+            c.eblk0 = (int)eblk;
+            fblk += blocks_of(s.n_face, kThreads);
+            eblk += blocks_of(g.n_elem, kThreads * 4);
+            face_off += s.n_face;
+            I.push_back(c);
+        }
+    }
+    if (fblk >= INT32_MAX || eblk >= INT32_MAX || fill_blk >= INT32_MAX || ov_blk >= INT32_MAX ||
+        need.elem_inst >= INT32_MAX) {
+        set_error("cut batch too large");
+        return OC_EINVAL;
+    }
+    sl->last_n_elem = n_elem_total;
+    const int n_cut = (int)I.size(), n_out = (int)O.size();
+    int32_t *n_bins_dev = sl->scalar + 4;
+    if (n_cut) OC_TRY(put_bytes(sl, sl->insts, I.data(), sizeof(CutInst) * I.size()));
+    if (fill_blk || ov_blk) OC_TRY(put_bytes(sl, sl->outs, O.data(), sizeof(CutOut) * O.size()));
+    LAUNCH(k_reset_counters, dim3(1), dim3(kThreads), sl->counters, sl->insts, n_cut);
+    if (fill_blk) LAUNCH(k_fill_field, dim3((unsigned)fill_blk), dim3(kThreads), sl->outs, n_out);
+    if (n_cut) {
+        LAUNCH(k_pose_faces, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut);
+        LAUNCH(k_bins_setup, dim3(1), dim3(kThreads), sl->insts, n_cut, n_bins_dev);
+        LAUNCH(k_zero_i32, dim3(grid_for(need.bins + 1, kThreads, 4096)), dim3(kThreads), sl->bin_count, n_bins_dev,
+               (int64_t)0);
+        LAUNCH(k_bin_count, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_count);
+        OC_TRY(scan_exclusive(ctx, st, sl->bin_count, sl->bin_start, need.bins, n_bins_dev, sl->bin_scan_tmp));
+        LAUNCH(k_bin_fill, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_start, sl->bin_count,
+               sl->bin_items);
+        LAUNCH(k_filter, dim3((unsigned)eblk), dim3(kThreads), sl->insts, n_cut, sl->l_inbox, sl->counters);
+        LAUNCH(k_candidates, dim3(8192), dim3(64), sl->insts, sl->bin_start, sl->bin_items, sl->l_inbox, sl->l_near,
+               sl->l_far, sl->l_hole, sl->counters);
+        ExactArgs ea;
+        ea.insts = sl->insts;
+        ea.bin_start = sl->bin_start;
+        ea.bitems = sl->bin_items;
+        ea.list_in = sl->l_near;
+        ea.list_side = sl->l_side;
+        ea.list_hole = sl->l_hole;
+        ea.cnt = sl->counters;
+        LAUNCH(k_hit, dim3(8192), dim3(64), ea);
+        ea.list_in = sl->l_side;
+        LAUNCH(k_side, dim3(8192), dim3(64), ea);
+        LAUNCH(k_ray, dim3(8192), dim3(64), sl->insts, sl->bin_start, sl->bin_items, sl->l_far, sl->l_hole,
+               sl->counters);
+        LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_hole, sl->counters);
+    }
+    if (ov_blk) LAUNCH(k_overset_fringe, dim3((unsigned)ov_blk), dim3(kThreads), sl->outs, n_out);
     OC_HIP(hipGetLastError());
     return OC_OK;
 }

@@ -69,9 +69,7 @@ static oc_status slot_alloc_lists(oc_slot *sl, int64_t n_elem)
 {
     oc_ctx *ctx = sl->ctx;
     const size_t ne = (size_t)std::max<int64_t>(n_elem, 1);
-    int32_t **lists[6] = {&sl->list_inbox, &sl->list_near, &sl->list_far, &sl->list_hole, &sl->list_fringe,
-                          &sl->list_side};
-    for (auto l : lists) OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * ne, (void **)l));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * ne, (void **)&sl->list_fringe));
     const int64_t nt = (n_elem + 4095) / 4096;
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * (2 * (nt + 1) + scan_tmp_ints(nt) + 8), (void **)&sl->fr_tiles));
     sl->list_cap = n_elem;
@@ -79,19 +77,30 @@ static oc_status slot_alloc_lists(oc_slot *sl, int64_t n_elem)
     return OC_OK;
 }
 
-static oc_status slot_alloc_surf(oc_slot *sl, int surf_id, const Surf &s)
+// cut scratch for caps c (replaces any previous cut scratch of the slot)
+static oc_status slot_alloc_cut(oc_slot *sl, CutCaps c)
 {
     oc_ctx *ctx = sl->ctx;
-    SurfWork w;
-    const int64_t bcap = (int64_t)s.nb_max * s.nb_max * s.nb_max + 1;
-    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(double) * 27 * s.n_face, (void **)&w.pnodes));
-    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(float) * 6 * s.n_face, (void **)&w.fbox));
-    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * bcap, (void **)&w.bin_count));
-    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * bcap, (void **)&w.bin_start));
-    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * 8 * s.n_face, (void **)&w.bin_items));
-    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * scan_tmp_ints(bcap), (void **)&w.scan_tmp));
-    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(SurfParams), (void **)&w.params));
-    sl->sw[surf_id] = w;
+    dev_free_all(ctx, sl->cut_owned);
+    sl->cc = CutCaps{};
+    c.elem_inst = std::max<int64_t>(c.elem_inst, 1);
+    c.faces = std::max<int64_t>(c.faces, 1);
+    c.bins = std::max<int64_t>(c.bins, 1);
+    c.cuts = std::max<int64_t>(c.cuts, 1);
+    c.outs = std::max<int64_t>(c.outs, 1);
+    auto &o = sl->cut_owned;
+    uint64_t **lists[5] = {&sl->l_inbox, &sl->l_near, &sl->l_far, &sl->l_side, &sl->l_hole};
+    for (auto l : lists) OC_TRY(dev_alloc(ctx, o, sizeof(uint64_t) * (size_t)c.elem_inst, (void **)l));
+    OC_TRY(dev_alloc(ctx, o, sizeof(CutInst) * (size_t)c.cuts, (void **)&sl->insts));
+    OC_TRY(dev_alloc(ctx, o, sizeof(CutOut) * (size_t)c.outs, (void **)&sl->outs));
+    OC_TRY(dev_alloc(ctx, o, sizeof(SurfParams) * (size_t)c.cuts, (void **)&sl->params));
+    OC_TRY(dev_alloc(ctx, o, sizeof(double) * 27 * (size_t)c.faces, (void **)&sl->pnodes));
+    OC_TRY(dev_alloc(ctx, o, sizeof(float) * 6 * (size_t)c.faces, (void **)&sl->fbox));
+    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)(c.bins + 1), (void **)&sl->bin_count));
+    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)(c.bins + 1), (void **)&sl->bin_start));
+    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * 8 * (size_t)c.faces, (void **)&sl->bin_items));
+    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)scan_tmp_ints(c.bins + 1), (void **)&sl->bin_scan_tmp));
+    sl->cc = c;
     return OC_OK;
 }
 
@@ -112,8 +121,8 @@ void slot_free(oc_slot *sl)
 {
     if (!sl) return;
     (void)hipStreamSynchronize(sl->stream);
+    dev_free_all(sl->ctx, sl->cut_owned);
     dev_free_all(sl->ctx, sl->owned);
-    sl->sw.clear();
 }
 
 // The default slot grows on demand (its calls may allocate); slots made by
@@ -157,14 +166,28 @@ oc_status slot_reserve_points(oc_slot *sl, int64_t cap)
     return slot_alloc_points(sl, cap);
 }
 
-oc_status slot_reserve_surf(oc_slot *sl, int surf_id, const Surf &s)
+static bool caps_fit(const CutCaps &have, const CutCaps &need)
 {
-    if (sl->sw.count(surf_id)) return OC_OK;
+    return need.elem_inst <= have.elem_inst && need.faces <= have.faces && need.bins <= have.bins &&
+           need.cuts <= have.cuts && need.outs <= have.outs;
+}
+
+oc_status slot_reserve_cut(oc_slot *sl, const CutCaps &need)
+{
+    if (caps_fit(sl->cc, need)) return OC_OK;
     if (!sl->grow) {
-        set_error("slot was not created for surface " + std::to_string(surf_id));
+        set_error("slot was not created for this cut (elements x surfaces " + std::to_string(need.elem_inst) +
+                  ", faces " + std::to_string(need.faces) + ", cuts " + std::to_string(need.cuts) + ")");
         return OC_EINVAL;
     }
-    return slot_alloc_surf(sl, surf_id, s);
+    OC_HIP(hipStreamSynchronize(sl->stream));
+    CutCaps c = need;
+    c.elem_inst = std::max(c.elem_inst, sl->cc.elem_inst);
+    c.faces = std::max(c.faces, sl->cc.faces);
+    c.bins = std::max(c.bins, sl->cc.bins);
+    c.cuts = std::max(c.cuts, sl->cc.cuts);
+    c.outs = std::max(c.outs, sl->cc.outs);
+    return slot_alloc_cut(sl, c);
 }
 
 static Pose to_pose(const double *p)
@@ -558,7 +581,76 @@ oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, co
     OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
     oc_slot *sl = ctx->dflt;
     OC_TRY(set_poses(sl, 0, poses, n_surf));
-    return cut_run(sl, *g, surf_ids, ss.data(), sl->poses, n_surf, iblank_out);
+    CutReq q;
+    q.g = g;
+    q.n_surf = n_surf;
+    q.surfs = ss.data();
+    q.poses = sl->poses;
+    q.iblank = iblank_out;
+    return cut_batch_run(sl, &q, 1);
+}
+
+// Validates a batch and resolves its ids; poses of request r start at
+// pose_base[r] (device).
+static oc_status batch_reqs(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req, std::vector<CutReq> &out,
+                            std::vector<std::vector<Surf *>> &surfs, bool need_outputs)
+{
+    if (n_req < 0 || (n_req > 0 && !reqs)) {
+        set_error("cut batch: invalid arguments");
+        return OC_EINVAL;
+    }
+    out.assign((size_t)n_req, CutReq{});
+    surfs.assign((size_t)n_req, {});
+    for (int r = 0; r < n_req; ++r) {
+        const oc_cut_req &q = reqs[r];
+        if (q.n_surf < 0 || (q.n_surf > 0 && !q.surf_ids) ||
+            (need_outputs && (!q.iblank_out || !aligned4(q.iblank_out) || (q.n_surf > 0 && !q.poses)))) {
+            set_error("cut batch: invalid request " + std::to_string(r));
+            return OC_EINVAL;
+        }
+        OC_TRY(get_grid(ctx, q.grid_id, &out[r].g));
+        OC_TRY(collect_surfs(ctx, q.surf_ids, q.n_surf, surfs[r]));
+        out[r].n_surf = q.n_surf;
+        out[r].surfs = surfs[r].data();
+        out[r].iblank = q.iblank_out;
+    }
+    return OC_OK;
+}
+
+oc_status oc_cut_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req)
+{
+    if (!ctx) {
+        set_error("oc_cut_batch: null context");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    std::vector<CutReq> rq;
+    std::vector<std::vector<Surf *>> ss;
+    OC_TRY(batch_reqs(ctx, reqs, n_req, rq, ss, true));
+    int n_pose = 0;
+    for (int r = 0; r < n_req; ++r) n_pose += reqs[r].n_surf;
+    if (n_pose > kPoseSlots - 2) {
+        set_error("oc_cut_batch: more than " + std::to_string(kPoseSlots - 2) + " poses");
+        return OC_EINVAL;
+    }
+    std::vector<double> P;
+    P.reserve((size_t)n_pose * 12);
+    for (int r = 0; r < n_req; ++r)
+        for (int k = 0; k < reqs[r].n_surf; ++k) {
+            if (!pose_ok(reqs[r].poses + 12 * k)) {
+                set_error("oc_cut_batch: non-finite pose");
+                return OC_EINVAL;
+            }
+            P.insert(P.end(), reqs[r].poses + 12 * k, reqs[r].poses + 12 * k + 12);
+        }
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, 0, P.data(), n_pose));
+    int p0 = 0;
+    for (int r = 0; r < n_req; ++r) {
+        rq[r].poses = sl->poses + p0;
+        p0 += reqs[r].n_surf;
+    }
+    return cut_batch_run(sl, rq.data(), n_req);
 }
 
 oc_status oc_cut(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pose[12], int8_t *iblank_out)
@@ -658,8 +750,15 @@ oc_status oc_cut_warm(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const doubl
     OC_TRY(collect_surfs(ctx, &surf_id, 1, ss));
     oc_slot *sl = ctx->dflt;
     OC_TRY(set_poses(sl, 0, pose, 1));
-    return cut_run(sl, *g, &surf_id, ss.data(), sl->poses, 1, iblank_out, prev_iblank,
-                   sweep_bound(*ss[0], prev_pose, pose));
+    CutReq q;
+    q.g = g;
+    q.n_surf = 1;
+    q.surfs = ss.data();
+    q.poses = sl->poses;
+    q.iblank = iblank_out;
+    q.prev = prev_iblank;
+    q.sweep = sweep_bound(*ss[0], prev_pose, pose);
+    return cut_batch_run(sl, &q, 1);
 }
 
 // ------------------------------------------------------------- slot API --
@@ -681,12 +780,20 @@ oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, 
     }
     std::vector<Surf *> ss;
     OC_TRY(collect_surfs(ctx, surf_ids, n_surfs, ss));
+    // any cut of one listed grid by any of the listed surfaces
+    CutCaps cc;
+    cc.outs = 1;
+    cc.cuts = n_surfs;
+    cc.elem_inst = ne * n_surfs;
+    for (auto s : ss) {
+        cc.faces += s->n_face;
+        cc.bins += (int64_t)s->nb_max * s->nb_max * s->nb_max;
+    }
     oc_slot *sl = new oc_slot();
     oc_status st = slot_init(ctx, sl, false);
     if (st == OC_OK) st = slot_alloc_lists(sl, ne);
+    if (st == OC_OK) st = slot_alloc_cut(sl, cc);
     if (st == OC_OK && points_cap > 0) st = slot_alloc_points(sl, points_cap);
-    for (int k = 0; k < n_surfs && st == OC_OK; ++k)
-        if (!sl->sw.count(surf_ids[k])) st = slot_alloc_surf(sl, surf_ids[k], *ss[k]);
     if (st != OC_OK) {
         slot_free(sl);
         delete sl;
@@ -748,7 +855,63 @@ oc_status oc_slot_cut(oc_slot *sl, int32_t grid_id, const int32_t *surf_ids, con
     OC_TRY(get_grid(ctx, grid_id, &g));
     std::vector<Surf *> ss;
     OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
-    return cut_run(sl, *g, surf_ids, ss.data(), reinterpret_cast<const Pose *>(poses_dev), n_surf, iblank_out);
+    CutReq q;
+    q.g = g;
+    q.n_surf = n_surf;
+    q.surfs = ss.data();
+    q.poses = reinterpret_cast<const Pose *>(poses_dev);
+    q.iblank = iblank_out;
+    return cut_batch_run(sl, &q, 1);
+}
+
+oc_status oc_slot_cut_batch(oc_slot *sl, const oc_cut_req *reqs, int32_t n_req)
+{
+    if (!sl) {
+        set_error("oc_slot_cut_batch: null slot");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    std::vector<CutReq> rq;
+    std::vector<std::vector<Surf *>> ss;
+    OC_TRY(batch_reqs(ctx, reqs, n_req, rq, ss, true));
+    for (int r = 0; r < n_req; ++r) {
+        if ((uintptr_t)reqs[r].poses & 7) {
+            set_error("oc_slot_cut_batch: poses must be 8-byte aligned");
+            return OC_EINVAL;
+        }
+        rq[r].poses = reinterpret_cast<const Pose *>(reqs[r].poses);
+    }
+    return cut_batch_run(sl, rq.data(), n_req);
+}
+
+oc_status oc_slot_create_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req, int64_t points_cap,
+                               oc_slot **out)
+{
+    if (!ctx || !out || points_cap < 0) {
+        set_error("oc_slot_create_batch: invalid arguments");
+        return OC_EINVAL;
+    }
+    *out = nullptr;
+    OC_HIP(hipSetDevice(ctx->device));
+    std::vector<CutReq> rq;
+    std::vector<std::vector<Surf *>> ss;
+    OC_TRY(batch_reqs(ctx, reqs, n_req, rq, ss, false));
+    int64_t ne = 1;
+    for (auto &q : rq) ne = std::max(ne, q.g->n_elem);
+    oc_slot *sl = new oc_slot();
+    oc_status st = slot_init(ctx, sl, false);
+    if (st == OC_OK) st = slot_alloc_lists(sl, ne);
+    if (st == OC_OK) st = slot_alloc_cut(sl, cut_caps(rq.data(), n_req));
+    if (st == OC_OK && points_cap > 0) st = slot_alloc_points(sl, points_cap);
+    if (st != OC_OK) {
+        slot_free(sl);
+        delete sl;
+        return st;
+    }
+    ctx->slots.push_back(sl);
+    *out = sl;
+    return OC_OK;
 }
 
 oc_status oc_slot_cut_warm(oc_slot *sl, int32_t grid_id, int32_t surf_id, const double *pose_dev, double sweep,
@@ -765,8 +928,15 @@ oc_status oc_slot_cut_warm(oc_slot *sl, int32_t grid_id, int32_t surf_id, const 
     OC_TRY(get_grid(ctx, grid_id, &g));
     std::vector<Surf *> ss;
     OC_TRY(collect_surfs(ctx, &surf_id, 1, ss));
-    return cut_run(sl, *g, &surf_id, ss.data(), reinterpret_cast<const Pose *>(pose_dev), 1, iblank_out,
-                   prev_iblank, sweep);
+    CutReq q;
+    q.g = g;
+    q.n_surf = 1;
+    q.surfs = ss.data();
+    q.poses = reinterpret_cast<const Pose *>(pose_dev);
+    q.iblank = iblank_out;
+    q.prev = prev_iblank;
+    q.sweep = sweep;
+    return cut_batch_run(sl, &q, 1);
 }
 
 oc_status oc_slot_fringe_points(oc_slot *sl, int32_t grid_id, const double *pose_dev, const int8_t *iblank,

@@ -47,7 +47,8 @@ struct SurfParams {
     float sbox[6];     // surface box (lo xyz, hi xyz), FP32, outward
     BinGrid grid;      // bins over the surface box
     int n_bins;        // grid.n[0]*n[1]*n[2]
-    int pad[3];
+    int bin_off;       // first bin of this cut in the batch's bin arrays
+    int pad[2];
 };
 
 // Per-cut counters (device).
@@ -97,24 +98,55 @@ struct Surf {
     std::vector<DevBuf> owned;
 };
 
-// Per-request scratch of one surface in a slot.
-struct SurfWork {
-    double *pnodes = nullptr;      // [n_face][27]: x[9], y[9], z[9] posed
-    float *fbox = nullptr;         // [n_face][6] inflated outward FP32 boxes
-    int32_t *bin_count = nullptr;  // [nb_max^3 + 1]
-    int32_t *bin_start = nullptr;  // [nb_max^3 + 1]
-    int32_t *bin_items = nullptr;  // [8 * n_face]
-    int32_t *scan_tmp = nullptr;
-    SurfParams *params = nullptr;
-};
-
 // Pose passed to kernels through device memory.
 struct Pose {
     double r[9];
     double t[3];
 };
 
-constexpr int kPoseSlots = 64;
+constexpr int kPoseSlots = 256;
+
+// One cut of a batch, as the kernels read it: a grid, one cutting surface
+// at a device pose, the iblank it writes (several cuts of one grid may
+// write the same iblank: union of holes) and its share of the slot's work
+// arrays.  Element lists of a batch hold (cut << 32 | element).
+struct CutInst {
+    const double *enodes;
+    const float *ebox;
+    const int32_t *nbr;
+    const double *snodes;       // surface nodes, [3][n_nodes] registration frame
+    const int32_t *conn;        // [n_face][9]
+    const Pose *pose;
+    double *pnodes;             // [n_face][27] posed: x[9], y[9], z[9]
+    float *fbox;                // [n_face][6] inflated outward FP32 boxes
+    SurfParams *params;
+    int8_t *iblank;
+    const int8_t *prev;         // warm start: previous iblank (or null)
+    int64_t stride, n_elem, n_nodes, n_face;
+    double first[3];            // first surface node, registration frame
+    double sweep;               // warm start: sweep bound
+    float dmax;
+    int nb_max, kind, write_field;
+    int fblk0, eblk0;           // first block in face / element flattened launches
+};
+
+// One output of a batch: the iblank of a grid after all of its cuts.
+struct CutOut {
+    int8_t *iblank;
+    const int32_t *overset;
+    int64_t n_elem, n_overset;
+    int fblk0;                  // first block of the field fill (no surface)
+    int oblk0;                  // first block of the overset-face fringe
+};
+
+// Capacity of a slot's cut scratch: summed over the cuts of one call.
+struct CutCaps {
+    int64_t elem_inst = 0;      // sum of the cut grids' element counts
+    int64_t faces = 0;          // sum of the surfaces' face counts
+    int64_t bins = 0;           // sum of nb_max^3
+    int64_t cuts = 0;
+    int64_t outs = 0;
+};
 
 }  // namespace oc
 
@@ -125,9 +157,8 @@ struct oc_slot {
     oc_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
     bool grow = false;                 // the context's default slot grows on demand
-    int64_t list_cap = 0;              // element lists capacity
-    int32_t *list_inbox = nullptr, *list_near = nullptr, *list_far = nullptr, *list_hole = nullptr;
-    int32_t *list_side = nullptr, *list_fringe = nullptr;
+    int64_t list_cap = 0;              // fringe-point compaction capacity (elements)
+    int32_t *list_fringe = nullptr;
     int32_t *fr_tiles = nullptr;       // fringe compaction: counts, offsets, scan scratch
     int64_t fr_tiles_cap = 0;
     oc::CutCounters *counters = nullptr;
@@ -140,7 +171,16 @@ struct oc_slot {
     double *dp_local = nullptr;
     int32_t *dp_cnt = nullptr, *dp_off = nullptr, *dp_best = nullptr, *dp_scan_tmp = nullptr;
     int32_t *dpair_pt = nullptr, *dpair_el = nullptr;
-    std::map<int, oc::SurfWork> sw;
+    // cut scratch of a batch
+    oc::CutCaps cc;
+    uint64_t *l_inbox = nullptr, *l_near = nullptr, *l_far = nullptr, *l_side = nullptr, *l_hole = nullptr;
+    oc::CutInst *insts = nullptr;
+    oc::CutOut *outs = nullptr;
+    oc::SurfParams *params = nullptr;
+    double *pnodes = nullptr;
+    float *fbox = nullptr;
+    int32_t *bin_count = nullptr, *bin_start = nullptr, *bin_items = nullptr, *bin_scan_tmp = nullptr;
+    std::vector<oc::DevBuf> cut_owned;   // the cut scratch above (replaced when the default slot grows)
     std::vector<oc::DevBuf> owned;
 };
 
@@ -193,19 +233,33 @@ oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g);
 
 // slot scratch sizing (grow-only for the default slot)
 oc_status slot_reserve_grid(oc_slot *sl, const Grid &g);
-oc_status slot_reserve_surf(oc_slot *sl, int surf_id, const Surf &s);
+oc_status slot_reserve_cut(oc_slot *sl, const CutCaps &need);
 oc_status slot_reserve_points(oc_slot *sl, int64_t cap);
 constexpr int kPairsPerPoint = 8;   // pair capacity per point capacity
 
 oc_status set_poses(oc_slot *sl, int first, const double *host, int n);
+// copy host bytes to device memory in stream order through kernel
+// arguments (capturable; the host array may be reused on return)
+oc_status put_bytes(oc_slot *sl, void *dst, const void *src, size_t n);
 oc_status slot_init(oc_ctx *ctx, oc_slot *sl, bool grow);
 void slot_free(oc_slot *sl);
 
-// cut pipeline; poses are device pointers (one Pose per surface)
-// warm start: prev = previous iblank of the same grid and single surface,
-// sweep = bound on how far any surface point moved since (0 / null: cold)
-oc_status cut_run(oc_slot *sl, Grid &g, const int *surf_ids, Surf **surfs, const Pose *poses_dev, int n_surf,
-                  int8_t *iblank, const int8_t *prev = nullptr, double sweep = 0.0);
+// One request of a cut batch: a grid cut by n_surf surfaces (union of
+// holes) at device poses, into its own iblank.  Warm start: prev = previous
+// iblank of the same grid and single surface, sweep = bound on how far any
+// surface point moved since (null / 0: cold).
+struct CutReq {
+    Grid *g = nullptr;
+    int n_surf = 0;
+    Surf *const *surfs = nullptr;
+    const Pose *poses = nullptr;
+    int8_t *iblank = nullptr;
+    const int8_t *prev = nullptr;
+    double sweep = 0.0;
+};
+CutCaps cut_caps(const CutReq *reqs, int n);
+// every request's cuts in one launch per stage
+oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n);
 // receptor points: the count stays on the device (n_dev, int32) and is also
 // returned on the host when n_host is not null (synchronising)
 oc_status fringe_points_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const int8_t *iblank, double *pts,

@@ -27,7 +27,8 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_donor_search", "oc_last_donor_info", "oc_timing", "oc_timing_report", "oc_memory_used",
            "oc_slot_create", "oc_slot_destroy", "oc_slot_set_stream", "oc_slot_bytes", "oc_slot_cut",
            "oc_slot_fringe_points", "oc_slot_donor_search", "oc_slot_cut_info", "oc_slot_donor_info",
-           "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm"]
+           "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm", "oc_cut_batch", "oc_slot_cut_batch",
+           "oc_slot_create_batch"]
 
 
 class OcError(RuntimeError):
@@ -44,6 +45,11 @@ class oc_config(C.Structure):
 class oc_cut_info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_elem", "n_inbox", "n_near", "n_far", "n_hit", "n_hole",
                                          "n_cand_pairs")]
+
+
+class oc_cut_req(C.Structure):
+    _fields_ = [("grid_id", C.c_int32), ("n_surf", C.c_int32), ("surf_ids", C.POINTER(C.c_int32)),
+                ("poses", C.c_void_p), ("iblank_out", C.c_void_p)]
 
 
 class oc_donor_info(C.Structure):
@@ -90,6 +96,9 @@ def load(path=LIB_PATH):
         "oc_cut_warm": ([vp, C.c_int32, C.c_int32, dp, dp, vp, vp]),
         "oc_sweep_bound": ([vp, C.c_int32, dp, dp, dp]),
         "oc_slot_cut_warm": ([vp, C.c_int32, C.c_int32, vp, C.c_double, vp, vp]),
+        "oc_cut_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32]),
+        "oc_slot_cut_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32]),
+        "oc_slot_create_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32, C.c_int64, C.POINTER(C.c_void_p)]),
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -119,6 +128,34 @@ def _dptr(t, dtype, n=None):
     if n is not None and t.numel() < n:
         raise ValueError("tensor too small: %d < %d" % (t.numel(), n))
     return C.c_void_p(t.data_ptr())
+
+
+def _cut_reqs(ctx, reqs, device_poses):
+    """oc_cut_req array for [(grid_id, surf_ids, poses, iblank)]; poses are
+    host arrays [k,12] or, with device_poses, float64 CUDA tensors [k,12]
+    (iblank may be None when only the shape of the batch matters).  Returns
+    the array and the host buffers it points into (keep them alive)."""
+    import torch
+    arr = (oc_cut_req * max(len(reqs), 1))()
+    keep = []
+    for r, (gid, sids, poses, ib) in enumerate(reqs):
+        ids = np.ascontiguousarray(sids, dtype=np.int32)
+        keep.append(ids)
+        arr[r].grid_id = int(gid)
+        arr[r].n_surf = len(ids)
+        arr[r].surf_ids = ids.ctypes.data_as(C.POINTER(C.c_int32))
+        if len(ids) and poses is not None:
+            if device_poses:
+                arr[r].poses = _dptr(poses, torch.float64, 12 * len(ids)).value
+            else:
+                pa = np.ascontiguousarray(poses, dtype=np.float64).reshape(-1)
+                if pa.size != 12 * len(ids):
+                    raise ValueError("request %d: %d poses for %d surfaces" % (r, pa.size // 12, len(ids)))
+                keep.append(pa)
+                arr[r].poses = pa.ctypes.data
+        if ib is not None:
+            arr[r].iblank_out = _dptr(ib, torch.int8, ctx.grids[gid]).value
+    return arr, keep
 
 
 class Context:
@@ -195,6 +232,12 @@ class Context:
                                    _dptr(iblank, torch.int8, self.grids[grid_id])))
         return iblank
 
+    def cut_batch(self, reqs):
+        """reqs: [(grid_id, surf_ids, host poses [k,12], iblank tensor)];
+        every request's cuts in one launch per stage."""
+        arr, keep = _cut_reqs(self, reqs, device_poses=False)
+        _check(load().oc_cut_batch(self._h, arr, len(reqs)))
+
     def cut_warm(self, grid_id, surf_id, pose, prev_pose, prev_iblank, iblank):
         import torch
         _, pp = _pose(pose)
@@ -256,6 +299,10 @@ class Context:
     def create_slot(self, grid_ids, surf_ids, points_cap=0, stream=None):
         return Slot(self, grid_ids, surf_ids, points_cap, stream)
 
+    def create_batch_slot(self, reqs, points_cap=0, stream=None):
+        """Slot sized for batches shaped like reqs [(grid_id, surf_ids, ...)]."""
+        return Slot(self, None, None, points_cap, stream, batch=[(r[0], r[1], None, None) for r in reqs])
+
 
 def _dev_or_null(t, dtype):
     return None if t is None else _dptr(t, dtype)
@@ -267,15 +314,19 @@ class Slot:
     (int32 tensors), never allocate and never synchronise, so they can be
     captured in a graph or run concurrently with other slots."""
 
-    def __init__(self, ctx: Context, grid_ids, surf_ids, points_cap=0, stream=None):
+    def __init__(self, ctx: Context, grid_ids, surf_ids, points_cap=0, stream=None, batch=None):
         import torch
         self.ctx = ctx
-        g = np.ascontiguousarray(grid_ids, dtype=np.int32)
-        sid = np.ascontiguousarray(surf_ids, dtype=np.int32)
         h = C.c_void_p()
-        _check(load().oc_slot_create(ctx._h, g.ctypes.data_as(C.POINTER(C.c_int32)), len(g),
-                                     sid.ctypes.data_as(C.POINTER(C.c_int32)), len(sid), int(points_cap),
-                                     C.byref(h)))
+        if batch is not None:
+            arr, keep = _cut_reqs(ctx, batch, device_poses=True)
+            _check(load().oc_slot_create_batch(ctx._h, arr, len(batch), int(points_cap), C.byref(h)))
+        else:
+            g = np.ascontiguousarray(grid_ids, dtype=np.int32)
+            sid = np.ascontiguousarray(surf_ids, dtype=np.int32)
+            _check(load().oc_slot_create(ctx._h, g.ctypes.data_as(C.POINTER(C.c_int32)), len(g),
+                                         sid.ctypes.data_as(C.POINTER(C.c_int32)), len(sid), int(points_cap),
+                                         C.byref(h)))
         self._h = h
         self.stream = stream if stream is not None else torch.cuda.Stream(device=ctx.device)
         self.set_stream(self.stream)
@@ -306,6 +357,11 @@ class Slot:
         pp = _dptr(poses_dev, torch.float64, 12 * len(ids)) if len(ids) else None
         _check(load().oc_slot_cut(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
                                   _dptr(iblank, torch.int8, self.ctx.grids[grid_id])))
+
+    def cut_batch(self, reqs):
+        """reqs: [(grid_id, surf_ids, device poses [k,12] tensor, iblank)]."""
+        arr, keep = _cut_reqs(self.ctx, reqs, device_poses=True)
+        _check(load().oc_slot_cut_batch(self._h, arr, len(reqs)))
 
     def cut_warm(self, grid_id, surf_id, pose_dev, sweep, prev_iblank, iblank):
         import torch
