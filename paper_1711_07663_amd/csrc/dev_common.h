@@ -27,7 +27,7 @@ __host__ __device__ inline float f32_up(double v)
     return f;
 }
 
-// Order-preserving map float <-> int (for atomic min / max of floats).
+// Order-preserving map float <-> int (min / max of floats taken on ints).
 __device__ inline int f2ord(float f)
 {
     int i = __float_as_int(f);

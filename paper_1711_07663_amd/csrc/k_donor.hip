@@ -5,15 +5,18 @@
 //   k_fringe_points                  27 Gauss points per fringe element mapped
 //                                    by the quadratic isoparametric map
 //                                    (eq. reftophys) and posed to world frame
-//   k_donor                          per point: inverse pose into the donor
+//   k_dp_count / scan / k_dp_fill    per point: inverse pose into the donor
 //                                    grid's registration frame (the rigid
 //                                    motion trick of Sec. 4.3), one bin lookup
-//                                    of control-net boxes, then Newton
-//                                    (eq. ref-update, eq. Jac) on the boxes that
-//                                    contain the point in ascending element id;
-//                                    the first element that contains it wins.
+//                                    of control-net boxes, and the boxes that
+//                                    contain it as (point, element) pairs
+//   k_dp_newton                      Newton (eq. ref-update, eq. Jac) on every
+//                                    pair; the lowest containing id wins
+//   k_dp_final                       donor id and reference coordinates
 // Registration-time kernels build the element node copies, the FP32 element
 // boxes and the donor bins.
+#include <cstring>
+
 #include "dev_common.h"
 
 namespace oc {
@@ -33,67 +36,87 @@ __device__ inline void lag2(double s, double *l, double *dl)
 
 __device__ inline double pick3(int i, double a, double b, double c) { return i == 0 ? a : (i == 1 ? b : c); }
 
-// x(xi) and J = dx/dxi of an element stored as x[27], y[27], z[27].  The
-// nine node rows (fixed eta, zeta index) are streamed one at a time so the
-// 81 coordinates never have to be resident in registers together.
+// One node row (fixed eta, zeta index r) of the sum-factorised map: adds its
+// share of x(xi) and, with WITH_J, of J = dx/dxi.
 template <bool WITH_J>
+__device__ inline void q2_row(const double *__restrict__ X, int r, const double *la, const double *da,
+                              const double *lb, const double *db, const double *lc, const double *dc, double *acc)
+{
+    const int b = r % 3, c = r / 3;
+    const double wb = pick3(b, lb[0], lb[1], lb[2]), wc = pick3(c, lc[0], lc[1], lc[2]);
+    const double w = wb * wc;
+    const double *R = X + 3 * r;
+    const double x0 = R[0], x1 = R[1], x2 = R[2];
+    const double y0 = R[27], y1 = R[28], y2 = R[29];
+    const double z0 = R[54], z1 = R[55], z2 = R[56];
+    const double ux = x0 * la[0] + x1 * la[1] + x2 * la[2];
+    const double uy = y0 * la[0] + y1 * la[1] + y2 * la[2];
+    const double uz = z0 * la[0] + z1 * la[1] + z2 * la[2];
+    acc[0] += ux * w;
+    acc[1] += uy * w;
+    acc[2] += uz * w;
+    if (WITH_J) {
+        const double wdb = pick3(b, db[0], db[1], db[2]) * wc;
+        const double wdc = wb * pick3(c, dc[0], dc[1], dc[2]);
+        const double vx = x0 * da[0] + x1 * da[1] + x2 * da[2];
+        const double vy = y0 * da[0] + y1 * da[1] + y2 * da[2];
+        const double vz = z0 * da[0] + z1 * da[1] + z2 * da[2];
+        acc[3] += vx * w; acc[4] += ux * wdb; acc[5] += ux * wdc;
+        acc[6] += vy * w; acc[7] += uy * wdb; acc[8] += uy * wdc;
+        acc[9] += vz * w; acc[10] += uz * wdb; acc[11] += uz * wdc;
+    }
+}
+
+// x(xi) and J = dx/dxi of an element stored as x[27], y[27], z[27].  With
+// STREAM the nine node rows are read one at a time (X in global memory, the
+// 81 coordinates never resident together); otherwise X is a register copy
+// and the rows are unrolled.  Both sum in the same order.
+template <bool WITH_J, bool STREAM>
 __device__ inline void q2_map(const double *__restrict__ X, const double *xi, double *x, double *J)
 {
     double la[3], da[3], lb[3], db[3], lc[3], dc[3];
     lag2(xi[0], la, da);
     lag2(xi[1], lb, db);
     lag2(xi[2], lc, dc);
-    double ax = 0.0, ay = 0.0, az = 0.0;
-    double j0 = 0.0, j1 = 0.0, j2 = 0.0, j3 = 0.0, j4 = 0.0, j5 = 0.0, j6 = 0.0, j7 = 0.0, j8 = 0.0;
+    double acc[12] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (STREAM) {
 #pragma unroll 1
-    for (int r = 0; r < 9; ++r) {
-        const int b = r % 3, c = r / 3;
-        const double wb = pick3(b, lb[0], lb[1], lb[2]), wc = pick3(c, lc[0], lc[1], lc[2]);
-        const double w = wb * wc;
-        const double *R = X + 3 * r;
-        const double x0 = R[0], x1 = R[1], x2 = R[2];
-        const double y0 = R[27], y1 = R[28], y2 = R[29];
-        const double z0 = R[54], z1 = R[55], z2 = R[56];
-        const double ux = x0 * la[0] + x1 * la[1] + x2 * la[2];
-        const double uy = y0 * la[0] + y1 * la[1] + y2 * la[2];
-        const double uz = z0 * la[0] + z1 * la[1] + z2 * la[2];
-        ax += ux * w;
-        ay += uy * w;
-        az += uz * w;
-        if (WITH_J) {
-            const double wdb = pick3(b, db[0], db[1], db[2]) * wc;
-            const double wdc = wb * pick3(c, dc[0], dc[1], dc[2]);
-            const double vx = x0 * da[0] + x1 * da[1] + x2 * da[2];
-            const double vy = y0 * da[0] + y1 * da[1] + y2 * da[2];
-            const double vz = z0 * da[0] + z1 * da[1] + z2 * da[2];
-            j0 += vx * w; j1 += ux * wdb; j2 += ux * wdc;
-            j3 += vy * w; j4 += uy * wdb; j5 += uy * wdc;
-            j6 += vz * w; j7 += uz * wdb; j8 += uz * wdc;
-        }
+        for (int r = 0; r < 9; ++r) q2_row<WITH_J>(X, r, la, da, lb, db, lc, dc, acc);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 9; ++r) q2_row<WITH_J>(X, r, la, da, lb, db, lc, dc, acc);
     }
-    x[0] = ax;
-    x[1] = ay;
-    x[2] = az;
-    if (WITH_J) {
-        J[0] = j0; J[1] = j1; J[2] = j2;
-        J[3] = j3; J[4] = j4; J[5] = j5;
-        J[6] = j6; J[7] = j7; J[8] = j8;
-    }
+    x[0] = acc[0];
+    x[1] = acc[1];
+    x[2] = acc[2];
+    if (WITH_J)
+        for (int k = 0; k < 9; ++k) J[k] = acc[3 + k];
 }
 
 // Newton inversion: xi0 = 0; stop when |x_p - x(xi)| <= 1e-13 diam (checked
 // before each step) or the clamped step is <= 1e-14; at most
 // OC_NEWTON_MAXIT iterations; contained if converged and
 // max|xi| <= 1 + OC_CONTAIN_TOL.  The 3x3 system is solved with the adjugate.
-__device__ inline bool newton_q2(const double *__restrict__ X, d3 p, double diam, double *xi, int &iters)
+// Without STREAM the element's 81 coordinates are loaded once into registers
+// (one round of independent loads) and reused by every iteration; with
+// STREAM they are read row by row from memory each iteration (few registers,
+// for rarely taken paths).  Both give the same bits.
+template <bool STREAM>
+__device__ inline bool newton_q2(const double *__restrict__ Xg, d3 p, double diam, double *xi, int &iters)
 {
+    double Xr[STREAM ? 1 : 81];
+    if (!STREAM) {
+#pragma unroll
+        for (int k = 0; k < 81; ++k) Xr[k] = Xg[k];
+    }
+    const double *X = STREAM ? Xg : Xr;
     xi[0] = xi[1] = xi[2] = 0.0;
     bool conv = false;
 #pragma unroll 1
     for (int it = 0; it < OC_NEWTON_MAXIT; ++it) {
         ++iters;
         double x[3], J[9];
-        q2_map<true>(X, xi, x, J);
+        q2_map<true, STREAM>(X, xi, x, J);
         const double r0 = p.x - x[0], r1 = p.y - x[1], r2 = p.z - x[2];
         if (sqrt(r0 * r0 + r1 * r1 + r2 * r2) <= 1e-13 * diam) {
             conv = true;
@@ -187,10 +210,95 @@ __global__ __launch_bounds__(kT) void k_elem_boxes(const double *__restrict__ en
     }
     ediam[e] = diam;
     double xi[3] = {0.0, 0.0, 0.0}, x[3], J[9];
-    q2_map<true>(X, xi, x, J);
+    q2_map<true, true>(X, xi, x, J);
     const double det = J[0] * (J[4] * J[8] - J[5] * J[7]) - J[1] * (J[3] * J[8] - J[5] * J[6]) +
                        J[2] * (J[3] * J[7] - J[4] * J[6]);
     if (!(det > 0.0)) atomicAdd(bad_jac, 1);
+}
+
+// Oriented box of the control net: a second, tighter candidate test for thin
+// curved elements, whose axis-aligned boxes are loose.  Axes: the element's
+// xi and eta centre chords (node 14 - node 12, node 16 - node 10),
+// orthonormalised, and their cross product; centre: node 13.  Centre and
+// axes are stored in FP32; the extents of the 27 control points along those
+// same FP32 axes are computed in FP64, rounded outward and widened by 1e-7
+// of the control-net box diagonal, which covers the containment tolerance
+// (|xi| <= 1 + 1e-10 moves x by far less) and the rounding of the query.
+// Record: c[3], u1[3], u2[3], u3[3], lo[3], hi[3].
+__global__ __launch_bounds__(kT) void k_elem_obb(const double *__restrict__ enodes, int64_t n_elem,
+                                                 const float *__restrict__ cbox, float *__restrict__ obox)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_elem) return;
+    const double *X = enodes + e * 81;
+    double u[3][3];
+    for (int d = 0; d < 3; ++d) {
+        u[0][d] = X[27 * d + 14] - X[27 * d + 12];
+        u[1][d] = X[27 * d + 16] - X[27 * d + 10];
+    }
+    double n0 = sqrt(u[0][0] * u[0][0] + u[0][1] * u[0][1] + u[0][2] * u[0][2]);
+    bool ok = n0 > 0.0;
+    if (ok)
+        for (int d = 0; d < 3; ++d) u[0][d] /= n0;
+    const double pr = u[1][0] * u[0][0] + u[1][1] * u[0][1] + u[1][2] * u[0][2];
+    for (int d = 0; d < 3; ++d) u[1][d] -= pr * u[0][d];
+    const double n1 = sqrt(u[1][0] * u[1][0] + u[1][1] * u[1][1] + u[1][2] * u[1][2]);
+    ok = ok && n1 > 0.0;
+    if (ok)
+        for (int d = 0; d < 3; ++d) u[1][d] /= n1;
+    u[2][0] = u[0][1] * u[1][2] - u[0][2] * u[1][1];
+    u[2][1] = u[0][2] * u[1][0] - u[0][0] * u[1][2];
+    u[2][2] = u[0][0] * u[1][1] - u[0][1] * u[1][0];
+    if (!ok)
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d) u[k][d] = k == d ? 1.0 : 0.0;
+    float fc[3], fu[3][3];
+    for (int d = 0; d < 3; ++d) fc[d] = (float)X[27 * d + 13];
+    for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 3; ++d) fu[k][d] = (float)u[k][d];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int st[3] = {1, 3, 9};
+    for (int j = 0; j < 27; ++j) {
+        // control point j: the tensor-product Bernstein net (middle point per
+        // reference axis 2 x1 - (x0 + x2) / 2, applied axis by axis)
+        double b[3];
+        for (int d = 0; d < 3; ++d) {
+            const double *C = X + 27 * d;
+            const int ja = j % 3, jb = (j / 3) % 3, jc = j / 9;
+            double v = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                const double wc = jc == 1 ? (c == 1 ? 2.0 : -0.5) : (c == jc ? 1.0 : 0.0);
+                if (wc == 0.0) continue;
+                for (int bb = 0; bb < 3; ++bb) {
+                    const double wb = jb == 1 ? (bb == 1 ? 2.0 : -0.5) : (bb == jb ? 1.0 : 0.0);
+                    if (wb == 0.0) continue;
+                    for (int a = 0; a < 3; ++a) {
+                        const double wa = ja == 1 ? (a == 1 ? 2.0 : -0.5) : (a == ja ? 1.0 : 0.0);
+                        if (wa == 0.0) continue;
+                        v += wa * wb * wc * C[a * st[0] + bb * st[1] + c * st[2]];
+                    }
+                }
+            }
+            b[d] = v;
+        }
+        for (int k = 0; k < 3; ++k) {
+            const double sk = (b[0] - (double)fc[0]) * (double)fu[k][0] + (b[1] - (double)fc[1]) * (double)fu[k][1] +
+                              (b[2] - (double)fc[2]) * (double)fu[k][2];
+            lo[k] = fmin(lo[k], sk);
+            hi[k] = fmax(hi[k], sk);
+        }
+    }
+    const float *cb = cbox + e * 6;
+    const double gx = (double)cb[3] - cb[0], gy = (double)cb[4] - cb[1], gz = (double)cb[5] - cb[2];
+    const double m = 1e-7 * sqrt(gx * gx + gy * gy + gz * gz);
+    float *o = obox + e * 18;
+    for (int d = 0; d < 3; ++d) o[d] = fc[d];
+    for (int k = 0; k < 3; ++k)
+        for (int d = 0; d < 3; ++d) o[3 + 3 * k + d] = fu[k][d];
+    for (int k = 0; k < 3; ++k) {
+        o[12 + k] = f32_down(lo[k] - m);
+        o[15 + k] = f32_up(hi[k] + m);
+    }
 }
 
 __global__ __launch_bounds__(kT) void k_dbin_count(const float *__restrict__ cbox, int64_t n_elem, BinGrid G,
@@ -320,7 +428,7 @@ __global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__
         const double g = 0.7745966692414834;  // sqrt(3/5), 3-point Gauss-Legendre
         const double xi[3] = {(k % 3 - 1) * g, ((k / 3) % 3 - 1) * g, (k / 9 - 1) * g};
         double x[3];
-        q2_map<false>(enodes + (int64_t)e * 81, xi, x, nullptr);
+        q2_map<false, true>(enodes + (int64_t)e * 81, xi, x, nullptr);
         const d3 w = pose_apply(pose, mk(x[0], x[1], x[2]));
         pts[3 * i] = w.x;
         pts[3 * i + 1] = w.y;
@@ -335,6 +443,24 @@ __device__ inline bool box_has(const float *__restrict__ c, d3 p)
            p.y <= (double)c[4] && p.z <= (double)c[5];
 }
 
+// the oriented control-net box (k_elem_obb) holds p
+__device__ inline bool obb_has(const float *__restrict__ o, d3 p)
+{
+    const double dx = p.x - (double)o[0], dy = p.y - (double)o[1], dz = p.z - (double)o[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double sk = dx * (double)o[3 + 3 * k] + dy * (double)o[4 + 3 * k] + dz * (double)o[5 + 3 * k];
+        if (sk < (double)o[12 + k] || sk > (double)o[15 + k]) return false;
+    }
+    return true;
+}
+
+// candidate test: axis-aligned control-net box, then the oriented one
+__device__ inline bool cand_has(const float *__restrict__ cbox, const float *__restrict__ obox, int64_t e, d3 p)
+{
+    return box_has(cbox + e * 6, p) && obb_has(obox + e * 18, p);
+}
+
 __device__ inline int64_t point_bin(const BinGrid &G, d3 p)
 {
     const int bx = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
@@ -346,6 +472,7 @@ __device__ inline int64_t point_bin(const BinGrid &G, d3 p)
 struct DonorArgs {
     const double *enodes;
     const float *cbox;
+    const float *obox;
     const double *ediam;
     BinGrid G;
     const int32_t *bstart;
@@ -361,15 +488,29 @@ struct DonorArgs {
     int32_t *best;         // [cap] lowest containing element id
     int32_t *pair_pt;      // [pair_cap]
     int32_t *pair_el;      // [pair_cap]
+    double *pair_xi;       // [pair_cap][3] reference coordinates of contained pairs
+    uint8_t *pair_it;      // [pair_cap] Newton iterations run per pair (statistics)
     int64_t pair_cap;
     int32_t *donor;
     double *ref;
     DonorCounters *dcnt;
+    int lanes;             // lanes per point in the bin walks (power of two, <= 64)
+    int pad;
 };
 
 __device__ inline int64_t donor_points(const DonorArgs &a)
 {
     return a.n_dev ? ((int64_t)*a.n_dev < a.cap ? (int64_t)*a.n_dev : a.cap) : a.cap;
+}
+
+// The bin walks give each point a group of `lanes` lanes of a wavefront
+// (64 / lanes points per wavefront): the group's lanes take the bin's
+// entries in turn, so a point whose bin holds many boxes is searched in
+// parallel while points with small bins share a wavefront.
+__device__ inline int group_sum(int v, int lanes)
+{
+    for (int d = lanes >> 1; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
 }
 
 // a10: per point, the registration-frame position (inverse pose, the rigid
@@ -380,77 +521,111 @@ __global__ __launch_bounds__(kT) void k_dp_count(DonorArgs a)
     const int64_t n = donor_points(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_eff = (int32_t)n;
     const Pose pose = *a.pose;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const d3 p = pose_inverse(pose, mk(a.pts[3 * i], a.pts[3 * i + 1], a.pts[3 * i + 2]));
-        a.plocal[3 * i] = p.x;
-        a.plocal[3 * i + 1] = p.y;
-        a.plocal[3 * i + 2] = p.z;
-        const int64_t b = point_bin(a.G, p);
+    const int L = a.lanes, lane = threadIdx.x & 63, sub = lane & (L - 1);
+    const int64_t ppw = 64 / L;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t base = wave * ppw; base < n; base += n_waves * ppw) {
+        const int64_t i = base + lane / L;
         int c = 0;
-        for (int j = a.bstart[b]; j < a.bstart[b + 1]; ++j) c += box_has(a.cbox + (int64_t)a.bitems[j] * 6, p);
-        a.cnt[i] = c;
-        a.best[i] = 0x7fffffff;
+        if (i < n) {
+            const d3 p = pose_inverse(pose, mk(a.pts[3 * i], a.pts[3 * i + 1], a.pts[3 * i + 2]));
+            if (sub == 0) {
+                a.plocal[3 * i] = p.x;
+                a.plocal[3 * i + 1] = p.y;
+                a.plocal[3 * i + 2] = p.z;
+            }
+            const int64_t b = point_bin(a.G, p);
+            const int j1 = a.bstart[b + 1];
+            for (int j = a.bstart[b] + sub; j < j1; j += L) c += cand_has(a.cbox, a.obox, a.bitems[j], p);
+        }
+        c = group_sum(c, L);
+        if (i < n && sub == 0) {
+            a.cnt[i] = c;
+            a.best[i] = 0x7fffffff;
+        }
     }
 }
 
-// a10: the candidates as (point, element) pairs (the containment tests are
-// deferred to the next kernel, as in Sec. 4.3); pairs past the capacity are
-// dropped and their points searched one by one in k_dp_final.
+// a10: the candidates as (point, element) pairs in ascending element id per
+// point (the containment tests are deferred to the next kernel, as in
+// Sec. 4.3); pairs past the capacity are dropped and their points searched
+// one by one in k_dp_final.
 __global__ __launch_bounds__(kT) void k_dp_fill(DonorArgs a)
 {
     const int64_t n = donor_points(a);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int L = a.lanes, lane = threadIdx.x & 63, sub = lane & (L - 1);
+    const unsigned long long gmask = (L == 64 ? ~0ull : ((1ull << L) - 1ull)) << (lane & ~(L - 1));
+    const unsigned long long below = (1ull << lane) - 1ull;
+    const int64_t ppw = 64 / L;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t base = wave * ppw; base < n; base += n_waves * ppw) {
+        const int64_t i = base + lane / L;
+        if (i >= n) continue;
         const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
         const int64_t b = point_bin(a.G, p);
+        const int j0 = a.bstart[b], j1 = a.bstart[b + 1];
         int64_t q = a.off[i];
-        for (int j = a.bstart[b]; j < a.bstart[b + 1] && q < a.pair_cap; ++j) {
-            const int e = a.bitems[j];
-            if (!box_has(a.cbox + (int64_t)e * 6, p)) continue;
-            a.pair_pt[q] = (int32_t)i;
-            a.pair_el[q] = e;
-            ++q;
+        for (int r = j0; r < j1; r += L) {
+            const int j = r + sub;
+            int e = -1;
+            bool has = false;
+            if (j < j1) {
+                e = a.bitems[j];
+                has = cand_has(a.cbox, a.obox, e, p);
+            }
+            const unsigned long long m = __ballot(has) & gmask;
+            const int64_t at = q + __popcll(m & below);
+            if (has && at < a.pair_cap) {
+                a.pair_pt[at] = (int32_t)i;
+                a.pair_el[at] = e;
+            }
+            q += __popcll(m);
         }
     }
 }
 
 // a11: Newton on every pair, one thread each; a point keeps the lowest
-// element id that contains it.
+// element id that contains it, and a contained pair keeps its xi.
 __global__ __launch_bounds__(kT) void k_dp_newton(DonorArgs a)
 {
     const int64_t n = *a.n_eff;
     const int64_t tot = a.off[n] < a.pair_cap ? (int64_t)a.off[n] : a.pair_cap;
-    int iters = 0;
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
         const int i = a.pair_pt[q], e = a.pair_el[q];
         const d3 p = mk(a.plocal[3 * (int64_t)i], a.plocal[3 * (int64_t)i + 1], a.plocal[3 * (int64_t)i + 2]);
         double xi[3];
-        if (newton_q2(a.enodes + (int64_t)e * 81, p, a.ediam[e], xi, iters)) atomicMin(&a.best[i], e);
+        int iters = 0;
+        if (newton_q2<false>(a.enodes + (int64_t)e * 81, p, a.ediam[e], xi, iters)) {
+            a.pair_xi[3 * q] = xi[0];
+            a.pair_xi[3 * q + 1] = xi[1];
+            a.pair_xi[3 * q + 2] = xi[2];
+            atomicMin(&a.best[i], e);
+        }
+        a.pair_it[q] = (uint8_t)iters;
     }
-    unsigned long long s = iters;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-    if ((threadIdx.x & 63) == 0 && s) atomicAdd(&a.dcnt->n_iter, s);
 }
 
-// donor id and reference coordinates per point: Newton is rerun on the
-// winning element (same code, same inputs, same result) for its xi.  Points
-// whose pairs did not all fit take their candidates in ascending id order.
+// donor id and reference coordinates per point: the xi kept by the winning
+// pair.  Points whose pairs did not all fit take their candidates one by one
+// in ascending id order.
 __global__ __launch_bounds__(kT) void k_dp_final(DonorArgs a)
 {
     const int64_t n = *a.n_eff;
-    int orph = 0, extra = 0;
+    int extra = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-        const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
         int32_t d = -1;
         double xi[3] = {NAN, NAN, NAN};
         int scratch = 0;
         if ((int64_t)a.off[i + 1] > a.pair_cap) {
+            const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
             const int64_t b = point_bin(a.G, p);
             for (int j = a.bstart[b]; j < a.bstart[b + 1]; ++j) {
                 const int e = a.bitems[j];
-                if (!box_has(a.cbox + (int64_t)e * 6, p)) continue;
+                if (!cand_has(a.cbox, a.obox, e, p)) continue;
                 ++extra;
-                if (newton_q2(a.enodes + (int64_t)e * 81, p, a.ediam[e], xi, scratch)) {
+                if (newton_q2<true>(a.enodes + (int64_t)e * 81, p, a.ediam[e], xi, scratch)) {
                     d = e;
                     break;
                 }
@@ -458,24 +633,59 @@ __global__ __launch_bounds__(kT) void k_dp_final(DonorArgs a)
             }
         } else if (a.best[i] != 0x7fffffff) {
             d = a.best[i];
-            (void)newton_q2(a.enodes + (int64_t)d * 81, p, a.ediam[d], xi, scratch);
+            for (int64_t q = a.off[i]; q < (int64_t)a.off[i + 1]; ++q)
+                if (a.pair_el[q] == d) {
+                    xi[0] = a.pair_xi[3 * q];
+                    xi[1] = a.pair_xi[3 * q + 1];
+                    xi[2] = a.pair_xi[3 * q + 2];
+                    break;
+                }
         }
         a.donor[i] = d;
         a.ref[3 * i] = xi[0];
         a.ref[3 * i + 1] = xi[1];
         a.ref[3 * i + 2] = xi[2];
-        orph += d < 0;
     }
-    unsigned long long so = orph, sx = extra;
+    // solves of the overflow path (rare: only points whose pairs did not fit)
+    unsigned long long sx = extra;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) sx += __shfl_xor(sx, d, 64);
+    if ((threadIdx.x & 63) == 0 && sx) atomicAdd(&a.dcnt->n_newton, sx);
+}
+
+// Statistics of the last search (only when asked for): Newton iterations
+// over the pairs and orphan points.
+__global__ __launch_bounds__(kT) void k_donor_stats(DonorArgs a)
+{
+    __shared__ unsigned long long acc[2];
+    if (threadIdx.x < 2) acc[threadIdx.x] = 0ull;
+    __syncthreads();
+    const int64_t n = *a.n_eff;
+    const int64_t tot = a.off[n] < a.pair_cap ? (int64_t)a.off[n] : a.pair_cap;
+    unsigned long long it = 0, orph = 0;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x)
+        it += a.pair_it[q];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        orph += a.donor[i] < 0;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
-        so += __shfl_xor(so, d, 64);
-        sx += __shfl_xor(sx, d, 64);
+        it += __shfl_xor(it, d, 64);
+        orph += __shfl_xor(orph, d, 64);
     }
     if ((threadIdx.x & 63) == 0) {
-        if (so) atomicAdd(&a.dcnt->n_orphan, so);
-        if (sx) atomicAdd(&a.dcnt->n_newton, sx);
+        atomicAdd(&acc[0], it);
+        atomicAdd(&acc[1], orph);
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&a.dcnt->n_iter, acc[0]);
+        atomicAdd(&a.dcnt->n_orphan, acc[1]);
+    }
+}
+
+__global__ void k_donor_stats_reset(DonorCounters *c)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) c->n_iter = c->n_orphan = 0ull;
 }
 
 __global__ void k_dp_newton_count(DonorArgs a)
@@ -514,6 +724,7 @@ oc_status grid_build_device(oc_ctx *ctx, Grid &g, const int32_t *conn_dev, const
     OC_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
     LAUNCH(k_elem_boxes, dim3(blocks(g.n_elem, kT)), dim3(kT), g.enodes, g.n_elem, g.ebox_stride, g.ebox, g.cbox,
            g.ediam, bad);
+    LAUNCH(k_elem_obb, dim3(blocks(g.n_elem, kT)), dim3(kT), g.enodes, g.n_elem, g.cbox, g.obox);
     int hbad = 0;
     OC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
     OC_HIP(hipStreamSynchronize(st));
@@ -566,6 +777,21 @@ oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g)
     LAUNCH(k_dbin_fill, dim3(blocks(g.n_elem, kT)), dim3(kT), g.cbox, g.n_elem, g.dgrid, start, count, g.dbin_items);
     LAUNCH(k_dbin_sort, dim3(blocks(nb, kT)), dim3(kT), start, nb, g.dbin_items);
     g.dbin_start = start;
+    // lanes per point in the donor bin walks: about two bin entries per lane
+    // for the typical query (bins weighted by their entry count, since
+    // points fall where elements are)
+    std::vector<int32_t> hs((size_t)nb + 1);
+    OC_HIP(hipMemcpyAsync(hs.data(), start, sizeof(int32_t) * (nb + 1), hipMemcpyDeviceToHost, st));
+    OC_HIP(hipStreamSynchronize(st));
+    double s1 = 0.0, s2 = 0.0;
+    for (int64_t k = 0; k < nb; ++k) {
+        const double c = hs[k + 1] - hs[k];
+        s1 += c;
+        s2 += c * c;
+    }
+    const double mean = s1 > 0 ? s2 / s1 : 1.0;
+    g.dlanes = 1;
+    while (g.dlanes < 64 && 2.0 * g.dlanes < mean) g.dlanes *= 2;
     OC_HIP(hipStreamSynchronize(st));
     OC_HIP(hipGetLastError());
     return OC_OK;
@@ -607,11 +833,13 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
     LAUNCH(k_donor_reset, dim3(1), dim3(64), sl->dcounters);
+    sl->last_donor_args.clear();
     if (cap <= 0) return OC_OK;
     OC_TRY(slot_reserve_points(sl, cap));
     DonorArgs a;
     a.enodes = g.enodes;
     a.cbox = g.cbox;
+    a.obox = g.obox;
     a.ediam = g.ediam;
     a.G = g.dgrid;
     a.bstart = g.dbin_start;
@@ -627,17 +855,39 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     a.best = sl->dp_best;
     a.pair_pt = sl->dpair_pt;
     a.pair_el = sl->dpair_el;
+    a.pair_xi = sl->dpair_xi;
+    a.pair_it = sl->dpair_it;
     a.pair_cap = sl->dpair_cap;
+    a.lanes = g.dlanes;
+    a.pad = 0;
     a.donor = donor;
     a.ref = ref;
     a.dcnt = sl->dcounters;
     const unsigned gp = std::min<unsigned>(blocks(cap, kT), 8192u);
-    LAUNCH(k_dp_count, dim3(gp), dim3(kT), a);
+    const unsigned gw = std::min<unsigned>(blocks(cap * g.dlanes, kT), 16384u);
+    LAUNCH(k_dp_count, dim3(gw), dim3(kT), a);
     OC_TRY(scan_exclusive(ctx, st, sl->dp_cnt, sl->dp_off, cap, a.n_eff, sl->dp_scan_tmp));
-    LAUNCH(k_dp_fill, dim3(gp), dim3(kT), a);
+    LAUNCH(k_dp_fill, dim3(gw), dim3(kT), a);
     LAUNCH(k_dp_newton_count, dim3(1), dim3(64), a);
     LAUNCH(k_dp_newton, dim3(std::min<unsigned>(blocks(sl->dpair_cap, kT), 16384u)), dim3(kT), a);
     LAUNCH(k_dp_final, dim3(gp), dim3(kT), a);
+    OC_HIP(hipGetLastError());
+    sl->last_donor_args.assign(reinterpret_cast<const unsigned char *>(&a),
+                               reinterpret_cast<const unsigned char *>(&a) + sizeof a);
+    return OC_OK;
+}
+
+// Counters of the slot's last donor search (stream ordered).
+oc_status donor_stats_run(oc_slot *sl)
+{
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    LAUNCH(k_donor_stats_reset, dim3(1), dim3(64), sl->dcounters);
+    if (sl->last_donor_args.size() == sizeof(DonorArgs)) {
+        DonorArgs a;
+        memcpy(&a, sl->last_donor_args.data(), sizeof a);
+        LAUNCH(k_donor_stats, dim3(256), dim3(kT), a);
+    }
     OC_HIP(hipGetLastError());
     return OC_OK;
 }

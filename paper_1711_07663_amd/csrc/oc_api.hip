@@ -89,8 +89,12 @@ static oc_status slot_alloc_cut(oc_slot *sl, CutCaps c)
     c.cuts = std::max<int64_t>(c.cuts, 1);
     c.outs = std::max<int64_t>(c.outs, 1);
     auto &o = sl->cut_owned;
-    uint64_t **lists[5] = {&sl->l_inbox, &sl->l_near, &sl->l_far, &sl->l_side, &sl->l_hole};
-    for (auto l : lists) OC_TRY(dev_alloc(ctx, o, sizeof(uint64_t) * (size_t)c.elem_inst, (void **)l));
+    OC_TRY(dev_alloc(ctx, o, sizeof(uint64_t) * (size_t)c.elem_inst, (void **)&sl->l_inbox));
+    OC_TRY(dev_alloc(ctx, o, sizeof(uint8_t) * (size_t)c.elem_inst, (void **)&sl->l_stat));
+    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)c.elem_inst, (void **)&sl->l_ncand));
+    // face blocks of 256 faces, plus one spare block per cut
+    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * 6 * (size_t)(c.faces / 256 + 2 * c.cuts + 1),
+                     (void **)&sl->sbox_part));
     OC_TRY(dev_alloc(ctx, o, sizeof(CutInst) * (size_t)c.cuts, (void **)&sl->insts));
     OC_TRY(dev_alloc(ctx, o, sizeof(CutOut) * (size_t)c.outs, (void **)&sl->outs));
     OC_TRY(dev_alloc(ctx, o, sizeof(SurfParams) * (size_t)c.cuts, (void **)&sl->params));
@@ -150,6 +154,8 @@ static oc_status slot_alloc_points(oc_slot *sl, int64_t cap)
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * scan_tmp_ints(cap), (void **)&sl->dp_scan_tmp));
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * pc, (void **)&sl->dpair_pt));
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * pc, (void **)&sl->dpair_el));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(double) * 3 * pc, (void **)&sl->dpair_xi));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(uint8_t) * pc, (void **)&sl->dpair_it));
     sl->dpt_cap = cap;
     sl->dpair_cap = pc;
     return OC_OK;
@@ -392,6 +398,7 @@ oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, co
     if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 6 * (size_t)g->ebox_stride, (void **)&g->ebox)) != OC_OK)
         return fail(st);
     if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 6 * ne, (void **)&g->cbox)) != OC_OK) return fail(st);
+    if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 18 * ne, (void **)&g->obox)) != OC_OK) return fail(st);
     if ((st = dev_alloc(ctx, g->owned, sizeof(double) * ne, (void **)&g->ediam)) != OC_OK) return fail(st);
     if ((st = upload(ctx, g->owned, nbr.data(), nbr.size(), &g->nbr)) != OC_OK) return fail(st);
     g->n_overset = (int64_t)overset.size();
@@ -488,6 +495,7 @@ oc_status oc_register_cut_surface(oc_ctx *ctx, const double *nodes, int64_t n_no
     nb = std::max(1, std::min(nb, 160));
     if (ctx->surf_bins > 0) nb = std::min(nb, ctx->surf_bins);
     s->nb_max = nb;
+    s->nb_auto = nb;
     for (int d = 0; d < 3; ++d) s->first[d] = nodes[d];
     for (int64_t i = 0; i < n_nodes; ++i)
         s->rmax = std::max(s->rmax, std::sqrt(nodes[3 * i] * nodes[3 * i] + nodes[3 * i + 1] * nodes[3 * i + 1] +
@@ -531,6 +539,7 @@ static oc_status collect_surfs(oc_ctx *ctx, const int32_t *surf_ids, int32_t n_s
 
 static oc_status read_cut_info(oc_slot *sl, oc_cut_info *info)
 {
+    OC_TRY(cut_stats_run(sl));
     CutCounters c;
     OC_HIP(hipMemcpyAsync(&c, sl->counters, sizeof c, hipMemcpyDeviceToHost, sl->stream));
     OC_HIP(hipStreamSynchronize(sl->stream));
@@ -546,6 +555,7 @@ static oc_status read_cut_info(oc_slot *sl, oc_cut_info *info)
 
 static oc_status read_donor_info(oc_slot *sl, oc_donor_info *info)
 {
+    OC_TRY(donor_stats_run(sl));
     DonorCounters c;
     OC_HIP(hipMemcpyAsync(&c, sl->dcounters, sizeof c, hipMemcpyDeviceToHost, sl->stream));
     OC_HIP(hipStreamSynchronize(sl->stream));
@@ -1037,6 +1047,37 @@ oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len)
     memcpy(buf, js.c_str(), js.size() + 1);
     ctx->trecs.clear();
     ctx->event_next = 0;
+    return OC_OK;
+}
+
+oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t *applied)
+{
+    if (!ctx) {
+        set_error("oc_tune: null context");
+        return OC_EINVAL;
+    }
+    int64_t v = 0;
+    if (knob == OC_TUNE_SURF_BINS) {
+        std::vector<Surf *> ss;
+        OC_TRY(collect_surfs(ctx, &arg, 1, ss));
+        if (value < 0) {
+            set_error("oc_tune: negative bin cap");
+            return OC_EINVAL;
+        }
+        ss[0]->nb_max = value == 0 ? ss[0]->nb_auto : (int)std::max<int64_t>(1, std::min<int64_t>(value, ss[0]->nb_auto));
+        v = ss[0]->nb_max;
+    } else if (knob == OC_TUNE_EXACT_WAVES) {
+        if (value < 0 || value > (1 << 20)) {
+            set_error("oc_tune: exact waves out of range");
+            return OC_EINVAL;
+        }
+        ctx->exact_waves = value == 0 ? 8192 : (int)value;
+        v = ctx->exact_waves;
+    } else {
+        set_error("oc_tune: unknown knob");
+        return OC_EINVAL;
+    }
+    if (applied) *applied = v;
     return OC_OK;
 }
 

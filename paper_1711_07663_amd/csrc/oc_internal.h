@@ -43,7 +43,6 @@ struct BinGrid {
 
 // Per-cut device state of a cutting surface.
 struct SurfParams {
-    int sbox_ord[6];   // surface box as order-preserving ints (atomic min/max)
     float sbox[6];     // surface box (lo xyz, hi xyz), FP32, outward
     BinGrid grid;      // bins over the surface box
     int n_bins;        // grid.n[0]*n[1]*n[2]
@@ -78,18 +77,21 @@ struct Grid {
     int64_t n_overset = 0;
     // donor search structure (registration frame)
     float *cbox = nullptr;      // [n_elem][6] control-net boxes, outward FP32
+    float *obox = nullptr;      // [n_elem][18] oriented control-net boxes (centre, axes, extents)
     double *ediam = nullptr;    // [n_elem] node-box diagonal
     BinGrid dgrid{};
     int32_t *dbin_start = nullptr; // [n_dbins + 1]
     int32_t *dbin_items = nullptr; // element ids, ascending within a bin
     int64_t n_dbins = 0, n_ditems = 0;
+    int dlanes = 1;                // lanes per point in the donor bin walks
     std::vector<DevBuf> owned;
 };
 
 struct Surf {
     int64_t n_face = 0, n_nodes = 0;
     int kind = OC_SURF_WALL;
-    int nb_max = 4;
+    int nb_max = 4;              // bins per axis cap in use
+    int nb_auto = 4;             // cap chosen at registration
     float dmax = 0.f;            // largest face-box diagonal (pose invariant bound)
     double *nodes = nullptr;     // [3][n_nodes] SoA registration frame
     int32_t *conn = nullptr;     // [n_face][9]
@@ -137,7 +139,13 @@ struct CutOut {
     int64_t n_elem, n_overset;
     int fblk0;                  // first block of the field fill (no surface)
     int oblk0;                  // first block of the overset-face fringe
+    int cblk0;                  // first block of the hole count (statistics)
+    int pad;
 };
+
+// Status of an in-box item of a batch (one byte per item): set by
+// k_candidates, refined by k_hit.
+enum : uint8_t { ST_NONE = 0, ST_NEAR = 1, ST_FAR = 2, ST_HIT = 3, ST_SIDE = 4 };
 
 // Capacity of a slot's cut scratch: summed over the cuts of one call.
 struct CutCaps {
@@ -171,9 +179,17 @@ struct oc_slot {
     double *dp_local = nullptr;
     int32_t *dp_cnt = nullptr, *dp_off = nullptr, *dp_best = nullptr, *dp_scan_tmp = nullptr;
     int32_t *dpair_pt = nullptr, *dpair_el = nullptr;
+    double *dpair_xi = nullptr;
+    uint8_t *dpair_it = nullptr;
+    std::vector<unsigned char> last_donor_args;   // arguments of the last donor search (statistics)
     // cut scratch of a batch
     oc::CutCaps cc;
-    uint64_t *l_inbox = nullptr, *l_near = nullptr, *l_far = nullptr, *l_side = nullptr, *l_hole = nullptr;
+    uint64_t *l_inbox = nullptr;       // in-box items (cut << 32 | element)
+    uint8_t *l_stat = nullptr;         // status per in-box item
+    int32_t *l_ncand = nullptr;        // candidate faces per in-box item
+    int32_t *sbox_part = nullptr;      // per face block: partial surface box (ordered ints)
+    int last_n_cut = 0, last_n_out = 0, last_cblk = 0;
+    std::vector<oc::CutOut> last_outs;
     oc::CutInst *insts = nullptr;
     oc::CutOut *outs = nullptr;
     oc::SurfParams *params = nullptr;
@@ -196,6 +212,7 @@ struct TimingRec {
 struct oc_ctx {
     int device = 0;
     int surf_bins = 0;
+    int exact_waves = 8192;                // persistent wavefronts of the exact-stage kernels
     double donor_bin_scale = 1.0;
     int64_t budget = 0;
     int64_t used = 0;
@@ -260,6 +277,10 @@ struct CutReq {
 CutCaps cut_caps(const CutReq *reqs, int n);
 // every request's cuts in one launch per stage
 oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n);
+// statistics of the slot's last cut batch into sl->counters (stream ordered)
+oc_status cut_stats_run(oc_slot *sl);
+// statistics of the slot's last donor search into sl->dcounters
+oc_status donor_stats_run(oc_slot *sl);
 // receptor points: the count stays on the device (n_dev, int32) and is also
 // returned on the host when n_host is not null (synchronising)
 oc_status fringe_points_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const int8_t *iblank, double *pts,
