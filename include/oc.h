@@ -256,6 +256,19 @@ oc_status oc_slot_donor_info(oc_slot *slot, oc_donor_info *info);
 oc_status oc_timing(oc_ctx *ctx, int32_t enable);
 oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len);
 
+/* Tuning knobs.  They change speed only, never results.
+ *   OC_TUNE_SURF_BINS    arg = surface id; value = cap on its bins per axis
+ *                        (1 .. the cap chosen at registration; 0 restores
+ *                        that cap).  Coarser bins hold more faces each.
+ *                        A slot reserves bins for the caps in force when it
+ *                        is created and refuses a later cut needing more
+ *                        (OC_EINVAL); lowering a cap never does that.
+ *   OC_TUNE_EXACT_WAVES  arg unused; value = wavefronts launched for each of
+ *                        the persistent exact-stage kernels (0 = 8192).
+ * *applied (may be NULL) receives the value in force afterwards. */
+enum { OC_TUNE_SURF_BINS = 1, OC_TUNE_EXACT_WAVES = 2 };
+oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t *applied);
+
 /* Device bytes currently held by the context. */
 oc_status oc_memory_used(oc_ctx *ctx, int64_t *bytes);
 

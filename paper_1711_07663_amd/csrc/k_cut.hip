@@ -87,27 +87,24 @@ __device__ inline int item_cut(uint64_t v) { return (int)(v >> 32); }
 __device__ inline int item_elem(uint64_t v) { return (int)(uint32_t)v; }
 
 // ------------------------------------------------------- surface stage ----
-// counters of the batch and the surface box of every cut
-__global__ __launch_bounds__(kThreads) void k_reset_counters(CutCounters *cnt, const CutInst *__restrict__ I, int n)
+// counters of the batch
+__global__ void k_reset_counters(CutCounters *cnt)
 {
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
         cnt->n_inbox = cnt->n_near = cnt->n_far = cnt->n_hit = cnt->n_hole = cnt->n_side = 0;
         cnt->n_cand_pairs = 0ull;
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        SurfParams *sp = I[i].params;
-        for (int k = 0; k < 3; ++k) {
-            sp->sbox_ord[k] = f2ord(INFINITY);
-            sp->sbox_ord[3 + k] = f2ord(-INFINITY);
-        }
     }
 }
 
 // a1 + a2 (face boxes): pose the 9 nodes of every face (x' = R x + t), store
 // them face-major, and build the face's FP32 box rounded outward and inflated
-// by tol_hit + 2^-20 * max|coordinate|.  Blocks are flattened over the cuts.
-__global__ __launch_bounds__(kThreads) void k_pose_faces(const CutInst *__restrict__ I, int n_cut)
+// by tol_hit + 2^-20 * max|coordinate|.  Blocks are flattened over the cuts;
+// each block writes the box of its faces to part[block] (ordered ints), and
+// k_bins_setup reduces a cut's blocks (no contended atomics).
+__global__ __launch_bounds__(kThreads) void k_pose_faces(const CutInst *__restrict__ I, int n_cut,
+                                                         int32_t *__restrict__ part)
 {
+    __shared__ float wb[kThreads / 64][6];
     const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].fblk0; });
     const CutInst &c = I[ci];
     const double *__restrict__ nodes = c.snodes;
@@ -116,6 +113,7 @@ __global__ __launch_bounds__(kThreads) void k_pose_faces(const CutInst *__restri
     double *__restrict__ pnodes = c.pnodes;
     float *__restrict__ fbox = c.fbox;
     SurfParams *sp = c.params;
+    (void)sp;
     const Pose pose = *c.pose;
     const int64_t f = (int64_t)(blockIdx.x - c.fblk0) * blockDim.x + threadIdx.x;
     float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -141,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_pose_faces(const CutInst *__restri
             fbox[f * 6 + 3 + a] = hi[a];
         }
     }
-    // surface box: wavefront reduction, one atomic per wave and bound
+    // surface box of the block: wavefront reduction, then across wavefronts
     for (int a = 0; a < 3; ++a) {
         float l = lo[a], h = hi[a];
 #pragma unroll
@@ -149,10 +147,17 @@ __global__ __launch_bounds__(kThreads) void k_pose_faces(const CutInst *__restri
             l = fminf(l, __shfl_xor(l, d, 64));
             h = fmaxf(h, __shfl_xor(h, d, 64));
         }
-        if (lane_id() == 0 && l <= h) {
-            atomicMin(&sp->sbox_ord[a], f2ord(l));
-            atomicMax(&sp->sbox_ord[3 + a], f2ord(h));
+        if (lane_id() == 0) {
+            wb[threadIdx.x >> 6][a] = l;
+            wb[threadIdx.x >> 6][3 + a] = h;
         }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        float v = wb[0][k];
+        for (int w = 1; w < kThreads / 64; ++w) v = k < 3 ? fminf(v, wb[w][k]) : fmaxf(v, wb[w][k]);
+        part[(int64_t)blockIdx.x * 6 + k] = f2ord(v);
     }
 }
 
@@ -185,7 +190,8 @@ __device__ inline int block_scan_excl(int v, int *total)
 // (dmax + 2 delta, pose invariant), so a face spans at most two bins per axis
 // and at most 8 bins in total.  One block; the batch's bin total goes to
 // *total.
-__global__ __launch_bounds__(kThreads) void k_bins_setup(const CutInst *__restrict__ I, int n_cut, int *total)
+__global__ __launch_bounds__(kThreads) void k_bins_setup(const CutInst *__restrict__ I, int n_cut,
+                                                         const int32_t *__restrict__ part, int *total)
 {
     int carry = 0;
     for (int i0 = 0; i0 < n_cut; i0 += kThreads) {
@@ -196,9 +202,17 @@ __global__ __launch_bounds__(kThreads) void k_bins_setup(const CutInst *__restri
             sp = I[i].params;
             const float dmax = I[i].dmax;
             const int nb_max = I[i].nb_max;
+            int ob[6] = {f2ord(INFINITY), f2ord(INFINITY), f2ord(INFINITY), f2ord(-INFINITY), f2ord(-INFINITY),
+                         f2ord(-INFINITY)};
+            const int b0 = I[i].fblk0, nblk = (int)((I[i].n_face + kThreads - 1) / kThreads);
+            for (int b = b0; b < b0 + nblk; ++b)
+                for (int k = 0; k < 6; ++k) {
+                    const int v = part[(int64_t)b * 6 + k];
+                    ob[k] = k < 3 ? min(ob[k], v) : max(ob[k], v);
+                }
             float L = 0.f;
             for (int k = 0; k < 6; ++k) {
-                sp->sbox[k] = ord2f(sp->sbox_ord[k]);
+                sp->sbox[k] = ord2f(ob[k]);
                 L = fmaxf(L, fabsf(sp->sbox[k]));
             }
             const float w = (dmax + 2.0f * (1e-7f + ldexpf(L, -20)) + ldexpf(L, -18)) * 1.001f;
@@ -437,15 +451,16 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
 }
 
 // a3, bin part: one wavefront per in-box element counts its candidate faces
-// (element box overlapping an inflated face box).  Warm start (prev != null):
-// the walk also counts faces whose box meets the element box grown by the
-// sweep bound; an element meeting none keeps its previous side (the surface
-// never came near it between the two poses) and skips the ray test.
+// (element box overlapping an inflated face box) and marks the item near
+// (some candidate) or far (none).  Warm start (prev != null): the walk also
+// counts faces whose box meets the element box grown by the sweep bound; an
+// element meeting none keeps its previous side (the surface never came near
+// it between the two poses) and needs no further test.  Later stages select
+// their items by status, so no list is appended under a shared counter.
 __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I, const int32_t *__restrict__ bin_start,
                                                    const int32_t *__restrict__ bitems,
-                                                   const uint64_t *__restrict__ list_inbox,
-                                                   uint64_t *__restrict__ list_near, uint64_t *__restrict__ list_far,
-                                                   uint64_t *__restrict__ list_hole, CutCounters *cnt)
+                                                   const uint64_t *__restrict__ list_inbox, uint8_t *__restrict__ stat,
+                                                   int32_t *__restrict__ ncand, const CutCounters *cnt)
 {
     __shared__ WalkLds L;
     const int n_in = cnt->n_inbox;
@@ -482,17 +497,15 @@ __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I
         const long long tot = wave_sum_ll(nc);
         const long long totw = prev ? wave_sum_ll(nw) : 1;
         if (lane == 0) {
+            uint8_t st = ST_FAR;
             if (tot > 0) {
-                list_near[atomicAdd(&cnt->n_near, 1)] = it;
-                atomicAdd(&cnt->n_cand_pairs, (unsigned long long)tot);
+                st = ST_NEAR;
             } else if (totw == 0) {
-                if (prev[e] == OC_HOLE && c.iblank[e] != OC_HOLE) {
-                    c.iblank[e] = OC_HOLE;
-                    list_hole[atomicAdd(&cnt->n_hole, 1)] = it;
-                }
-            } else {
-                list_far[atomicAdd(&cnt->n_far, 1)] = it;
+                st = ST_NONE;
+                if (prev[e] == OC_HOLE) c.iblank[e] = OC_HOLE;
             }
+            stat[item] = st;
+            ncand[item] = (int32_t)(tot < 0x7fffffff ? tot : 0x7fffffff);
         }
     }
 }
@@ -613,36 +626,41 @@ struct ExactArgs {
     const CutInst *insts;
     const int32_t *bin_start;
     const int32_t *bitems;
-    const uint64_t *list_in;    // near (k_hit) or side (k_side) elements
-    uint64_t *list_side;
-    uint64_t *list_hole;
-    CutCounters *cnt;
+    const uint64_t *list_inbox;
+    uint8_t *stat;              // k_hit takes ST_NEAR items, k_side ST_SIDE items
+    const CutCounters *cnt;
 };
 
 constexpr int kFaceCap = 256;
+constexpr int kGroup = 8;   // candidate faces tested together by k_hit
 
 // a4: one wavefront per near element decides whether the surface intersects
 // it: some element-boundary / surface triangle pair closer than tol_hit
 // (Alg. cp2, with no truncation of the candidate faces), or the whole surface
 // inside the element.  Candidate faces that come within the element's
-// boundary-face boxes are collected in LDS; for each, the 384 triangle pairs
-// are screened by FP64 boxes and only the survivors get the exact test, one
-// pair per lane.
+// boundary-face boxes are collected in LDS and taken in groups of 1, 2, 4,
+// then kGroup faces (most intersected elements are decided by their first
+// faces; the others must test them all): a group's nodes are loaded
+// together, one lane builds each face triangle's box, the group's triangle
+// pairs (384 per face) are screened by FP64 boxes and only the survivors get
+// the exact test, one pair per lane; the element stops at the first group
+// with a hit.
 __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
 {
     __shared__ double sX[81];
     __shared__ double sTB[48 * 6];   // element triangle boxes
     __shared__ double sEF[6 * 6];    // element boundary-face boxes
-    __shared__ double sF[27];        // current face nodes
-    __shared__ double sFT[8 * 6];    // current face triangle boxes
+    __shared__ double sF[kGroup * 27];       // nodes of the current group of faces
+    __shared__ double sFT[kGroup * 8 * 6];   // their triangle boxes
     __shared__ int sList[kFaceCap];
-    __shared__ short sPair[384];
+    __shared__ short sPair[kGroup * 384];
     __shared__ WalkLds L;
     const int lane = threadIdx.x;
-    const int n_near = a.cnt->n_near;
+    const int n_in = a.cnt->n_inbox;
     const double tol = kTolHit;
-    for (int item = blockIdx.x; item < n_near; item += gridDim.x) {
-        const uint64_t it = a.list_in[item];
+    for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
+        if (a.stat[item] != ST_NEAR) continue;
+        const uint64_t it = a.list_inbox[item];
         const int ci = item_cut(it), e = item_elem(it);
         const CutInst &c = a.insts[ci];
         const BinGrid G = c.params->grid;
@@ -685,25 +703,33 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         int nlist = 0;
         // exact test of the listed faces
         auto flush = [&]() {
-            for (int i = 0; i < nlist && !hit; ++i) {
-                const int fid = sList[i];
-                if (lane < 27) sF[lane] = pnodes[(int64_t)fid * 27 + lane];
+            int ng = 0;
+            for (int i0 = 0, round = 0; i0 < nlist && !hit; i0 += ng, ++round) {
+                ng = min(min(1 << round, kGroup), nlist - i0);
+                for (int k = lane; k < 27 * ng; k += 64) {
+                    const int g = k / 27;
+                    sF[k] = pnodes[(int64_t)sList[i0 + g] * 27 + (k - 27 * g)];
+                }
                 __syncthreads();
-                if (lane < 8) {
+                if (lane < 8 * ng) {
                     d3 F[3];
-                    face_tri(sF, lane, F);
+                    face_tri(sF + 27 * (lane >> 3), lane & 7, F);
                     double *bb = sFT + 6 * lane;
                     bb[0] = fmin(F[0].x, fmin(F[1].x, F[2].x)); bb[3] = fmax(F[0].x, fmax(F[1].x, F[2].x));
                     bb[1] = fmin(F[0].y, fmin(F[1].y, F[2].y)); bb[4] = fmax(F[0].y, fmax(F[1].y, F[2].y));
                     bb[2] = fmin(F[0].z, fmin(F[1].z, F[2].z)); bb[5] = fmax(F[0].z, fmax(F[1].z, F[2].z));
                 }
                 __syncthreads();
-                // screen the 384 pairs (pair p = 48 * face_tri + elem_tri)
+                // screen the pairs p = 384 * group face + 48 * face triangle + element triangle
                 int np = 0;
-                for (int kk = 0; kk < 6; ++kk) {
-                    const int p = lane + 64 * kk;
-                    const int s = p / 48, t = p - 48 * s;
-                    const bool pass = boxes_within(sTB + 6 * t, sFT + 6 * s, tol);
+                for (int p0 = 0; p0 < 384 * ng; p0 += 64) {
+                    const int p = p0 + lane;
+                    bool pass = false;
+                    if (p < 384 * ng) {
+                        const int g = p / 384, r = p - 384 * g;
+                        const int s = r / 48, t = r - 48 * s;
+                        pass = boxes_within(sTB + 6 * t, sFT + 6 * (8 * g + s), tol);
+                    }
                     const unsigned long long m = __ballot(pass);
                     if (pass) sPair[np + __popcll(m & ((1ull << lane) - 1ull))] = (short)p;
                     np += __popcll(m);
@@ -712,10 +738,11 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
                 bool lh = false;
                 for (int q = lane; q < np && !lh; q += 64) {
                     const int p = sPair[q];
-                    const int s = p / 48, t = p - 48 * s;
+                    const int g = p / 384, r = p - 384 * g;
+                    const int s = r / 48, t = r - 48 * s;
                     d3 T[3], F[3];
                     elem_tri(sX, t, T);
-                    face_tri(sF, s, F);
+                    face_tri(sF + 27 * g, s, F);
                     lh = tri_tri_within(T, F, tol);
                 }
                 if (__ballot(lh)) hit = true;
@@ -759,15 +786,8 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
             if (__popcll(__ballot(c)) & 1) hit = true;
         }
         if (lane == 0) {
-            if (hit) {
-                atomicAdd(&a.cnt->n_hit, 1);
-                if (c.kind == OC_SURF_WALL && c.iblank[e] != OC_HOLE) {
-                    c.iblank[e] = OC_HOLE;
-                    a.list_hole[atomicAdd(&a.cnt->n_hole, 1)] = it;
-                }
-            } else {
-                a.list_side[atomicAdd(&a.cnt->n_side, 1)] = it;
-            }
+            a.stat[item] = hit ? ST_HIT : ST_SIDE;
+            if (hit && c.kind == OC_SURF_WALL) c.iblank[e] = OC_HOLE;
         }
     }
 }
@@ -783,9 +803,10 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
     __shared__ TieRec rec[128];
     __shared__ WalkLds L;
     const int lane = threadIdx.x;
-    const int n_side = a.cnt->n_side;
-    for (int item = blockIdx.x; item < n_side; item += gridDim.x) {
-        const uint64_t it = a.list_in[item];
+    const int n_in = a.cnt->n_inbox;
+    for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
+        if (a.stat[item] != ST_SIDE) continue;
+        const uint64_t it = a.list_inbox[item];
         const int ci = item_cut(it), e = item_elem(it);
         const CutInst &c = a.insts[ci];
         const BinGrid G = c.params->grid;
@@ -808,6 +829,7 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
                     if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb) && point_box_dist(p, fb) < u)
                         u = fmin(u, point_face_dist(p, pnodes + (int64_t)f * 27));
                 }
+                u = wave_min_d(u);   // every lane prunes with the wavefront's best so far
                 return false;
             });
         }
@@ -824,6 +846,7 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
                     if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
                         best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
                 }
+                best = wave_min_d(best);
                 return false;
             });
         }
@@ -881,10 +904,7 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
             double sg = c1.dot;
             if (c2.valid && c1.absdot - c2.absdot <= 1e-9 && ((c1.dot > 0.0) != (c2.dot > 0.0)))
                 sg = c1.vx * (c1.nx + c2.nx) + c1.vy * (c1.ny + c2.ny) + c1.vz * (c1.nz + c2.nz);
-            if (c1.valid && sg < 0.0 && c.iblank[e] != OC_HOLE) {
-                c.iblank[e] = OC_HOLE;
-                a.list_hole[atomicAdd(&a.cnt->n_hole, 1)] = it;
-            }
+            if (c1.valid && sg < 0.0) c.iblank[e] = OC_HOLE;
         }
     }
 }
@@ -893,14 +913,15 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
 // the column of bins that holds the ray.
 __global__ __launch_bounds__(64) void k_ray(const CutInst *__restrict__ I, const int32_t *__restrict__ bin_start,
                                             const int32_t *__restrict__ bitems,
-                                            const uint64_t *__restrict__ list_far, uint64_t *__restrict__ list_hole,
-                                            CutCounters *cnt)
+                                            const uint64_t *__restrict__ list_inbox,
+                                            const uint8_t *__restrict__ stat, const CutCounters *cnt)
 {
     __shared__ WalkLds L;
-    const int n_far = cnt->n_far;
+    const int n_in = cnt->n_inbox;
     const int lane = threadIdx.x;
-    for (int item = blockIdx.x; item < n_far; item += gridDim.x) {
-        const uint64_t it = list_far[item];
+    for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
+        if (stat[item] != ST_FAR) continue;
+        const uint64_t it = list_inbox[item];
         const int ci = item_cut(it), e = item_elem(it);
         const CutInst &c = I[ci];
         const SurfParams *sp = c.params;
@@ -935,29 +956,77 @@ __global__ __launch_bounds__(64) void k_ray(const CutInst *__restrict__ I, const
             return false;
         });
         const int odd = __popcll(__ballot(par)) & 1;
-        if (lane == 0 && odd && c.iblank[e] != OC_HOLE) {
-            c.iblank[e] = OC_HOLE;
-            list_hole[atomicAdd(&cnt->n_hole, 1)] = it;
-        }
+        if (lane == 0 && odd) c.iblank[e] = OC_HOLE;
     }
 }
 
-// a8: fringe layer (field elements sharing a face with a hole)
+// a8: fringe layer (field elements sharing a face with a hole).  Every hole
+// is an in-box item of some cut of its output, so the scatter runs over the
+// in-box items that ended up holes.
 __global__ __launch_bounds__(kThreads) void k_fringe(const CutInst *__restrict__ I,
-                                                     const uint64_t *__restrict__ list_hole,
+                                                     const uint64_t *__restrict__ list_inbox,
                                                      const CutCounters *__restrict__ cnt)
 {
-    const int n = cnt->n_hole;
+    const int n = cnt->n_inbox;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const uint64_t it = list_hole[i];
+        const uint64_t it = list_inbox[i];
         const int e = item_elem(it);
         const CutInst &c = I[item_cut(it)];
-        const int32_t *nbr = c.nbr;
         int8_t *iblank = c.iblank;
+        if (iblank[e] != OC_HOLE) continue;
+        const int32_t *nbr = c.nbr;
         for (int f = 0; f < 6; ++f) {
             const int q = nbr[(int64_t)e * 6 + f];
             if (q >= 0 && iblank[q] != OC_HOLE) iblank[q] = OC_FRINGE;
         }
+    }
+}
+
+// Statistics of the last batch (only when asked for): item statuses,
+// candidate pairs, and the holes of every output.
+__global__ __launch_bounds__(kThreads) void k_cut_stats(const uint8_t *__restrict__ stat,
+                                                        const int32_t *__restrict__ ncand, CutCounters *cnt)
+{
+    __shared__ unsigned long long acc[5];
+    if (threadIdx.x < 5) acc[threadIdx.x] = 0ull;
+    __syncthreads();
+    const int n = cnt->n_inbox;
+    unsigned long long h = 0, sd = 0, fr = 0, cp = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint8_t s = stat[i];
+        h += s == ST_HIT;
+        sd += s == ST_SIDE;
+        fr += s == ST_FAR;
+        if (s == ST_HIT || s == ST_SIDE) cp += (unsigned long long)ncand[i];
+    }
+    atomicAdd(&acc[0], h);
+    atomicAdd(&acc[1], sd);
+    atomicAdd(&acc[2], fr);
+    atomicAdd(&acc[3], cp);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&cnt->n_hit, (int)acc[0]);
+        atomicAdd(&cnt->n_side, (int)acc[1]);
+        atomicAdd(&cnt->n_near, (int)(acc[0] + acc[1]));
+        atomicAdd(&cnt->n_far, (int)acc[2]);
+        atomicAdd(&cnt->n_cand_pairs, acc[3]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_count_holes(const CutOut *__restrict__ O, int n_out, CutCounters *cnt)
+{
+    const int oi = block_owner(n_out, blockIdx.x, [&](int k) { return O[k].cblk0; });
+    const CutOut &o = O[oi];
+    const int64_t e = (int64_t)(blockIdx.x - o.cblk0) * blockDim.x + threadIdx.x;
+    const int h = __syncthreads_count(e < o.n_elem && o.iblank[e] == OC_HOLE);
+    if (threadIdx.x == 0 && h) atomicAdd(&cnt->n_hole, h);
+}
+
+__global__ void k_stats_reset(CutCounters *cnt)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        cnt->n_near = cnt->n_far = cnt->n_hit = cnt->n_hole = cnt->n_side = 0;
+        cnt->n_cand_pairs = 0ull;
     }
 }
 
@@ -1090,7 +1159,7 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
     }
     std::vector<CutInst> I;
     std::vector<CutOut> O;
-    int64_t fblk = 0, eblk = 0, face_off = 0, fill_blk = 0, ov_blk = 0, n_elem_total = 0;
+    int64_t fblk = 0, eblk = 0, face_off = 0, fill_blk = 0, ov_blk = 0, cnt_blk = 0, n_elem_total = 0;
     for (int r = 0; r < n_req; ++r) {
         const CutReq &q = reqs[r];
         const Grid &g = *q.g;
@@ -1101,6 +1170,9 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         o.n_overset = g.n_overset;
         o.fblk0 = (int)fill_blk;
         o.oblk0 = (int)ov_blk;
+        o.cblk0 = (int)cnt_blk;
+        o.pad = 0;
+        cnt_blk += blocks_of(g.n_elem, kThreads);
         if (q.n_surf == 0) fill_blk += blocks_of(g.n_elem, kThreads);
         ov_blk += blocks_of(g.n_overset, kThreads);
         O.push_back(o);
@@ -1138,20 +1210,24 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         }
     }
     if (fblk >= INT32_MAX || eblk >= INT32_MAX || fill_blk >= INT32_MAX || ov_blk >= INT32_MAX ||
-        need.elem_inst >= INT32_MAX) {
+        need.elem_inst >= INT32_MAX || cnt_blk >= INT32_MAX) {
         set_error("cut batch too large");
         return OC_EINVAL;
     }
     sl->last_n_elem = n_elem_total;
     const int n_cut = (int)I.size(), n_out = (int)O.size();
+    sl->last_n_cut = n_cut;
+    sl->last_n_out = n_out;
+    sl->last_cblk = (int)cnt_blk;
+    sl->last_outs = O;
     int32_t *n_bins_dev = sl->scalar + 4;
     if (n_cut) OC_TRY(put_bytes(sl, sl->insts, I.data(), sizeof(CutInst) * I.size()));
     if (fill_blk || ov_blk) OC_TRY(put_bytes(sl, sl->outs, O.data(), sizeof(CutOut) * O.size()));
-    LAUNCH(k_reset_counters, dim3(1), dim3(kThreads), sl->counters, sl->insts, n_cut);
+    LAUNCH(k_reset_counters, dim3(1), dim3(64), sl->counters);
     if (fill_blk) LAUNCH(k_fill_field, dim3((unsigned)fill_blk), dim3(kThreads), sl->outs, n_out);
     if (n_cut) {
-        LAUNCH(k_pose_faces, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut);
-        LAUNCH(k_bins_setup, dim3(1), dim3(kThreads), sl->insts, n_cut, n_bins_dev);
+        LAUNCH(k_pose_faces, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->sbox_part);
+        LAUNCH(k_bins_setup, dim3(1), dim3(kThreads), sl->insts, n_cut, sl->sbox_part, n_bins_dev);
         LAUNCH(k_zero_i32, dim3(grid_for(need.bins + 1, kThreads, 4096)), dim3(kThreads), sl->bin_count, n_bins_dev,
                (int64_t)0);
         LAUNCH(k_bin_count, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_count);
@@ -1159,24 +1235,39 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         LAUNCH(k_bin_fill, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_start, sl->bin_count,
                sl->bin_items);
         LAUNCH(k_filter, dim3((unsigned)eblk), dim3(kThreads), sl->insts, n_cut, sl->l_inbox, sl->counters);
-        LAUNCH(k_candidates, dim3(8192), dim3(64), sl->insts, sl->bin_start, sl->bin_items, sl->l_inbox, sl->l_near,
-               sl->l_far, sl->l_hole, sl->counters);
+        LAUNCH(k_candidates, dim3((unsigned)ctx->exact_waves), dim3(64), sl->insts, sl->bin_start, sl->bin_items,
+               sl->l_inbox, sl->l_stat, sl->l_ncand, sl->counters);
         ExactArgs ea;
         ea.insts = sl->insts;
         ea.bin_start = sl->bin_start;
         ea.bitems = sl->bin_items;
-        ea.list_in = sl->l_near;
-        ea.list_side = sl->l_side;
-        ea.list_hole = sl->l_hole;
+        ea.list_inbox = sl->l_inbox;
+        ea.stat = sl->l_stat;
         ea.cnt = sl->counters;
-        LAUNCH(k_hit, dim3(8192), dim3(64), ea);
-        ea.list_in = sl->l_side;
-        LAUNCH(k_side, dim3(8192), dim3(64), ea);
-        LAUNCH(k_ray, dim3(8192), dim3(64), sl->insts, sl->bin_start, sl->bin_items, sl->l_far, sl->l_hole,
-               sl->counters);
-        LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_hole, sl->counters);
+        LAUNCH(k_hit, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
+        LAUNCH(k_side, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
+        LAUNCH(k_ray, dim3((unsigned)ctx->exact_waves), dim3(64), sl->insts, sl->bin_start, sl->bin_items,
+               sl->l_inbox, sl->l_stat, sl->counters);
+        LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_inbox, sl->counters);
     }
     if (ov_blk) LAUNCH(k_overset_fringe, dim3((unsigned)ov_blk), dim3(kThreads), sl->outs, n_out);
+    OC_HIP(hipGetLastError());
+    return OC_OK;
+}
+
+// Counters of the slot's last cut batch (on the slot stream; the caller
+// reads them back).
+oc_status cut_stats_run(oc_slot *sl)
+{
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    LAUNCH(k_stats_reset, dim3(1), dim3(64), sl->counters);
+    if (sl->last_n_cut > 0)
+        LAUNCH(k_cut_stats, dim3(256), dim3(kThreads), sl->l_stat, sl->l_ncand, sl->counters);
+    if (sl->last_cblk > 0) {
+        OC_TRY(put_bytes(sl, sl->outs, sl->last_outs.data(), sizeof(CutOut) * sl->last_outs.size()));
+        LAUNCH(k_count_holes, dim3((unsigned)sl->last_cblk), dim3(kThreads), sl->outs, sl->last_n_out, sl->counters);
+    }
     OC_HIP(hipGetLastError());
     return OC_OK;
 }

@@ -11,6 +11,7 @@ from __future__ import annotations
 import ctypes as C
 import json
 import os
+import weakref
 
 import numpy as np
 
@@ -21,6 +22,7 @@ OC_OK, OC_EINVAL, OC_ENOMEM, OC_EDEVICE, OC_ENOTFOUND, OC_EBUDGET, OC_EGEOM, OC_
 OC_HOLE, OC_FIELD, OC_FRINGE = 0, 1, -1
 OC_SURF_WALL, OC_SURF_OVERSET = 0, 1
 OC_FACE_INTERIOR, OC_FACE_WALL, OC_FACE_OVERSET, OC_FACE_FARFIELD = 0, 1, 2, 3
+OC_TUNE_SURF_BINS, OC_TUNE_EXACT_WAVES = 1, 2
 
 EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_register_grid",
            "oc_register_cut_surface", "oc_cut", "oc_cut_multi", "oc_last_cut_info", "oc_fringe_points",
@@ -28,7 +30,7 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_slot_create", "oc_slot_destroy", "oc_slot_set_stream", "oc_slot_bytes", "oc_slot_cut",
            "oc_slot_fringe_points", "oc_slot_donor_search", "oc_slot_cut_info", "oc_slot_donor_info",
            "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm", "oc_cut_batch", "oc_slot_cut_batch",
-           "oc_slot_create_batch"]
+           "oc_slot_create_batch", "oc_tune"]
 
 
 class OcError(RuntimeError):
@@ -99,6 +101,7 @@ def load(path=LIB_PATH):
         "oc_cut_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32]),
         "oc_slot_cut_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32]),
         "oc_slot_create_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32, C.c_int64, C.POINTER(C.c_void_p)]),
+        "oc_tune": ([vp, C.c_int32, C.c_int32, C.c_int64, i64p]),
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -169,12 +172,18 @@ class Context:
         _check(L.oc_create(C.byref(h), C.byref(cfg)))
         self._h = h
         self.device = device
+        self._slots = weakref.WeakSet()
         self.grids = {}
         self.surfs = {}
         self.set_stream(stream)
 
     def close(self):
+        """Destroy the context.  Its slots are destroyed with it: Slot
+        objects still alive become closed handles."""
         if getattr(self, "_h", None):
+            for sl in list(self._slots):
+                sl._h = None
+            self._slots.clear()
             load().oc_destroy(self._h)
             self._h = None
 
@@ -291,6 +300,12 @@ class Context:
         _check(load().oc_timing_report(self._h, buf, len(buf)))
         return json.loads(buf.value.decode())
 
+    def tune(self, knob, arg, value):
+        """Set a tuning knob (OC_TUNE_*); returns the value in force."""
+        v = C.c_int64(0)
+        _check(load().oc_tune(self._h, int(knob), int(arg), int(value), C.byref(v)))
+        return v.value
+
     def memory_used(self):
         v = C.c_int64(0)
         _check(load().oc_memory_used(self._h, C.byref(v)))
@@ -328,6 +343,7 @@ class Slot:
                                          sid.ctypes.data_as(C.POINTER(C.c_int32)), len(sid), int(points_cap),
                                          C.byref(h)))
         self._h = h
+        ctx._slots.add(self)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=ctx.device)
         self.set_stream(self.stream)
 
@@ -335,6 +351,7 @@ class Slot:
         if getattr(self, "_h", None):
             load().oc_slot_destroy(self._h)
             self._h = None
+            self.ctx._slots.discard(self)
 
     def __del__(self):
         try:

@@ -65,6 +65,11 @@ def test_batch_equals_solo_and_oracle(ctx, orc):
         assert np.array_equal(got, ref), c["name"]
         n_hole += int((got == 0).sum())
     assert n_hole > 0
+    # batch statistics: holes of every output, item statuses
+    assert info["n_hole"] == n_hole
+    assert 0 < info["n_hit"] <= info["n_near"] <= info["n_inbox"]
+    assert info["n_near"] + info["n_far"] <= info["n_inbox"]
+    assert info["n_cand_pairs"] >= info["n_near"]
 
 
 def test_batch_mixed_requests(ctx, orc):
@@ -162,3 +167,40 @@ def test_batch_errors(ctx):
         ctx.cut_batch([(g, [a], bad.reshape(1, 12), ib)])
     assert e.value.status == oc.OC_EINVAL
     ctx.cut_batch([])
+
+
+def test_tuning_knobs_do_not_change_results(ctx):
+    """Bin caps and exact-stage wavefront counts change speed only."""
+    import torch
+    from paper_1711_07663_amd import autotune, oc
+    _note("tuning knobs: same iblank under every setting")
+    cases = _small_batch(6)
+    ids = _register(ctx, cases)
+    outs = [torch.empty(c["bg"].n_elem, dtype=torch.int8, device="cuda") for c in cases]
+    reqs = [(g, [s], c["poses"][0].reshape(1, 12), ib) for (g, s), c, ib in zip(ids, cases, outs)]
+    ctx.cut_batch(reqs)
+    torch.cuda.synchronize()
+    ref = [o.cpu().numpy().copy() for o in outs]
+    auto = {s: ctx.tune(oc.OC_TUNE_SURF_BINS, s, 0) for _, s in ids}
+    for factor, waves in ((0.5, 64), (0.25, 1), (1.0, 20000), (0.01, 8192)):
+        for s, nb in auto.items():
+            assert ctx.tune(oc.OC_TUNE_SURF_BINS, s, max(1, int(nb * factor))) >= 1
+        ctx.tune(oc.OC_TUNE_EXACT_WAVES, 0, waves)
+        for o in outs:
+            o.fill_(5)
+        ctx.cut_batch(reqs)
+        torch.cuda.synchronize()
+        for a, b in zip(ref, outs):
+            assert np.array_equal(a, b.cpu().numpy())
+    faces = {s: c["bodies"][0]["surface"].n_face for (g, s), c in zip(ids, cases)}
+    params, report = autotune.tune_batch(ctx, reqs, faces, reps=1)
+    assert params["exact_waves"] in (2048, 4096, 8192, 16384)
+    ctx.cut_batch(reqs)
+    torch.cuda.synchronize()
+    for a, b in zip(ref, outs):
+        assert np.array_equal(a, b.cpu().numpy())
+    for s in auto:
+        ctx.tune(oc.OC_TUNE_SURF_BINS, s, 0)
+    ctx.tune(oc.OC_TUNE_EXACT_WAVES, 0, 0)
+    with pytest.raises(oc.OcError):
+        ctx.tune(99, 0, 0)
