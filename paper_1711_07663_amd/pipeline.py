@@ -95,28 +95,89 @@ class OversetSystem:
         return counts
 
 
+def _alloc_outputs(system, dev, n_ib_bg=1):
+    """Device output buffers of one connectivity step of ``system``."""
+    out = dict(ib_bg=[torch.empty(system.n_bg, dtype=torch.int8, device=dev) for _ in range(n_ib_bg)])
+    cap_bg = system.pts_bg.shape[0]
+    out["pts_bg"] = torch.empty((cap_bg, 3), dtype=torch.float64, device=dev)
+    out["src_bg"] = torch.empty(cap_bg, dtype=torch.int32, device=dev)
+    out["bodies"] = []
+    for b in system.bodies:
+        cap = b["pts"].shape[0]
+        out["bodies"].append(dict(
+            ib=torch.empty(b["n_shell"], dtype=torch.int8, device=dev),
+            pts=torch.empty((cap, 3), dtype=torch.float64, device=dev),
+            src=torch.empty(cap, dtype=torch.int32, device=dev),
+            donor=torch.empty(cap, dtype=torch.int32, device=dev),
+            ref=torch.empty((cap, 3), dtype=torch.float64, device=dev),
+            donor_bg=torch.empty(cap_bg, dtype=torch.int32, device=dev),
+            ref_bg=torch.empty((cap_bg, 3), dtype=torch.float64, device=dev)))
+    return out
+
+
 class SlotStep:
-    """The same connectivity step on a slot of an OversetSystem: poses and
-    point counts live on the device, nothing synchronises, and the launch
-    sequence can be captured once in a graph and replayed with new poses.
+    """The connectivity step of an OversetSystem on slots of its own: poses
+    and point counts live on the device, the outputs belong to this object
+    (several SlotSteps of one system can run at once), nothing synchronises,
+    and the launch sequence can be captured in a graph and replayed with new
+    poses.
+
+    The step is two independent chains, each on its own slot and stream:
+      A  background cut by every wall -> background receptor points -> their
+         donors in every shell;
+      B  each shell cut by the other walls -> shell receptor points -> their
+         donors in the background.
+    Chain B forks from A's stream after the pose upload and joins it at the
+    end, so the latency-bound cut kernels of A overlap B's donor search (also
+    inside a captured graph).
 
     Device pose table rows: [0, nb) body poses (background cut; shell receptor
     points and bg->shell searches); then for body i the poses of the other
-    bodies in body i's frame (shell cuts); the last row is the identity."""
+    bodies in body i's frame (shell cuts); the last row is the identity.
 
-    def __init__(self, system: OversetSystem, stream=None):
+    ``warm``: (one body) the background cut of step k starts from the iblank
+    of step k-1 with the sweep bound ``sweep`` (a bound on how far any wall
+    point moves in one step, e.g. Context.sweep_bound of two consecutive
+    poses); the two iblank buffers alternate, so a captured step exists for
+    each parity."""
+
+    def __init__(self, system: OversetSystem, stream=None, warm=False, sweep=0.0):
         self.sys = system
         ctx = system.ctx
         dev = torch.device("cuda", ctx.device)
         nb = len(system.bodies)
+        if warm and nb != 1:
+            raise ValueError("warm start needs exactly one body")
         grids = [system.bg_id] + [b["shell"] for b in system.bodies]
-        surfs = sorted(set(b["surf"] for b in system.bodies))
+        surfs = [b["surf"] for b in system.bodies]
         cap = max([system.pts_bg.shape[0]] + [b["pts"].shape[0] for b in system.bodies])
         self.slot = ctx.create_slot(grids, surfs, cap, stream)
+        self.slot_b = ctx.create_slot(grids, surfs, cap)
         self.n_pose = nb + nb * (nb - 1) + 1
         self.poses_dev = torch.zeros((self.n_pose, 12), dtype=torch.float64, device=dev)
         self.n_dev = torch.zeros(1 + nb, dtype=torch.int32, device=dev)
-        self.graph = None
+        self.warm = warm
+        self.sweep = float(sweep)
+        self.out = _alloc_outputs(system, dev, 2 if warm else 1)
+        self.k = 0              # steps launched (selects the iblank buffer when warm)
+        self.graphs = {}
+
+    @property
+    def stream(self):
+        return self.slot.stream
+
+    def close(self):
+        self.slot.close()
+        self.slot_b.close()
+
+    def nbytes(self):
+        return self.slot.nbytes() + self.slot_b.nbytes()
+
+    def ib_bg(self, k=None):
+        """Background iblank of step k (default: the last launched step)."""
+        bufs = self.out["ib_bg"]
+        k = self.k - 1 if k is None else k
+        return bufs[k % len(bufs)]
 
     def _pose_table(self, poses):
         nb = len(self.sys.bodies)
@@ -127,55 +188,114 @@ class SlotStep:
         rows.append(IDENTITY)
         return torch.from_numpy(np.stack(rows))
 
-    def _launch(self):
-        s, sl = self.sys, self.slot
+    def _launch(self, k, cold, main=None, serial=False):
+        """Both chains; ``main`` is the stream chain A runs on (the slot's
+        own stream, or the capture stream).  ``serial`` runs chain B on the
+        main stream too (no overlap: every kernel has the device to itself,
+        for per-kernel timing)."""
+        s, o = self.sys, self.out
+        sa, sb = self.slot, self.slot_b
+        main = main if main is not None else sa.stream
+        side = sb.stream
+        if serial:
+            sb.set_stream(main)
+            side = main
         nb = len(s.bodies)
         sids = [b["surf"] for b in s.bodies]
-        sl.cut(s.bg_id, sids, self.poses_dev[:nb], s.ib_bg)
+        bufs = o["ib_bg"]
+        ib_bg = bufs[k % len(bufs)]
+        ident = self.poses_dev[self.n_pose - 1]
+        side.wait_stream(main)
+        # chain B: shells
         r = nb
         for i, b in enumerate(s.bodies):
             others = [sids[j] for j in range(nb) if j != i]
-            sl.cut(b["shell"], others, self.poses_dev[r:r + nb - 1], b["ib"])
+            ob = o["bodies"][i]
+            sb.cut(b["shell"], others, self.poses_dev[r:r + nb - 1], ob["ib"])
             r += nb - 1
-        ident = self.poses_dev[self.n_pose - 1]
-        cap_bg = s.pts_bg.shape[0]
-        sl.fringe_points(s.bg_id, ident, s.ib_bg, s.pts_bg, self.n_dev[0:1], s.src_bg)
-        for i, b in enumerate(s.bodies):
-            sl.donor_search(b["shell"], self.poses_dev[i], s.pts_bg, cap_bg, self.n_dev[0:1], b["donor_bg"],
-                            b["ref_bg"])
-        for i, b in enumerate(s.bodies):
-            cap = b["pts"].shape[0]
-            sl.fringe_points(b["shell"], self.poses_dev[i], b["ib"], b["pts"], self.n_dev[1 + i:2 + i], b["src"])
-            sl.donor_search(s.bg_id, ident, b["pts"], cap, self.n_dev[1 + i:2 + i], b["donor"], b["ref"])
+            cap = ob["pts"].shape[0]
+            sb.fringe_points(b["shell"], self.poses_dev[i], ob["ib"], ob["pts"], self.n_dev[1 + i:2 + i], ob["src"])
+            sb.donor_search(s.bg_id, ident, ob["pts"], cap, self.n_dev[1 + i:2 + i], ob["donor"], ob["ref"])
+        # chain A: background
+        if self.warm and not cold:
+            sa.cut_warm(s.bg_id, sids[0], self.poses_dev[0], self.sweep, bufs[(k - 1) % 2], ib_bg)
+        else:
+            sa.cut(s.bg_id, sids, self.poses_dev[:nb], ib_bg)
+        cap_bg = o["pts_bg"].shape[0]
+        sa.fringe_points(s.bg_id, ident, ib_bg, o["pts_bg"], self.n_dev[0:1], o["src_bg"])
+        for i, b in enumerate(o["bodies"]):
+            sa.donor_search(s.bodies[i]["shell"], self.poses_dev[i], o["pts_bg"], cap_bg, self.n_dev[0:1],
+                            b["donor_bg"], b["ref_bg"])
+        if serial:
+            sb.set_stream(sb.stream)
+        else:
+            main.wait_stream(side)
 
     def set_poses(self, poses):
         with torch.cuda.stream(self.slot.stream):
             self.poses_dev.copy_(self._pose_table(poses))
 
-    def step(self, poses):
-        """Eager launches on the slot stream (no synchronisation)."""
+    def step(self, poses, cold=False, serial=False):
+        """Eager launches on the slot streams (no synchronisation); the step
+        is complete when the slot stream (``stream``) reaches its end.  The
+        first step of a warm SlotStep (or one with ``cold``) is a cold cut;
+        ``serial`` runs both chains on the slot stream, one after the other."""
         self.set_poses(poses)
-        self._launch()
+        self._launch(self.k, cold or self.k == 0, serial=serial)
+        self.k += 1
 
     def capture(self):
-        g = torch.cuda.CUDAGraph()
+        """Capture the step (both iblank parities when warm); a warm
+        SlotStep must have run one eager step first."""
+        if self.warm and self.k == 0:
+            raise RuntimeError("run one eager step before capturing a warm step")
         torch.cuda.synchronize()
-        with torch.cuda.graph(g):
-            self.slot.set_stream(torch.cuda.current_stream())
-            self._launch()
-        self.slot.set_stream(self.slot.stream)
-        self.graph = g
-        return g
+        side = self.slot_b.stream
+        for par in ((0, 1) if self.warm else (0,)):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                cur = torch.cuda.current_stream()
+                self.slot.set_stream(cur)
+                self._launch(par, False, main=cur)
+            self.slot.set_stream(self.slot.stream)
+            self.slot_b.set_stream(side)
+            self.graphs[par] = g
+        return self.graphs
+
+    def pose_table_dev(self, poses):
+        """Device copy of the pose table of ``poses`` (for replay_table)."""
+        return self._pose_table(poses).to(self.poses_dev.device)
 
     def replay(self, poses):
-        """Graph replay on the slot stream with new poses."""
-        if self.graph is None:
+        """Graph replay of the next step on the slot stream with new poses."""
+        self.replay_table(self._pose_table(poses))
+
+    def replay_table(self, table):
+        """Graph replay with a pose table (host, or device: then the copy is
+        stream ordered and the host does not wait)."""
+        if not self.graphs:
             self.capture()
         with torch.cuda.stream(self.slot.stream):
-            self.poses_dev.copy_(self._pose_table(poses))
-            self.graph.replay()
+            self.poses_dev.copy_(table, non_blocking=table.is_cuda)
+            self.graphs[self.k % 2 if self.warm else 0].replay()
+        self.k += 1
 
     def counts(self):
-        """Point counts (synchronises)."""
+        """Point counts (waits for the slot stream)."""
+        self.slot.stream.synchronize()
         n = self.n_dev.cpu().tolist()
         return dict(n_bg_points=n[0], n_shell_points=n[1:])
+
+    def snapshot(self):
+        """Host copy of the last step's outputs (synchronises)."""
+        c = self.counts()
+        n_bg = c["n_bg_points"]
+        o = self.out
+        out = dict(ib_bg=self.ib_bg().cpu().numpy(), pts_bg=o["pts_bg"][:n_bg].cpu().numpy(),
+                   src_bg=o["src_bg"][:n_bg].cpu().numpy(), bodies=[])
+        for b, n in zip(o["bodies"], c["n_shell_points"]):
+            out["bodies"].append(dict(ib=b["ib"].cpu().numpy(), pts=b["pts"][:n].cpu().numpy(),
+                                      src=b["src"][:n].cpu().numpy(), donor_bg=b["donor_bg"][:n_bg].cpu().numpy(),
+                                      ref_bg=b["ref_bg"][:n_bg].cpu().numpy(), donor=b["donor"][:n].cpu().numpy(),
+                                      ref=b["ref"][:n].cpu().numpy()))
+        return out

@@ -70,8 +70,7 @@ def test_slot_step_matches_oracle_and_default_path(ctx, orc):
     ref = _snapshot(system, c0)
     ss = SlotStep(system)
     ss.step(poses)
-    torch.cuda.synchronize()
-    got = _snapshot(system, ss.counts())
+    got = ss.snapshot()
     _equal(ref, got)
     compare(got, oracle_step(case, poses))
 
@@ -91,38 +90,58 @@ def test_graph_replay_matches_eager(ctx, orc):
     ss.capture()
     for k, p in enumerate(poses):
         ss.step(p)
-        torch.cuda.synchronize()
-        eager = _snapshot(system, ss.counts())
+        eager = ss.snapshot()
         ss.replay(poses[(k + 3) % len(poses)])
         torch.cuda.synchronize()
         ss.replay(p)
-        torch.cuda.synchronize()
-        _equal(eager, _snapshot(system, ss.counts()))
-    compare(_snapshot(system, ss.counts()), oracle_step(case, poses[-1]))
+        _equal(eager, ss.snapshot())
+    compare(ss.snapshot(), oracle_step(case, poses[-1]))
 
 
 def test_two_slots_concurrent(ctx):
-    """Two slots of two systems on two streams, launched back to back without
-    synchronisation, give the results each gives alone."""
+    """Two SlotSteps of one system on two streams, launched back to back
+    without synchronisation, give the results each gives alone."""
     import torch
     from paper_1711_07663_amd.pipeline import OversetSystem, SlotStep
-    _note("two slots on two streams concurrently")
+    _note("two slots of one system on two streams concurrently")
     case = _small_case()
-    sa, sb = OversetSystem(ctx, case), OversetSystem(ctx, case)
-    ta, tb = SlotStep(sa), SlotStep(sb)
+    system = OversetSystem(ctx, case)
+    ta, tb = SlotStep(system), SlotStep(system)
     pa, pb = [M.pose_rz(0.3, (0.05, 0, 0))], [M.pose_rz(-0.2, (0, 0.04, 0.02))]
     ta.step(pa)
-    torch.cuda.synchronize()
-    solo_a = _snapshot(sa, ta.counts())
+    solo_a = ta.snapshot()
     tb.step(pb)
-    torch.cuda.synchronize()
-    solo_b = _snapshot(sb, tb.counts())
+    solo_b = tb.snapshot()
     for _ in range(3):
         ta.step(pa)
         tb.step(pb)
         torch.cuda.synchronize()
-        _equal(solo_a, _snapshot(sa, ta.counts()))
-        _equal(solo_b, _snapshot(sb, tb.counts()))
+        _equal(solo_a, ta.snapshot())
+        _equal(solo_b, tb.snapshot())
+
+
+def test_warm_slot_graph_spinning(ctx, orc):
+    """The spinning-body step: cold first step, then warm-started graph
+    replays (two parities) over 8 poses; each equals a cold eager step at
+    the same pose, and the last equals the oracle."""
+    import torch
+    from paper_1711_07663_amd.pipeline import OversetSystem, SlotStep
+    _note("warm-started graph replay of a spinning dimpled sphere, 8 steps")
+    case = _small_case()
+    system = OversetSystem(ctx, case)
+    poses = [[M.pose_rz(2 * np.pi * k / 50)] for k in range(9)]
+    sweep = ctx.sweep_bound(system.bodies[0]["surf"], poses[0][0], poses[1][0])
+    warm = SlotStep(system, warm=True, sweep=sweep)
+    cold = SlotStep(system)
+    warm.step(poses[0])
+    torch.cuda.synchronize()
+    warm.capture()
+    for k in range(1, len(poses)):
+        warm.replay(poses[k])
+        got = warm.snapshot()
+        cold.step(poses[k])
+        _equal(cold.snapshot(), got)
+    compare(got, oracle_step(case, poses[-1]))
 
 
 def test_slot_budget(ctx):
@@ -168,3 +187,22 @@ def test_warm_start_equals_cold(ctx, orc):
             assert np.array_equal(cur.cpu().numpy(), orc.cut(bg, [s], [poses[k]]))
         prev, cur = cur, prev
     assert ctx.sweep_bound(sid, poses[0], poses[1]) >= 0.5 * 2 * np.pi / 40
+
+
+def test_slot_outlives_context():
+    """Closing a context destroys its slots; a Slot object that outlives it
+    becomes a closed handle (its calls fail cleanly, closing it is a no-op)."""
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("slot object outliving its context")
+    c = oc.Context(device=0)
+    g = M.background_grid(4, -1, 1)
+    gid = c.register_grid(g.nodes, g.conn)
+    sl = c.create_slot([gid], [])
+    c.close()
+    ib = torch.empty(g.n_elem, dtype=torch.int8, device="cuda")
+    c.grids[gid] = g.n_elem
+    with pytest.raises(oc.OcError):
+        sl.cut(gid, [], None, ib)
+    sl.close()
+    del sl
