@@ -1,13 +1,21 @@
-"""Benchmark: one full overset connectivity step on one MI355X.
+"""Benchmark: the overset connectivity hot path on one MI355X.
 
-Workload (the single dimpled-sphere cut): background 128^3 quadratic hexes on
-[-3,3]^3 with the sinusoidal displacement; cut surface: R = 0.5 sphere with
-300 spherical-cap dimples, 24 576 quadratic quads; near-body shell of 8
-layers (196 608 hexes) to r = 1.  A step is the whole hot path: pose, bins,
-filter, exact intersection, nearest-face side, ray parity, union, fringe
+Default workload (the single dimpled-sphere cut): background 128^3 quadratic
+hexes on [-3,3]^3 with the sinusoidal displacement; cut surface: R = 0.5
+sphere with 300 spherical-cap dimples, 24 576 quadratic quads; near-body shell
+of 8 layers (196 608 hexes) to r = 1.  A step is the whole hot path: pose,
+bins, filter, exact intersection, nearest-face side, ray parity, union, fringe
 marking, Gauss receptor points and Newton donor search in both directions.
 Inputs are generated from fixed formulas (synthetic), resident on the device
 before timing.
+
+Other workloads (--workload):
+  spin   the dimpled sphere spinning about z at one turn per 400 steps, 200
+         steps, each a warm-started re-cut plus donors, replayed as HIP graphs;
+  batch  64 uneven instances (SeedSequence(1711)) cut in one launch per stage,
+         against the same instances cut one at a time;
+  serve  Poisson arrivals over four device-resident grid sets served with
+         continuous batching, against one-at-a-time service.
 
 Prints one JSON line.  Only N = 1 GPU is supported.
 """
@@ -29,14 +37,51 @@ FP64_VECTOR_PEAK = 78.6        # TFLOP/s, MI355X FP64 vector: 256 CU x 4 SIMD x 
 NEWTON_FLOP = 640              # FLOP per Newton iteration of the quadratic map (sum-factorised x, J, 3x3 solve)
 
 
+KERNEL_SOURCE = {"k_dp_newton": "paper_1711_07663_amd/csrc/k_donor.hip",
+                 "k_filter": "paper_1711_07663_amd/csrc/k_cut.hip"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of ``kernel`` from the committed profiler
+    summary profiles/<kernel>_traffic_dimpled128.md (FETCH_SIZE and
+    WRITE_SIZE passes scaled by the copy-kernel calibration), or None when
+    there is none or the kernel's source file changed since it was taken
+    (the summary records the source's SHA-256)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_traffic_dimpled128.md" % kernel)
+    src = KERNEL_SOURCE.get(kernel)
+    if not src or not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    try:
+        sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        if vals.get("source_sha256") != sha:
+            return None
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError, OSError):
+        return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=4, help="oracle runs on every k-th element / point")
+    ap.add_argument("--cpu-sample", type=int, default=1, help="oracle runs on every k-th element / point")
     ap.add_argument("--bg", type=int, default=128)
+    ap.add_argument("--workload", default="dimpled", choices=["dimpled", "spin", "batch", "serve"])
+    ap.add_argument("--spin-steps", type=int, default=200)
+    ap.add_argument("--batch-n", type=int, default=64)
+    ap.add_argument("--rates", default="50,100,200,500", help="serve: arrival rates, requests/s")
+    ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first run one plain 512 MiB device-to-device copy (calibrates profiler byte counters)")
     return ap.parse_args()
 
 
@@ -45,11 +90,16 @@ def log(msg):
 
 
 def cpu_baseline(case, sample_every):
-    """The oracle, as it stands, on a strided sample of the same step."""
+    """The oracle, as it stands, on the same step: cut of the background
+    (every sample_every-th element; 1 = all), fringe layer, receptor points
+    and donors of the background fringe in the shell, the shell's overset
+    fringe, its receptor points and their donors in the background (every
+    sample_every-th point).  The step time is scaled by sample_every."""
     import oracle as O
     bg = case["bg"]
     body = case["bodies"][0]
     s, sh = body["surface"], body["shell"]
+    pose = case["poses"][0]
     O.build(force=False)
     threads = os.cpu_count() or 1
     try:
@@ -57,24 +107,25 @@ def cpu_baseline(case, sample_every):
     except Exception:
         pass
     threads = min(threads, 16)
-    sel = np.arange(0, bg.n_elem, sample_every, dtype=np.int64)
+    k = max(1, int(sample_every))
     t0 = time.perf_counter()
-    O.cut_surface(bg, s, O.IDENTITY, sel=sel, threads=threads)
-    t_cut = time.perf_counter() - t0
-    # donors: shell fringe points (outer layer) searched in the background
-    nf = s.n_face
-    layers = sh.n_elem // nf
-    fe = np.arange((layers - 1) * nf, layers * nf, sample_every, dtype=np.int64)
-    pts = O.fringe_points(sh, fe)
-    t0 = time.perf_counter()
-    O.donor_search(bg, pts, threads=threads)
-    t_don = time.perf_counter() - t0
-    t_step = (t_cut + t_don) * sample_every
+    sel = np.arange(0, bg.n_elem, k, dtype=np.int64)
+    st = O.cut_surface(bg, s, pose, sel=sel, threads=threads)
+    hole = np.zeros(bg.n_elem, dtype=bool)
+    hole[sel] = st == 0
+    ib = O.mark_fringe(hole, O.face_neighbors(bg.conn))
+    pts_bg = O.fringe_points(bg, O.fringe_elements(ib))
+    O.donor_search(sh, pts_bg[::k], pose, threads=threads)
+    ib_sh = O.cut(sh, [], [])
+    pts_sh = O.fringe_points(sh, O.fringe_elements(ib_sh), pose)
+    O.donor_search(bg, pts_sh[::k], threads=threads)
+    t_wall = time.perf_counter() - t0
+    t_step = t_wall * k
+    what = "the whole step" if k == 1 else "every %d-th background element and receptor point (step time x %d)" % (k, k)
     return dict(value=bg.n_elem / t_step, unit="elements/s", cores=threads, kind="oracle",
-                sample="every %d-th background element classified (cut only, no fringe) and every %d-th "
-                       "outer-shell element's 27 Gauss points searched in the background; step time scaled "
-                       "by %d (cut %.2f s + donors %.2f s of wall time on %d threads)"
-                       % (sample_every, sample_every, sample_every, t_cut, t_don, threads),
+                sample="%s: cut of the 128^3 background, fringe, %d + %d receptor points and their donors in "
+                       "both directions; %.1f s of wall time on %d threads" % (what, pts_bg.shape[0],
+                                                                              pts_sh.shape[0], t_wall, threads),
                 t_step_s=t_step)
 
 
@@ -84,9 +135,22 @@ def main():
         print("bench.py measures one GPU only: the method's multi-GPU sharding is a design note, "
               "not part of this build (got --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
+    if a.copy_probe:
+        import torch
+        src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
+        del src, dst
+    out = dict(dimpled=run_dimpled, spin=run_spin, batch=run_batch, serve=run_serve)[a.workload](a)
+    print(json.dumps(out), flush=True)
+
+
+def run_dimpled(a):
     import torch
     from paper_1711_07663_amd import oc
-    from paper_1711_07663_amd.pipeline import OversetSystem
+    from paper_1711_07663_amd.pipeline import OversetSystem, SlotStep
     from workloads import configs as CF
 
     log("generating the dimpled-sphere workload")
@@ -110,27 +174,61 @@ def main():
     st = counts.pop("stats")
     info = st["bg_cut"]
 
-    log("timed %d steps" % a.steps)
-    lat = []
+    # the plain step: default slot, eager, one chain, synchronous point
+    # counts (the per-instance baseline)
+    log("plain steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(a.steps):
-        ts = time.perf_counter()
         counts = system.step(poses)
         torch.cuda.synchronize()
-        lat.append(time.perf_counter() - ts)
+    ms_plain = 1e3 * (time.perf_counter() - t0) / a.steps
+
+    # the step as served: two chains on two streams, captured once, replayed
+    log("graph-replayed steps, %d timed" % a.steps)
+    ss = SlotStep(system)
+    ss.step(poses)
+    torch.cuda.synchronize()
+    same = ss.snapshot()["ib_bg"].tobytes() == system.ib_bg.cpu().numpy().tobytes()
+    ss.capture()
+    table = ss.pose_table_dev(poses)
+    st_ = ss.stream
+    for _ in range(a.warmup):
+        ss.replay_table(table)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ss.replay_table(table)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
     ms = 1e3 * t_total / a.steps
-
-    # per-kernel HIP-event timing over a second pass of the same steps
-    log("per-kernel event timing over %d steps" % a.steps)
-    ctx.timing(True)
+    evs = []
     for _ in range(a.steps):
-        system.step(poses)
-    rep = ctx.timing_report()
-    ctx.timing(False)
-    per_kernel = {k: dict(total_ms=v[0], launches=v[1], avg_us=1e3 * v[0] / max(v[1], 1)) for k, v in rep.items()}
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(st_)
+        ss.replay_table(table)
+        e1.record(st_)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    lat = [x.elapsed_time(y) * 1e-3 for x, y in evs]
+
+    # per-kernel HIP-event timing (events on the kernel's own stream) over
+    # eager launches of the same step with the two chains one after the
+    # other, so that each kernel has the device to itself; then the same with
+    # the chains overlapped as in the timed steps
+    log("per-kernel event timing over %d steps" % a.steps)
+
+    def kernel_times(serial):
+        ctx.timing(True)
+        for _ in range(a.steps):
+            ss.step(poses, serial=serial)
+        rep = ctx.timing_report()
+        ctx.timing(False)
+        return {k: dict(total_ms=v[0], launches=v[1], avg_us=1e3 * v[0] / max(v[1], 1)) for k, v in rep.items()}
+
+    per_kernel = kernel_times(True)
+    per_kernel_overlapped = kernel_times(False)
 
     n_pts = counts["n_bg_points"] + sum(counts["n_shell_points"])
     value = bg.n_elem / (ms / 1e3)
@@ -142,7 +240,7 @@ def main():
         bytes_per_launch = 25.0 * bg.n_elem
         achieved = bytes_per_launch / (kf["avg_us"] * 1e-6) / 1e9
         roof_filter = dict(bound="hbm", kernel="k_filter", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                           frac=achieved / HBM_PEAK_GBS, traffic=None,
+                           frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic("k_filter"),
                            algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=kf["avg_us"])
     # dominant kernel of the step; when it is the Newton kernel of the donor
     # search (FP64 VALU bound) its algorithmic FLOP per launch is
@@ -156,8 +254,13 @@ def main():
         flop_per_launch = NEWTON_FLOP * iters / launches_per_step
         achieved = flop_per_launch / (kd["avg_us"] * 1e-6) / 1e12
         roof = dict(bound="alu", kernel=dominant, achieved=achieved, peak=FP64_VECTOR_PEAK, unit="TFLOP/s",
-                    frac=achieved / FP64_VECTOR_PEAK, traffic=None, algorithmic_flop_per_launch=flop_per_launch,
+                    frac=achieved / FP64_VECTOR_PEAK, traffic=measured_traffic(dominant),
+                    algorithmic_flop_per_launch=flop_per_launch,
                     newton_iterations_per_step=iters, avg_launch_us=kd["avg_us"])
+        ko = per_kernel_overlapped.get(dominant)
+        if ko:
+            roof["overlapped"] = dict(avg_launch_us=ko["avg_us"],
+                                      achieved=flop_per_launch / (ko["avg_us"] * 1e-6) / 1e12)
     out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
                value=value, unit="elements/s", n_gpus=1, steps=a.steps, warmup=a.warmup, ms_per_step=ms,
                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
@@ -168,15 +271,313 @@ def main():
                            shell_elements=case["bodies"][0]["shell"].n_elem, parallelism="1 GPU"),
                donors_per_s=n_pts / (ms / 1e3), points_per_step=n_pts,
                latency_ms=dict(p50=1e3 * float(np.percentile(lat, 50)), p99=1e3 * float(np.percentile(lat, 99))),
+               plain_ms_per_step=ms_plain, speedup_vs_plain=ms_plain / ms, slot_equals_plain=bool(same),
                cut_info=info, donor_info=dict(bg_to_shell=st["donor_bg"], shell_to_bg=st["donor_shell"]),
-               registration_s=t_reg, per_kernel=per_kernel, roofline=roof, roofline_filter=roof_filter,
+               registration_s=t_reg, per_kernel=per_kernel, per_kernel_overlapped=per_kernel_overlapped,
+               roofline=roof, roofline_filter=roof_filter,
                dominant_kernel=dominant)
     if not a.no_cpu_baseline:
         log("oracle baseline on the host")
         cb = cpu_baseline(case, a.cpu_sample)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
     ctx.close()
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def _percentiles(lat_s):
+    return dict(p50=1e3 * float(np.percentile(lat_s, 50)), p99=1e3 * float(np.percentile(lat_s, 99)))
+
+
+def run_spin(a):
+    """Moving body: cold step at theta_0 = 0, then steps n = 1..N at
+    R_z(2 pi n / 400), each a warm-started background re-cut (sweep bound of
+    one step) plus fringe points and donors in both directions, replayed from
+    two captured graphs (the two iblank parities) with device pose tables."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from paper_1711_07663_amd.pipeline import OversetSystem, SlotStep
+    from workloads import configs as CF
+    log("generating the dimpled-sphere workload")
+    case = CF.dimpled(bg_n=a.bg)
+    bg = case["bg"]
+    torch.cuda.set_device(0)
+    ctx = oc.Context(device=0)
+    system = OversetSystem(ctx, case, bg_points_cap=27 * 40000)
+    poses = [case["poses"][0]] + CF.spinning_poses(a.spin_steps)
+    sid = system.bodies[0]["surf"]
+    sweep = max(ctx.sweep_bound(sid, poses[k], poses[k + 1]) for k in range(len(poses) - 1))
+    ss = SlotStep(system, warm=True, sweep=sweep)
+    tables = [ss.pose_table_dev([p]) for p in poses]
+    st = ss.stream
+
+    def run_sequence(timed):
+        ss.k = 0
+        ss.set_poses([poses[0]])
+        ss._launch(0, True)       # cold step n = 0
+        ss.k = 1
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        for n in range(1, len(poses)):
+            if timed:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e0.record(st)
+            ss.replay_table(tables[n])
+            if timed:
+                e1 = torch.cuda.Event(enable_timing=True)
+                e1.record(st)
+                evs.append((e0, e1))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, evs
+
+    ss.step([poses[0]])
+    torch.cuda.synchronize()
+    ss.capture()
+    log("warmup pass over %d steps" % a.spin_steps)
+    run_sequence(False)
+    log("timed pass")
+    t_total, _ = run_sequence(False)
+    _, evs = run_sequence(True)
+    lat = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs]
+    ms = 1e3 * t_total / a.spin_steps
+    # the plain per-instance GPU step: cold, eager, synchronous (default slot)
+    log("plain per-step baseline")
+    t0 = time.perf_counter()
+    for n in range(1, len(poses)):
+        system.step([poses[n]])
+        torch.cuda.synchronize()
+    ms_plain = 1e3 * (time.perf_counter() - t0) / a.spin_steps
+    # per-kernel event timing over eager warm steps of the same sequence
+    ctx.timing(True)
+    ss.k = 0
+    ss.step([poses[0]])
+    for n in range(1, min(len(poses), 21)):
+        ss.step([poses[n]])
+    rep = ctx.timing_report()
+    ctx.timing(False)
+    per_kernel = {k: dict(total_ms=v[0], launches=v[1], avg_us=1e3 * v[0] / max(v[1], 1)) for k, v in rep.items()}
+    cut = ss.slot.cut_info()
+    out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
+               value=bg.n_elem / (ms / 1e3), unit="elements/s", n_gpus=1, steps=a.spin_steps, warmup=a.spin_steps,
+               ms_per_step=ms, steps_per_s=1e3 / ms, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64", data="synthetic",
+               config=dict(workload="spinning dimpled sphere: the 128^3 dimpled case rotating about z at 1 rev / "
+                                    "400 steps, %d warm-started steps replayed as HIP graphs" % a.spin_steps,
+                           bg_elements=bg.n_elem, sweep_bound=sweep, parallelism="1 GPU"),
+               latency_ms=_percentiles(lat), plain_ms_per_step=ms_plain, speedup_vs_plain=ms_plain / ms,
+               last_warm_cut_info=cut, per_kernel=per_kernel)
+    ctx.close()
+    return out
+
+
+def run_batch(a):
+    """64 uneven instances: every instance's cut in one launch per stage
+    (a slot sized for the batch, captured once as a HIP graph), against the
+    plain per-instance cut (one synchronous oc_cut per instance)."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from workloads import configs as CF
+    from workloads import meshes as M
+    specs = CF.batch_instances(n=a.batch_n)
+    torch.cuda.set_device(0)
+    ctx = oc.Context(device=0)
+    log("generating and registering %d instances" % len(specs))
+    reqs, plain_args, n_tot, n_face = [], [], 0, 0
+    poses = torch.zeros((len(specs), 12), dtype=torch.float64, device="cuda")
+    host_poses = np.stack([np.asarray(sp["pose"], dtype=np.float64) for sp in specs])
+    poses.copy_(torch.from_numpy(host_poses))
+    for i, sp in enumerate(specs):
+        axes = (0.5, 0.35, 0.25) if sp["kind"] == "ellipsoid" else None
+        bgm = M.background_grid(sp["bg_n"], -2.0, 2.0, amp=0.02)
+        surf = M.cube_sphere(sp["m"], R=0.5, axes=axes, dimples=sp["dimples"], dimple_a=CF.DIMPLE_A,
+                             dimple_k=CF.DIMPLE_K)
+        gid = ctx.register_grid(bgm.nodes, bgm.conn)
+        sid = ctx.register_cut_surface(surf.nodes, surf.conn)
+        ib = torch.empty(bgm.n_elem, dtype=torch.int8, device="cuda")
+        reqs.append((gid, [sid], poses[i:i + 1], ib))
+        plain_args.append((gid, sid, host_poses[i], bgm.n_elem))
+        n_tot += bgm.n_elem
+        n_face += surf.n_face
+        del bgm, surf
+    log("batch of %d instances, %d elements, %d faces" % (len(specs), n_tot, n_face))
+    # eager batches on the default slot, before and after autotuning
+    from paper_1711_07663_amd import autotune
+    host_reqs = [(g_, s_, host_poses[i:i + 1], ib_) for i, (g_, s_, _, ib_) in enumerate(reqs)]
+    surf_faces = {}
+    for (gid, sids, _, _), sp in zip(reqs, specs):
+        surf_faces[sids[0]] = 6 * sp["m"] * sp["m"]
+    t_untuned = autotune._time(lambda: ctx.cut_batch(host_reqs), 3)
+    t0 = time.perf_counter()
+    params, tune_report = autotune.tune_batch(ctx, host_reqs, surf_faces)
+    t_tune = time.perf_counter() - t0
+    t_tuned = autotune._time(lambda: ctx.cut_batch(host_reqs), 3)
+    log("autotuned in %.1f s: %s (eager batch %.2f -> %.2f ms)" % (t_tune, params, 1e3 * t_untuned, 1e3 * t_tuned))
+    slot = ctx.create_batch_slot(reqs)
+    for _ in range(a.warmup):
+        slot.cut_batch(reqs)
+    torch.cuda.synchronize()
+    info = slot.cut_info()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        slot.set_stream(torch.cuda.current_stream())
+        slot.cut_batch(reqs)
+    slot.set_stream(slot.stream)
+    st = slot.stream
+    lat = []
+    with torch.cuda.stream(st):
+        for _ in range(a.warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            g.replay()
+            e1.record(st)
+            lat.append((e0, e1))
+        torch.cuda.synchronize()
+        t_batch = (time.perf_counter() - t0) / a.steps
+    lat = [x.elapsed_time(y) * 1e-3 for x, y in lat]
+    batch_out = [r[3].clone() for r in reqs]
+    # plain: one synchronous cut per instance on the default slot
+    plain_ib = [torch.empty_like(r[3]) for r in reqs]
+    for (gid, sid, pz, ne), ib in zip(plain_args, plain_ib):
+        ctx.cut(gid, sid, pz, ib)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, a.steps // 4)):
+        for (gid, sid, pz, ne), ib in zip(plain_args, plain_ib):
+            ctx.cut(gid, sid, pz, ib)
+            torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / max(1, a.steps // 4)
+    same = all(torch.equal(x, y) for x, y in zip(batch_out, plain_ib))
+    # per-kernel event timing of eager batch launches
+    ctx.timing(True)
+    for _ in range(5):
+        slot.cut_batch(reqs)
+    rep = ctx.timing_report()
+    ctx.timing(False)
+    per_kernel = {k: dict(total_ms=v[0], launches=v[1], avg_us=1e3 * v[0] / max(v[1], 1)) for k, v in rep.items()}
+    kf = per_kernel.get("k_filter")
+    roof = None
+    if kf:
+        achieved = 25.0 * n_tot / (kf["avg_us"] * 1e-6) / 1e9
+        roof = dict(bound="hbm", kernel="k_filter", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=25.0 * n_tot,
+                    avg_launch_us=kf["avg_us"])
+    out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
+               value=n_tot / t_batch, unit="elements/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+               ms_per_step=1e3 * t_batch, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload="64 uneven instances from SeedSequence(1711): backgrounds 16^3..96^3 on "
+                                    "[-2,2]^3, sphere / ellipsoid / dimpled bodies of 6 m^2 faces (m 8..64), "
+                                    "random rotation and +-0.3 translation; cut only, one graph-captured batch",
+                           instances=len(specs), total_elements=n_tot, total_faces=n_face, parallelism="1 GPU"),
+               latency_ms=_percentiles(lat), plain_ms=1e3 * t_plain, plain_elements_per_s=n_tot / t_plain,
+               speedup_vs_plain=t_plain / t_batch, batch_equals_plain=bool(same), cut_info=info,
+               autotune=dict(params=params, report=tune_report, seconds=t_tune, eager_ms_untuned=1e3 * t_untuned,
+                             eager_ms_tuned=1e3 * t_tuned),
+               per_kernel=per_kernel, roofline=roof,
+               instance_sizes=[(sp["bg_n"], sp["m"], sp["kind"]) for sp in specs])
+    slot.close()
+    ctx.close()
+    return out
+
+
+def run_serve(a):
+    """Poisson arrivals over four grid sets (tiny case, dimpled case, the
+    spinning ball at a random step, the two-body case on a 160^3 background
+    at a random step), served with continuous batching (slots on their own
+    streams, graph replays, admission by HBM budget), against one-at-a-time
+    service of the same arrival trace on the default slot."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from paper_1711_07663_amd.pipeline import OversetSystem
+    from paper_1711_07663_amd.serve import Server
+    from workloads import configs as CF
+    torch.cuda.set_device(0)
+    ctx = oc.Context(device=0)
+    log("registering the grid sets")
+    tiny, dimp, two = CF.tiny(), CF.dimpled(), CF.two_body()
+    systems = dict(tiny=OversetSystem(ctx, tiny), dimpled=OversetSystem(ctx, dimp, bg_points_cap=27 * 40000),
+                   two_body=OversetSystem(ctx, two, bg_points_cap=27 * 80000))
+    sets = ["tiny", "dimpled", "spin", "two_body"]
+    rng = np.random.default_rng(7663)
+
+    def draw():
+        k = sets[int(rng.integers(0, 4))]
+        if k == "tiny":
+            return "tiny", tiny["poses"]
+        if k == "dimpled":
+            return "dimpled", dimp["poses"]
+        n = int(rng.integers(1, 201))
+        if k == "spin":
+            return "dimpled", [CF.spinning_poses(n)[-1]]
+        return "two_body", CF.two_body_poses(n)
+
+    budget = int(a.budget_gb * (1 << 30))
+    srv = Server(ctx, systems, budget, max_slots=16)
+    log("warming slots")
+    home = dict(tiny=tiny["poses"], dimpled=dimp["poses"], two_body=two["poses"])
+    for _ in range(3):
+        for name in systems:
+            for _ in range(2):
+                srv.submit(name, home[name])
+        srv.drain()
+    torch.cuda.synchronize()
+    rates = [float(x) for x in a.rates.split(",")]
+    results = []
+    for lam in rates:
+        n_req = a.requests
+        gaps = rng.exponential(1.0 / lam, size=n_req)
+        arrivals = np.cumsum(gaps)
+        reqs = [draw() for _ in range(n_req)]
+        for mode in ("served", "one_at_a_time"):
+            log("rate %g req/s, %s, %d requests" % (lam, mode, n_req))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            lat = []
+            if mode == "served":
+                srv.done = []
+                i = 0
+                while i < n_req or srv.queue or srv.busy:
+                    now = time.perf_counter() - t0
+                    while i < n_req and arrivals[i] <= now:
+                        srv.submit(reqs[i][0], reqs[i][1], t_arrival=t0 + arrivals[i])
+                        i += 1
+                    srv.pump()
+                lat = [r["t_done"] - r["t_arrival"] for r in srv.done]
+                t_end = max(r["t_done"] for r in srv.done) - t0
+            else:
+                t_free = 0.0
+                for i in range(n_req):
+                    now = time.perf_counter() - t0
+                    if arrivals[i] > now:
+                        time.sleep(max(0.0, arrivals[i] - now - 2e-4))
+                        while time.perf_counter() - t0 < arrivals[i]:
+                            pass
+                    systems[reqs[i][0]].step(reqs[i][1])
+                    torch.cuda.synchronize()
+                    lat.append(time.perf_counter() - t0 - arrivals[i])
+                t_end = time.perf_counter() - t0
+            results.append(dict(rate=lam, mode=mode, requests=n_req, throughput=n_req / t_end,
+                                latency_ms=_percentiles(lat), mean_ms=1e3 * float(np.mean(lat)),
+                                slots=len(srv.slots) if mode == "served" else 1))
+    served = [r for r in results if r["mode"] == "served"]
+    best = max(served, key=lambda r: r["rate"])
+    out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
+               value=best["throughput"], unit="requests/s", n_gpus=1, steps=a.requests, warmup=6,
+               ms_per_step=1e3 / best["throughput"], higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64", data="synthetic",
+               config=dict(workload="serving: Poisson arrivals at %s req/s over {tiny 16^3 case, dimpled 128^3 "
+                                    "case, spinning ball at a random step, two-body 160^3 case at a random step}, "
+                                    "continuous batching with slots admitted under a %.0f GB budget"
+                                    % (a.rates, a.budget_gb), parallelism="1 GPU"),
+               latency_ms=best["latency_ms"], rates=results, slots=len(srv.slots),
+               hbm_used_gb=srv.used_bytes() / (1 << 30), refused_admissions=srv.n_refused)
+    ctx.close()
+    return out
 
 
 if __name__ == "__main__":
