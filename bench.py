@@ -41,16 +41,29 @@ KERNEL_SOURCE = {"k_dp_newton": "paper_1711_07663_amd/csrc/k_donor.hip",
                  "k_filter": "paper_1711_07663_amd/csrc/k_cut.hip"}
 
 
+def kernel_source_sha(kernel):
+    """SHA-256 of the source text of ``kernel``'s definition (from its
+    ``__global__`` line to the closing brace at column 0)."""
+    import hashlib
+    src = KERNEL_SOURCE.get(kernel)
+    if not src:
+        return None
+    lines = open(os.path.join(ROOT, src)).read().split("\n")
+    start = next((i for i, l in enumerate(lines) if l.startswith("__global__") and (" %s(" % kernel) in l), None)
+    if start is None:
+        return None
+    end = next(i for i in range(start, len(lines)) if lines[i] == "}")
+    return hashlib.sha256("\n".join(lines[start:end + 1]).encode()).hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of ``kernel`` from the committed profiler
     summary profiles/<kernel>_traffic_dimpled128.md (FETCH_SIZE and
     WRITE_SIZE passes scaled by the copy-kernel calibration), or None when
-    there is none or the kernel's source file changed since it was taken
-    (the summary records the source's SHA-256)."""
-    import hashlib
+    there is none or the kernel's definition changed since it was taken
+    (the summary records the SHA-256 of the definition's source text)."""
     path = os.path.join(ROOT, "profiles", "%s_traffic_dimpled128.md" % kernel)
-    src = KERNEL_SOURCE.get(kernel)
-    if not src or not os.path.exists(path):
+    if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
@@ -58,11 +71,10 @@ def measured_traffic(kernel):
             k, v = line[2:].split(":", 1)
             vals[k.strip()] = v.strip().strip("`")
     try:
-        sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
-        if vals.get("source_sha256") != sha:
+        if vals.get("kernel_source_sha256") != kernel_source_sha(kernel):
             return None
         return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError, OSError):
+    except (KeyError, ValueError, OSError, StopIteration):
         return None
 
 
