@@ -6,7 +6,6 @@
 // A call cuts a batch: one or more requests, each a grid cut by one or more
 // surfaces into its own iblank.  Each (grid, surface, pose) is a "cut" with
 // a descriptor (CutInst); every stage is one launch for the whole batch:
-//   k_reset_counters                batch counters, surface boxes
 //   k_pose_faces                    pose the surface nodes, FP32 face boxes
 //                                   inflated by the hit tolerance, surface box
 //   k_bins_setup / k_bin_count /    uniform bins over each surface box, packed
@@ -87,15 +86,6 @@ __device__ inline int item_cut(uint64_t v) { return (int)(v >> 32); }
 __device__ inline int item_elem(uint64_t v) { return (int)(uint32_t)v; }
 
 // ------------------------------------------------------- surface stage ----
-// counters of the batch
-__global__ void k_reset_counters(CutCounters *cnt)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        cnt->n_inbox = cnt->n_near = cnt->n_far = cnt->n_hit = cnt->n_hole = cnt->n_side = 0;
-        cnt->n_cand_pairs = 0ull;
-    }
-}
-
 // a1 + a2 (face boxes): pose the 9 nodes of every face (x' = R x + t), store
 // them face-major, and build the face's FP32 box rounded outward and inflated
 // by tol_hit + 2^-20 * max|coordinate|.  Blocks are flattened over the cuts;
@@ -191,32 +181,39 @@ __device__ inline int block_scan_excl(int v, int *total)
 // and at most 8 bins in total.  One block; the batch's bin total goes to
 // *total.
 __global__ __launch_bounds__(kThreads) void k_bins_setup(const CutInst *__restrict__ I, int n_cut,
-                                                         const int32_t *__restrict__ part, int *total)
+                                                         const int32_t *__restrict__ part, int *total,
+                                                         CutCounters *cnt)
 {
-    int carry = 0;
-    for (int i0 = 0; i0 < n_cut; i0 += kThreads) {
-        const int i = i0 + (int)threadIdx.x;
-        int nb = 0;
-        SurfParams *sp = nullptr;
-        if (i < n_cut) {
-            sp = I[i].params;
+    if (threadIdx.x == 0) cnt->n_inbox = 0;   // k_filter appends after this kernel
+    // surface box and bin grid of every cut: one wavefront per cut folds the
+    // cut's per-block partial boxes
+    const int lane = lane_id(), wid = threadIdx.x >> 6;
+    for (int i = wid; i < n_cut; i += kThreads / 64) {
+        SurfParams *sp = I[i].params;
+        const int b0 = I[i].fblk0, nblk = (int)((I[i].n_face + kThreads - 1) / kThreads);
+        int ob[6] = {f2ord(INFINITY), f2ord(INFINITY), f2ord(INFINITY), f2ord(-INFINITY), f2ord(-INFINITY),
+                     f2ord(-INFINITY)};
+        for (int b = b0 + lane; b < b0 + nblk; b += 64)
+            for (int k = 0; k < 6; ++k) {
+                const int v = part[(int64_t)b * 6 + k];
+                ob[k] = k < 3 ? min(ob[k], v) : max(ob[k], v);
+            }
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const int o = __shfl_xor(ob[k], d, 64);
+                ob[k] = k < 3 ? min(ob[k], o) : max(ob[k], o);
+            }
+        if (lane == 0) {
             const float dmax = I[i].dmax;
             const int nb_max = I[i].nb_max;
-            int ob[6] = {f2ord(INFINITY), f2ord(INFINITY), f2ord(INFINITY), f2ord(-INFINITY), f2ord(-INFINITY),
-                         f2ord(-INFINITY)};
-            const int b0 = I[i].fblk0, nblk = (int)((I[i].n_face + kThreads - 1) / kThreads);
-            for (int b = b0; b < b0 + nblk; ++b)
-                for (int k = 0; k < 6; ++k) {
-                    const int v = part[(int64_t)b * 6 + k];
-                    ob[k] = k < 3 ? min(ob[k], v) : max(ob[k], v);
-                }
             float L = 0.f;
             for (int k = 0; k < 6; ++k) {
                 sp->sbox[k] = ord2f(ob[k]);
                 L = fmaxf(L, fabsf(sp->sbox[k]));
             }
             const float w = (dmax + 2.0f * (1e-7f + ldexpf(L, -20)) + ldexpf(L, -18)) * 1.001f;
-            nb = 1;
+            int nb = 1;
             for (int a = 0; a < 3; ++a) {
                 float ext = sp->sbox[3 + a] - sp->sbox[a];
                 int n = 1;
@@ -231,19 +228,19 @@ __global__ __launch_bounds__(kThreads) void k_bins_setup(const CutInst *__restri
             }
             sp->n_bins = nb;
         }
+    }
+    __syncthreads();
+    // each cut's first bin in the batch's bin arrays
+    int carry = 0;
+    for (int i0 = 0; i0 < n_cut; i0 += kThreads) {
+        const int i = i0 + (int)threadIdx.x;
+        const int nb = i < n_cut ? I[i].params->n_bins : 0;
         int tot;
         const int off = block_scan_excl(nb, &tot);
-        if (sp) sp->bin_off = carry + off;
+        if (i < n_cut) I[i].params->bin_off = carry + off;
         carry += tot;
     }
     if (threadIdx.x == 0) *total = carry;
-}
-
-__global__ __launch_bounds__(kThreads) void k_zero_i32(int32_t *p, const int *n_dev, int64_t n_host)
-{
-    const int64_t n = n_dev ? (int64_t)*n_dev + 1 : n_host;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0;
 }
 
 __device__ inline void box_bins(const BinGrid &G, const float *b, int *lo, int *hi)
@@ -401,12 +398,18 @@ struct WalkLds {
 // round are issued by the whole wavefront at once.  fn(face, xyz) is called
 // with the same trip count on every lane (face < 0 on idle lanes) and may use
 // wavefront operations; it returns true (wave-uniformly) to stop the walk.
-// Requires a one-wavefront workgroup.
+// The walk synchronises its workgroup: every wavefront of the workgroup must
+// walk the same range R (each with its own WalkLds), and only a one-wavefront
+// workgroup may stop early.
+// With nparts > 1 only the chunks of 64 stored faces whose running index is
+// part (mod nparts) are visited, so nparts wavefronts can share one walk.
 template <class Fn>
 __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int32_t *__restrict__ bstart,
-                                  const int32_t *__restrict__ bitems, WalkLds &L, Fn &&fn)
+                                  const int32_t *__restrict__ bitems, WalkLds &L, Fn &&fn, int part = 0,
+                                  int nparts = 1)
 {
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int chunk = 0;
     for (int r = 0; r < R.total; r += 64) {
         const int idx = r + lane;
         int cnt = 0, j0 = 0, packed = 0;
@@ -429,7 +432,8 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
         L.j0[lane] = j0;
         L.xyz[lane] = packed;
         __syncthreads();
-        for (int k0 = 0; k0 < total; k0 += 64) {
+        for (int k0 = 0; k0 < total; k0 += 64, ++chunk) {
+            if (chunk % nparts != part) continue;
             const int k = k0 + lane;
             int face = -1, xyz[3] = {0, 0, 0};
             if (k < total) {
@@ -629,7 +633,10 @@ struct ExactArgs {
     const uint64_t *list_inbox;
     uint8_t *stat;              // k_hit takes ST_NEAR items, k_side ST_SIDE items
     const CutCounters *cnt;
+    unsigned long long *side;   // per in-box item: [2 i] upper bound U, [2 i + 1] nearest distance (bits)
 };
+
+constexpr int kSideParts = 4;   // wavefronts sharing one side item's walks
 
 constexpr int kFaceCap = 256;
 constexpr int kGroup = 8;   // candidate faces tested together by k_hit
@@ -788,69 +795,139 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         if (lane == 0) {
             a.stat[item] = hit ? ST_HIT : ST_SIDE;
             if (hit && c.kind == OC_SURF_WALL) c.iblank[e] = OC_HOLE;
+            if (!hit) a.side[2 * (int64_t)item] = a.side[2 * (int64_t)item + 1] = 0x7FF0000000000000ull;
         }
     }
 }
 
 // a5: near elements that the surface does not intersect lie on one side of
 // it; that side is the nearest-face side of the element's first node:
-// wavefront minimum of the point-to-triangle distance over the binned faces,
-// then the tie rule (largest |dot| of the unit point-to-surface vector with
-// the outward triangle normal; normals averaged only for equally visible
-// triangles of opposite sign).
-__global__ __launch_bounds__(64) void k_side(ExactArgs a)
+// minimum of the point-to-triangle distance over the binned faces, then the
+// tie rule (largest |dot| of the unit point-to-surface vector with the
+// outward triangle normal; normals averaged only for equally visible
+// triangles of opposite sign).  Three kernels: an upper bound U and the
+// nearest distance are each computed by kSideParts wavefronts per element
+// (every wavefront takes every kSideParts-th chunk of faces and they meet
+// in a 64-bit atomic minimum per element: distances are non-negative, so
+// their bit patterns order like the values), then one wavefront per element
+// collects the tie set and decides the side.
+__device__ inline void side_item(const ExactArgs &a, int item, int &e, const CutInst *&cp, d3 &p)
 {
-    __shared__ TieRec rec[128];
+    const uint64_t it = a.list_inbox[item];
+    e = item_elem(it);
+    cp = &a.insts[item_cut(it)];
+    const double *X = cp->enodes + (int64_t)e * 81;
+    p = mk(X[0], X[27], X[54]);
+}
+
+__global__ __launch_bounds__(64) void k_side_bound(ExactArgs a)
+{
     __shared__ WalkLds L;
-    const int lane = threadIdx.x;
     const int n_in = a.cnt->n_inbox;
-    for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
+    for (int w = blockIdx.x; w < n_in * kSideParts; w += gridDim.x) {
+        const int item = w / kSideParts, part = w - kSideParts * item;
         if (a.stat[item] != ST_SIDE) continue;
-        const uint64_t it = a.list_inbox[item];
-        const int ci = item_cut(it), e = item_elem(it);
-        const CutInst &c = a.insts[ci];
+        int e;
+        const CutInst *cp;
+        d3 p;
+        side_item(a, item, e, cp, p);
+        const CutInst &c = *cp;
         const BinGrid G = c.params->grid;
         const int32_t *bstart = a.bin_start + c.params->bin_off;
         const float *__restrict__ fboxc = c.fbox;
         const double *__restrict__ pnodes = c.pnodes;
-        const double *X = c.enodes + (int64_t)e * 81;
-        const d3 p = mk(X[0], X[27], X[54]);
         float eb[6];
         for (int k = 0; k < 6; ++k) eb[k] = c.ebox[(int64_t)k * c.stride + e];
-        // upper bound: nearest of the element's candidate faces
+        // upper bound: nearest node of the element's candidate faces (every
+        // face node lies on the surface, so its distance bounds the nearest
+        // distance from above; it only sizes the exact search)
         double u = INFINITY;
-        {
-            int lo[3], hi[3];
-            box_bins(G, eb, lo, hi);
-            const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
-                if (f >= 0) {
-                    const float *fb = fboxc + (int64_t)f * 6;
-                    if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb) && point_box_dist(p, fb) < u)
-                        u = fmin(u, point_face_dist(p, pnodes + (int64_t)f * 27));
+        int lo[3], hi[3];
+        box_bins(G, eb, lo, hi);
+        const BinRange R = make_range(lo, hi);
+        walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
+            if (f >= 0) {
+                const float *fb = fboxc + (int64_t)f * 6;
+                if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb) && point_box_dist(p, fb) < u) {
+                    const double *P = pnodes + (int64_t)f * 27;
+                    double d2 = INFINITY;
+                    for (int k = 0; k < 9; ++k) {
+                        const double dx = P[k] - p.x, dy = P[9 + k] - p.y, dz = P[18 + k] - p.z;
+                        d2 = fmin(d2, dx * dx + dy * dy + dz * dz);
+                    }
+                    u = fmin(u, sqrt(d2));
                 }
-                u = wave_min_d(u);   // every lane prunes with the wavefront's best so far
-                return false;
-            });
-        }
-        const double U = wave_min_d(u);
+            }
+            u = wave_min_d(u);
+            return false;
+        }, part, kSideParts);
+        u = wave_min_d(u);
+        if (threadIdx.x == 0 && u < INFINITY)
+            atomicMin(&a.side[2 * (int64_t)item], (unsigned long long)__double_as_longlong(u));
+    }
+}
+
+__global__ __launch_bounds__(64) void k_side_near(ExactArgs a)
+{
+    __shared__ WalkLds L;
+    const int n_in = a.cnt->n_inbox;
+    for (int w = blockIdx.x; w < n_in * kSideParts; w += gridDim.x) {
+        const int item = w / kSideParts, part = w - kSideParts * item;
+        if (a.stat[item] != ST_SIDE) continue;
+        int e;
+        const CutInst *cp;
+        d3 p;
+        side_item(a, item, e, cp, p);
+        const CutInst &c = *cp;
+        const BinGrid G = c.params->grid;
+        const int32_t *bstart = a.bin_start + c.params->bin_off;
+        const float *__restrict__ fboxc = c.fbox;
+        const double *__restrict__ pnodes = c.pnodes;
+        const double U = __longlong_as_double((long long)a.side[2 * (int64_t)item]);
         // every face whose box is within U of the node
         double best = U;
-        {
-            int lo[3], hi[3];
-            query_bins(G, p, U, lo, hi);
-            const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
-                if (f >= 0) {
-                    const float *fb = fboxc + (int64_t)f * 6;
-                    if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
-                        best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
-                }
-                best = wave_min_d(best);
-                return false;
-            });
-        }
+        int lo[3], hi[3];
+        query_bins(G, p, U, lo, hi);
+        const BinRange R = make_range(lo, hi);
+        walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
+            if (f >= 0) {
+                const float *fb = fboxc + (int64_t)f * 6;
+                if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
+                    best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
+            }
+            best = wave_min_d(best);
+            return false;
+        }, part, kSideParts);
         best = wave_min_d(best);
+        if (threadIdx.x == 0)
+            atomicMin(&a.side[2 * (int64_t)item + 1], (unsigned long long)__double_as_longlong(best));
+    }
+}
+
+// Tie stage: one workgroup of kSideParts wavefronts per element, each taking
+// every kSideParts-th chunk of the faces within the tie radius; their valid
+// records are gathered in LDS and merged by one thread (the tie order is a
+// total order on (|dot|, face, triangle), so the merge order does not
+// matter).
+__global__ __launch_bounds__(64 * kSideParts) void k_side(ExactArgs a)
+{
+    __shared__ TieRec rec[kSideParts * 128];
+    __shared__ int nrec[kSideParts];
+    __shared__ WalkLds L[kSideParts];
+    const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+    const int n_in = a.cnt->n_inbox;
+    for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
+        if (a.stat[item] != ST_SIDE) continue;
+        int e;
+        const CutInst *cp;
+        d3 p;
+        side_item(a, item, e, cp, p);
+        const CutInst &c = *cp;
+        const BinGrid G = c.params->grid;
+        const int32_t *bstart = a.bin_start + c.params->bin_off;
+        const float *__restrict__ fboxc = c.fbox;
+        const double *__restrict__ pnodes = c.pnodes;
+        const double best = __longlong_as_double((long long)a.side[2 * (int64_t)item + 1]);
         // tie set within best * (1 + 1e-9)
         const double thr = best * (1.0 + 1e-9);
         TieRec b1, b2;
@@ -859,7 +936,7 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
             int lo[3], hi[3];
             query_bins(G, p, thr, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
+            walk_faces(G, R, bstart, a.bitems, L[part], [&](int f, const int *xyz) {
                 if (f >= 0) {
                     const float *fb = fboxc + (int64_t)f * 6;
                     if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= thr) {
@@ -890,22 +967,28 @@ __global__ __launch_bounds__(64) void k_side(ExactArgs a)
                     }
                 }
                 return false;
-            });
+            }, part, kSideParts);
         }
+        // gather the valid records of each wavefront (b2 valid implies b1 valid)
+        const unsigned long long m1 = __ballot(b1.valid), m2 = __ballot(b2.valid);
+        const unsigned long long below = (1ull << lane) - 1ull;
+        const int n1 = __popcll(m1);
+        TieRec *R0 = rec + 128 * part;
+        if (b1.valid) R0[__popcll(m1 & below)] = b1;
+        if (b2.valid) R0[n1 + __popcll(m2 & below)] = b2;
+        if (lane == 0) nrec[part] = n1 + __popcll(m2);
         __syncthreads();
-        rec[2 * lane] = b1;
-        rec[2 * lane + 1] = b2;
-        __syncthreads();
-        if (lane == 0) {
+        if (threadIdx.x == 0) {
             TieRec c1, c2;
             c1.valid = c2.valid = 0;
-            for (int k = 0; k < 128; ++k)
-                if (rec[k].valid) tie_offer(c1, c2, rec[k]);
+            for (int w = 0; w < kSideParts; ++w)
+                for (int k = 0; k < nrec[w]; ++k) tie_offer(c1, c2, rec[128 * w + k]);
             double sg = c1.dot;
             if (c2.valid && c1.absdot - c2.absdot <= 1e-9 && ((c1.dot > 0.0) != (c2.dot > 0.0)))
                 sg = c1.vx * (c1.nx + c2.nx) + c1.vy * (c1.ny + c2.ny) + c1.vz * (c1.nz + c2.nz);
             if (c1.valid && sg < 0.0) c.iblank[e] = OC_HOLE;
         }
+        __syncthreads();
     }
 }
 
@@ -1223,13 +1306,12 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
     int32_t *n_bins_dev = sl->scalar + 4;
     if (n_cut) OC_TRY(put_bytes(sl, sl->insts, I.data(), sizeof(CutInst) * I.size()));
     if (fill_blk || ov_blk) OC_TRY(put_bytes(sl, sl->outs, O.data(), sizeof(CutOut) * O.size()));
-    LAUNCH(k_reset_counters, dim3(1), dim3(64), sl->counters);
     if (fill_blk) LAUNCH(k_fill_field, dim3((unsigned)fill_blk), dim3(kThreads), sl->outs, n_out);
     if (n_cut) {
         LAUNCH(k_pose_faces, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->sbox_part);
-        LAUNCH(k_bins_setup, dim3(1), dim3(kThreads), sl->insts, n_cut, sl->sbox_part, n_bins_dev);
-        LAUNCH(k_zero_i32, dim3(grid_for(need.bins + 1, kThreads, 4096)), dim3(kThreads), sl->bin_count, n_bins_dev,
-               (int64_t)0);
+        // the bin counts are zero here: zeroed when the slot's arrays were
+        // made, and k_bin_fill takes every count back to zero
+        LAUNCH(k_bins_setup, dim3(1), dim3(kThreads), sl->insts, n_cut, sl->sbox_part, n_bins_dev, sl->counters);
         LAUNCH(k_bin_count, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_count);
         OC_TRY(scan_exclusive(ctx, st, sl->bin_count, sl->bin_start, need.bins, n_bins_dev, sl->bin_scan_tmp));
         LAUNCH(k_bin_fill, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_start, sl->bin_count,
@@ -1244,8 +1326,11 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         ea.list_inbox = sl->l_inbox;
         ea.stat = sl->l_stat;
         ea.cnt = sl->counters;
+        ea.side = sl->l_side;
         LAUNCH(k_hit, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
-        LAUNCH(k_side, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
+        LAUNCH(k_side_bound, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
+        LAUNCH(k_side_near, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
+        LAUNCH(k_side, dim3((unsigned)std::max(1, ctx->exact_waves / kSideParts)), dim3(64 * kSideParts), ea);
         LAUNCH(k_ray, dim3((unsigned)ctx->exact_waves), dim3(64), sl->insts, sl->bin_start, sl->bin_items,
                sl->l_inbox, sl->l_stat, sl->counters);
         LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_inbox, sl->counters);

@@ -486,6 +486,7 @@ struct DonorArgs {
     int32_t *cnt;          // [cap + 1] candidates per point
     int32_t *off;          // [cap + 1] exclusive scan of cnt
     int32_t *best;         // [cap] lowest containing element id
+    int32_t *cache;        // [cap][kCandCache] first candidates of each point (ascending id)
     int32_t *pair_pt;      // [pair_cap]
     int32_t *pair_el;      // [pair_cap]
     double *pair_xi;       // [pair_cap][3] reference coordinates of contained pairs
@@ -498,6 +499,8 @@ struct DonorArgs {
     int pad;
 };
 
+constexpr int kCandCache = 4;   // candidates per point kept by k_dp_count for k_dp_fill
+
 __device__ inline int64_t donor_points(const DonorArgs &a)
 {
     return a.n_dev ? ((int64_t)*a.n_dev < a.cap ? (int64_t)*a.n_dev : a.cap) : a.cap;
@@ -507,21 +510,22 @@ __device__ inline int64_t donor_points(const DonorArgs &a)
 // (64 / lanes points per wavefront): the group's lanes take the bin's
 // entries in turn, so a point whose bin holds many boxes is searched in
 // parallel while points with small bins share a wavefront.
-__device__ inline int group_sum(int v, int lanes)
-{
-    for (int d = lanes >> 1; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    return v;
-}
-
+//
 // a10: per point, the registration-frame position (inverse pose, the rigid
-// motion of Sec. 4.3), its bin, and the number of elements of the bin whose
-// control-net box contains it.
+// motion of Sec. 4.3), its bin, the number of elements of the bin whose
+// control-net boxes contain it, and the first kCandCache of them.
 __global__ __launch_bounds__(kT) void k_dp_count(DonorArgs a)
 {
     const int64_t n = donor_points(a);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_eff = (int32_t)n;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *a.n_eff = (int32_t)n;
+        a.dcnt->n_points = (unsigned long long)n;
+        a.dcnt->n_newton = a.dcnt->n_iter = a.dcnt->n_orphan = 0ull;
+    }
     const Pose pose = *a.pose;
     const int L = a.lanes, lane = threadIdx.x & 63, sub = lane & (L - 1);
+    const unsigned long long gmask = (L == 64 ? ~0ull : ((1ull << L) - 1ull)) << (lane & ~(L - 1));
+    const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t ppw = 64 / L;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
@@ -536,10 +540,23 @@ __global__ __launch_bounds__(kT) void k_dp_count(DonorArgs a)
                 a.plocal[3 * i + 2] = p.z;
             }
             const int64_t b = point_bin(a.G, p);
-            const int j1 = a.bstart[b + 1];
-            for (int j = a.bstart[b] + sub; j < j1; j += L) c += cand_has(a.cbox, a.obox, a.bitems[j], p);
+            const int j0 = a.bstart[b], j1 = a.bstart[b + 1];
+            // the group takes the bin's entries L at a time, in order, and
+            // keeps the first kCandCache candidates (ascending element id)
+            for (int r = j0; r < j1; r += L) {
+                const int j = r + sub;
+                int e = -1;
+                bool has = false;
+                if (j < j1) {
+                    e = a.bitems[j];
+                    has = cand_has(a.cbox, a.obox, e, p);
+                }
+                const unsigned long long m = __ballot(has) & gmask;
+                const int at = c + __popcll(m & below);
+                if (has && at < kCandCache) a.cache[i * kCandCache + at] = e;
+                c += __popcll(m);
+            }
         }
-        c = group_sum(c, L);
         if (i < n && sub == 0) {
             a.cnt[i] = c;
             a.best[i] = 0x7fffffff;
@@ -563,10 +580,20 @@ __global__ __launch_bounds__(kT) void k_dp_fill(DonorArgs a)
     for (int64_t base = wave * ppw; base < n; base += n_waves * ppw) {
         const int64_t i = base + lane / L;
         if (i >= n) continue;
+        int64_t q = a.off[i];
+        const int nc = a.cnt[i];
+        if (nc <= kCandCache) {
+            // the candidates k_dp_count kept
+            for (int k = sub; k < nc; k += L)
+                if (q + k < a.pair_cap) {
+                    a.pair_pt[q + k] = (int32_t)i;
+                    a.pair_el[q + k] = a.cache[i * kCandCache + k];
+                }
+            continue;
+        }
         const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
         const int64_t b = point_bin(a.G, p);
         const int j0 = a.bstart[b], j1 = a.bstart[b + 1];
-        int64_t q = a.off[i];
         for (int r = j0; r < j1; r += L) {
             const int j = r + sub;
             int e = -1;
@@ -592,6 +619,7 @@ __global__ __launch_bounds__(kT) void k_dp_newton(DonorArgs a)
 {
     const int64_t n = *a.n_eff;
     const int64_t tot = a.off[n] < a.pair_cap ? (int64_t)a.off[n] : a.pair_cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.dcnt->n_newton, (unsigned long long)tot);
     for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
         const int i = a.pair_pt[q], e = a.pair_el[q];
         const d3 p = mk(a.plocal[3 * (int64_t)i], a.plocal[3 * (int64_t)i + 1], a.plocal[3 * (int64_t)i + 2]);
@@ -686,15 +714,6 @@ __global__ __launch_bounds__(kT) void k_donor_stats(DonorArgs a)
 __global__ void k_donor_stats_reset(DonorCounters *c)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) c->n_iter = c->n_orphan = 0ull;
-}
-
-__global__ void k_dp_newton_count(DonorArgs a)
-{
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const int64_t n = *a.n_eff;
-        a.dcnt->n_points = (unsigned long long)n;
-        a.dcnt->n_newton += (unsigned long long)(a.off[n] < a.pair_cap ? (int64_t)a.off[n] : a.pair_cap);
-    }
 }
 
 __global__ void k_donor_reset(DonorCounters *c)
@@ -832,9 +851,11 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
 {
     oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
-    LAUNCH(k_donor_reset, dim3(1), dim3(64), sl->dcounters);
     sl->last_donor_args.clear();
-    if (cap <= 0) return OC_OK;
+    if (cap <= 0) {
+        LAUNCH(k_donor_reset, dim3(1), dim3(64), sl->dcounters);
+        return OC_OK;
+    }
     OC_TRY(slot_reserve_points(sl, cap));
     DonorArgs a;
     a.enodes = g.enodes;
@@ -853,6 +874,7 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     a.cnt = sl->dp_cnt;
     a.off = sl->dp_off;
     a.best = sl->dp_best;
+    a.cache = sl->dp_cache;
     a.pair_pt = sl->dpair_pt;
     a.pair_el = sl->dpair_el;
     a.pair_xi = sl->dpair_xi;
@@ -868,7 +890,6 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     LAUNCH(k_dp_count, dim3(gw), dim3(kT), a);
     OC_TRY(scan_exclusive(ctx, st, sl->dp_cnt, sl->dp_off, cap, a.n_eff, sl->dp_scan_tmp));
     LAUNCH(k_dp_fill, dim3(gw), dim3(kT), a);
-    LAUNCH(k_dp_newton_count, dim3(1), dim3(64), a);
     LAUNCH(k_dp_newton, dim3(std::min<unsigned>(blocks(sl->dpair_cap, kT), 16384u)), dim3(kT), a);
     LAUNCH(k_dp_final, dim3(gp), dim3(kT), a);
     OC_HIP(hipGetLastError());

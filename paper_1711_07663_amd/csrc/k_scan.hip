@@ -115,6 +115,61 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *__re
     }
 }
 
+// Scan-and-apply that finds its tile's offset itself (the sum of the tile
+// sums before it, and block 0 also the total): with few tiles this saves the
+// separate tile-scan launch.
+__device__ inline int block_sum(int v)
+{
+    __shared__ int bs[kScanThreads / 64];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) bs[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int t = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / 64; ++w) t += bs[w];
+    return t;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply_direct(const int32_t *__restrict__ in,
+                                                                    int32_t *__restrict__ out, const int *n_dev,
+                                                                    int64_t n_host, const int32_t *__restrict__ tsum,
+                                                                    int nt)
+{
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_host;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    if (blockIdx.x == 0) {
+        int pt = 0;
+        for (int t = threadIdx.x; t < nt; t += kScanThreads) pt += tsum[t];
+        const int tot = block_sum(pt);
+        if (threadIdx.x == 0) out[n] = tot;
+    }
+    if (base >= n) return;
+    int pp = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += kScanThreads) pp += tsum[t];
+    const int pre = block_sum(pp);
+    int v[kScanItems];
+    int s = 0;
+    const int64_t my = base + (int64_t)threadIdx.x * kScanItems;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = my + k;
+        v[k] = i < n ? in[i] : 0;
+        s += v[k];
+    }
+    int tot;
+    int run = block_excl_scan(s, &tot) + pre;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = my + k;
+        if (i < n) out[i] = run;
+        run += v[k];
+    }
+}
+
+constexpr int kScanDirectMaxTiles = 1024;
+
 int64_t scan_tmp_ints(int64_t cap) { return (cap + kScanTile - 1) / kScanTile + 1; }
 
 oc_status scan_exclusive(oc_ctx *ctx, hipStream_t st, const int32_t *in, int32_t *out, int64_t cap,
@@ -129,9 +184,14 @@ oc_status scan_exclusive(oc_ctx *ctx, hipStream_t st, const int32_t *in, int32_t
     size_t slot;
     time_begin(ctx, st, "scan", &slot);
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nt), dim3(kScanThreads), 0, st, in, n_dev, cap, tmp);
-    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tmp, (int)nt);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(kScanThreads), 0, st, in, out, n_dev, cap, tmp,
-                       (int)nt);
+    if (nt <= kScanDirectMaxTiles) {
+        hipLaunchKernelGGL(k_scan_apply_direct, dim3((unsigned)nt), dim3(kScanThreads), 0, st, in, out, n_dev, cap,
+                           tmp, (int)nt);
+    } else {
+        hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tmp, (int)nt);
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nt), dim3(kScanThreads), 0, st, in, out, n_dev, cap, tmp,
+                           (int)nt);
+    }
     time_end(ctx, st, slot);
     OC_HIP(hipGetLastError());
     return OC_OK;

@@ -92,6 +92,7 @@ static oc_status slot_alloc_cut(oc_slot *sl, CutCaps c)
     OC_TRY(dev_alloc(ctx, o, sizeof(uint64_t) * (size_t)c.elem_inst, (void **)&sl->l_inbox));
     OC_TRY(dev_alloc(ctx, o, sizeof(uint8_t) * (size_t)c.elem_inst, (void **)&sl->l_stat));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)c.elem_inst, (void **)&sl->l_ncand));
+    OC_TRY(dev_alloc(ctx, o, sizeof(unsigned long long) * 2 * (size_t)c.elem_inst, (void **)&sl->l_side));
     // face blocks of 256 faces, plus one spare block per cut
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * 6 * (size_t)(c.faces / 256 + 2 * c.cuts + 1),
                      (void **)&sl->sbox_part));
@@ -104,6 +105,8 @@ static oc_status slot_alloc_cut(oc_slot *sl, CutCaps c)
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)(c.bins + 1), (void **)&sl->bin_start));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * 8 * (size_t)c.faces, (void **)&sl->bin_items));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)scan_tmp_ints(c.bins + 1), (void **)&sl->bin_scan_tmp));
+    // bin counts start at zero; every cut returns them to zero
+    OC_HIP(hipMemset(sl->bin_count, 0, sizeof(int32_t) * (size_t)(c.bins + 1)));
     sl->cc = c;
     return OC_OK;
 }
@@ -151,6 +154,7 @@ static oc_status slot_alloc_points(oc_slot *sl, int64_t cap)
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * (cap + 1), (void **)&sl->dp_cnt));
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * (cap + 1), (void **)&sl->dp_off));
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * cap, (void **)&sl->dp_best));
+    OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * 4 * cap, (void **)&sl->dp_cache));
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * scan_tmp_ints(cap), (void **)&sl->dp_scan_tmp));
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * pc, (void **)&sl->dpair_pt));
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * pc, (void **)&sl->dpair_el));
@@ -544,7 +548,7 @@ static oc_status read_cut_info(oc_slot *sl, oc_cut_info *info)
     OC_HIP(hipMemcpyAsync(&c, sl->counters, sizeof c, hipMemcpyDeviceToHost, sl->stream));
     OC_HIP(hipStreamSynchronize(sl->stream));
     info->n_elem = sl->last_n_elem;
-    info->n_inbox = c.n_inbox;
+    info->n_inbox = sl->last_n_cut > 0 ? c.n_inbox : 0;
     info->n_near = c.n_near;
     info->n_far = c.n_far;
     info->n_hit = c.n_hit;

@@ -178,6 +178,7 @@ struct oc_slot {
     int64_t dpt_cap = 0, dpair_cap = 0;
     double *dp_local = nullptr;
     int32_t *dp_cnt = nullptr, *dp_off = nullptr, *dp_best = nullptr, *dp_scan_tmp = nullptr;
+    int32_t *dp_cache = nullptr;       // [cap][4] first candidates per point
     int32_t *dpair_pt = nullptr, *dpair_el = nullptr;
     double *dpair_xi = nullptr;
     uint8_t *dpair_it = nullptr;
@@ -187,6 +188,7 @@ struct oc_slot {
     uint64_t *l_inbox = nullptr;       // in-box items (cut << 32 | element)
     uint8_t *l_stat = nullptr;         // status per in-box item
     int32_t *l_ncand = nullptr;        // candidate faces per in-box item
+    unsigned long long *l_side = nullptr; // per in-box item: side search bound and distance (bits)
     int32_t *sbox_part = nullptr;      // per face block: partial surface box (ordered ints)
     int last_n_cut = 0, last_n_out = 0, last_cblk = 0;
     std::vector<oc::CutOut> last_outs;

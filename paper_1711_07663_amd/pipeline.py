@@ -129,7 +129,7 @@ class SlotStep:
          donors in the background.
     Chain B forks from A's stream after the pose upload and joins it at the
     end, so the latency-bound cut kernels of A overlap B's donor search (also
-    inside a captured graph).
+    inside a captured graph).  Chain A, the longer one, is issued first.
 
     Device pose table rows: [0, nb) body poses (background cut; shell receptor
     points and bg->shell searches); then for body i the poses of the other
@@ -206,16 +206,6 @@ class SlotStep:
         ib_bg = bufs[k % len(bufs)]
         ident = self.poses_dev[self.n_pose - 1]
         side.wait_stream(main)
-        # chain B: shells
-        r = nb
-        for i, b in enumerate(s.bodies):
-            others = [sids[j] for j in range(nb) if j != i]
-            ob = o["bodies"][i]
-            sb.cut(b["shell"], others, self.poses_dev[r:r + nb - 1], ob["ib"])
-            r += nb - 1
-            cap = ob["pts"].shape[0]
-            sb.fringe_points(b["shell"], self.poses_dev[i], ob["ib"], ob["pts"], self.n_dev[1 + i:2 + i], ob["src"])
-            sb.donor_search(s.bg_id, ident, ob["pts"], cap, self.n_dev[1 + i:2 + i], ob["donor"], ob["ref"])
         # chain A: background
         if self.warm and not cold:
             sa.cut_warm(s.bg_id, sids[0], self.poses_dev[0], self.sweep, bufs[(k - 1) % 2], ib_bg)
@@ -226,6 +216,16 @@ class SlotStep:
         for i, b in enumerate(o["bodies"]):
             sa.donor_search(s.bodies[i]["shell"], self.poses_dev[i], o["pts_bg"], cap_bg, self.n_dev[0:1],
                             b["donor_bg"], b["ref_bg"])
+        # chain B: shells
+        r = nb
+        for i, b in enumerate(s.bodies):
+            others = [sids[j] for j in range(nb) if j != i]
+            ob = o["bodies"][i]
+            sb.cut(b["shell"], others, self.poses_dev[r:r + nb - 1], ob["ib"])
+            r += nb - 1
+            cap = ob["pts"].shape[0]
+            sb.fringe_points(b["shell"], self.poses_dev[i], ob["ib"], ob["pts"], self.n_dev[1 + i:2 + i], ob["src"])
+            sb.donor_search(s.bg_id, ident, ob["pts"], cap, self.n_dev[1 + i:2 + i], ob["donor"], ob["ref"])
         if serial:
             sb.set_stream(sb.stream)
         else:
