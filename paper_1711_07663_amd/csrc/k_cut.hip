@@ -88,39 +88,55 @@ __device__ inline int item_elem(uint64_t v) { return (int)(uint32_t)v; }
 // ------------------------------------------------------- surface stage ----
 // a1 + a2 (face boxes): pose the 9 nodes of every face (x' = R x + t), store
 // them face-major, and build the face's FP32 box rounded outward and inflated
-// by tol_hit + 2^-20 * max|coordinate|.  Blocks are flattened over the cuts;
-// each block writes the box of its faces to part[block] (ordered ints), and
-// k_bins_setup reduces a cut's blocks (no contended atomics).
+// by tol_hit + 2^-20 * max|coordinate|.  A face takes a group of 16 lanes,
+// one node per lane (lanes 9..15 idle), so the gathers of a face's nodes are
+// issued together; the face box is reduced within the group.  Blocks hold
+// kPoseFaces faces and are flattened over the cuts (pblk0); each block writes
+// the box of its faces to part[block] (ordered ints) and k_bins_setup reduces
+// a cut's blocks (no contended atomics).
+constexpr int kPoseFaces = kThreads / 16;
+
 __global__ __launch_bounds__(kThreads) void k_pose_faces(const CutInst *__restrict__ I, int n_cut,
                                                          int32_t *__restrict__ part)
 {
     __shared__ float wb[kThreads / 64][6];
-    const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].fblk0; });
+    const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].pblk0; });
     const CutInst &c = I[ci];
     const double *__restrict__ nodes = c.snodes;
     const int32_t *__restrict__ conn = c.conn;
     const int64_t n_nodes = c.n_nodes, n_face = c.n_face;
     double *__restrict__ pnodes = c.pnodes;
     float *__restrict__ fbox = c.fbox;
-    SurfParams *sp = c.params;
-    (void)sp;
     const Pose pose = *c.pose;
-    const int64_t f = (int64_t)(blockIdx.x - c.fblk0) * blockDim.x + threadIdx.x;
-    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    if (f < n_face) {
-        double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        double L = 0.0;
-        for (int k = 0; k < 9; ++k) {
-            int id = conn[f * 9 + k];
-            d3 x = pose_apply(pose, mk(nodes[id], nodes[n_nodes + id], nodes[2 * n_nodes + id]));
-            pnodes[f * 27 + k] = x.x;
-            pnodes[f * 27 + 9 + k] = x.y;
-            pnodes[f * 27 + 18 + k] = x.z;
-            blo[0] = fmin(blo[0], x.x); bhi[0] = fmax(bhi[0], x.x);
-            blo[1] = fmin(blo[1], x.y); bhi[1] = fmax(bhi[1], x.y);
-            blo[2] = fmin(blo[2], x.z); bhi[2] = fmax(bhi[2], x.z);
-            L = fmax(L, fmax(fabs(x.x), fmax(fabs(x.y), fabs(x.z))));
+    const int j = threadIdx.x & 15;
+    const int64_t f = (int64_t)(blockIdx.x - c.pblk0) * kPoseFaces + (threadIdx.x >> 4);
+    const bool on = f < n_face && j < 9;
+    double xv[3] = {0.0, 0.0, 0.0};
+    if (on) {
+        const int id = conn[f * 9 + j];
+        const d3 x = pose_apply(pose, mk(nodes[id], nodes[n_nodes + id], nodes[2 * n_nodes + id]));
+        xv[0] = x.x;
+        xv[1] = x.y;
+        xv[2] = x.z;
+        pnodes[f * 27 + j] = x.x;
+        pnodes[f * 27 + 9 + j] = x.y;
+        pnodes[f * 27 + 18 + j] = x.z;
+    }
+    double blo[3], bhi[3], L = on ? fmax(fabs(xv[0]), fmax(fabs(xv[1]), fabs(xv[2]))) : 0.0;
+    for (int k = 0; k < 3; ++k) {
+        blo[k] = on ? xv[k] : INFINITY;
+        bhi[k] = on ? xv[k] : -INFINITY;
+    }
+#pragma unroll
+    for (int d = 8; d >= 1; d >>= 1) {
+        for (int k = 0; k < 3; ++k) {
+            blo[k] = fmin(blo[k], __shfl_xor(blo[k], d, 64));
+            bhi[k] = fmax(bhi[k], __shfl_xor(bhi[k], d, 64));
         }
+        L = fmax(L, __shfl_xor(L, d, 64));
+    }
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (f < n_face && j == 0) {
         const double delta = kTolHit + ldexp(L, -20);
         for (int a = 0; a < 3; ++a) {
             lo[a] = f32_down(blo[a] - delta);
@@ -190,7 +206,7 @@ __global__ __launch_bounds__(kThreads) void k_bins_setup(const CutInst *__restri
     const int lane = lane_id(), wid = threadIdx.x >> 6;
     for (int i = wid; i < n_cut; i += kThreads / 64) {
         SurfParams *sp = I[i].params;
-        const int b0 = I[i].fblk0, nblk = (int)((I[i].n_face + kThreads - 1) / kThreads);
+        const int b0 = I[i].pblk0, nblk = (int)((I[i].n_face + kPoseFaces - 1) / kPoseFaces);
         int ob[6] = {f2ord(INFINITY), f2ord(INFINITY), f2ord(INFINITY), f2ord(-INFINITY), f2ord(-INFINITY),
                      f2ord(-INFINITY)};
         for (int b = b0 + lane; b < b0 + nblk; b += 64)
@@ -638,7 +654,7 @@ struct ExactArgs {
 
 constexpr int kSideParts = 4;   // wavefronts sharing one side item's walks
 
-constexpr int kFaceCap = 256;
+constexpr int kFaceCap = 64;    // one chunk of candidate faces
 constexpr int kGroup = 8;   // candidate faces tested together by k_hit
 
 // a4: one wavefront per near element decides whether the surface intersects
@@ -709,9 +725,10 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         bool hit = false;
         int nlist = 0;
         // exact test of the listed faces
+        int round = 0;   // group size ramp, kept across flushes
         auto flush = [&]() {
             int ng = 0;
-            for (int i0 = 0, round = 0; i0 < nlist && !hit; i0 += ng, ++round) {
+            for (int i0 = 0; i0 < nlist && !hit; i0 += ng, ++round) {
                 ng = min(min(1 << round, kGroup), nlist - i0);
                 for (int k = lane; k < 27 * ng; k += 64) {
                     const int g = k / 27;
@@ -769,7 +786,9 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
             const unsigned long long m = __ballot(pass);
             if (pass) sList[nlist + __popcll(m & ((1ull << lane) - 1ull))] = f;
             nlist += __popcll(m);
-            if (nlist > kFaceCap - 64) {
+            // test what this chunk found: an intersected element usually
+            // stops here, before the rest of its bins are walked
+            if (nlist > 0) {
                 __syncthreads();
                 flush();
             }
@@ -1242,7 +1261,7 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
     }
     std::vector<CutInst> I;
     std::vector<CutOut> O;
-    int64_t fblk = 0, eblk = 0, face_off = 0, fill_blk = 0, ov_blk = 0, cnt_blk = 0, n_elem_total = 0;
+    int64_t fblk = 0, pblk = 0, eblk = 0, face_off = 0, fill_blk = 0, ov_blk = 0, cnt_blk = 0, n_elem_total = 0;
     for (int r = 0; r < n_req; ++r) {
         const CutReq &q = reqs[r];
         const Grid &g = *q.g;
@@ -1285,14 +1304,16 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
             c.kind = s.kind;
             c.write_field = k == 0;
             c.fblk0 = (int)fblk;
+            c.pblk0 = (int)pblk;
             c.eblk0 = (int)eblk;
             fblk += blocks_of(s.n_face, kThreads);
+            pblk += blocks_of(s.n_face, kPoseFaces);
             eblk += blocks_of(g.n_elem, kThreads * 4);
             face_off += s.n_face;
             I.push_back(c);
         }
     }
-    if (fblk >= INT32_MAX || eblk >= INT32_MAX || fill_blk >= INT32_MAX || ov_blk >= INT32_MAX ||
+    if (fblk >= INT32_MAX || pblk >= INT32_MAX || eblk >= INT32_MAX || fill_blk >= INT32_MAX || ov_blk >= INT32_MAX ||
         need.elem_inst >= INT32_MAX || cnt_blk >= INT32_MAX) {
         set_error("cut batch too large");
         return OC_EINVAL;
@@ -1308,7 +1329,7 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
     if (fill_blk || ov_blk) OC_TRY(put_bytes(sl, sl->outs, O.data(), sizeof(CutOut) * O.size()));
     if (fill_blk) LAUNCH(k_fill_field, dim3((unsigned)fill_blk), dim3(kThreads), sl->outs, n_out);
     if (n_cut) {
-        LAUNCH(k_pose_faces, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->sbox_part);
+        LAUNCH(k_pose_faces, dim3((unsigned)pblk), dim3(kThreads), sl->insts, n_cut, sl->sbox_part);
         // the bin counts are zero here: zeroed when the slot's arrays were
         // made, and k_bin_fill takes every count back to zero
         LAUNCH(k_bins_setup, dim3(1), dim3(kThreads), sl->insts, n_cut, sl->sbox_part, n_bins_dev, sl->counters);

@@ -93,8 +93,9 @@ static oc_status slot_alloc_cut(oc_slot *sl, CutCaps c)
     OC_TRY(dev_alloc(ctx, o, sizeof(uint8_t) * (size_t)c.elem_inst, (void **)&sl->l_stat));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)c.elem_inst, (void **)&sl->l_ncand));
     OC_TRY(dev_alloc(ctx, o, sizeof(unsigned long long) * 2 * (size_t)c.elem_inst, (void **)&sl->l_side));
-    // face blocks of 256 faces, plus one spare block per cut
-    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * 6 * (size_t)(c.faces / 256 + 2 * c.cuts + 1),
+    // partial boxes of the pose launch: blocks of 16 faces, plus one spare
+    // block per cut
+    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * 6 * (size_t)(c.faces / 16 + 2 * c.cuts + 1),
                      (void **)&sl->sbox_part));
     OC_TRY(dev_alloc(ctx, o, sizeof(CutInst) * (size_t)c.cuts, (void **)&sl->insts));
     OC_TRY(dev_alloc(ctx, o, sizeof(CutOut) * (size_t)c.outs, (void **)&sl->outs));

@@ -130,6 +130,7 @@ struct CutInst {
     float dmax;
     int nb_max, kind, write_field;
     int fblk0, eblk0;           // first block in face / element flattened launches
+    int pblk0, pad;             // first block of the pose launch (16 faces per block)
 };
 
 // One output of a batch: the iblank of a grid after all of its cuts.
