@@ -10,6 +10,8 @@ Functions follow the paper (Crabill, Witherden & Jameson, arXiv:1711.07663):
 * :func:`cut` -- Sec. 4.2 (parallel direct cut), the per-surface status, the
   union of holes over cutting surfaces and the artificial-boundary (fringe)
   layer of Sec. 4.2's last paragraphs.
+* :func:`unblank` -- Sec. 3, Alg. unblank: the blanking of a moving grid's
+  time step from the cuts at t and t + dt, and the cells to unblank.
 * :func:`fringe_points` -- receptor points: a 3x3x3 Gauss-Legendre tensor per
   fringe element mapped by eq. reftophys.
 * :func:`donor_search` -- Sec. 4.3, Newton inversion of eq. reftophys with
@@ -223,6 +225,38 @@ def cut(grid, surfaces, poses, kinds=None, nbr=None, brute=False, threads=0):
     if nbr is None:
         nbr = face_neighbors(grid.conn)
     return mark_fringe(hole, nbr, grid.face_tags)
+
+
+def hole_mask(grid, surfaces, poses, kind=SURF_WALL, threads=0):
+    """Union over the surfaces of their holes in ``grid`` (Sec. 4.2)."""
+    hole = np.zeros(grid.conn.shape[0], dtype=bool)
+    for s, p in zip(surfaces, poses):
+        hole |= cut_surface(grid, s, p, kind, threads=threads) == 0
+    return hole
+
+
+def unblank(grid, surfaces, poses_t, poses_tp, prev_iblank, kind=SURF_WALL, nbr=None, threads=0):
+    """Blanking of one time step with unblanking (Alg. unblank, steps 3-8),
+    for a grid cut by surfaces of one kind.
+
+    I_t and I_{t+} are the hole sets of the cuts at the poses of time t and
+    t + dt.  A grid cut by solid walls takes the holes of either
+    (a cell that becomes a hole at t + dt is a hole now); a grid cut by
+    overset boundaries keeps a hole only where both cuts agree (cells are
+    not blanked before they are known not to be needed, and are unblanked
+    before they are needed).  The cells to unblank are the holes of the
+    previous blanking (``prev_iblank``, I_{t-}) that are not holes of the
+    new one.  Returns the new iblank (one fringe layer around its holes,
+    overset-tagged faces fringe) and the ascending ids of the cells to
+    unblank."""
+    h_t = hole_mask(grid, surfaces, poses_t, kind, threads)
+    h_tp = hole_mask(grid, surfaces, poses_tp, kind, threads)
+    hole = (h_t | h_tp) if kind == SURF_WALL else (h_t & h_tp)
+    if nbr is None:
+        nbr = face_neighbors(grid.conn)
+    ib = mark_fringe(hole, nbr, grid.face_tags)
+    ub = np.nonzero((np.asarray(prev_iblank) == HOLE) & ~hole)[0].astype(np.int64)
+    return ib, ub
 
 
 def fringe_elements(iblank):
