@@ -159,6 +159,35 @@ oc_status oc_sweep_bound(oc_ctx *ctx, int32_t surf_id, const double pose_a[12], 
 
 oc_status oc_last_cut_info(oc_ctx *ctx, oc_cut_info *info);
 
+/* Blanking of one time step of a moving grid, with unblanking (Sec. 3,
+ * Alg. unblank, steps 3-7).  The grid is cut by its n_surf surfaces (all of
+ * one kind) at the poses of time t (poses_t) and of t + dt (poses_tp), host
+ * FP64 [n_surf*12] each.  The new holes are, for WALL surfaces, the cells
+ * that are holes at t or at t + dt (a cell about to enter the wall is a hole
+ * now); for OVERSET surfaces, the cells that are holes at both (a cell is
+ * not blanked before it is known to be unneeded).  iblank_out (device int8
+ * [n_elem]) receives the new blanking with one fringe layer around its
+ * holes and overset-tagged faces fringe.  The cells to unblank -- holes of
+ * prev_iblank (the previous step's blanking, device, not aliasing
+ * iblank_out) that are not holes of the new one -- are written to
+ * unblank_out (device int32 [cap], ascending ids) and counted in
+ * *n_unblank (host; synchronises).  OC_ECAPACITY if cap is too small
+ * (*n_unblank is set); OC_EINVAL if the surfaces mix kinds.  At most 127
+ * surfaces.  Their interior points come from oc_element_points and their
+ * donors from oc_donor_search. */
+oc_status oc_unblank(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, int32_t n_surf, const double *poses_t,
+                     const double *poses_tp, const int8_t *prev_iblank, int8_t *iblank_out, int32_t *unblank_out,
+                     int64_t cap, int64_t *n_unblank);
+/* Receptor points of listed elements (Alg. unblank step 8: the interior
+ * points of the cells to unblank): 27 Gauss-Legendre points per element of
+ * elems (device int32 [n], any order), order a+3b+9c, mapped by
+ * eq. reftophys and posed by grid_pose, into points_out (device FP64
+ * [27*n*3]); src_out (device int32 [27*n], may be NULL) receives each
+ * point's element.  An id outside [0, n_elem) yields NaN points and
+ * source -1 (the ids are checked on the device, not the host). */
+oc_status oc_element_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int32_t *elems, int64_t n,
+                            double *points_out, int32_t *src_out);
+
 /* One request of a cut batch: grid grid_id cut by n_surf posed surfaces
  * (union of holes, as oc_cut_multi) into its own iblank_out (device int8
  * [n_elem], 4-byte aligned; no two requests of a batch may share one). */

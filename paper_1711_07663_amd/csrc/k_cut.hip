@@ -725,11 +725,12 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         bool hit = false;
         int nlist = 0;
         // exact test of the listed faces
-        int round = 0;   // group size ramp, kept across flushes
+        int round = 0;   // group size 1, 2, 4 .. kGroup, kept across flushes
         auto flush = [&]() {
             int ng = 0;
-            for (int i0 = 0; i0 < nlist && !hit; i0 += ng, ++round) {
-                ng = min(min(1 << round, kGroup), nlist - i0);
+            for (int i0 = 0; i0 < nlist && !hit; i0 += ng) {
+                ng = min(1 << round, nlist - i0);
+                if ((1 << round) < kGroup) ++round;
                 for (int k = lane; k < 27 * ng; k += 64) {
                     const int g = k / 27;
                     sF[k] = pnodes[(int64_t)sList[i0 + g] * 27 + (k - 27 * g)];

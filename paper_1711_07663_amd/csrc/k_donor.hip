@@ -359,14 +359,21 @@ __global__ __launch_bounds__(kT) void k_dbin_sort(const int32_t *__restrict__ st
 constexpr int kFrItems = 16;
 constexpr int kFrTile = kT * kFrItems;
 
-__global__ __launch_bounds__(kT) void k_fr_count(const int8_t *__restrict__ iblank, int64_t n_elem,
-                                                 int32_t *__restrict__ tcount)
+// element listed by an ordered compaction: a fringe element of iblank, or
+// (prev given) a hole of prev that is not a hole of iblank (to unblank)
+__device__ inline bool listed(const int8_t *__restrict__ ib, const int8_t *__restrict__ prev, int64_t i)
+{
+    return prev ? (prev[i] == OC_HOLE && ib[i] != OC_HOLE) : ib[i] == OC_FRINGE;
+}
+
+__global__ __launch_bounds__(kT) void k_fr_count(const int8_t *__restrict__ iblank, const int8_t *__restrict__ prev,
+                                                 int64_t n_elem, int32_t *__restrict__ tcount)
 {
     const int64_t base = (int64_t)blockIdx.x * kFrTile;
     int c = 0;
     for (int k = 0; k < kFrItems; ++k) {
         const int64_t i = base + (int64_t)k * kT + threadIdx.x;
-        if (i < n_elem) c += iblank[i] == OC_FRINGE;
+        if (i < n_elem) c += listed(iblank, prev, i);
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
@@ -380,14 +387,16 @@ __global__ __launch_bounds__(kT) void k_fr_count(const int8_t *__restrict__ ibla
     }
 }
 
-__global__ __launch_bounds__(kT) void k_fr_write(const int8_t *__restrict__ iblank, int64_t n_elem,
-                                                 const int32_t *__restrict__ toff, int32_t *__restrict__ list)
+// ordered write of the listed elements (at most cap)
+__global__ __launch_bounds__(kT) void k_fr_write(const int8_t *__restrict__ iblank, const int8_t *__restrict__ prev,
+                                                 int64_t n_elem, const int32_t *__restrict__ toff,
+                                                 int32_t *__restrict__ list, int64_t cap)
 {
     const int64_t my = (int64_t)blockIdx.x * kFrTile + (int64_t)threadIdx.x * kFrItems;
     int c = 0;
     for (int k = 0; k < kFrItems; ++k) {
         const int64_t i = my + k;
-        if (i < n_elem) c += iblank[i] == OC_FRINGE;
+        if (i < n_elem) c += listed(iblank, prev, i);
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int inc = c;
@@ -404,14 +413,18 @@ __global__ __launch_bounds__(kT) void k_fr_write(const int8_t *__restrict__ ibla
     int pos = off + inc - c;
     for (int k = 0; k < kFrItems; ++k) {
         const int64_t i = my + k;
-        if (i < n_elem && iblank[i] == OC_FRINGE) list[pos++] = (int32_t)i;
+        if (i < n_elem && listed(iblank, prev, i)) {
+            if (pos < cap) list[pos] = (int32_t)i;
+            ++pos;
+        }
     }
 }
 
 // a9: Gauss point k = a + 3b + 9c of fringe element list[i / 27], posed.
 // The number of fringe elements is read from the device (nfr); at most cap
-// points are written; n_out receives 27 * nfr.
-__global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__ enodes,
+// points are written; n_out receives 27 * nfr.  An id outside [0, n_elem)
+// gives NaN points and source -1.
+__global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__ enodes, int64_t n_elem,
                                                       const int32_t *__restrict__ list, const int32_t *__restrict__ nfr,
                                                       int64_t cap, const Pose *__restrict__ pose_dev,
                                                       double *__restrict__ pts, int32_t *__restrict__ src,
@@ -425,6 +438,14 @@ __global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__
         const int64_t q = i / 27;
         const int k = (int)(i - q * 27);
         const int e = list[q];
+        if (e < 0 || e >= n_elem) {
+            const double nan = __builtin_nan("");
+            pts[3 * i] = nan;
+            pts[3 * i + 1] = nan;
+            pts[3 * i + 2] = nan;
+            if (src) src[i] = -1;
+            continue;
+        }
         const double g = 0.7745966692414834;  // sqrt(3/5), 3-point Gauss-Legendre
         const double xi[3] = {(k % 3 - 1) * g, ((k / 3) % 3 - 1) * g, (k / 9 - 1) * g};
         double x[3];
@@ -816,23 +837,52 @@ oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g)
     return OC_OK;
 }
 
-oc_status fringe_points_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const int8_t *iblank, double *pts,
-                            int64_t cap, int32_t *n_dev, int64_t *n_host, int32_t *src)
+// Ordered compaction of the listed elements of g (see listed()) into list
+// (at most cap; null: the slot's own list, taken after the slot's lists have
+// been sized for g); the count stays on the device at *total.
+oc_status list_elements_run(oc_slot *sl, const Grid &g, const int8_t *iblank, const int8_t *prev, int32_t *list,
+                            int64_t cap, const int32_t **total)
 {
     oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
     OC_TRY(slot_reserve_grid(sl, g));
+    if (!list) {
+        list = sl->list_fringe;
+        cap = std::min<int64_t>(cap, sl->list_cap);
+    }
     const int64_t nt = (g.n_elem + kFrTile - 1) / kFrTile;
     int32_t *tcount = sl->fr_tiles, *toff = sl->fr_tiles + (nt + 1);
     int32_t *tmp = sl->fr_tiles + 2 * (nt + 1);
-    int32_t *cnt_out = n_dev ? n_dev : sl->scalar;
-    LAUNCH(k_fr_count, dim3((unsigned)std::max<int64_t>(nt, 1)), dim3(kT), iblank, g.n_elem, tcount);
+    LAUNCH(k_fr_count, dim3((unsigned)std::max<int64_t>(nt, 1)), dim3(kT), iblank, prev, g.n_elem, tcount);
     OC_TRY(scan_exclusive(ctx, st, tcount, toff, nt, nullptr, tmp));
-    LAUNCH(k_fr_write, dim3((unsigned)std::max<int64_t>(nt, 1)), dim3(kT), iblank, g.n_elem, toff, sl->list_fringe);
+    LAUNCH(k_fr_write, dim3((unsigned)std::max<int64_t>(nt, 1)), dim3(kT), iblank, prev, g.n_elem, toff, list, cap);
+    OC_HIP(hipGetLastError());
+    *total = toff + nt;
+    return OC_OK;
+}
+
+// 27 Gauss points of the first min(*count, cap / 27) listed elements;
+// n_out (device, may be null) receives 27 * *count.
+oc_status element_points_run(oc_slot *sl, const Grid &g, const Pose *pose_dev, const int32_t *list,
+                             const int32_t *count, double *pts, int64_t cap, int32_t *n_out, int32_t *src)
+{
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
     const int64_t cap_pts = std::min<int64_t>(cap, 27 * g.n_elem);
     LAUNCH(k_fringe_points, dim3(std::min<unsigned>(blocks(std::max<int64_t>(cap_pts, 1), kT), 8192u)), dim3(kT),
-           g.enodes, sl->list_fringe, toff + nt, cap, pose_dev, pts, src, cnt_out);
+           g.enodes, g.n_elem, list, count, cap, pose_dev, pts, src, n_out);
     OC_HIP(hipGetLastError());
+    return OC_OK;
+}
+
+oc_status fringe_points_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const int8_t *iblank, double *pts,
+                            int64_t cap, int32_t *n_dev, int64_t *n_host, int32_t *src)
+{
+    hipStream_t st = sl->stream;
+    const int32_t *total = nullptr;
+    OC_TRY(list_elements_run(sl, g, iblank, nullptr, nullptr, g.n_elem, &total));
+    int32_t *cnt_out = n_dev ? n_dev : sl->scalar;
+    OC_TRY(element_points_run(sl, g, pose_dev, sl->list_fringe, total, pts, cap, cnt_out, src));
     if (n_host) {
         int32_t n = 0;
         OC_HIP(hipMemcpyAsync(&n, cnt_out, sizeof(int32_t), hipMemcpyDeviceToHost, st));

@@ -776,6 +776,52 @@ oc_status oc_cut_warm(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const doubl
     return cut_batch_run(sl, &q, 1);
 }
 
+oc_status oc_unblank(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, int32_t n_surf, const double *poses_t,
+                     const double *poses_tp, const int8_t *prev_iblank, int8_t *iblank_out, int32_t *unblank_out,
+                     int64_t cap, int64_t *n_unblank)
+{
+    if (!ctx || !prev_iblank || !iblank_out || !n_unblank || cap < 0 || (cap > 0 && !unblank_out) || n_surf < 0 ||
+        2 * n_surf > kPoseSlots - 2 || (n_surf > 0 && (!surf_ids || !poses_t || !poses_tp)) ||
+        prev_iblank == iblank_out) {
+        set_error("oc_unblank: invalid arguments");
+        return OC_EINVAL;
+    }
+    for (int k = 0; k < n_surf; ++k)
+        if (!pose_ok(poses_t + 12 * k) || !pose_ok(poses_tp + 12 * k)) {
+            set_error("oc_unblank: non-finite pose");
+            return OC_EINVAL;
+        }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, 0, poses_t, n_surf));
+    OC_TRY(set_poses(sl, n_surf, poses_tp, n_surf));
+    return unblank_run(sl, *g, ss.data(), n_surf, sl->poses, sl->poses + n_surf, prev_iblank, iblank_out,
+                       unblank_out, cap, nullptr, n_unblank);
+}
+
+oc_status oc_element_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int32_t *elems, int64_t n,
+                            double *points_out, int32_t *src_out)
+{
+    if (!ctx || n < 0 || (n > 0 && (!elems || !points_out)) || !pose_ok(grid_pose) || n > INT32_MAX / 27) {
+        set_error("oc_element_points: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    if (n == 0) return OC_OK;
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, kPoseSlots - 2, grid_pose, 1));
+    const int32_t n32 = (int32_t)n;
+    OC_TRY(put_bytes(sl, sl->scalar + 2, &n32, sizeof n32));
+    return element_points_run(sl, *g, sl->poses + kPoseSlots - 2, elems, sl->scalar + 2, points_out, 27 * n,
+                              nullptr, src_out);
+}
+
 // ------------------------------------------------------------- slot API --
 oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, const int32_t *surf_ids,
                          int32_t n_surfs, int64_t points_cap, oc_slot **out)

@@ -175,6 +175,8 @@ struct oc_slot {
     oc::Pose *poses = nullptr;         // [kPoseSlots] device
     int32_t *scalar = nullptr;         // device scratch
     int64_t last_n_elem = 0;
+    int8_t *ub_a = nullptr, *ub_b = nullptr;   // unblank: iblank at t and at t + dt
+    int64_t ub_cap = 0;
     // donor search scratch: per point and per (point, candidate) pair
     int64_t dpt_cap = 0, dpair_cap = 0;
     double *dp_local = nullptr;
@@ -288,6 +290,20 @@ oc_status donor_stats_run(oc_slot *sl);
 // returned on the host when n_host is not null (synchronising)
 oc_status fringe_points_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const int8_t *iblank, double *pts,
                             int64_t cap, int32_t *n_dev, int64_t *n_host, int32_t *src);
+// ordered compaction of the elements of g that are fringe in iblank (prev
+// null) or holes of prev that are not holes of iblank; at most cap ids into
+// list, the count left on the device at *total
+oc_status list_elements_run(oc_slot *sl, const Grid &g, const int8_t *iblank, const int8_t *prev, int32_t *list,
+                            int64_t cap, const int32_t **total);
+// 27 Gauss points of the first min(*count, cap / 27) listed elements
+oc_status element_points_run(oc_slot *sl, const Grid &g, const Pose *pose_dev, const int32_t *list,
+                             const int32_t *count, double *pts, int64_t cap, int32_t *n_out, int32_t *src);
+// blanking of a moving grid's time step with unblanking: cuts at poses_t
+// and poses_tp (device), combined by the surfaces' kind, fringe layer, and
+// the holes of prev that are holes no more (ascending, at most cap)
+oc_status unblank_run(oc_slot *sl, Grid &g, Surf *const *surfs, int n_surf, const Pose *poses_t,
+                      const Pose *poses_tp, const int8_t *prev, int8_t *out, int32_t *ub_list, int64_t cap,
+                      int32_t *n_dev, int64_t *n_host);
 // donor search of min(*n_dev, cap) points (n_dev may be null: cap points)
 oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pts, int64_t cap, const int32_t *n_dev,
                     int32_t *donor, double *ref);

@@ -30,7 +30,7 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_slot_create", "oc_slot_destroy", "oc_slot_set_stream", "oc_slot_bytes", "oc_slot_cut",
            "oc_slot_fringe_points", "oc_slot_donor_search", "oc_slot_cut_info", "oc_slot_donor_info",
            "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm", "oc_cut_batch", "oc_slot_cut_batch",
-           "oc_slot_create_batch", "oc_tune"]
+           "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points"]
 
 
 class OcError(RuntimeError):
@@ -102,6 +102,8 @@ def load(path=LIB_PATH):
         "oc_slot_cut_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32]),
         "oc_slot_create_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32, C.c_int64, C.POINTER(C.c_void_p)]),
         "oc_tune": ([vp, C.c_int32, C.c_int32, C.c_int64, i64p]),
+        "oc_unblank": ([vp, C.c_int32, i32p, C.c_int32, dp, dp, vp, vp, vp, C.c_int64, i64p]),
+        "oc_element_points": ([vp, C.c_int32, dp, vp, C.c_int64, vp, vp]),
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -254,6 +256,31 @@ class Context:
         _check(load().oc_cut_warm(self._h, grid_id, surf_id, pp, qq, _dptr(prev_iblank, torch.int8, self.grids[grid_id]),
                                   _dptr(iblank, torch.int8, self.grids[grid_id])))
         return iblank
+
+    def unblank(self, grid_id, surf_ids, poses_t, poses_tp, prev_iblank, iblank, unblank_out):
+        """Blanking of a moving grid's time step with unblanking (oc_unblank);
+        returns the number of cells to unblank (their ids in unblank_out)."""
+        import torch
+        ids = np.ascontiguousarray(surf_ids, dtype=np.int32)
+        n = len(ids)
+        pa, pp = _pose(np.asarray(poses_t, dtype=np.float64).reshape(-1) if n else np.zeros(12))
+        qa, qq = _pose(np.asarray(poses_tp, dtype=np.float64).reshape(-1) if n else np.zeros(12))
+        cnt = C.c_int64(0)
+        ne = self.grids[grid_id]
+        _check(load().oc_unblank(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), n, pp, qq,
+                                 _dptr(prev_iblank, torch.int8, ne), _dptr(iblank, torch.int8, ne),
+                                 _dptr(unblank_out, torch.int32), unblank_out.numel(), C.byref(cnt)))
+        return cnt.value
+
+    def element_points(self, grid_id, pose, elems, n, points, src=None):
+        """27 Gauss points of each of the first n element ids of ``elems``."""
+        import torch
+        _, pp = _pose(pose)
+        if n == 0:
+            return
+        _check(load().oc_element_points(self._h, grid_id, pp, _dptr(elems, torch.int32, n), int(n),
+                                        _dptr(points, torch.float64, 81 * n),
+                                        None if src is None else _dptr(src, torch.int32, 27 * n)))
 
     def sweep_bound(self, surf_id, pose_a, pose_b):
         _, pa = _pose(pose_a)

@@ -1,0 +1,174 @@
+"""Unblanking of a moving grid (Alg. unblank) through the C ABI against the
+oracle: the new blanking, the cells to unblank, their interior points and
+their donors."""
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import meshes as M
+
+from parity_util import PT_TOL, XI_TOL
+
+pytestmark = pytest.mark.gpu
+
+
+def _note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1711_07663_amd import oc
+    c = oc.Context(device=0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _case():
+    bg = M.background_grid(18, -1.3, 1.3, amp=0.03)
+    s = M.cube_sphere(6, R=0.45, dimples=24, dimple_a=0.08, dimple_k=0.02)
+    sh = M.shell_grid(s, 3, r_out=0.9)
+    return bg, s, sh
+
+
+def _poses(k):
+    """A body spinning about z and drifting along x (several cells per step,
+    so cells are unblanked every step)."""
+    return M.pose_rz(0.4 * k, (0.09 * k - 0.2, 0.02 * k, 0.0))
+
+
+def test_unblank_wall_sequence(ctx, orc):
+    import torch
+    _note("unblank, wall rule, 4 steps of a moving dimpled sphere")
+    bg, s, sh = _case()
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    shid = ctx.register_grid(sh.nodes, sh.conn, sh.face_tags)
+    prev = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+    ctx.cut(gid, sid, _poses(0), prev)
+    prev_o = orc.cut(bg, [s], [_poses(0)])
+    assert np.array_equal(prev.cpu().numpy(), prev_o)
+    cur = torch.empty_like(prev)
+    ub = torch.empty(bg.n_elem, dtype=torch.int32, device="cuda")
+    total = 0
+    for k in range(1, 5):
+        n = ctx.unblank(gid, [sid], _poses(k), _poses(k + 1), prev, cur, ub)
+        torch.cuda.synchronize()
+        ib_o, ub_o = orc.unblank(bg, [s], [_poses(k)], [_poses(k + 1)], prev_o)
+        assert np.array_equal(cur.cpu().numpy(), ib_o), "step %d" % k
+        assert n == ub_o.size and np.array_equal(ub[:n].cpu().numpy(), ub_o), "step %d" % k
+        total += n
+        if n:
+            # step 8: interior points of the cells to unblank and their donors
+            # in the body's near-body grid at time t
+            pts = torch.empty((27 * n, 3), dtype=torch.float64, device="cuda")
+            src = torch.empty(27 * n, dtype=torch.int32, device="cuda")
+            ctx.element_points(gid, M.IDENTITY_POSE, ub, n, pts, src)
+            donor = torch.empty(27 * n, dtype=torch.int32, device="cuda")
+            ref = torch.empty((27 * n, 3), dtype=torch.float64, device="cuda")
+            ctx.donor_search(shid, _poses(k), pts, 27 * n, donor, ref)
+            torch.cuda.synchronize()
+            p_o = orc.fringe_points(bg, ub_o)
+            assert np.abs(pts.cpu().numpy() - p_o).max() <= PT_TOL
+            assert np.array_equal(src.cpu().numpy(), np.repeat(ub_o, 27))
+            d_o, r_o, _ = orc.donor_search(sh, p_o, _poses(k))
+            assert np.array_equal(donor.cpu().numpy(), d_o)
+            ok = d_o >= 0
+            assert np.abs(ref.cpu().numpy()[ok] - r_o[ok]).max() <= XI_TOL
+        prev, cur = cur, prev
+        prev_o = ib_o
+    assert total > 0
+
+
+def test_unblank_overset_rule(ctx, orc):
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("unblank, overset rule")
+    bg, s, _ = _case()
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn, oc.OC_SURF_OVERSET)
+    prev_o = orc.cut(bg, [s], [_poses(1)], kinds=[orc.SURF_OVERSET])
+    prev = torch.from_numpy(prev_o).cuda()
+    cur = torch.empty_like(prev)
+    ub = torch.empty(bg.n_elem, dtype=torch.int32, device="cuda")
+    n = ctx.unblank(gid, [sid], _poses(2), _poses(3), prev, cur, ub)
+    torch.cuda.synchronize()
+    ib_o, ub_o = orc.unblank(bg, [s], [_poses(2)], [_poses(3)], prev_o, kind=orc.SURF_OVERSET)
+    assert np.array_equal(cur.cpu().numpy(), ib_o)
+    assert n == ub_o.size > 0 and np.array_equal(ub[:n].cpu().numpy(), ub_o)
+
+
+def test_unblank_errors(ctx):
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("unblank argument errors")
+    bg, s, _ = _case()
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    wall = ctx.register_cut_surface(s.nodes, s.conn)
+    ovs = ctx.register_cut_surface(s.nodes, s.conn, oc.OC_SURF_OVERSET)
+    prev = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+    ctx.cut(gid, wall, _poses(0), prev)
+    cur = torch.empty_like(prev)
+    ub = torch.empty(bg.n_elem, dtype=torch.int32, device="cuda")
+    with pytest.raises(oc.OcError) as e:
+        ctx.unblank(gid, [wall, ovs], np.stack([_poses(1)] * 2), np.stack([_poses(2)] * 2), prev, cur, ub)
+    assert e.value.status == oc.OC_EINVAL
+    with pytest.raises(oc.OcError) as e:
+        ctx.unblank(gid, [wall], _poses(1), _poses(2), prev, prev, ub)
+    assert e.value.status == oc.OC_EINVAL
+    n = ctx.unblank(gid, [wall], _poses(3), _poses(4), prev, cur, ub)
+    assert n > 1
+    with pytest.raises(oc.OcError) as e:
+        ctx.unblank(gid, [wall], _poses(3), _poses(4), prev, cur, ub[:1])
+    assert e.value.status == oc.OC_ECAPACITY
+
+
+def test_element_points_bad_ids(ctx, orc):
+    """Ids outside the grid give NaN points and source -1; the others are
+    the oracle's points."""
+    import torch
+    _note("element points with out-of-range ids")
+    bg = M.background_grid(6, -1.0, 1.0, amp=0.04)
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    ids = torch.tensor([3, -1, bg.n_elem, 0, bg.n_elem - 1], dtype=torch.int32, device="cuda")
+    pose = M.pose_rz(0.2, (0.1, 0.0, -0.05))
+    pts = torch.empty((27 * 5, 3), dtype=torch.float64, device="cuda")
+    src = torch.empty(27 * 5, dtype=torch.int32, device="cuda")
+    ctx.element_points(gid, pose, ids, 5, pts, src)
+    torch.cuda.synchronize()
+    p = pts.cpu().numpy().reshape(5, 27, 3)
+    s = src.cpu().numpy().reshape(5, 27)
+    assert np.all(np.isnan(p[1:3])) and np.all(s[1:3] == -1)
+    good = [0, 3, 4]
+    ref = orc.fringe_points(bg, ids.cpu().numpy()[good], pose).reshape(3, 27, 3)
+    assert np.abs(p[good] - ref).max() <= PT_TOL
+    assert np.array_equal(s[good], np.repeat(ids.cpu().numpy()[good], 27).reshape(3, 27))
+
+
+def test_fringe_points_first_call_of_context(orc):
+    """Receptor points listed by a context's very first call (its lists are
+    sized inside the call) equal the oracle's."""
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("fringe points as the first call of a fresh context")
+    bg, s, _ = _case()
+    ib_o = orc.cut(bg, [s], [_poses(1)])
+    fr = orc.fringe_elements(ib_o)
+    c = oc.Context(device=0)
+    try:
+        gid = c.register_grid(bg.nodes, bg.conn)
+        ib = torch.from_numpy(ib_o).cuda()
+        pts = torch.empty((27 * fr.size, 3), dtype=torch.float64, device="cuda")
+        src = torch.empty(27 * fr.size, dtype=torch.int32, device="cuda")
+        n = c.fringe_points(gid, M.IDENTITY_POSE, ib, pts, src)
+        torch.cuda.synchronize()
+        assert n == 27 * fr.size > 0
+        assert np.abs(pts.cpu().numpy() - orc.fringe_points(bg, fr)).max() <= PT_TOL
+        assert np.array_equal(src.cpu().numpy(), np.repeat(fr, 27))
+    finally:
+        torch.cuda.synchronize()
+        c.close()
