@@ -15,7 +15,11 @@ Other workloads (--workload):
   batch  64 uneven instances (SeedSequence(1711)) cut in one launch per stage,
          against the same instances cut one at a time;
   serve  Poisson arrivals over four device-resident grid sets served with
-         continuous batching, against one-at-a-time service.
+         continuous batching, against one-at-a-time service;
+  unblank  the dimpled sphere turning and oscillating (amplitude 0.5) through
+         the background: per step the background is cut at the poses of t
+         and t + dt (wall rule: union of holes), the cells to unblank are
+         listed, and their 27 interior points get donors in the shell.
 
 Prints one JSON line.  Only N = 1 GPU is supported.
 """
@@ -86,7 +90,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1, help="oracle runs on every k-th element / point")
     ap.add_argument("--bg", type=int, default=128)
-    ap.add_argument("--workload", default="dimpled", choices=["dimpled", "spin", "batch", "serve"])
+    ap.add_argument("--workload", default="dimpled", choices=["dimpled", "spin", "batch", "serve", "unblank"])
     ap.add_argument("--spin-steps", type=int, default=200)
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--rates", default="50,100,200,500", help="serve: arrival rates, requests/s")
@@ -155,7 +159,8 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
         del src, dst
-    out = dict(dimpled=run_dimpled, spin=run_spin, batch=run_batch, serve=run_serve)[a.workload](a)
+    out = dict(dimpled=run_dimpled, spin=run_spin, batch=run_batch, serve=run_serve,
+               unblank=run_unblank)[a.workload](a)
     print(json.dumps(out), flush=True)
 
 
@@ -378,6 +383,85 @@ def run_spin(a):
                            bg_elements=bg.n_elem, sweep_bound=sweep, parallelism="1 GPU"),
                latency_ms=_percentiles(lat), plain_ms_per_step=ms_plain, speedup_vs_plain=ms_plain / ms,
                last_warm_cut_info=cut, per_kernel=per_kernel)
+    ctx.close()
+    return out
+
+
+def run_unblank(a):
+    """Moving body with unblanking (Alg. unblank): steps n = 1..N of the
+    turning, oscillating dimpled sphere.  A step is oc_unblank at the poses
+    of steps n and n + 1 (two cuts in one batch, wall rule, fringe layer,
+    cells to unblank; the call returns their count), then the 27 interior
+    points of those cells and their donors in the shell posed at step n."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from workloads import configs as CF
+    from workloads import meshes as M
+    log("generating the dimpled-sphere workload")
+    case = CF.dimpled(bg_n=a.bg)
+    bg, body = case["bg"], case["bodies"][0]
+    s, sh = body["surface"], body["shell"]
+    torch.cuda.set_device(0)
+    ctx = oc.Context(device=0)
+    gid = ctx.register_grid(bg.nodes, bg.conn, bg.face_tags)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    shid = ctx.register_grid(sh.nodes, sh.conn, sh.face_tags)
+    n_steps = a.spin_steps
+    poses = CF.moving_poses(n_steps + 1)
+    dev = torch.device("cuda", 0)
+    ib = [torch.empty(bg.n_elem, dtype=torch.int8, device=dev) for _ in range(2)]
+    ub = torch.empty(bg.n_elem, dtype=torch.int32, device=dev)
+    cap = 27 * 20000
+    pts = torch.empty((cap, 3), dtype=torch.float64, device=dev)
+    src = torch.empty(cap, dtype=torch.int32, device=dev)
+    donor = torch.empty(cap, dtype=torch.int32, device=dev)
+    ref = torch.empty((cap, 3), dtype=torch.float64, device=dev)
+
+    def sequence(collect):
+        ctx.cut(gid, sid, poses[0], ib[0])
+        torch.cuda.synchronize()
+        cur = 0
+        counts, orphans = [], 0
+        t0 = time.perf_counter()
+        for n in range(1, n_steps + 1):
+            m = ctx.unblank(gid, [sid], poses[n], poses[n + 1], ib[cur], ib[1 - cur], ub)
+            if m:
+                if 27 * m > cap:
+                    raise RuntimeError("more cells to unblank than the point buffers hold")
+                ctx.element_points(gid, M.IDENTITY_POSE, ub, m, pts, src)
+                ctx.donor_search(shid, poses[n], pts, 27 * m, donor, ref)
+                if collect:
+                    orphans += int((donor[:27 * m] < 0).sum())
+            counts.append(m)
+            cur = 1 - cur
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, counts, orphans
+
+    log("warmup pass over %d steps" % n_steps)
+    sequence(False)
+    log("timed pass")
+    t_total, counts, _ = sequence(False)
+    _, _, orphans = sequence(True)
+    ms = 1e3 * t_total / n_steps
+    ctx.timing(True)
+    sequence(False)
+    rep = ctx.timing_report()
+    ctx.timing(False)
+    per_kernel = {k: dict(total_ms=v[0], launches=v[1], avg_us=1e3 * v[0] / max(v[1], 1)) for k, v in rep.items()}
+    n_ub = int(np.sum(counts))
+    out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
+               value=bg.n_elem / (ms / 1e3), unit="elements/s", n_gpus=1, steps=n_steps, warmup=n_steps,
+               ms_per_step=ms, steps_per_s=1e3 / ms, higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64", data="synthetic",
+               config=dict(workload="unblanking of a moving body: the 128^3 dimpled case turning about z at "
+                                    "1 rev / 400 steps and oscillating along x (amplitude 0.5); per step two "
+                                    "cuts (t, t + dt), wall rule, fringe, cells to unblank, their interior "
+                                    "points and donors in the shell; %d steps, eager" % n_steps,
+                           bg_elements=bg.n_elem, parallelism="1 GPU"),
+               cells_unblanked=dict(total=n_ub, max_per_step=int(np.max(counts)),
+                                    steps_with_any=int(np.count_nonzero(counts))),
+               interior_points=27 * n_ub, orphan_points=orphans,
+               cut_elements_per_s=2 * bg.n_elem / (ms / 1e3), per_kernel=per_kernel)
     ctx.close()
     return out
 

@@ -90,3 +90,79 @@ def test_dimpled_full_size_parity(orc):
         ok = d_o >= 0
         assert np.abs(r_g[ok] - r_o[ok]).max() <= XI_TOL
         assert np.all(np.isnan(r_g[~ok]))
+
+
+def test_moving_full_size_unblank(orc):
+    """Unblanking at full size (Alg. unblank): the 128^3 dimpled case moving
+    as in the benchmark's unblank workload, step 37.  The oracle cuts the
+    band of elements near the surface at the three poses (every other
+    element is field at all three); the previous blanking, the new one, the
+    cells to unblank, their interior points and their donors in the shell
+    must match."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from parity_util import PT_TOL, XI_TOL
+    from workloads import meshes as M
+
+    _note("full-size unblank: generating inputs")
+    case = CF.dimpled()
+    bg, body = case["bg"], case["bodies"][0]
+    s, sh = body["surface"], body["shell"]
+    poses = CF.moving_poses(40)
+    n = 37
+    ctx = oc.Context(device=0)
+    try:
+        gid = ctx.register_grid(bg.nodes, bg.conn, bg.face_tags)
+        sid = ctx.register_cut_surface(s.nodes, s.conn)
+        shid = ctx.register_grid(sh.nodes, sh.conn, sh.face_tags)
+        _note("full-size unblank: GPU cut at step %d, unblank at steps %d, %d" % (n - 1, n, n + 1))
+        prev = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+        cur = torch.empty_like(prev)
+        ub = torch.empty(bg.n_elem, dtype=torch.int32, device="cuda")
+        ctx.cut(gid, sid, poses[n - 1], prev)
+        m = ctx.unblank(gid, [sid], poses[n], poses[n + 1], prev, cur, ub)
+        pts = torch.empty((max(27 * m, 1), 3), dtype=torch.float64, device="cuda")
+        src = torch.empty(max(27 * m, 1), dtype=torch.int32, device="cuda")
+        donor = torch.empty(max(27 * m, 1), dtype=torch.int32, device="cuda")
+        ref = torch.empty((max(27 * m, 1), 3), dtype=torch.float64, device="cuda")
+        ctx.element_points(gid, M.IDENTITY_POSE, ub, m, pts, src)
+        ctx.donor_search(shid, poses[n], pts, 27 * m, donor, ref)
+        torch.cuda.synchronize()
+        prev_g, cur_g, ub_g = prev.cpu().numpy(), cur.cpu().numpy(), ub[:m].cpu().numpy()
+        pts_g, src_g = pts[:27 * m].cpu().numpy(), src[:27 * m].cpu().numpy()
+        d_g, r_g = donor[:27 * m].cpu().numpy(), ref[:27 * m].cpu().numpy()
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+
+    _note("full-size unblank: oracle cuts of the band at three poses")
+    P = bg.nodes[bg.conn]
+    elo, ehi = P.min(axis=1), P.max(axis=1)
+    del P
+    h = 6.0 / 128
+    posed = [s.nodes @ np.asarray(poses[k][:9]).reshape(3, 3).T + np.asarray(poses[k][9:]) for k in (n - 1, n, n + 1)]
+    slo = np.min([x.min(axis=0) for x in posed], axis=0)
+    shi = np.max([x.max(axis=0) for x in posed], axis=0)
+    band = np.nonzero(np.all(ehi >= slo - 2 * h, axis=1) & np.all(elo <= shi + 2 * h, axis=1))[0]
+    holes = []
+    for k in (n - 1, n, n + 1):
+        st = orc.cut_surface(bg, s, poses[k], sel=band, threads=0)
+        hm = np.zeros(bg.n_elem, dtype=bool)
+        hm[band] = st == 0
+        holes.append(hm)
+    nbr = orc.face_neighbors(bg.conn)
+    prev_o = orc.mark_fringe(holes[0], nbr)
+    cur_o = orc.mark_fringe(holes[1] | holes[2], nbr)
+    ub_o = np.nonzero(holes[0] & ~(holes[1] | holes[2]))[0]
+    assert np.array_equal(prev_g, prev_o)
+    bad = np.nonzero(cur_g != cur_o)[0]
+    assert bad.size == 0, "%d background elements differ, first %s" % (bad.size, bad[:8])
+    assert ub_o.size > 10 and np.array_equal(ub_g, ub_o)
+    pts_o = orc.fringe_points(bg, ub_o)
+    assert np.abs(pts_g - pts_o).max() <= PT_TOL
+    assert np.array_equal(src_g, np.repeat(ub_o, 27))
+    d_o, r_o, _ = orc.donor_search(sh, pts_g, poses[n], threads=0)
+    assert np.array_equal(d_g, d_o)
+    ok = d_o >= 0
+    assert ok.any() and np.abs(r_g[ok] - r_o[ok]).max() <= XI_TOL
+    assert np.all(np.isnan(r_g[~ok]))

@@ -8,6 +8,8 @@ cut surface of kind wall plus its near-body shell) and the per-body poses.
 * dimpled     128^3 background on [-3,3]^3, 300-dimple sphere of 24 576 faces,
               8-layer shell to r = 1.
 * spinning    the dimpled case rotating about z at one turn per 400 steps.
+* moving      the dimpled case turning about z and oscillating along x
+              (amplitude 0.5), for the unblanking of a moving body.
 * batch64     64 uneven instances drawn from SeedSequence(1711).
 * two-body    two dimpled spheres 1.5 apart on a 160^3 background.
 """
@@ -47,6 +49,17 @@ def dimpled(bg_n=128, m=64, layers=8, dimples=300):
 def spinning_poses(n_steps=200, steps_per_rev=400):
     """Poses R_z(2 pi n / steps_per_rev), n = 1..n_steps."""
     return [M.pose_rz(2.0 * math.pi * n / steps_per_rev) for n in range(1, n_steps + 1)]
+
+
+def moving_poses(n_steps=200, steps_per_rev=400, amp=0.5):
+    """Poses of a body turning about z at one turn per steps_per_rev steps
+    while oscillating along x with amplitude amp: R_z(2 pi n / steps_per_rev),
+    t = (amp sin(2 pi n / steps_per_rev), 0, 0), n = 0..n_steps."""
+    out = []
+    for n in range(n_steps + 1):
+        th = 2.0 * math.pi * n / steps_per_rev
+        out.append(M.pose_rz(th, (amp * math.sin(th), 0.0, 0.0)))
+    return out
 
 
 def batch_instances(n=64, seed=1711, n_lo=16, n_hi=96, m_lo=8, m_hi=64):
