@@ -16,6 +16,11 @@ Functions follow the paper (Crabill, Witherden & Jameson, arXiv:1711.07663):
   fringe element mapped by eq. reftophys.
 * :func:`donor_search` -- Sec. 4.3, Newton inversion of eq. reftophys with
   eq. ref-update / eq. Jac, at most 10 iterations, clamped near [-1, 1].
+* :func:`ab_faces`, :func:`face_points`, :func:`interp_weights` -- the
+  artificial-boundary (AB) method of Sec. 2: the faces between a hole and a
+  kept element (and overset-tagged faces), the flux points on them (the
+  receptor points of the AB method), and the Lagrange weights that query a
+  donor's solution polynomial at a receptor's reference location.
 """
 from __future__ import annotations
 
@@ -291,3 +296,101 @@ def donor_search(grid, pts, pose=IDENTITY, brute=False, maxit=10, threads=0):
                            _p(donor, C.c_int32), _p(xi, C.c_double), _p(iters, C.c_int32),
                            _p(ncand, C.c_int32))
     return donor, xi, dict(iters=iters, n_cand=ncand)
+
+
+# ---------------------------------------------------------------------------
+# artificial-boundary faces, flux points, interpolation weights (Sec. 2)
+# ---------------------------------------------------------------------------
+
+def ab_faces(grid, iblank, nbr=None):
+    """Artificial-boundary faces (Sec. 2, step 1; Sec. 4.2, last paragraph):
+    a face with a hole on one side and a kept (field or fringe) element on
+    the other, plus the overset-tagged faces of kept elements (the outer
+    boundary of a near-body grid, where the AB method exchanges data).
+    Each face is named from its kept side, id = 6 e + f (f in the order
+    -xi, +xi, -eta, +eta, -zeta, +zeta); ids ascending."""
+    ib = np.asarray(iblank)
+    if nbr is None:
+        nbr = face_neighbors(grid.conn)
+    kept = ib != HOLE
+    out = []
+    for f in range(6):
+        nb = nbr[:, f]
+        ab = kept & (nb >= 0)
+        ab[ab] = ib[nb[ab]] == HOLE
+        if grid.face_tags is not None:
+            ab |= kept & (np.asarray(grid.face_tags)[:, f] == TAG_OVERSET)
+        out.append(6 * np.nonzero(ab)[0].astype(np.int64) + f)
+    return np.sort(np.concatenate(out))
+
+
+def lagrange_1d(nodes1d, s):
+    """Lagrange basis through the 1-D nodes, at the values s: (len(s), m)."""
+    z = np.asarray(nodes1d, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64).reshape(-1)
+    L = np.ones((s.size, z.size))
+    for i in range(z.size):
+        for j in range(z.size):
+            if j != i:
+                L[:, i] *= (s - z[j]) / (z[i] - z[j])
+    return L
+
+
+def q2_map_points(grid, elems, xi, pose=IDENTITY):
+    """x(xi) of eq. reftophys for element elems[k] at reference point xi[k]
+    (quadratic Lagrange basis on the equispaced nodes -1, 0, 1, node order
+    a + 3b + 9c), then posed: R x + t."""
+    elems = np.asarray(elems, dtype=np.int64).reshape(-1)
+    xi = np.asarray(xi, dtype=np.float64).reshape(-1, 3)
+    eq = np.array([-1.0, 0.0, 1.0])
+    La, Lb, Lc = (lagrange_1d(eq, xi[:, d]) for d in range(3))
+    W = (La[:, None, None, :] * Lb[:, None, :, None] * Lc[:, :, None, None]).reshape(-1, 27)
+    X = np.asarray(grid.nodes, dtype=np.float64)[np.asarray(grid.conn)[elems]]   # (n, 27, 3)
+    x = np.einsum("nk,nkd->nd", W, X)
+    pose = np.asarray(pose, dtype=np.float64)
+    return x @ pose[:9].reshape(3, 3).T + pose[9:]
+
+
+def face_reference_points(f, nodes1d):
+    """Reference coordinates of the m x m flux points of local face f: the
+    face's own axis at -1 (f even) or +1 (f odd); the two other axes, in
+    increasing axis order, take nodes1d[a] and nodes1d[b], point a + m b."""
+    z = np.asarray(nodes1d, dtype=np.float64)
+    m = z.size
+    d = f // 2
+    u, v = [k for k in range(3) if k != d]
+    out = np.empty((m * m, 3))
+    out[:, d] = -1.0 if f % 2 == 0 else 1.0
+    out[:, u] = np.tile(z, m)
+    out[:, v] = np.repeat(z, m)
+    return out
+
+
+GAUSS3 = np.array([-np.sqrt(0.6), 0.0, np.sqrt(0.6)])
+
+
+def face_points(grid, faces, nodes1d=GAUSS3, pose=IDENTITY):
+    """Flux points of the faces (ids 6 e + f): m x m points per face, order
+    of face_reference_points, mapped by eq. reftophys and posed."""
+    faces = np.asarray(faces, dtype=np.int64).reshape(-1)
+    m = len(nodes1d)
+    if faces.size == 0:
+        return np.zeros((0, 3))
+    refs = np.stack([face_reference_points(f, nodes1d) for f in range(6)])   # (6, m*m, 3)
+    e = np.repeat(faces // 6, m * m)
+    xi = refs[faces % 6].reshape(-1, 3)
+    return q2_map_points(grid, e, xi, pose)
+
+
+def interp_weights(donor, ref, nodes1d=GAUSS3):
+    """Interpolation weights of the donor's nodal solution basis at each
+    receptor's reference location (Sec. 2, step 3): the tensor Lagrange
+    basis through nodes1d on each axis, weight a + m b + m^2 c =
+    l_a(xi) l_b(eta) l_c(zeta).  Orphans (donor < 0) get NaN."""
+    donor = np.asarray(donor).reshape(-1)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1, 3)
+    m = len(nodes1d)
+    La, Lb, Lc = (lagrange_1d(nodes1d, ref[:, d]) for d in range(3))
+    W = (La[:, None, None, :] * Lb[:, None, :, None] * Lc[:, :, None, None]).reshape(-1, m ** 3)
+    W[donor < 0] = np.nan
+    return W
