@@ -188,6 +188,37 @@ oc_status oc_unblank(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, int3
 oc_status oc_element_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int32_t *elems, int64_t n,
                             double *points_out, int32_t *src_out);
 
+/* Artificial-boundary (AB) faces (Sec. 2, step 1; Sec. 4.2, last
+ * paragraph): the faces of kept (field or fringe) elements of iblank (device
+ * int8 [n_elem]) whose neighbour across is a hole, and the OVERSET-tagged
+ * faces of kept elements (a near-body grid's outer boundary, where the AB
+ * method exchanges data).  Each face is named from its kept side, id =
+ * 6 e + f with f in the order -xi, +xi, -eta, +eta, -zeta, +zeta; ids are
+ * written ascending into faces_out (device int32 [cap]).  *n_out (host)
+ * receives their number (synchronises); OC_ECAPACITY if cap is too small. */
+oc_status oc_ab_faces(oc_ctx *ctx, int32_t grid_id, const int8_t *iblank, int32_t *faces_out, int64_t cap,
+                      int64_t *n_out);
+/* Flux points of faces (Sec. 2, step 2: the receptor points of the AB
+ * method): m x m points per face id of faces (device int32 [n]).  The face's
+ * own reference axis is at -1 (even f) or +1 (odd f); the two other axes, in
+ * increasing axis order, take nodes1d[a] and nodes1d[b] (host FP64 [m],
+ * 1 <= m <= 8, distinct), point a + m b.  Mapped by eq. reftophys and posed
+ * by grid_pose into points_out (device FP64 [n*m*m*3]); src_out (device int32
+ * [n*m*m], may be NULL) receives each point's face id.  An id outside
+ * [0, 6 n_elem) gives NaN points and source -1. */
+oc_status oc_face_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int32_t *faces, int64_t n,
+                         const double *nodes1d, int32_t m, double *points_out, int32_t *src_out);
+/* Interpolation weights (Sec. 2, step 3): for n receptor points with donor
+ * ids donors (device int32 [n]) and reference coordinates ref (device FP64
+ * [n*3], as oc_donor_search writes them), the m^3 values of the tensor
+ * Lagrange basis through nodes1d (host FP64 [m], 1 <= m <= 8, distinct) at
+ * the point's reference location, weight a + m b + m^2 c =
+ * (l_a(xi) l_b(eta)) l_c(zeta), l_a(s) = prod_{j != a} (s - z_j)/(z_a - z_j)
+ * with the factors taken in j order, into weights_out (device FP64
+ * [n*m^3]).  Orphans (donor < 0) get NaN weights. */
+oc_status oc_interp_weights(oc_ctx *ctx, const int32_t *donors, const double *ref, int64_t n, const double *nodes1d,
+                            int32_t m, double *weights_out);
+
 /* One request of a cut batch: grid grid_id cut by n_surf posed surfaces
  * (union of holes, as oc_cut_multi) into its own iblank_out (device int8
  * [n_elem], 4-byte aligned; no two requests of a batch may share one). */
@@ -274,6 +305,21 @@ oc_status oc_slot_fringe_points(oc_slot *slot, int32_t grid_id, const double *po
  * cap points); pose_dev: device FP64 [12]. */
 oc_status oc_slot_donor_search(oc_slot *slot, int32_t donor_grid_id, const double *pose_dev, const double *points,
                                int64_t cap, const int32_t *n_dev, int32_t *donor_out, double *ref_out);
+/* oc_ab_faces on a slot: at most cap ids written; their number goes to the
+ * device int32 *n_dev (no synchronisation). */
+oc_status oc_slot_ab_faces(oc_slot *slot, int32_t grid_id, const int8_t *iblank, int32_t *faces_out, int64_t cap,
+                           int32_t *n_dev);
+/* oc_face_points on a slot for min(*n_faces_dev, faces_cap) faces
+ * (n_faces_dev may be NULL: faces_cap); pose_dev: device FP64 [12]; at most
+ * cap points written; their number (m*m per face) goes to the device int32
+ * *n_points_dev (may be NULL). */
+oc_status oc_slot_face_points(oc_slot *slot, int32_t grid_id, const double *pose_dev, const int32_t *faces,
+                              const int32_t *n_faces_dev, int64_t faces_cap, const double *nodes1d, int32_t m,
+                              double *points_out, int64_t cap, int32_t *n_points_dev, int32_t *src_out);
+/* oc_interp_weights on a slot for min(*n_dev, cap) points (n_dev may be
+ * NULL: cap points). */
+oc_status oc_slot_interp_weights(oc_slot *slot, const int32_t *donors, const double *ref, const int32_t *n_dev,
+                                 int64_t cap, const double *nodes1d, int32_t m, double *weights_out);
 /* counters of the slot's last cut / donor search (synchronise the slot stream) */
 oc_status oc_slot_cut_info(oc_slot *slot, oc_cut_info *info);
 oc_status oc_slot_donor_info(oc_slot *slot, oc_donor_info *info);

@@ -18,80 +18,11 @@
 #include <cstring>
 
 #include "dev_common.h"
+#include "q2.h"
 
 namespace oc {
 
 constexpr int kT = 256;
-
-// ----------------------------------------------------- quadratic map ------
-__device__ inline void lag2(double s, double *l, double *dl)
-{
-    l[0] = 0.5 * s * (s - 1.0);
-    l[1] = 1.0 - s * s;
-    l[2] = 0.5 * s * (s + 1.0);
-    dl[0] = s - 0.5;
-    dl[1] = -2.0 * s;
-    dl[2] = s + 0.5;
-}
-
-__device__ inline double pick3(int i, double a, double b, double c) { return i == 0 ? a : (i == 1 ? b : c); }
-
-// One node row (fixed eta, zeta index r) of the sum-factorised map: adds its
-// share of x(xi) and, with WITH_J, of J = dx/dxi.
-template <bool WITH_J>
-__device__ inline void q2_row(const double *__restrict__ X, int r, const double *la, const double *da,
-                              const double *lb, const double *db, const double *lc, const double *dc, double *acc)
-{
-    const int b = r % 3, c = r / 3;
-    const double wb = pick3(b, lb[0], lb[1], lb[2]), wc = pick3(c, lc[0], lc[1], lc[2]);
-    const double w = wb * wc;
-    const double *R = X + 3 * r;
-    const double x0 = R[0], x1 = R[1], x2 = R[2];
-    const double y0 = R[27], y1 = R[28], y2 = R[29];
-    const double z0 = R[54], z1 = R[55], z2 = R[56];
-    const double ux = x0 * la[0] + x1 * la[1] + x2 * la[2];
-    const double uy = y0 * la[0] + y1 * la[1] + y2 * la[2];
-    const double uz = z0 * la[0] + z1 * la[1] + z2 * la[2];
-    acc[0] += ux * w;
-    acc[1] += uy * w;
-    acc[2] += uz * w;
-    if (WITH_J) {
-        const double wdb = pick3(b, db[0], db[1], db[2]) * wc;
-        const double wdc = wb * pick3(c, dc[0], dc[1], dc[2]);
-        const double vx = x0 * da[0] + x1 * da[1] + x2 * da[2];
-        const double vy = y0 * da[0] + y1 * da[1] + y2 * da[2];
-        const double vz = z0 * da[0] + z1 * da[1] + z2 * da[2];
-        acc[3] += vx * w; acc[4] += ux * wdb; acc[5] += ux * wdc;
-        acc[6] += vy * w; acc[7] += uy * wdb; acc[8] += uy * wdc;
-        acc[9] += vz * w; acc[10] += uz * wdb; acc[11] += uz * wdc;
-    }
-}
-
-// x(xi) and J = dx/dxi of an element stored as x[27], y[27], z[27].  With
-// STREAM the nine node rows are read one at a time (X in global memory, the
-// 81 coordinates never resident together); otherwise X is a register copy
-// and the rows are unrolled.  Both sum in the same order.
-template <bool WITH_J, bool STREAM>
-__device__ inline void q2_map(const double *__restrict__ X, const double *xi, double *x, double *J)
-{
-    double la[3], da[3], lb[3], db[3], lc[3], dc[3];
-    lag2(xi[0], la, da);
-    lag2(xi[1], lb, db);
-    lag2(xi[2], lc, dc);
-    double acc[12] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    if (STREAM) {
-#pragma unroll 1
-        for (int r = 0; r < 9; ++r) q2_row<WITH_J>(X, r, la, da, lb, db, lc, dc, acc);
-    } else {
-#pragma unroll
-        for (int r = 0; r < 9; ++r) q2_row<WITH_J>(X, r, la, da, lb, db, lc, dc, acc);
-    }
-    x[0] = acc[0];
-    x[1] = acc[1];
-    x[2] = acc[2];
-    if (WITH_J)
-        for (int k = 0; k < 9; ++k) J[k] = acc[3 + k];
-}
 
 // Newton inversion: xi0 = 0; stop when |x_p - x(xi)| <= 1e-13 diam (checked
 // before each step) or the clamped step is <= 1e-14; at most

@@ -106,6 +106,15 @@ static oc_status combine_overset(oc_slot *sl, Grid &g, Surf *const *surfs, int n
     return OC_OK;
 }
 
+oc_status copy_count_run(oc_slot *sl, const int32_t *src, int32_t *dst)
+{
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    LAUNCH(k_copy_i32, dim3(1), dim3(64), src, dst);
+    OC_HIP(hipGetLastError());
+    return OC_OK;
+}
+
 oc_status unblank_run(oc_slot *sl, Grid &g, Surf *const *surfs, int n_surf, const Pose *poses_t,
                       const Pose *poses_tp, const int8_t *prev, int8_t *out, int32_t *ub_list, int64_t cap,
                       int32_t *n_dev, int64_t *n_host)

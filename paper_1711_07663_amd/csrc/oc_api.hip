@@ -72,6 +72,8 @@ static oc_status slot_alloc_lists(oc_slot *sl, int64_t n_elem)
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * ne, (void **)&sl->list_fringe));
     const int64_t nt = (n_elem + 4095) / 4096;
     OC_TRY(dev_alloc(ctx, sl->owned, sizeof(int32_t) * (2 * (nt + 1) + scan_tmp_ints(nt) + 8), (void **)&sl->fr_tiles));
+    OC_TRY(dev_alloc(ctx, sl->owned, (ne + 3) / 4 * 4, (void **)&sl->ab_mask));
+    OC_HIP(hipMemset(sl->ab_mask, 0, (ne + 3) / 4 * 4));
     sl->list_cap = n_elem;
     sl->fr_tiles_cap = nt;
     return OC_OK;
@@ -408,6 +410,13 @@ oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, co
     if ((st = upload(ctx, g->owned, nbr.data(), nbr.size(), &g->nbr)) != OC_OK) return fail(st);
     g->n_overset = (int64_t)overset.size();
     if ((st = upload(ctx, g->owned, overset.data(), overset.size(), &g->overset)) != OC_OK) return fail(st);
+    if (!overset.empty()) {
+        std::vector<uint8_t> ovm((size_t)n_elem, 0);
+        for (int64_t e = 0; e < n_elem; ++e)
+            for (int f = 0; f < 6; ++f)
+                if (face_tags[e * 6 + f] == OC_FACE_OVERSET) ovm[(size_t)e] |= (uint8_t)(1u << f);
+        if ((st = upload(ctx, g->owned, ovm.data(), ovm.size(), &g->ovmask)) != OC_OK) return fail(st);
+    }
     if ((st = grid_build_device(ctx, *g, conn_dev, nodes_dev)) != OC_OK) return fail(st);
     dev_free_all(ctx, tmp);
     if ((st = grid_build_donor_bins(ctx, *g)) != OC_OK) return fail(st);
@@ -822,6 +831,87 @@ oc_status oc_element_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose
                               nullptr, src_out);
 }
 
+// ------------------------------------------------- artificial boundary --
+static oc_status get_nodes1d(const double *z, int32_t m, Nodes1D *out, const char *who)
+{
+    if (!z || m < 1 || m > kMaxNodes1D) {
+        set_error(std::string(who) + ": need 1 to " + std::to_string(kMaxNodes1D) + " one-dimensional nodes");
+        return OC_EINVAL;
+    }
+    for (int i = 0; i < kMaxNodes1D; ++i) out->z[i] = 0.0;
+    for (int i = 0; i < m; ++i) {
+        if (!std::isfinite(z[i])) {
+            set_error(std::string(who) + ": non-finite node");
+            return OC_EINVAL;
+        }
+        for (int j = 0; j < i; ++j)
+            if (z[j] == z[i]) {
+                set_error(std::string(who) + ": repeated node");
+                return OC_EINVAL;
+            }
+        out->z[i] = z[i];
+    }
+    out->m = m;
+    return OC_OK;
+}
+
+oc_status oc_ab_faces(oc_ctx *ctx, int32_t grid_id, const int8_t *iblank, int32_t *faces_out, int64_t cap,
+                      int64_t *n_out)
+{
+    if (!ctx || !iblank || !n_out || cap < 0 || (cap > 0 && !faces_out)) {
+        set_error("oc_ab_faces: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    oc_slot *sl = ctx->dflt;
+    const int32_t *total = nullptr;
+    OC_TRY(ab_faces_run(sl, *g, iblank, faces_out, cap, &total));
+    int32_t n = 0;
+    OC_HIP(hipMemcpyAsync(&n, total, sizeof(int32_t), hipMemcpyDeviceToHost, sl->stream));
+    OC_HIP(hipStreamSynchronize(sl->stream));
+    *n_out = n;
+    if (n > cap) {
+        set_error("oc_ab_faces: capacity " + std::to_string(cap) + " < " + std::to_string(n) + " faces");
+        return OC_ECAPACITY;
+    }
+    return OC_OK;
+}
+
+oc_status oc_face_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int32_t *faces, int64_t n,
+                         const double *nodes1d, int32_t m, double *points_out, int32_t *src_out)
+{
+    Nodes1D z;
+    OC_TRY(get_nodes1d(nodes1d, m, &z, "oc_face_points"));
+    if (!ctx || n < 0 || (n > 0 && (!faces || !points_out)) || !pose_ok(grid_pose) || n > INT32_MAX / (m * m)) {
+        set_error("oc_face_points: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    if (n == 0) return OC_OK;
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, kPoseSlots - 2, grid_pose, 1));
+    return face_points_run(sl, *g, sl->poses + kPoseSlots - 2, faces, nullptr, n, z, points_out, n * m * m, nullptr,
+                           src_out);
+}
+
+oc_status oc_interp_weights(oc_ctx *ctx, const int32_t *donors, const double *ref, int64_t n, const double *nodes1d,
+                            int32_t m, double *weights_out)
+{
+    Nodes1D z;
+    OC_TRY(get_nodes1d(nodes1d, m, &z, "oc_interp_weights"));
+    if (!ctx || n < 0 || (n > 0 && (!donors || !ref || !weights_out)) || n > ((int64_t)1 << 40) / (m * m * m)) {
+        set_error("oc_interp_weights: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    if (n == 0) return OC_OK;
+    return weights_run(ctx->dflt, donors, ref, nullptr, n, z, weights_out);
+}
+
 // ------------------------------------------------------------- slot API --
 oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, const int32_t *surf_ids,
                          int32_t n_surfs, int64_t points_cap, oc_slot **out)
@@ -1028,6 +1118,54 @@ oc_status oc_slot_donor_search(oc_slot *sl, int32_t donor_grid_id, const double 
     Grid *g;
     OC_TRY(get_grid(ctx, donor_grid_id, &g));
     return donor_run(sl, *g, reinterpret_cast<const Pose *>(pose_dev), points, cap, n_dev, donor_out, ref_out);
+}
+
+oc_status oc_slot_ab_faces(oc_slot *sl, int32_t grid_id, const int8_t *iblank, int32_t *faces_out, int64_t cap,
+                           int32_t *n_dev)
+{
+    if (!sl || !iblank || !n_dev || cap < 0 || (cap > 0 && !faces_out)) {
+        set_error("oc_slot_ab_faces: invalid arguments");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    const int32_t *total = nullptr;
+    OC_TRY(ab_faces_run(sl, *g, iblank, faces_out, cap, &total));
+    return copy_count_run(sl, total, n_dev);
+}
+
+oc_status oc_slot_face_points(oc_slot *sl, int32_t grid_id, const double *pose_dev, const int32_t *faces,
+                              const int32_t *n_faces_dev, int64_t faces_cap, const double *nodes1d, int32_t m,
+                              double *points_out, int64_t cap, int32_t *n_points_dev, int32_t *src_out)
+{
+    Nodes1D z;
+    OC_TRY(get_nodes1d(nodes1d, m, &z, "oc_slot_face_points"));
+    if (!sl || !pose_dev || ((uintptr_t)pose_dev & 7) || faces_cap < 0 || cap < 0 ||
+        (faces_cap > 0 && !faces) || (cap > 0 && !points_out) || faces_cap > INT32_MAX / (m * m)) {
+        set_error("oc_slot_face_points: invalid arguments");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    return face_points_run(sl, *g, reinterpret_cast<const Pose *>(pose_dev), faces, n_faces_dev, faces_cap, z,
+                           points_out, cap, n_points_dev, src_out);
+}
+
+oc_status oc_slot_interp_weights(oc_slot *sl, const int32_t *donors, const double *ref, const int32_t *n_dev,
+                                 int64_t cap, const double *nodes1d, int32_t m, double *weights_out)
+{
+    Nodes1D z;
+    OC_TRY(get_nodes1d(nodes1d, m, &z, "oc_slot_interp_weights"));
+    if (!sl || cap < 0 || (cap > 0 && (!donors || !ref || !weights_out)) || cap > ((int64_t)1 << 40) / (m * m * m)) {
+        set_error("oc_slot_interp_weights: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(sl->ctx->device));
+    return weights_run(sl, donors, ref, n_dev, cap, z, weights_out);
 }
 
 oc_status oc_slot_cut_info(oc_slot *sl, oc_cut_info *info)

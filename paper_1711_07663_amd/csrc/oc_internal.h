@@ -75,6 +75,7 @@ struct Grid {
     int32_t *nbr = nullptr;     // [n_elem][6], -1 = boundary
     int32_t *overset = nullptr; // elements with an OVERSET-tagged face (ascending)
     int64_t n_overset = 0;
+    uint8_t *ovmask = nullptr;  // [n_elem] bit f: face f OVERSET-tagged (null without tags)
     // donor search structure (registration frame)
     float *cbox = nullptr;      // [n_elem][6] control-net boxes, outward FP32
     float *obox = nullptr;      // [n_elem][18] oriented control-net boxes (centre, axes, extents)
@@ -170,6 +171,7 @@ struct oc_slot {
     int32_t *list_fringe = nullptr;
     int32_t *fr_tiles = nullptr;       // fringe compaction: counts, offsets, scan scratch
     int64_t fr_tiles_cap = 0;
+    uint32_t *ab_mask = nullptr;       // [list_cap] bytes: AB face bits per element, zero between calls
     oc::CutCounters *counters = nullptr;
     oc::DonorCounters *dcounters = nullptr;
     oc::Pose *poses = nullptr;         // [kPoseSlots] device
@@ -298,6 +300,27 @@ oc_status list_elements_run(oc_slot *sl, const Grid &g, const int8_t *iblank, co
 // 27 Gauss points of the first min(*count, cap / 27) listed elements
 oc_status element_points_run(oc_slot *sl, const Grid &g, const Pose *pose_dev, const int32_t *list,
                              const int32_t *count, double *pts, int64_t cap, int32_t *n_out, int32_t *src);
+// 1-D reference nodes of the flux points and of the interpolation basis
+constexpr int kMaxNodes1D = 8;
+struct Nodes1D {
+    double z[kMaxNodes1D];
+    int m;
+};
+// artificial-boundary faces of iblank (ids 6 e + f, ascending, at most cap
+// into faces); the count stays on the device at *total
+oc_status ab_faces_run(oc_slot *sl, const Grid &g, const int8_t *iblank, int32_t *faces, int64_t cap,
+                       const int32_t **total);
+// m x m flux points of min(*n_faces, faces_cap) faces (n_faces null:
+// faces_cap); at most cap points; n_out (device, may be null) receives the
+// number of points
+oc_status face_points_run(oc_slot *sl, const Grid &g, const Pose *pose_dev, const int32_t *faces,
+                          const int32_t *n_faces, int64_t faces_cap, const Nodes1D &z, double *pts, int64_t cap,
+                          int32_t *n_out, int32_t *src);
+// *dst = *src on the slot stream (device counts)
+oc_status copy_count_run(oc_slot *sl, const int32_t *src, int32_t *dst);
+// m^3 interpolation weights of min(*n_dev, cap) points (n_dev null: cap)
+oc_status weights_run(oc_slot *sl, const int32_t *donors, const double *ref, const int32_t *n_dev, int64_t cap,
+                      const Nodes1D &z, double *w);
 // blanking of a moving grid's time step with unblanking: cuts at poses_t
 // and poses_tp (device), combined by the surfaces' kind, fringe layer, and
 // the holes of prev that are holes no more (ascending, at most cap)

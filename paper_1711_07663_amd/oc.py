@@ -30,7 +30,8 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_slot_create", "oc_slot_destroy", "oc_slot_set_stream", "oc_slot_bytes", "oc_slot_cut",
            "oc_slot_fringe_points", "oc_slot_donor_search", "oc_slot_cut_info", "oc_slot_donor_info",
            "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm", "oc_cut_batch", "oc_slot_cut_batch",
-           "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points"]
+           "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points", "oc_ab_faces", "oc_face_points",
+           "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights"]
 
 
 class OcError(RuntimeError):
@@ -104,6 +105,12 @@ def load(path=LIB_PATH):
         "oc_tune": ([vp, C.c_int32, C.c_int32, C.c_int64, i64p]),
         "oc_unblank": ([vp, C.c_int32, i32p, C.c_int32, dp, dp, vp, vp, vp, C.c_int64, i64p]),
         "oc_element_points": ([vp, C.c_int32, dp, vp, C.c_int64, vp, vp]),
+        "oc_ab_faces": ([vp, C.c_int32, vp, vp, C.c_int64, i64p]),
+        "oc_face_points": ([vp, C.c_int32, dp, vp, C.c_int64, dp, C.c_int32, vp, vp]),
+        "oc_interp_weights": ([vp, vp, vp, C.c_int64, dp, C.c_int32, vp]),
+        "oc_slot_ab_faces": ([vp, C.c_int32, vp, vp, C.c_int64, vp]),
+        "oc_slot_face_points": ([vp, C.c_int32, vp, vp, vp, C.c_int64, dp, C.c_int32, vp, C.c_int64, vp, vp]),
+        "oc_slot_interp_weights": ([vp, vp, vp, vp, C.c_int64, dp, C.c_int32, vp]),
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -123,6 +130,14 @@ def _check(st):
 def _pose(p):
     a = np.ascontiguousarray(p, dtype=np.float64).reshape(-1)
     return a, a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+GAUSS3 = (-0.7745966692414834, 0.0, 0.7745966692414834)   # 3-point Gauss-Legendre nodes, +-sqrt(3/5)
+
+
+def _nodes1d(z):
+    a = np.ascontiguousarray(z, dtype=np.float64).reshape(-1)
+    return a, a.ctypes.data_as(C.POINTER(C.c_double)), a.size
 
 
 def _dptr(t, dtype, n=None):
@@ -282,6 +297,35 @@ class Context:
                                         _dptr(points, torch.float64, 81 * n),
                                         None if src is None else _dptr(src, torch.int32, 27 * n)))
 
+    def ab_faces(self, grid_id, iblank, faces):
+        """Artificial-boundary faces (ids 6 e + f, ascending) into ``faces``
+        (int32 device tensor); returns their number."""
+        import torch
+        n = C.c_int64(0)
+        _check(load().oc_ab_faces(self._h, grid_id, _dptr(iblank, torch.int8, self.grids[grid_id]),
+                                  _dptr(faces, torch.int32), faces.numel(), C.byref(n)))
+        return n.value
+
+    def face_points(self, grid_id, pose, faces, n, points, src=None, nodes1d=GAUSS3):
+        """m x m flux points per face id of the first n entries of ``faces``."""
+        import torch
+        _, pp = _pose(pose)
+        z, zp, m = _nodes1d(nodes1d)
+        if n == 0:
+            return
+        _check(load().oc_face_points(self._h, grid_id, pp, _dptr(faces, torch.int32, n), int(n), zp, m,
+                                     _dptr(points, torch.float64, 3 * m * m * n),
+                                     None if src is None else _dptr(src, torch.int32, m * m * n)))
+
+    def interp_weights(self, donors, ref, n, weights, nodes1d=GAUSS3):
+        """m^3 Lagrange weights per receptor (NaN for orphans)."""
+        import torch
+        z, zp, m = _nodes1d(nodes1d)
+        if n == 0:
+            return
+        _check(load().oc_interp_weights(self._h, _dptr(donors, torch.int32, n), _dptr(ref, torch.float64, 3 * n),
+                                        int(n), zp, m, _dptr(weights, torch.float64, n * m ** 3)))
+
     def sweep_bound(self, surf_id, pose_a, pose_b):
         _, pa = _pose(pose_a)
         _, pb = _pose(pose_b)
@@ -427,6 +471,28 @@ class Slot:
                                            _dptr(points, torch.float64, 3 * cap), int(cap),
                                            _dev_or_null(n_dev, torch.int32), _dptr(donor, torch.int32, cap),
                                            _dptr(ref, torch.float64, 3 * cap)))
+
+    def ab_faces(self, grid_id, iblank, faces, n_dev):
+        import torch
+        _check(load().oc_slot_ab_faces(self._h, grid_id, _dptr(iblank, torch.int8, self.ctx.grids[grid_id]),
+                                       _dptr(faces, torch.int32), faces.numel(), _dptr(n_dev, torch.int32, 1)))
+
+    def face_points(self, grid_id, pose_dev, faces, n_faces_dev, points, n_dev, src=None, nodes1d=GAUSS3):
+        import torch
+        z, zp, m = _nodes1d(nodes1d)
+        cap = points.numel() // 3
+        _check(load().oc_slot_face_points(self._h, grid_id, _dptr(pose_dev, torch.float64, 12),
+                                          _dptr(faces, torch.int32), _dev_or_null(n_faces_dev, torch.int32),
+                                          faces.numel(), zp, m, _dptr(points, torch.float64), cap,
+                                          _dev_or_null(n_dev, torch.int32),
+                                          None if src is None else _dptr(src, torch.int32, cap)))
+
+    def interp_weights(self, donors, ref, cap, n_dev, weights, nodes1d=GAUSS3):
+        import torch
+        z, zp, m = _nodes1d(nodes1d)
+        _check(load().oc_slot_interp_weights(self._h, _dptr(donors, torch.int32, cap), _dptr(ref, torch.float64, 3 * cap),
+                                             _dev_or_null(n_dev, torch.int32), int(cap), zp, m,
+                                             _dptr(weights, torch.float64, cap * m ** 3)))
 
     def cut_info(self):
         info = oc_cut_info()

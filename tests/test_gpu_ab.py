@@ -1,0 +1,220 @@
+"""Artificial-boundary method (Sec. 2) through the C ABI against the oracle:
+AB faces of a cut background and of a near-body grid, their flux points,
+the donors of those points and the interpolation weights at the donors'
+reference coordinates."""
+import sys
+
+import numpy as np
+import pytest
+
+from workloads import meshes as M
+
+from parity_util import PT_TOL, XI_TOL
+
+pytestmark = pytest.mark.gpu
+
+GAUSS4 = np.polynomial.legendre.leggauss(4)[0]
+
+
+def _note(msg):
+    print("[gpu-case] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_1711_07663_amd import oc
+    c = oc.Context(device=0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _case():
+    bg = M.background_grid(18, -1.3, 1.3, amp=0.03)
+    s = M.cube_sphere(6, R=0.45, dimples=24, dimple_a=0.08, dimple_k=0.02)
+    sh = M.shell_grid(s, 3, r_out=0.9)
+    return bg, s, sh
+
+
+def _t(a, dtype):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def test_ab_faces_points_donors_weights(ctx, orc):
+    """Both directions of one AB step: the background's AB faces (around the
+    holes) with flux points and donors in the posed shell, and the shell's
+    AB faces (its overset outer boundary) with donors in the background;
+    weights for the 3-point Gauss and the 4-point Gauss bases."""
+    import torch
+    _note("AB step, dimpled sphere on an 18^3 background")
+    bg, s, sh = _case()
+    pose = M.pose_rz(0.5, (0.07, -0.04, 0.02))
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    shid = ctx.register_grid(sh.nodes, sh.conn, sh.face_tags)
+    ib = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+    ib_sh = torch.empty(sh.n_elem, dtype=torch.int8, device="cuda")
+    ctx.cut(gid, sid, pose, ib)
+    ctx.cut_multi(shid, [], np.zeros(12), ib_sh)
+    ib_o = orc.cut(bg, [s], [pose])
+    ib_sh_o = orc.cut(sh, [], [])
+    assert np.array_equal(ib.cpu().numpy(), ib_o) and np.array_equal(ib_sh.cpu().numpy(), ib_sh_o)
+    for name, g_id, grid, ibd, ibo, dgid, dgrid, gpose, dpose in (
+            ("bg->shell", gid, bg, ib, ib_o, shid, sh, M.IDENTITY_POSE, pose),
+            ("shell->bg", shid, sh, ib_sh, ib_sh_o, gid, bg, pose, M.IDENTITY_POSE)):
+        _note(name)
+        faces = torch.empty(6 * grid.n_elem, dtype=torch.int32, device="cuda")
+        n = ctx.ab_faces(g_id, ibd, faces)
+        f_o = orc.ab_faces(grid, ibo)
+        assert n == f_o.size > 0
+        assert np.array_equal(faces[:n].cpu().numpy(), f_o), name
+        for z in (orc.GAUSS3, GAUSS4):
+            m = z.size
+            npts = n * m * m
+            pts = torch.empty((npts, 3), dtype=torch.float64, device="cuda")
+            src = torch.empty(npts, dtype=torch.int32, device="cuda")
+            ctx.face_points(g_id, gpose, faces, n, pts, src, nodes1d=z)
+            p_o = orc.face_points(grid, f_o, z, gpose)
+            donor = torch.empty(npts, dtype=torch.int32, device="cuda")
+            ref = torch.empty((npts, 3), dtype=torch.float64, device="cuda")
+            ctx.donor_search(dgid, dpose, pts, npts, donor, ref)
+            w = torch.empty((npts, m ** 3), dtype=torch.float64, device="cuda")
+            ctx.interp_weights(donor, ref, npts, w, nodes1d=z)
+            torch.cuda.synchronize()
+            pts_g = pts.cpu().numpy()
+            assert np.abs(pts_g - p_o).max() <= PT_TOL
+            assert np.array_equal(src.cpu().numpy(), np.repeat(f_o, m * m))
+            d_o, r_o, _ = orc.donor_search(dgrid, pts_g, dpose)
+            d_g, r_g = donor.cpu().numpy(), ref.cpu().numpy()
+            assert np.array_equal(d_g, d_o), name
+            ok = d_o >= 0
+            assert ok.sum() > 0.9 * ok.size
+            assert np.abs(r_g[ok] - r_o[ok]).max() <= XI_TOL
+            # weights at the GPU's reference coordinates: same operations, same order
+            w_o = orc.interp_weights(d_g, r_g, z)
+            w_g = w.cpu().numpy()
+            assert np.array_equal(np.isnan(w_g), np.isnan(w_o))
+            assert np.abs(w_g[ok] - w_o[ok]).max() <= 1e-15
+            assert np.abs(w_g[ok].sum(axis=1) - 1.0).max() <= 1e-12
+
+
+def test_ab_mask_is_clean_between_calls(ctx, orc):
+    """Consecutive calls on different blankings (the per-element mask is
+    cleared by each call), with a request too small for the faces."""
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("AB faces: consecutive calls, capacity")
+    bg, s, _ = _case()
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    ib = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+    faces = torch.empty(6 * bg.n_elem, dtype=torch.int32, device="cuda")
+    for k, pose in enumerate([M.pose_rz(0.2 * k, (0.1 * k - 0.15, 0.0, 0.05)) for k in range(4)]):
+        ctx.cut(gid, sid, pose, ib)
+        if k == 2:
+            with pytest.raises(oc.OcError) as e:
+                ctx.ab_faces(gid, ib, faces[:5])
+            assert e.value.status == oc.OC_ECAPACITY
+            continue
+        n = ctx.ab_faces(gid, ib, faces)
+        torch.cuda.synchronize()
+        f_o = orc.ab_faces(bg, orc.cut(bg, [s], [pose]))
+        assert n == f_o.size and np.array_equal(faces[:n].cpu().numpy(), f_o), "call %d" % k
+    # no hole: no AB face
+    ib.fill_(1)
+    assert ctx.ab_faces(gid, ib, faces) == 0
+
+
+def test_ab_argument_errors(ctx):
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("AB argument errors and bad face ids")
+    bg = M.background_grid(5, -1.0, 1.0, amp=0.04)
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    faces = torch.tensor([7, -3, 6 * bg.n_elem, 6 * bg.n_elem - 1], dtype=torch.int32, device="cuda")
+    pts = torch.empty((4 * 9, 3), dtype=torch.float64, device="cuda")
+    src = torch.empty(4 * 9, dtype=torch.int32, device="cuda")
+    ctx.face_points(gid, M.IDENTITY_POSE, faces, 4, pts, src)
+    torch.cuda.synchronize()
+    p = pts.cpu().numpy().reshape(4, 9, 3)
+    s = src.cpu().numpy().reshape(4, 9)
+    assert np.all(np.isnan(p[1:3])) and np.all(s[1:3] == -1)
+    assert not np.any(np.isnan(p[[0, 3]])) and np.all(s[0] == 7)
+    for bad in ([], [0.1] * 9, [0.2, 0.2, 0.5], [0.0, np.nan]):
+        with pytest.raises(oc.OcError) as e:
+            ctx.face_points(gid, M.IDENTITY_POSE, faces, 4, torch.empty((4 * 81, 3), dtype=torch.float64,
+                                                                        device="cuda"), nodes1d=bad)
+        assert e.value.status == oc.OC_EINVAL
+    d = torch.zeros(2, dtype=torch.int32, device="cuda")
+    r = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(oc.OcError) as e:
+        ctx.interp_weights(d, r, 2, torch.empty((2, 27), dtype=torch.float64, device="cuda"), nodes1d=[1.0, 1.0])
+    assert e.value.status == oc.OC_EINVAL
+
+
+def test_slot_ab_matches_context_and_replays(ctx, orc):
+    """The slot calls (device counts, no synchronisation) give the context
+    calls' results, eagerly and from a captured graph replayed at new poses."""
+    import torch
+    _note("AB on a slot: eager and graph replay")
+    bg, s, sh = _case()
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    shid = ctx.register_grid(sh.nodes, sh.conn, sh.face_tags)
+    slot = ctx.create_slot([gid, shid], [sid], points_cap=27 * 4000)
+    ib = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+    faces = torch.empty(6 * 4000, dtype=torch.int32, device="cuda")
+    nf = torch.zeros(1, dtype=torch.int32, device="cuda")
+    npts = torch.zeros(1, dtype=torch.int32, device="cuda")
+    cap = 9 * 4000
+    pts = torch.empty((cap, 3), dtype=torch.float64, device="cuda")
+    donor = torch.empty(cap, dtype=torch.int32, device="cuda")
+    ref = torch.empty((cap, 3), dtype=torch.float64, device="cuda")
+    w = torch.empty((cap, 27), dtype=torch.float64, device="cuda")
+    poses = torch.zeros((1, 12), dtype=torch.float64, device="cuda")
+    ident = torch.from_numpy(M.IDENTITY_POSE.copy()).cuda()
+
+    def launch():
+        slot.cut(gid, [sid], poses, ib)
+        slot.ab_faces(gid, ib, faces, nf)
+        slot.face_points(gid, ident, faces, nf, pts, npts)
+        slot.donor_search(shid, poses[0], pts, cap, npts, donor, ref)
+        slot.interp_weights(donor, ref, cap, npts, w)
+
+    def check(pose):
+        torch.cuda.synchronize()
+        n = int(nf.item())
+        f_o = orc.ab_faces(bg, orc.cut(bg, [s], [pose]))
+        assert n == f_o.size and np.array_equal(faces[:n].cpu().numpy(), f_o)
+        assert int(npts.item()) == 9 * n
+        p_o = orc.face_points(bg, f_o)
+        assert np.abs(pts[:9 * n].cpu().numpy() - p_o).max() <= PT_TOL
+        d_o, r_o, _ = orc.donor_search(sh, pts[:9 * n].cpu().numpy(), pose)
+        assert np.array_equal(donor[:9 * n].cpu().numpy(), d_o)
+        w_o = orc.interp_weights(donor[:9 * n].cpu().numpy(), ref[:9 * n].cpu().numpy())
+        ok = d_o >= 0
+        assert np.abs(w[:9 * n].cpu().numpy()[ok] - w_o[ok]).max() <= 1e-15
+
+    rng = np.random.default_rng(4)
+    sets = [M.pose_rz(rng.uniform(0, 6.28), rng.uniform(-0.15, 0.15, 3)) for _ in range(3)]
+    with torch.cuda.stream(slot.stream):
+        poses.copy_(torch.from_numpy(sets[0]).reshape(1, 12))
+    torch.cuda.synchronize()
+    with torch.cuda.stream(slot.stream):
+        launch()
+    check(sets[0])
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph):
+        slot.set_stream(torch.cuda.current_stream())
+        launch()
+    slot.set_stream(slot.stream)
+    for k in (1, 2, 1):
+        poses.copy_(torch.from_numpy(sets[k]).reshape(1, 12))
+        torch.cuda.synchronize()
+        graph.replay()
+        check(sets[k])
+    slot.close()
