@@ -16,6 +16,10 @@ Other workloads (--workload):
          against the same instances cut one at a time;
   serve  Poisson arrivals over four device-resident grid sets served with
          continuous batching, against one-at-a-time service;
+  ab     the dimpled case with the receptors of the artificial-boundary
+         method: AB faces of the background and of the shell, 3 x 3 Gauss
+         flux points per face, their donors and 27 interpolation weights per
+         point, both directions, replayed as a HIP graph;
   unblank  the dimpled sphere turning and oscillating (amplitude 0.5) through
          the background: per step the background is cut at the poses of t
          and t + dt (wall rule: union of holes), the cells to unblank are
@@ -90,7 +94,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1, help="oracle runs on every k-th element / point")
     ap.add_argument("--bg", type=int, default=128)
-    ap.add_argument("--workload", default="dimpled", choices=["dimpled", "spin", "batch", "serve", "unblank"])
+    ap.add_argument("--workload", default="dimpled", choices=["dimpled", "spin", "batch", "serve", "unblank", "ab"])
     ap.add_argument("--spin-steps", type=int, default=200)
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--rates", default="50,100,200,500", help="serve: arrival rates, requests/s")
@@ -160,7 +164,7 @@ def main():
         log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
         del src, dst
     out = dict(dimpled=run_dimpled, spin=run_spin, batch=run_batch, serve=run_serve,
-               unblank=run_unblank)[a.workload](a)
+               unblank=run_unblank, ab=run_ab)[a.workload](a)
     print(json.dumps(out), flush=True)
 
 
@@ -383,6 +387,90 @@ def run_spin(a):
                            bg_elements=bg.n_elem, sweep_bound=sweep, parallelism="1 GPU"),
                latency_ms=_percentiles(lat), plain_ms_per_step=ms_plain, speedup_vs_plain=ms_plain / ms,
                last_warm_cut_info=cut, per_kernel=per_kernel)
+    ctx.close()
+    return out
+
+
+def run_ab(a):
+    """The dimpled 128^3 step with the artificial-boundary receptors (Sec. 2):
+    cut, AB faces of the background and of the shell, 9 flux points per face,
+    donors in the other grid and 27 weights per point, both directions; the
+    two-chain step replayed from its captured graph."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from paper_1711_07663_amd.pipeline import OversetSystem, SlotStep
+    from workloads import configs as CF
+    log("generating the dimpled-sphere workload")
+    case = CF.dimpled(bg_n=a.bg)
+    bg = case["bg"]
+    torch.cuda.set_device(0)
+    ctx = oc.Context(device=0)
+    system = OversetSystem(ctx, case, bg_points_cap=27 * 40000)
+    poses = case["poses"]
+    ss = SlotStep(system, ab=True)
+    # the plain step: the same launches, eager, chains one after the other,
+    # waiting for each step
+    for _ in range(a.warmup):
+        ss.step(poses, serial=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ss.step(poses, serial=True)
+        ss.stream.synchronize()
+    ms_plain = 1e3 * (time.perf_counter() - t0) / a.steps
+    counts = ss.counts()
+    info_a, info_b = ss.slot.donor_info(), ss.slot_b.donor_info()
+    ss.capture()
+    table = ss.pose_table_dev(poses)
+    for _ in range(a.warmup):
+        ss.replay_table(table)
+    torch.cuda.synchronize()
+    log("graph-replayed AB steps, %d timed" % a.steps)
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        ss.replay_table(table)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / a.steps
+    evs = []
+    for _ in range(a.steps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(ss.stream)
+        ss.replay_table(table)
+        e1.record(ss.stream)
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    lat = [x.elapsed_time(y) * 1e-3 for x, y in evs]
+    ctx.timing(True)
+    for _ in range(a.steps):
+        ss.step(poses, serial=True)
+    rep = ctx.timing_report()
+    ctx.timing(False)
+    per_kernel = {k: dict(total_ms=v[0], launches=v[1], avg_us=1e3 * v[0] / max(v[1], 1)) for k, v in rep.items()}
+    n_pts = counts["n_bg_points"] + sum(counts["n_shell_points"])
+    # the weights kernel streams its output: 27 FP64 weights (216 B) written
+    # and one point's donor and reference coordinates (28 B) read per point
+    kw = per_kernel.get("k_interp_weights")
+    roof_w = None
+    if kw:
+        bytes_per_launch = 244.0 * n_pts / kw["launches"] * a.steps
+        achieved = bytes_per_launch / (kw["avg_us"] * 1e-6) / 1e9
+        roof_w = dict(bound="hbm", kernel="k_interp_weights", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                      frac=achieved / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=bytes_per_launch,
+                      avg_launch_us=kw["avg_us"])
+    out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
+               value=bg.n_elem / (ms / 1e3), unit="elements/s", n_gpus=1, steps=a.steps, warmup=a.warmup,
+               ms_per_step=ms, higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+               data="synthetic",
+               config=dict(workload="dimpled sphere, artificial-boundary receptors: %d^3 background, 24576-face "
+                                    "300-dimple sphere, 8-layer shell; cut + AB faces + 3x3 Gauss flux points + "
+                                    "Newton donors + 27 interpolation weights per point, both directions" % a.bg,
+                           bg_elements=bg.n_elem, parallelism="1 GPU"),
+               donors_per_s=n_pts / (ms / 1e3), points_per_step=n_pts, counts=counts,
+               donor_info=dict(bg_to_shell=info_a, shell_to_bg=info_b),
+               latency_ms=_percentiles(lat), plain_ms_per_step=ms_plain, speedup_vs_plain=ms_plain / ms,
+               per_kernel=per_kernel, roofline_weights=roof_w)
+    ss.close()
     ctx.close()
     return out
 

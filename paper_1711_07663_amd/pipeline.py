@@ -8,6 +8,11 @@ Step (Sec. 2.1 steps 1-2, Sec. 4.2, Sec. 4.3):
      its overset-tagged outer faces give its fringe elements;
   3. Gauss receptor points of the background fringe -> donors in each shell;
   4. Gauss receptor points of each shell's fringe -> donors in the background.
+
+SlotStep(ab=True) takes the receptors of the artificial-boundary method
+(Sec. 2) instead: the flux points of each grid's AB faces (faces between a
+kept cell and a hole, and a shell's overset outer faces), their donors, and
+the interpolation weights of the donor's solution basis at each receptor.
 """
 from __future__ import annotations
 
@@ -48,7 +53,8 @@ class OversetSystem:
             s, sh = b["surface"], b["shell"]
             sid = ctx.register_cut_surface(s.nodes, s.conn, _oc.OC_SURF_WALL)
             gid = ctx.register_grid(sh.nodes, sh.conn, sh.face_tags)
-            self.bodies.append(dict(surf=sid, shell=gid, n_shell=sh.n_elem))
+            n_tagged = 0 if sh.face_tags is None else int((np.asarray(sh.face_tags) == _oc.OC_FACE_OVERSET).sum())
+            self.bodies.append(dict(surf=sid, shell=gid, n_shell=sh.n_elem, n_tagged=n_tagged))
         self.ib_bg = torch.empty(self.n_bg, dtype=torch.int8, device=dev)
         cap_bg = bg_points_cap or 27 * self.n_bg
         self.pts_bg = torch.empty((cap_bg, 3), dtype=torch.float64, device=dev)
@@ -115,6 +121,31 @@ def _alloc_outputs(system, dev, n_ib_bg=1):
     return out
 
 
+def _alloc_ab_outputs(system, dev, n_ib_bg, faces_bg_cap, faces_sh_caps, m):
+    """Device output buffers of one AB step: face ids, m*m flux points per
+    face, donors and m^3 weights per point."""
+    mm, m3 = m * m, m ** 3
+    cap_bg = faces_bg_cap * mm
+    out = dict(ib_bg=[torch.empty(system.n_bg, dtype=torch.int8, device=dev) for _ in range(n_ib_bg)],
+               faces_bg=torch.empty(faces_bg_cap, dtype=torch.int32, device=dev),
+               pts_bg=torch.empty((cap_bg, 3), dtype=torch.float64, device=dev),
+               src_bg=torch.empty(cap_bg, dtype=torch.int32, device=dev), bodies=[])
+    for b, fcap in zip(system.bodies, faces_sh_caps):
+        cap = fcap * mm
+        out["bodies"].append(dict(
+            ib=torch.empty(b["n_shell"], dtype=torch.int8, device=dev),
+            faces=torch.empty(fcap, dtype=torch.int32, device=dev),
+            pts=torch.empty((cap, 3), dtype=torch.float64, device=dev),
+            src=torch.empty(cap, dtype=torch.int32, device=dev),
+            donor=torch.empty(cap, dtype=torch.int32, device=dev),
+            ref=torch.empty((cap, 3), dtype=torch.float64, device=dev),
+            w=torch.empty((cap, m3), dtype=torch.float64, device=dev),
+            donor_bg=torch.empty(cap_bg, dtype=torch.int32, device=dev),
+            ref_bg=torch.empty((cap_bg, 3), dtype=torch.float64, device=dev),
+            w_bg=torch.empty((cap_bg, m3), dtype=torch.float64, device=dev)))
+    return out
+
+
 class SlotStep:
     """The connectivity step of an OversetSystem on slots of its own: poses
     and point counts live on the device, the outputs belong to this object
@@ -141,7 +172,8 @@ class SlotStep:
     poses); the two iblank buffers alternate, so a captured step exists for
     each parity."""
 
-    def __init__(self, system: OversetSystem, stream=None, warm=False, sweep=0.0):
+    def __init__(self, system: OversetSystem, stream=None, warm=False, sweep=0.0, ab=False, ab_faces_cap=None,
+                 nodes1d=_oc.GAUSS3):
         self.sys = system
         ctx = system.ctx
         dev = torch.device("cuda", ctx.device)
@@ -150,15 +182,25 @@ class SlotStep:
             raise ValueError("warm start needs exactly one body")
         grids = [system.bg_id] + [b["shell"] for b in system.bodies]
         surfs = [b["surf"] for b in system.bodies]
-        cap = max([system.pts_bg.shape[0]] + [b["pts"].shape[0] for b in system.bodies])
+        self.ab = ab
+        self.nodes1d = tuple(float(v) for v in nodes1d)
+        if ab:
+            m = len(self.nodes1d)
+            if ab_faces_cap is None:
+                ab_faces_cap = [system.pts_bg.shape[0] // (m * m)] + [2 * b["n_tagged"] + 8192 for b in system.bodies]
+            self.out = _alloc_ab_outputs(system, dev, 2 if warm else 1, ab_faces_cap[0], ab_faces_cap[1:], m)
+            cap = max([self.out["pts_bg"].shape[0]] + [b["pts"].shape[0] for b in self.out["bodies"]])
+        else:
+            self.out = _alloc_outputs(system, dev, 2 if warm else 1)
+            cap = max([system.pts_bg.shape[0]] + [b["pts"].shape[0] for b in system.bodies])
         self.slot = ctx.create_slot(grids, surfs, cap, stream)
         self.slot_b = ctx.create_slot(grids, surfs, cap)
         self.n_pose = nb + nb * (nb - 1) + 1
         self.poses_dev = torch.zeros((self.n_pose, 12), dtype=torch.float64, device=dev)
         self.n_dev = torch.zeros(1 + nb, dtype=torch.int32, device=dev)
+        self.nf_dev = torch.zeros(1 + nb, dtype=torch.int32, device=dev)
         self.warm = warm
         self.sweep = float(sweep)
-        self.out = _alloc_outputs(system, dev, 2 if warm else 1)
         self.k = 0              # steps launched (selects the iblank buffer when warm)
         self.graphs = {}
 
@@ -212,10 +254,18 @@ class SlotStep:
         else:
             sa.cut(s.bg_id, sids, self.poses_dev[:nb], ib_bg)
         cap_bg = o["pts_bg"].shape[0]
-        sa.fringe_points(s.bg_id, ident, ib_bg, o["pts_bg"], self.n_dev[0:1], o["src_bg"])
+        z = self.nodes1d
+        if self.ab:
+            sa.ab_faces(s.bg_id, ib_bg, o["faces_bg"], self.nf_dev[0:1])
+            sa.face_points(s.bg_id, ident, o["faces_bg"], self.nf_dev[0:1], o["pts_bg"], self.n_dev[0:1], o["src_bg"],
+                           nodes1d=z)
+        else:
+            sa.fringe_points(s.bg_id, ident, ib_bg, o["pts_bg"], self.n_dev[0:1], o["src_bg"])
         for i, b in enumerate(o["bodies"]):
             sa.donor_search(s.bodies[i]["shell"], self.poses_dev[i], o["pts_bg"], cap_bg, self.n_dev[0:1],
                             b["donor_bg"], b["ref_bg"])
+            if self.ab:
+                sa.interp_weights(b["donor_bg"], b["ref_bg"], cap_bg, self.n_dev[0:1], b["w_bg"], nodes1d=z)
         # chain B: shells
         r = nb
         for i, b in enumerate(s.bodies):
@@ -224,8 +274,16 @@ class SlotStep:
             sb.cut(b["shell"], others, self.poses_dev[r:r + nb - 1], ob["ib"])
             r += nb - 1
             cap = ob["pts"].shape[0]
-            sb.fringe_points(b["shell"], self.poses_dev[i], ob["ib"], ob["pts"], self.n_dev[1 + i:2 + i], ob["src"])
-            sb.donor_search(s.bg_id, ident, ob["pts"], cap, self.n_dev[1 + i:2 + i], ob["donor"], ob["ref"])
+            nd = self.n_dev[1 + i:2 + i]
+            if self.ab:
+                sb.ab_faces(b["shell"], ob["ib"], ob["faces"], self.nf_dev[1 + i:2 + i])
+                sb.face_points(b["shell"], self.poses_dev[i], ob["faces"], self.nf_dev[1 + i:2 + i], ob["pts"], nd,
+                               ob["src"], nodes1d=z)
+            else:
+                sb.fringe_points(b["shell"], self.poses_dev[i], ob["ib"], ob["pts"], nd, ob["src"])
+            sb.donor_search(s.bg_id, ident, ob["pts"], cap, nd, ob["donor"], ob["ref"])
+            if self.ab:
+                sb.interp_weights(ob["donor"], ob["ref"], cap, nd, ob["w"], nodes1d=z)
         if serial:
             sb.set_stream(sb.stream)
         else:
@@ -284,7 +342,11 @@ class SlotStep:
         """Point counts (waits for the slot stream)."""
         self.slot.stream.synchronize()
         n = self.n_dev.cpu().tolist()
-        return dict(n_bg_points=n[0], n_shell_points=n[1:])
+        out = dict(n_bg_points=n[0], n_shell_points=n[1:])
+        if self.ab:
+            f = self.nf_dev.cpu().tolist()
+            out.update(n_bg_faces=f[0], n_shell_faces=f[1:])
+        return out
 
     def snapshot(self):
         """Host copy of the last step's outputs (synchronises)."""
@@ -293,9 +355,16 @@ class SlotStep:
         o = self.out
         out = dict(ib_bg=self.ib_bg().cpu().numpy(), pts_bg=o["pts_bg"][:n_bg].cpu().numpy(),
                    src_bg=o["src_bg"][:n_bg].cpu().numpy(), bodies=[])
-        for b, n in zip(o["bodies"], c["n_shell_points"]):
-            out["bodies"].append(dict(ib=b["ib"].cpu().numpy(), pts=b["pts"][:n].cpu().numpy(),
-                                      src=b["src"][:n].cpu().numpy(), donor_bg=b["donor_bg"][:n_bg].cpu().numpy(),
-                                      ref_bg=b["ref_bg"][:n_bg].cpu().numpy(), donor=b["donor"][:n].cpu().numpy(),
-                                      ref=b["ref"][:n].cpu().numpy()))
+        nf = self.nf_dev.cpu().tolist()
+        if self.ab:
+            out["faces_bg"] = o["faces_bg"][:nf[0]].cpu().numpy()
+        for i, (b, n) in enumerate(zip(o["bodies"], c["n_shell_points"])):
+            d = dict(ib=b["ib"].cpu().numpy(), pts=b["pts"][:n].cpu().numpy(),
+                     src=b["src"][:n].cpu().numpy(), donor_bg=b["donor_bg"][:n_bg].cpu().numpy(),
+                     ref_bg=b["ref_bg"][:n_bg].cpu().numpy(), donor=b["donor"][:n].cpu().numpy(),
+                     ref=b["ref"][:n].cpu().numpy())
+            if self.ab:
+                d.update(faces=b["faces"][:nf[1 + i]].cpu().numpy(), w=b["w"][:n].cpu().numpy(),
+                         w_bg=b["w_bg"][:n_bg].cpu().numpy())
+            out["bodies"].append(d)
         return out

@@ -90,3 +90,53 @@ def compare(g, o):
         # each side's own points are compared
         _cmp_donors(gb["donor_bg"], gb["ref_bg"], ob["donor_bg"], ob["ref_bg"], "bg->shell %d" % k)
         _cmp_donors(gb["donor"], gb["ref"], ob["donor"], ob["ref"], "shell %d->bg" % k)
+
+
+def oracle_ab_step(case, poses, nodes1d=O.GAUSS3, threads=0, ib_bg=None):
+    """The artificial-boundary step computed by the oracle alone: AB faces of
+    the background and of each shell, their flux points and donors (weights
+    are compared at the GPU's own reference coordinates, see compare_ab).
+    ib_bg: the background blanking when already known."""
+    bg = case["bg"]
+    walls = [b["surface"] for b in case["bodies"]]
+    m2 = len(nodes1d) ** 2
+    out = {}
+    out["ib_bg"] = O.cut(bg, walls, poses, threads=threads) if ib_bg is None else ib_bg
+    out["faces_bg"] = O.ab_faces(bg, out["ib_bg"])
+    out["pts_bg"] = O.face_points(bg, out["faces_bg"], nodes1d)
+    out["src_bg"] = np.repeat(out["faces_bg"], m2)
+    out["bodies"] = []
+    for i, b in enumerate(case["bodies"]):
+        others = [j for j in range(len(walls)) if j != i]
+        inv = pose_inverse(poses[i])
+        ib = O.cut(b["shell"], [walls[j] for j in others], [pose_compose(inv, poses[j]) for j in others],
+                   threads=threads)
+        faces = O.ab_faces(b["shell"], ib)
+        pts = O.face_points(b["shell"], faces, nodes1d, poses[i])
+        d_bg, r_bg, _ = O.donor_search(b["shell"], out["pts_bg"], poses[i], threads=threads)
+        d, r, _ = O.donor_search(bg, pts, threads=threads)
+        out["bodies"].append(dict(ib=ib, faces=faces, pts=pts, src=np.repeat(faces, m2), donor_bg=d_bg,
+                                  ref_bg=r_bg, donor=d, ref=r))
+    return out
+
+
+def _cmp_weights(w_g, donor, ref, nodes1d, what):
+    w_o = O.interp_weights(donor, ref, nodes1d)
+    assert w_g.shape == w_o.shape, what
+    assert np.array_equal(np.isnan(w_g), np.isnan(w_o)), what
+    ok = donor >= 0
+    if ok.any():
+        err = np.abs(w_g[ok] - w_o[ok]).max()
+        assert err <= 1e-15, "%s: max |w_gpu - w_oracle| = %g" % (what, err)
+
+
+def compare_ab(g, o, nodes1d=O.GAUSS3):
+    """compare() plus bit-exact AB face lists and the weights, which the
+    oracle evaluates at the GPU's reference coordinates (the same operations
+    in the same order)."""
+    compare(g, o)
+    assert np.array_equal(g["faces_bg"], o["faces_bg"])
+    for k, (gb, ob) in enumerate(zip(g["bodies"], o["bodies"])):
+        assert np.array_equal(gb["faces"], ob["faces"]), "shell %d AB faces" % k
+        _cmp_weights(gb["w_bg"], gb["donor_bg"], gb["ref_bg"], nodes1d, "bg->shell %d weights" % k)
+        _cmp_weights(gb["w"], gb["donor"], gb["ref"], nodes1d, "shell %d->bg weights" % k)

@@ -166,3 +166,48 @@ def test_moving_full_size_unblank(orc):
     ok = d_o >= 0
     assert ok.any() and np.abs(r_g[ok] - r_o[ok]).max() <= XI_TOL
     assert np.all(np.isnan(r_g[~ok]))
+
+
+def test_ab_full_size(orc):
+    """The artificial-boundary step at full size (the benchmark's ab
+    workload, graph-replayed two-chain step): AB faces of the 128^3
+    background and of the shell, 9 flux points per face, donors in both
+    directions and 27 weights per point.  The background blanking is the
+    oracle's band cut (every other element is field)."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from paper_1711_07663_amd.pipeline import OversetSystem, SlotStep
+    from parity_util import compare_ab, oracle_ab_step
+
+    _note("full-size AB step: generating inputs")
+    case = CF.dimpled()
+    bg, body = case["bg"], case["bodies"][0]
+    s = body["surface"]
+    ctx = oc.Context(device=0)
+    try:
+        system = OversetSystem(ctx, case, bg_points_cap=27 * 40000)
+        ss = SlotStep(system, ab=True)
+        _note("full-size AB step: eager step, capture, replay")
+        ss.step(case["poses"])
+        ss.capture()
+        ss.replay(case["poses"])
+        got = ss.snapshot()
+        c = ss.counts()
+        ss.close()
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+    assert c["n_shell_faces"][0] == s.n_face and c["n_bg_faces"] > 1000
+
+    _note("full-size AB step: oracle band cut, AB faces, points, donors")
+    P = bg.nodes[bg.conn]
+    elo, ehi = P.min(axis=1), P.max(axis=1)
+    del P
+    h = 6.0 / 128
+    slo, shi = s.nodes.min(axis=0), s.nodes.max(axis=0)
+    band = np.nonzero(np.all(ehi >= slo - 2 * h, axis=1) & np.all(elo <= shi + 2 * h, axis=1))[0]
+    st = orc.cut_surface(bg, s, orc.IDENTITY, sel=band, threads=0)
+    hole = np.zeros(bg.n_elem, dtype=bool)
+    hole[band] = st == 0
+    ib_o = orc.mark_fringe(hole, orc.face_neighbors(bg.conn))
+    compare_ab(got, oracle_ab_step(case, case["poses"], ib_bg=ib_o))
