@@ -16,6 +16,10 @@ Functions follow the paper (Crabill, Witherden & Jameson, arXiv:1711.07663):
   fringe element mapped by eq. reftophys.
 * :func:`donor_search` -- Sec. 4.3, Newton inversion of eq. reftophys with
   eq. ref-update / eq. Jac, at most 10 iterations, clamped near [-1, 1].
+* :func:`cut_heuristic` -- the paper's own filtered cut (Sec. 4.2, Alg. cp0,
+  bboxdix, cp1, cp2): approximate distances, the nearest N_F^1 faces, a
+  linear first pass keeping N_F^2 of them, the lattice second pass at the
+  nearest corner, the nearest pair's normal side.
 * :func:`ab_faces`, :func:`face_points`, :func:`interp_weights` -- the
   artificial-boundary (AB) method of Sec. 2: the faces between a hole and a
   kept element (and overset-tagged faces), the flux points on them (the
@@ -77,6 +81,15 @@ def lib():
         L.orc_cut_surface.restype = C.c_int
         L.orc_cut_surface.argtypes = [dp, ip, C.c_int64, i64p, C.c_int64, dp, C.c_int64, ip, C.c_int64,
                                       dp, C.c_int, C.c_int, C.c_int, i8p, i8p, dp, i8p, dp, i8p]
+        L.orc_cut_heuristic.restype = C.c_int
+        L.orc_cut_heuristic.argtypes = [dp, ip, C.c_int64, dp, C.c_int64, ip, C.c_int64, dp, C.c_int, C.c_int,
+                                        C.c_int, C.c_int, i8p, i8p]
+        L.orc_hx_obb.restype = None
+        L.orc_hx_obb.argtypes = [dp, dp]
+        L.orc_hx_bbox_dist.restype = C.c_double
+        L.orc_hx_bbox_dist.argtypes = [dp, dp]
+        L.orc_hx_lists.restype = C.c_int
+        L.orc_hx_lists.argtypes = [dp, dp, ip, C.c_int64, dp, C.c_int, C.c_int, i64p, dp, i64p, dp, ip]
         L.orc_fringe_points.restype = C.c_int
         L.orc_fringe_points.argtypes = [dp, ip, i64p, C.c_int64, dp, dp]
         L.orc_donor_search.restype = C.c_int
@@ -394,3 +407,69 @@ def interp_weights(donor, ref, nodes1d=GAUSS3):
     W = (La[:, None, None, :] * Lb[:, None, :, None] * Lc[:, :, None, None]).reshape(-1, m ** 3)
     W[donor < 0] = np.nan
     return W
+
+
+# ---------------------------------------------------------------------------
+# the paper's filtered cut (Sec. 4.2; Alg. cp0, bboxdix, cp1, cp2)
+# ---------------------------------------------------------------------------
+
+def hx_obb(X):
+    """Element OBB of Alg. cp0 from the corner nodes of X (27 x 3): centroid,
+    axes (rows: eigenvectors of the corner covariance), extents (lo3 hi3)."""
+    X = _f64(X).reshape(81)
+    o = np.zeros(18)
+    lib().orc_hx_obb(_p(X, C.c_double), _p(o, C.c_double))
+    return o[:3], o[3:12].reshape(3, 3), o[12:]
+
+
+def hx_bbox_dist(b1, b2):
+    """Alg. bboxdix between two 6-vector boxes (lo3 hi3)."""
+    b1, b2 = _f64(b1).reshape(6), _f64(b2).reshape(6)
+    return lib().orc_hx_bbox_dist(_p(b1, C.c_double), _p(b2, C.c_double))
+
+
+def hx_lists(X, surf, pose=IDENTITY, nf1=16, nf2=4):
+    """The filtered cut's kept lists for one element X (27 x 3): the nf1
+    faces of smallest approximate distance (Alg. cp0) with their distances,
+    then the nf2 of those of smallest first-pass distance (Alg. cp1) with
+    their distances and kept corners."""
+    X = _f64(X).reshape(81)
+    sn, sc = _f64(surf.nodes), _i32(surf.conn)
+    pose = _f64(pose)
+    l1, d1 = np.empty(nf1, dtype=np.int64), np.empty(nf1)
+    l2, d2, c2 = np.empty(nf2, dtype=np.int64), np.empty(nf2), np.empty(nf2, dtype=np.int32)
+    rc = lib().orc_hx_lists(_p(X, C.c_double), _p(sn, C.c_double), _p(sc, C.c_int32), sc.shape[0],
+                            _p(pose, C.c_double), int(nf1), int(nf2), _p(l1, C.c_int64), _p(d1, C.c_double),
+                            _p(l2, C.c_int64), _p(d2, C.c_double), _p(c2, C.c_int32))
+    if rc != 0:
+        raise ValueError("orc_hx_lists: need 1 <= nf2 <= nf1 <= faces")
+    return l1, d1, l2, d2, c2
+
+
+def cut_surface_heuristic(grid, surf, pose=IDENTITY, kind=SURF_WALL, nf1=16, nf2=4, threads=0):
+    """Per element status (0 hole, 1 field) and hit flag of the filtered cut."""
+    gn, gc = _f64(grid.nodes), _i32(grid.conn)
+    sn, sc = _f64(surf.nodes), _i32(surf.conn)
+    pose = _f64(pose)
+    n = gc.shape[0]
+    st = np.empty(n, dtype=np.int8)
+    hit = np.empty(n, dtype=np.int8)
+    rc = lib().orc_cut_heuristic(_p(gn, C.c_double), _p(gc, C.c_int32), n, _p(sn, C.c_double), sn.shape[0],
+                                 _p(sc, C.c_int32), sc.shape[0], _p(pose, C.c_double), int(kind), int(nf1), int(nf2),
+                                 int(threads), _p(st, C.c_int8), _p(hit, C.c_int8))
+    if rc != 0:
+        raise ValueError("orc_cut_heuristic: nf1 and nf2 must be >= 1")
+    return st, hit
+
+
+def cut_heuristic(grid, surfaces, poses, kinds=None, nf1=16, nf2=4, nbr=None, threads=0):
+    """iblank of the filtered cut: union of holes over the surfaces, then one
+    fringe layer (as :func:`cut`)."""
+    if kinds is None:
+        kinds = [SURF_WALL] * len(surfaces)
+    hole = np.zeros(grid.conn.shape[0], dtype=bool)
+    for s, p, k in zip(surfaces, poses, kinds):
+        hole |= cut_surface_heuristic(grid, s, p, k, nf1, nf2, threads)[0] == 0
+    if nbr is None:
+        nbr = face_neighbors(grid.conn)
+    return mark_fringe(hole, nbr, grid.face_tags)

@@ -1155,3 +1155,350 @@ int orc_donor_search(const double *gnodes, const int32_t *gconn, int64_t n_elem,
     free(boxes);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* the paper's filtered cut (Sec. 4.2, Alg. cp0, bboxdix, cp1, cp2)          */
+/* ------------------------------------------------------------------------ */
+/* Element corners in the order i = ia + 2 ib + 4 ic (ia, ib, ic in {0, 1}),
+ * i.e. lattice nodes a + 3b + 9c with a, b, c in {0, 2}. */
+static const int hx_corner[8] = {0, 2, 6, 8, 18, 20, 24, 26};
+
+/* Eigenvectors (columns of V) of the symmetric 3x3 matrix A by the cyclic
+ * Jacobi method: 8 sweeps over the planes (0,1), (0,2), (1,2); each rotation
+ * zeroes A[p][q] (Numerical Recipes' angle choice, the smaller rotation). */
+static void hx_jacobi(double *A, double *V)
+{
+    static const int P[3] = {0, 0, 1}, Q[3] = {1, 2, 2};
+    for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 8; ++sweep)
+        for (int r = 0; r < 3; ++r) {
+            const int p = P[r], q = Q[r];
+            const double apq = A[3 * p + q];
+            if (apq == 0.0) continue;
+            const double theta = (A[3 * q + q] - A[3 * p + p]) / (2.0 * apq);
+            double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+            if (theta < 0.0) t = -t;
+            const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+            for (int k = 0; k < 3; ++k) {
+                const double akp = A[3 * k + p], akq = A[3 * k + q];
+                A[3 * k + p] = c * akp - s * akq;
+                A[3 * k + q] = s * akp + c * akq;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const double apk = A[3 * p + k], aqk = A[3 * q + k];
+                A[3 * p + k] = c * apk - s * aqk;
+                A[3 * q + k] = s * apk + c * aqk;
+            }
+            for (int k = 0; k < 3; ++k) {
+                const double vkp = V[3 * k + p], vkq = V[3 * k + q];
+                V[3 * k + p] = c * vkp - s * vkq;
+                V[3 * k + q] = s * vkp + c * vkq;
+            }
+        }
+}
+
+static double hx_rot(const double *R, int r, const double *x)
+{
+    return (R[3 * r] * x[0] + R[3 * r + 1] * x[1]) + R[3 * r + 2] * x[2];
+}
+
+/* Element OBB from its corner nodes: centroid, axes R (rows: eigenvectors of
+ * the corner covariance), extents B = (lo0 lo1 lo2 hi0 hi1 hi2) of the
+ * corners along R.  obb: cg[3], R[9], B[6]. */
+static void hx_obb(const double *X /* 27 nodes xyz */, double *obb)
+{
+    double cg[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 8; ++i)
+        for (int d = 0; d < 3; ++d) cg[d] += X[3 * hx_corner[i] + d];
+    for (int d = 0; d < 3; ++d) cg[d] *= 0.125;
+    double A[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, V[9];
+    for (int i = 0; i < 8; ++i) {
+        double dv[3];
+        for (int d = 0; d < 3; ++d) dv[d] = X[3 * hx_corner[i] + d] - cg[d];
+        for (int j = 0; j < 3; ++j)
+            for (int k = 0; k < 3; ++k) A[3 * j + k] += dv[j] * dv[k];
+    }
+    for (int k = 0; k < 9; ++k) A[k] *= 0.125;
+    hx_jacobi(A, V);
+    double *R = obb + 3, *B = obb + 12;
+    for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j) R[3 * r + j] = V[3 * j + r];
+    for (int r = 0; r < 3; ++r) {
+        B[r] = INFINITY;
+        B[3 + r] = -INFINITY;
+    }
+    for (int i = 0; i < 8; ++i)
+        for (int r = 0; r < 3; ++r) {
+            const double v = hx_rot(R, r, X + 3 * hx_corner[i]);
+            B[r] = fmin(B[r], v);
+            B[3 + r] = fmax(B[3 + r], v);
+        }
+    for (int d = 0; d < 3; ++d) obb[d] = cg[d];
+}
+
+void orc_hx_obb(const double *X, double *obb) { hx_obb(X, obb); }
+
+/* Alg. bboxdix (its loop read as i = 0, 1, 2 over a 6-vector box) */
+double orc_hx_bbox_dist(const double *B1, const double *B2)
+{
+    double D = 0.0;
+    for (int i = 0; i < 3; ++i)
+        if (B1[i + 3] < B2[i] || B2[i + 3] < B1[i]) {
+            const double d = fmax(B2[i] - B1[i + 3], B1[i] - B2[i + 3]);
+            D += d * d;
+        }
+    return sqrt(D);
+}
+
+/* centroid of a posed face's corner nodes 0, 2, 6, 8 */
+static void hx_face_cg(const double *P /* 9 nodes */, double *cg)
+{
+    for (int d = 0; d < 3; ++d) cg[d] = (((P[d] + P[6 + d]) + P[18 + d]) + P[24 + d]) * 0.25;
+}
+
+/* Alg. cp0: approximate element-face distance */
+static double hx_approx(const double *obb, const double *P)
+{
+    const double *cg = obb, *R = obb + 3, *Be = obb + 12;
+    double Bf[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    static const int fc[4] = {0, 2, 6, 8};
+    for (int k = 0; k < 4; ++k)
+        for (int r = 0; r < 3; ++r) {
+            const double v = hx_rot(R, r, P + 3 * fc[k]);
+            Bf[r] = fmin(Bf[r], v);
+            Bf[3 + r] = fmax(Bf[3 + r], v);
+        }
+    double fcg[3];
+    hx_face_cg(P, fcg);
+    const double dx = fcg[0] - cg[0], dy = fcg[1] - cg[1], dz = fcg[2] - cg[2];
+    const double dxc = sqrt((dx * dx + dy * dy) + dz * dz);
+    return 0.01 * dxc + orc_hx_bbox_dist(Bf, Be);
+}
+
+typedef struct {
+    double d;
+    int64_t f;
+    int c;
+} hx_cand;
+
+/* keep the k smallest (d, f) of a list in ascending order */
+static void hx_keep(hx_cand *list, int *n, int k, hx_cand x)
+{
+    if (*n == k && !(x.d < list[k - 1].d || (x.d == list[k - 1].d && x.f < list[k - 1].f))) return;
+    int i = *n < k ? (*n)++ : k - 1;
+    while (i > 0 && (x.d < list[i - 1].d || (x.d == list[i - 1].d && x.f < list[i - 1].f))) {
+        list[i] = list[i - 1];
+        --i;
+    }
+    list[i] = x;
+}
+
+/* faces of an element touching corner c, in the order xi, eta, zeta */
+static void hx_corner_faces(int c, int *fl)
+{
+    fl[0] = (c & 1) ? 1 : 0;
+    fl[1] = (c & 2) ? 3 : 2;
+    fl[2] = (c & 4) ? 5 : 4;
+}
+
+/* Alg. cp1: nearest element corner to the face centroid, then the minimum
+ * distance between the linear triangles of the 3 element faces at that
+ * corner and of the face's corner quad. */
+static double hx_pass1(const double *X, const double *P, int *corner)
+{
+    double fcg[3];
+    hx_face_cg(P, fcg);
+    double dmin = INFINITY;
+    int c = 0;
+    for (int i = 0; i < 8; ++i) {
+        const double *x = X + 3 * hx_corner[i];
+        const double dx = x[0] - fcg[0], dy = x[1] - fcg[1], dz = x[2] - fcg[2];
+        const double D = sqrt((dx * dx + dy * dy) + dz * dz);
+        if (D < dmin) {
+            dmin = D;
+            c = i;
+        }
+    }
+    int fl[3];
+    hx_corner_faces(c, fl);
+    double TF[2][9];
+    static const int ft[2][3] = {{0, 2, 8}, {0, 8, 6}};
+    for (int j = 0; j < 2; ++j)
+        for (int k = 0; k < 3; ++k) v_copy(TF[j] + 3 * k, P + 3 * ft[j][k]);
+    dmin = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        const int q00 = face_node(fl[a], 0, 0), q20 = face_node(fl[a], 2, 0), q22 = face_node(fl[a], 2, 2),
+                  q02 = face_node(fl[a], 0, 2);
+        const int et[2][3] = {{q00, q20, q22}, {q00, q22, q02}};
+        for (int i = 0; i < 2; ++i) {
+            double TC[9];
+            for (int k = 0; k < 3; ++k) v_copy(TC + 3 * k, X + 3 * et[i][k]);
+            for (int j = 0; j < 2; ++j) {
+                const double D = orc_tri_tri(TC, TF[j], NULL, NULL);
+                if (D < dmin) dmin = D;
+            }
+        }
+    }
+    if (dmin < TOL_HIT) dmin = 0.0;
+    *corner = c;
+    return dmin;
+}
+
+/* One element through the filtered cut: returns 1 for a hole.  *hit_out: the
+ * element was found intersected (a pass-2 distance below the tolerance). */
+static int hx_classify(const double *X, const surf_t *S, const double *Pposed /* n_face x 27 */, int kind,
+                       int nf1, int nf2, hx_cand *l1, hx_cand *l2, int8_t *hit_out)
+{
+    double obb[18];
+    hx_obb(X, obb);
+    int n1 = 0;
+    for (int64_t f = 0; f < S->n_face; ++f) {
+        hx_cand x = {hx_approx(obb, Pposed + 27 * f), f, 0};
+        hx_keep(l1, &n1, nf1, x);
+    }
+    int n2 = 0;
+    for (int k = 0; k < n1; ++k) {
+        int c;
+        const double D = hx_pass1(X, Pposed + 27 * l1[k].f, &c);
+        hx_cand x = {D, l1[k].f, c};
+        hx_keep(l2, &n2, nf2, x);
+    }
+    /* Alg. cp2 over the element's lattice triangles at the kept corner */
+    double et[48 * 9];
+    tris_from_elem(X, et);
+    double best = INFINITY;
+    int hit = 0;
+    for (int k = 0; k < n2 && !hit; ++k) {
+        int fl[3];
+        hx_corner_faces(l2[k].c, fl);
+        const int64_t f = l2[k].f;
+        for (int a = 0; a < 3 && !hit; ++a)
+            for (int tl = 0; tl < 8 && !hit; ++tl)
+                for (int s = 0; s < 8; ++s) {
+                    const double D = orc_tri_tri(et + 9 * (8 * fl[a] + tl), S->tris + 72 * f + 9 * s, NULL, NULL);
+                    if (D < TOL_HIT) {
+                        hit = 1;
+                        break;
+                    }
+                    if (D < best) best = D;
+                }
+    }
+    if (hit_out) *hit_out = (int8_t)hit;
+    if (hit) return kind == 0;
+    /* nearest pair and its tie set (reading of the normal averaging) */
+    const double thr = best * (1.0 + TIE_REL);
+    tie_rec b1, b2;
+    b1.valid = b2.valid = 0;
+    for (int k = 0; k < n2; ++k) {
+        int fl[3];
+        hx_corner_faces(l2[k].c, fl);
+        const int64_t f = l2[k].f;
+        for (int a = 0; a < 3; ++a)
+            for (int tl = 0; tl < 8; ++tl)
+                for (int s = 0; s < 8; ++s) {
+                    double pa[3], pb[3];
+                    const int t = 8 * fl[a] + tl;
+                    const double D = orc_tri_tri(et + 9 * t, S->tris + 72 * f + 9 * s, pa, pb);
+                    if (D > thr) continue;
+                    tie_rec r;
+                    v_sub(pa, pb, r.v);
+                    const double L = sqrt(v_dot(r.v, r.v));
+                    v_copy(r.n, S->tnrm + 24 * f + 3 * s);
+                    r.dot = L > 0.0 ? v_dot(r.v, r.n) / L : 0.0;
+                    r.absdot = fabs(r.dot);
+                    r.f = f;
+                    r.s = s;
+                    r.t = t;
+                    r.valid = 1;
+                    tie_offer(&b1, &b2, &r);
+                }
+    }
+    double sgn = b1.dot;
+    if (b2.valid && b1.absdot - b2.absdot <= TIE_DOT && (b1.dot > 0.0) != (b2.dot > 0.0)) {
+        const double nn[3] = {b1.n[0] + b2.n[0], b1.n[1] + b2.n[1], b1.n[2] + b2.n[2]};
+        sgn = v_dot(b1.v, nn);
+    }
+    return sgn < 0.0;
+}
+
+int orc_cut_heuristic(const double *gnodes, const int32_t *gconn, int64_t n_elem, const double *snodes,
+                      int64_t n_snodes, const int32_t *sconn, int64_t n_face, const double *pose, int kind, int nf1,
+                      int nf2, int n_threads, int8_t *status, int8_t *hit)
+{
+    if (nf1 < 1 || nf2 < 1) return -1;
+    if (nf1 > n_face) nf1 = (int)n_face;
+    if (nf2 > nf1) nf2 = nf1;
+    surf_t S;
+    surf_build(&S, snodes, n_snodes, sconn, n_face, pose, 0);
+    double *Pp = (double *)malloc(sizeof(double) * 27 * (size_t)n_face + 8);
+    for (int64_t f = 0; f < n_face; ++f)
+        for (int k = 0; k < 9; ++k) pose_point(pose, snodes + 3 * (int64_t)sconn[f * 9 + k], Pp + 27 * f + 3 * k);
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel
+    {
+        hx_cand *l1 = (hx_cand *)malloc(sizeof(hx_cand) * (size_t)nf1);
+        hx_cand *l2 = (hx_cand *)malloc(sizeof(hx_cand) * (size_t)nf2);
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t e = 0; e < n_elem; ++e) {
+            double X[81], box[6];
+            elem_nodes(gnodes, gconn, e, X);
+            box_of(X, 27, box);
+            /* filter: elements whose node box misses the surface's node box
+             * (grown by the hit tolerance) lie outside the surface */
+            int near = 1;
+            for (int d = 0; d < 3; ++d)
+                if (box[3 + d] < S.sbox[d] - TOL_HIT || box[d] > S.sbox[3 + d] + TOL_HIT) near = 0;
+            int8_t h = 0;
+            const int hole = near ? hx_classify(X, &S, Pp, kind, nf1, nf2, l1, l2, &h) : 0;
+            status[e] = hole ? 0 : 1;
+            if (hit) hit[e] = h;
+        }
+        free(l1);
+        free(l2);
+    }
+    free(Pp);
+    surf_free(&S);
+    return 0;
+}
+
+/* The kept lists of one element (for the pins): the nf1 faces of smallest
+ * approximate distance (l1, with their distances d1) and the nf2 of those
+ * with the smallest first-pass distance (l2, d2, kept corner c2). */
+int orc_hx_lists(const double *X, const double *snodes, const int32_t *sconn, int64_t n_face, const double *pose,
+                 int nf1, int nf2, int64_t *l1, double *d1, int64_t *l2, double *d2, int32_t *c2)
+{
+    if (nf1 < 1 || nf2 < 1 || nf1 > n_face || nf2 > nf1) return -1;
+    double *Pp = (double *)malloc(sizeof(double) * 27 * (size_t)n_face + 8);
+    hx_cand *a = (hx_cand *)malloc(sizeof(hx_cand) * (size_t)nf1);
+    hx_cand *b = (hx_cand *)malloc(sizeof(hx_cand) * (size_t)nf2);
+    for (int64_t f = 0; f < n_face; ++f)
+        for (int k = 0; k < 9; ++k) pose_point(pose, snodes + 3 * (int64_t)sconn[f * 9 + k], Pp + 27 * f + 3 * k);
+    double obb[18];
+    hx_obb(X, obb);
+    int n1 = 0, n2 = 0;
+    for (int64_t f = 0; f < n_face; ++f) {
+        hx_cand x = {hx_approx(obb, Pp + 27 * f), f, 0};
+        hx_keep(a, &n1, nf1, x);
+    }
+    for (int k = 0; k < n1; ++k) {
+        int c;
+        const double D = hx_pass1(X, Pp + 27 * a[k].f, &c);
+        hx_cand x = {D, a[k].f, c};
+        hx_keep(b, &n2, nf2, x);
+        l1[k] = a[k].f;
+        d1[k] = a[k].d;
+    }
+    for (int k = 0; k < n2; ++k) {
+        l2[k] = b[k].f;
+        d2[k] = b[k].d;
+        c2[k] = b[k].c;
+    }
+    free(Pp);
+    free(a);
+    free(b);
+    return 0;
+}

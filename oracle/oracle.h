@@ -59,7 +59,25 @@ int orc_donor_search(const double *gnodes, const int32_t *gconn, int64_t n_elem,
                      const double *pts, int64_t n, int brute, int maxit, int n_threads,
                      int32_t *donor, double *xi, int32_t *iters, int32_t *n_cand);
 
+/* The paper's filtered cut (Sec. 4.2; Alg. cp0, bboxdix, cp1, cp2): per
+ * element near the surface's box, the nf1 faces of smallest approximate
+ * distance, the nf2 of those with the smallest linear first-pass distance,
+ * then the lattice triangles at the kept corner; hit if any pair is closer
+ * than 1e-7, else the side of the nearest pair's face normal.  status: 0
+ * hole, 1 field; hit (may be NULL): 1 where a second-pass pair hit. */
+int orc_cut_heuristic(const double *gnodes, const int32_t *gconn, int64_t n_elem, const double *snodes,
+                      int64_t n_snodes, const int32_t *sconn, int64_t n_face, const double *pose, int kind, int nf1,
+                      int nf2, int n_threads, int8_t *status, int8_t *hit);
+/* element OBB of Alg. cp0: centroid[3], axes R[9] (rows), extents[6] */
+void orc_hx_obb(const double *X, double *obb);
+/* Alg. bboxdix */
+double orc_hx_bbox_dist(const double *B1, const double *B2);
+/* the two kept lists of the filtered cut for one element X (27 x 3) */
+int orc_hx_lists(const double *X, const double *snodes, const int32_t *sconn, int64_t n_face, const double *pose,
+                 int nf1, int nf2, int64_t *l1, double *d1, int64_t *l2, double *d2, int32_t *c2);
+
 #ifdef __cplusplus
 }
 #endif
+
 #endif
