@@ -157,6 +157,21 @@ oc_status oc_cut_warm(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const doubl
  * rotation angle of R_b R_a^T times the largest node radius plus |t_b - t_a|. */
 oc_status oc_sweep_bound(oc_ctx *ctx, int32_t surf_id, const double pose_a[12], const double pose_b[12], double *out);
 
+/* The paper's filtered cut (Sec. 4.2; Alg. cp0, bboxdix, cp1, cp2), for
+ * comparison with oc_cut_multi: per element whose box meets a surface's box,
+ * the nf1 (N_F^1, 1..32) faces of smallest approximate distance (box distance
+ * in the element's corner OBB frame plus 1/100 of the centroid distance), of
+ * those the nf2 (N_F^2, 1..16, <= nf1) of smallest linear first-pass
+ * distance over the three element faces at the corner nearest the face
+ * centroid, then the lattice triangles at that corner: a pair closer than
+ * 1e-7 is a hit, else the nearest pair's face normal gives the side (the tie
+ * rule of the exact cut).  Holes are united over the surfaces, then one
+ * fringe layer.  poses: host FP64 [n_surf*12].  Synchronises once per
+ * surface; *n_listed (may be NULL) receives the number of (surface,
+ * element) pairs examined. */
+oc_status oc_cut_filtered(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
+                          int32_t nf1, int32_t nf2, int8_t *iblank_out, int64_t *n_listed);
+
 oc_status oc_last_cut_info(oc_ctx *ctx, oc_cut_info *info);
 
 /* Blanking of one time step of a moving grid, with unblanking (Sec. 3,

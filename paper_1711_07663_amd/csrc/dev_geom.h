@@ -1,5 +1,8 @@
 // FP64 device geometry on the linearised (triangulated) curved faces.
 //
+// * the lattice triangles of a surface face and of an element's boundary
+//   (Fig. quadsplit: each 2x2 sub-quad split along its (m,n)-(m+1,n+1)
+//   diagonal);
 // * closest point of a triangle to a point (Voronoi-region classification of
 //   the point against the triangle's vertices, edges and face);
 // * squared distance of two segments (clamped stationary point);
@@ -7,6 +10,7 @@
 //   by plane separation, edge/triangle crossing (signed volumes) and the
 //   vertex-face / edge-edge distances that realise the distance of disjoint
 //   triangles (Sec. 4.2, Alg. cp1/cp2: tol = 1e-7);
+// * the distance of two triangles with a closest pair;
 // * +x ray / triangle crossing with a symbolic perturbation of the ray
 //   origin, so that a ray through shared vertices or edges of a watertight
 //   triangulation is counted exactly once (parity classification).
@@ -15,6 +19,28 @@
 #include "dev_common.h"
 
 namespace oc {
+
+// triangle s of a face stored x[9], y[9], z[9]
+__device__ inline void face_tri(const double *P, int s, d3 *T)
+{
+    int uv[6];
+    quad_tri_uv((s >> 1) & 1, s >> 2, s & 1, uv);
+    for (int k = 0; k < 3; ++k) {
+        int nd = uv[2 * k] + 3 * uv[2 * k + 1];
+        T[k] = mk(P[nd], P[9 + nd], P[18 + nd]);
+    }
+}
+
+// boundary triangle t (0..47) of an element stored x[27], y[27], z[27]
+__device__ inline void elem_tri(const double *X, int t, d3 *T)
+{
+    int uv[6];
+    quad_tri_uv((t >> 1) & 1, (t >> 2) & 1, t & 1, uv);
+    for (int k = 0; k < 3; ++k) {
+        int nd = elem_face_node(t >> 3, uv[2 * k], uv[2 * k + 1]);
+        T[k] = mk(X[nd], X[27 + nd], X[54 + nd]);
+    }
+}
 
 __device__ inline double clamp01(double v) { return fmin(fmax(v, 0.0), 1.0); }
 
@@ -133,6 +159,95 @@ __device__ inline bool tri_tri_within(const d3 *A, const d3 *B, double tol)
         }
     }
     return false;
+}
+
+// Closest points of segments [p1, q1] and [p2, q2] (clamped stationary
+// point); returns the squared distance.
+__device__ inline double seg_seg_cp(d3 p1, d3 q1, d3 p2, d3 q2, d3 &c1, d3 &c2)
+{
+    d3 d1 = q1 - p1, d2 = q2 - p2, r = p1 - p2;
+    double a = dot(d1, d1), e = dot(d2, d2), f = dot(d2, r);
+    double s = 0.0, t = 0.0;
+    if (a <= 0.0 && e <= 0.0) {
+        s = t = 0.0;
+    } else if (a <= 0.0) {
+        t = clamp01(f / e);
+    } else {
+        double c = dot(d1, r);
+        if (e <= 0.0) {
+            s = clamp01(-c / a);
+        } else {
+            double b = dot(d1, d2), den = a * e - b * b;
+            s = den > 0.0 ? clamp01((b * f - c * e) / den) : 0.0;
+            t = (b * s + f) / e;
+            if (t < 0.0) {
+                t = 0.0;
+                s = clamp01(-c / a);
+            } else if (t > 1.0) {
+                t = 1.0;
+                s = clamp01((b - c) / a);
+            }
+        }
+    }
+    c1 = p1 + d1 * s;
+    c2 = p2 + d2 * t;
+    d3 w = c1 - c2;
+    return dot(w, w);
+}
+
+// Distance of triangles A and B with a closest pair (pa on A, pb on B): zero
+// (at the crossing point) when an edge of one crosses the other, else the
+// least of the six vertex-triangle and nine edge-edge distances, which
+// realise the distance of disjoint triangles.
+__device__ inline double tri_tri_dist(const d3 *A, const d3 *B, d3 &pa, d3 &pb)
+{
+    for (int pass = 0; pass < 2; ++pass) {
+        const d3 *P = pass ? B : A, *Q = pass ? A : B;
+        d3 n = cross(Q[1] - Q[0], Q[2] - Q[0]);
+        for (int k = 0; k < 3; ++k) {
+            const int k1 = k == 2 ? 0 : k + 1;
+            if (seg_meets_tri(P[k], P[k1], Q[0], Q[1], Q[2])) {
+                double sp = dot(n, P[k] - Q[0]), sq = dot(n, P[k1] - Q[0]);
+                d3 x = P[k] + (P[k1] - P[k]) * (sp / (sp - sq));
+                pa = x;
+                pb = x;
+                return 0.0;
+            }
+        }
+    }
+    double best = INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        d3 q = closest_on_tri(A[k], B[0], B[1], B[2]);
+        d3 w = A[k] - q;
+        double d = dot(w, w);
+        if (d < best) {
+            best = d;
+            pa = A[k];
+            pb = q;
+        }
+        q = closest_on_tri(B[k], A[0], A[1], A[2]);
+        w = B[k] - q;
+        d = dot(w, w);
+        if (d < best) {
+            best = d;
+            pa = q;
+            pb = B[k];
+        }
+    }
+    for (int i = 0; i < 3; ++i) {
+        const int i1 = i == 2 ? 0 : i + 1;
+        for (int j = 0; j < 3; ++j) {
+            const int j1 = j == 2 ? 0 : j + 1;
+            d3 c1, c2;
+            const double d = seg_seg_cp(A[i], A[i1], B[j], B[j1], c1, c2);
+            if (d < best) {
+                best = d;
+                pa = c1;
+                pb = c2;
+            }
+        }
+    }
+    return sqrt(best);
 }
 
 // 2D edge function of directed edge (a, b) at q = (py, pz) in the (y, z)

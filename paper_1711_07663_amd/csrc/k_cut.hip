@@ -573,28 +573,6 @@ __device__ inline void tie_offer(TieRec &b1, TieRec &b2, const TieRec &r)
     b2 = n2;
 }
 
-// triangle s of a face stored x[9], y[9], z[9]
-__device__ inline void face_tri(const double *P, int s, d3 *T)
-{
-    int uv[6];
-    quad_tri_uv((s >> 1) & 1, s >> 2, s & 1, uv);
-    for (int k = 0; k < 3; ++k) {
-        int nd = uv[2 * k] + 3 * uv[2 * k + 1];
-        T[k] = mk(P[nd], P[9 + nd], P[18 + nd]);
-    }
-}
-
-// boundary triangle t (0..47) of an element stored x[27], y[27], z[27]
-__device__ inline void elem_tri(const double *X, int t, d3 *T)
-{
-    int uv[6];
-    quad_tri_uv((t >> 1) & 1, (t >> 2) & 1, t & 1, uv);
-    for (int k = 0; k < 3; ++k) {
-        int nd = elem_face_node(t >> 3, uv[2 * k], uv[2 * k + 1]);
-        T[k] = mk(X[nd], X[27 + nd], X[54 + nd]);
-    }
-}
-
 __device__ inline double point_box_dist(d3 p, const float *b)
 {
     double gx = fmax(0.0, fmax((double)b[0] - p.x, p.x - (double)b[3]));

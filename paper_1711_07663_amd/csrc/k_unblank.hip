@@ -106,6 +106,16 @@ static oc_status combine_overset(oc_slot *sl, Grid &g, Surf *const *surfs, int n
     return OC_OK;
 }
 
+oc_status fringe_layer_run(oc_slot *sl, const Grid &g, int8_t *out)
+{
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    LAUNCH(k_fringe_stencil, dim3(ublocks(g.n_elem)), dim3(kUT), g.nbr, g.n_elem, out);
+    if (g.n_overset > 0) LAUNCH(k_overset_list, dim3(ublocks(g.n_overset)), dim3(kUT), g.overset, g.n_overset, out);
+    OC_HIP(hipGetLastError());
+    return OC_OK;
+}
+
 oc_status copy_count_run(oc_slot *sl, const int32_t *src, int32_t *dst)
 {
     oc_ctx *ctx = sl->ctx;

@@ -831,6 +831,29 @@ oc_status oc_element_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose
                               nullptr, src_out);
 }
 
+oc_status oc_cut_filtered(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
+                          int32_t nf1, int32_t nf2, int8_t *iblank_out, int64_t *n_listed)
+{
+    if (!ctx || !iblank_out || n_surf < 0 || n_surf > kPoseSlots - 2 || (n_surf > 0 && (!surf_ids || !poses)) ||
+        nf1 < 1 || nf1 > 32 || nf2 < 1 || nf2 > 16 || nf2 > nf1) {
+        set_error("oc_cut_filtered: invalid arguments (1 <= nf2 <= nf1, nf1 <= 32, nf2 <= 16)");
+        return OC_EINVAL;
+    }
+    for (int k = 0; k < n_surf; ++k)
+        if (!pose_ok(poses + 12 * k)) {
+            set_error("oc_cut_filtered: non-finite pose");
+            return OC_EINVAL;
+        }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, 0, poses, n_surf));
+    return filtered_cut_run(sl, *g, ss.data(), sl->poses, n_surf, nf1, nf2, iblank_out, n_listed);
+}
+
 // ------------------------------------------------- artificial boundary --
 static oc_status get_nodes1d(const double *z, int32_t m, Nodes1D *out, const char *who)
 {

@@ -172,6 +172,8 @@ struct oc_slot {
     int32_t *fr_tiles = nullptr;       // fringe compaction: counts, offsets, scan scratch
     int64_t fr_tiles_cap = 0;
     uint32_t *ab_mask = nullptr;       // [list_cap] bytes: AB face bits per element, zero between calls
+    void *hx_buf = nullptr;            // filtered-cut arena (grown on demand)
+    size_t hx_cap = 0;
     oc::CutCounters *counters = nullptr;
     oc::DonorCounters *dcounters = nullptr;
     oc::Pose *poses = nullptr;         // [kPoseSlots] device
@@ -316,6 +318,14 @@ oc_status ab_faces_run(oc_slot *sl, const Grid &g, const int8_t *iblank, int32_t
 oc_status face_points_run(oc_slot *sl, const Grid &g, const Pose *pose_dev, const int32_t *faces,
                           const int32_t *n_faces, int64_t faces_cap, const Nodes1D &z, double *pts, int64_t cap,
                           int32_t *n_out, int32_t *src);
+// one fringe layer around the holes of out (full-grid stencil) and the
+// overset-tagged faces
+oc_status fringe_layer_run(oc_slot *sl, const Grid &g, int8_t *out);
+// the paper's filtered cut (N_F^1 = nf1 <= 32, N_F^2 = nf2 <= 16) of g by
+// the surfaces at poses_dev; synchronises once per surface; *n_listed
+// (may be null) receives the number of (surface, element) pairs examined
+oc_status filtered_cut_run(oc_slot *sl, Grid &g, Surf *const *surfs, const Pose *poses_dev, int n_surf, int nf1,
+                           int nf2, int8_t *iblank, int64_t *n_listed);
 // *dst = *src on the slot stream (device counts)
 oc_status copy_count_run(oc_slot *sl, const int32_t *src, int32_t *dst);
 // m^3 interpolation weights of min(*n_dev, cap) points (n_dev null: cap)

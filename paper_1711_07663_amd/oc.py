@@ -31,7 +31,7 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_slot_fringe_points", "oc_slot_donor_search", "oc_slot_cut_info", "oc_slot_donor_info",
            "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm", "oc_cut_batch", "oc_slot_cut_batch",
            "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points", "oc_ab_faces", "oc_face_points",
-           "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights"]
+           "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered"]
 
 
 class OcError(RuntimeError):
@@ -111,6 +111,7 @@ def load(path=LIB_PATH):
         "oc_slot_ab_faces": ([vp, C.c_int32, vp, vp, C.c_int64, vp]),
         "oc_slot_face_points": ([vp, C.c_int32, vp, vp, vp, C.c_int64, dp, C.c_int32, vp, C.c_int64, vp, vp]),
         "oc_slot_interp_weights": ([vp, vp, vp, vp, C.c_int64, dp, C.c_int32, vp]),
+        "oc_cut_filtered": ([vp, C.c_int32, i32p, dp, C.c_int32, C.c_int32, C.c_int32, vp, i64p]),
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -296,6 +297,17 @@ class Context:
         _check(load().oc_element_points(self._h, grid_id, pp, _dptr(elems, torch.int32, n), int(n),
                                         _dptr(points, torch.float64, 81 * n),
                                         None if src is None else _dptr(src, torch.int32, 27 * n)))
+
+    def cut_filtered(self, grid_id, surf_ids, poses, iblank, nf1=16, nf2=4):
+        """The paper's filtered cut (oc_cut_filtered); returns the number of
+        (surface, element) pairs it examined."""
+        import torch
+        ids = np.ascontiguousarray(surf_ids, dtype=np.int32)
+        pa, pp = _pose(np.asarray(poses, dtype=np.float64).reshape(-1) if len(ids) else np.zeros(12))
+        n = C.c_int64(0)
+        _check(load().oc_cut_filtered(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
+                                      int(nf1), int(nf2), _dptr(iblank, torch.int8, self.grids[grid_id]), C.byref(n)))
+        return n.value
 
     def ab_faces(self, grid_id, iblank, faces):
         """Artificial-boundary faces (ids 6 e + f, ascending) into ``faces``

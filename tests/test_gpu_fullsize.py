@@ -16,6 +16,8 @@ import pytest
 
 from workloads import configs as CF
 
+M_IDENTITY = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], dtype=np.float64)
+
 pytestmark = pytest.mark.gpu
 
 
@@ -211,3 +213,34 @@ def test_ab_full_size(orc):
     hole[band] = st == 0
     ib_o = orc.mark_fringe(hole, orc.face_neighbors(bg.conn))
     compare_ab(got, oracle_ab_step(case, case["poses"], ib_bg=ib_o))
+
+
+def test_filtered_full_size(orc):
+    """The paper's filtered cut (N_F^1 = 16, N_F^2 = 4) of the 128^3
+    background by the dimpled sphere, against the oracle's filtered cut, and
+    its disagreement with the exact cut."""
+    import torch
+    from paper_1711_07663_amd import oc
+
+    _note("full-size filtered cut: generating inputs")
+    case = CF.dimpled()
+    bg, s = case["bg"], case["bodies"][0]["surface"]
+    ctx = oc.Context(device=0)
+    try:
+        gid = ctx.register_grid(bg.nodes, bg.conn)
+        sid = ctx.register_cut_surface(s.nodes, s.conn)
+        ib = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+        ib_ex = torch.empty_like(ib)
+        _note("full-size filtered cut: GPU")
+        n = ctx.cut_filtered(gid, [sid], M_IDENTITY, ib)
+        ctx.cut(gid, sid, M_IDENTITY, ib_ex)
+        torch.cuda.synchronize()
+        got, ex = ib.cpu().numpy(), ib_ex.cpu().numpy()
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+    _note("full-size filtered cut: oracle (%d elements examined)" % n)
+    ref = orc.cut_heuristic(bg, [s], [M_IDENTITY])
+    bad = np.nonzero(got != ref)[0]
+    assert bad.size == 0, "%d elements differ, first %s" % (bad.size, bad[:8])
+    _note("full-size filtered cut: %d elements differ from the exact cut" % int((got != ex).sum()))
