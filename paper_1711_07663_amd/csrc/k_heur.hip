@@ -13,7 +13,9 @@
 //   k_hx_approx   Alg. cp0 against every face, N_F^1 smallest per element:
 //                 16 elements per block share LDS tiles of face corners;
 //                 each of an element's 16 threads keeps a sorted register
-//                 list, merged at the end
+//                 list, merged at the end; a face whose lower bound
+//                 (centroid distance less both radii) exceeds the thread's
+//                 current K-th distance is skipped, which changes nothing
 //   k_hx_pass1    Alg. cp1 per (element, kept face): nearest corner, linear
 //                 triangles of the three element faces at it
 //   k_hx_keep2    N_F^2 smallest first-pass distances per element
@@ -202,14 +204,15 @@ __global__ __launch_bounds__(kHT) void k_hx_obb(const double *__restrict__ enode
 __device__ inline bool hx_less(double d, int f, double e, int g) { return d < e || (d == e && f < g); }
 
 // Alg. cp0 for 16 elements per block: each element's 16 threads take every
-// 16th face of each LDS tile and keep their 32 smallest (d, f), sorted;
-// the element's N_F^1 smallest are merged from those lists.
+// 16th face of each LDS tile and keep their K >= N_F^1 smallest (d, f),
+// sorted; the element's N_F^1 smallest are merged from those lists.
+template <int K>
 __global__ __launch_bounds__(kHT) void k_hx_approx(const double *__restrict__ P, int64_t n_face,
                                                    const double *__restrict__ obb, const int32_t *__restrict__ count,
                                                    int nf1, int32_t *__restrict__ l1)
 {
 #pragma clang fp contract(off)
-    __shared__ double sF[kHxTile][15];   // corners 0, 2, 6, 8 (x y z each), centroid
+    __shared__ double sF[kHxTile][16];   // corners 0, 2, 6, 8 (x y z each), centroid, corner radius
     const int n = *count;
     const int j = threadIdx.x / kHxSub, sub = threadIdx.x % kHxSub;
     for (int base = blockIdx.x * kHxElems; base < n; base += gridDim.x * kHxElems) {
@@ -217,10 +220,19 @@ __global__ __launch_bounds__(kHT) void k_hx_approx(const double *__restrict__ P,
         const bool act = i < n;
         double o[18];
         for (int k = 0; k < 18; ++k) o[k] = act ? obb[(int64_t)i * 18 + k] : 0.0;
-        double Ld[kHxK1];
-        int Lf[kHxK1];
+        // radius of the OBB about the rotated centroid: every point of the
+        // box is within re of it
+        double re = 0.0;
+        for (int r = 0; r < 3; ++r) {
+            const double c = hx_rot(o + 3, r, o[0], o[1], o[2]);
+            const double h = fmax(fabs(o[12 + r] - c), fabs(o[15 + r] - c));
+            re += h * h;
+        }
+        re = sqrt(re) * (1.0 + 1e-12);
+        double Ld[K];
+        int Lf[K];
 #pragma unroll
-        for (int k = 0; k < kHxK1; ++k) {
+        for (int k = 0; k < K; ++k) {
             Ld[k] = INFINITY;
             Lf[k] = 0x7fffffff;
         }
@@ -236,10 +248,25 @@ __global__ __launch_bounds__(kHT) void k_hx_approx(const double *__restrict__ P,
                     sF[q][3 * k + 2] = F[18 + cn[k]];
                 }
                 for (int d = 0; d < 3; ++d) sF[q][12 + d] = (((F[9 * d] + F[9 * d + 2]) + F[9 * d + 6]) + F[9 * d + 8]) * 0.25;
+                double rf = 0.0;
+                for (int k = 0; k < 4; ++k) {
+                    const double ax = sF[q][3 * k] - sF[q][12], ay = sF[q][3 * k + 1] - sF[q][13],
+                                 az = sF[q][3 * k + 2] - sF[q][14];
+                    rf = fmax(rf, ax * ax + ay * ay + az * az);
+                }
+                sF[q][15] = sqrt(rf) * (1.0 + 1e-12);
             }
             __syncthreads();
             if (!act) continue;
             for (int q = sub; q < tn; q += kHxSub) {
+                const double dx = sF[q][12] - o[0], dy = sF[q][13] - o[1], dz = sF[q][14] - o[2];
+                const double dxc = sqrt((dx * dx + dy * dy) + dz * dz);
+                // the rotated corner box lies within sqrt(3) rf of the rotated
+                // face centroid, so the box distance is at least
+                // dxc - re - sqrt(3) rf; a face whose bound exceeds this
+                // thread's K-th distance cannot enter its list
+                const double lb = 0.01 * dxc + fmax(0.0, dxc - re - 1.7320508075688774 * sF[q][15]);
+                if (lb * (1.0 - 1e-12) > Ld[K - 1]) continue;
                 double Bf[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
                 for (int k = 0; k < 4; ++k)
                     for (int r = 0; r < 3; ++r) {
@@ -247,8 +274,6 @@ __global__ __launch_bounds__(kHT) void k_hx_approx(const double *__restrict__ P,
                         Bf[r] = fmin(Bf[r], v);
                         Bf[3 + r] = fmax(Bf[3 + r], v);
                     }
-                const double dx = sF[q][12] - o[0], dy = sF[q][13] - o[1], dz = sF[q][14] - o[2];
-                const double dxc = sqrt((dx * dx + dy * dy) + dz * dz);
                 double D = 0.0;
                 for (int a = 0; a < 3; ++a)
                     if (Bf[a + 3] < o[12 + a] || o[15 + a] < Bf[a]) {
@@ -258,10 +283,10 @@ __global__ __launch_bounds__(kHT) void k_hx_approx(const double *__restrict__ P,
                 const double dist = 0.01 * dxc + sqrt(D);
                 int cf = (int)(t0 + q);
                 double cd = dist;
-                if (hx_less(cd, cf, Ld[kHxK1 - 1], Lf[kHxK1 - 1])) {
+                if (hx_less(cd, cf, Ld[K - 1], Lf[K - 1])) {
                     // bubble the candidate through the sorted list
 #pragma unroll
-                    for (int k = 0; k < kHxK1; ++k) {
+                    for (int k = 0; k < K; ++k) {
                         const bool sw = hx_less(cd, cf, Ld[k], Lf[k]);
                         const double td = Ld[k];
                         const int tf = Lf[k];
@@ -288,12 +313,12 @@ __global__ __launch_bounds__(kHT) void k_hx_approx(const double *__restrict__ P,
             }
             if (bl == sub) {
 #pragma unroll
-                for (int k = 0; k < kHxK1 - 1; ++k) {
+                for (int k = 0; k < K - 1; ++k) {
                     Ld[k] = Ld[k + 1];
                     Lf[k] = Lf[k + 1];
                 }
-                Ld[kHxK1 - 1] = INFINITY;
-                Lf[kHxK1 - 1] = 0x7fffffff;
+                Ld[K - 1] = INFINITY;
+                Lf[K - 1] = 0x7fffffff;
             }
             if (act && sub == 0) l1[(int64_t)i * nf1 + r] = bf;
         }
@@ -448,12 +473,16 @@ __device__ inline HxTie hx_shfl(const HxTie &a, int d)
 
 // Alg. cp2, one wavefront per listed element: work item (kept face k,
 // element triangle at the kept corner); every item runs over the face's 8
-// lattice triangles.  Writes HOLE only (union over surfaces).
+// lattice triangles.  A pair closer than the tolerance is a hit; the
+// distances are kept in LDS so the tie pass recomputes closest points only
+// for the pairs within the tie threshold.  Writes HOLE only (union over
+// surfaces).
 __global__ __launch_bounds__(64) void k_hx_pass2(const double *__restrict__ enodes, const int32_t *__restrict__ list,
                                                  const int32_t *__restrict__ count, const double *__restrict__ P,
                                                  int nf2, const int32_t *__restrict__ l2, const int8_t *__restrict__ c2,
                                                  int wall, int8_t *__restrict__ iblank)
 {
+    __shared__ double sD[kHxK2 * 24 * 8];
     const int n = *count;
     const int lane = threadIdx.x;
     const int n_items = nf2 * 24;
@@ -462,7 +491,7 @@ __global__ __launch_bounds__(64) void k_hx_pass2(const double *__restrict__ enod
         const double *X = enodes + (int64_t)e * 81;
         bool hit = false;
         double best = INFINITY;
-        for (int it = lane; it < n_items; it += 64) {
+        for (int it = lane; it < n_items && !hit; it += 64) {
             const int k = it / 24, r = it - 24 * k;
             const int f = l2[(int64_t)i * nf2 + k];
             int fl[3];
@@ -470,15 +499,16 @@ __global__ __launch_bounds__(64) void k_hx_pass2(const double *__restrict__ enod
             d3 T[3];
             elem_tri(X, 8 * fl[r >> 3] + (r & 7), T);
             const double *F = P + (int64_t)f * 27;
-            for (int s = 0; s < 8 && !hit; ++s) {
-                d3 S[3];
+            for (int s = 0; s < 8; ++s) {
+                d3 S[3], pa, pb;
                 face_tri(F, s, S);
-                if (tri_tri_within(T, S, kTolHit)) {
+                const double d = tri_tri_dist(T, S, pa, pb);
+                sD[8 * it + s] = d;
+                if (d < kTolHit) {
                     hit = true;
                     break;
                 }
-                d3 pa, pb;
-                best = fmin(best, tri_tri_dist(T, S, pa, pb));
+                best = fmin(best, d);
             }
         }
         if (__ballot(hit)) {
@@ -495,15 +525,12 @@ __global__ __launch_bounds__(64) void k_hx_pass2(const double *__restrict__ enod
             int fl[3];
             hx_corner_faces(c2[(int64_t)i * nf2 + k], fl);
             const int t = 8 * fl[r >> 3] + (r & 7);
-            d3 T[3];
-            elem_tri(X, t, T);
-            const double *F = P + (int64_t)f * 27;
             for (int s = 0; s < 8; ++s) {
-                d3 S[3];
-                face_tri(F, s, S);
-                d3 pa, pb;
-                const double dd = tri_tri_dist(T, S, pa, pb);
-                if (dd > thr) continue;
+                if (sD[8 * it + s] > thr) continue;
+                d3 T[3], S[3], pa, pb;
+                elem_tri(X, t, T);
+                face_tri(P + (int64_t)f * 27, s, S);
+                tri_tri_dist(T, S, pa, pb);
                 HxTie rec;
                 const d3 v = pa - pb;
                 const double L = sqrt(dot(v, v));
@@ -630,7 +657,14 @@ oc_status filtered_cut_run(oc_slot *sl, Grid &g, Surf *const *surfs, const Pose 
         int32_t *l1 = reinterpret_cast<int32_t *>(base + o_l1), *l2 = reinterpret_cast<int32_t *>(base + o_l2);
         int8_t *c1 = reinterpret_cast<int8_t *>(base + o_c1), *c2 = reinterpret_cast<int8_t *>(base + o_c2);
         LAUNCH(k_hx_obb, dim3(hx_blocks(n, kHT)), dim3(kHT), g.enodes, list, cnt, obb);
-        LAUNCH(k_hx_approx, dim3(hx_blocks(n, kHxElems)), dim3(kHT), P, s.n_face, obb, cnt, k1, l1);
+        if (k1 <= 4)
+            LAUNCH(k_hx_approx<4>, dim3(hx_blocks(n, kHxElems)), dim3(kHT), P, s.n_face, obb, cnt, k1, l1);
+        else if (k1 <= 8)
+            LAUNCH(k_hx_approx<8>, dim3(hx_blocks(n, kHxElems)), dim3(kHT), P, s.n_face, obb, cnt, k1, l1);
+        else if (k1 <= 16)
+            LAUNCH(k_hx_approx<16>, dim3(hx_blocks(n, kHxElems)), dim3(kHT), P, s.n_face, obb, cnt, k1, l1);
+        else
+            LAUNCH(k_hx_approx<kHxK1>, dim3(hx_blocks(n, kHxElems)), dim3(kHT), P, s.n_face, obb, cnt, k1, l1);
         LAUNCH(k_hx_pass1, dim3(hx_blocks((int64_t)n * k1, kHT)), dim3(kHT), g.enodes, list, cnt, P, k1, l1, d1, c1);
         LAUNCH(k_hx_keep2, dim3(hx_blocks(n, kHT)), dim3(kHT), cnt, k1, k2, l1, d1, c1, l2, c2);
         LAUNCH(k_hx_pass2, dim3(hx_blocks(n, 1)), dim3(64), g.enodes, list, cnt, P, k2, l2, c2,
