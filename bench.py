@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--bg", type=int, default=128)
     ap.add_argument("--workload", default="dimpled", choices=["dimpled", "spin", "batch", "serve", "unblank", "ab", "filtered"])
     ap.add_argument("--spin-steps", type=int, default=200)
+    ap.add_argument("--topology", default="walls", choices=["walls", "paper"],
+                    help="ab: the background cut by the walls, or by the shells' overset boundaries")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--rates", default="50,100,200,500", help="serve: arrival rates, requests/s")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
@@ -408,7 +410,7 @@ def run_ab(a):
     bg = case["bg"]
     torch.cuda.set_device(0)
     ctx = oc.Context(device=0)
-    system = OversetSystem(ctx, case, bg_points_cap=27 * 40000)
+    system = OversetSystem(ctx, case, bg_points_cap=27 * 40000, topology=a.topology)
     poses = case["poses"]
     ss = SlotStep(system, ab=True)
     # the plain step: the same launches, eager, chains one after the other,
@@ -467,8 +469,10 @@ def run_ab(a):
                data="synthetic",
                config=dict(workload="dimpled sphere, artificial-boundary receptors: %d^3 background, 24576-face "
                                     "300-dimple sphere, 8-layer shell; cut + AB faces + 3x3 Gauss flux points + "
-                                    "Newton donors + 27 interpolation weights per point, both directions" % a.bg,
-                           bg_elements=bg.n_elem, parallelism="1 GPU"),
+                                    "Newton donors + 27 interpolation weights per point, both directions; the "
+                                    "background cut by %s" % (a.bg, "the wall" if a.topology == "walls" else
+                                                             "the shell's overset boundary"),
+                           bg_elements=bg.n_elem, topology=a.topology, parallelism="1 GPU"),
                donors_per_s=n_pts / (ms / 1e3), points_per_step=n_pts, counts=counts,
                donor_info=dict(bg_to_shell=info_a, shell_to_bg=info_b),
                latency_ms=_percentiles(lat), plain_ms_per_step=ms_plain, speedup_vs_plain=ms_plain / ms,

@@ -42,8 +42,15 @@ class OversetSystem:
     """Registers a case (dict with ``bg`` grid and ``bodies`` [{surface,
     shell}]) on a context and keeps all per-step buffers on the device."""
 
-    def __init__(self, ctx: _oc.Context, case, shell_points_cap=None, bg_points_cap=None):
+    def __init__(self, ctx: _oc.Context, case, shell_points_cap=None, bg_points_cap=None, topology="walls"):
+        """topology "walls": the background is cut by the bodies' walls;
+        "paper": by each near-body grid's overset outer boundary (Sec. 3:
+        background elements enclosed by another grid's overset boundary are
+        removed), the shells by the other bodies' walls."""
+        if topology not in ("walls", "paper"):
+            raise ValueError("topology must be 'walls' or 'paper'")
         self.ctx = ctx
+        self.topology = topology
         dev = torch.device("cuda", ctx.device)
         bg = case["bg"]
         self.bg_id = ctx.register_grid(bg.nodes, bg.conn, bg.face_tags)
@@ -54,7 +61,11 @@ class OversetSystem:
             sid = ctx.register_cut_surface(s.nodes, s.conn, _oc.OC_SURF_WALL)
             gid = ctx.register_grid(sh.nodes, sh.conn, sh.face_tags)
             n_tagged = 0 if sh.face_tags is None else int((np.asarray(sh.face_tags) == _oc.OC_FACE_OVERSET).sum())
-            self.bodies.append(dict(surf=sid, shell=gid, n_shell=sh.n_elem, n_tagged=n_tagged))
+            d = dict(surf=sid, shell=gid, n_shell=sh.n_elem, n_tagged=n_tagged)
+            if topology == "paper":
+                bnd = b["boundary"]
+                d["bsurf"] = ctx.register_cut_surface(bnd.nodes, bnd.conn, _oc.OC_SURF_OVERSET)
+            self.bodies.append(d)
         self.ib_bg = torch.empty(self.n_bg, dtype=torch.int8, device=dev)
         cap_bg = bg_points_cap or 27 * self.n_bg
         self.pts_bg = torch.empty((cap_bg, 3), dtype=torch.float64, device=dev)
@@ -70,6 +81,10 @@ class OversetSystem:
             b["donor_bg"] = torch.empty(cap_bg, dtype=torch.int32, device=dev)
             b["ref_bg"] = torch.empty((cap_bg, 3), dtype=torch.float64, device=dev)
 
+    def bg_cutters(self):
+        """Surface ids that cut the background, one per body."""
+        return [b["bsurf"] if self.topology == "paper" else b["surf"] for b in self.bodies]
+
     def step(self, poses, stats=False):
         """Full connectivity step at the given body poses; returns counts.
         With ``stats`` the cut and donor counters of each call are collected
@@ -77,7 +92,7 @@ class OversetSystem:
         ctx = self.ctx
         poses = [np.asarray(p, dtype=np.float64) for p in poses]
         sids = [b["surf"] for b in self.bodies]
-        ctx.cut_multi(self.bg_id, sids, np.concatenate(poses), self.ib_bg)
+        ctx.cut_multi(self.bg_id, self.bg_cutters(), np.concatenate(poses), self.ib_bg)
         st = dict(bg_cut=ctx.last_cut_info(), donor_bg=[], donor_shell=[]) if stats else None
         for i, b in enumerate(self.bodies):
             others = [j for j in range(len(self.bodies)) if j != i]
@@ -181,7 +196,7 @@ class SlotStep:
         if warm and nb != 1:
             raise ValueError("warm start needs exactly one body")
         grids = [system.bg_id] + [b["shell"] for b in system.bodies]
-        surfs = [b["surf"] for b in system.bodies]
+        surfs = [b["surf"] for b in system.bodies] + (system.bg_cutters() if system.topology == "paper" else [])
         self.ab = ab
         self.nodes1d = tuple(float(v) for v in nodes1d)
         if ab:
@@ -244,15 +259,16 @@ class SlotStep:
             side = main
         nb = len(s.bodies)
         sids = [b["surf"] for b in s.bodies]
+        cutters = s.bg_cutters()
         bufs = o["ib_bg"]
         ib_bg = bufs[k % len(bufs)]
         ident = self.poses_dev[self.n_pose - 1]
         side.wait_stream(main)
         # chain A: background
         if self.warm and not cold:
-            sa.cut_warm(s.bg_id, sids[0], self.poses_dev[0], self.sweep, bufs[(k - 1) % 2], ib_bg)
+            sa.cut_warm(s.bg_id, cutters[0], self.poses_dev[0], self.sweep, bufs[(k - 1) % 2], ib_bg)
         else:
-            sa.cut(s.bg_id, sids, self.poses_dev[:nb], ib_bg)
+            sa.cut(s.bg_id, cutters, self.poses_dev[:nb], ib_bg)
         cap_bg = o["pts_bg"].shape[0]
         z = self.nodes1d
         if self.ab:

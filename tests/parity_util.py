@@ -92,16 +92,23 @@ def compare(g, o):
         _cmp_donors(gb["donor"], gb["ref"], ob["donor"], ob["ref"], "shell %d->bg" % k)
 
 
-def oracle_ab_step(case, poses, nodes1d=O.GAUSS3, threads=0, ib_bg=None):
+def oracle_ab_step(case, poses, nodes1d=O.GAUSS3, threads=0, ib_bg=None, topology="walls"):
     """The artificial-boundary step computed by the oracle alone: AB faces of
     the background and of each shell, their flux points and donors (weights
     are compared at the GPU's own reference coordinates, see compare_ab).
-    ib_bg: the background blanking when already known."""
+    ib_bg: the background blanking when already known.  topology "paper":
+    the background is cut by the shells' overset boundaries."""
     bg = case["bg"]
     walls = [b["surface"] for b in case["bodies"]]
     m2 = len(nodes1d) ** 2
     out = {}
-    out["ib_bg"] = O.cut(bg, walls, poses, threads=threads) if ib_bg is None else ib_bg
+    if ib_bg is None:
+        if topology == "paper":
+            ib_bg = O.cut(bg, [b["boundary"] for b in case["bodies"]], poses,
+                          kinds=[O.SURF_OVERSET] * len(walls), threads=threads)
+        else:
+            ib_bg = O.cut(bg, walls, poses, threads=threads)
+    out["ib_bg"] = ib_bg
     out["faces_bg"] = O.ab_faces(bg, out["ib_bg"])
     out["pts_bg"] = O.face_points(bg, out["faces_bg"], nodes1d)
     out["src_bg"] = np.repeat(out["faces_bg"], m2)

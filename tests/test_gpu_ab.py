@@ -246,3 +246,36 @@ def test_ab_slot_step_two_bodies(ctx, orc):
         assert c["n_bg_faces"] > 0 and all(f > s.n_face for f in c["n_shell_faces"])
         compare_ab(got, oracle_ab_step(case, poses))
     ss.close()
+
+
+def test_ab_step_paper_topology(ctx, orc):
+    """The paper's cut topology (Sec. 3): the background is cut by each
+    near-body grid's overset outer boundary (elements it encloses are
+    removed, elements it crosses stay), the shells by the other bodies'
+    walls; the AB step of that system, one body and two, against the oracle."""
+    import torch
+    from paper_1711_07663_amd.pipeline import OversetSystem, SlotStep
+    from parity_util import compare_ab, oracle_ab_step
+    _note("AB step, paper topology: one body, then two bodies 1.2 apart")
+    bg = M.background_grid(24, -1.6, 1.6, amp=0.03)
+    s = M.cube_sphere(6, R=0.5, dimples=30, dimple_a=0.08, dimple_k=0.02)
+    sh = M.shell_grid(s, 3, r_out=0.95)
+    bnd = M.shell_boundary(sh, s)
+    one = dict(bg=bg, bodies=[dict(surface=s, shell=sh, boundary=bnd)])
+    two = dict(bg=bg, bodies=[dict(surface=s, shell=sh, boundary=bnd)] * 2)
+    for case, poses in ((one, [M.pose_rz(0.4, (0.06, -0.02, 0.03))]),
+                        (two, [M.pose_rz(0.3, (-0.6, 0.0, 0.0)), M.pose_rz(-0.3, (0.6, 0.0, 0.0))])):
+        system = OversetSystem(ctx, case, topology="paper")
+        ss = SlotStep(system, ab=True)
+        ss.step(poses)
+        got = ss.snapshot()
+        o = oracle_ab_step(case, poses, topology="paper")
+        compare_ab(got, o)
+        assert (got["ib_bg"] == 0).sum() > 0
+        if case is one:
+            # every background receptor lies inside the one shell
+            assert np.all(got["bodies"][0]["donor_bg"] >= 0)
+        ss.capture()
+        ss.replay(poses)
+        compare_ab(ss.snapshot(), o)
+        ss.close()

@@ -31,7 +31,8 @@ def make_case(bg_n, bg_lo, bg_hi, m, layers, R=0.5, dimples=0, axes=None, amp=0.
     surf = M.cube_sphere(m, R=R, axes=axes, dimples=dimples, dimple_a=DIMPLE_A,
                          dimple_k=DIMPLE_K, name=name + "/wall")
     shell = M.shell_grid(surf, layers, r_out=r_out, scale_out=scale_out, name=name + "/shell")
-    return dict(name=name, bg=bg, bodies=[dict(surface=surf, shell=shell)],
+    return dict(name=name, bg=bg, bodies=[dict(surface=surf, shell=shell,
+                                               boundary=M.shell_boundary(shell, surf, name + "/boundary"))],
                 poses=[M.IDENTITY_POSE.copy()])
 
 
@@ -97,7 +98,8 @@ def two_body(bg_n=160, m=64, layers=8, dimples=300):
     surf = M.cube_sphere(m, R=0.5, dimples=dimples, dimple_a=DIMPLE_A, dimple_k=DIMPLE_K,
                          name="two-body/wall")
     shell = M.shell_grid(surf, layers, r_out=1.0, name="two-body/shell")
-    bodies = [dict(surface=surf, shell=shell), dict(surface=surf, shell=shell)]
+    bnd = M.shell_boundary(shell, surf, "two-body/boundary")
+    bodies = [dict(surface=surf, shell=shell, boundary=bnd), dict(surface=surf, shell=shell, boundary=bnd)]
     poses = [M.pose_rz(0.0, (-0.75, 0.0, 0.0)), M.pose_rz(0.0, (0.75, 0.0, 0.0))]
     return dict(name="two-body", bg=bg, bodies=bodies, poses=poses)
 

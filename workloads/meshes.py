@@ -233,6 +233,16 @@ def shell_grid(surf: Surface, layers, r_out=1.0, scale_out=None, name="shell"):
     return Grid(nodes=nodes, conn=conn.astype(np.int32), face_tags=tags, name=name)
 
 
+def shell_boundary(shell: Grid, surf: Surface, name="boundary"):
+    """The outer (overset) boundary of a near-body grid made by shell_grid,
+    as a closed cut surface: the outermost node level (the same coordinates
+    as the grid's outer faces) with the wall's face connectivity, so it is
+    oriented outward like the wall."""
+    ns = surf.nodes.shape[0]
+    nlev = shell.nodes.shape[0] // ns
+    return Surface(nodes=np.ascontiguousarray(shell.nodes[(nlev - 1) * ns:]), conn=surf.conn.copy(), name=name)
+
+
 # --------------------------------------------------------------------------
 # poses
 # --------------------------------------------------------------------------
