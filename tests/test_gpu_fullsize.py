@@ -244,3 +244,45 @@ def test_filtered_full_size(orc):
     bad = np.nonzero(got != ref)[0]
     assert bad.size == 0, "%d elements differ, first %s" % (bad.size, bad[:8])
     _note("full-size filtered cut: %d elements differ from the exact cut" % int((got != ex).sum()))
+
+
+def test_ab_paper_topology_full_size(orc):
+    """The paper's cut topology at full size: the 128^3 background cut by
+    the shell's overset boundary (the r = 1 sphere of 24 576 faces), the AB
+    step of the benchmark's ab workload with --topology paper.  The oracle
+    cuts the band of elements meeting the boundary's box (every other
+    element lies outside it and is field)."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from paper_1711_07663_amd.pipeline import OversetSystem, SlotStep
+    from parity_util import compare_ab, oracle_ab_step
+
+    _note("full-size AB step, paper topology: generating inputs")
+    case = CF.dimpled()
+    bg, bnd = case["bg"], case["bodies"][0]["boundary"]
+    ctx = oc.Context(device=0)
+    try:
+        system = OversetSystem(ctx, case, bg_points_cap=27 * 40000, topology="paper")
+        ss = SlotStep(system, ab=True)
+        ss.step(case["poses"])
+        ss.capture()
+        ss.replay(case["poses"])
+        got = ss.snapshot()
+        ss.close()
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+    _note("full-size AB step, paper topology: oracle band cut by the boundary")
+    P = bg.nodes[bg.conn]
+    elo, ehi = P.min(axis=1), P.max(axis=1)
+    del P
+    h = 6.0 / 128
+    slo, shi = bnd.nodes.min(axis=0), bnd.nodes.max(axis=0)
+    band = np.nonzero(np.all(ehi >= slo - 2 * h, axis=1) & np.all(elo <= shi + 2 * h, axis=1))[0]
+    st = orc.cut_surface(bg, bnd, orc.IDENTITY, kind=orc.SURF_OVERSET, sel=band, threads=0)
+    hole = np.zeros(bg.n_elem, dtype=bool)
+    hole[band] = st == 0
+    ib_o = orc.mark_fringe(hole, orc.face_neighbors(bg.conn))
+    assert hole.sum() > 30000
+    compare_ab(got, oracle_ab_step(case, case["poses"], ib_bg=ib_o))
+    assert np.all(got["bodies"][0]["donor_bg"] >= 0) and np.all(got["bodies"][0]["donor"] >= 0)
