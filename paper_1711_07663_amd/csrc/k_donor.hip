@@ -47,7 +47,21 @@ __device__ inline bool newton_q2(const double *__restrict__ Xg, d3 p, double dia
     for (int it = 0; it < OC_NEWTON_MAXIT; ++it) {
         ++iters;
         double x[3], J[9];
-        q2_map<true, STREAM>(X, xi, x, J);
+        if (it == 0) {
+            // at xi = 0 the basis is l = (0, 1, 0), dl = (-1/2, 0, 1/2) on
+            // every axis: x is the centre node 13 and the Jacobian columns
+            // are half the differences of the opposite face-centre nodes
+            // (14 - 12, 16 - 10, 22 - 4)
+            for (int d = 0; d < 3; ++d) {
+                const double *C = X + 27 * d;
+                x[d] = C[13];
+                J[3 * d] = 0.5 * (C[14] - C[12]);
+                J[3 * d + 1] = 0.5 * (C[16] - C[10]);
+                J[3 * d + 2] = 0.5 * (C[22] - C[4]);
+            }
+        } else {
+            q2_map<true, STREAM>(X, xi, x, J);
+        }
         const double r0 = p.x - x[0], r1 = p.y - x[1], r2 = p.z - x[2];
         if (sqrt(r0 * r0 + r1 * r1 + r2 * r2) <= 1e-13 * diam) {
             conv = true;
