@@ -762,9 +762,11 @@ oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g)
     LAUNCH(k_dbin_fill, dim3(blocks(g.n_elem, kT)), dim3(kT), g.cbox, g.n_elem, g.dgrid, start, count, g.dbin_items);
     LAUNCH(k_dbin_sort, dim3(blocks(nb, kT)), dim3(kT), start, nb, g.dbin_items);
     g.dbin_start = start;
-    // lanes per point in the donor bin walks: about two bin entries per lane
-    // for the typical query (bins weighted by their entry count, since
-    // points fall where elements are)
+    // lanes per point in the donor bin walks: about four bin entries per
+    // lane for the typical query (bins weighted by their entry count, since
+    // points fall where elements are); on the dimpled case one or two
+    // entries per lane run more, emptier waves and are slower, eight starts
+    // to lengthen the per-point chains
     std::vector<int32_t> hs((size_t)nb + 1);
     OC_HIP(hipMemcpyAsync(hs.data(), start, sizeof(int32_t) * (nb + 1), hipMemcpyDeviceToHost, st));
     OC_HIP(hipStreamSynchronize(st));
@@ -776,7 +778,7 @@ oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g)
     }
     const double mean = s1 > 0 ? s2 / s1 : 1.0;
     g.dlanes = 1;
-    while (g.dlanes < 64 && 2.0 * g.dlanes < mean) g.dlanes *= 2;
+    while (g.dlanes < 64 && 4.0 * g.dlanes < mean) g.dlanes *= 2;
     OC_HIP(hipStreamSynchronize(st));
     OC_HIP(hipGetLastError());
     return OC_OK;
