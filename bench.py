@@ -50,21 +50,25 @@ NEWTON_FLOP = 640              # FLOP per Newton iteration of the quadratic map 
 
 KERNEL_SOURCE = {"k_dp_newton": "paper_1711_07663_amd/csrc/k_donor.hip",
                  "k_filter": "paper_1711_07663_amd/csrc/k_cut.hip"}
+# headers every kernel source includes (their device functions are part of the kernels)
+KERNEL_HEADERS = ["paper_1711_07663_amd/csrc/dev_common.h", "paper_1711_07663_amd/csrc/dev_geom.h",
+                  "paper_1711_07663_amd/csrc/q2.h", "paper_1711_07663_amd/csrc/oc_internal.h", "include/oc.h"]
 
 
 def kernel_source_sha(kernel):
-    """SHA-256 of the source text of ``kernel``'s definition (from its
-    ``__global__`` line to the closing brace at column 0)."""
+    """SHA-256 of everything ``kernel`` is compiled from: its source file and
+    the shared headers (so a change to a device function it calls counts)."""
     import hashlib
     src = KERNEL_SOURCE.get(kernel)
     if not src:
         return None
-    lines = open(os.path.join(ROOT, src)).read().split("\n")
-    start = next((i for i, l in enumerate(lines) if l.startswith("__global__") and (" %s(" % kernel) in l), None)
-    if start is None:
-        return None
-    end = next(i for i in range(start, len(lines)) if lines[i] == "}")
-    return hashlib.sha256("\n".join(lines[start:end + 1]).encode()).hexdigest()
+    h = hashlib.sha256()
+    for f in [src] + KERNEL_HEADERS:
+        path = f if os.path.isabs(f) else os.path.join(ROOT, f)
+        if not os.path.exists(path):
+            return None
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
@@ -72,7 +76,7 @@ def measured_traffic(kernel):
     summary profiles/<kernel>_traffic_dimpled128.md (FETCH_SIZE and
     WRITE_SIZE passes scaled by the copy-kernel calibration), or None when
     there is none or the kernel's definition changed since it was taken
-    (the summary records the SHA-256 of the definition's source text)."""
+    (the summary records the SHA-256 of the kernel's sources)."""
     path = os.path.join(ROOT, "profiles", "%s_traffic_dimpled128.md" % kernel)
     if not os.path.exists(path):
         return None

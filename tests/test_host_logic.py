@@ -177,6 +177,11 @@ def test_bench_traffic_follows_kernel_source(tmp_path, monkeypatch):
                    .replace("const int write_field = c.write_field;", "const int write_field = c.write_field;  "))
     monkeypatch.setitem(bench.KERNEL_SOURCE, "k_filter", str(src))
     assert bench.measured_traffic("k_filter") is None
+    # so does a change to a device function in a shared header
+    hdr = tmp_path / "q2.h"
+    hdr.write_text(open(os.path.join(ROOT, "paper_1711_07663_amd/csrc/q2.h")).read() + "\n// edited\n")
+    monkeypatch.setattr(bench, "KERNEL_HEADERS", [str(hdr) if h.endswith("q2.h") else h for h in bench.KERNEL_HEADERS])
+    assert bench.measured_traffic("k_dp_newton") is None
 
 
 def test_bench_refuses_several_gpus():
