@@ -109,6 +109,10 @@ def parse():
     ap.add_argument("--rates", default="50,100,200,500", help="serve: arrival rates, requests/s")
     ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
+    ap.add_argument("--surf-bins", type=float, default=0.0,
+                    help="scale of the wall's bins per axis (0: the library's choice)")
+    ap.add_argument("--exact-waves", type=int, default=0,
+                    help="wavefronts of the persistent exact-stage kernels (0: the library default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first run one plain 512 MiB device-to-device copy (calibrates profiler byte counters)")
     return ap.parse_args()
@@ -188,11 +192,17 @@ def run_dimpled(a):
     bg = case["bg"]
     torch.cuda.set_device(0)
     ctx = oc.Context(device=0)
+    if a.exact_waves:
+        ctx.tune(oc.OC_TUNE_EXACT_WAVES, 0, a.exact_waves)
     log("registering grids and surface")
     t0 = time.perf_counter()
     system = OversetSystem(ctx, case, bg_points_cap=27 * 40000)
     torch.cuda.synchronize()
     t_reg = time.perf_counter() - t0
+    if a.surf_bins:
+        sid = system.bodies[0]["surf"]
+        nb = ctx.tune(oc.OC_TUNE_SURF_BINS, sid, 0)
+        log("wall bins per axis: %d" % ctx.tune(oc.OC_TUNE_SURF_BINS, sid, max(1, int(round(nb * a.surf_bins)))))
     poses = case["poses"]
     log("warmup %d" % a.warmup)
     counts = None
