@@ -43,6 +43,8 @@ __device__ inline bool newton_q2(const double *__restrict__ Xg, d3 p, double dia
     const double *X = STREAM ? Xg : Xr;
     xi[0] = xi[1] = xi[2] = 0.0;
     bool conv = false;
+    // |r| <= 1e-13 diam, compared squared (no square root in the loop)
+    const double rtol = 1e-13 * diam, rtol2 = rtol * rtol;
 #pragma unroll 1
     for (int it = 0; it < OC_NEWTON_MAXIT; ++it) {
         ++iters;
@@ -63,7 +65,7 @@ __device__ inline bool newton_q2(const double *__restrict__ Xg, d3 p, double dia
             q2_map<true, STREAM>(X, xi, x, J);
         }
         const double r0 = p.x - x[0], r1 = p.y - x[1], r2 = p.z - x[2];
-        if (sqrt(r0 * r0 + r1 * r1 + r2 * r2) <= 1e-13 * diam) {
+        if (r0 * r0 + r1 * r1 + r2 * r2 <= rtol2) {
             conv = true;
             break;
         }
@@ -72,7 +74,11 @@ __device__ inline bool newton_q2(const double *__restrict__ Xg, d3 p, double dia
         const double c02 = J[3] * J[7] - J[4] * J[6];
         const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
         if (det == 0.0) break;
-        const double id = 1.0 / det;
+        // 1 / det: hardware reciprocal and two Newton-Raphson corrections
+        // (within an ulp; the quotients only steer the iteration)
+        double id = __builtin_amdgcn_rcp(det);
+        id = fma(id, fma(-det, id, 1.0), id);
+        id = fma(id, fma(-det, id, 1.0), id);
         // inverse = adj / det, adj(i,j) = cofactor(j,i)
         const double d0 = (c00 * r0 + (J[2] * J[7] - J[1] * J[8]) * r1 + (J[1] * J[5] - J[2] * J[4]) * r2) * id;
         const double d1 = (c01 * r0 + (J[0] * J[8] - J[2] * J[6]) * r1 + (J[2] * J[3] - J[0] * J[5]) * r2) * id;
