@@ -607,10 +607,43 @@ def run_unblank(a):
 
     log("warmup pass over %d steps" % n_steps)
     sequence(False)
-    log("timed pass")
+    log("timed pass (eager)")
     t_total, counts, _ = sequence(False)
     _, _, orphans = sequence(True)
-    ms = 1e3 * t_total / n_steps
+    ms_eager = 1e3 * t_total / n_steps
+
+    # the same steps on a slot of their own, device pose tables, replayed
+    # from the two captured parities
+    from paper_1711_07663_amd.pipeline import UnblankStep
+    us = UnblankStep(ctx, gid, sid, shid, ub_cap=20000)
+    tables = [us.table_dev(poses[n], poses[n + 1]) for n in range(1, n_steps + 1)]
+
+    def graph_sequence():
+        us.start(poses[0])
+        torch.cuda.synchronize()
+        evs = []
+        t0 = time.perf_counter()
+        for n in range(1, n_steps + 1):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e0.record(us.stream)
+            us.replay_table(tables[n - 1])
+            e1 = torch.cuda.Event(enable_timing=True)
+            e1.record(us.stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, evs
+
+    us.start(poses[0])
+    us.step(poses[1], poses[2])
+    torch.cuda.synchronize()
+    us.capture()
+    log("graph-replayed pass")
+    graph_sequence()
+    t_graph, evs = graph_sequence()
+    ms = 1e3 * t_graph / n_steps
+    lat = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs]
+    n_ub_last = int(us.n_ub.item())
+    us.close()
     ctx.timing(True)
     sequence(False)
     rep = ctx.timing_report()
@@ -624,8 +657,10 @@ def run_unblank(a):
                config=dict(workload="unblanking of a moving body: the 128^3 dimpled case turning about z at "
                                     "1 rev / 400 steps and oscillating along x (amplitude 0.5); per step two "
                                     "cuts (t, t + dt), wall rule, fringe, cells to unblank, their interior "
-                                    "points and donors in the shell; %d steps, eager" % n_steps,
+                                    "points and donors in the shell; %d steps replayed as HIP graphs" % n_steps,
                            bg_elements=bg.n_elem, parallelism="1 GPU"),
+               latency_ms=_percentiles(lat), eager_ms_per_step=ms_eager, speedup_vs_eager=ms_eager / ms,
+               last_step_cells_unblanked=n_ub_last,
                cells_unblanked=dict(total=n_ub, max_per_step=int(np.max(counts)),
                                     steps_with_any=int(np.count_nonzero(counts))),
                interior_points=27 * n_ub, orphan_points=orphans,

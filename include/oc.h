@@ -320,6 +320,20 @@ oc_status oc_slot_fringe_points(oc_slot *slot, int32_t grid_id, const double *po
  * cap points); pose_dev: device FP64 [12]. */
 oc_status oc_slot_donor_search(oc_slot *slot, int32_t donor_grid_id, const double *pose_dev, const double *points,
                                int64_t cap, const int32_t *n_dev, int32_t *donor_out, double *ref_out);
+/* oc_unblank on a slot: poses_dev is device FP64 [2*n_surf*12], the poses
+ * of t followed by those of t + dt; the number of cells to unblank goes to
+ * the device int32 *n_dev (no synchronisation; at most cap ids written).
+ * The overset rule (surfaces of kind OC_SURF_OVERSET) needs a slot that may
+ * grow (the context's own), the wall rule none. */
+oc_status oc_slot_unblank(oc_slot *slot, int32_t grid_id, const int32_t *surf_ids, int32_t n_surf,
+                          const double *poses_dev, const int8_t *prev_iblank, int8_t *iblank_out, int32_t *unblank_out,
+                          int64_t cap, int32_t *n_dev);
+/* oc_element_points on a slot for the first *n_dev ids of elems (device
+ * count); at most cap points written; their number (27 per element) goes
+ * to the device int32 *n_points_dev (may be NULL). */
+oc_status oc_slot_element_points(oc_slot *slot, int32_t grid_id, const double *pose_dev, const int32_t *elems,
+                                 const int32_t *n_dev, int64_t cap, double *points_out, int32_t *n_points_dev,
+                                 int32_t *src_out);
 /* oc_ab_faces on a slot: at most cap ids written; their number goes to the
  * device int32 *n_dev (no synchronisation). */
 oc_status oc_slot_ab_faces(oc_slot *slot, int32_t grid_id, const int8_t *iblank, int32_t *faces_out, int64_t cap,

@@ -1146,6 +1146,42 @@ oc_status oc_slot_donor_search(oc_slot *sl, int32_t donor_grid_id, const double 
     return donor_run(sl, *g, reinterpret_cast<const Pose *>(pose_dev), points, cap, n_dev, donor_out, ref_out);
 }
 
+oc_status oc_slot_unblank(oc_slot *sl, int32_t grid_id, const int32_t *surf_ids, int32_t n_surf, const double *poses_dev,
+                          const int8_t *prev_iblank, int8_t *iblank_out, int32_t *unblank_out, int64_t cap,
+                          int32_t *n_dev)
+{
+    if (!sl || !prev_iblank || !iblank_out || !n_dev || cap < 0 || (cap > 0 && !unblank_out) || n_surf < 0 ||
+        (n_surf > 0 && (!surf_ids || !poses_dev)) || ((uintptr_t)poses_dev & 7) || prev_iblank == iblank_out) {
+        set_error("oc_slot_unblank: invalid arguments");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
+    const Pose *P = reinterpret_cast<const Pose *>(poses_dev);
+    return unblank_run(sl, *g, ss.data(), n_surf, P, P + n_surf, prev_iblank, iblank_out, unblank_out, cap, n_dev,
+                       nullptr);
+}
+
+oc_status oc_slot_element_points(oc_slot *sl, int32_t grid_id, const double *pose_dev, const int32_t *elems,
+                                 const int32_t *n_dev, int64_t cap, double *points_out, int32_t *n_points_dev,
+                                 int32_t *src_out)
+{
+    if (!sl || !pose_dev || ((uintptr_t)pose_dev & 7) || !n_dev || cap < 0 || (cap > 0 && (!elems || !points_out))) {
+        set_error("oc_slot_element_points: invalid arguments");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    return element_points_run(sl, *g, reinterpret_cast<const Pose *>(pose_dev), elems, n_dev, points_out, cap,
+                              n_points_dev, src_out);
+}
+
 oc_status oc_slot_ab_faces(oc_slot *sl, int32_t grid_id, const int8_t *iblank, int32_t *faces_out, int64_t cap,
                            int32_t *n_dev)
 {

@@ -31,7 +31,7 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_slot_fringe_points", "oc_slot_donor_search", "oc_slot_cut_info", "oc_slot_donor_info",
            "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm", "oc_cut_batch", "oc_slot_cut_batch",
            "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points", "oc_ab_faces", "oc_face_points",
-           "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered"]
+           "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered", "oc_slot_unblank", "oc_slot_element_points"]
 
 
 class OcError(RuntimeError):
@@ -112,6 +112,8 @@ def load(path=LIB_PATH):
         "oc_slot_face_points": ([vp, C.c_int32, vp, vp, vp, C.c_int64, dp, C.c_int32, vp, C.c_int64, vp, vp]),
         "oc_slot_interp_weights": ([vp, vp, vp, vp, C.c_int64, dp, C.c_int32, vp]),
         "oc_cut_filtered": ([vp, C.c_int32, i32p, dp, C.c_int32, C.c_int32, C.c_int32, vp, i64p]),
+        "oc_slot_unblank": ([vp, C.c_int32, i32p, C.c_int32, vp, vp, vp, vp, C.c_int64, vp]),
+        "oc_slot_element_points": ([vp, C.c_int32, vp, vp, vp, C.c_int64, vp, vp, vp]),
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -483,6 +485,25 @@ class Slot:
                                            _dptr(points, torch.float64, 3 * cap), int(cap),
                                            _dev_or_null(n_dev, torch.int32), _dptr(donor, torch.int32, cap),
                                            _dptr(ref, torch.float64, 3 * cap)))
+
+    def unblank(self, grid_id, surf_ids, poses_dev, prev_iblank, iblank, unblank_out, n_dev):
+        """poses_dev: float64 [2k, 12] device tensor (poses of t, then of t + dt)."""
+        import torch
+        ids = np.ascontiguousarray(surf_ids, dtype=np.int32)
+        ne = self.ctx.grids[grid_id]
+        _check(load().oc_slot_unblank(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), len(ids),
+                                      _dptr(poses_dev, torch.float64, 24 * len(ids)) if len(ids) else None,
+                                      _dptr(prev_iblank, torch.int8, ne), _dptr(iblank, torch.int8, ne),
+                                      _dptr(unblank_out, torch.int32), unblank_out.numel(),
+                                      _dptr(n_dev, torch.int32, 1)))
+
+    def element_points(self, grid_id, pose_dev, elems, n_dev, points, n_points_dev=None, src=None):
+        import torch
+        cap = points.numel() // 3
+        _check(load().oc_slot_element_points(self._h, grid_id, _dptr(pose_dev, torch.float64, 12),
+                                             _dptr(elems, torch.int32), _dptr(n_dev, torch.int32, 1), cap,
+                                             _dptr(points, torch.float64), _dev_or_null(n_points_dev, torch.int32),
+                                             None if src is None else _dptr(src, torch.int32, cap)))
 
     def ab_faces(self, grid_id, iblank, faces, n_dev):
         import torch

@@ -384,3 +384,106 @@ class SlotStep:
                          w_bg=b["w_bg"][:n_bg].cpu().numpy())
             out["bodies"].append(d)
         return out
+
+
+class UnblankStep:
+    """The time step of a moving body with unblanking (Sec. 3, Alg. unblank)
+    on a slot of its own: the background cut at the poses of t and t + dt
+    (wall rule), the cells to unblank, their 27 interior points and their
+    donors in the body's near-body grid at t.  Poses and counts live on the
+    device and nothing synchronises, so the step can be captured; the two
+    iblank buffers alternate (step k reads buffer k mod 2 as the previous
+    blanking and writes the other), so a captured step exists for each
+    parity."""
+
+    def __init__(self, ctx: _oc.Context, bg_id, surf_id, shell_id, ub_cap, stream=None):
+        self.ctx = ctx
+        self.bg, self.surf, self.shell = bg_id, surf_id, shell_id
+        dev = torch.device("cuda", ctx.device)
+        n_bg = ctx.grids[bg_id]
+        # two cut instances per step (the wall at t and at t + dt)
+        self.slot = ctx.create_slot([bg_id, shell_id], [surf_id, surf_id], 27 * ub_cap, stream)
+        self.ib = [torch.empty(n_bg, dtype=torch.int8, device=dev) for _ in range(2)]
+        self.ub = torch.empty(ub_cap, dtype=torch.int32, device=dev)
+        self.n_ub = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.n_pts = torch.zeros(1, dtype=torch.int32, device=dev)
+        cap = 27 * ub_cap
+        self.cap = cap
+        self.pts = torch.empty((cap, 3), dtype=torch.float64, device=dev)
+        self.src = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.donor = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.ref = torch.empty((cap, 3), dtype=torch.float64, device=dev)
+        # rows: pose at t, pose at t + dt, identity (the background's pose)
+        self.poses = torch.zeros((3, 12), dtype=torch.float64, device=dev)
+        self.k = 0
+        self.graphs = {}
+
+    @property
+    def stream(self):
+        return self.slot.stream
+
+    def close(self):
+        self.slot.close()
+
+    def _table(self, pose_t, pose_tp):
+        return torch.from_numpy(np.stack([np.asarray(pose_t, dtype=np.float64),
+                                          np.asarray(pose_tp, dtype=np.float64), IDENTITY]))
+
+    def start(self, pose0):
+        """Plain cut at the first pose into the first iblank buffer."""
+        with torch.cuda.stream(self.slot.stream):
+            self.poses.copy_(self._table(pose0, pose0))
+        self.slot.cut(self.bg, [self.surf], self.poses[0:1], self.ib[0])
+        self.k = 0
+
+    def _launch(self, k):
+        s = self.slot
+        prev, cur = self.ib[k % 2], self.ib[(k + 1) % 2]
+        s.unblank(self.bg, [self.surf], self.poses[0:2], prev, cur, self.ub, self.n_ub)
+        s.element_points(self.bg, self.poses[2], self.ub, self.n_ub, self.pts, self.n_pts, self.src)
+        s.donor_search(self.shell, self.poses[0], self.pts, self.cap, self.n_pts, self.donor, self.ref)
+
+    def step(self, pose_t, pose_tp):
+        """Eager step k (no synchronisation)."""
+        with torch.cuda.stream(self.slot.stream):
+            self.poses.copy_(self._table(pose_t, pose_tp))
+        self._launch(self.k)
+        self.k += 1
+
+    def capture(self):
+        torch.cuda.synchronize()
+        own = self.slot.stream
+        for par in (0, 1):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                self.slot.set_stream(torch.cuda.current_stream())
+                self._launch(par)
+            self.slot.set_stream(own)
+            self.graphs[par] = g
+        return self.graphs
+
+    def replay_table(self, table):
+        """Graph replay of the next step with a device (or host) pose table
+        [3, 12]: pose at t, at t + dt, identity."""
+        if not self.graphs:
+            self.capture()
+        with torch.cuda.stream(self.slot.stream):
+            self.poses.copy_(table, non_blocking=table.is_cuda)
+            self.graphs[self.k % 2].replay()
+        self.k += 1
+
+    def replay(self, pose_t, pose_tp):
+        self.replay_table(self._table(pose_t, pose_tp))
+
+    def table_dev(self, pose_t, pose_tp):
+        return self._table(pose_t, pose_tp).to(self.poses.device)
+
+    def result(self):
+        """Host copy of the last step (synchronises): new iblank, cells to
+        unblank, their points and donors."""
+        self.slot.stream.synchronize()
+        n = int(self.n_ub.item())
+        m = min(27 * n, self.cap)
+        return dict(ib=self.ib[self.k % 2].cpu().numpy(), ub=self.ub[:n].cpu().numpy(),
+                    pts=self.pts[:m].cpu().numpy(), src=self.src[:m].cpu().numpy(),
+                    donor=self.donor[:m].cpu().numpy(), ref=self.ref[:m].cpu().numpy())

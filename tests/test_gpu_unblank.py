@@ -172,3 +172,42 @@ def test_fringe_points_first_call_of_context(orc):
     finally:
         torch.cuda.synchronize()
         c.close()
+
+
+def test_unblank_step_eager_and_graph(ctx, orc):
+    """The capturable unblank step (slot calls, device counts): three eager
+    steps, then three replays of the two captured parities, each against
+    the oracle's unblanking, interior points and donors."""
+    import torch
+    from paper_1711_07663_amd.pipeline import UnblankStep
+    _note("unblank step on a slot: eager, then graph replays")
+    bg, s, sh = _case()
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    shid = ctx.register_grid(sh.nodes, sh.conn, sh.face_tags)
+    us = UnblankStep(ctx, gid, sid, shid, ub_cap=2000)
+    us.start(_poses(0))
+    prev_o = orc.cut(bg, [s], [_poses(0)])
+    total = 0
+    for k in range(1, 7):
+        if k == 4:
+            us.capture()
+        if k < 4:
+            us.step(_poses(k), _poses(k + 1))
+        else:
+            us.replay(_poses(k), _poses(k + 1))
+        got = us.result()
+        ib_o, ub_o = orc.unblank(bg, [s], [_poses(k)], [_poses(k + 1)], prev_o)
+        assert np.array_equal(got["ib"], ib_o), "step %d" % k
+        assert np.array_equal(got["ub"], ub_o), "step %d" % k
+        p_o = orc.fringe_points(bg, ub_o)
+        assert got["pts"].shape == p_o.shape and (p_o.size == 0 or np.abs(got["pts"] - p_o).max() <= PT_TOL)
+        if ub_o.size:
+            d_o, r_o, _ = orc.donor_search(sh, got["pts"], _poses(k))
+            assert np.array_equal(got["donor"], d_o)
+            ok = d_o >= 0
+            assert np.abs(got["ref"][ok] - r_o[ok]).max() <= XI_TOL
+        total += ub_o.size
+        prev_o = ib_o
+    assert total > 0
+    us.close()
