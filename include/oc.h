@@ -50,7 +50,8 @@ enum {
     OC_ENOTFOUND = -4, /* unknown grid / surface id */
     OC_EBUDGET = -5,   /* the context's HBM budget would be exceeded */
     OC_EGEOM = -6,     /* invalid geometry (open or inverted surface, inverted element) */
-    OC_ECAPACITY = -7  /* an output buffer is too small */
+    OC_ECAPACITY = -7, /* an output buffer is too small */
+    OC_ETIMEDOUT = -8  /* oc_wait: the request has not finished yet */
 };
 
 /* int8 blanking values (hole map values are not reused: hole 0, field 1,
@@ -256,6 +257,48 @@ typedef struct oc_cut_req {
  * oc_last_cut_info then reports totals over the batch. */
 oc_status oc_cut_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req);
 
+/* ---------------------------------------------------------- cut service
+ * Requests served as they arrive (the serving case of Sec. 5: many grids and
+ * bodies, each request one cut of Sec. 4.2).  oc_submit takes one request,
+ * copies its surface ids and host poses, and returns a ticket at once; the
+ * request is ordered after the work enqueued on the context stream
+ * (oc_set_stream) before the call.  It runs on a service slot of its own (a
+ * slot sized for it, with its own stream), so requests submitted while
+ * others run share the device.  A request is admitted as soon as an idle
+ * service slot covers it, or a new one fits within the context's HBM budget
+ * and the slot limit (OC_TUNE_SERVICE_SLOTS); idle slots that do not cover
+ * it are released to make room, least recently used first.  A request that
+ * cannot be admitted yet waits without holding back later requests that
+ * can; queued requests are tried in submission order whenever oc_submit,
+ * oc_wait or oc_service_info is called.
+ *   oc_submit: OC_EINVAL for a bad request or an iblank_out that is the
+ *   output of a request not yet waited for; OC_EBUDGET when the request does
+ *   not fit in the budget even with every service slot released (no ticket
+ *   is issued then).  iblank_out must stay allocated and untouched until
+ *   oc_wait has returned for the ticket.
+ *   oc_wait: blocks until the request has finished (timeout_ms < 0), or for
+ *   at most timeout_ms milliseconds (0 = poll).  OC_OK: iblank_out holds the
+ *   result, equal bit for bit to oc_cut_multi's; OC_ETIMEDOUT: not finished
+ *   yet, the ticket stays valid; any other status is the request's own
+ *   failure.  A ticket is forgotten once oc_wait has returned anything but
+ *   OC_ETIMEDOUT (OC_ENOTFOUND after that, and for tickets never issued).
+ * One host thread per context: the service is not thread safe.  Queued
+ * requests are dropped and service slots released by oc_destroy. */
+typedef oc_cut_req oc_request;
+oc_status oc_submit(oc_ctx *ctx, const oc_request *req, uint64_t *ticket);
+oc_status oc_wait(oc_ctx *ctx, uint64_t ticket, int32_t timeout_ms);
+
+typedef struct oc_service_stats {
+    int32_t slots;        /* service slots held */
+    int32_t running;      /* requests on the device */
+    int32_t queued;       /* requests waiting for admission */
+    int32_t finished;     /* finished, not yet waited for */
+    int32_t peak_running; /* most requests on the device at once so far */
+    int32_t pad;
+    int64_t slot_bytes;   /* device bytes of the service slots */
+} oc_service_stats;
+oc_status oc_service_info(oc_ctx *ctx, oc_service_stats *info);
+
 /* Receptor points: 27 Gauss-Legendre points (3x3x3 tensor, order a+3b+9c)
  * per FRINGE element of iblank, in ascending element id, mapped by
  * eq. reftophys and posed by grid_pose into the world frame.
@@ -369,8 +412,16 @@ oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len);
  *                        (OC_EINVAL); lowering a cap never does that.
  *   OC_TUNE_EXACT_WAVES  arg unused; value = wavefronts launched for each of
  *                        the persistent exact-stage kernels (0 = 8192).
+ *   OC_TUNE_SERVICE_SLOTS arg unused; value = most slots the cut service
+ *                        keeps, hence most requests running at once
+ *                        (1 .. 64, 0 = 4).
+ *   OC_TUNE_HBM_BUDGET   arg unused; value = the context's HBM budget in
+ *                        bytes (0 = none), as oc_config.hbm_budget; later
+ *                        allocations are held to it, memory already held is
+ *                        kept (registration needs transient room beyond
+ *                        what it keeps, so a budget can be set after it).
  * *applied (may be NULL) receives the value in force afterwards. */
-enum { OC_TUNE_SURF_BINS = 1, OC_TUNE_EXACT_WAVES = 2 };
+enum { OC_TUNE_SURF_BINS = 1, OC_TUNE_EXACT_WAVES = 2, OC_TUNE_SERVICE_SLOTS = 3, OC_TUNE_HBM_BUDGET = 4 };
 oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t *applied);
 
 /* Device bytes currently held by the context. */

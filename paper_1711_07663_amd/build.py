@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liboc.so")
-SOURCES = ["oc_api.hip", "k_cut.hip", "k_donor.hip", "k_scan.hip", "k_unblank.hip", "k_ab.hip", "k_heur.hip"]
+SOURCES = ["oc_api.hip", "k_cut.hip", "k_donor.hip", "k_scan.hip", "k_unblank.hip", "k_ab.hip", "k_heur.hip",
+           "oc_service.hip"]
 ARCH = os.environ.get("OC_OFFLOAD_ARCH", "gfx950")
 
 

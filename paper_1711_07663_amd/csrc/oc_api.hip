@@ -211,7 +211,7 @@ static Pose to_pose(const double *p)
     return q;
 }
 
-static bool pose_ok(const double *p)
+bool pose_finite(const double *p)
 {
     if (!p) return false;
     for (int i = 0; i < 12; ++i)
@@ -325,6 +325,7 @@ oc_status oc_destroy(oc_ctx *ctx)
 {
     if (!ctx) return OC_OK;
     (void)hipSetDevice(ctx->device);
+    service_destroy(ctx);
     for (auto sl : ctx->slots) {
         slot_free(sl);
         delete sl;
@@ -597,7 +598,7 @@ oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, co
         return OC_EINVAL;
     }
     for (int k = 0; k < n_surf; ++k)
-        if (!pose_ok(poses + 12 * k)) {
+        if (!pose_finite(poses + 12 * k)) {
             set_error("oc_cut: non-finite pose");
             return OC_EINVAL;
         }
@@ -619,8 +620,12 @@ oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, co
 
 // Validates a batch and resolves its ids; poses of request r start at
 // pose_base[r] (device).
-static oc_status batch_reqs(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req, std::vector<CutReq> &out,
-                            std::vector<std::vector<Surf *>> &surfs, bool need_outputs)
+}  // extern "C"
+
+namespace oc {
+
+oc_status collect_cut_reqs(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req, std::vector<CutReq> &out,
+                          std::vector<std::vector<Surf *>> &surfs, bool need_outputs)
 {
     if (n_req < 0 || (n_req > 0 && !reqs)) {
         set_error("cut batch: invalid arguments");
@@ -644,6 +649,10 @@ static oc_status batch_reqs(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req, 
     return OC_OK;
 }
 
+}  // namespace oc
+
+extern "C" {
+
 oc_status oc_cut_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req)
 {
     if (!ctx) {
@@ -653,7 +662,7 @@ oc_status oc_cut_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req)
     OC_HIP(hipSetDevice(ctx->device));
     std::vector<CutReq> rq;
     std::vector<std::vector<Surf *>> ss;
-    OC_TRY(batch_reqs(ctx, reqs, n_req, rq, ss, true));
+    OC_TRY(collect_cut_reqs(ctx, reqs, n_req, rq, ss, true));
     int n_pose = 0;
     for (int r = 0; r < n_req; ++r) n_pose += reqs[r].n_surf;
     if (n_pose > kPoseSlots - 2) {
@@ -664,7 +673,7 @@ oc_status oc_cut_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req)
     P.reserve((size_t)n_pose * 12);
     for (int r = 0; r < n_req; ++r)
         for (int k = 0; k < reqs[r].n_surf; ++k) {
-            if (!pose_ok(reqs[r].poses + 12 * k)) {
+            if (!pose_finite(reqs[r].poses + 12 * k)) {
                 set_error("oc_cut_batch: non-finite pose");
                 return OC_EINVAL;
             }
@@ -708,7 +717,7 @@ oc_status oc_last_donor_info(oc_ctx *ctx, oc_donor_info *info)
 oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int8_t *iblank,
                            double *points_out, int64_t cap, int64_t *n_out, int32_t *src_out)
 {
-    if (!ctx || !iblank || !n_out || cap < 0 || (cap > 0 && !points_out) || !pose_ok(grid_pose)) {
+    if (!ctx || !iblank || !n_out || cap < 0 || (cap > 0 && !points_out) || !pose_finite(grid_pose)) {
         set_error("oc_fringe_points: invalid arguments");
         return OC_EINVAL;
     }
@@ -723,7 +732,7 @@ oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[
 oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12], const double *points,
                           int64_t n, int32_t *donor_out, double *ref_out)
 {
-    if (!ctx || n < 0 || (n > 0 && (!points || !donor_out || !ref_out)) || !pose_ok(grid_pose)) {
+    if (!ctx || n < 0 || (n > 0 && (!points || !donor_out || !ref_out)) || !pose_finite(grid_pose)) {
         set_error("oc_donor_search: invalid arguments");
         return OC_EINVAL;
     }
@@ -752,7 +761,7 @@ static double sweep_bound(const Surf &s, const double *a, const double *b)
 
 oc_status oc_sweep_bound(oc_ctx *ctx, int32_t surf_id, const double pose_a[12], const double pose_b[12], double *out)
 {
-    if (!ctx || !out || !pose_ok(pose_a) || !pose_ok(pose_b)) {
+    if (!ctx || !out || !pose_finite(pose_a) || !pose_finite(pose_b)) {
         set_error("oc_sweep_bound: invalid arguments");
         return OC_EINVAL;
     }
@@ -765,7 +774,7 @@ oc_status oc_sweep_bound(oc_ctx *ctx, int32_t surf_id, const double pose_a[12], 
 oc_status oc_cut_warm(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pose[12], const double prev_pose[12],
                       const int8_t *prev_iblank, int8_t *iblank_out)
 {
-    if (!ctx || !iblank_out || !prev_iblank || !aligned4(iblank_out) || !pose_ok(pose) || !pose_ok(prev_pose) ||
+    if (!ctx || !iblank_out || !prev_iblank || !aligned4(iblank_out) || !pose_finite(pose) || !pose_finite(prev_pose) ||
         prev_iblank == iblank_out) {
         set_error("oc_cut_warm: invalid arguments");
         return OC_EINVAL;
@@ -799,7 +808,7 @@ oc_status oc_unblank(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, int3
         return OC_EINVAL;
     }
     for (int k = 0; k < n_surf; ++k)
-        if (!pose_ok(poses_t + 12 * k) || !pose_ok(poses_tp + 12 * k)) {
+        if (!pose_finite(poses_t + 12 * k) || !pose_finite(poses_tp + 12 * k)) {
             set_error("oc_unblank: non-finite pose");
             return OC_EINVAL;
         }
@@ -818,7 +827,7 @@ oc_status oc_unblank(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, int3
 oc_status oc_element_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int32_t *elems, int64_t n,
                             double *points_out, int32_t *src_out)
 {
-    if (!ctx || n < 0 || (n > 0 && (!elems || !points_out)) || !pose_ok(grid_pose) || n > INT32_MAX / 27) {
+    if (!ctx || n < 0 || (n > 0 && (!elems || !points_out)) || !pose_finite(grid_pose) || n > INT32_MAX / 27) {
         set_error("oc_element_points: invalid arguments");
         return OC_EINVAL;
     }
@@ -843,7 +852,7 @@ oc_status oc_cut_filtered(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids,
         return OC_EINVAL;
     }
     for (int k = 0; k < n_surf; ++k)
-        if (!pose_ok(poses + 12 * k)) {
+        if (!pose_finite(poses + 12 * k)) {
             set_error("oc_cut_filtered: non-finite pose");
             return OC_EINVAL;
         }
@@ -910,7 +919,7 @@ oc_status oc_face_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12
 {
     Nodes1D z;
     OC_TRY(get_nodes1d(nodes1d, m, &z, "oc_face_points"));
-    if (!ctx || n < 0 || (n > 0 && (!faces || !points_out)) || !pose_ok(grid_pose) || n > INT32_MAX / (m * m)) {
+    if (!ctx || n < 0 || (n > 0 && (!faces || !points_out)) || !pose_finite(grid_pose) || n > INT32_MAX / (m * m)) {
         set_error("oc_face_points: invalid arguments");
         return OC_EINVAL;
     }
@@ -939,6 +948,34 @@ oc_status oc_interp_weights(oc_ctx *ctx, const int32_t *donors, const double *re
 }
 
 // ------------------------------------------------------------- slot API --
+}  // extern "C"
+
+namespace oc {
+
+oc_status slot_make(oc_ctx *ctx, const CutReq *rq, int n_req, int64_t points_cap, hipStream_t stream,
+                    oc_slot **out)
+{
+    int64_t ne = 1;
+    for (int r = 0; r < n_req; ++r) ne = std::max(ne, rq[r].g->n_elem);
+    oc_slot *sl = new oc_slot();
+    sl->stream = stream;
+    oc_status st = slot_init(ctx, sl, false);
+    if (st == OC_OK) st = slot_alloc_lists(sl, ne);
+    if (st == OC_OK) st = slot_alloc_cut(sl, cut_caps(rq, n_req));
+    if (st == OC_OK && points_cap > 0) st = slot_alloc_points(sl, points_cap);
+    if (st != OC_OK) {
+        slot_free(sl);
+        delete sl;
+        return st;
+    }
+    *out = sl;
+    return OC_OK;
+}
+
+}  // namespace oc
+
+extern "C" {
+
 oc_status oc_slot_create(oc_ctx *ctx, const int32_t *grid_ids, int32_t n_grids, const int32_t *surf_ids,
                          int32_t n_surfs, int64_t points_cap, oc_slot **out)
 {
@@ -1006,15 +1043,29 @@ oc_status oc_slot_set_stream(oc_slot *sl, void *hip_stream)
     return OC_OK;
 }
 
+}  // extern "C"
+
+namespace oc {
+
+int64_t slot_bytes(const oc_slot *sl)
+{
+    int64_t b = 0;
+    for (auto &d : sl->owned) b += (int64_t)d.bytes;
+    for (auto &d : sl->cut_owned) b += (int64_t)d.bytes;
+    return b;
+}
+
+}  // namespace oc
+
+extern "C" {
+
 oc_status oc_slot_bytes(oc_slot *sl, int64_t *bytes)
 {
     if (!sl || !bytes) {
         set_error("oc_slot_bytes: invalid arguments");
         return OC_EINVAL;
     }
-    int64_t b = 0;
-    for (auto &d : sl->owned) b += (int64_t)d.bytes;
-    *bytes = b;
+    *bytes = slot_bytes(sl);
     return OC_OK;
 }
 
@@ -1051,7 +1102,7 @@ oc_status oc_slot_cut_batch(oc_slot *sl, const oc_cut_req *reqs, int32_t n_req)
     OC_HIP(hipSetDevice(ctx->device));
     std::vector<CutReq> rq;
     std::vector<std::vector<Surf *>> ss;
-    OC_TRY(batch_reqs(ctx, reqs, n_req, rq, ss, true));
+    OC_TRY(collect_cut_reqs(ctx, reqs, n_req, rq, ss, true));
     for (int r = 0; r < n_req; ++r) {
         if ((uintptr_t)reqs[r].poses & 7) {
             set_error("oc_slot_cut_batch: poses must be 8-byte aligned");
@@ -1073,19 +1124,9 @@ oc_status oc_slot_create_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_re
     OC_HIP(hipSetDevice(ctx->device));
     std::vector<CutReq> rq;
     std::vector<std::vector<Surf *>> ss;
-    OC_TRY(batch_reqs(ctx, reqs, n_req, rq, ss, false));
-    int64_t ne = 1;
-    for (auto &q : rq) ne = std::max(ne, q.g->n_elem);
-    oc_slot *sl = new oc_slot();
-    oc_status st = slot_init(ctx, sl, false);
-    if (st == OC_OK) st = slot_alloc_lists(sl, ne);
-    if (st == OC_OK) st = slot_alloc_cut(sl, cut_caps(rq.data(), n_req));
-    if (st == OC_OK && points_cap > 0) st = slot_alloc_points(sl, points_cap);
-    if (st != OC_OK) {
-        slot_free(sl);
-        delete sl;
-        return st;
-    }
+    OC_TRY(collect_cut_reqs(ctx, reqs, n_req, rq, ss, false));
+    oc_slot *sl;
+    OC_TRY(slot_make(ctx, rq.data(), n_req, points_cap, nullptr, &sl));
     ctx->slots.push_back(sl);
     *out = sl;
     return OC_OK;
@@ -1324,6 +1365,20 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
         }
         ctx->exact_waves = value == 0 ? 8192 : (int)value;
         v = ctx->exact_waves;
+    } else if (knob == OC_TUNE_SERVICE_SLOTS) {
+        if (value < 0 || value > 64) {
+            set_error("oc_tune: service slots out of range");
+            return OC_EINVAL;
+        }
+        ctx->service_slots = value == 0 ? 4 : (int)value;
+        v = ctx->service_slots;
+    } else if (knob == OC_TUNE_HBM_BUDGET) {
+        if (value < 0) {
+            set_error("oc_tune: negative budget");
+            return OC_EINVAL;
+        }
+        ctx->budget = value;
+        v = ctx->budget;
     } else {
         set_error("oc_tune: unknown knob");
         return OC_EINVAL;

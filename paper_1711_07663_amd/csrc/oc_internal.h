@@ -211,6 +211,8 @@ struct oc_slot {
 
 namespace oc {
 
+struct Service;   // cut service state (oc_submit / oc_wait)
+
 struct TimingRec {
     hipEvent_t a, b;
     const char *name;
@@ -236,6 +238,9 @@ struct oc_ctx {
     std::vector<oc::TimingRec> trecs;
     std::vector<hipEvent_t> event_pool;
     size_t event_next = 0;
+    // cut service (oc_submit / oc_wait)
+    oc::Service *service = nullptr;
+    int service_slots = 4;                 // most slots the service keeps
 };
 
 namespace oc {
@@ -284,6 +289,18 @@ struct CutReq {
     double sweep = 0.0;
 };
 CutCaps cut_caps(const CutReq *reqs, int n);
+// validate the public requests and resolve their grids and surfaces (poses
+// are left null; with need_outputs the outputs and poses must be given)
+oc_status collect_cut_reqs(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req, std::vector<CutReq> &out,
+                           std::vector<std::vector<Surf *>> &surfs, bool need_outputs);
+// a slot sized for batches shaped like rq, on the given stream (not entered
+// in ctx->slots)
+oc_status slot_make(oc_ctx *ctx, const CutReq *rq, int n_req, int64_t points_cap, hipStream_t stream,
+                    oc_slot **out);
+int64_t slot_bytes(const oc_slot *sl);
+bool pose_finite(const double *p);
+// the cut service's slots and queue, released with the context
+void service_destroy(oc_ctx *ctx);
 // every request's cuts in one launch per stage
 oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n);
 // statistics of the slot's last cut batch into sl->counters (stream ordered)

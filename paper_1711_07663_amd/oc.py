@@ -19,10 +19,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboc.so")
 
 OC_OK, OC_EINVAL, OC_ENOMEM, OC_EDEVICE, OC_ENOTFOUND, OC_EBUDGET, OC_EGEOM, OC_ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
+OC_ETIMEDOUT = -8
 OC_HOLE, OC_FIELD, OC_FRINGE = 0, 1, -1
 OC_SURF_WALL, OC_SURF_OVERSET = 0, 1
 OC_FACE_INTERIOR, OC_FACE_WALL, OC_FACE_OVERSET, OC_FACE_FARFIELD = 0, 1, 2, 3
-OC_TUNE_SURF_BINS, OC_TUNE_EXACT_WAVES = 1, 2
+OC_TUNE_SURF_BINS, OC_TUNE_EXACT_WAVES, OC_TUNE_SERVICE_SLOTS, OC_TUNE_HBM_BUDGET = 1, 2, 3, 4
 
 EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_register_grid",
            "oc_register_cut_surface", "oc_cut", "oc_cut_multi", "oc_last_cut_info", "oc_fringe_points",
@@ -31,7 +32,8 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_slot_fringe_points", "oc_slot_donor_search", "oc_slot_cut_info", "oc_slot_donor_info",
            "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm", "oc_cut_batch", "oc_slot_cut_batch",
            "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points", "oc_ab_faces", "oc_face_points",
-           "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered", "oc_slot_unblank", "oc_slot_element_points"]
+           "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered", "oc_slot_unblank", "oc_slot_element_points",
+           "oc_submit", "oc_wait", "oc_service_info"]
 
 
 class OcError(RuntimeError):
@@ -53,6 +55,11 @@ class oc_cut_info(C.Structure):
 class oc_cut_req(C.Structure):
     _fields_ = [("grid_id", C.c_int32), ("n_surf", C.c_int32), ("surf_ids", C.POINTER(C.c_int32)),
                 ("poses", C.c_void_p), ("iblank_out", C.c_void_p)]
+
+
+class oc_service_stats(C.Structure):
+    _fields_ = [("slots", C.c_int32), ("running", C.c_int32), ("queued", C.c_int32), ("finished", C.c_int32),
+                ("peak_running", C.c_int32), ("pad", C.c_int32), ("slot_bytes", C.c_int64)]
 
 
 class oc_donor_info(C.Structure):
@@ -103,6 +110,9 @@ def load(path=LIB_PATH):
         "oc_slot_cut_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32]),
         "oc_slot_create_batch": ([vp, C.POINTER(oc_cut_req), C.c_int32, C.c_int64, C.POINTER(C.c_void_p)]),
         "oc_tune": ([vp, C.c_int32, C.c_int32, C.c_int64, i64p]),
+        "oc_submit": ([vp, C.POINTER(oc_cut_req), C.POINTER(C.c_uint64)]),
+        "oc_wait": ([vp, C.c_uint64, C.c_int32]),
+        "oc_service_info": ([vp, C.POINTER(oc_service_stats)]),
         "oc_unblank": ([vp, C.c_int32, i32p, C.c_int32, dp, dp, vp, vp, vp, C.c_int64, i64p]),
         "oc_element_points": ([vp, C.c_int32, dp, vp, C.c_int64, vp, vp]),
         "oc_ab_faces": ([vp, C.c_int32, vp, vp, C.c_int64, i64p]),
@@ -266,6 +276,28 @@ class Context:
         every request's cuts in one launch per stage."""
         arr, keep = _cut_reqs(self, reqs, device_poses=False)
         _check(load().oc_cut_batch(self._h, arr, len(reqs)))
+
+    def submit(self, grid_id, surf_ids, poses, iblank):
+        """Queue one cut request (host poses [k,12], iblank tensor) on the
+        cut service; returns its ticket at once."""
+        arr, keep = _cut_reqs(self, [(grid_id, surf_ids, poses, iblank)], device_poses=False)
+        t = C.c_uint64(0)
+        _check(load().oc_submit(self._h, arr, C.byref(t)))
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        """True once the request has finished (its iblank is written),
+        False if timeout_ms passed first; raises the request's failure."""
+        st = load().oc_wait(self._h, C.c_uint64(ticket), int(timeout_ms))
+        if st == OC_ETIMEDOUT:
+            return False
+        _check(st)
+        return True
+
+    def service_info(self):
+        v = oc_service_stats()
+        _check(load().oc_service_info(self._h, C.byref(v)))
+        return {n: getattr(v, n) for n, _ in oc_service_stats._fields_ if n != "pad"}
 
     def cut_warm(self, grid_id, surf_id, pose, prev_pose, prev_iblank, iblank):
         import torch

@@ -37,3 +37,14 @@ def test_binding_refuses_missing_library(tmp_path):
             oc.load(str(tmp_path / "missing.so"))
     finally:
         oc._lib = saved
+
+
+def test_service_refuses_null_arguments_without_a_device():
+    """The cut service checks its arguments before any HIP call."""
+    from paper_1711_07663_amd import oc
+    L = oc.load()
+    t = ctypes.c_uint64(99)
+    assert L.oc_submit(None, None, ctypes.byref(t)) == oc.OC_EINVAL
+    assert L.oc_wait(None, 1, 0) == oc.OC_EINVAL
+    assert L.oc_service_info(None, None) == oc.OC_EINVAL
+    assert b"oc_service_info" in L.oc_last_error()
