@@ -751,6 +751,26 @@ def run_batch(a):
             torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / max(1, a.steps // 4)
     same = all(torch.equal(x, y) for x, y in zip(batch_out, plain_ib))
+    # the cut service: every instance submitted back to back (oc_submit) and
+    # then waited for; requests run on service slots of their own streams
+    svc_ib = [torch.empty_like(r[3]) for r in reqs]
+
+    def serve_all():
+        tickets = [ctx.submit(gid, [sid], pz.reshape(1, 12), ib)
+                   for (gid, sid, pz, ne), ib in zip(plain_args, svc_ib)]
+        for t in tickets:
+            ctx.wait(t)
+
+    serve_all()     # creates the service slots
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(max(1, a.steps // 4)):
+        serve_all()
+    t_service = (time.perf_counter() - t0) / max(1, a.steps // 4)
+    svc_info = ctx.service_info()
+    svc_same = all(torch.equal(x, y) for x, y in zip(svc_ib, plain_ib))
+    log("service: %.2f ms for %d requests on %d slots (peak %d running)" % (
+        1e3 * t_service, len(reqs), svc_info["slots"], svc_info["peak_running"]))
     # per-kernel event timing of eager batch launches
     ctx.timing(True)
     for _ in range(5):
@@ -775,6 +795,9 @@ def run_batch(a):
                            instances=len(specs), total_elements=n_tot, total_faces=n_face, parallelism="1 GPU"),
                latency_ms=_percentiles(lat), plain_ms=1e3 * t_plain, plain_elements_per_s=n_tot / t_plain,
                speedup_vs_plain=t_plain / t_batch, batch_equals_plain=bool(same), cut_info=info,
+               service=dict(ms=1e3 * t_service, elements_per_s=n_tot / t_service, equals_plain=bool(svc_same),
+                            slots=svc_info["slots"], peak_running=svc_info["peak_running"],
+                            slot_gb=svc_info["slot_bytes"] / (1 << 30)),
                autotune=dict(params=params, report=tune_report, seconds=t_tune, eager_ms_untuned=1e3 * t_untuned,
                              eager_ms_tuned=1e3 * t_tuned),
                per_kernel=per_kernel, roofline=roof,

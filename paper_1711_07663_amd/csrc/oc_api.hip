@@ -952,16 +952,14 @@ oc_status oc_interp_weights(oc_ctx *ctx, const int32_t *donors, const double *re
 
 namespace oc {
 
-oc_status slot_make(oc_ctx *ctx, const CutReq *rq, int n_req, int64_t points_cap, hipStream_t stream,
+oc_status slot_make(oc_ctx *ctx, const CutCaps &cc, int64_t ne, int64_t points_cap, hipStream_t stream,
                     oc_slot **out)
 {
-    int64_t ne = 1;
-    for (int r = 0; r < n_req; ++r) ne = std::max(ne, rq[r].g->n_elem);
     oc_slot *sl = new oc_slot();
     sl->stream = stream;
     oc_status st = slot_init(ctx, sl, false);
-    if (st == OC_OK) st = slot_alloc_lists(sl, ne);
-    if (st == OC_OK) st = slot_alloc_cut(sl, cut_caps(rq, n_req));
+    if (st == OC_OK) st = slot_alloc_lists(sl, std::max<int64_t>(ne, 1));
+    if (st == OC_OK) st = slot_alloc_cut(sl, cc);
     if (st == OC_OK && points_cap > 0) st = slot_alloc_points(sl, points_cap);
     if (st != OC_OK) {
         slot_free(sl);
@@ -1126,7 +1124,9 @@ oc_status oc_slot_create_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_re
     std::vector<std::vector<Surf *>> ss;
     OC_TRY(collect_cut_reqs(ctx, reqs, n_req, rq, ss, false));
     oc_slot *sl;
-    OC_TRY(slot_make(ctx, rq.data(), n_req, points_cap, nullptr, &sl));
+    int64_t ne = 1;
+    for (auto &q : rq) ne = std::max(ne, q.g->n_elem);
+    OC_TRY(slot_make(ctx, cut_caps(rq.data(), n_req), ne, points_cap, nullptr, &sl));
     ctx->slots.push_back(sl);
     *out = sl;
     return OC_OK;

@@ -293,9 +293,10 @@ CutCaps cut_caps(const CutReq *reqs, int n);
 // are left null; with need_outputs the outputs and poses must be given)
 oc_status collect_cut_reqs(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req, std::vector<CutReq> &out,
                            std::vector<std::vector<Surf *>> &surfs, bool need_outputs);
-// a slot sized for batches shaped like rq, on the given stream (not entered
-// in ctx->slots)
-oc_status slot_make(oc_ctx *ctx, const CutReq *rq, int n_req, int64_t points_cap, hipStream_t stream,
+// a slot with cut capacity cc, element lists for grids of up to ne
+// elements and points_cap donor points, on the given stream (not entered in
+// ctx->slots)
+oc_status slot_make(oc_ctx *ctx, const CutCaps &cc, int64_t ne, int64_t points_cap, hipStream_t stream,
                     oc_slot **out);
 int64_t slot_bytes(const oc_slot *sl);
 bool pose_finite(const double *p);

@@ -1,9 +1,11 @@
 // Cut service: oc_submit queues a cut request and returns a ticket at once,
-// oc_wait retires it.  Requests run on service slots (slots sized for one
-// request, each with its own stream), so requests submitted while others
-// are on the device run beside them.  A request is admitted when an idle
-// slot covers it or a new slot fits in the context's HBM budget; idle slots
-// that do not cover it are released first, oldest first.  A request that
+// oc_wait retires it.  Requests run on service slots (each with its own
+// stream), so requests submitted while others are on the device run beside
+// them.  A request is admitted when an idle slot covers it or a new slot
+// fits in the context's HBM budget; idle slots that do not cover it are
+// released first, oldest first.  New slots are sized for the largest
+// request so far (componentwise), or for the request alone when that does
+// not fit.  A request that
 // cannot be admitted yet stays queued without holding back later requests.
 #include <algorithm>
 #include <chrono>
@@ -51,6 +53,8 @@ struct Service {
     uint64_t next_ticket = 1;
     uint64_t admissions = 0;
     int peak_running = 0;
+    CutCaps hwm;                  // componentwise largest request so far
+    int64_t hwm_ne = 0;
 };
 
 namespace {
@@ -71,7 +75,7 @@ void release(oc_ctx *ctx, SvcSlot &s)
     (void)ctx;
 }
 
-oc_status new_slot(oc_ctx *ctx, const CutReq &rq, SvcSlot *out)
+oc_status new_slot(oc_ctx *ctx, const CutCaps &cc, int64_t ne, SvcSlot *out)
 {
     hipStream_t st = nullptr;
     hipEvent_t ev = nullptr;
@@ -84,7 +88,7 @@ oc_status new_slot(oc_ctx *ctx, const CutReq &rq, SvcSlot *out)
         return OC_EDEVICE;
     }
     oc_slot *sl;
-    oc_status r = slot_make(ctx, &rq, 1, 0, st, &sl);
+    oc_status r = slot_make(ctx, cc, ne, 0, st, &sl);
     if (r != OC_OK) {
         (void)hipStreamDestroy(st);
         (void)hipEventDestroy(ev);
@@ -132,6 +136,13 @@ Admit try_admit(oc_ctx *ctx, Service &sv, SvcReq &q, Done *fail)
     }
     const CutCaps need = cut_caps(rq.data(), 1);
     const int64_t ne = rq[0].g->n_elem;
+    CutCaps big = sv.hwm;
+    big.elem_inst = std::max(big.elem_inst, need.elem_inst);
+    big.faces = std::max(big.faces, need.faces);
+    big.bins = std::max(big.bins, need.bins);
+    big.cuts = std::max(big.cuts, need.cuts);
+    big.outs = std::max(big.outs, need.outs);
+    const int64_t big_ne = std::max(sv.hwm_ne, ne);
     // the smallest idle slot that covers the request
     int pick = -1;
     for (int k = 0; k < (int)sv.slots.size(); ++k) {
@@ -146,8 +157,12 @@ Admit try_admit(oc_ctx *ctx, Service &sv, SvcReq &q, Done *fail)
             for (int k = 0; k < (int)sv.slots.size(); ++k)
                 if (sv.slots[k].ticket == 0 && (oldest < 0 || sv.slots[k].last_use < sv.slots[oldest].last_use))
                     oldest = k;
+            // sized for the largest request so far, so that later requests
+            // reuse it; sized for this one alone when that does not fit
             SvcSlot s;
-            st = (int)sv.slots.size() >= ctx->service_slots ? OC_EBUDGET : new_slot(ctx, rq[0], &s);
+            st = (int)sv.slots.size() >= ctx->service_slots ? OC_EBUDGET : new_slot(ctx, big, big_ne, &s);
+            if (st == OC_EBUDGET && (int)sv.slots.size() < ctx->service_slots)
+                st = new_slot(ctx, need, ne, &s);
             if (st == OC_OK) {
                 sv.slots.push_back(s);
                 pick = (int)sv.slots.size() - 1;
@@ -176,6 +191,8 @@ Admit try_admit(oc_ctx *ctx, Service &sv, SvcReq &q, Done *fail)
     s.ticket = q.ticket;
     s.iblank = q.iblank;
     s.last_use = ++sv.admissions;
+    sv.hwm = big;
+    sv.hwm_ne = big_ne;
     sv.peak_running = std::max(sv.peak_running, n_running(sv));
     return kAdmitted;
 }
