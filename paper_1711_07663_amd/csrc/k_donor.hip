@@ -585,25 +585,98 @@ __global__ __launch_bounds__(kT) void k_dp_fill(DonorArgs a)
     }
 }
 
-// a11: Newton on every pair, one thread each; a point keeps the lowest
-// element id that contains it, and a contained pair keeps its xi.
+// a11: Newton on every pair, three lanes each: lane d of a group holds
+// coordinate d of the element's 27 nodes and evaluates component d of x(xi)
+// and row d of J; the group shares them and every lane takes the same step
+// (the arithmetic of newton_q2, component by component), so the three stay
+// in lock step and agree bit for bit.  21 groups per wavefront, lane 63
+// idle.  A point keeps the lowest element id that contains it, and a
+// contained pair keeps its xi.
+constexpr int kNewtonGroups = 21;
+
 __global__ __launch_bounds__(kT) void k_dp_newton(DonorArgs a)
 {
     const int64_t n = *a.n_eff;
     const int64_t tot = a.off[n] < a.pair_cap ? (int64_t)a.off[n] : a.pair_cap;
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(&a.dcnt->n_newton, (unsigned long long)tot);
-    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += (int64_t)gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x & 63;
+    if (lane >= 3 * kNewtonGroups) return;
+    const int grp = lane / 3, d = lane - 3 * grp, base = 3 * grp;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = wave * kNewtonGroups + grp; q < tot; q += n_waves * kNewtonGroups) {
         const int i = a.pair_pt[q], e = a.pair_el[q];
-        const d3 p = mk(a.plocal[3 * (int64_t)i], a.plocal[3 * (int64_t)i + 1], a.plocal[3 * (int64_t)i + 2]);
-        double xi[3];
+        const double *Xg = a.enodes + (int64_t)e * 81 + 27 * d;
+        double C[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) C[k] = Xg[k];
+        const double px = a.plocal[3 * (int64_t)i], py = a.plocal[3 * (int64_t)i + 1],
+                     pz = a.plocal[3 * (int64_t)i + 2];
+        const double rtol = 1e-13 * a.ediam[e], rtol2 = rtol * rtol;
+        double xi[3] = {0.0, 0.0, 0.0};
+        bool conv = false;
         int iters = 0;
-        if (newton_q2<false>(a.enodes + (int64_t)e * 81, p, a.ediam[e], xi, iters)) {
-            a.pair_xi[3 * q] = xi[0];
-            a.pair_xi[3 * q + 1] = xi[1];
-            a.pair_xi[3 * q + 2] = xi[2];
-            atomicMin(&a.best[i], e);
+#pragma unroll 1
+        for (int it = 0; it < OC_NEWTON_MAXIT; ++it) {
+            ++iters;
+            double xd, jd[3];
+            if (it == 0) {
+                // xi = 0: the centre node and half the differences of the
+                // opposite face-centre nodes (as in newton_q2)
+                xd = C[13];
+                jd[0] = 0.5 * (C[14] - C[12]);
+                jd[1] = 0.5 * (C[16] - C[10]);
+                jd[2] = 0.5 * (C[22] - C[4]);
+            } else {
+                q2_map_comp(C, xi, xd, jd);
+            }
+            double x[3], J[9];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                x[k] = __shfl(xd, base + k, 64);
+                J[3 * k] = __shfl(jd[0], base + k, 64);
+                J[3 * k + 1] = __shfl(jd[1], base + k, 64);
+                J[3 * k + 2] = __shfl(jd[2], base + k, 64);
+            }
+            const double r0 = px - x[0], r1 = py - x[1], r2 = pz - x[2];
+            if (r0 * r0 + r1 * r1 + r2 * r2 <= rtol2) {
+                conv = true;
+                break;
+            }
+            const double c00 = J[4] * J[8] - J[5] * J[7];
+            const double c01 = J[5] * J[6] - J[3] * J[8];
+            const double c02 = J[3] * J[7] - J[4] * J[6];
+            const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+            if (det == 0.0) break;
+            double id = __builtin_amdgcn_rcp(det);
+            id = fma(id, fma(-det, id, 1.0), id);
+            id = fma(id, fma(-det, id, 1.0), id);
+            const double d0 = (c00 * r0 + (J[2] * J[7] - J[1] * J[8]) * r1 + (J[1] * J[5] - J[2] * J[4]) * r2) * id;
+            const double d1 = (c01 * r0 + (J[0] * J[8] - J[2] * J[6]) * r1 + (J[2] * J[3] - J[0] * J[5]) * r2) * id;
+            const double d2 = (c02 * r0 + (J[1] * J[6] - J[0] * J[7]) * r1 + (J[0] * J[4] - J[1] * J[3]) * r2) * id;
+            const double lim = 1.0 + OC_NEWTON_CLAMP;
+            const double n0 = fmin(fmax(xi[0] + d0, -lim), lim);
+            const double n1 = fmin(fmax(xi[1] + d1, -lim), lim);
+            const double n2 = fmin(fmax(xi[2] + d2, -lim), lim);
+            const double step = fmax(fabs(n0 - xi[0]), fmax(fabs(n1 - xi[1]), fabs(n2 - xi[2])));
+            xi[0] = n0;
+            xi[1] = n1;
+            xi[2] = n2;
+            if (step <= 1e-14) {
+                conv = true;
+                break;
+            }
         }
-        a.pair_it[q] = (uint8_t)iters;
+        if (d == 0) {
+            const double m = fmax(fabs(xi[0]), fmax(fabs(xi[1]), fabs(xi[2])));
+            if (conv && m <= 1.0 + OC_CONTAIN_TOL) {
+                a.pair_xi[3 * q] = xi[0];
+                a.pair_xi[3 * q + 1] = xi[1];
+                a.pair_xi[3 * q + 2] = xi[2];
+                atomicMin(&a.best[i], e);
+            }
+            a.pair_it[q] = (uint8_t)iters;
+        }
     }
 }
 
@@ -893,7 +966,7 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     LAUNCH(k_dp_count, dim3(gw), dim3(kT), a);
     OC_TRY(scan_exclusive(ctx, st, sl->dp_cnt, sl->dp_off, cap, a.n_eff, sl->dp_scan_tmp));
     LAUNCH(k_dp_fill, dim3(gw), dim3(kT), a);
-    LAUNCH(k_dp_newton, dim3(std::min<unsigned>(blocks(sl->dpair_cap, kT), 16384u)), dim3(kT), a);
+    LAUNCH(k_dp_newton, dim3(std::min<unsigned>(blocks(sl->dpair_cap, (kT / 64) * kNewtonGroups), 32768u)), dim3(kT), a);
     LAUNCH(k_dp_final, dim3(gp), dim3(kT), a);
     OC_HIP(hipGetLastError());
     sl->last_donor_args.assign(reinterpret_cast<const unsigned char *>(&a),
