@@ -201,7 +201,10 @@ __global__ __launch_bounds__(kThreads) void k_bins_setup(const CutInst *__restri
                                                          const int32_t *__restrict__ part, int *total,
                                                          CutCounters *cnt)
 {
-    if (threadIdx.x == 0) cnt->n_inbox = 0;   // k_filter appends after this kernel
+    if (threadIdx.x == 0) {
+        cnt->n_inbox = 0;     // k_filter appends after this kernel
+        cnt->n_sidelist = 0;  // k_hit appends after it
+    }
     // surface box and bin grid of every cut: one wavefront per cut folds the
     // cut's per-block partial boxes
     const int lane = lane_id(), wid = threadIdx.x >> 6;
@@ -626,12 +629,12 @@ struct ExactArgs {
     const int32_t *bin_start;
     const int32_t *bitems;
     const uint64_t *list_inbox;
-    uint8_t *stat;              // k_hit takes ST_NEAR items, k_side ST_SIDE items
-    const CutCounters *cnt;
-    unsigned long long *side;   // per in-box item: [2 i] upper bound U, [2 i + 1] nearest distance (bits)
+    uint8_t *stat;              // k_hit takes ST_NEAR items and marks them ST_HIT or ST_SIDE
+    CutCounters *cnt;
+    int32_t *sidelist;          // the ST_SIDE items, appended by k_hit (count cnt->n_sidelist)
 };
 
-constexpr int kSideParts = 4;   // wavefronts sharing one side item's walks
+constexpr int kSideWaves = 8;   // wavefronts sharing one side item's walks
 
 // a6: a far element (no candidate face) lies on one side of the surface:
 // +x ray parity of its first node over the column of bins that holds the
@@ -845,7 +848,7 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         if (lane == 0) {
             a.stat[item] = hit ? ST_HIT : ST_SIDE;
             if (hit && c.kind == OC_SURF_WALL) c.iblank[e] = OC_HOLE;
-            if (!hit) a.side[2 * (int64_t)item] = a.side[2 * (int64_t)item + 1] = 0x7FF0000000000000ull;
+            if (!hit) a.sidelist[atomicAdd(&a.cnt->n_sidelist, 1)] = item;
         }
     }
 }
@@ -855,12 +858,14 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
 // minimum of the point-to-triangle distance over the binned faces, then the
 // tie rule (largest |dot| of the unit point-to-surface vector with the
 // outward triangle normal; normals averaged only for equally visible
-// triangles of opposite sign).  Three kernels: an upper bound U and the
-// nearest distance are each computed by kSideParts wavefronts per element
-// (every wavefront takes every kSideParts-th chunk of faces and they meet
-// in a 64-bit atomic minimum per element: distances are non-negative, so
-// their bit patterns order like the values), then one wavefront per element
-// collects the tie set and decides the side.
+// triangles of opposite sign).  One workgroup of kSideWaves wavefronts per
+// element of the list k_hit leaves, three stages that meet in LDS: an upper
+// bound U (the nearest node of the element's candidate faces), the nearest
+// distance over the faces within U, and the two first records of the tie
+// set in tie order.  In every stage each wavefront takes every
+// kSideWaves-th chunk of the stage's bin walk.  The stages compute a
+// minimum over an exact set and the first two records of a total order, so
+// the split among wavefronts does not change any bit.
 __device__ inline void side_item(const ExactArgs &a, int item, int &e, const CutInst *&cp, d3 &p)
 {
     const uint64_t it = a.list_inbox[item];
@@ -870,104 +875,45 @@ __device__ inline void side_item(const ExactArgs &a, int item, int &e, const Cut
     p = mk(X[0], X[27], X[54]);
 }
 
-__global__ __launch_bounds__(64) void k_side_bound(ExactArgs a)
+__device__ inline TieRec tie_shfl_xor(const TieRec &r, int d)
 {
-    __shared__ WalkLds L;
-    const int n_in = a.cnt->n_inbox;
-    for (int w = blockIdx.x; w < n_in * kSideParts; w += gridDim.x) {
-        const int item = w / kSideParts, part = w - kSideParts * item;
-        if (a.stat[item] != ST_SIDE) continue;
-        int e;
-        const CutInst *cp;
-        d3 p;
-        side_item(a, item, e, cp, p);
-        const CutInst &c = *cp;
-        const BinGrid G = c.params->grid;
-        const int32_t *bstart = a.bin_start + c.params->bin_off;
-        const float *__restrict__ fboxc = c.fbox;
-        const double *__restrict__ pnodes = c.pnodes;
-        float eb[6];
-        for (int k = 0; k < 6; ++k) eb[k] = c.ebox[(int64_t)k * c.stride + e];
-        // upper bound: nearest node of the element's candidate faces (every
-        // face node lies on the surface, so its distance bounds the nearest
-        // distance from above; it only sizes the exact search)
-        double u = INFINITY;
-        int lo[3], hi[3];
-        box_bins(G, eb, lo, hi);
-        const BinRange R = make_range(lo, hi);
-        walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
-            if (f >= 0) {
-                const float *fb = fboxc + (int64_t)f * 6;
-                if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb) && point_box_dist(p, fb) < u) {
-                    const double *P = pnodes + (int64_t)f * 27;
-                    double d2 = INFINITY;
-                    for (int k = 0; k < 9; ++k) {
-                        const double dx = P[k] - p.x, dy = P[9 + k] - p.y, dz = P[18 + k] - p.z;
-                        d2 = fmin(d2, dx * dx + dy * dy + dz * dz);
-                    }
-                    u = fmin(u, sqrt(d2));
-                }
-            }
-            u = wave_min_d(u);
-            return false;
-        }, part, kSideParts);
-        u = wave_min_d(u);
-        if (threadIdx.x == 0 && u < INFINITY)
-            atomicMin(&a.side[2 * (int64_t)item], (unsigned long long)__double_as_longlong(u));
+    TieRec o;
+    o.absdot = __shfl_xor(r.absdot, d, 64);
+    o.dot = __shfl_xor(r.dot, d, 64);
+    o.vx = __shfl_xor(r.vx, d, 64);
+    o.vy = __shfl_xor(r.vy, d, 64);
+    o.vz = __shfl_xor(r.vz, d, 64);
+    o.nx = __shfl_xor(r.nx, d, 64);
+    o.ny = __shfl_xor(r.ny, d, 64);
+    o.nz = __shfl_xor(r.nz, d, 64);
+    o.f = __shfl_xor(r.f, d, 64);
+    o.s = __shfl_xor(r.s, d, 64);
+    o.valid = __shfl_xor(r.valid, d, 64);
+    o.pad = 0;
+    return o;
+}
+
+// the two first records of the wavefront in tie order, on every lane (the
+// butterfly merges disjoint halves, so no record is offered twice)
+__device__ inline void tie_wave_first2(TieRec &b1, TieRec &b2)
+{
+#pragma unroll 1
+    for (int d = 32; d >= 1; d >>= 1) {
+        const TieRec o1 = tie_shfl_xor(b1, d), o2 = tie_shfl_xor(b2, d);
+        tie_offer(b1, b2, o1);
+        tie_offer(b1, b2, o2);
     }
 }
 
-__global__ __launch_bounds__(64) void k_side_near(ExactArgs a)
+__global__ __launch_bounds__(64 * kSideWaves) void k_side(ExactArgs a)
 {
-    __shared__ WalkLds L;
-    const int n_in = a.cnt->n_inbox;
-    for (int w = blockIdx.x; w < n_in * kSideParts; w += gridDim.x) {
-        const int item = w / kSideParts, part = w - kSideParts * item;
-        if (a.stat[item] != ST_SIDE) continue;
-        int e;
-        const CutInst *cp;
-        d3 p;
-        side_item(a, item, e, cp, p);
-        const CutInst &c = *cp;
-        const BinGrid G = c.params->grid;
-        const int32_t *bstart = a.bin_start + c.params->bin_off;
-        const float *__restrict__ fboxc = c.fbox;
-        const double *__restrict__ pnodes = c.pnodes;
-        const double U = __longlong_as_double((long long)a.side[2 * (int64_t)item]);
-        // every face whose box is within U of the node
-        double best = U;
-        int lo[3], hi[3];
-        query_bins(G, p, U, lo, hi);
-        const BinRange R = make_range(lo, hi);
-        walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
-            if (f >= 0) {
-                const float *fb = fboxc + (int64_t)f * 6;
-                if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
-                    best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
-            }
-            best = wave_min_d(best);
-            return false;
-        }, part, kSideParts);
-        best = wave_min_d(best);
-        if (threadIdx.x == 0)
-            atomicMin(&a.side[2 * (int64_t)item + 1], (unsigned long long)__double_as_longlong(best));
-    }
-}
-
-// Tie stage: one workgroup of kSideParts wavefronts per element, each taking
-// every kSideParts-th chunk of the faces within the tie radius; their valid
-// records are gathered in LDS and merged by one thread (the tie order is a
-// total order on (|dot|, face, triangle), so the merge order does not
-// matter).
-__global__ __launch_bounds__(64 * kSideParts) void k_side(ExactArgs a)
-{
-    __shared__ TieRec rec[kSideParts * 128];
-    __shared__ int nrec[kSideParts];
-    __shared__ WalkLds L[kSideParts];
+    __shared__ WalkLds L[kSideWaves];
+    __shared__ double red[kSideWaves];
+    __shared__ TieRec rec[2 * kSideWaves];
     const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
-    const int n_in = a.cnt->n_inbox;
-    for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
-        if (a.stat[item] != ST_SIDE) continue;
+    const int n_side = a.cnt->n_sidelist;
+    for (int si = blockIdx.x; si < n_side; si += gridDim.x) {
+        const int item = a.sidelist[si];
         int e;
         const CutInst *cp;
         d3 p;
@@ -977,9 +923,61 @@ __global__ __launch_bounds__(64 * kSideParts) void k_side(ExactArgs a)
         const int32_t *bstart = a.bin_start + c.params->bin_off;
         const float *__restrict__ fboxc = c.fbox;
         const double *__restrict__ pnodes = c.pnodes;
-        const double best = __longlong_as_double((long long)a.side[2 * (int64_t)item + 1]);
-        // tie set within best * (1 + 1e-9)
-        const double thr = best * (1.0 + 1e-9);
+        // stage 1: upper bound, the nearest node of the element's candidate
+        // faces (every face node lies on the surface; U only sizes stage 2)
+        double u = INFINITY;
+        {
+            float eb[6];
+            for (int k = 0; k < 6; ++k) eb[k] = c.ebox[(int64_t)k * c.stride + e];
+            int lo[3], hi[3];
+            box_bins(G, eb, lo, hi);
+            const BinRange R = make_range(lo, hi);
+            walk_faces(G, R, bstart, a.bitems, L[part], [&](int f, const int *xyz) {
+                if (f >= 0) {
+                    const float *fb = fboxc + (int64_t)f * 6;
+                    if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb) && point_box_dist(p, fb) < u) {
+                        const double *P = pnodes + (int64_t)f * 27;
+                        double d2 = INFINITY;
+                        for (int k = 0; k < 9; ++k) {
+                            const double dx = P[k] - p.x, dy = P[9 + k] - p.y, dz = P[18 + k] - p.z;
+                            d2 = fmin(d2, dx * dx + dy * dy + dz * dz);
+                        }
+                        u = fmin(u, sqrt(d2));
+                    }
+                }
+                u = wave_min_d(u);
+                return false;
+            }, part, kSideWaves);
+        }
+        u = wave_min_d(u);
+        if (lane == 0) red[part] = u;
+        __syncthreads();
+        double U = red[0];
+        for (int k = 1; k < kSideWaves; ++k) U = fmin(U, red[k]);
+        __syncthreads();
+        // stage 2: nearest distance over every face whose box is within U
+        double best = U;
+        {
+            int lo[3], hi[3];
+            query_bins(G, p, U, lo, hi);
+            const BinRange R = make_range(lo, hi);
+            walk_faces(G, R, bstart, a.bitems, L[part], [&](int f, const int *xyz) {
+                if (f >= 0) {
+                    const float *fb = fboxc + (int64_t)f * 6;
+                    if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
+                        best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
+                }
+                best = wave_min_d(best);
+                return false;
+            }, part, kSideWaves);
+        }
+        best = wave_min_d(best);
+        if (lane == 0) red[part] = best;
+        __syncthreads();
+        double B = red[0];
+        for (int k = 1; k < kSideWaves; ++k) B = fmin(B, red[k]);
+        // stage 3: tie set within B * (1 + 1e-9)
+        const double thr = B * (1.0 + 1e-9);
         TieRec b1, b2;
         b1.valid = b2.valid = 0;
         {
@@ -1017,22 +1015,18 @@ __global__ __launch_bounds__(64 * kSideParts) void k_side(ExactArgs a)
                     }
                 }
                 return false;
-            }, part, kSideParts);
+            }, part, kSideWaves);
         }
-        // gather the valid records of each wavefront (b2 valid implies b1 valid)
-        const unsigned long long m1 = __ballot(b1.valid), m2 = __ballot(b2.valid);
-        const unsigned long long below = (1ull << lane) - 1ull;
-        const int n1 = __popcll(m1);
-        TieRec *R0 = rec + 128 * part;
-        if (b1.valid) R0[__popcll(m1 & below)] = b1;
-        if (b2.valid) R0[n1 + __popcll(m2 & below)] = b2;
-        if (lane == 0) nrec[part] = n1 + __popcll(m2);
+        tie_wave_first2(b1, b2);
+        if (lane == 0) {
+            rec[2 * part] = b1;
+            rec[2 * part + 1] = b2;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             TieRec c1, c2;
             c1.valid = c2.valid = 0;
-            for (int w = 0; w < kSideParts; ++w)
-                for (int k = 0; k < nrec[w]; ++k) tie_offer(c1, c2, rec[128 * w + k]);
+            for (int k = 0; k < 2 * kSideWaves; ++k) tie_offer(c1, c2, rec[k]);
             double sg = c1.dot;
             if (c2.valid && c1.absdot - c2.absdot <= 1e-9 && ((c1.dot > 0.0) != (c2.dot > 0.0)))
                 sg = c1.vx * (c1.nx + c2.nx) + c1.vy * (c1.ny + c2.ny) + c1.vz * (c1.nz + c2.nz);
@@ -1327,11 +1321,9 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         ea.list_inbox = sl->l_inbox;
         ea.stat = sl->l_stat;
         ea.cnt = sl->counters;
-        ea.side = sl->l_side;
+        ea.sidelist = sl->l_sidelist;
         LAUNCH(k_hit, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
-        LAUNCH(k_side_bound, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
-        LAUNCH(k_side_near, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
-        LAUNCH(k_side, dim3((unsigned)std::max(1, ctx->exact_waves / kSideParts)), dim3(64 * kSideParts), ea);
+        LAUNCH(k_side, dim3((unsigned)std::max(1, ctx->exact_waves / kSideWaves)), dim3(64 * kSideWaves), ea);
         LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_inbox, sl->counters);
     }
     if (ov_blk) LAUNCH(k_overset_fringe, dim3((unsigned)ov_blk), dim3(kThreads), sl->outs, n_out);

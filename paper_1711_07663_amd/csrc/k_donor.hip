@@ -961,12 +961,16 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     a.donor = donor;
     a.ref = ref;
     a.dcnt = sl->dcounters;
-    const unsigned gp = std::min<unsigned>(blocks(cap, kT), 8192u);
-    const unsigned gw = std::min<unsigned>(blocks(cap * g.dlanes, kT), 16384u);
+    // every kernel loops over its work, so a cap on the blocks only lowers
+    // the search's share of the device (room for concurrent work)
+    const unsigned bcap = ctx->donor_waves > 0 ? (unsigned)std::max(1, ctx->donor_waves / (kT / 64)) : 1u << 30;
+    const unsigned gp = std::min({blocks(cap, kT), 8192u, bcap});
+    const unsigned gw = std::min({blocks(cap * g.dlanes, kT), 16384u, bcap});
+    const unsigned gn = std::min({blocks(sl->dpair_cap, (kT / 64) * kNewtonGroups), 32768u, bcap});
     LAUNCH(k_dp_count, dim3(gw), dim3(kT), a);
     OC_TRY(scan_exclusive(ctx, st, sl->dp_cnt, sl->dp_off, cap, a.n_eff, sl->dp_scan_tmp));
     LAUNCH(k_dp_fill, dim3(gw), dim3(kT), a);
-    LAUNCH(k_dp_newton, dim3(std::min<unsigned>(blocks(sl->dpair_cap, (kT / 64) * kNewtonGroups), 32768u)), dim3(kT), a);
+    LAUNCH(k_dp_newton, dim3(gn), dim3(kT), a);
     LAUNCH(k_dp_final, dim3(gp), dim3(kT), a);
     OC_HIP(hipGetLastError());
     sl->last_donor_args.assign(reinterpret_cast<const unsigned char *>(&a),

@@ -94,7 +94,7 @@ static oc_status slot_alloc_cut(oc_slot *sl, CutCaps c)
     OC_TRY(dev_alloc(ctx, o, sizeof(uint64_t) * (size_t)c.elem_inst, (void **)&sl->l_inbox));
     OC_TRY(dev_alloc(ctx, o, sizeof(uint8_t) * (size_t)c.elem_inst, (void **)&sl->l_stat));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)c.elem_inst, (void **)&sl->l_ncand));
-    OC_TRY(dev_alloc(ctx, o, sizeof(unsigned long long) * 2 * (size_t)c.elem_inst, (void **)&sl->l_side));
+    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)c.elem_inst, (void **)&sl->l_sidelist));
     // partial boxes of the pose launch: blocks of 16 faces, plus one spare
     // block per cut
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * 6 * (size_t)(c.faces / 16 + 2 * c.cuts + 1),
@@ -1372,6 +1372,13 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
         }
         ctx->service_slots = value == 0 ? 4 : (int)value;
         v = ctx->service_slots;
+    } else if (knob == OC_TUNE_DONOR_WAVES) {
+        if (value < 0 || value > (1 << 22)) {
+            set_error("oc_tune: donor waves out of range");
+            return OC_EINVAL;
+        }
+        ctx->donor_waves = (int)value;
+        v = ctx->donor_waves;
     } else if (knob == OC_TUNE_HBM_BUDGET) {
         if (value < 0) {
             set_error("oc_tune: negative budget");

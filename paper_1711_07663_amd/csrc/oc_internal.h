@@ -54,6 +54,7 @@ struct SurfParams {
 struct CutCounters {
     int n_inbox, n_near, n_far, n_hit, n_hole, n_side;
     unsigned long long n_cand_pairs;
+    int n_sidelist, pad;   // entries of the side list (stream order, not statistics)
 };
 
 // Per-donor-search counters (device).
@@ -195,7 +196,7 @@ struct oc_slot {
     uint64_t *l_inbox = nullptr;       // in-box items (cut << 32 | element)
     uint8_t *l_stat = nullptr;         // status per in-box item
     int32_t *l_ncand = nullptr;        // candidate faces per in-box item
-    unsigned long long *l_side = nullptr; // per in-box item: side search bound and distance (bits)
+    int32_t *l_sidelist = nullptr;     // in-box items left to the side search
     int32_t *sbox_part = nullptr;      // per face block: partial surface box (ordered ints)
     int last_n_cut = 0, last_n_out = 0, last_cblk = 0;
     std::vector<oc::CutOut> last_outs;
@@ -224,6 +225,7 @@ struct oc_ctx {
     int device = 0;
     int surf_bins = 0;
     int exact_waves = 8192;                // persistent wavefronts of the exact-stage kernels
+    int donor_waves = 0;                   // cap on the donor-search wavefronts (0 = none)
     double donor_bin_scale = 1.0;
     int64_t budget = 0;
     int64_t used = 0;
