@@ -76,7 +76,7 @@ enum { OC_FACE_INTERIOR = 0, OC_FACE_WALL = 1, OC_FACE_OVERSET = 2, OC_FACE_FARF
 typedef struct oc_config {
     int32_t device;         /* HIP device ordinal */
     int32_t surf_bins;      /* cut-surface bins per axis; 0 = automatic */
-    double donor_bin_scale; /* donor bin edge / mean element extent; 0 = 1 */
+    double donor_bin_scale; /* donor bin edge / mean element extent; 0 = 0.5 */
     int64_t hbm_budget;     /* device bytes the context may hold; 0 = no limit */
 } oc_config;
 
@@ -415,13 +415,24 @@ oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len);
  *   OC_TUNE_SERVICE_SLOTS arg unused; value = most slots the cut service
  *                        keeps, hence most requests running at once
  *                        (1 .. 64, 0 = 4).
+ *   OC_TUNE_DONOR_WAVES  arg unused; value = most wavefronts launched for
+ *                        each donor-search kernel (0 = as many as the
+ *                        points and pairs ask for).  A lower cap leaves
+ *                        room on the device for work running beside the
+ *                        search on another stream.
  *   OC_TUNE_HBM_BUDGET   arg unused; value = the context's HBM budget in
  *                        bytes (0 = none), as oc_config.hbm_budget; later
  *                        allocations are held to it, memory already held is
  *                        kept (registration needs transient room beyond
  *                        what it keeps, so a budget can be set after it).
  * *applied (may be NULL) receives the value in force afterwards. */
-enum { OC_TUNE_SURF_BINS = 1, OC_TUNE_EXACT_WAVES = 2, OC_TUNE_SERVICE_SLOTS = 3, OC_TUNE_HBM_BUDGET = 4 };
+enum {
+    OC_TUNE_SURF_BINS = 1,
+    OC_TUNE_EXACT_WAVES = 2,
+    OC_TUNE_SERVICE_SLOTS = 3,
+    OC_TUNE_HBM_BUDGET = 4,
+    OC_TUNE_DONOR_WAVES = 5
+};
 oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t *applied);
 
 /* Device bytes currently held by the context. */

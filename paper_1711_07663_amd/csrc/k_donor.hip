@@ -966,7 +966,9 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     const unsigned bcap = ctx->donor_waves > 0 ? (unsigned)std::max(1, ctx->donor_waves / (kT / 64)) : 1u << 30;
     const unsigned gp = std::min({blocks(cap, kT), 8192u, bcap});
     const unsigned gw = std::min({blocks(cap * g.dlanes, kT), 16384u, bcap});
-    const unsigned gn = std::min({blocks(sl->dpair_cap, (kT / 64) * kNewtonGroups), 32768u, bcap});
+    // Newton loops over the pairs: 4096 blocks (four waves per SIMD, four
+    // rounds) cover any pair count without launching a wave per possible pair
+    const unsigned gn = std::min({blocks(sl->dpair_cap, (kT / 64) * kNewtonGroups), 4096u, bcap});
     LAUNCH(k_dp_count, dim3(gw), dim3(kT), a);
     OC_TRY(scan_exclusive(ctx, st, sl->dp_cnt, sl->dp_off, cap, a.n_eff, sl->dp_scan_tmp));
     LAUNCH(k_dp_fill, dim3(gw), dim3(kT), a);

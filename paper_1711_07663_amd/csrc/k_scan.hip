@@ -172,9 +172,63 @@ constexpr int kScanDirectMaxTiles = 1024;
 
 int64_t scan_tmp_ints(int64_t cap) { return (cap + kScanTile - 1) / kScanTile + 1; }
 
+// One block for short arrays: chunks of kSingleChunk items in order, each
+// scanned by the block and offset by the running total (one launch instead
+// of a reduce and an apply).
+constexpr int kSingleThreads = 1024;
+constexpr int kSingleItems = 4;
+constexpr int kSingleChunk = kSingleThreads * kSingleItems;
+constexpr int64_t kSingleMax = 4 * kSingleChunk;   // at most four chunks
+
+__global__ __launch_bounds__(kSingleThreads) void k_scan_single(const int32_t *__restrict__ in,
+                                                                int32_t *__restrict__ out, const int *n_dev,
+                                                                int64_t n_host)
+{
+    __shared__ int wsum[kSingleThreads / 64];
+    // the device count never exceeds the capacity the arrays were sized for
+    const int64_t n = n_dev ? ((int64_t)*n_dev < n_host ? (int64_t)*n_dev : n_host) : n_host;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int run = 0;   // total of the chunks before (the same on every thread)
+    for (int64_t base = 0; base < n; base += kSingleChunk) {
+        int v[kSingleItems];
+        int s = 0;
+        const int64_t my = base + (int64_t)threadIdx.x * kSingleItems;
+#pragma unroll
+        for (int k = 0; k < kSingleItems; ++k) {
+            v[k] = my + k < n ? in[my + k] : 0;
+            s += v[k];
+        }
+        const int inc = wave_incl_scan(s);
+        if (lane == 63) wsum[wid] = inc;
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < kSingleThreads / 64; ++w) {
+            if (w < wid) off += wsum[w];
+            tot += wsum[w];
+        }
+        __syncthreads();
+        int r = run + off + inc - s;
+#pragma unroll
+        for (int k = 0; k < kSingleItems; ++k) {
+            if (my + k < n) out[my + k] = r;
+            r += v[k];
+        }
+        run += tot;
+    }
+    if (threadIdx.x == 0) out[n] = run;
+}
+
 oc_status scan_exclusive(oc_ctx *ctx, hipStream_t st, const int32_t *in, int32_t *out, int64_t cap,
                          const int *n_dev, int32_t *tmp)
 {
+    if (cap <= kSingleMax) {
+        size_t slot;
+        time_begin(ctx, st, "scan", &slot);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(kSingleThreads), 0, st, in, out, n_dev, cap);
+        time_end(ctx, st, slot);
+        OC_HIP(hipGetLastError());
+        return OC_OK;
+    }
     int64_t nt = (cap + kScanTile - 1) / kScanTile;
     if (nt < 1) nt = 1;
     if (nt > kScanMaxTiles) {

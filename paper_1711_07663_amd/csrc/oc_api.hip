@@ -295,7 +295,7 @@ oc_status oc_create(oc_ctx **out, const oc_config *cfg)
     if (cfg) {
         ctx->device = cfg->device;
         ctx->surf_bins = cfg->surf_bins;
-        ctx->donor_bin_scale = cfg->donor_bin_scale > 0 ? cfg->donor_bin_scale : 1.0;
+        ctx->donor_bin_scale = cfg->donor_bin_scale > 0 ? cfg->donor_bin_scale : 0.5;
         ctx->budget = cfg->hbm_budget;
     }
     if (ctx->device < 0 || ctx->device >= ndev || hipSetDevice(ctx->device) != hipSuccess) {

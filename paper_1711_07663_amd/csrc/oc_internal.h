@@ -226,7 +226,7 @@ struct oc_ctx {
     int surf_bins = 0;
     int exact_waves = 8192;                // persistent wavefronts of the exact-stage kernels
     int donor_waves = 0;                   // cap on the donor-search wavefronts (0 = none)
-    double donor_bin_scale = 1.0;
+    double donor_bin_scale = 0.5;
     int64_t budget = 0;
     int64_t used = 0;
     std::vector<std::unique_ptr<oc::Grid>> grids;
