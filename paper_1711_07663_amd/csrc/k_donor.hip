@@ -23,6 +23,10 @@
 namespace oc {
 
 constexpr int kT = 256;
+// blocks of the kernels that loop over a device-side count: 16 waves per
+// SIMD, twice what the device holds at once (dynamic balance) without a
+// wave per possible item of the capacity
+constexpr unsigned kLoopBlocks = 4096;
 
 // Newton inversion: xi0 = 0; stop when |x_p - x(xi)| <= 1e-13 diam (checked
 // before each step) or the clamped step is <= 1e-14; at most
@@ -478,10 +482,21 @@ __device__ inline int64_t donor_points(const DonorArgs &a)
     return a.n_dev ? ((int64_t)*a.n_dev < a.cap ? (int64_t)*a.n_dev : a.cap) : a.cap;
 }
 
-// The bin walks give each point a group of `lanes` lanes of a wavefront
-// (64 / lanes points per wavefront): the group's lanes take the bin's
-// entries in turn, so a point whose bin holds many boxes is searched in
-// parallel while points with small bins share a wavefront.
+// The bin walks give each point a group of L lanes of a wavefront (64 / L
+// points per wavefront): the group's lanes take the bin's entries in turn,
+// so a point whose bin holds many boxes is searched in parallel while points
+// with small bins share a wavefront.  L starts at the grid's `lanes` and
+// doubles while the launch has threads for it (a search far below its
+// capacity then walks each bin in fewer dependent rounds); the candidates
+// and their order do not depend on L.
+__device__ inline int walk_lanes(const DonorArgs &a, int64_t n)
+{
+    const int64_t threads = (int64_t)gridDim.x * blockDim.x;
+    int L = a.lanes;
+    while (L < 64 && (int64_t)(2 * L) * n <= threads) L *= 2;
+    return L;
+}
+
 //
 // a10: per point, the registration-frame position (inverse pose, the rigid
 // motion of Sec. 4.3), its bin, the number of elements of the bin whose
@@ -495,7 +510,7 @@ __global__ __launch_bounds__(kT) void k_dp_count(DonorArgs a)
         a.dcnt->n_newton = a.dcnt->n_iter = a.dcnt->n_orphan = 0ull;
     }
     const Pose pose = *a.pose;
-    const int L = a.lanes, lane = threadIdx.x & 63, sub = lane & (L - 1);
+    const int L = walk_lanes(a, n), lane = threadIdx.x & 63, sub = lane & (L - 1);
     const unsigned long long gmask = (L == 64 ? ~0ull : ((1ull << L) - 1ull)) << (lane & ~(L - 1));
     const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t ppw = 64 / L;
@@ -543,7 +558,7 @@ __global__ __launch_bounds__(kT) void k_dp_count(DonorArgs a)
 __global__ __launch_bounds__(kT) void k_dp_fill(DonorArgs a)
 {
     const int64_t n = donor_points(a);
-    const int L = a.lanes, lane = threadIdx.x & 63, sub = lane & (L - 1);
+    const int L = walk_lanes(a, n), lane = threadIdx.x & 63, sub = lane & (L - 1);
     const unsigned long long gmask = (L == 64 ? ~0ull : ((1ull << L) - 1ull)) << (lane & ~(L - 1));
     const unsigned long long below = (1ull << lane) - 1ull;
     const int64_t ppw = 64 / L;
@@ -895,7 +910,7 @@ oc_status element_points_run(oc_slot *sl, const Grid &g, const Pose *pose_dev, c
     oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
     const int64_t cap_pts = std::min<int64_t>(cap, 27 * g.n_elem);
-    LAUNCH(k_fringe_points, dim3(std::min<unsigned>(blocks(std::max<int64_t>(cap_pts, 1), kT), 8192u)), dim3(kT),
+    LAUNCH(k_fringe_points, dim3(std::min<unsigned>(blocks(std::max<int64_t>(cap_pts, 1), kT), kLoopBlocks)), dim3(kT),
            g.enodes, g.n_elem, list, count, cap, pose_dev, pts, src, n_out);
     OC_HIP(hipGetLastError());
     return OC_OK;
@@ -961,14 +976,14 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     a.donor = donor;
     a.ref = ref;
     a.dcnt = sl->dcounters;
-    // every kernel loops over its work, so a cap on the blocks only lowers
-    // the search's share of the device (room for concurrent work)
+    // every kernel loops over its work: grids are sized for the capacities
+    // (the counts are on the device) but capped at kLoopBlocks, so a search
+    // far below its capacity does not launch a wave per possible point or
+    // pair; the tuning cap only lowers the search's share of the device
     const unsigned bcap = ctx->donor_waves > 0 ? (unsigned)std::max(1, ctx->donor_waves / (kT / 64)) : 1u << 30;
-    const unsigned gp = std::min({blocks(cap, kT), 8192u, bcap});
-    const unsigned gw = std::min({blocks(cap * g.dlanes, kT), 16384u, bcap});
-    // Newton loops over the pairs: 4096 blocks (four waves per SIMD, four
-    // rounds) cover any pair count without launching a wave per possible pair
-    const unsigned gn = std::min({blocks(sl->dpair_cap, (kT / 64) * kNewtonGroups), 4096u, bcap});
+    const unsigned gp = std::min({blocks(cap, kT), kLoopBlocks, bcap});
+    const unsigned gw = std::min({blocks(cap * g.dlanes, kT), kLoopBlocks, bcap});
+    const unsigned gn = std::min({blocks(sl->dpair_cap, (kT / 64) * kNewtonGroups), kLoopBlocks, bcap});
     LAUNCH(k_dp_count, dim3(gw), dim3(kT), a);
     OC_TRY(scan_exclusive(ctx, st, sl->dp_cnt, sl->dp_off, cap, a.n_eff, sl->dp_scan_tmp));
     LAUNCH(k_dp_fill, dim3(gw), dim3(kT), a);
