@@ -14,12 +14,10 @@
 //                                   meeting the surface box go to a list
 //   k_candidates                    element box x binned face boxes: elements
 //                                   with a candidate face are "near", others
-//                                   "far"
+//                                   "far" and decided at once by the +x ray
+//                                   parity of the first node
 //   k_hit                           one wavefront per near element: FP64
-//                                   triangle-pair intersection; in the same
-//                                   launch, one wavefront per far element: +x
-//                                   ray parity of the first node against the
-//                                   surface triangles
+//                                   triangle-pair intersection
 //   k_side                          near elements not hit: nearest-face side of
 //                                   the first node (wavefront minimum + tie rule)
 //   k_fringe / k_overset_fringe     one fringe layer around holes, overset faces
@@ -474,13 +472,57 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
     }
 }
 
+// a6: a far element (no candidate face) lies on one side of the surface:
+// +x ray parity of its first node over the column of bins that holds the
+// ray (one wavefront).
+__device__ inline void ray_item(const CutInst &c, const int32_t *__restrict__ bin_start,
+                                const int32_t *__restrict__ bitems, int e, WalkLds &L)
+{
+    const int lane = threadIdx.x & 63;
+    const SurfParams *sp = c.params;
+    const double *X = c.enodes + (int64_t)e * 81;
+    const d3 p = mk(X[0], X[27], X[54]);
+    if (p.y < sp->sbox[1] || p.y > sp->sbox[4] || p.z < sp->sbox[2] || p.z > sp->sbox[5] || p.x > sp->sbox[3])
+        return;
+    const BinGrid G = sp->grid;
+    const int32_t *bstart = bin_start + sp->bin_off;
+    const float *__restrict__ fbox = c.fbox;
+    const double *__restrict__ pnodes = c.pnodes;
+    int lo[3], hi[3];
+    lo[0] = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
+    lo[1] = hi[1] = bin_of((float)p.y, G.o[1], G.inv[1], G.n[1]);
+    lo[2] = hi[2] = bin_of((float)p.z, G.o[2], G.inv[2], G.n[2]);
+    hi[0] = G.n[0] - 1;
+    const BinRange R = make_range(lo, hi);
+    int par = 0;
+    walk_faces(G, R, bstart, bitems, L, [&](int f, const int *xyz) {
+        if (f >= 0) {
+            const float *fb = fbox + (int64_t)f * 6;
+            if (first_common_bin(G, fb, xyz, lo) && (double)fb[1] <= p.y && (double)fb[4] >= p.y &&
+                (double)fb[2] <= p.z && (double)fb[5] >= p.z && (double)fb[3] >= p.x) {
+                const double *P = pnodes + (int64_t)f * 27;
+                for (int s = 0; s < 8; ++s) {
+                    d3 F[3];
+                    face_tri(P, s, F);
+                    par ^= ray_x_crosses(p, F[0], F[1], F[2]);
+                }
+            }
+        }
+        return false;
+    });
+    const int odd = __popcll(__ballot(par)) & 1;
+    if (lane == 0 && odd) c.iblank[e] = OC_HOLE;
+}
+
 // a3, bin part: one wavefront per in-box element counts its candidate faces
 // (element box overlapping an inflated face box) and marks the item near
-// (some candidate) or far (none).  Warm start (prev != null): the walk also
-// counts faces whose box meets the element box grown by the sweep bound; an
-// element meeting none keeps its previous side (the surface never came near
-// it between the two poses) and needs no further test.  Later stages select
-// their items by status, so no list is appended under a shared counter.
+// (some candidate) or far (none); a far element is then decided here by its
+// ray parity (ray_item: far elements need no exact test, and this kernel
+// holds more wavefronts per SIMD than the exact stage).  Warm start
+// (prev != null): the walk also counts faces whose box meets the element
+// box grown by the sweep bound; an element meeting none keeps its previous
+// side (the surface never came near it between the two poses) and needs no
+// further test.  k_hit takes the near items by status.
 __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I, const int32_t *__restrict__ bin_start,
                                                    const int32_t *__restrict__ bitems,
                                                    const uint64_t *__restrict__ list_inbox, uint8_t *__restrict__ stat,
@@ -530,6 +572,10 @@ __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I
             }
             stat[item] = st;
             ncand[item] = (int32_t)(tot < 0x7fffffff ? tot : 0x7fffffff);
+        }
+        if (tot == 0 && totw > 0) {
+            __syncthreads();   // the ray walk reuses L
+            ray_item(c, bin_start, bitems, e, L);
         }
     }
 }
@@ -636,53 +682,11 @@ struct ExactArgs {
 
 constexpr int kSideWaves = 8;   // wavefronts sharing one side item's walks
 
-// a6: a far element (no candidate face) lies on one side of the surface:
-// +x ray parity of its first node over the column of bins that holds the
-// ray (one wavefront).
-__device__ inline void ray_item(const CutInst &c, const int32_t *__restrict__ bin_start,
-                                const int32_t *__restrict__ bitems, int e, WalkLds &L)
-{
-    const int lane = threadIdx.x & 63;
-    const SurfParams *sp = c.params;
-    const double *X = c.enodes + (int64_t)e * 81;
-    const d3 p = mk(X[0], X[27], X[54]);
-    if (p.y < sp->sbox[1] || p.y > sp->sbox[4] || p.z < sp->sbox[2] || p.z > sp->sbox[5] || p.x > sp->sbox[3])
-        return;
-    const BinGrid G = sp->grid;
-    const int32_t *bstart = bin_start + sp->bin_off;
-    const float *__restrict__ fbox = c.fbox;
-    const double *__restrict__ pnodes = c.pnodes;
-    int lo[3], hi[3];
-    lo[0] = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
-    lo[1] = hi[1] = bin_of((float)p.y, G.o[1], G.inv[1], G.n[1]);
-    lo[2] = hi[2] = bin_of((float)p.z, G.o[2], G.inv[2], G.n[2]);
-    hi[0] = G.n[0] - 1;
-    const BinRange R = make_range(lo, hi);
-    int par = 0;
-    walk_faces(G, R, bstart, bitems, L, [&](int f, const int *xyz) {
-        if (f >= 0) {
-            const float *fb = fbox + (int64_t)f * 6;
-            if (first_common_bin(G, fb, xyz, lo) && (double)fb[1] <= p.y && (double)fb[4] >= p.y &&
-                (double)fb[2] <= p.z && (double)fb[5] >= p.z && (double)fb[3] >= p.x) {
-                const double *P = pnodes + (int64_t)f * 27;
-                for (int s = 0; s < 8; ++s) {
-                    d3 F[3];
-                    face_tri(P, s, F);
-                    par ^= ray_x_crosses(p, F[0], F[1], F[2]);
-                }
-            }
-        }
-        return false;
-    });
-    const int odd = __popcll(__ballot(par)) & 1;
-    if (lane == 0 && odd) c.iblank[e] = OC_HOLE;
-}
-
 constexpr int kFaceCap = 64;    // one chunk of candidate faces
 constexpr int kGroup = 8;   // candidate faces tested together by k_hit
 
-// a4 (and a6 for the far items, ray_item): one wavefront per near element
-// decides whether the surface intersects it: some element-boundary / surface triangle pair closer than tol_hit
+// a4: one wavefront per near element decides whether the surface intersects
+// it: some element-boundary / surface triangle pair closer than tol_hit
 // (Alg. cp2, with no truncation of the candidate faces), or the whole surface
 // inside the element.  Candidate faces that come within the element's
 // boundary-face boxes are collected in LDS and taken in groups of 1, 2, 4,
@@ -706,16 +710,7 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
     const int n_in = a.cnt->n_inbox;
     const double tol = kTolHit;
     for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
-        const uint8_t st = a.stat[item];
-        if (st == ST_FAR) {
-            // far items share the launch: the few near items alone leave
-            // most SIMDs idle
-            const uint64_t it = a.list_inbox[item];
-            __syncthreads();
-            ray_item(a.insts[item_cut(it)], a.bin_start, a.bitems, item_elem(it), L);
-            continue;
-        }
-        if (st != ST_NEAR) continue;
+        if (a.stat[item] != ST_NEAR) continue;
         const uint64_t it = a.list_inbox[item];
         const int ci = item_cut(it), e = item_elem(it);
         const CutInst &c = a.insts[ci];
