@@ -23,7 +23,7 @@ OC_ETIMEDOUT = -8
 OC_HOLE, OC_FIELD, OC_FRINGE = 0, 1, -1
 OC_SURF_WALL, OC_SURF_OVERSET = 0, 1
 OC_FACE_INTERIOR, OC_FACE_WALL, OC_FACE_OVERSET, OC_FACE_FARFIELD = 0, 1, 2, 3
-OC_TUNE_SURF_BINS, OC_TUNE_EXACT_WAVES, OC_TUNE_SERVICE_SLOTS, OC_TUNE_HBM_BUDGET = 1, 2, 3, 4
+OC_TUNE_SURF_BINS, OC_TUNE_EXACT_WAVES, OC_TUNE_SERVICE_SLOTS, OC_TUNE_HBM_BUDGET, OC_TUNE_DONOR_WAVES = 1, 2, 3, 4, 5
 
 EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_register_grid",
            "oc_register_cut_surface", "oc_cut", "oc_cut_multi", "oc_last_cut_info", "oc_fringe_points",
