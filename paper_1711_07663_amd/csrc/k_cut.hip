@@ -18,7 +18,7 @@
 //                                   parity of the first node
 //   k_hit                           one wavefront per near element: FP64
 //                                   triangle-pair intersection
-//   k_side                          near elements not hit: nearest-face side of
+//   k_side_group / k_side_solo      near elements not hit: nearest-face side of
 //                                   the first node (wavefront minimum + tie rule)
 //   k_fringe / k_overset_fringe     one fringe layer around holes, overset faces
 #include <algorithm>
@@ -680,7 +680,8 @@ struct ExactArgs {
     int32_t *sidelist;          // the ST_SIDE items, appended by k_hit (count cnt->n_sidelist)
 };
 
-constexpr int kSideWaves = 8;   // wavefronts sharing one side item's walks
+constexpr int kSideWaves = 8;     // wavefronts sharing one side item's walks (the first items)
+constexpr int kSideGroups = 256;  // items taken that way: one workgroup per CU
 
 constexpr int kFaceCap = 64;    // one chunk of candidate faces
 constexpr int kGroup = 8;   // candidate faces tested together by k_hit
@@ -853,12 +854,12 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
 // minimum of the point-to-triangle distance over the binned faces, then the
 // tie rule (largest |dot| of the unit point-to-surface vector with the
 // outward triangle normal; normals averaged only for equally visible
-// triangles of opposite sign).  One workgroup of kSideWaves wavefronts per
-// element of the list k_hit leaves, three stages that meet in LDS: an upper
+// triangles of opposite sign).  Per element of the list k_hit leaves, three
+// stages that meet in LDS (or in registers, with one wavefront): an upper
 // bound U (the nearest node of the element's candidate faces), the nearest
 // distance over the faces within U, and the two first records of the tie
-// set in tie order.  In every stage each wavefront takes every
-// kSideWaves-th chunk of the stage's bin walk.  The stages compute a
+// set in tie order.  In every stage each of the NW wavefronts takes every
+// NW-th chunk of the stage's bin walk.  The stages compute a
 // minimum over an exact set and the first two records of a total order, so
 // the split among wavefronts does not change any bit.
 __device__ inline void side_item(const ExactArgs &a, int item, int &e, const CutInst *&cp, d3 &p)
@@ -900,14 +901,21 @@ __device__ inline void tie_wave_first2(TieRec &b1, TieRec &b2)
     }
 }
 
-__global__ __launch_bounds__(64 * kSideWaves) void k_side(ExactArgs a)
+// NW wavefronts per item.  The list is split on the device: k_side_group
+// (NW = kSideWaves) takes the first kSideGroups items, one workgroup each
+// (the latency of a few items); k_side_solo (NW = 1) takes the rest
+// (throughput when there are many).
+template <int NW>
+__device__ inline void side_items(const ExactArgs &a)
 {
-    __shared__ WalkLds L[kSideWaves];
-    __shared__ double red[kSideWaves];
-    __shared__ TieRec rec[2 * kSideWaves];
+    __shared__ WalkLds L[NW];
+    __shared__ double red[NW];
+    __shared__ TieRec rec[2 * NW];
     const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
-    const int n_side = a.cnt->n_sidelist;
-    for (int si = blockIdx.x; si < n_side; si += gridDim.x) {
+    const int n_list = a.cnt->n_sidelist;
+    const int first = NW == 1 ? kSideGroups : 0;
+    const int n_side = NW == 1 ? n_list : (n_list < kSideGroups ? n_list : kSideGroups);
+    for (int si = first + blockIdx.x; si < n_side; si += gridDim.x) {
         const int item = a.sidelist[si];
         int e;
         const CutInst *cp;
@@ -942,13 +950,13 @@ __global__ __launch_bounds__(64 * kSideWaves) void k_side(ExactArgs a)
                 }
                 u = wave_min_d(u);
                 return false;
-            }, part, kSideWaves);
+            }, part, NW);
         }
         u = wave_min_d(u);
         if (lane == 0) red[part] = u;
         __syncthreads();
         double U = red[0];
-        for (int k = 1; k < kSideWaves; ++k) U = fmin(U, red[k]);
+        for (int k = 1; k < NW; ++k) U = fmin(U, red[k]);
         __syncthreads();
         // stage 2: nearest distance over every face whose box is within U
         double best = U;
@@ -964,13 +972,13 @@ __global__ __launch_bounds__(64 * kSideWaves) void k_side(ExactArgs a)
                 }
                 best = wave_min_d(best);
                 return false;
-            }, part, kSideWaves);
+            }, part, NW);
         }
         best = wave_min_d(best);
         if (lane == 0) red[part] = best;
         __syncthreads();
         double B = red[0];
-        for (int k = 1; k < kSideWaves; ++k) B = fmin(B, red[k]);
+        for (int k = 1; k < NW; ++k) B = fmin(B, red[k]);
         // stage 3: tie set within B * (1 + 1e-9)
         const double thr = B * (1.0 + 1e-9);
         TieRec b1, b2;
@@ -1010,7 +1018,7 @@ __global__ __launch_bounds__(64 * kSideWaves) void k_side(ExactArgs a)
                     }
                 }
                 return false;
-            }, part, kSideWaves);
+            }, part, NW);
         }
         tie_wave_first2(b1, b2);
         if (lane == 0) {
@@ -1021,7 +1029,7 @@ __global__ __launch_bounds__(64 * kSideWaves) void k_side(ExactArgs a)
         if (threadIdx.x == 0) {
             TieRec c1, c2;
             c1.valid = c2.valid = 0;
-            for (int k = 0; k < 2 * kSideWaves; ++k) tie_offer(c1, c2, rec[k]);
+            for (int k = 0; k < 2 * NW; ++k) tie_offer(c1, c2, rec[k]);
             double sg = c1.dot;
             if (c2.valid && c1.absdot - c2.absdot <= 1e-9 && ((c1.dot > 0.0) != (c2.dot > 0.0)))
                 sg = c1.vx * (c1.nx + c2.nx) + c1.vy * (c1.ny + c2.ny) + c1.vz * (c1.nz + c2.nz);
@@ -1030,6 +1038,9 @@ __global__ __launch_bounds__(64 * kSideWaves) void k_side(ExactArgs a)
         __syncthreads();
     }
 }
+
+__global__ __launch_bounds__(64 * kSideWaves) void k_side_group(ExactArgs a) { side_items<kSideWaves>(a); }
+__global__ __launch_bounds__(64) void k_side_solo(ExactArgs a) { side_items<1>(a); }
 
 // a8: fringe layer (field elements sharing a face with a hole).  Every hole
 // is an in-box item of some cut of its output, so the scatter runs over the
@@ -1318,7 +1329,10 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         ea.cnt = sl->counters;
         ea.sidelist = sl->l_sidelist;
         LAUNCH(k_hit, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
-        LAUNCH(k_side, dim3((unsigned)std::max(1, ctx->exact_waves / kSideWaves)), dim3(64 * kSideWaves), ea);
+        LAUNCH(k_side_group, dim3((unsigned)kSideGroups), dim3(64 * kSideWaves), ea);
+        // the items past the first kSideGroups, a wavefront each (a loop, so
+        // few blocks: the launch costs little when there are none)
+        LAUNCH(k_side_solo, dim3((unsigned)std::min(ctx->exact_waves, 4096)), dim3(64), ea);
         LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_inbox, sl->counters);
     }
     if (ov_blk) LAUNCH(k_overset_fringe, dim3((unsigned)ov_blk), dim3(kThreads), sl->outs, n_out);
