@@ -680,8 +680,9 @@ struct ExactArgs {
     int32_t *sidelist;          // the ST_SIDE items, appended by k_hit (count cnt->n_sidelist)
 };
 
-constexpr int kSideWaves = 8;     // wavefronts sharing one side item's walks (the first items)
-constexpr int kSideGroups = 256;  // items taken that way: one workgroup per CU
+constexpr int kSideWaves = 8;        // wavefronts sharing one side item's walks (short lists)
+constexpr int kSideGroups = 256;     // their workgroups: one per CU
+constexpr int kSideGroupMax = 512;   // longest list taken that way (two rounds)
 
 constexpr int kFaceCap = 64;    // one chunk of candidate faces
 constexpr int kGroup = 8;   // candidate faces tested together by k_hit
@@ -901,10 +902,11 @@ __device__ inline void tie_wave_first2(TieRec &b1, TieRec &b2)
     }
 }
 
-// NW wavefronts per item.  The list is split on the device: k_side_group
-// (NW = kSideWaves) takes the first kSideGroups items, one workgroup each
-// (the latency of a few items); k_side_solo (NW = 1) takes the rest
-// (throughput when there are many).
+// NW wavefronts per item.  One of the two kernels takes the whole list,
+// chosen on the device by its length: up to kSideGroupMax items
+// k_side_group (NW = kSideWaves, one workgroup per CU at a time: the
+// latency of a few items), beyond that k_side_solo (NW = 1: throughput when
+// there are many).
 template <int NW>
 __device__ inline void side_items(const ExactArgs &a)
 {
@@ -912,10 +914,9 @@ __device__ inline void side_items(const ExactArgs &a)
     __shared__ double red[NW];
     __shared__ TieRec rec[2 * NW];
     const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
-    const int n_list = a.cnt->n_sidelist;
-    const int first = NW == 1 ? kSideGroups : 0;
-    const int n_side = NW == 1 ? n_list : (n_list < kSideGroups ? n_list : kSideGroups);
-    for (int si = first + blockIdx.x; si < n_side; si += gridDim.x) {
+    const int n_side = a.cnt->n_sidelist;
+    if ((n_side <= kSideGroupMax) != (NW > 1)) return;   // the other kernel takes the list
+    for (int si = blockIdx.x; si < n_side; si += gridDim.x) {
         const int item = a.sidelist[si];
         int e;
         const CutInst *cp;
@@ -1330,8 +1331,8 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         ea.sidelist = sl->l_sidelist;
         LAUNCH(k_hit, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
         LAUNCH(k_side_group, dim3((unsigned)kSideGroups), dim3(64 * kSideWaves), ea);
-        // the items past the first kSideGroups, a wavefront each (a loop, so
-        // few blocks: the launch costs little when there are none)
+        // a long list, a wavefront per item (a loop, so few blocks: the launch
+        // costs little when the list is short)
         LAUNCH(k_side_solo, dim3((unsigned)std::min(ctx->exact_waves, 4096)), dim3(64), ea);
         LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_inbox, sl->counters);
     }
