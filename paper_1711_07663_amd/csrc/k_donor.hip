@@ -35,7 +35,8 @@ constexpr unsigned kLoopBlocks = 4096;
 // Without STREAM the element's 81 coordinates are loaded once into registers
 // (one round of independent loads) and reused by every iteration; with
 // STREAM they are read row by row from memory each iteration (few registers,
-// for rarely taken paths).  Both give the same bits.
+// for rarely taken paths).  Both give the same bits; k_dp_newton's
+// per-component map rounds differently in the last bits.
 template <bool STREAM>
 __device__ inline bool newton_q2(const double *__restrict__ Xg, d3 p, double diam, double *xi, int &iters)
 {
@@ -602,9 +603,9 @@ __global__ __launch_bounds__(kT) void k_dp_fill(DonorArgs a)
 
 // a11: Newton on every pair, three lanes each: lane d of a group holds
 // coordinate d of the element's 27 nodes and evaluates component d of x(xi)
-// and row d of J; the group shares them and every lane takes the same step
-// (the arithmetic of newton_q2, component by component), so the three stay
-// in lock step and agree bit for bit.  21 groups per wavefront, lane 63
+// and row d of J (q2_map_comp); the group shares them and every lane takes
+// the same step (the steps of newton_q2), so the three stay in lock step and
+// agree bit for bit.  21 groups per wavefront, lane 63
 // idle.  A point keeps the lowest element id that contains it, and a
 // contained pair keeps its xi.
 constexpr int kNewtonGroups = 21;
