@@ -45,7 +45,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 FP64_VECTOR_PEAK = 78.6        # TFLOP/s, MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
-NEWTON_FLOP = 640              # FLOP per Newton iteration of the quadratic map (sum-factorised x, J, 3x3 solve)
+NEWTON_FLOP = 590              # FLOP per Newton iteration: x and J contracted axis by axis (3 x 155), 3x3 solve ~90, basis and residual ~35
 
 
 KERNEL_SOURCE = {"k_dp_newton": "paper_1711_07663_amd/csrc/k_donor.hip",
