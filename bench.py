@@ -148,10 +148,10 @@ def cpu_baseline(case, sample_every):
     hole[sel] = st == 0
     ib = O.mark_fringe(hole, O.face_neighbors(bg.conn))
     pts_bg = O.fringe_points(bg, O.fringe_elements(ib))
-    O.donor_search(sh, pts_bg[::k], pose, threads=threads)
+    d_bg, r_bg, _ = O.donor_search(sh, pts_bg[::k], pose, threads=threads)
     ib_sh = O.cut(sh, [], [])
     pts_sh = O.fringe_points(sh, O.fringe_elements(ib_sh), pose)
-    O.donor_search(bg, pts_sh[::k], threads=threads)
+    d_sh, r_sh, _ = O.donor_search(bg, pts_sh[::k], threads=threads)
     t_wall = time.perf_counter() - t0
     t_step = t_wall * k
     what = "the whole step" if k == 1 else "every %d-th background element and receptor point (step time x %d)" % (k, k)
@@ -159,7 +159,55 @@ def cpu_baseline(case, sample_every):
                 sample="%s: cut of the 128^3 background, fringe, %d + %d receptor points and their donors in "
                        "both directions; %.1f s of wall time on %d threads" % (what, pts_bg.shape[0],
                                                                               pts_sh.shape[0], t_wall, threads),
-                t_step_s=t_step)
+                t_step_s=t_step, results=dict(k=k, sel=sel, ib=ib, d_bg=d_bg, r_bg=r_bg, d_sh=d_sh, r_sh=r_sh))
+
+
+def precision_report(system, info, res):
+    """How the FP32 stages and the FP64 path compare with the FP64 oracle on
+    the same step: the share of the FP32 candidate filter's near elements that
+    the exact test does not find intersected, and the iblank, donor ids and
+    largest reference-coordinate difference against the oracle (when the
+    oracle ran the whole step)."""
+    k = res["k"]
+    ib_g = system.ib_bg.cpu().numpy()
+    out = dict(filter_in_box=info["n_inbox"], filter_near=info["n_near"], exact_hit=info["n_hit"],
+               near_not_hit_frac=(info["n_near"] - info["n_hit"]) / max(info["n_near"], 1))
+    if k != 1:
+        return out   # a sampled cut gives the oracle another fringe: nothing to compare point by point
+    out["iblank_equal"] = bool(np.array_equal(ib_g, res["ib"]))
+    b = system.bodies[0]
+    err = 0.0
+    same = True
+    for d_o, r_o, dg, rg in ((res["d_bg"], res["r_bg"], b["donor_bg"], b["ref_bg"]),
+                             (res["d_sh"], res["r_sh"], b["donor"], b["ref"])):
+        n = d_o.shape[0]
+        d_g = dg.cpu().numpy()[:n]
+        r_g = rg.cpu().numpy()[:n]
+        same &= bool(np.array_equal(d_g, d_o))
+        ok = (d_o >= 0) & (d_g == d_o)
+        if ok.any():
+            err = max(err, float(np.abs(r_g[ok] - r_o[ok]).max()))
+    out["donor_ids_equal"] = same
+    out["max_ref_coord_diff"] = err
+    return out
+
+
+def copy_ceiling_gbs(nbytes=1 << 29, reps=10):
+    """HBM rate of a plain device-to-device copy (bytes read + written per
+    second), the practical ceiling for a streaming kernel."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3 / reps
+    del src, dst
+    return 2.0 * nbytes / t / 1e9
 
 
 def main():
@@ -316,10 +364,15 @@ def run_dimpled(a):
                registration_s=t_reg, per_kernel=per_kernel, per_kernel_overlapped=per_kernel_overlapped,
                roofline=roof, roofline_filter=roof_filter,
                dominant_kernel=dominant)
+    if roof_filter:
+        ceil = copy_ceiling_gbs()
+        roof_filter["copy_ceiling_gbs"] = ceil
+        roof_filter["frac_of_copy_ceiling"] = roof_filter["achieved"] / ceil
     if not a.no_cpu_baseline:
         log("oracle baseline on the host")
         cb = cpu_baseline(case, a.cpu_sample)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
+        out["precision"] = precision_report(system, info, cb["results"])
     ctx.close()
     return out
 
