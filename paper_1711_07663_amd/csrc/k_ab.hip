@@ -158,28 +158,49 @@ __device__ inline double lagrange(const Nodes1D &z, int a, double s)
     return l;
 }
 
-// weight k = a + m b + m^2 c of receptor i: (l_a(xi) l_b(eta)) l_c(zeta)
+// weight k = a + m b + m^2 c of receptor i: (l_a(xi) l_b(eta)) l_c(zeta).
+// A block takes weight_receptors(m) receptors at a time: their 3m basis
+// values go to LDS first (each computed once, two divisions at m = 3, not
+// per weight), then the block writes their weights in order, one per
+// thread.  The values and the products are those of the per-weight form.
+constexpr int kWBasis = 3 * kAT;   // basis values staged per round (3m per receptor)
+constexpr int kWRec = kAT;         // receptors per round, at most
+
+// receptors per round: about four weights per thread, within the LDS
+__host__ __device__ inline int weight_receptors(int m)
+{
+    const int m3 = m * m * m;
+    int r = (4 * kAT) / m3;
+    if (r > kWBasis / (3 * m)) r = kWBasis / (3 * m);
+    if (r > kWRec) r = kWRec;
+    return r < 1 ? 1 : r;
+}
+
 __global__ __launch_bounds__(kAT) void k_interp_weights(const int32_t *__restrict__ donors,
                                                         const double *__restrict__ ref,
                                                         const int32_t *__restrict__ n_dev, int64_t cap, Nodes1D z,
                                                         double *__restrict__ w)
 {
+    __shared__ double sb[kWBasis];
+    __shared__ int sok[kWRec];
     const int m = z.m, m3 = m * m * m;
+    const int rec = weight_receptors(m);
     const int64_t n = n_dev ? min((int64_t)*n_dev, cap) : cap;
-    const int64_t total = n * m3;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = t / m3;
-        const int k = (int)(t - i * m3);
-        if (donors[i] < 0) {
-            w[t] = __builtin_nan("");
-            continue;
+    for (int64_t i0 = (int64_t)blockIdx.x * rec; i0 < n; i0 += (int64_t)gridDim.x * rec) {
+        const int nr = (int)min((int64_t)rec, n - i0);
+        for (int v = threadIdx.x; v < nr * 3 * m; v += blockDim.x) {
+            const int r = v / (3 * m), q = v - r * 3 * m, d = q / m, a = q - d * m;
+            sb[v] = lagrange(z, a, ref[3 * (i0 + r) + d]);
         }
-        const int a = k % m, b = (k / m) % m, c = k / (m * m);
-        const double la = lagrange(z, a, ref[3 * i]);
-        const double lb = lagrange(z, b, ref[3 * i + 1]);
-        const double lc = lagrange(z, c, ref[3 * i + 2]);
-        w[t] = (la * lb) * lc;
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) sok[r] = donors[i0 + r] >= 0;
+        __syncthreads();
+        for (int t = threadIdx.x; t < nr * m3; t += blockDim.x) {
+            const int r = t / m3, k = t - r * m3;
+            const int a = k % m, b = (k / m) % m, c = k / (m * m);
+            const double *L = sb + r * 3 * m;
+            w[i0 * m3 + t] = sok[r] ? (L[a] * L[m + b]) * L[2 * m + c] : __builtin_nan("");
+        }
+        __syncthreads();
     }
 }
 
@@ -240,8 +261,9 @@ oc_status weights_run(oc_slot *sl, const int32_t *donors, const double *ref, con
 {
     oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
-    const int64_t work = cap * z.m * z.m * z.m;
-    LAUNCH(k_interp_weights, dim3(ab_blocks(std::max<int64_t>(work, 1))), dim3(kAT), donors, ref, n_dev, cap, z, w);
+    const int64_t rec = weight_receptors(z.m);
+    const int64_t blk = std::max<int64_t>(1, std::min<int64_t>((cap + rec - 1) / rec, 4096));
+    LAUNCH(k_interp_weights, dim3((unsigned)blk), dim3(kAT), donors, ref, n_dev, cap, z, w);
     OC_HIP(hipGetLastError());
     return OC_OK;
 }
