@@ -279,3 +279,30 @@ def test_ab_step_paper_topology(ctx, orc):
         ss.replay(poses)
         compare_ab(ss.snapshot(), o)
         ss.close()
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 8])
+def test_weights_every_node_count(ctx, orc, m):
+    """Weights for node counts whose staging differs (256, 128, 8 and 2
+    receptors per round; at m = 8 a round has 512 weights for 256 threads):
+    a ragged receptor count with orphans, equal to the oracle's products."""
+    import torch
+    _note("weights, m = %d" % m)
+    z = np.polynomial.legendre.leggauss(m)[0] if m > 1 else np.array([0.3])
+    rng = np.random.default_rng(1000 + m)
+    n = 1037
+    ref_h = rng.uniform(-1.0, 1.0, size=(n, 3))
+    don_h = rng.integers(0, 5000, size=n).astype(np.int32)
+    don_h[rng.random(n) < 0.1] = -1
+    ref_h[don_h < 0] = np.nan
+    donor = torch.from_numpy(don_h).cuda()
+    ref = torch.from_numpy(ref_h).cuda()
+    w = torch.full((n, m ** 3), 7.0, dtype=torch.float64, device="cuda")
+    ctx.interp_weights(donor, ref, n, w, nodes1d=z)
+    torch.cuda.synchronize()
+    w_g = w.cpu().numpy()
+    w_o = orc.interp_weights(don_h, ref_h, z)
+    assert np.array_equal(np.isnan(w_g), np.isnan(w_o))
+    ok = don_h >= 0
+    assert np.abs(w_g[ok] - w_o[ok]).max() <= 1e-15
+    assert np.abs(w_g[ok].sum(axis=1) - 1.0).max() <= 1e-12
