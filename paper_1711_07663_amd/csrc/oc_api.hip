@@ -203,14 +203,6 @@ oc_status slot_reserve_cut(oc_slot *sl, const CutCaps &need)
     return slot_alloc_cut(sl, c);
 }
 
-static Pose to_pose(const double *p)
-{
-    Pose q;
-    for (int i = 0; i < 9; ++i) q.r[i] = p[i];
-    for (int i = 0; i < 3; ++i) q.t[i] = p[9 + i];
-    return q;
-}
-
 bool pose_finite(const double *p)
 {
     if (!p) return false;
