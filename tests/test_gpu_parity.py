@@ -183,3 +183,29 @@ def test_deterministic(ctx, orc):
     assert np.array_equal(a["ib_bg"], b["ib_bg"])
     for x, y in zip(a["bodies"], b["bodies"]):
         assert np.array_equal(x["donor"], y["donor"]) and np.array_equal(x["ref"], y["ref"], equal_nan=True)
+
+
+def test_donor_wave_caps_do_not_change_results(ctx, orc):
+    """The donor-search wavefront cap changes the grids, and with them the
+    lanes each point's bin walk gets: donors and reference coordinates stay
+    the same bit for bit, and equal to the oracle's."""
+    from paper_1711_07663_amd import oc
+    _note("donor wave caps: same donors under every cap")
+    case = CF.make_case(24, -2.0, 2.0, m=5, layers=3, dimples=30, name="caps")
+    system = _system(ctx, case)
+    ref = None
+    try:
+        for cap in (0, 64, 1024, 4096, 0):
+            ctx.tune(oc.OC_TUNE_DONOR_WAVES, 0, cap)
+            g = gpu_step(system, case["poses"])
+            if ref is None:
+                ref = g
+                compare(g, oracle_step(case, case["poses"]))
+                continue
+            for k in ("ib_bg", "pts_bg"):
+                assert np.array_equal(g[k], ref[k]), (cap, k)
+            for gb, rb in zip(g["bodies"], ref["bodies"]):
+                for k in ("donor_bg", "ref_bg", "donor", "ref"):
+                    assert np.array_equal(gb[k], rb[k], equal_nan=True), (cap, k)
+    finally:
+        ctx.tune(oc.OC_TUNE_DONOR_WAVES, 0, 0)
