@@ -101,13 +101,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1, help="oracle runs on every k-th element / point")
     ap.add_argument("--bg", type=int, default=128)
-    ap.add_argument("--workload", default="dimpled", choices=["dimpled", "spin", "batch", "serve", "unblank", "ab", "filtered"])
+    ap.add_argument("--workload", default="dimpled",
+                    choices=["dimpled", "spin", "batch", "serve", "service", "unblank", "ab", "filtered"])
     ap.add_argument("--spin-steps", type=int, default=200)
     ap.add_argument("--topology", default="walls", choices=["walls", "paper"],
                     help="ab: the background cut by the walls, or by the shells' overset boundaries")
     ap.add_argument("--batch-n", type=int, default=64)
     ap.add_argument("--rates", default="50,100,200,500", help="serve: arrival rates, requests/s")
-    ap.add_argument("--requests", type=int, default=2000, help="serve: requests per rate")
+    ap.add_argument("--requests", type=int, default=2000, help="serve, service: requests per rate")
+    ap.add_argument("--service-rates", default="500,1000,2000,4000", help="service: arrival rates, requests/s")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
     ap.add_argument("--surf-bins", type=float, default=0.0,
                     help="scale of the wall's bins per axis (0: the library's choice)")
@@ -224,7 +226,7 @@ def main():
         torch.cuda.synchronize()
         log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
         del src, dst
-    out = dict(dimpled=run_dimpled, spin=run_spin, batch=run_batch, serve=run_serve,
+    out = dict(dimpled=run_dimpled, spin=run_spin, batch=run_batch, serve=run_serve, service=run_service,
                unblank=run_unblank, ab=run_ab, filtered=run_filtered)[a.workload](a)
     print(json.dumps(out), flush=True)
 
@@ -951,6 +953,110 @@ def run_serve(a):
                                     % (a.rates, a.budget_gb), parallelism="1 GPU"),
                latency_ms=best["latency_ms"], rates=results, slots=len(srv.slots),
                hbm_used_gb=srv.used_bytes() / (1 << 30), refused_admissions=srv.n_refused)
+    ctx.close()
+    return out
+
+
+def run_service(a):
+    """Cut requests served as they arrive by the native cut service
+    (oc_submit / oc_wait): Poisson arrivals (seed 7663) at the given rates,
+    each request one of the 64 uneven instances drawn uniformly, against the
+    same arrival trace served one synchronous cut at a time."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from workloads import configs as CF
+    from workloads import meshes as M
+    specs = CF.batch_instances(n=a.batch_n)
+    torch.cuda.set_device(0)
+    ctx = oc.Context(device=0)
+    log("registering %d instances" % len(specs))
+    inst = []
+    for sp in specs:
+        axes = (0.5, 0.35, 0.25) if sp["kind"] == "ellipsoid" else None
+        bgm = M.background_grid(sp["bg_n"], -2.0, 2.0, amp=0.02)
+        surf = M.cube_sphere(sp["m"], R=0.5, axes=axes, dimples=sp["dimples"], dimple_a=CF.DIMPLE_A,
+                             dimple_k=CF.DIMPLE_K)
+        gid = ctx.register_grid(bgm.nodes, bgm.conn)
+        sid = ctx.register_cut_surface(surf.nodes, surf.conn)
+        pose = np.asarray(sp["pose"], dtype=np.float64)
+        # a few outputs per instance, so that repeated requests of one
+        # instance can be in flight together
+        bufs = [torch.empty(bgm.n_elem, dtype=torch.int8, device="cuda") for _ in range(4)]
+        inst.append(dict(gid=gid, sid=sid, pose=pose, bufs=bufs, busy=[None] * 4, next=0))
+        del bgm, surf
+    solo = [torch.empty_like(d["bufs"][0]) for d in inst]
+    log("warming the service and the plain path")
+    for d, o in zip(inst, solo):
+        assert ctx.wait(ctx.submit(d["gid"], [d["sid"]], d["pose"].reshape(1, 12), d["bufs"][0]))
+        ctx.cut(d["gid"], d["sid"], d["pose"], o)
+    torch.cuda.synchronize()
+    same = all(torch.equal(d["bufs"][0], o) for d, o in zip(inst, solo))
+    rng = np.random.default_rng(7663)
+    rates = [float(x) for x in a.service_rates.split(",")]
+    results = []
+    for lam in rates:
+        n_req = a.requests
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=n_req))
+        which = rng.integers(0, len(inst), size=n_req)
+        for mode in ("service", "one_at_a_time"):
+            log("rate %g req/s, %s, %d requests" % (lam, mode, n_req))
+            torch.cuda.synchronize()
+            lat = []
+            t0 = time.perf_counter()
+            if mode == "service":
+                pending = []   # (ticket, arrival, instance, buffer)
+                i = 0
+                while i < n_req or pending:
+                    now = time.perf_counter() - t0
+                    while i < n_req and arrivals[i] <= now:
+                        d = inst[which[i]]
+                        k = d["next"]
+                        d["next"] = (k + 1) % len(d["bufs"])
+                        if d["busy"][k] is not None:   # that output is still in flight: wait for it
+                            t_old, a_old = d["busy"][k]
+                            ctx.wait(t_old)
+                            lat.append(time.perf_counter() - t0 - a_old)
+                            pending = [p for p in pending if p[0] != t_old]
+                        t = ctx.submit(d["gid"], [d["sid"]], d["pose"].reshape(1, 12), d["bufs"][k])
+                        d["busy"][k] = (t, arrivals[i])
+                        pending.append((t, arrivals[i], which[i], k))
+                        i += 1
+                    still = []
+                    for t, arr, w, k in pending:
+                        if ctx.wait(t, 0):
+                            lat.append(time.perf_counter() - t0 - arr)
+                            inst[w]["busy"][k] = None
+                        else:
+                            still.append((t, arr, w, k))
+                    pending = still
+                t_end = time.perf_counter() - t0
+            else:
+                for i in range(n_req):
+                    now = time.perf_counter() - t0
+                    if arrivals[i] > now:
+                        time.sleep(max(0.0, arrivals[i] - now - 2e-4))
+                        while time.perf_counter() - t0 < arrivals[i]:
+                            pass
+                    d = inst[which[i]]
+                    ctx.cut(d["gid"], d["sid"], d["pose"], solo[which[i]])
+                    torch.cuda.synchronize()
+                    lat.append(time.perf_counter() - t0 - arrivals[i])
+                t_end = time.perf_counter() - t0
+            results.append(dict(rate=lam, mode=mode, requests=n_req, throughput=n_req / t_end,
+                                latency_ms=_percentiles(lat), mean_ms=1e3 * float(np.mean(lat))))
+    info = ctx.service_info()
+    served = [r for r in results if r["mode"] == "service"]
+    best = max(served, key=lambda r: r["rate"])
+    out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
+               value=best["throughput"], unit="requests/s", n_gpus=1, steps=a.requests, warmup=len(inst),
+               ms_per_step=1e3 / best["throughput"], higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f64", data="synthetic",
+               config=dict(workload="native cut service: Poisson arrivals at %s req/s, each request one of the 64 "
+                                    "uneven instances (backgrounds 16^3..96^3, surfaces of 6 m^2 faces, m 8..64), "
+                                    "oc_submit / oc_wait" % a.service_rates, parallelism="1 GPU"),
+               latency_ms=best["latency_ms"], rates=results, service_equals_plain=bool(same),
+               service=dict(slots=info["slots"], peak_running=info["peak_running"],
+                            slot_gb=info["slot_bytes"] / (1 << 30)))
     ctx.close()
     return out
 
