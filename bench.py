@@ -111,6 +111,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000, help="serve, service: requests per rate")
     ap.add_argument("--service-rates", default="500,1000,2000,4000", help="service: arrival rates, requests/s")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serve: HBM budget")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="default workload: requests of the short serving segment (0: none)")
+    ap.add_argument("--serve-rate", type=float, default=500.0, help="default workload: its arrival rate, req/s")
     ap.add_argument("--surf-bins", type=float, default=0.0,
                     help="scale of the wall's bins per axis (0: the library's choice)")
     ap.add_argument("--exact-waves", type=int, default=0,
@@ -164,27 +167,31 @@ def cpu_baseline(case, sample_every):
                 t_step_s=t_step, results=dict(k=k, sel=sel, ib=ib, d_bg=d_bg, r_bg=r_bg, d_sh=d_sh, r_sh=r_sh))
 
 
-def precision_report(system, info, res):
+def precision_report(snap, info, res):
     """How the FP32 stages and the FP64 path compare with the FP64 oracle on
     the same step: the share of the FP32 candidate filter's near elements that
     the exact test does not find intersected, and the iblank, donor ids and
     largest reference-coordinate difference against the oracle (when the
-    oracle ran the whole step)."""
+    oracle ran the whole step).  ``snap``: host copy of the outputs of the
+    timed path (the last graph-replayed step)."""
     k = res["k"]
-    ib_g = system.ib_bg.cpu().numpy()
+    ib_g = snap["ib_bg"]
     out = dict(filter_in_box=info["n_inbox"], filter_near=info["n_near"], exact_hit=info["n_hit"],
                near_not_hit_frac=(info["n_near"] - info["n_hit"]) / max(info["n_near"], 1))
     if k != 1:
         return out   # a sampled cut gives the oracle another fringe: nothing to compare point by point
     out["iblank_equal"] = bool(np.array_equal(ib_g, res["ib"]))
-    b = system.bodies[0]
+    b = snap["bodies"][0]
     err = 0.0
     same = True
     for d_o, r_o, dg, rg in ((res["d_bg"], res["r_bg"], b["donor_bg"], b["ref_bg"]),
                              (res["d_sh"], res["r_sh"], b["donor"], b["ref"])):
         n = d_o.shape[0]
-        d_g = dg.cpu().numpy()[:n]
-        r_g = rg.cpu().numpy()[:n]
+        if dg.shape[0] != n:
+            same = False
+            continue
+        d_g = dg[:n]
+        r_g = rg[:n]
         same &= bool(np.array_equal(d_g, d_o))
         ok = (d_o >= 0) & (d_g == d_o)
         if ok.any():
@@ -302,6 +309,7 @@ def run_dimpled(a):
         evs.append((e0, e1))
     torch.cuda.synchronize()
     lat = [x.elapsed_time(y) * 1e-3 for x, y in evs]
+    snap = ss.snapshot()      # outputs of the last timed (replayed) step
 
     # per-kernel HIP-event timing (events on the kernel's own stream) over
     # eager launches of the same step with the two chains one after the
@@ -370,11 +378,31 @@ def run_dimpled(a):
         ceil = copy_ceiling_gbs()
         roof_filter["copy_ceiling_gbs"] = ceil
         roof_filter["frac_of_copy_ceiling"] = roof_filter["achieved"] / ceil
+    if a.serve_requests > 0:
+        # the serving stream, shortened: one rate, Poisson arrivals over the
+        # four grid sets (this dimpled system is one of them)
+        log("serving stream: %d requests at %g req/s" % (a.serve_requests, a.serve_rate))
+        ss.close()
+        systems, cases = serving_systems(ctx, dimpled=(case, system))
+        res, srv = serve_stream(ctx, systems, cases, [a.serve_rate], a.serve_requests, a.budget_gb)
+        sv = {r["mode"]: r for r in res}
+        out["serving"] = dict(rate_per_s=a.serve_rate, requests=a.serve_requests,
+                              sets="tiny 16^3, dimpled 128^3, spinning ball at a random step, two-body 160^3 at a "
+                                   "random step",
+                              served=dict(p50_ms=sv["served"]["latency_ms"]["p50"],
+                                          p99_ms=sv["served"]["latency_ms"]["p99"],
+                                          throughput_per_s=sv["served"]["throughput"], slots=sv["served"]["slots"]),
+                              one_at_a_time=dict(p50_ms=sv["one_at_a_time"]["latency_ms"]["p50"],
+                                                 p99_ms=sv["one_at_a_time"]["latency_ms"]["p99"],
+                                                 throughput_per_s=sv["one_at_a_time"]["throughput"]),
+                              hbm_used_gb=srv.used_bytes() / (1 << 30))
+        for sl in list(srv.slots):
+            srv._release(sl)
     if not a.no_cpu_baseline:
         log("oracle baseline on the host")
         cb = cpu_baseline(case, a.cpu_sample)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
-        out["precision"] = precision_report(system, info, cb["results"])
+        out["precision"] = precision_report(snap, info, cb["results"])
     ctx.close()
     return out
 
@@ -862,73 +890,79 @@ def run_batch(a):
     return out
 
 
-def run_serve(a):
-    """Poisson arrivals over four grid sets (tiny case, dimpled case, the
-    spinning ball at a random step, the two-body case on a 160^3 background
-    at a random step), served with continuous batching (slots on their own
-    streams, graph replays, admission by HBM budget), against one-at-a-time
-    service of the same arrival trace on the default slot."""
-    import torch
-    from paper_1711_07663_amd import oc
+def serving_systems(ctx, dimpled=None):
+    """The four grid sets of the serving stream, registered on ctx: the tiny
+    case, the dimpled 128^3 case (whose spinning poses give the moving-ball
+    set), and the two-body case on a 160^3 background.  ``dimpled``: an
+    (case, OversetSystem) pair already registered on ctx, reused."""
     from paper_1711_07663_amd.pipeline import OversetSystem
+    from workloads import configs as CF
+    tiny, two = CF.tiny(), CF.two_body()
+    if dimpled is None:
+        dimp = CF.dimpled()
+        dsys = OversetSystem(ctx, dimp, bg_points_cap=27 * 40000)
+    else:
+        dimp, dsys = dimpled
+    systems = dict(tiny=OversetSystem(ctx, tiny), dimpled=dsys,
+                   two_body=OversetSystem(ctx, two, bg_points_cap=27 * 80000))
+    return systems, dict(tiny=tiny, dimpled=dimp, two_body=two)
+
+
+def serve_stream(ctx, systems, cases, rates, n_requests, budget_gb, seed=7663):
+    """Poisson arrivals (seed) at each rate, each request one of the four
+    sets drawn uniformly (the spinning ball and the two-body case at a
+    random step), served with continuous batching (Server) and, on the same
+    arrival trace, one request at a time on the default slot.  Returns the
+    per-rate results and the server."""
+    import torch
     from paper_1711_07663_amd.serve import Server
     from workloads import configs as CF
-    torch.cuda.set_device(0)
-    ctx = oc.Context(device=0)
-    log("registering the grid sets")
-    tiny, dimp, two = CF.tiny(), CF.dimpled(), CF.two_body()
-    systems = dict(tiny=OversetSystem(ctx, tiny), dimpled=OversetSystem(ctx, dimp, bg_points_cap=27 * 40000),
-                   two_body=OversetSystem(ctx, two, bg_points_cap=27 * 80000))
     sets = ["tiny", "dimpled", "spin", "two_body"]
-    rng = np.random.default_rng(7663)
+    rng = np.random.default_rng(seed)
 
     def draw():
         k = sets[int(rng.integers(0, 4))]
         if k == "tiny":
-            return "tiny", tiny["poses"]
+            return "tiny", cases["tiny"]["poses"]
         if k == "dimpled":
-            return "dimpled", dimp["poses"]
+            return "dimpled", cases["dimpled"]["poses"]
         n = int(rng.integers(1, 201))
         if k == "spin":
             return "dimpled", [CF.spinning_poses(n)[-1]]
         return "two_body", CF.two_body_poses(n)
 
-    budget = int(a.budget_gb * (1 << 30))
+    budget = int(budget_gb * (1 << 30))
     srv = Server(ctx, systems, budget, max_slots=16)
     log("warming slots")
-    home = dict(tiny=tiny["poses"], dimpled=dimp["poses"], two_body=two["poses"])
     for _ in range(3):
         for name in systems:
             for _ in range(2):
-                srv.submit(name, home[name])
+                srv.submit(name, cases[name]["poses"])
         srv.drain()
     torch.cuda.synchronize()
-    rates = [float(x) for x in a.rates.split(",")]
     results = []
     for lam in rates:
-        n_req = a.requests
-        gaps = rng.exponential(1.0 / lam, size=n_req)
+        gaps = rng.exponential(1.0 / lam, size=n_requests)
         arrivals = np.cumsum(gaps)
-        reqs = [draw() for _ in range(n_req)]
+        reqs = [draw() for _ in range(n_requests)]
         for mode in ("served", "one_at_a_time"):
-            log("rate %g req/s, %s, %d requests" % (lam, mode, n_req))
+            log("rate %g req/s, %s, %d requests" % (lam, mode, n_requests))
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             lat = []
             if mode == "served":
                 srv.done = []
                 i = 0
-                while i < n_req or srv.queue or srv.busy:
+                while i < n_requests or srv.queue or srv.busy:
                     now = time.perf_counter() - t0
-                    while i < n_req and arrivals[i] <= now:
+                    while i < n_requests and arrivals[i] <= now:
                         srv.submit(reqs[i][0], reqs[i][1], t_arrival=t0 + arrivals[i])
                         i += 1
                     srv.pump()
                 lat = [r["t_done"] - r["t_arrival"] for r in srv.done]
                 t_end = max(r["t_done"] for r in srv.done) - t0
             else:
-                t_free = 0.0
-                for i in range(n_req):
+                for i in range(n_requests):
                     now = time.perf_counter() - t0
                     if arrivals[i] > now:
                         time.sleep(max(0.0, arrivals[i] - now - 2e-4))
@@ -938,9 +972,26 @@ def run_serve(a):
                     torch.cuda.synchronize()
                     lat.append(time.perf_counter() - t0 - arrivals[i])
                 t_end = time.perf_counter() - t0
-            results.append(dict(rate=lam, mode=mode, requests=n_req, throughput=n_req / t_end,
+            results.append(dict(rate=lam, mode=mode, requests=n_requests, throughput=n_requests / t_end,
                                 latency_ms=_percentiles(lat), mean_ms=1e3 * float(np.mean(lat)),
                                 slots=len(srv.slots) if mode == "served" else 1))
+    return results, srv
+
+
+def run_serve(a):
+    """Poisson arrivals over four grid sets (tiny case, dimpled case, the
+    spinning ball at a random step, the two-body case on a 160^3 background
+    at a random step), served with continuous batching (slots on their own
+    streams, graph replays, admission by HBM budget), against one-at-a-time
+    service of the same arrival trace on the default slot."""
+    import torch
+    from paper_1711_07663_amd import oc
+    torch.cuda.set_device(0)
+    ctx = oc.Context(device=0)
+    log("registering the grid sets")
+    systems, cases = serving_systems(ctx)
+    results, srv = serve_stream(ctx, systems, cases, [float(x) for x in a.rates.split(",")], a.requests,
+                                a.budget_gb)
     served = [r for r in results if r["mode"] == "served"]
     best = max(served, key=lambda r: r["rate"])
     out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",

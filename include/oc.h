@@ -90,6 +90,9 @@ typedef struct oc_cut_info {
     int64_t n_hit;        /* elements intersected by a surface */
     int64_t n_hole;       /* hole elements */
     int64_t n_cand_pairs; /* element x face pairs passing the FP32 box filter */
+    int64_t n_side;       /* near elements not intersected: their side comes from the
+                             nearest-face search (over 512 of them in one call: one
+                             wavefront per element, else an 8-wavefront group each) */
 } oc_cut_info;
 
 /* Statistics of the last oc_donor_search call (host copy; synchronises). */
@@ -98,6 +101,8 @@ typedef struct oc_donor_info {
     int64_t n_newton;  /* Newton solves run (candidates whose box holds the point) */
     int64_t n_iter;    /* Newton iterations run in total */
     int64_t n_orphan;  /* points without a donor */
+    int64_t n_overflow;/* points whose candidates did not fit the pair capacity and
+                          were solved one candidate at a time in ascending id */
 } oc_donor_info;
 
 /* Create / destroy a context on cfg->device (cfg may be NULL: device 0,
@@ -420,6 +425,11 @@ oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len);
  *                        points and pairs ask for).  A lower cap leaves
  *                        room on the device for work running beside the
  *                        search on another stream.
+ *   OC_TUNE_DONOR_PAIRS  arg unused; value = most (point, element) pairs one
+ *                        donor search keeps for its batched Newton solves
+ *                        (0 = the slot's capacity, 8 per point); the points
+ *                        whose pairs fall beyond it are solved one candidate
+ *                        at a time in ascending id (same donors).
  *   OC_TUNE_HBM_BUDGET   arg unused; value = the context's HBM budget in
  *                        bytes (0 = none), as oc_config.hbm_budget; later
  *                        allocations are held to it, memory already held is
@@ -431,7 +441,8 @@ enum {
     OC_TUNE_EXACT_WAVES = 2,
     OC_TUNE_SERVICE_SLOTS = 3,
     OC_TUNE_HBM_BUDGET = 4,
-    OC_TUNE_DONOR_WAVES = 5
+    OC_TUNE_DONOR_WAVES = 5,
+    OC_TUNE_DONOR_PAIRS = 6
 };
 oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t *applied);
 

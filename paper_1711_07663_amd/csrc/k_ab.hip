@@ -228,14 +228,15 @@ oc_status ab_faces_run(oc_slot *sl, const Grid &g, const int8_t *iblank, int32_t
     int32_t *tcount = sl->fr_tiles, *toff = sl->fr_tiles + (nt + 1);
     int32_t *tmp = sl->fr_tiles + 2 * (nt + 1);
     uint8_t *m8 = reinterpret_cast<uint8_t *>(sl->ab_mask);
+    // sizes the scan refuses are refused before the mask is marked: k_ab_write
+    // is what takes the mask back to zero, so nothing may fail in between
+    if (nt > scan_max_items()) {
+        set_error("ab faces: grid too large for the tile scan");
+        return OC_EINVAL;
+    }
     LAUNCH(k_ab_mark, dim3(ab_blocks(g.n_elem)), dim3(kAT), iblank, g.nbr, g.n_elem, sl->ab_mask);
     LAUNCH(k_ab_count, dim3((unsigned)std::max<int64_t>(nt, 1)), dim3(kAT), m8, iblank, g.ovmask, g.n_elem, tcount);
-    const oc_status sc = scan_exclusive(ctx, st, tcount, toff, nt, nullptr, tmp);
-    if (sc != OC_OK) {
-        // leave the mask zero for the next call
-        (void)hipMemsetAsync(sl->ab_mask, 0, (size_t)(g.n_elem + 3) / 4 * 4, st);
-        return sc;
-    }
+    OC_TRY(scan_exclusive(ctx, st, tcount, toff, nt, nullptr, tmp));
     LAUNCH(k_ab_write, dim3((unsigned)std::max<int64_t>(nt, 1)), dim3(kAT), m8, iblank, g.ovmask, g.n_elem, toff,
            faces, cap);
     OC_HIP(hipGetLastError());

@@ -1228,6 +1228,9 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
     oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
     const CutCaps need = cut_caps(reqs, n_req);
+    // refused before anything is launched: a scan that failed after
+    // k_bin_count would leave counts behind that the next cut would build on
+    OC_TRY(cut_caps_check(need));
     OC_TRY(slot_reserve_cut(sl, need));
     for (int r = 0; r < n_req; ++r) {
         if (reqs[r].prev && reqs[r].n_surf != 1) {

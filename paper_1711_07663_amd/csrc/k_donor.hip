@@ -508,7 +508,7 @@ __global__ __launch_bounds__(kT) void k_dp_count(DonorArgs a)
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         *a.n_eff = (int32_t)n;
         a.dcnt->n_points = (unsigned long long)n;
-        a.dcnt->n_newton = a.dcnt->n_iter = a.dcnt->n_orphan = 0ull;
+        a.dcnt->n_newton = a.dcnt->n_iter = a.dcnt->n_orphan = a.dcnt->n_overflow = 0ull;
     }
     const Pose pose = *a.pose;
     const int L = walk_lanes(a, n), lane = threadIdx.x & 63, sub = lane & (L - 1);
@@ -702,12 +702,13 @@ __global__ __launch_bounds__(kT) void k_dp_newton(DonorArgs a)
 __global__ __launch_bounds__(kT) void k_dp_final(DonorArgs a)
 {
     const int64_t n = *a.n_eff;
-    int extra = 0;
+    int extra = 0, over = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         int32_t d = -1;
         double xi[3] = {NAN, NAN, NAN};
         int scratch = 0;
         if ((int64_t)a.off[i + 1] > a.pair_cap) {
+            ++over;
             const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
             const int64_t b = point_bin(a.G, p);
             for (int j = a.bstart[b]; j < a.bstart[b + 1]; ++j) {
@@ -735,11 +736,16 @@ __global__ __launch_bounds__(kT) void k_dp_final(DonorArgs a)
         a.ref[3 * i + 1] = xi[1];
         a.ref[3 * i + 2] = xi[2];
     }
-    // solves of the overflow path (rare: only points whose pairs did not fit)
-    unsigned long long sx = extra;
+    // solves and points of the overflow path (rare: only points whose pairs
+    // did not fit)
+    unsigned long long sx = extra, so = over;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) sx += __shfl_xor(sx, d, 64);
+    for (int d = 32; d >= 1; d >>= 1) {
+        sx += __shfl_xor(sx, d, 64);
+        so += __shfl_xor(so, d, 64);
+    }
     if ((threadIdx.x & 63) == 0 && sx) atomicAdd(&a.dcnt->n_newton, sx);
+    if ((threadIdx.x & 63) == 0 && so) atomicAdd(&a.dcnt->n_overflow, so);
 }
 
 // Statistics of the last search (only when asked for): Newton iterations
@@ -781,7 +787,7 @@ __global__ void k_donor_reset(DonorCounters *c)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         c->n_points = 0ull;
-        c->n_newton = c->n_iter = c->n_orphan = 0ull;
+        c->n_newton = c->n_iter = c->n_orphan = c->n_overflow = 0ull;
     }
 }
 
@@ -971,7 +977,7 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     a.pair_el = sl->dpair_el;
     a.pair_xi = sl->dpair_xi;
     a.pair_it = sl->dpair_it;
-    a.pair_cap = sl->dpair_cap;
+    a.pair_cap = ctx->donor_pairs > 0 ? std::min<int64_t>(sl->dpair_cap, ctx->donor_pairs) : sl->dpair_cap;
     a.lanes = g.dlanes;
     a.pad = 0;
     a.donor = donor;

@@ -171,6 +171,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply_direct(const int32_
 constexpr int kScanDirectMaxTiles = 1024;
 
 int64_t scan_tmp_ints(int64_t cap) { return (cap + kScanTile - 1) / kScanTile + 1; }
+int64_t scan_max_items() { return (int64_t)kScanMaxTiles * kScanTile; }
 
 // One block for short arrays: chunks of kSingleChunk items in order, each
 // scanned by the block and offset by the running total (one launch instead

@@ -45,7 +45,7 @@ void dev_free_all(oc_ctx *ctx, std::vector<DevBuf> &owner)
 void time_begin(oc_ctx *ctx, hipStream_t st, const char *name, size_t *slot)
 {
     *slot = std::numeric_limits<size_t>::max();
-    if (!ctx->timing) return;
+    if (!ctx || !ctx->timing) return;
     while (ctx->event_pool.size() < ctx->event_next + 2) {
         hipEvent_t ev;
         if (hipEventCreate(&ev) != hipSuccess) return;
@@ -80,9 +80,23 @@ static oc_status slot_alloc_lists(oc_slot *sl, int64_t n_elem)
 }
 
 // cut scratch for caps c (replaces any previous cut scratch of the slot)
+oc_status cut_caps_check(const CutCaps &c)
+{
+    // bins are scanned in one device-wide scan and indexed by int32, element
+    // lists hold int32 element ids per cut
+    if (c.bins > scan_max_items() || c.bins >= INT32_MAX || c.elem_inst >= INT32_MAX || c.faces >= INT32_MAX / 27) {
+        set_error("cut too large: " + std::to_string(c.bins) + " surface bins (at most " +
+                  std::to_string(std::min<int64_t>(scan_max_items(), INT32_MAX - 1)) + "), " +
+                  std::to_string(c.elem_inst) + " elements x surfaces, " + std::to_string(c.faces) + " faces");
+        return OC_EINVAL;
+    }
+    return OC_OK;
+}
+
 static oc_status slot_alloc_cut(oc_slot *sl, CutCaps c)
 {
     oc_ctx *ctx = sl->ctx;
+    OC_TRY(cut_caps_check(c));
     dev_free_all(ctx, sl->cut_owned);
     sl->cc = CutCaps{};
     c.elem_inst = std::max<int64_t>(c.elem_inst, 1);
@@ -560,6 +574,7 @@ static oc_status read_cut_info(oc_slot *sl, oc_cut_info *info)
     info->n_hit = c.n_hit;
     info->n_hole = c.n_hole;
     info->n_cand_pairs = (int64_t)c.n_cand_pairs;
+    info->n_side = c.n_side;
     return OC_OK;
 }
 
@@ -573,6 +588,7 @@ static oc_status read_donor_info(oc_slot *sl, oc_donor_info *info)
     info->n_newton = (int64_t)c.n_newton;
     info->n_iter = (int64_t)c.n_iter;
     info->n_orphan = (int64_t)c.n_orphan;
+    info->n_overflow = (int64_t)c.n_overflow;
     return OC_OK;
 }
 
@@ -1371,6 +1387,13 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
         }
         ctx->donor_waves = (int)value;
         v = ctx->donor_waves;
+    } else if (knob == OC_TUNE_DONOR_PAIRS) {
+        if (value < 0) {
+            set_error("oc_tune: negative pair cap");
+            return OC_EINVAL;
+        }
+        ctx->donor_pairs = value;
+        v = ctx->donor_pairs;
     } else if (knob == OC_TUNE_HBM_BUDGET) {
         if (value < 0) {
             set_error("oc_tune: negative budget");

@@ -59,7 +59,7 @@ struct CutCounters {
 
 // Per-donor-search counters (device).
 struct DonorCounters {
-    unsigned long long n_points, n_newton, n_iter, n_orphan;
+    unsigned long long n_points, n_newton, n_iter, n_orphan, n_overflow;
 };
 
 // -------------------------------------------------------- device buffers --
@@ -226,6 +226,7 @@ struct oc_ctx {
     int surf_bins = 0;
     int exact_waves = 8192;                // persistent wavefronts of the exact-stage kernels
     int donor_waves = 0;                   // cap on the donor-search wavefronts (0 = none)
+    int64_t donor_pairs = 0;               // cap on the pairs one donor search keeps (0 = none)
     double donor_bin_scale = 0.5;
     int64_t budget = 0;
     int64_t used = 0;
@@ -257,6 +258,8 @@ void time_end(oc_ctx *ctx, hipStream_t st, size_t slot);
 // exclusive scan of n (device count n_dev if non-null, else n_host) int32
 // values; out[n] receives the total.  tmp must hold scan_tmp_ints(cap) ints.
 int64_t scan_tmp_ints(int64_t cap);
+// largest count scan_exclusive takes
+int64_t scan_max_items();
 oc_status scan_exclusive(oc_ctx *ctx, hipStream_t st, const int32_t *in, int32_t *out, int64_t cap,
                          const int *n_dev, int32_t *tmp);
 
@@ -291,6 +294,9 @@ struct CutReq {
     double sweep = 0.0;
 };
 CutCaps cut_caps(const CutReq *reqs, int n);
+// OC_EINVAL (with a message) for cut capacities beyond what the scans and
+// the int32 indices of the cut kernels take
+oc_status cut_caps_check(const CutCaps &c);
 // validate the public requests and resolve their grids and surfaces (poses
 // are left null; with need_outputs the outputs and poses must be given)
 oc_status collect_cut_reqs(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req, std::vector<CutReq> &out,

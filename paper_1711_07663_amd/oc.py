@@ -24,6 +24,7 @@ OC_HOLE, OC_FIELD, OC_FRINGE = 0, 1, -1
 OC_SURF_WALL, OC_SURF_OVERSET = 0, 1
 OC_FACE_INTERIOR, OC_FACE_WALL, OC_FACE_OVERSET, OC_FACE_FARFIELD = 0, 1, 2, 3
 OC_TUNE_SURF_BINS, OC_TUNE_EXACT_WAVES, OC_TUNE_SERVICE_SLOTS, OC_TUNE_HBM_BUDGET, OC_TUNE_DONOR_WAVES = 1, 2, 3, 4, 5
+OC_TUNE_DONOR_PAIRS = 6
 
 EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_register_grid",
            "oc_register_cut_surface", "oc_cut", "oc_cut_multi", "oc_last_cut_info", "oc_fringe_points",
@@ -49,7 +50,7 @@ class oc_config(C.Structure):
 
 class oc_cut_info(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("n_elem", "n_inbox", "n_near", "n_far", "n_hit", "n_hole",
-                                         "n_cand_pairs")]
+                                         "n_cand_pairs", "n_side")]
 
 
 class oc_cut_req(C.Structure):
@@ -63,7 +64,7 @@ class oc_service_stats(C.Structure):
 
 
 class oc_donor_info(C.Structure):
-    _fields_ = [(n, C.c_int64) for n in ("n_points", "n_newton", "n_iter", "n_orphan")]
+    _fields_ = [(n, C.c_int64) for n in ("n_points", "n_newton", "n_iter", "n_orphan", "n_overflow")]
 
 
 _lib = None

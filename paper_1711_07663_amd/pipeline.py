@@ -185,7 +185,11 @@ class SlotStep:
     of step k-1 with the sweep bound ``sweep`` (a bound on how far any wall
     point moves in one step, e.g. Context.sweep_bound of two consecutive
     poses); the two iblank buffers alternate, so a captured step exists for
-    each parity."""
+    each parity.  A warm step whose pose lies farther than ``sweep`` from
+    the previous step's (checked on the host poses given to ``step``,
+    ``replay`` and ``replay_table`` with a host table) runs as an eager cold
+    step instead; a device pose table is not read back, so its caller keeps
+    consecutive poses within ``sweep``."""
 
     def __init__(self, system: OversetSystem, stream=None, warm=False, sweep=0.0, ab=False, ab_faces_cap=None,
                  nodes1d=_oc.GAUSS3):
@@ -218,6 +222,8 @@ class SlotStep:
         self.sweep = float(sweep)
         self.k = 0              # steps launched (selects the iblank buffer when warm)
         self.graphs = {}
+        self._last_pose = None  # host pose of the last warm-checked step (None: unknown)
+        self.cold_fallbacks = 0  # warm steps run cold because the pose moved too far
 
     @property
     def stream(self):
@@ -309,14 +315,31 @@ class SlotStep:
         with torch.cuda.stream(self.slot.stream):
             self.poses_dev.copy_(self._pose_table(poses))
 
+    def _warm_ok(self, pose):
+        """True when a warm cut from the last step's pose to ``pose`` (host,
+        the body's) stays within the sweep bound the step was built with."""
+        if self._last_pose is None:
+            return True             # after a device table: the caller's bound
+        need = self.sys.ctx.sweep_bound(self.sys.bg_cutters()[0], self._last_pose, pose)
+        # sweep_bound is inflated by a relative 1e-9 beyond the true largest
+        # travel, so equal steps whose bounds differ in the last bits still
+        # pass, and a passing pose never moves a point farther than sweep
+        return need <= self.sweep * (1.0 + 1e-9)
+
     def step(self, poses, cold=False, serial=False):
         """Eager launches on the slot streams (no synchronisation); the step
         is complete when the slot stream (``stream``) reaches its end.  The
-        first step of a warm SlotStep (or one with ``cold``) is a cold cut;
-        ``serial`` runs both chains on the slot stream, one after the other."""
+        first step of a warm SlotStep (or one with ``cold``, or one whose
+        pose moved farther than the sweep bound) is a cold cut; ``serial``
+        runs both chains on the slot stream, one after the other."""
+        if self.warm and self.k > 0 and not cold and not self._warm_ok(poses[0]):
+            cold = True
+            self.cold_fallbacks += 1
         self.set_poses(poses)
         self._launch(self.k, cold or self.k == 0, serial=serial)
         self.k += 1
+        if self.warm:
+            self._last_pose = np.asarray(poses[0], dtype=np.float64).copy()
 
     def capture(self):
         """Capture the step (both iblank parities when warm); a warm
@@ -346,9 +369,24 @@ class SlotStep:
 
     def replay_table(self, table):
         """Graph replay with a pose table (host, or device: then the copy is
-        stream ordered and the host does not wait)."""
+        stream ordered and the host does not wait).  A warm step whose host
+        table moves the body beyond the sweep bound runs eagerly and cold."""
         if not self.graphs:
             self.capture()
+        if self.warm:
+            if table.is_cuda:
+                self._last_pose = None      # not read back: the caller keeps the bound
+            else:
+                pose = table[0].numpy().astype(np.float64)
+                if not self._warm_ok(pose):
+                    with torch.cuda.stream(self.slot.stream):
+                        self.poses_dev.copy_(table)
+                    self.cold_fallbacks += 1
+                    self._launch(self.k, True)
+                    self.k += 1
+                    self._last_pose = pose.copy()
+                    return
+                self._last_pose = pose.copy()
         with torch.cuda.stream(self.slot.stream):
             self.poses_dev.copy_(table, non_blocking=table.is_cuda)
             self.graphs[self.k % 2 if self.warm else 0].replay()

@@ -44,6 +44,80 @@ def oracle_step(case, poses, threads=0):
     return out
 
 
+def element_boxes(grid, chunk=1 << 18):
+    """Node boxes (lo, hi) of every element, computed in chunks."""
+    n = grid.n_elem
+    lo = np.empty((n, 3))
+    hi = np.empty((n, 3))
+    for d in range(3):
+        x = np.ascontiguousarray(grid.nodes[:, d])
+        for s in range(0, n, chunk):
+            c = grid.conn[s:s + chunk]
+            a = x[c[:, 0]]
+            b = a.copy()
+            for k in range(1, c.shape[1]):
+                v = x[c[:, k]]
+                np.minimum(a, v, out=a)
+                np.maximum(b, v, out=b)
+            lo[s:s + chunk, d] = a
+            hi[s:s + chunk, d] = b
+    return lo, hi
+
+
+def band_hole_mask(grid, surfaces, poses, kinds=None, threads=0, pad=1e-4, boxes=None):
+    """Holes of grid cut by posed surfaces, the oracle run only on the
+    elements whose node box comes within pad of a posed surface's node box.
+    Every other element is farther than pad (> 1e-7) from that surface and
+    its first node lies outside the surface's box, hence outside the closed
+    surface (winding number 0): not a hole under the plain definition."""
+    if kinds is None:
+        kinds = [O.SURF_WALL] * len(surfaces)
+    lo, hi = boxes if boxes is not None else element_boxes(grid)
+    hole = np.zeros(grid.n_elem, dtype=bool)
+    n_band = 0
+    for s, p, k in zip(surfaces, poses, kinds):
+        R = np.asarray(p[:9], dtype=np.float64).reshape(3, 3)
+        X = s.nodes @ R.T + np.asarray(p[9:12], dtype=np.float64)
+        slo, shi = X.min(axis=0) - pad, X.max(axis=0) + pad
+        band = np.nonzero(np.all(hi >= slo, axis=1) & np.all(lo <= shi, axis=1))[0]
+        n_band += band.size
+        if band.size:
+            st = O.cut_surface(grid, s, p, k, sel=band, threads=threads)
+            hole[band[st == 0]] = True
+    return hole, n_band
+
+
+def band_cut(grid, surfaces, poses, kinds=None, threads=0, boxes=None):
+    """The oracle's iblank of a large grid by the band method (holes as
+    band_hole_mask, then the fringe layer over the whole grid)."""
+    hole, _ = band_hole_mask(grid, surfaces, poses, kinds, threads, boxes=boxes)
+    return O.mark_fringe(hole, O.face_neighbors(grid.conn), grid.face_tags)
+
+
+def oracle_step_band(case, poses, threads=0):
+    """oracle_step for cases too large for a whole-grid oracle cut: the cuts
+    by the band method, receptor points and donors for every point."""
+    bg = case["bg"]
+    walls = [b["surface"] for b in case["bodies"]]
+    out = {}
+    out["ib_bg"] = band_cut(bg, walls, poses, threads=threads)
+    fe = O.fringe_elements(out["ib_bg"])
+    out["pts_bg"] = O.fringe_points(bg, fe)
+    out["src_bg"] = np.repeat(fe, 27)
+    out["bodies"] = []
+    for i, b in enumerate(case["bodies"]):
+        others = [j for j in range(len(walls)) if j != i]
+        inv = pose_inverse(poses[i])
+        ib = band_cut(b["shell"], [walls[j] for j in others], [pose_compose(inv, poses[j]) for j in others],
+                      threads=threads)
+        fs = O.fringe_elements(ib)
+        pts = O.fringe_points(b["shell"], fs, poses[i])
+        d_bg, r_bg, _ = O.donor_search(b["shell"], out["pts_bg"], poses[i], threads=threads)
+        d, r, _ = O.donor_search(bg, pts, threads=threads)
+        out["bodies"].append(dict(ib=ib, pts=pts, src=np.repeat(fs, 27), donor_bg=d_bg, ref_bg=r_bg, donor=d, ref=r))
+    return out
+
+
 def gpu_step(system, poses):
     """The same step through the HIP library (pipeline.OversetSystem)."""
     import torch

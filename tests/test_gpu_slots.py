@@ -144,6 +144,32 @@ def test_warm_slot_graph_spinning(ctx, orc):
     compare(got, oracle_step(case, poses[-1]))
 
 
+def test_warm_slot_pose_jump_runs_cold(ctx, orc):
+    """A warm step whose pose moved farther than the sweep bound the step was
+    built with runs cold (eagerly) instead of keeping stale statuses; steps
+    within the bound stay on the warm graph."""
+    import torch
+    from paper_1711_07663_amd.pipeline import OversetSystem, SlotStep
+    _note("warm-started step with a pose jump beyond its sweep bound")
+    case = _small_case()
+    system = OversetSystem(ctx, case)
+    step = 2 * np.pi / 50
+    sweep = ctx.sweep_bound(system.bodies[0]["surf"], M.pose_rz(0.0), M.pose_rz(step))
+    warm = SlotStep(system, warm=True, sweep=sweep)
+    cold = SlotStep(system)
+    warm.step([M.pose_rz(0.0)])
+    torch.cuda.synchronize()
+    warm.capture()
+    seq = [step, 2 * step, 2 * step + 0.9, 3 * step + 0.9, 0.1]   # jumps at the third and fifth
+    for k, th in enumerate(seq):
+        warm.replay([M.pose_rz(th)])
+        got = warm.snapshot()
+        cold.step([M.pose_rz(th)])
+        _equal(cold.snapshot(), got)
+    assert warm.cold_fallbacks == 2
+    compare(got, oracle_step(case, [M.pose_rz(seq[-1])]))
+
+
 def test_slot_budget(ctx):
     from paper_1711_07663_amd import oc
     _note("slot creation over the HBM budget")

@@ -196,6 +196,157 @@ def box_surface(m, lo, hi, name="box"):
 
 
 # --------------------------------------------------------------------------
+# flat-faced solids from patches (slots, grooves, thin wedges)
+# --------------------------------------------------------------------------
+
+def patch_surface(corners, patches, k=1, name="patches"):
+    """Closed surface of 9-node quads from flat quadrilateral patches.
+
+    ``corners`` (nc, 3) and ``patches`` [(i00, i10, i11, i01)] of corner ids,
+    each ordered so that (c10 - c00) x (c01 - c00) points out of the solid.
+    Every patch becomes k x k quadratic faces on a (2k+1)^2 node lattice.
+    Points on a patch edge are interpolated from the edge's two corners in
+    ascending id order, so two patches sharing an edge share its nodes bit
+    for bit (the surface is watertight when every patch edge is shared)."""
+    corners = np.asarray(corners, dtype=np.float64)
+    N = 2 * k
+    keys = {}
+    pts = []
+
+    def node(key, xyz):
+        v = keys.get(key)
+        if v is None:
+            v = len(pts)
+            keys[key] = v
+            pts.append(xyz)
+        return v
+
+    def edge_point(a, b, m):
+        # point m of N along the edge from corner a to corner b
+        if m == 0:
+            return node(("c", a), corners[a])
+        if m == N:
+            return node(("c", b), corners[b])
+        lo, hi, mm = (a, b, m) if a < b else (b, a, N - m)
+        t = mm / N
+        return node(("e", lo, hi, mm), (1.0 - t) * corners[lo] + t * corners[hi])
+
+    conn = []
+    for pi_, (c00, c10, c11, c01) in enumerate(patches):
+        P00, P10, P11, P01 = corners[c00], corners[c10], corners[c11], corners[c01]
+        lat = np.empty((N + 1, N + 1), dtype=np.int64)
+        for j in range(N + 1):
+            for i in range(N + 1):
+                if j == 0:
+                    lat[i, j] = edge_point(c00, c10, i)
+                elif j == N:
+                    lat[i, j] = edge_point(c01, c11, i)
+                elif i == 0:
+                    lat[i, j] = edge_point(c00, c01, j)
+                elif i == N:
+                    lat[i, j] = edge_point(c10, c11, j)
+                else:
+                    u, v = i / N, j / N
+                    xyz = ((1 - u) * (1 - v)) * P00 + (u * (1 - v)) * P10 + (u * v) * P11 + ((1 - u) * v) * P01
+                    lat[i, j] = node(("i", pi_, i, j), xyz)
+        for fj in range(k):
+            for fi in range(k):
+                conn.append([lat[2 * fi + a, 2 * fj + b] for b in range(3) for a in range(3)])
+    return Surface(nodes=np.array(pts, dtype=np.float64), conn=np.array(conn, dtype=np.int32), name=name,
+                   meta=dict(k=k))
+
+
+def voxel_solid_surface(xs, ys, zs, solid, k=1, name="voxels"):
+    """Boundary of a union of cells of the rectilinear lattice xs x ys x zs
+    (solid[i, j, l] True = cell filled) as a closed surface of flat 9-node
+    quads, k x k per cell face, oriented outward."""
+    xs, ys, zs = (np.asarray(v, dtype=np.float64) for v in (xs, ys, zs))
+    solid = np.asarray(solid, dtype=bool)
+    nx, ny, nz = solid.shape
+    cid = lambda i, j, l: i + (nx + 1) * (j + (ny + 1) * l)
+    corners = np.array([(xs[i], ys[j], zs[l]) for l in range(nz + 1) for j in range(ny + 1)
+                        for i in range(nx + 1)], dtype=np.float64)
+
+    def filled(i, j, l):
+        return 0 <= i < nx and 0 <= j < ny and 0 <= l < nz and solid[i, j, l]
+
+    patches = []
+    for l in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                if not solid[i, j, l]:
+                    continue
+                if not filled(i + 1, j, l):   # +x: edges along y then z
+                    patches.append((cid(i + 1, j, l), cid(i + 1, j + 1, l), cid(i + 1, j + 1, l + 1), cid(i + 1, j, l + 1)))
+                if not filled(i - 1, j, l):   # -x
+                    patches.append((cid(i, j, l), cid(i, j, l + 1), cid(i, j + 1, l + 1), cid(i, j + 1, l)))
+                if not filled(i, j + 1, l):   # +y: edges along z then x
+                    patches.append((cid(i, j + 1, l), cid(i, j + 1, l + 1), cid(i + 1, j + 1, l + 1), cid(i + 1, j + 1, l)))
+                if not filled(i, j - 1, l):   # -y
+                    patches.append((cid(i, j, l), cid(i + 1, j, l), cid(i + 1, j, l + 1), cid(i, j, l + 1)))
+                if not filled(i, j, l + 1):   # +z: edges along x then y
+                    patches.append((cid(i, j, l + 1), cid(i + 1, j, l + 1), cid(i + 1, j + 1, l + 1), cid(i, j + 1, l + 1)))
+                if not filled(i, j, l - 1):   # -z
+                    patches.append((cid(i, j, l), cid(i, j + 1, l), cid(i + 1, j + 1, l), cid(i + 1, j, l)))
+    surf = patch_surface(corners, patches, k, name)
+    surf.meta.update(xs=xs, ys=ys, zs=zs)
+    return surf
+
+
+def slotted_plate(a=1.0, b=0.8, c=0.35, w=0.3, s=0.5, k=2, name="slotted plate"):
+    """A plate [-a,a] x [-b,b] x [-c,c] with a straight-sided slot |x| < w,
+    |y| < s cut through it along z (the slot test of Sec. 4.4): a closed
+    genus-one surface of flat faces."""
+    solid = np.ones((3, 3, 1), dtype=bool)
+    solid[1, 1, 0] = False
+    return voxel_solid_surface([-a, -w, w, a], [-b, -s, s, b], [-c, c], solid, k, name)
+
+
+def grooved_block(a=1.0, b=0.8, c=0.5, w=0.2, depth=0.35, k=2, name="grooved block"):
+    """A block [-a,a] x [-b,b] x [-c,c] with a groove |x| < w, z > c - depth
+    cut along its whole length in y (a concave channel, Sec. 4.4)."""
+    solid = np.ones((3, 1, 2), dtype=bool)
+    solid[1, 0, 1] = False
+    return voxel_solid_surface([-a, -w, w, a], [-b, b], [-c, c - depth, c], solid, k, name)
+
+
+def thin_wedge(apex, e, b, t, L, U, k=1, name="thin wedge"):
+    """A thin triangular prism (a blade): cross-section triangle with apex
+    at ``apex``, opening towards -b with half-thickness t per unit length
+    (vertices apex, apex - L b +- t L n0, n0 = e x b), extruded along the unit
+    vector e over [-U, U].  The two long faces meet at the apex edge at a
+    dihedral angle of about 2t; their outward normals are nearly opposite."""
+    e = np.asarray(e, dtype=np.float64) / np.linalg.norm(e)
+    b = np.asarray(b, dtype=np.float64)
+    b = b - e * (b @ e)
+    b /= np.linalg.norm(b)
+    n0 = np.cross(e, b)
+    apex = np.asarray(apex, dtype=np.float64)
+    sec = dict(A=(0.0, 0.0), B=(-L, t * L), C=(-L, -t * L))     # (b, n0) coordinates, counter-clockwise
+    sec["Mab"] = tuple(0.5 * (np.array(sec["A"]) + np.array(sec["B"])))
+    sec["Mbc"] = tuple(0.5 * (np.array(sec["B"]) + np.array(sec["C"])))
+    sec["Mca"] = tuple(0.5 * (np.array(sec["C"]) + np.array(sec["A"])))
+    sec["G"] = tuple((np.array(sec["A"]) + np.array(sec["B"]) + np.array(sec["C"])) / 3.0)
+    names = ["A", "Mab", "B", "Mbc", "C", "Mca", "G"]
+    corners, cid = [], {}
+    for side, g in (("-", -U), ("+", U)):
+        for nm in names:
+            cid[nm + side] = len(corners)
+            corners.append(apex + sec[nm][0] * b + sec[nm][1] * n0 + g * e)
+    ring = ["A", "Mab", "B", "Mbc", "C", "Mca"]
+    patches = []
+    for i in range(6):
+        p, q = ring[i], ring[(i + 1) % 6]
+        patches.append((cid[p + "-"], cid[q + "-"], cid[q + "+"], cid[p + "+"]))
+    for quad in (("A", "Mab", "G", "Mca"), ("B", "Mbc", "G", "Mab"), ("C", "Mca", "G", "Mbc")):
+        patches.append(tuple(cid[nm + "+"] for nm in quad))
+        patches.append(tuple(cid[nm + "-"] for nm in (quad[0], quad[3], quad[2], quad[1])))
+    surf = patch_surface(np.array(corners), patches, k, name)
+    surf.meta.update(apex=apex, e=e, b=b, n0=n0, t=t, L=L, U=U)
+    return surf
+
+
+# --------------------------------------------------------------------------
 # near-body shells
 # --------------------------------------------------------------------------
 
