@@ -328,6 +328,27 @@ oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_
 
 oc_status oc_last_donor_info(oc_ctx *ctx, oc_donor_info *info);
 
+/* oc_donor_search without any allocation, for callers that cannot allocate
+ * device memory during the call (code under HIP graph capture, tight
+ * serving loops, hosts that forbid allocation after start-up).  Same
+ * arguments, layout, stream (the context's) and results as oc_donor_search
+ * (donor ids equal; reference coordinates equal to the last bits unless a
+ * point has more candidate boxes than oc_donor_search's pair capacity
+ * holds, and always within 1e-10).  Its scratch is one fixed device array
+ * of the library (under 48 MiB, one per device, held from the first
+ * oc_create on that device until the process ends) sized for at most
+ * oc_noalloc_max_points() points: a larger n returns OC_EINVAL (split the
+ * points: each is searched on its own).  Every call on a device shares that
+ * array and leaves its contents behind; the call writes every part it reads
+ * first, so no clearing is needed, but calls that overlap in time on one
+ * device (two streams, two contexts, two threads) race and give wrong
+ * results: order them.  oc_last_donor_info and oc_timing do not cover this
+ * call.  No hipMalloc, hipFree or other allocation is made. */
+oc_status oc_donor_search_noalloc(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12],
+                                  const double *points, int64_t n, int32_t *donor_out, double *ref_out);
+/* the largest n oc_donor_search_noalloc accepts */
+oc_status oc_noalloc_max_points(int64_t *n);
+
 /* ------------------------------------------------------------------ slots
  * A slot is the per-request scratch of the compute calls (element lists,
  * posed surface copies and bins, counters) plus the stream they run on.

@@ -16,6 +16,7 @@
 // Registration-time kernels build the element node copies, the FP32 element
 // boxes and the donor bins.
 #include <cstring>
+#include <mutex>
 
 #include "dev_common.h"
 #include "q2.h"
@@ -1013,6 +1014,131 @@ oc_status donor_stats_run(oc_slot *sl)
         memcpy(&a, sl->last_donor_args.data(), sizeof a);
         LAUNCH(k_donor_stats, dim3(256), dim3(kT), a);
     }
+    OC_HIP(hipGetLastError());
+    return OC_OK;
+}
+
+// ------------------------------------------------ allocation-free search --
+// oc_donor_search_noalloc runs the same kernels as oc_donor_search on a
+// fixed scratch array that the code object carries (one copy per device,
+// held until the process ends), so the call allocates nothing.  Layout, each
+// part 256-byte aligned: the pose, the counters and the effective point
+// count, then the per-point and per-pair arrays of a search of up to
+// kNaPoints points with kPairsPerPoint pairs per point.
+constexpr int64_t kNaPoints = int64_t(1) << 17;
+constexpr int64_t kNaPairs = kNaPoints * kPairsPerPoint;
+constexpr size_t na_up(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t kNaPose = 0;
+constexpr size_t kNaCounters = kNaPose + na_up(sizeof(Pose));
+constexpr size_t kNaNeff = kNaCounters + na_up(sizeof(DonorCounters));
+constexpr size_t kNaLocal = kNaNeff + 256;
+constexpr size_t kNaCnt = kNaLocal + na_up(sizeof(double) * 3 * kNaPoints);
+constexpr size_t kNaOff = kNaCnt + na_up(sizeof(int32_t) * (kNaPoints + 1));
+constexpr size_t kNaBest = kNaOff + na_up(sizeof(int32_t) * (kNaPoints + 1));
+constexpr size_t kNaCache = kNaBest + na_up(sizeof(int32_t) * kNaPoints);
+constexpr size_t kNaScan = kNaCache + na_up(sizeof(int32_t) * kCandCache * kNaPoints);
+constexpr size_t kNaPairPt = kNaScan + na_up(sizeof(int32_t) * ((kNaPoints + 4095) / 4096 + 1));
+constexpr size_t kNaPairEl = kNaPairPt + na_up(sizeof(int32_t) * kNaPairs);
+constexpr size_t kNaPairXi = kNaPairEl + na_up(sizeof(int32_t) * kNaPairs);
+constexpr size_t kNaPairIt = kNaPairXi + na_up(sizeof(double) * 3 * kNaPairs);
+constexpr size_t kNaBytes = kNaPairIt + na_up(sizeof(uint8_t) * kNaPairs);
+static_assert(kNaBytes < (size_t(48) << 20), "allocation-free scratch exceeds its stated 48 MiB bound");
+
+// The scratch itself.  Host code never passes this name to a kernel (on the
+// host it is only a stand-in for the symbol): it uses the device address
+// taken by noalloc_init for the device at hand.
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+constexpr int kNaMaxDevices = 64;
+static unsigned char *g_na_base[kNaMaxDevices];
+static std::mutex g_na_mutex;
+
+// device address of this device's scratch array (once per device; the
+// device must be current)
+oc_status noalloc_init(int device)
+{
+    if (device < 0 || device >= kNaMaxDevices) {
+        set_error("device ordinal beyond the allocation-free scratch table");
+        return OC_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_na_mutex);
+    if (g_na_base[device]) return OC_OK;
+    void *ptr = nullptr;
+    OC_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_na_base[device] = static_cast<unsigned char *>(ptr);
+    return OC_OK;
+}
+
+int64_t noalloc_max_points() { return kNaPoints; }
+
+__global__ void k_na_pose(Pose p, Pose *dst)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = p;
+}
+
+oc_status donor_noalloc_run(oc_ctx *ctx, Grid &g, const double *pose_host, const double *pts, int64_t n,
+                            int32_t *donor, double *ref)
+{
+    if (n < 0 || n > kNaPoints) {
+        set_error("oc_donor_search_noalloc: " + std::to_string(n) + " points; at most " + std::to_string(kNaPoints) +
+                  " per call (split larger searches: every point is searched on its own)");
+        return OC_EINVAL;
+    }
+    unsigned char *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_na_mutex);
+        if (ctx->device >= 0 && ctx->device < kNaMaxDevices) base = g_na_base[ctx->device];
+    }
+    if (!base) {
+        set_error("oc_donor_search_noalloc: scratch of this device not initialised");
+        return OC_EDEVICE;
+    }
+    if (n == 0) return OC_OK;
+    hipStream_t st = ctx->dflt->stream;
+    Pose P;
+    for (int i = 0; i < 9; ++i) P.r[i] = pose_host[i];
+    for (int i = 0; i < 3; ++i) P.t[i] = pose_host[9 + i];
+    hipLaunchKernelGGL(k_na_pose, dim3(1), dim3(64), 0, st, P, reinterpret_cast<Pose *>(base + kNaPose));
+    DonorArgs a;
+    a.enodes = g.enodes;
+    a.cbox = g.cbox;
+    a.obox = g.obox;
+    a.ediam = g.ediam;
+    a.G = g.dgrid;
+    a.bstart = g.dbin_start;
+    a.bitems = g.dbin_items;
+    a.pose = reinterpret_cast<const Pose *>(base + kNaPose);
+    a.pts = pts;
+    a.cap = n;
+    a.n_dev = nullptr;
+    a.n_eff = reinterpret_cast<int32_t *>(base + kNaNeff);
+    a.plocal = reinterpret_cast<double *>(base + kNaLocal);
+    a.cnt = reinterpret_cast<int32_t *>(base + kNaCnt);
+    a.off = reinterpret_cast<int32_t *>(base + kNaOff);
+    a.best = reinterpret_cast<int32_t *>(base + kNaBest);
+    a.cache = reinterpret_cast<int32_t *>(base + kNaCache);
+    a.pair_pt = reinterpret_cast<int32_t *>(base + kNaPairPt);
+    a.pair_el = reinterpret_cast<int32_t *>(base + kNaPairEl);
+    a.pair_xi = reinterpret_cast<double *>(base + kNaPairXi);
+    a.pair_it = reinterpret_cast<uint8_t *>(base + kNaPairIt);
+    a.pair_cap = ctx->donor_pairs > 0 ? std::min<int64_t>(kNaPairs, ctx->donor_pairs) : kNaPairs;
+    a.lanes = g.dlanes;
+    a.pad = 0;
+    a.donor = donor;
+    a.ref = ref;
+    a.dcnt = reinterpret_cast<DonorCounters *>(base + kNaCounters);
+    const unsigned bcap = ctx->donor_waves > 0 ? (unsigned)std::max(1, ctx->donor_waves / (kT / 64)) : 1u << 30;
+    const unsigned gp = std::min({blocks(n, kT), kLoopBlocks, bcap});
+    const unsigned gw = std::min({blocks(n * g.dlanes, kT), kLoopBlocks, bcap});
+    const unsigned gn = std::min({blocks(kPairsPerPoint * n, (kT / 64) * kNewtonGroups), kLoopBlocks, bcap});
+    // every array is written before it is read within the call (k_dp_count
+    // sets the count, counters and per-point minima; the scan the offsets;
+    // k_dp_fill the pairs), so nothing left by an earlier call is used
+    hipLaunchKernelGGL(k_dp_count, dim3(gw), dim3(kT), 0, st, a);
+    OC_TRY(scan_exclusive(nullptr, st, a.cnt, a.off, n, a.n_eff, reinterpret_cast<int32_t *>(base + kNaScan)));
+    hipLaunchKernelGGL(k_dp_fill, dim3(gw), dim3(kT), 0, st, a);
+    hipLaunchKernelGGL(k_dp_newton, dim3(gn), dim3(kT), 0, st, a);
+    hipLaunchKernelGGL(k_dp_final, dim3(gp), dim3(kT), 0, st, a);
     OC_HIP(hipGetLastError());
     return OC_OK;
 }

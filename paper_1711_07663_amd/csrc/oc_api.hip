@@ -309,6 +309,11 @@ oc_status oc_create(oc_ctx **out, const oc_config *cfg)
         set_error("oc_create: invalid device");
         return OC_EINVAL;
     }
+    // device address of the allocation-free search's scratch on this device
+    if (noalloc_init(ctx->device) != OC_OK) {
+        delete ctx;
+        return OC_EDEVICE;
+    }
     if (hipMalloc(&ctx->dev_scalar, 64) != hipSuccess) {
         delete ctx;
         set_error("oc_create: allocation failed");
@@ -750,6 +755,29 @@ oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_
     oc_slot *sl = ctx->dflt;
     OC_TRY(set_poses(sl, kPoseSlots - 1, grid_pose, 1));
     return donor_run(sl, *g, sl->poses + kPoseSlots - 1, points, n, nullptr, donor_out, ref_out);
+}
+
+oc_status oc_donor_search_noalloc(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12],
+                                  const double *points, int64_t n, int32_t *donor_out, double *ref_out)
+{
+    if (!ctx || n < 0 || (n > 0 && (!points || !donor_out || !ref_out)) || !pose_finite(grid_pose)) {
+        set_error("oc_donor_search_noalloc: invalid arguments");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, donor_grid_id, &g));
+    return donor_noalloc_run(ctx, *g, grid_pose, points, n, donor_out, ref_out);
+}
+
+oc_status oc_noalloc_max_points(int64_t *n)
+{
+    if (!n) {
+        set_error("oc_noalloc_max_points: null output");
+        return OC_EINVAL;
+    }
+    *n = noalloc_max_points();
+    return OC_OK;
 }
 
 // Bound on the distance any point of surface s travels between two poses:

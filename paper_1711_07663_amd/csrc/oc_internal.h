@@ -363,6 +363,13 @@ oc_status weights_run(oc_slot *sl, const int32_t *donors, const double *ref, con
 oc_status unblank_run(oc_slot *sl, Grid &g, Surf *const *surfs, int n_surf, const Pose *poses_t,
                       const Pose *poses_tp, const int8_t *prev, int8_t *out, int32_t *ub_list, int64_t cap,
                       int32_t *n_dev, int64_t *n_host);
+// the allocation-free donor search: device address of this device's
+// scratch array (once per device, device current), its point limit, and
+// the search of n <= noalloc_max_points() points on the context stream
+oc_status noalloc_init(int device);
+int64_t noalloc_max_points();
+oc_status donor_noalloc_run(oc_ctx *ctx, Grid &g, const double *pose_host, const double *pts, int64_t n,
+                            int32_t *donor, double *ref);
 // donor search of min(*n_dev, cap) points (n_dev may be null: cap points)
 oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pts, int64_t cap, const int32_t *n_dev,
                     int32_t *donor, double *ref);

@@ -34,7 +34,7 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm", "oc_cut_batch", "oc_slot_cut_batch",
            "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points", "oc_ab_faces", "oc_face_points",
            "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered", "oc_slot_unblank", "oc_slot_element_points",
-           "oc_submit", "oc_wait", "oc_service_info"]
+           "oc_submit", "oc_wait", "oc_service_info", "oc_donor_search_noalloc", "oc_noalloc_max_points"]
 
 
 class OcError(RuntimeError):
@@ -91,6 +91,8 @@ def load(path=LIB_PATH):
         "oc_last_cut_info": ([vp, C.POINTER(oc_cut_info)]),
         "oc_fringe_points": ([vp, C.c_int32, dp, vp, vp, C.c_int64, i64p, vp]),
         "oc_donor_search": ([vp, C.c_int32, dp, vp, C.c_int64, vp, vp]),
+        "oc_donor_search_noalloc": ([vp, C.c_int32, dp, vp, C.c_int64, vp, vp]),
+        "oc_noalloc_max_points": ([i64p]),
         "oc_last_donor_info": ([vp, C.POINTER(oc_donor_info)]),
         "oc_timing": ([vp, C.c_int32]),
         "oc_timing_report": ([vp, C.c_char_p, C.c_int64]),
@@ -408,6 +410,22 @@ class Context:
             return
         _check(load().oc_donor_search(self._h, grid_id, pp, _dptr(points, torch.float64, 3 * n), int(n),
                                       _dptr(donor, torch.int32, n), _dptr(ref, torch.float64, 3 * n)))
+
+    def donor_search_noalloc(self, grid_id, pose, points, n, donor, ref):
+        """oc_donor_search_noalloc: the donor search on the library's fixed
+        scratch array (no allocation; at most noalloc_max_points() points)."""
+        import torch
+        _, pp = _pose(pose)
+        _check(load().oc_donor_search_noalloc(self._h, grid_id, pp,
+                                              _dptr(points, torch.float64, 3 * n) if n else None, int(n),
+                                              _dptr(donor, torch.int32, n) if n else None,
+                                              _dptr(ref, torch.float64, 3 * n) if n else None))
+
+    @staticmethod
+    def noalloc_max_points():
+        v = C.c_int64(0)
+        _check(load().oc_noalloc_max_points(C.byref(v)))
+        return v.value
 
     # ------------------------------------------------------------- timing ---
     def timing(self, enable):
