@@ -379,25 +379,11 @@ def run_dimpled(a):
         roof_filter["copy_ceiling_gbs"] = ceil
         roof_filter["frac_of_copy_ceiling"] = roof_filter["achieved"] / ceil
     if a.serve_requests > 0:
-        # the serving stream, shortened: one rate, Poisson arrivals over the
-        # four grid sets (this dimpled system is one of them)
-        log("serving stream: %d requests at %g req/s" % (a.serve_requests, a.serve_rate))
-        ss.close()
-        systems, cases = serving_systems(ctx, dimpled=(case, system))
-        res, srv = serve_stream(ctx, systems, cases, [a.serve_rate], a.serve_requests, a.budget_gb)
-        sv = {r["mode"]: r for r in res}
-        out["serving"] = dict(rate_per_s=a.serve_rate, requests=a.serve_requests,
-                              sets="tiny 16^3, dimpled 128^3, spinning ball at a random step, two-body 160^3 at a "
-                                   "random step",
-                              served=dict(p50_ms=sv["served"]["latency_ms"]["p50"],
-                                          p99_ms=sv["served"]["latency_ms"]["p99"],
-                                          throughput_per_s=sv["served"]["throughput"], slots=sv["served"]["slots"]),
-                              one_at_a_time=dict(p50_ms=sv["one_at_a_time"]["latency_ms"]["p50"],
-                                                 p99_ms=sv["one_at_a_time"]["latency_ms"]["p99"],
-                                                 throughput_per_s=sv["one_at_a_time"]["throughput"]),
-                              hbm_used_gb=srv.used_bytes() / (1 << 30))
-        for sl in list(srv.slots):
-            srv._release(sl)
+        # the serving stream, shortened to one rate: run as a child process
+        # (its own context and grid sets), so that a failure there leaves
+        # this measurement standing
+        log("serving stream: %d requests at %g req/s (child process)" % (a.serve_requests, a.serve_rate))
+        out["serving"] = serve_child(a)
     if not a.no_cpu_baseline:
         log("oracle baseline on the host")
         cb = cpu_baseline(case, a.cpu_sample)
@@ -976,6 +962,30 @@ def serve_stream(ctx, systems, cases, rates, n_requests, budget_gb, seed=7663):
                                 latency_ms=_percentiles(lat), mean_ms=1e3 * float(np.mean(lat)),
                                 slots=len(srv.slots) if mode == "served" else 1))
     return results, srv
+
+
+def serve_child(a):
+    """bench.py --workload serve at one rate in a child process; its results,
+    or the child's failure."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", "serve", "--rates", "%g" % a.serve_rate,
+           "--requests", str(a.serve_requests), "--budget-gb", "%g" % a.budget_gb]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=600)
+    for line in r.stderr.splitlines():
+        print(line, file=sys.stderr, flush=True)
+    lines = [x for x in r.stdout.splitlines() if x.startswith("{")]
+    if r.returncode != 0 or not lines:
+        return dict(error="serving child exited with status %d" % r.returncode)
+    res = json.loads(lines[-1])
+    sv = {x["mode"]: x for x in res["rates"]}
+    return dict(rate_per_s=a.serve_rate, requests=a.serve_requests,
+                sets="tiny 16^3, dimpled 128^3, spinning ball at a random step, two-body 160^3 at a random step",
+                served=dict(p50_ms=sv["served"]["latency_ms"]["p50"], p99_ms=sv["served"]["latency_ms"]["p99"],
+                            throughput_per_s=sv["served"]["throughput"], slots=sv["served"]["slots"]),
+                one_at_a_time=dict(p50_ms=sv["one_at_a_time"]["latency_ms"]["p50"],
+                                   p99_ms=sv["one_at_a_time"]["latency_ms"]["p99"],
+                                   throughput_per_s=sv["one_at_a_time"]["throughput"]),
+                hbm_used_gb=res.get("hbm_used_gb"))
 
 
 def run_serve(a):
