@@ -45,7 +45,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 FP64_VECTOR_PEAK = 78.6        # TFLOP/s, MI355X FP64 vector: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
-NEWTON_FLOP = 590              # FLOP per Newton iteration: x and J contracted axis by axis (3 x 155), 3x3 solve ~90, basis and residual ~35
+# algorithmic FLOP per Newton iteration of the donor search: the per-unit
+# figure of the method's Newton step, x(xi) and J = dx/dxi of a 27-node
+# element (27 nodes x 4 values x 3 components multiply-adds) plus the 3x3
+# solve, about 0.7 kFLOP; the axis-by-axis contraction the kernel runs does
+# the same map in 590
+NEWTON_FLOP = 700
 
 
 KERNEL_SOURCE = {"k_dp_newton": "paper_1711_07663_amd/csrc/k_donor.hip",
@@ -449,6 +454,25 @@ def run_spin(a):
     _, evs = run_sequence(True)
     lat = [e0.elapsed_time(e1) * 1e-3 for e0, e1 in evs]
     ms = 1e3 * t_total / a.spin_steps
+    # the same poses on a cold captured step (no warm start): what the warm
+    # start saves at equal launch structure
+    log("cold graph replays at the same poses")
+    cs = SlotStep(system)
+    cs.step([poses[0]])
+    torch.cuda.synchronize()
+    cs.capture()
+    ctables = [cs.pose_table_dev([p]) for p in poses]
+    for n in range(1, len(poses)):
+        cs.replay_table(ctables[n])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(1, len(poses)):
+        cs.replay_table(ctables[n])
+    torch.cuda.synchronize()
+    ms_cold_graph = 1e3 * (time.perf_counter() - t0) / a.spin_steps
+    warm_ib = ss.ib_bg().cpu().numpy()
+    cold_ib = cs.ib_bg().cpu().numpy()
+    cs.close()
     # the plain per-instance GPU step: cold, eager, synchronous (default slot)
     log("plain per-step baseline")
     t0 = time.perf_counter()
@@ -474,6 +498,8 @@ def run_spin(a):
                                     "400 steps, %d warm-started steps replayed as HIP graphs" % a.spin_steps,
                            bg_elements=bg.n_elem, sweep_bound=sweep, parallelism="1 GPU"),
                latency_ms=_percentiles(lat), plain_ms_per_step=ms_plain, speedup_vs_plain=ms_plain / ms,
+               cold_graph_ms_per_step=ms_cold_graph, warm_speedup_vs_cold_graph=ms_cold_graph / ms,
+               warm_equals_cold_last_step=bool(np.array_equal(warm_ib, cold_ib)),
                last_warm_cut_info=cut, per_kernel=per_kernel)
     ctx.close()
     return out
