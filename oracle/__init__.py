@@ -473,3 +473,187 @@ def cut_heuristic(grid, surfaces, poses, kinds=None, nf1=16, nf2=4, nbr=None, th
     if nbr is None:
         nbr = face_neighbors(grid.conn)
     return mark_fringe(hole, nbr, grid.face_tags)
+
+
+# ---------------------------------------------------------------------------
+# refined (curved-face) cut
+# ---------------------------------------------------------------------------
+#
+# The paper cuts with the node-lattice triangulation of every curved face
+# (Sec. 4.2, Fig. quadsplit) and notes the linearisation error.  The refined
+# cut of level k applies the same exact predicate to the curved geometry
+# restricted to a finer lattice: every quadratic surface face is split into
+# k x k quadratic sub-faces and every element into k^3 quadratic
+# sub-elements, each the exact restriction of the isoparametric map
+# (eq. reftophys) to a sub-square / sub-cube of the reference domain, so
+# their 9 / 27 nodes are the map evaluated on the sub-lattice.  An element is
+# a hole when any of its sub-elements is one (a closed surface that meets
+# the element meets one of its pieces, and one that does not lies on the side
+# of the element's first node, which is its first sub-element's first node).
+# Level 1 is the lattice cut; the triangulations of level k lie within
+# (M_uu + M_uv + M_vv) / k^2 of the curved faces (refinement_bound), so the
+# predicate converges to the one on the curved faces.
+
+class _Mesh:
+    """Plain container of a grid (nodes, conn, face_tags) or a surface
+    (nodes, conn) for the refined cut."""
+
+    def __init__(self, nodes, conn, face_tags=None):
+        self.nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+        self.conn = np.ascontiguousarray(conn, dtype=np.int32)
+        self.face_tags = face_tags
+
+    @property
+    def n_elem(self):
+        return int(self.conn.shape[0])
+
+    @property
+    def n_face(self):
+        return int(self.conn.shape[0])
+
+
+def _lag2(s):
+    """Equispaced quadratic Lagrange values on the nodes -1, 0, 1 (eq.
+    reftophys with K = 2), shape (..., 3)."""
+    s = np.asarray(s, dtype=np.float64)
+    return np.stack([0.5 * s * (s - 1.0), 1.0 - s * s, 0.5 * s * (s + 1.0)], axis=-1)
+
+
+def _sub_params(k):
+    """Reference coordinates of the level-k node lattice, -1 + I / k."""
+    return -1.0 + np.arange(2 * k + 1, dtype=np.float64) / k
+
+
+def refine_surface(surf, k):
+    """The k x k quadratic sub-faces of every face of a surface of 9-node
+    quads (node order a + 3b), as a surface of n_face k^2 faces.  Points on a
+    face's boundary are evaluated from that edge's three nodes taken from the
+    end with the lower node id, so faces sharing an edge share its refined
+    points bit for bit (the refined surface stays watertight)."""
+    if k == 1:
+        return surf
+    X = np.asarray(surf.nodes, dtype=np.float64)
+    conn = np.asarray(surf.conn)
+    N = 2 * k
+    t = _sub_params(k)
+    L = _lag2(t)                                      # (N+1, 3)
+    nf = conn.shape[0]
+    P = X[conn].reshape(nf, 3, 3, 3)                  # [f, b, a, xyz]  (node a + 3b)
+    # interior: x(u_I, v_J) = sum_ab X_ab l_a(u_I) l_b(v_J)
+    G = np.einsum("fbax,ia,jb->fijx", P, L, L)        # (nf, N+1, N+1, 3) indexed [I (u), J (v)]
+    # edges, canonically: nodes (n0, n1, n2) along the edge; parameter from
+    # the lower-id end
+    def edge(ids, params_up):
+        n0, n1, n2 = ids
+        flip = n0 > n2
+        s = np.where(flip[:, None], -params_up[None, :], params_up[None, :])
+        lo = np.where(flip, n2, n0)
+        hi = np.where(flip, n0, n2)
+        l = _lag2(s)                                  # (nf, N+1, 3)
+        return (X[lo][:, None, :] * l[:, :, 0:1] + X[n1][:, None, :] * l[:, :, 1:2]) + X[hi][:, None, :] * l[:, :, 2:3]
+    G[:, :, 0, :] = edge((conn[:, 0], conn[:, 1], conn[:, 2]), t)          # v = -1, a = 0..2
+    G[:, :, N, :] = edge((conn[:, 6], conn[:, 7], conn[:, 8]), t)          # v = +1
+    G[:, 0, :, :] = edge((conn[:, 0], conn[:, 3], conn[:, 6]), t)          # u = -1, b = 0..2
+    G[:, N, :, :] = edge((conn[:, 2], conn[:, 5], conn[:, 8]), t)          # u = +1
+    nodes = []
+    for bj in range(k):
+        for bi in range(k):
+            sub = G[:, 2 * bi:2 * bi + 3, 2 * bj:2 * bj + 3, :]            # [f, a, b]
+            nodes.append(np.transpose(sub, (0, 2, 1, 3)).reshape(nf, 9, 3))  # node a + 3b
+    nodes = np.stack(nodes, axis=1).reshape(nf * k * k, 9, 3)
+    return _Mesh(nodes.reshape(-1, 3), np.arange(nf * k * k * 9, dtype=np.int32).reshape(-1, 9))
+
+
+def refine_elements(grid, elems, k):
+    """The k^3 quadratic sub-elements of each listed element (27 nodes
+    a + 3b + 9c each, the element's map on a sub-cube), as a grid of
+    len(elems) k^3 elements, element-major then sub-element (i + k j + k^2 l)."""
+    X = np.asarray(grid.nodes, dtype=np.float64)[np.asarray(grid.conn)[np.asarray(elems)]]   # (n, 27, 3)
+    n = X.shape[0]
+    L = _lag2(_sub_params(k))
+    Xc = X.reshape(n, 3, 3, 3, 3)                     # [e, c, b, a, xyz]
+    G = np.einsum("ecbax,ia,jb,lc->eijlx", Xc, L, L, L)   # (n, N+1, N+1, N+1, 3) [I, J, L]
+    subs = []
+    for bl in range(k):
+        for bj in range(k):
+            for bi in range(k):
+                s = G[:, 2 * bi:2 * bi + 3, 2 * bj:2 * bj + 3, 2 * bl:2 * bl + 3, :]   # [e, a, b, c]
+                subs.append(np.transpose(s, (0, 3, 2, 1, 4)).reshape(n, 27, 3))       # a + 3b + 9c
+    nodes = np.stack(subs, axis=1).reshape(n * k ** 3 * 27, 3)
+    return _Mesh(nodes, np.arange(n * k ** 3 * 27, dtype=np.int32).reshape(-1, 27))
+
+
+def _control_boxes(grid, elems):
+    """Boxes of the Bernstein control nets of the listed elements (they hold
+    the curved elements: convex-hull property)."""
+    X = np.asarray(grid.nodes, dtype=np.float64)[np.asarray(grid.conn)[np.asarray(elems)]]
+    B = X.reshape(-1, 3, 3, 3, 3).copy()              # [e, c, b, a, xyz]
+    for ax in (3, 2, 1):
+        idx = [slice(None)] * 5
+        mid, lo_, hi_ = list(idx), list(idx), list(idx)
+        mid[ax], lo_[ax], hi_[ax] = 1, 0, 2
+        B[tuple(mid)] = 2.0 * B[tuple(mid)] - 0.5 * (B[tuple(lo_)] + B[tuple(hi_)])
+    B = B.reshape(-1, 27, 3)
+    return B.min(axis=1), B.max(axis=1)
+
+
+def cut_surface_refined(grid, surf, k, pose=IDENTITY, kind=SURF_WALL, threads=0, pad=1e-4, sub_status=False):
+    """Per-surface status (0 hole / 1 field) of every element of grid under
+    the refined cut of level k.  Elements whose control-net box stays farther
+    than pad from the posed refined surface's box are field (their curved
+    extent is away from the surface, their first node outside it)."""
+    sv = refine_surface(surf, k)
+    R = np.asarray(pose[:9], dtype=np.float64).reshape(3, 3)
+    Y = sv.nodes @ R.T + np.asarray(pose[9:12], dtype=np.float64)
+    slo, shi = Y.min(axis=0) - pad, Y.max(axis=0) + pad
+    n = grid.conn.shape[0]
+    status = np.ones(n, dtype=np.int8)
+    band = []
+    for s0 in range(0, n, 1 << 16):
+        ids = np.arange(s0, min(n, s0 + (1 << 16)))
+        lo, hi = _control_boxes(grid, ids)
+        band.append(ids[np.all(hi >= slo, axis=1) & np.all(lo <= shi, axis=1)])
+    band = np.concatenate(band)
+    if band.size == 0:
+        return (status, band, np.zeros(0, dtype=np.int8)) if sub_status else status
+    sub = refine_elements(grid, band, k)
+    st = cut_surface(sub, sv, pose, kind, threads=threads)
+    hole = (st.reshape(band.size, k ** 3) == 0).any(axis=1)
+    status[band[hole]] = 0
+    return (status, band, st) if sub_status else status
+
+
+def cut_refined(grid, surfaces, poses, k, kinds=None, nbr=None, threads=0):
+    """iblank of grid under the refined cut of level k: union of holes over
+    the surfaces, then one fringe layer."""
+    if kinds is None:
+        kinds = [SURF_WALL] * len(surfaces)
+    hole = np.zeros(grid.conn.shape[0], dtype=bool)
+    for s, p, kd in zip(surfaces, poses, kinds):
+        hole |= cut_surface_refined(grid, s, k, p, kd, threads=threads) == 0
+    if nbr is None:
+        nbr = face_neighbors(grid.conn)
+    return mark_fringe(hole, nbr, grid.face_tags)
+
+
+def refinement_bound(nodes9, k):
+    """Bound on the distance between a quadratic patch (9 nodes, a + 3b, on
+    [-1,1]^2) and its level-k lattice triangulation (2k x 2k sub-quads of
+    parameter side h = 1/k, two triangles each): on a triangle, linear
+    interpolation misses f by at most M R^2 / 2 with R the circumradius
+    (h / sqrt 2) and M a bound on |D^2 x [d, d]| for unit d, here
+    |x_uu| + |x_uv| + |x_vv| maximised over the patch: x_uu and x_vv are
+    quadratics in one variable (bounded by their Bernstein control points),
+    x_uv is bilinear (bounded at the corners).  Returns M h^2 / 4."""
+    P = np.asarray(nodes9, dtype=np.float64).reshape(3, 3, 3)     # [b, a, xyz]
+    d2 = np.array([1.0, -2.0, 1.0])
+    def bern_max(c):                                               # c: (3, 3) values at -1, 0, 1
+        b = np.stack([c[0], 2.0 * c[1] - 0.5 * (c[0] + c[2]), c[2]])
+        return np.linalg.norm(b, axis=1).max()
+    xuu = np.einsum("bax,a->bx", P, d2)                            # x_uu at v = -1, 0, 1
+    xvv = np.einsum("bax,b->ax", P, d2)
+    dl = lambda s: np.array([s - 0.5, -2.0 * s, s + 0.5])
+    m_uv = max(np.linalg.norm(np.einsum("bax,a,b->x", P, dl(u), dl(v))) for u in (-1.0, 1.0) for v in (-1.0, 1.0))
+    M = bern_max(xuu) + m_uv + bern_max(xvv)
+    h = 1.0 / k
+    return M * h * h / 4.0
