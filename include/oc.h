@@ -178,6 +178,24 @@ oc_status oc_sweep_bound(oc_ctx *ctx, int32_t surf_id, const double pose_a[12], 
 oc_status oc_cut_filtered(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
                           int32_t nf1, int32_t nf2, int8_t *iblank_out, int64_t *n_listed);
 
+/* The cut with the curved faces resolved to level k (Sec. 4.2, the closing
+ * paragraph on linearising the curved faces): every surface face is split
+ * into k x k quadratic sub-faces (the face map of eq. reftophys on the
+ * sub-squares of [-1,1]^2, points on a face edge evaluated from the edge's
+ * lower-id node so neighbouring faces share them) and every element whose
+ * control-net box meets the refined surface's face boxes into k^3 quadratic
+ * sub-elements; each sub-element is cut as an element is by oc_cut, and an
+ * element is a hole when one of its sub-elements is.  The triangulations of
+ * level k lie within M / (4 k^2) of the curved faces (M bounds the second
+ * derivatives of the face map); k = 1 is oc_cut_multi.  Union of holes
+ * over the n_surf surfaces, then one fringe layer.  poses: host FP64
+ * [n_surf*12]; 1 <= k <= 8; iblank_out device int8 [n_elem], 4-byte
+ * aligned.  Synchronises; scratch on the context grows with k^3 times the
+ * near elements (81 doubles each).  *n_near (may be NULL) receives the
+ * number of (surface, element) items refined. */
+oc_status oc_cut_refined(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
+                         int32_t k, int8_t *iblank_out, int64_t *n_near);
+
 oc_status oc_last_cut_info(oc_ctx *ctx, oc_cut_info *info);
 
 /* Blanking of one time step of a moving grid, with unblanking (Sec. 3,

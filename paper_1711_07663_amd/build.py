@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liboc.so")
 SOURCES = ["oc_api.hip", "k_cut.hip", "k_donor.hip", "k_scan.hip", "k_unblank.hip", "k_ab.hip", "k_heur.hip",
-           "oc_service.hip"]
+           "oc_service.hip", "k_refined.hip"]
 ARCH = os.environ.get("OC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -1056,8 +1056,8 @@ __global__ __launch_bounds__(kThreads) void k_fringe(const CutInst *__restrict__
         const int e = item_elem(it);
         const CutInst &c = I[item_cut(it)];
         int8_t *iblank = c.iblank;
-        if (iblank[e] != OC_HOLE) continue;
         const int32_t *nbr = c.nbr;
+        if (!nbr || iblank[e] != OC_HOLE) continue;   // no neighbours: loose elements
         for (int f = 0; f < 6; ++f) {
             const int q = nbr[(int64_t)e * 6 + f];
             if (q >= 0 && iblank[q] != OC_HOLE) iblank[q] = OC_FRINGE;

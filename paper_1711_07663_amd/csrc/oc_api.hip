@@ -902,6 +902,32 @@ oc_status oc_cut_filtered(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids,
     return filtered_cut_run(sl, *g, ss.data(), sl->poses, n_surf, nf1, nf2, iblank_out, n_listed);
 }
 
+oc_status oc_cut_refined(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
+                         int32_t k, int8_t *iblank_out, int64_t *n_near)
+{
+    if (!ctx || !iblank_out || n_surf < 1 || n_surf > kPoseSlots - 2 || !surf_ids || !poses || k < 1 || k > 8) {
+        set_error("oc_cut_refined: invalid arguments (1 <= k <= 8, at least one surface)");
+        return OC_EINVAL;
+    }
+    if (reinterpret_cast<uintptr_t>(iblank_out) % 4) {
+        set_error("oc_cut_refined: iblank_out must be 4-byte aligned");
+        return OC_EINVAL;
+    }
+    for (int i = 0; i < n_surf; ++i)
+        if (!pose_finite(poses + 12 * i)) {
+            set_error("oc_cut_refined: non-finite pose");
+            return OC_EINVAL;
+        }
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
+    oc_slot *sl = ctx->dflt;
+    OC_TRY(set_poses(sl, 0, poses, n_surf));
+    return refined_cut_run(sl, *g, ss.data(), sl->poses, n_surf, k, iblank_out, n_near);
+}
+
 // ------------------------------------------------- artificial boundary --
 static oc_status get_nodes1d(const double *z, int32_t m, Nodes1D *out, const char *who)
 {

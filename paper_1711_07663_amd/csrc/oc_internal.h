@@ -175,6 +175,8 @@ struct oc_slot {
     uint32_t *ab_mask = nullptr;       // [list_cap] bytes: AB face bits per element, zero between calls
     void *hx_buf = nullptr;            // filtered-cut arena (grown on demand)
     size_t hx_cap = 0;
+    void *rf_buf[2] = {nullptr, nullptr};   // refined-cut arenas (grown on demand)
+    size_t rf_cap[2] = {0, 0};
     oc::CutCounters *counters = nullptr;
     oc::DonorCounters *dcounters = nullptr;
     oc::Pose *poses = nullptr;         // [kPoseSlots] device
@@ -370,6 +372,12 @@ oc_status noalloc_init(int device);
 int64_t noalloc_max_points();
 oc_status donor_noalloc_run(oc_ctx *ctx, Grid &g, const double *pose_host, const double *pts, int64_t n,
                             int32_t *donor, double *ref);
+// the refined cut of level k (the curved faces split k x k, the near
+// elements k^3 times) of g by the surfaces at poses_dev into iblank;
+// synchronises; *n_near (may be null) receives the number of near
+// (surface, element) items refined
+oc_status refined_cut_run(oc_slot *sl, Grid &g, Surf *const *surfs, const Pose *poses_dev, int n_surf, int k,
+                          int8_t *iblank, int64_t *n_near);
 // donor search of min(*n_dev, cap) points (n_dev may be null: cap points)
 oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pts, int64_t cap, const int32_t *n_dev,
                     int32_t *donor, double *ref);

@@ -34,7 +34,8 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_cut_warm", "oc_sweep_bound", "oc_slot_cut_warm", "oc_cut_batch", "oc_slot_cut_batch",
            "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points", "oc_ab_faces", "oc_face_points",
            "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered", "oc_slot_unblank", "oc_slot_element_points",
-           "oc_submit", "oc_wait", "oc_service_info", "oc_donor_search_noalloc", "oc_noalloc_max_points"]
+           "oc_submit", "oc_wait", "oc_service_info", "oc_donor_search_noalloc", "oc_noalloc_max_points",
+           "oc_cut_refined"]
 
 
 class OcError(RuntimeError):
@@ -125,6 +126,7 @@ def load(path=LIB_PATH):
         "oc_slot_face_points": ([vp, C.c_int32, vp, vp, vp, C.c_int64, dp, C.c_int32, vp, C.c_int64, vp, vp]),
         "oc_slot_interp_weights": ([vp, vp, vp, vp, C.c_int64, dp, C.c_int32, vp]),
         "oc_cut_filtered": ([vp, C.c_int32, i32p, dp, C.c_int32, C.c_int32, C.c_int32, vp, i64p]),
+        "oc_cut_refined": ([vp, C.c_int32, i32p, dp, C.c_int32, C.c_int32, vp, i64p]),
         "oc_slot_unblank": ([vp, C.c_int32, i32p, C.c_int32, vp, vp, vp, vp, C.c_int64, vp]),
         "oc_slot_element_points": ([vp, C.c_int32, vp, vp, vp, C.c_int64, vp, vp, vp]),
     }
@@ -344,6 +346,18 @@ class Context:
         n = C.c_int64(0)
         _check(load().oc_cut_filtered(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
                                       int(nf1), int(nf2), _dptr(iblank, torch.int8, self.grids[grid_id]), C.byref(n)))
+        return n.value
+
+    def cut_refined(self, grid_id, surf_ids, poses, iblank, k):
+        """The cut with the curved faces resolved to level k
+        (oc_cut_refined); returns the number of (surface, element) items
+        refined."""
+        import torch
+        ids = np.ascontiguousarray(surf_ids, dtype=np.int32)
+        pa, pp = _pose(np.asarray(poses, dtype=np.float64).reshape(-1))
+        n = C.c_int64(0)
+        _check(load().oc_cut_refined(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
+                                     int(k), _dptr(iblank, torch.int8, self.grids[grid_id]), C.byref(n)))
         return n.value
 
     def ab_faces(self, grid_id, iblank, faces):
