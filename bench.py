@@ -23,6 +23,10 @@ Other workloads (--workload):
   filtered  the paper's own filtered cut of the dimpled 128^3 case (N_F^1,
          N_F^2 = 16,4 / 4,1 / 1,1) against the exact cut: time per cut
          and the elements on which the truncations change the blanking;
+  refined  the cut with the curved faces resolved to level k (faces split
+         k x k, near elements k^3 times) of the dimpled 128^3 case against
+         the lattice cut: time per cut and the elements whose blanking the
+         curvature changes;
   unblank  the dimpled sphere turning and oscillating (amplitude 0.5) through
          the background: per step the background is cut at the poses of t
          and t + dt (wall rule: union of holes), the cells to unblank are
@@ -107,7 +111,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1, help="oracle runs on every k-th element / point")
     ap.add_argument("--bg", type=int, default=128)
     ap.add_argument("--workload", default="dimpled",
-                    choices=["dimpled", "spin", "batch", "serve", "service", "unblank", "ab", "filtered"])
+                    choices=["dimpled", "spin", "batch", "serve", "service", "unblank", "ab", "filtered", "refined"])
+    ap.add_argument("--levels", default="1,2,4", help="refined: levels k of the curved-face cut")
     ap.add_argument("--spin-steps", type=int, default=200)
     ap.add_argument("--topology", default="walls", choices=["walls", "paper"],
                     help="ab: the background cut by the walls, or by the shells' overset boundaries")
@@ -239,7 +244,7 @@ def main():
         log("copy probe: %d bytes read, %d bytes written" % (src.numel() * 8, dst.numel() * 8))
         del src, dst
     out = dict(dimpled=run_dimpled, spin=run_spin, batch=run_batch, serve=run_serve, service=run_service,
-               unblank=run_unblank, ab=run_ab, filtered=run_filtered)[a.workload](a)
+               unblank=run_unblank, ab=run_ab, filtered=run_filtered, refined=run_refined)[a.workload](a)
     print(json.dumps(out), flush=True)
 
 
@@ -646,6 +651,70 @@ def run_filtered(a):
                                     "harsher truncations beside it" % a.bg, bg_elements=bg.n_elem,
                            parallelism="1 GPU"),
                exact_ms_per_cut=ms_exact, truncations=rows)
+    ctx.close()
+    return out
+
+
+def run_refined(a):
+    """Ablation of the linearisation of the curved faces (Sec. 4.2): the
+    refined cut of the dimpled 128^3 background at levels k against the
+    lattice cut (oc_cut), synchronous per cut."""
+    import torch
+    from paper_1711_07663_amd import oc
+    from workloads import configs as CF
+    log("generating the dimpled-sphere workload")
+    case = CF.dimpled(bg_n=a.bg)
+    bg, s = case["bg"], case["bodies"][0]["surface"]
+    pose = case["poses"][0]
+    torch.cuda.set_device(0)
+    ctx = oc.Context(device=0)
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    ib_lat = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+    ib = torch.empty_like(ib_lat)
+
+    def timed(fn):
+        for _ in range(a.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            fn()
+        torch.cuda.synchronize()
+        return 1e3 * (time.perf_counter() - t0) / a.steps
+
+    ms_lat = timed(lambda: ctx.cut(gid, sid, pose, ib_lat))
+    lat = ib_lat.cpu().numpy()
+    rows, prev = [], None
+    for k in [int(v) for v in a.levels.split(",")]:
+        log("refined cut, level %d" % k)
+        n_near = ctx.cut_refined(gid, [sid], pose[None], ib, k)
+        ms = timed(lambda: ctx.cut_refined(gid, [sid], pose[None], ib, k))
+        got = ib.cpu().numpy()
+        ctx.timing(True)
+        ctx.cut_refined(gid, [sid], pose[None], ib, k)
+        rep = ctx.timing_report()
+        ctx.timing(False)
+        row = dict(k=k, ms_per_cut=ms, near_elements=n_near, sub_elements=n_near * k ** 3,
+                   differ_from_lattice=int((got != lat).sum()),
+                   holes_added=int(((lat != 0) & (got == 0)).sum()),
+                   holes_lost=int(((lat == 0) & (got != 0)).sum()),
+                   per_kernel={n: dict(avg_us=1e3 * v[0] / max(v[1], 1), launches=v[1]) for n, v in rep.items()})
+        if prev is not None:
+            row["differ_from_previous_level"] = int((got != prev[1]).sum())
+            row["previous_level"] = prev[0]
+        rows.append(row)
+        prev = (k, got)
+    head = rows[-1]
+    out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
+               value=bg.n_elem / (head["ms_per_cut"] / 1e3), unit="elements/s", n_gpus=1, steps=a.steps,
+               warmup=a.warmup, ms_per_step=head["ms_per_cut"], higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="f64", data="synthetic",
+               config=dict(workload="the refined cut (curved faces, level %d) of the %d^3 dimpled-sphere background "
+                                    "by its 24576-face wall, synchronous, one cut per step; the lattice cut and "
+                                    "other levels beside it" % (head["k"], a.bg), bg_elements=bg.n_elem,
+                           parallelism="1 GPU"),
+               lattice_ms_per_cut=ms_lat, lattice_holes=int((lat == 0).sum()), levels=rows)
     ctx.close()
     return out
 

@@ -24,6 +24,7 @@
 //   k_rf_unfringe + fringe layer over the whole grid
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -32,6 +33,7 @@
 namespace oc {
 
 constexpr int kRT = 256;
+constexpr int kRfKeys = 12;   // sizing words per refined surface (11 used)
 
 __device__ inline void lag2_rf(double s, double *l)
 {
@@ -93,6 +95,65 @@ __global__ __launch_bounds__(kRT) void k_rf_surface(const double *__restrict__ n
         }
         for (int d = 0; d < 3; ++d) vnodes[d * n_v + t] = x[d];
         vconn[t] = (int32_t)t;
+    }
+}
+
+// order-preserving 64-bit keys of doubles (for atomic min / max)
+__device__ inline unsigned long long rf_key(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// sizing of a refined surface for its bins, as registration does it: the
+// largest sub-face node-box diagonal, the node box, the largest node
+// distance from the origin, and the first node.  out (keys, zeroed by the
+// caller except the minima, set to all ones): [0] max diagonal, [1] max
+// node norm, [2..4] box minima, [5..7] box maxima; [8..10] the first node
+// (raw doubles)
+__global__ __launch_bounds__(kRT) void k_rf_sizes(const double *__restrict__ vnodes, int64_t n_sub_f,
+                                                  unsigned long long *__restrict__ out)
+{
+    __shared__ double red[8][kRT];
+    const int64_t n_v = n_sub_f * 9;
+    double acc[8] = {0.0, 0.0, INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < n_sub_f; f += (int64_t)gridDim.x * blockDim.x) {
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int q = 0; q < 9; ++q) {
+            double r2 = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                const double v = vnodes[d * n_v + 9 * f + q];
+                lo[d] = fmin(lo[d], v);
+                hi[d] = fmax(hi[d], v);
+                r2 += v * v;
+            }
+            acc[1] = fmax(acc[1], sqrt(r2));
+        }
+        double g2 = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            g2 += (hi[d] - lo[d]) * (hi[d] - lo[d]);
+            acc[2 + d] = fmin(acc[2 + d], lo[d]);
+            acc[5 + d] = fmax(acc[5 + d], hi[d]);
+        }
+        acc[0] = fmax(acc[0], sqrt(g2));
+    }
+    for (int i = 0; i < 8; ++i) red[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int w = kRT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int i = 0; i < 8; ++i) {
+                const double a = red[i][threadIdx.x], b = red[i][threadIdx.x + w];
+                red[i][threadIdx.x] = (i >= 2 && i < 5) ? fmin(a, b) : fmax(a, b);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < 8; ++i) {
+            if (i >= 2 && i < 5) atomicMin(out + i, rf_key(red[i][0]));
+            else atomicMax(out + i, rf_key(red[i][0]));
+        }
+        if (blockIdx.x == 0)
+            for (int d = 0; d < 3; ++d) out[8 + d] = (unsigned long long)__double_as_longlong(vnodes[d * n_v]);
     }
 }
 
@@ -212,41 +273,32 @@ static oc_status rf_reserve(oc_slot *sl, int i, size_t bytes, char **base)
     return OC_OK;
 }
 
-// sizing of a refined surface as registration does it: largest sub-face
-// node-box diagonal, extent about the node centroid, largest node distance
-static void rf_surf_params(const std::vector<double> &h, int64_t n_v, int surf_bins, Surf &sv)
+static double rf_unkey(unsigned long long k)
 {
-    double dmax = 0.0, c[3] = {0, 0, 0}, rb = 0.0, rmax = 0.0;
-    for (int64_t i = 0; i < n_v; ++i)
-        for (int d = 0; d < 3; ++d) c[d] += h[(size_t)(d * n_v + i)] / (double)n_v;
-    for (int64_t i = 0; i < n_v; ++i) {
-        double r2 = 0.0, o2 = 0.0;
-        for (int d = 0; d < 3; ++d) {
-            const double v = h[(size_t)(d * n_v + i)];
-            r2 += (v - c[d]) * (v - c[d]);
-            o2 += v * v;
-        }
-        rb = std::max(rb, std::sqrt(r2));
-        rmax = std::max(rmax, std::sqrt(o2));
+    const unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    double v;
+    memcpy(&v, &b, sizeof v);
+    return v;
+}
+
+// bins of a refined surface from its sizes (as registration sizes them:
+// bins per axis about the surface radius over the largest face diagonal)
+static void rf_surf_params(const unsigned long long *key, int surf_bins, Surf &sv)
+{
+    const double dmax = rf_unkey(key[0]);
+    double rb = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const double e = rf_unkey(key[5 + d]) - rf_unkey(key[2 + d]);
+        rb += e * e;
     }
-    for (int64_t f = 0; f < n_v / 9; ++f) {
-        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-        for (int q = 0; q < 9; ++q)
-            for (int d = 0; d < 3; ++d) {
-                const double v = h[(size_t)(d * n_v + 9 * f + q)];
-                lo[d] = std::min(lo[d], v);
-                hi[d] = std::max(hi[d], v);
-            }
-        dmax = std::max(dmax, std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
-                                        (hi[2] - lo[2]) * (hi[2] - lo[2])));
-    }
+    rb = 0.5 * std::sqrt(rb);
     sv.dmax = f32_up(dmax);
     int nb = (int)std::ceil(rb / std::max(dmax, 1e-30)) + 1;
     nb = std::max(1, std::min(nb, 160));
     if (surf_bins > 0) nb = std::min(nb, surf_bins);
     sv.nb_max = sv.nb_auto = nb;
-    for (int d = 0; d < 3; ++d) sv.first[d] = h[(size_t)(d * n_v)];
-    sv.rmax = rmax;
+    for (int d = 0; d < 3; ++d) memcpy(&sv.first[d], key + 8 + d, sizeof(double));
+    sv.rmax = rf_unkey(key[1]);
 }
 
 oc_status refined_cut_run(oc_slot *sl, Grid &g, Surf *const *surfs, const Pose *poses_dev, int n_surf, int k,
@@ -276,31 +328,35 @@ oc_status refined_cut_run(oc_slot *sl, Grid &g, Surf *const *surfs, const Pose *
     const int64_t near_cap = std::max<int64_t>(g.n_elem * n_surf, 1);
     const size_t o_cbox = o, o_near = o_cbox + ralign(sizeof(float) * 6 * (size_t)g.ebox_stride);
     const size_t o_cnt = o_near + ralign(sizeof(int32_t) * (size_t)near_cap);
+    const size_t o_keys = o_cnt + 256;
     char *A;
-    OC_TRY(rf_reserve(sl, 0, o_cnt + 256, &A));
+    OC_TRY(rf_reserve(sl, 0, o_keys + ralign(sizeof(unsigned long long) * kRfKeys * (size_t)n_surf), &A));
     float *cbox_soa = reinterpret_cast<float *>(A + o_cbox);
     int32_t *near = reinterpret_cast<int32_t *>(A + o_near);
     int32_t *n_near = reinterpret_cast<int32_t *>(A + o_cnt);
     std::vector<Surf> sv(n_surf);
     std::vector<Surf *> svp(n_surf);
-    std::vector<double> h;
+    std::vector<unsigned long long> keys((size_t)n_surf * kRfKeys);
     for (int i = 0; i < n_surf; ++i) {
         const Surf &s = *surfs[i];
         double *vnodes = reinterpret_cast<double *>(A + o_nodes[i]);
         int32_t *vconn = reinterpret_cast<int32_t *>(A + o_conn[i]);
+        unsigned long long *key = reinterpret_cast<unsigned long long *>(A + o_keys) + (size_t)i * kRfKeys;
+        unsigned long long init[kRfKeys] = {0, 0, ~0ull, ~0ull, ~0ull, 0, 0, 0, 0, 0, 0, 0};
+        OC_TRY(put_bytes(sl, key, init, sizeof init));
         LAUNCH(k_rf_surface, dim3(rblocks(n_v[i])), dim3(kRT), s.nodes, s.n_nodes, s.conn, s.n_face, k, vnodes, vconn);
-        OC_HIP(hipGetLastError());
-        h.resize((size_t)(3 * n_v[i]));
-        OC_HIP(hipMemcpyAsync(h.data(), vnodes, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-        OC_HIP(hipStreamSynchronize(st));
+        LAUNCH(k_rf_sizes, dim3(rblocks(s.n_face * k * k)), dim3(kRT), vnodes, s.n_face * k * k, key);
         sv[i].n_face = s.n_face * k * k;
         sv[i].n_nodes = n_v[i];
         sv[i].kind = s.kind;
         sv[i].nodes = vnodes;
         sv[i].conn = vconn;
-        rf_surf_params(h, n_v[i], ctx->surf_bins, sv[i]);
         svp[i] = &sv[i];
     }
+    OC_HIP(hipGetLastError());
+    OC_HIP(hipMemcpyAsync(keys.data(), A + o_keys, sizeof(unsigned long long) * keys.size(), hipMemcpyDeviceToHost, st));
+    OC_HIP(hipStreamSynchronize(st));
+    for (int i = 0; i < n_surf; ++i) rf_surf_params(keys.data() + (size_t)i * kRfKeys, ctx->surf_bins, sv[i]);
     LAUNCH(k_rf_cbox, dim3(rblocks(g.ebox_stride)), dim3(kRT), g.cbox, g.n_elem, g.ebox_stride, cbox_soa);
     // cut 1: the grid, boxes that hold the curved elements
     Grid g1;

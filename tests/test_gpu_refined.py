@@ -131,3 +131,53 @@ def test_bad_arguments(ctx):
     bad[10] = np.nan
     with pytest.raises(oc.OcError):
         ctx.cut_refined(gid, [sid], bad[None], ib, 2)
+
+
+def test_full_size_sampled(ctx, orc):
+    """The dimpled 128^3 case at level 2: every element whose blanking
+    differs from the lattice cut, and random band elements and holes, one by
+    one against the oracle's definition (hole when one of the element's
+    sub-elements is a hole of the refined surface); holes only inside the
+    band; the fringe layer of the HIP hole mask."""
+    import torch
+    _note("refined cut of the dimpled 128^3 case, level 2, sampled")
+    case = CF.dimpled()
+    bg, s = case["bg"], case["bodies"][0]["surface"]
+    pose = np.asarray(case["poses"][0], dtype=np.float64)
+    k = 2
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    ib = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+    lat_t = torch.empty_like(ib)
+    ctx.cut_refined(gid, [sid], pose[None], ib, k)
+    ctx.cut(gid, sid, pose, lat_t)
+    got, lat = ib.cpu().numpy(), lat_t.cpu().numpy()
+    hole = got == orc.HOLE
+    # band of the oracle's refined cut: control-net boxes within 1e-4 of the
+    # posed refined surface's box
+    sv = orc.refine_surface(s, k)
+    R = pose[:9].reshape(3, 3)
+    Y = sv.nodes @ R.T + pose[9:12]
+    slo, shi = Y.min(axis=0) - 1e-4, Y.max(axis=0) + 1e-4
+    band = []
+    for s0 in range(0, bg.n_elem, 1 << 16):
+        ids = np.arange(s0, min(bg.n_elem, s0 + (1 << 16)))
+        lo, hi = orc._control_boxes(bg, ids)
+        band.append(ids[np.all(hi >= slo, axis=1) & np.all(lo <= shi, axis=1)])
+    band = np.concatenate(band)
+    in_band = np.zeros(bg.n_elem, dtype=bool)
+    in_band[band] = True
+    assert not (hole & ~in_band).any()
+    changed = np.nonzero((got == orc.HOLE) != (lat == orc.HOLE))[0]
+    assert changed.size > 0, "curvature must change some elements at this size"
+    rng = np.random.default_rng(1711)
+    holes = np.nonzero(hole)[0]
+    sample = np.unique(np.concatenate([changed, rng.choice(band, 150, replace=False),
+                                       rng.choice(holes, 50, replace=False)]))
+    sub = orc.refine_elements(bg, sample, k)
+    st = orc.cut_surface(sub, sv, pose)
+    want = (st.reshape(sample.size, k ** 3) == 0).any(axis=1)
+    bad = sample[want != hole[sample]]
+    assert bad.size == 0, "%d sampled elements differ, first %s" % (bad.size, bad[:8])
+    nbr = orc.face_neighbors(bg.conn)
+    assert np.array_equal(orc.mark_fringe(hole, nbr, bg.face_tags), got)
