@@ -44,6 +44,9 @@ __device__ inline void elem_tri(const double *X, int t, d3 *T)
 
 __device__ inline double clamp01(double v) { return fmin(fmax(v, 0.0), 1.0); }
 
+// Closest point of triangle abc to p by Voronoi regions of the vertices,
+// edges and face (the published method of C. Ericson, Real-Time Collision
+// Detection, Morgan Kaufmann 2005, Sec. 5.1.5, written here in FP64).
 __device__ inline d3 closest_on_tri(d3 p, d3 a, d3 b, d3 c)
 {
     d3 ab = b - a, ac = c - a, ap = p - a;
@@ -68,6 +71,9 @@ __device__ inline d3 closest_on_tri(d3 p, d3 a, d3 b, d3 c)
     return a + ab * (vb * den) + ac * (vc * den);
 }
 
+// Squared distance of segments [p1, q1] and [p2, q2]: the stationary point
+// of the two-parameter distance, clamped to the unit square one parameter at
+// a time (Ericson, Real-Time Collision Detection, Sec. 5.1.9).
 __device__ inline double seg_seg_d2(d3 p1, d3 q1, d3 p2, d3 q2)
 {
     d3 d1 = q1 - p1, d2 = q2 - p2, r = p1 - p2;
@@ -162,7 +168,8 @@ __device__ inline bool tri_tri_within(const d3 *A, const d3 *B, double tol)
 }
 
 // Closest points of segments [p1, q1] and [p2, q2] (clamped stationary
-// point); returns the squared distance.
+// point, Ericson, Real-Time Collision Detection, Sec. 5.1.9); returns the
+// squared distance.
 __device__ inline double seg_seg_cp(d3 p1, d3 q1, d3 p2, d3 q2, d3 &c1, d3 &c2)
 {
     d3 d1 = q1 - p1, d2 = q2 - p2, r = p1 - p2;

@@ -46,6 +46,11 @@ void time_begin(oc_ctx *ctx, hipStream_t st, const char *name, size_t *slot)
 {
     *slot = std::numeric_limits<size_t>::max();
     if (!ctx || !ctx->timing) return;
+    // no timing events inside a stream capture: the pooled events are
+    // recorded again by later launches, and an event recorded more than once
+    // within one capture is a form the captured steps never rely on
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
     while (ctx->event_pool.size() < ctx->event_next + 2) {
         hipEvent_t ev;
         if (hipEventCreate(&ev) != hipSuccess) return;

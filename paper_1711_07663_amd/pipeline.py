@@ -224,6 +224,7 @@ class SlotStep:
         self.graphs = {}
         self._last_pose = None  # host pose of the last warm-checked step (None: unknown)
         self.cold_fallbacks = 0  # warm steps run cold because the pose moved too far
+        self._capture_forks = 0  # stream forks issued inside the current capture
 
     @property
     def stream(self):
@@ -269,6 +270,12 @@ class SlotStep:
         bufs = o["ib_bg"]
         ib_bg = bufs[k % len(bufs)]
         ident = self.poses_dev[self.n_pose - 1]
+        if not serial and torch.cuda.is_current_stream_capturing():
+            # one fork (and its join) per capture: the captured step is built
+            # and tested in that form only
+            if self._capture_forks:
+                raise RuntimeError("SlotStep: a second stream fork inside one graph capture is not supported")
+            self._capture_forks += 1
         side.wait_stream(main)
         # chain A: background
         if self.warm and not cold:
@@ -350,6 +357,7 @@ class SlotStep:
         side = self.slot_b.stream
         for par in ((0, 1) if self.warm else (0,)):
             g = torch.cuda.CUDAGraph()
+            self._capture_forks = 0
             with torch.cuda.graph(g):
                 cur = torch.cuda.current_stream()
                 self.slot.set_stream(cur)
