@@ -51,7 +51,8 @@ enum {
     OC_EBUDGET = -5,   /* the context's HBM budget would be exceeded */
     OC_EGEOM = -6,     /* invalid geometry (open or inverted surface, inverted element) */
     OC_ECAPACITY = -7, /* an output buffer is too small */
-    OC_ETIMEDOUT = -8  /* oc_wait: the request has not finished yet */
+    OC_ETIMEDOUT = -8, /* oc_wait: the request has not finished yet */
+    OC_ESTARTED = -9   /* oc_cancel: the request is already on the device or finished */
 };
 
 /* int8 blanking values (hole map values are not reused: hole 0, field 1,
@@ -310,6 +311,14 @@ oc_status oc_cut_batch(oc_ctx *ctx, const oc_cut_req *reqs, int32_t n_req);
 typedef oc_cut_req oc_request;
 oc_status oc_submit(oc_ctx *ctx, const oc_request *req, uint64_t *ticket);
 oc_status oc_wait(oc_ctx *ctx, uint64_t ticket, int32_t timeout_ms);
+
+/* Cancel a request of the cut service that has not been admitted yet: it is
+ * taken out of the queue, its ticket is forgotten (oc_wait then returns
+ * OC_ENOTFOUND) and its iblank_out is left untouched and free for reuse.
+ * OC_ESTARTED if the request is already on the device or has finished (its
+ * result must be retired with oc_wait), OC_ENOTFOUND for an unknown
+ * ticket.  Queued requests behind it are admitted as usual. */
+oc_status oc_cancel(oc_ctx *ctx, uint64_t ticket);
 
 typedef struct oc_service_stats {
     int32_t slots;        /* service slots held */

@@ -39,7 +39,8 @@ SURF_WALL, SURF_OVERSET = 0, 1
 TAG_OVERSET = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_LIB names another build of oracle.c to load (the sanitizer test's)
+_LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
@@ -54,6 +55,18 @@ def build(force=True):
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized(path):
+    """Compile oracle.c with AddressSanitizer and UndefinedBehaviorSanitizer
+    into path (a checking build for tests; loaded through ORACLE_LIB with the
+    ASan runtime preloaded)."""
+    src = os.path.join(_HERE, "oracle.c")
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", src,
+           "-o", path, "-lm"]
+    subprocess.run(cmd, check=True)
+    return path
 
 
 def lib():

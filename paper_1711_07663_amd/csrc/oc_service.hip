@@ -358,6 +358,34 @@ oc_status oc_wait(oc_ctx *ctx, uint64_t ticket, int32_t timeout_ms)
     }
 }
 
+oc_status oc_cancel(oc_ctx *ctx, uint64_t ticket)
+{
+    if (!ctx) {
+        set_error("oc_cancel: null context");
+        return OC_EINVAL;
+    }
+    OC_HIP(hipSetDevice(ctx->device));
+    Service *sv = ctx->service;
+    if (sv) {
+        // a request still queued is dropped before anything is admitted
+        for (auto it = sv->queue.begin(); it != sv->queue.end(); ++it)
+            if (it->ticket == ticket) {
+                (void)hipEventDestroy(it->after);
+                sv->queue.erase(it);
+                pump(ctx, *sv);
+                return OC_OK;
+            }
+        bool started = sv->done.count(ticket) > 0;
+        for (auto &s : sv->slots) started |= s.ticket == ticket;
+        if (started) {
+            set_error("oc_cancel: ticket " + std::to_string(ticket) + " has started; retire it with oc_wait");
+            return OC_ESTARTED;
+        }
+    }
+    set_error("oc_cancel: unknown ticket " + std::to_string(ticket));
+    return OC_ENOTFOUND;
+}
+
 oc_status oc_service_info(oc_ctx *ctx, oc_service_stats *info)
 {
     if (!ctx || !info) {

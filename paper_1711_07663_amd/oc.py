@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liboc.so")
 
 OC_OK, OC_EINVAL, OC_ENOMEM, OC_EDEVICE, OC_ENOTFOUND, OC_EBUDGET, OC_EGEOM, OC_ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
 OC_ETIMEDOUT = -8
+OC_ESTARTED = -9
 OC_HOLE, OC_FIELD, OC_FRINGE = 0, 1, -1
 OC_SURF_WALL, OC_SURF_OVERSET = 0, 1
 OC_FACE_INTERIOR, OC_FACE_WALL, OC_FACE_OVERSET, OC_FACE_FARFIELD = 0, 1, 2, 3
@@ -35,7 +36,7 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points", "oc_ab_faces", "oc_face_points",
            "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered", "oc_slot_unblank", "oc_slot_element_points",
            "oc_submit", "oc_wait", "oc_service_info", "oc_donor_search_noalloc", "oc_noalloc_max_points",
-           "oc_cut_refined"]
+           "oc_cut_refined", "oc_cancel"]
 
 
 class OcError(RuntimeError):
@@ -116,6 +117,7 @@ def load(path=LIB_PATH):
         "oc_tune": ([vp, C.c_int32, C.c_int32, C.c_int64, i64p]),
         "oc_submit": ([vp, C.POINTER(oc_cut_req), C.POINTER(C.c_uint64)]),
         "oc_wait": ([vp, C.c_uint64, C.c_int32]),
+        "oc_cancel": ([vp, C.c_uint64]),
         "oc_service_info": ([vp, C.POINTER(oc_service_stats)]),
         "oc_unblank": ([vp, C.c_int32, i32p, C.c_int32, dp, dp, vp, vp, vp, C.c_int64, i64p]),
         "oc_element_points": ([vp, C.c_int32, dp, vp, C.c_int64, vp, vp]),
@@ -295,6 +297,15 @@ class Context:
         False if timeout_ms passed first; raises the request's failure."""
         st = load().oc_wait(self._h, C.c_uint64(ticket), int(timeout_ms))
         if st == OC_ETIMEDOUT:
+            return False
+        _check(st)
+        return True
+
+    def cancel(self, ticket):
+        """Drop a request that is still queued (True); False when it has
+        already started or finished (retire it with wait)."""
+        st = load().oc_cancel(self._h, C.c_uint64(ticket))
+        if st == OC_ESTARTED:
             return False
         _check(st)
         return True

@@ -230,3 +230,48 @@ def test_service_ticket_and_argument_rules():
     finally:
         torch.cuda.synchronize()
         ctx.close()
+
+
+def test_service_cancel_queued_request():
+    """With one service slot held by a request that waits behind work on the
+    context stream, a second request stays queued: cancelling it forgets its
+    ticket and leaves its output untouched; the running one cannot be
+    cancelled and finishes with the solo result; later requests run."""
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("service: cancel a queued request")
+    ctx = oc.Context(device=0)
+    try:
+        assert ctx.tune(oc.OC_TUNE_SERVICE_SLOTS, 0, 1) == 1
+        bg, s, poses = _same_shape_requests()
+        g, sid = ctx.register_grid(bg.nodes, bg.conn), ctx.register_cut_surface(s.nodes, s.conn)
+        outs = [torch.full((bg.n_elem,), 7, dtype=torch.int8, device="cuda") for _ in range(3)]
+        torch.cuda.synchronize()
+        with torch.cuda.stream(ctx.stream):
+            torch.cuda._sleep(200_000_000)       # about 0.1 s of spinning on the context stream
+        ta = ctx.submit(g, [sid], poses[0].reshape(1, 12), outs[0])
+        tb = ctx.submit(g, [sid], poses[1].reshape(1, 12), outs[1])
+        info = ctx.service_info()
+        assert info["running"] == 1 and info["queued"] == 1
+        assert ctx.cancel(tb) is True
+        assert ctx.service_info()["queued"] == 0
+        assert ctx.cancel(ta) is False
+        with pytest.raises(oc.OcError) as e:
+            ctx.cancel(987654)
+        assert e.value.status == oc.OC_ENOTFOUND
+        assert ctx.wait(ta)
+        with pytest.raises(oc.OcError) as e:
+            ctx.wait(tb)
+        assert e.value.status == oc.OC_ENOTFOUND
+        torch.cuda.synchronize()
+        assert (outs[1].cpu().numpy() == 7).all()
+        assert np.array_equal(outs[0].cpu().numpy(), _solo(ctx, g, [sid], poses[0], bg.n_elem))
+        tc = ctx.submit(g, [sid], poses[2].reshape(1, 12), outs[2])
+        assert ctx.wait(tc)
+        with pytest.raises(oc.OcError) as e:     # forgotten once waited for
+            ctx.cancel(tc)
+        assert e.value.status == oc.OC_ENOTFOUND
+        assert np.array_equal(outs[2].cpu().numpy(), _solo(ctx, g, [sid], poses[2], bg.n_elem))
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
