@@ -79,6 +79,12 @@ typedef struct oc_config {
     int32_t surf_bins;      /* cut-surface bins per axis; 0 = automatic */
     double donor_bin_scale; /* donor bin edge / mean element extent; 0 = 0.5 */
     int64_t hbm_budget;     /* device bytes the context may hold; 0 = no limit */
+    const char *tune_cache; /* tuning file applied at creation (NULL = none): text lines
+                               "exact_waves N", "filter_block N", "donor_waves N" and
+                               "bin_factor C F" (surfaces of 2^C .. 2^(C+1)-1 faces get
+                               F times the automatic bins per axis, F in (0, 1]), as
+                               written by the autotuner; '#' starts a comment.  An
+                               unreadable file or a bad line is OC_EINVAL. */
 } oc_config;
 
 /* Statistics of the last oc_cut / oc_cut_multi call (host copy; the call
@@ -478,11 +484,15 @@ oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len);
  *                        (0 = the slot's capacity, 8 per point); the points
  *                        whose pairs fall beyond it are solved one candidate
  *                        at a time in ascending id (same donors).
+ *   OC_TUNE_FILTER_BLOCK arg unused; value = threads per block of the
+ *                        element-box filter (64, 128, 256, 512 or 1024, four
+ *                        elements per thread; 0 = 256).
  *   OC_TUNE_HBM_BUDGET   arg unused; value = the context's HBM budget in
  *                        bytes (0 = none), as oc_config.hbm_budget; later
  *                        allocations are held to it, memory already held is
  *                        kept (registration needs transient room beyond
  *                        what it keeps, so a budget can be set after it).
+ * value = -1 changes nothing and returns the value in force (a query).
  * *applied (may be NULL) receives the value in force afterwards. */
 enum {
     OC_TUNE_SURF_BINS = 1,
@@ -490,7 +500,8 @@ enum {
     OC_TUNE_SERVICE_SLOTS = 3,
     OC_TUNE_HBM_BUDGET = 4,
     OC_TUNE_DONOR_WAVES = 5,
-    OC_TUNE_DONOR_PAIRS = 6
+    OC_TUNE_DONOR_PAIRS = 6,
+    OC_TUNE_FILTER_BLOCK = 7
 };
 oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t *applied);
 

@@ -1,17 +1,19 @@
 """Autotuner of the batched cut's launch parameters.
 
-Two knobs change speed, never results (every setting gives the same
+Three knobs change speed, never results (every setting gives the same
 iblank): the cap on a surface's bins per axis (coarser bins hold more faces
-each, so bin walks get longer but bin arrays smaller) and the number of
-wavefronts the persistent exact-stage kernels launch.  The tuner groups the
-cuts of a batch into size classes by face count (octaves), times each class
-alone under each bin-cap factor and keeps the fastest, then times the whole
-batch under each wavefront count.  Results can be saved and reloaded as
-JSON keyed by size class.
+each, so bin walks get longer but bin arrays smaller), the number of
+wavefronts the persistent exact-stage kernels launch, and the block shape
+of the streaming element filter (threads per block, four elements each).
+The tuner groups the cuts of a batch into size classes by face count
+(octaves), times each class alone under each bin-cap factor and keeps the
+fastest, then times the whole batch under each wavefront count and each
+filter block.  ``save`` writes the tuning file a context reads at creation
+(``Context(tune_cache=path)``, oc_config.tune_cache): one "key value" line
+per knob, "bin_factor <octave> <factor>" per size class.
 """
 from __future__ import annotations
 
-import json
 import math
 import time
 
@@ -46,9 +48,11 @@ def apply(ctx, surf_faces, params):
         f = params.get("bin_factor", {}).get(str(size_class(nf)), 1.0)
         ctx.tune(_oc.OC_TUNE_SURF_BINS, sid, max(1, int(round(auto[sid] * f))))
     ctx.tune(_oc.OC_TUNE_EXACT_WAVES, 0, int(params.get("exact_waves", 0)))
+    ctx.tune(_oc.OC_TUNE_FILTER_BLOCK, 0, int(params.get("filter_block", 0)))
 
 
-def tune_batch(ctx, reqs, surf_faces, factors=(1.0, 0.75, 0.5), waves=(2048, 4096, 8192, 16384), reps=3):
+def tune_batch(ctx, reqs, surf_faces, factors=(1.0, 0.75, 0.5), waves=(2048, 4096, 8192, 16384),
+               blocks=(128, 256, 512, 1024), reps=3):
     """reqs: [(grid_id, [surf_id], host poses [1,12], iblank)] cut with
     Context.cut_batch (default slot).  Returns the chosen parameters and
     the timings behind them."""
@@ -78,15 +82,39 @@ def tune_batch(ctx, reqs, surf_faces, factors=(1.0, 0.75, 0.5), waves=(2048, 409
     best_w = min(wt, key=wt.get)
     ctx.tune(_oc.OC_TUNE_EXACT_WAVES, 0, best_w)
     report["waves"] = {str(k): 1e3 * v for k, v in wt.items()}
-    params = dict(bin_factor=chosen, exact_waves=best_w)
+    bt = {}
+    for b in blocks:
+        ctx.tune(_oc.OC_TUNE_FILTER_BLOCK, 0, b)
+        bt[b] = _time(lambda: ctx.cut_batch(reqs), reps)
+    best_b = min(bt, key=bt.get)
+    ctx.tune(_oc.OC_TUNE_FILTER_BLOCK, 0, best_b)
+    report["filter_block"] = {str(k): 1e3 * v for k, v in bt.items()}
+    params = dict(bin_factor=chosen, exact_waves=best_w, filter_block=best_b)
     return params, report
 
 
 def save(params, path):
+    """Write params as the library's tuning file (oc_config.tune_cache)."""
+    lines = ["# overset cut tuning: knob value (bin_factor: face-count octave, factor)"]
+    for k in ("exact_waves", "filter_block", "donor_waves"):
+        if k in params:
+            lines.append("%s %d" % (k, int(params[k])))
+    for c, f in sorted(params.get("bin_factor", {}).items(), key=lambda kv: int(kv[0])):
+        lines.append("bin_factor %d %.17g" % (int(c), float(f)))
     with open(path, "w") as f:
-        json.dump(params, f, indent=1, sort_keys=True)
+        f.write("\n".join(lines) + "\n")
 
 
 def load(path):
+    """Read a tuning file back into params."""
+    params = dict(bin_factor={})
     with open(path) as f:
-        return json.load(f)
+        for line in f:
+            t = line.split("#", 1)[0].split()
+            if not t:
+                continue
+            if t[0] == "bin_factor":
+                params["bin_factor"][str(int(t[1]))] = float(t[2])
+            else:
+                params[t[0]] = int(t[1])
+    return params

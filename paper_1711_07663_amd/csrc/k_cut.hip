@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_bin_fill(const CutInst *__restrict
 // thread) is tested against its cut's surface box.  The first cut of an
 // output also initialises its iblank to field.  Blocks are flattened over
 // the cuts, 1024 elements per block.
-__global__ __launch_bounds__(kThreads) void k_filter(const CutInst *__restrict__ I, int n_cut,
+__global__ __launch_bounds__(1024) void k_filter(const CutInst *__restrict__ I, int n_cut,
                                                      uint64_t *__restrict__ list_inbox, CutCounters *cnt)
 {
     const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].eblk0; });
@@ -1292,7 +1292,7 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
             c.eblk0 = (int)eblk;
             fblk += blocks_of(s.n_face, kThreads);
             pblk += blocks_of(s.n_face, kPoseFaces);
-            eblk += blocks_of(g.n_elem, kThreads * 4);
+            eblk += blocks_of(g.n_elem, (int64_t)ctx->filter_block * 4);
             face_off += s.n_face;
             I.push_back(c);
         }
@@ -1321,7 +1321,8 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         OC_TRY(scan_exclusive(ctx, st, sl->bin_count, sl->bin_start, need.bins, n_bins_dev, sl->bin_scan_tmp));
         LAUNCH(k_bin_fill, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_start, sl->bin_count,
                sl->bin_items);
-        LAUNCH(k_filter, dim3((unsigned)eblk), dim3(kThreads), sl->insts, n_cut, sl->l_inbox, sl->counters);
+        LAUNCH(k_filter, dim3((unsigned)eblk), dim3((unsigned)ctx->filter_block), sl->insts, n_cut, sl->l_inbox,
+               sl->counters);
         LAUNCH(k_candidates, dim3((unsigned)ctx->exact_waves), dim3(64), sl->insts, sl->bin_start, sl->bin_items,
                sl->l_inbox, sl->l_stat, sl->l_ncand, sl->counters);
         ExactArgs ea;

@@ -289,6 +289,48 @@ extern "C" {
 
 const char *oc_last_error(void) { return g_error.c_str(); }
 
+// The tuning file of oc_config.tune_cache: "key value" lines (see oc.h).
+static oc_status read_tune_cache(oc_ctx *ctx, const char *path)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) {
+        set_error(std::string("oc_create: cannot read tuning file ") + path);
+        return OC_EINVAL;
+    }
+    char line[512];
+    int ln = 0;
+    oc_status st = OC_OK;
+    while (st == OC_OK && fgets(line, sizeof line, f)) {
+        ++ln;
+        if (char *h = strchr(line, '#')) *h = 0;
+        char key[64];
+        long long a = 0;
+        double b = 0.0;
+        int n = sscanf(line, "%63s %lld %lf", key, &a, &b);
+        if (n <= 0) continue;   // blank or comment
+        bool ok = false;
+        if (n == 2 && !strcmp(key, "exact_waves")) {
+            ok = a >= 0 && a <= (1 << 20);
+            if (ok) ctx->exact_waves = a == 0 ? 8192 : (int)a;
+        } else if (n == 2 && !strcmp(key, "filter_block")) {
+            ok = a == 0 || a == 64 || a == 128 || a == 256 || a == 512 || a == 1024;
+            if (ok) ctx->filter_block = a == 0 ? 256 : (int)a;
+        } else if (n == 2 && !strcmp(key, "donor_waves")) {
+            ok = a >= 0 && a <= (1 << 22);
+            if (ok) ctx->donor_waves = (int)a;
+        } else if (n == 3 && !strcmp(key, "bin_factor")) {
+            ok = a >= 0 && a < 63 && b > 0.0 && b <= 1.0;
+            if (ok) ctx->bin_factor.emplace_back((int)a, b);
+        }
+        if (!ok) {
+            set_error(std::string("oc_create: bad line ") + std::to_string(ln) + " in tuning file " + path);
+            st = OC_EINVAL;
+        }
+    }
+    fclose(f);
+    return st;
+}
+
 oc_status oc_create(oc_ctx **out, const oc_config *cfg)
 {
     if (!out) {
@@ -308,6 +350,13 @@ oc_status oc_create(oc_ctx **out, const oc_config *cfg)
         ctx->surf_bins = cfg->surf_bins;
         ctx->donor_bin_scale = cfg->donor_bin_scale > 0 ? cfg->donor_bin_scale : 0.5;
         ctx->budget = cfg->hbm_budget;
+        if (cfg->tune_cache) {
+            oc_status ts = read_tune_cache(ctx, cfg->tune_cache);
+            if (ts != OC_OK) {
+                delete ctx;
+                return ts;
+            }
+        }
     }
     if (ctx->device < 0 || ctx->device >= ndev || hipSetDevice(ctx->device) != hipSuccess) {
         delete ctx;
@@ -528,8 +577,13 @@ oc_status oc_register_cut_surface(oc_ctx *ctx, const double *nodes, int64_t n_no
     int nb = (int)std::ceil(rb / std::max(dmax, 1e-30)) + 1;
     nb = std::max(1, std::min(nb, 160));
     if (ctx->surf_bins > 0) nb = std::min(nb, ctx->surf_bins);
-    s->nb_max = nb;
     s->nb_auto = nb;
+    // a tuned factor for the surface's size class (face-count octave)
+    int oct = 0;
+    while (oct < 62 && (int64_t(2) << oct) <= n_face) ++oct;
+    for (auto &bf : ctx->bin_factor)
+        if (bf.first == oct) nb = std::max(1, (int)std::lround(nb * bf.second));
+    s->nb_max = nb;
     for (int d = 0; d < 3; ++d) s->first[d] = nodes[d];
     for (int64_t i = 0; i < n_nodes; ++i)
         s->rmax = std::max(s->rmax, std::sqrt(nodes[3 * i] * nodes[3 * i] + nodes[3 * i + 1] * nodes[3 * i + 1] +
@@ -1416,6 +1470,30 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
         return OC_EINVAL;
     }
     int64_t v = 0;
+    if (value == -1) {   // query: the value in force, nothing changed
+        if (knob == OC_TUNE_SURF_BINS) {
+            std::vector<Surf *> ss;
+            OC_TRY(collect_surfs(ctx, &arg, 1, ss));
+            v = ss[0]->nb_max;
+        } else if (knob == OC_TUNE_EXACT_WAVES) {
+            v = ctx->exact_waves;
+        } else if (knob == OC_TUNE_SERVICE_SLOTS) {
+            v = ctx->service_slots;
+        } else if (knob == OC_TUNE_DONOR_WAVES) {
+            v = ctx->donor_waves;
+        } else if (knob == OC_TUNE_DONOR_PAIRS) {
+            v = ctx->donor_pairs;
+        } else if (knob == OC_TUNE_FILTER_BLOCK) {
+            v = ctx->filter_block;
+        } else if (knob == OC_TUNE_HBM_BUDGET) {
+            v = ctx->budget;
+        } else {
+            set_error("oc_tune: unknown knob");
+            return OC_EINVAL;
+        }
+        if (applied) *applied = v;
+        return OC_OK;
+    }
     if (knob == OC_TUNE_SURF_BINS) {
         std::vector<Surf *> ss;
         OC_TRY(collect_surfs(ctx, &arg, 1, ss));
@@ -1453,6 +1531,13 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
         }
         ctx->donor_pairs = value;
         v = ctx->donor_pairs;
+    } else if (knob == OC_TUNE_FILTER_BLOCK) {
+        if (value != 0 && value != 64 && value != 128 && value != 256 && value != 512 && value != 1024) {
+            set_error("oc_tune: filter block must be 64, 128, 256, 512 or 1024 threads");
+            return OC_EINVAL;
+        }
+        ctx->filter_block = value == 0 ? 256 : (int)value;
+        v = ctx->filter_block;
     } else if (knob == OC_TUNE_HBM_BUDGET) {
         if (value < 0) {
             set_error("oc_tune: negative budget");

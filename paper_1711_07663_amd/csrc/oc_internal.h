@@ -227,6 +227,8 @@ struct oc_ctx {
     int device = 0;
     int surf_bins = 0;
     int exact_waves = 8192;                // persistent wavefronts of the exact-stage kernels
+    int filter_block = 256;                // threads per block of the element-box filter
+    std::vector<std::pair<int, double>> bin_factor;   // tuned bins factor per face-count octave
     int donor_waves = 0;                   // cap on the donor-search wavefronts (0 = none)
     int64_t donor_pairs = 0;               // cap on the pairs one donor search keeps (0 = none)
     double donor_bin_scale = 0.5;

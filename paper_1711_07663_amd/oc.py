@@ -26,6 +26,7 @@ OC_SURF_WALL, OC_SURF_OVERSET = 0, 1
 OC_FACE_INTERIOR, OC_FACE_WALL, OC_FACE_OVERSET, OC_FACE_FARFIELD = 0, 1, 2, 3
 OC_TUNE_SURF_BINS, OC_TUNE_EXACT_WAVES, OC_TUNE_SERVICE_SLOTS, OC_TUNE_HBM_BUDGET, OC_TUNE_DONOR_WAVES = 1, 2, 3, 4, 5
 OC_TUNE_DONOR_PAIRS = 6
+OC_TUNE_FILTER_BLOCK = 7
 
 EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_register_grid",
            "oc_register_cut_surface", "oc_cut", "oc_cut_multi", "oc_last_cut_info", "oc_fringe_points",
@@ -47,7 +48,7 @@ class OcError(RuntimeError):
 
 class oc_config(C.Structure):
     _fields_ = [("device", C.c_int32), ("surf_bins", C.c_int32), ("donor_bin_scale", C.c_double),
-                ("hbm_budget", C.c_int64)]
+                ("hbm_budget", C.c_int64), ("tune_cache", C.c_char_p)]
 
 
 class oc_cut_info(C.Structure):
@@ -202,9 +203,12 @@ class Context:
     """Owns one oc_ctx on one device; all compute calls run on ``stream``
     (torch's current stream of that device when not given)."""
 
-    def __init__(self, device=0, surf_bins=0, donor_bin_scale=0.0, hbm_budget=0, stream=None):
+    def __init__(self, device=0, surf_bins=0, donor_bin_scale=0.0, hbm_budget=0, stream=None, tune_cache=None):
+        """tune_cache: path of a tuning file (autotune.save) applied at
+        creation."""
         L = load()
-        cfg = oc_config(device, surf_bins, donor_bin_scale, hbm_budget)
+        cfg = oc_config(device, surf_bins, donor_bin_scale, hbm_budget,
+                        None if tune_cache is None else os.fsencode(tune_cache))
         h = C.c_void_p()
         _check(L.oc_create(C.byref(h), C.byref(cfg)))
         self._h = h

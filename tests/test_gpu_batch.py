@@ -169,7 +169,7 @@ def test_batch_errors(ctx):
     ctx.cut_batch([])
 
 
-def test_tuning_knobs_do_not_change_results(ctx):
+def test_tuning_knobs_do_not_change_results(ctx, tmp_path):
     """Bin caps and exact-stage wavefront counts change speed only."""
     import torch
     from paper_1711_07663_amd import autotune, oc
@@ -199,8 +199,37 @@ def test_tuning_knobs_do_not_change_results(ctx):
     torch.cuda.synchronize()
     for a, b in zip(ref, outs):
         assert np.array_equal(a, b.cpu().numpy())
+    assert params["filter_block"] in (128, 256, 512, 1024)
     for s in auto:
         ctx.tune(oc.OC_TUNE_SURF_BINS, s, 0)
     ctx.tune(oc.OC_TUNE_EXACT_WAVES, 0, 0)
+    ctx.tune(oc.OC_TUNE_FILTER_BLOCK, 0, 0)
     with pytest.raises(oc.OcError):
         ctx.tune(99, 0, 0)
+    with pytest.raises(oc.OcError):
+        ctx.tune(oc.OC_TUNE_FILTER_BLOCK, 0, 96)
+    # the tuning file: a new context applies it at creation
+    path = str(tmp_path / "tune.txt")
+    params["bin_factor"] = {str(autotune.size_class(n)): 0.5 for n in faces.values()}
+    autotune.save(params, path)
+    assert autotune.load(path) == params
+    ctx2 = oc.Context(device=0, tune_cache=path)
+    try:
+        assert ctx2.tune(oc.OC_TUNE_EXACT_WAVES, 0, -1) == params["exact_waves"]
+        assert ctx2.tune(oc.OC_TUNE_FILTER_BLOCK, 0, -1) == params["filter_block"]
+        ids2 = _register(ctx2, cases)
+        for (g, s), (g1, s1) in zip(ids2, ids):
+            assert ctx2.tune(oc.OC_TUNE_SURF_BINS, s, -1) == max(1, int(auto[s1] * 0.5 + 0.5))
+        outs2 = [torch.full((c["bg"].n_elem,), 5, dtype=torch.int8, device="cuda") for c in cases]
+        ctx2.cut_batch([(g, [s], c["poses"][0].reshape(1, 12), ib) for (g, s), c, ib in zip(ids2, cases, outs2)])
+        torch.cuda.synchronize()
+        for a, b in zip(ref, outs2):
+            assert np.array_equal(a, b.cpu().numpy())
+    finally:
+        torch.cuda.synchronize()
+        ctx2.close()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("filter_block 300\n")
+    with pytest.raises(oc.OcError) as e:
+        oc.Context(device=0, tune_cache=str(bad))
+    assert e.value.status == oc.OC_EINVAL

@@ -163,6 +163,17 @@ def test_autotune_size_classes():
     assert [autotune.size_class(6 * m * m) for m in (8, 16, 32, 64)] == [8, 10, 12, 14]
 
 
+def test_autotune_file_round_trip(tmp_path):
+    pytest.importorskip("torch")
+    from paper_1711_07663_amd import autotune
+    params = dict(exact_waves=4096, filter_block=512, bin_factor={"8": 0.75, "14": 0.5, "10": 1.0})
+    path = str(tmp_path / "t.txt")
+    autotune.save(params, path)
+    text = open(path).read()
+    assert "filter_block 512" in text and "bin_factor 14 0.5" in text
+    assert autotune.load(path) == params
+
+
 # ------------------------------------------------------------------- bench --
 def test_bench_traffic_follows_kernel_source(tmp_path, monkeypatch):
     import bench
