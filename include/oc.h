@@ -121,8 +121,17 @@ const char *oc_last_error(void);
 /* Stream for all later compute calls (a hipStream_t; NULL = default stream). */
 oc_status oc_set_stream(oc_ctx *ctx, void *hip_stream);
 
+/* Host or device memory.  The arrays given to the plain (non-slot) calls
+ * below -- registration inputs, oc_cut / oc_cut_multi / oc_cut_posed
+ * outputs, oc_donor_search and oc_fringe_points inputs and outputs -- may
+ * be host or device memory: the pointer's attributes decide (device and
+ * managed memory are used in place; anything else is host memory, staged
+ * through device memory the context keeps, and the call then synchronises
+ * the context stream).  Device inputs are read in the context stream's
+ * order.  The slot calls take device memory only. */
+
 /* Register a grid of quadratic 27-node hexahedra (eq. reftophys with K = 2).
- *   nodes     [n_nodes*3] FP64 xyz, host
+ *   nodes     [n_nodes*3] FP64 xyz, host or device
  *   conn      [n_elem*27] int32, lexicographic a+3b+9c over reference nodes
  *             {-1,0,1}^3, host; every id in [0, n_nodes)
  *   face_tags [n_elem*6] int8 OC_FACE_* or NULL (all interior/boundary)
@@ -136,7 +145,7 @@ oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, co
 /* Register a closed cutting surface of 9-node quadratic quads (Sec. 4.2:
  * each face is split into 2x2 linear quads of two triangles each, along the
  * diagonal from lattice node (m,n) to (m+1,n+1)).
- *   nodes [n_nodes*3] FP64 host, conn [n_face*9] int32 host (a+3b),
+ *   nodes [n_nodes*3] FP64, conn [n_face*9] int32 (a+3b), host or device,
  *   outward normal = d/dxi x d/deta.
  *   kind  OC_SURF_WALL or OC_SURF_OVERSET
  * Errors: OC_EGEOM if the triangulation is not closed and consistently
@@ -144,8 +153,8 @@ oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, co
 oc_status oc_register_cut_surface(oc_ctx *ctx, const double *nodes, int64_t n_nodes, const int32_t *conn,
                                   int64_t n_face, int32_t kind, int32_t *surf_id);
 
-/* Direct cut of a grid by one posed surface (Sec. 4.2).  iblank_out: device
- * int8 [n_elem] receiving OC_HOLE / OC_FIELD / OC_FRINGE.  An element is a
+/* Direct cut of a grid by one posed surface (Sec. 4.2).  iblank_out: int8
+ * [n_elem] (host or device) receiving OC_HOLE / OC_FIELD / OC_FRINGE.  An element is a
  * hole if the surface (wall) intersects it -- some element/surface triangle
  * pair closer than OC_TOL_HIT -- or if it lies inside the surface.  Fringe =
  * field element sharing a face with a hole, or carrying an OVERSET face tag
@@ -157,6 +166,12 @@ oc_status oc_cut(oc_ctx *ctx, int32_t grid_id, int32_t surf_id, const double pos
  * n_surf = 0 gives the fringe layer of OVERSET-tagged faces only. */
 oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses,
                        int32_t n_surf, int8_t *iblank_out);
+/* oc_cut_multi with the grid moving too: grid_pose and poses are world-frame
+ * rigid poses (host FP64), and each surface is cut at inverse(grid_pose)
+ * after its own pose (R = Rg^T Rs, t = Rg^T ts - Rg^T tg), the rigid-motion
+ * composition of Sec. 4.3 done by the library. */
+oc_status oc_cut_posed(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int32_t *surf_ids,
+                       const double *poses, int32_t n_surf, int8_t *iblank_out);
 
 /* Warm-started cut of a moving surface (the per-time-step recut of Sec. 3):
  * prev_iblank (device, not aliasing iblank_out) is this grid's iblank from
@@ -340,22 +355,24 @@ oc_status oc_service_info(oc_ctx *ctx, oc_service_stats *info);
 /* Receptor points: 27 Gauss-Legendre points (3x3x3 tensor, order a+3b+9c)
  * per FRINGE element of iblank, in ascending element id, mapped by
  * eq. reftophys and posed by grid_pose into the world frame.
- *   iblank      device int8 [n_elem]
- *   points_out  device FP64 [cap*3] xyz
- *   src_out     device int32 [cap] source element of each point (may be NULL)
+ *   iblank      int8 [n_elem], host or device
+ *   points_out  FP64 [cap*3] xyz, host or device
+ *   src_out     int32 [cap] source element of each point (may be NULL), host
+ *               or device
  *   n_out       host: number of points (27 * fringe elements)
  * Synchronises the stream.  OC_ECAPACITY if cap is too small (n_out is set). */
 oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int8_t *iblank,
                            double *points_out, int64_t cap, int64_t *n_out, int32_t *src_out);
 
-/* Donor search (Sec. 4.3).  points: device FP64 [n*3] world frame.  Each
+/* Donor search (Sec. 4.3).  points: FP64 [n*3] world frame.  Each
  * point is mapped into the donor grid's registration frame by the inverse
  * of grid_pose, candidates are the elements whose Bernstein control-net box
  * contains it, and Newton iterations from xi = 0 (at most OC_NEWTON_MAXIT,
  * clamped to [-1-OC_NEWTON_CLAMP, 1+OC_NEWTON_CLAMP]) decide containment;
  * the lowest-id containing element is the donor.
- *   donor_out device int32 [n]   (-1 = orphan)
- *   ref_out   device FP64 [n*3]  reference coordinates (NaN for orphans) */
+ *   donor_out int32 [n]   (-1 = orphan)
+ *   ref_out   FP64 [n*3]  reference coordinates (NaN for orphans)
+ * points, donor_out and ref_out: host or device. */
 oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12], const double *points,
                           int64_t n, int32_t *donor_out, double *ref_out);
 
@@ -408,6 +425,11 @@ oc_status oc_slot_bytes(oc_slot *slot, int64_t *bytes);
 /* oc_cut_multi on a slot; poses_dev: device FP64 [n_surf*12] (8-byte aligned) */
 oc_status oc_slot_cut(oc_slot *slot, int32_t grid_id, const int32_t *surf_ids, const double *poses_dev,
                       int32_t n_surf, int8_t *iblank_out);
+/* oc_cut_posed on a slot: grid_pose_dev device FP64 [12], poses_dev device
+ * FP64 [n_surf*12] (world frame, 8-byte aligned); the composition runs on
+ * the slot stream into the slot's pose slots (capturable). */
+oc_status oc_slot_cut_posed(oc_slot *slot, int32_t grid_id, const double *grid_pose_dev, const int32_t *surf_ids,
+                            const double *poses_dev, int32_t n_surf, int8_t *iblank_out);
 /* oc_cut_batch on a slot; every request's poses are in device memory */
 oc_status oc_slot_cut_batch(oc_slot *slot, const oc_cut_req *reqs, int32_t n_req);
 /* oc_cut_warm on a slot; sweep from oc_sweep_bound for the two poses */

@@ -1202,6 +1202,34 @@ oc_status put_bytes(oc_slot *sl, void *dst, const void *src, size_t n)
     return OC_OK;
 }
 
+// Device poses of surfaces in a grid's frame: out[k] = inverse(grid) after
+// surfs[k] (R = Rg^T Rs, t = Rg^T ts - Rg^T tg), one thread per pose.
+__global__ void k_compose_poses(const double *__restrict__ grid, const double *__restrict__ surfs, int n,
+                                Pose *__restrict__ out)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const double *G = grid, *S = surfs + 12 * k;
+    Pose P;
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) P.r[3 * i + j] = G[i] * S[j] + G[3 + i] * S[3 + j] + G[6 + i] * S[6 + j];
+        const double a = G[i] * S[9] + G[3 + i] * S[10] + G[6 + i] * S[11];
+        const double b = G[i] * G[9] + G[3 + i] * G[10] + G[6 + i] * G[11];
+        P.t[i] = a - b;
+    }
+    out[k] = P;
+}
+
+oc_status compose_poses_run(oc_slot *sl, const double *grid_dev, const double *surfs_dev, int n, Pose *out)
+{
+    oc_ctx *ctx = sl->ctx;
+    hipStream_t st = sl->stream;
+    if (n <= 0) return OC_OK;
+    LAUNCH(k_compose_poses, dim3((unsigned)((n + 63) / 64)), dim3(64), grid_dev, surfs_dev, n, out);
+    OC_HIP(hipGetLastError());
+    return OC_OK;
+}
+
 // Host poses into the slot's device pose slots.
 oc_status set_poses(oc_slot *sl, int first, const double *host, int n)
 {

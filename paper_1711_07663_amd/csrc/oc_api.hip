@@ -69,6 +69,61 @@ void time_end(oc_ctx *ctx, hipStream_t st, size_t slot)
     (void)hipEventRecord(ctx->trecs[slot].b, st);
 }
 
+// ------------------------------------------------ host or device memory --
+// Caller arrays of the plain calls may be host or device memory (the
+// pointer's attributes decide); host arrays pass through a staging area on
+// the device, grown on demand and kept by the context.
+bool device_memory(const void *p)
+{
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// a host copy of a caller array that may be device memory (read on the
+// context stream, so work the caller ordered there before is seen)
+template <class T>
+static oc_status host_view(oc_ctx *ctx, const T *p, int64_t n, std::vector<T> &buf, const T **out)
+{
+    *out = p;
+    if (!p || n <= 0 || !device_memory(p)) return OC_OK;
+    buf.resize((size_t)n);
+    OC_HIP(hipMemcpyAsync(buf.data(), p, sizeof(T) * (size_t)n, hipMemcpyDeviceToHost, ctx->dflt->stream));
+    OC_HIP(hipStreamSynchronize(ctx->dflt->stream));
+    *out = buf.data();
+    return OC_OK;
+}
+
+oc_status stage_reserve(oc_ctx *ctx, size_t bytes, char **base)
+{
+    bytes = (bytes + 255) / 256 * 256;
+    if (bytes > ctx->stage_cap) {
+        OC_HIP(hipStreamSynchronize(ctx->dflt->stream));
+        dev_free_all(ctx, ctx->stage_owned);
+        ctx->stage_cap = 0;
+        OC_TRY(dev_alloc(ctx, ctx->stage_owned, bytes, &ctx->stage));
+        ctx->stage_cap = bytes;
+    }
+    *base = reinterpret_cast<char *>(ctx->stage);
+    return OC_OK;
+}
+
+// rigid pose of a surface in a grid's frame: inverse(grid) after surface,
+// R = Rg^T Rs, t = Rg^T ts - Rg^T tg (poses: R row-major, then t)
+void pose_relative(const double *grid, const double *surf, double *out)
+{
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j)
+            out[3 * i + j] = grid[i] * surf[j] + grid[3 + i] * surf[3 + j] + grid[6 + i] * surf[6 + j];
+        const double a = grid[i] * surf[9] + grid[3 + i] * surf[10] + grid[6 + i] * surf[11];
+        const double b = grid[i] * grid[9] + grid[3 + i] * grid[10] + grid[6 + i] * grid[11];
+        out[9 + i] = a - b;
+    }
+}
+
 // ------------------------------------------------------------------ slots --
 static oc_status slot_alloc_lists(oc_slot *sl, int64_t n_elem)
 {
@@ -402,6 +457,7 @@ oc_status oc_destroy(oc_ctx *ctx)
         if (g) dev_free_all(ctx, g->owned);
     for (auto &s : ctx->surfs)
         if (s) dev_free_all(ctx, s->owned);
+    dev_free_all(ctx, ctx->stage_owned);
     (void)hipFree(ctx->dev_scalar);
     for (auto ev : ctx->event_pool) (void)hipEventDestroy(ev);
     delete ctx;
@@ -427,6 +483,13 @@ oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, co
         return OC_EINVAL;
     }
     OC_HIP(hipSetDevice(ctx->device));
+    // device arrays are read back first (registration validates on the host)
+    std::vector<double> hn;
+    std::vector<int32_t> hc;
+    std::vector<int8_t> ht;
+    OC_TRY(host_view(ctx, nodes, n_nodes * 3, hn, &nodes));
+    OC_TRY(host_view(ctx, conn, n_elem * 27, hc, &conn));
+    OC_TRY(host_view(ctx, face_tags, n_elem * 6, ht, &face_tags));
     for (int64_t i = 0; i < n_elem * 27; ++i)
         if (conn[i] < 0 || conn[i] >= n_nodes) {
             set_error("oc_register_grid: node id out of range at conn[" + std::to_string(i) + "]");
@@ -500,6 +563,10 @@ oc_status oc_register_cut_surface(oc_ctx *ctx, const double *nodes, int64_t n_no
         return OC_EINVAL;
     }
     OC_HIP(hipSetDevice(ctx->device));
+    std::vector<double> hn;
+    std::vector<int32_t> hc;
+    OC_TRY(host_view(ctx, nodes, n_nodes * 3, hn, &nodes));
+    OC_TRY(host_view(ctx, conn, n_face * 9, hc, &conn));
     for (int64_t i = 0; i < n_face * 9; ++i)
         if (conn[i] < 0 || conn[i] >= n_nodes) {
             set_error("oc_register_cut_surface: node id out of range");
@@ -658,15 +725,15 @@ static oc_status read_donor_info(oc_slot *sl, oc_donor_info *info)
 
 static bool aligned4(const void *p) { return ((uintptr_t)p & 3) == 0; }
 
-oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
-                       int8_t *iblank_out)
+// The cut of oc_cut_multi / oc_cut_posed: surfaces at poses in the grid's
+// frame, or (grid_pose given) both in the world frame, composed here as
+// inverse(grid pose) after the surface pose.  A host iblank_out is written
+// through the staging area.
+static oc_status cut_multi_posed(oc_ctx *ctx, int32_t grid_id, const double *grid_pose, const int32_t *surf_ids,
+                                 const double *poses, int32_t n_surf, int8_t *iblank_out)
 {
     if (!ctx || !iblank_out || n_surf < 0 || n_surf > kPoseSlots - 2 || (n_surf > 0 && (!surf_ids || !poses))) {
         set_error("oc_cut: invalid arguments");
-        return OC_EINVAL;
-    }
-    if (!aligned4(iblank_out)) {
-        set_error("oc_cut: iblank_out must be 4-byte aligned");
         return OC_EINVAL;
     }
     for (int k = 0; k < n_surf; ++k)
@@ -674,20 +741,62 @@ oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, co
             set_error("oc_cut: non-finite pose");
             return OC_EINVAL;
         }
+    if (grid_pose && !pose_finite(grid_pose)) {
+        set_error("oc_cut_posed: non-finite grid pose");
+        return OC_EINVAL;
+    }
     OC_HIP(hipSetDevice(ctx->device));
+    const bool host_out = !device_memory(iblank_out);
+    if (!host_out && !aligned4(iblank_out)) {
+        set_error("oc_cut: iblank_out must be 4-byte aligned");
+        return OC_EINVAL;
+    }
     Grid *g;
     OC_TRY(get_grid(ctx, grid_id, &g));
     std::vector<Surf *> ss;
     OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
+    std::vector<double> rel;
+    if (grid_pose && n_surf > 0) {
+        rel.resize((size_t)n_surf * 12);
+        for (int k = 0; k < n_surf; ++k) pose_relative(grid_pose, poses + 12 * k, rel.data() + 12 * k);
+        poses = rel.data();
+    }
     oc_slot *sl = ctx->dflt;
     OC_TRY(set_poses(sl, 0, poses, n_surf));
+    int8_t *dst = iblank_out;
+    if (host_out) {
+        char *base;
+        OC_TRY(stage_reserve(ctx, (size_t)g->n_elem, &base));
+        dst = reinterpret_cast<int8_t *>(base);
+    }
     CutReq q;
     q.g = g;
     q.n_surf = n_surf;
     q.surfs = ss.data();
     q.poses = sl->poses;
-    q.iblank = iblank_out;
-    return cut_batch_run(sl, &q, 1);
+    q.iblank = dst;
+    OC_TRY(cut_batch_run(sl, &q, 1));
+    if (host_out) {
+        OC_HIP(hipMemcpyAsync(iblank_out, dst, (size_t)g->n_elem, hipMemcpyDeviceToHost, sl->stream));
+        OC_HIP(hipStreamSynchronize(sl->stream));
+    }
+    return OC_OK;
+}
+
+oc_status oc_cut_multi(oc_ctx *ctx, int32_t grid_id, const int32_t *surf_ids, const double *poses, int32_t n_surf,
+                       int8_t *iblank_out)
+{
+    return cut_multi_posed(ctx, grid_id, nullptr, surf_ids, poses, n_surf, iblank_out);
+}
+
+oc_status oc_cut_posed(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int32_t *surf_ids,
+                       const double *poses, int32_t n_surf, int8_t *iblank_out)
+{
+    if (!grid_pose) {
+        set_error("oc_cut_posed: null grid pose");
+        return OC_EINVAL;
+    }
+    return cut_multi_posed(ctx, grid_id, grid_pose, surf_ids, poses, n_surf, iblank_out);
 }
 
 // Validates a batch and resolves its ids; poses of request r start at
@@ -789,7 +898,7 @@ oc_status oc_last_donor_info(oc_ctx *ctx, oc_donor_info *info)
 oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[12], const int8_t *iblank,
                            double *points_out, int64_t cap, int64_t *n_out, int32_t *src_out)
 {
-    if (!ctx || !iblank || !n_out || cap < 0 || (cap > 0 && !points_out) || !pose_finite(grid_pose)) {
+    if (!ctx || !iblank || !n_out || cap < 0 || (cap > 0 && !points_out) || !grid_pose || !pose_finite(grid_pose)) {
         set_error("oc_fringe_points: invalid arguments");
         return OC_EINVAL;
     }
@@ -798,7 +907,34 @@ oc_status oc_fringe_points(oc_ctx *ctx, int32_t grid_id, const double grid_pose[
     OC_TRY(get_grid(ctx, grid_id, &g));
     oc_slot *sl = ctx->dflt;
     OC_TRY(set_poses(sl, kPoseSlots - 2, grid_pose, 1));
-    return fringe_points_run(sl, *g, sl->poses + kPoseSlots - 2, iblank, points_out, cap, nullptr, n_out, src_out);
+    // host arrays through the staging area: iblank in, points and sources out
+    const bool h_ib = !device_memory(iblank), h_pts = cap > 0 && !device_memory(points_out),
+               h_src = src_out && cap > 0 && !device_memory(src_out);
+    const int8_t *ib = iblank;
+    double *pts = points_out;
+    int32_t *src = src_out;
+    if (h_ib || h_pts || h_src) {
+        const size_t o_pts = (size_t)(g->n_elem + 255) / 256 * 256, o_src = o_pts + sizeof(double) * 3 * (size_t)cap;
+        char *base;
+        OC_TRY(stage_reserve(ctx, o_src + sizeof(int32_t) * (size_t)cap, &base));
+        if (h_ib) {
+            OC_HIP(hipMemcpyAsync(base, iblank, (size_t)g->n_elem, hipMemcpyHostToDevice, sl->stream));
+            ib = reinterpret_cast<const int8_t *>(base);
+        }
+        if (h_pts) pts = reinterpret_cast<double *>(base + o_pts);
+        if (h_src) src = reinterpret_cast<int32_t *>(base + o_src);
+    }
+    const oc_status r = fringe_points_run(sl, *g, sl->poses + kPoseSlots - 2, ib, pts, cap, nullptr, n_out, src);
+    if (r != OC_OK && r != OC_ECAPACITY) return r;
+    const int64_t n = std::min(*n_out, cap);
+    if (h_pts && n > 0)
+        OC_HIP(hipMemcpyAsync(points_out, pts, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToHost, sl->stream));
+    if (h_src && n > 0)
+        OC_HIP(hipMemcpyAsync(src_out, src, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, sl->stream));
+    if (h_ib || h_pts || h_src) OC_HIP(hipStreamSynchronize(sl->stream));
+    if (r != OC_OK) set_error("oc_fringe_points: capacity " + std::to_string(cap) + " < " + std::to_string(*n_out) +
+                              " points");
+    return r;
 }
 
 oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12], const double *points,
@@ -813,7 +949,28 @@ oc_status oc_donor_search(oc_ctx *ctx, int32_t donor_grid_id, const double grid_
     OC_TRY(get_grid(ctx, donor_grid_id, &g));
     oc_slot *sl = ctx->dflt;
     OC_TRY(set_poses(sl, kPoseSlots - 1, grid_pose, 1));
-    return donor_run(sl, *g, sl->poses + kPoseSlots - 1, points, n, nullptr, donor_out, ref_out);
+    if (n == 0) return donor_run(sl, *g, sl->poses + kPoseSlots - 1, points, n, nullptr, donor_out, ref_out);
+    // host arrays through the staging area: points in, donors and xi out
+    const bool h_p = !device_memory(points), h_d = !device_memory(donor_out), h_r = !device_memory(ref_out);
+    const double *P = points;
+    int32_t *D = donor_out;
+    double *X = ref_out;
+    if (h_p || h_d || h_r) {
+        const size_t b3 = sizeof(double) * 3 * (size_t)n, o_x = b3, o_d = 2 * b3;
+        char *base;
+        OC_TRY(stage_reserve(ctx, o_d + sizeof(int32_t) * (size_t)n, &base));
+        if (h_p) {
+            OC_HIP(hipMemcpyAsync(base, points, b3, hipMemcpyHostToDevice, sl->stream));
+            P = reinterpret_cast<const double *>(base);
+        }
+        if (h_r) X = reinterpret_cast<double *>(base + o_x);
+        if (h_d) D = reinterpret_cast<int32_t *>(base + o_d);
+    }
+    OC_TRY(donor_run(sl, *g, sl->poses + kPoseSlots - 1, P, n, nullptr, D, X));
+    if (h_r) OC_HIP(hipMemcpyAsync(ref_out, X, sizeof(double) * 3 * (size_t)n, hipMemcpyDeviceToHost, sl->stream));
+    if (h_d) OC_HIP(hipMemcpyAsync(donor_out, D, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, sl->stream));
+    if (h_p || h_d || h_r) OC_HIP(hipStreamSynchronize(sl->stream));
+    return OC_OK;
 }
 
 oc_status oc_donor_search_noalloc(oc_ctx *ctx, int32_t donor_grid_id, const double grid_pose[12],
@@ -1207,6 +1364,31 @@ oc_status oc_slot_cut(oc_slot *sl, int32_t grid_id, const int32_t *surf_ids, con
     q.n_surf = n_surf;
     q.surfs = ss.data();
     q.poses = reinterpret_cast<const Pose *>(poses_dev);
+    q.iblank = iblank_out;
+    return cut_batch_run(sl, &q, 1);
+}
+
+oc_status oc_slot_cut_posed(oc_slot *sl, int32_t grid_id, const double *grid_pose_dev, const int32_t *surf_ids,
+                            const double *poses_dev, int32_t n_surf, int8_t *iblank_out)
+{
+    if (!sl || !iblank_out || !grid_pose_dev || n_surf < 0 || n_surf > kPoseSlots ||
+        (n_surf > 0 && (!surf_ids || !poses_dev)) || !aligned4(iblank_out) || ((uintptr_t)poses_dev & 7) ||
+        ((uintptr_t)grid_pose_dev & 7)) {
+        set_error("oc_slot_cut_posed: invalid arguments");
+        return OC_EINVAL;
+    }
+    oc_ctx *ctx = sl->ctx;
+    OC_HIP(hipSetDevice(ctx->device));
+    Grid *g;
+    OC_TRY(get_grid(ctx, grid_id, &g));
+    std::vector<Surf *> ss;
+    OC_TRY(collect_surfs(ctx, surf_ids, n_surf, ss));
+    OC_TRY(compose_poses_run(sl, grid_pose_dev, poses_dev, n_surf, sl->poses));
+    CutReq q;
+    q.g = g;
+    q.n_surf = n_surf;
+    q.surfs = ss.data();
+    q.poses = sl->poses;
     q.iblank = iblank_out;
     return cut_batch_run(sl, &q, 1);
 }

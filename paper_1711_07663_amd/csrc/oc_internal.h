@@ -248,6 +248,10 @@ struct oc_ctx {
     // cut service (oc_submit / oc_wait)
     oc::Service *service = nullptr;
     int service_slots = 4;                 // most slots the service keeps
+    // staging of host arrays given to the plain calls
+    std::vector<oc::DevBuf> stage_owned;
+    void *stage = nullptr;
+    size_t stage_cap = 0;
 };
 
 namespace oc {
@@ -374,6 +378,14 @@ oc_status noalloc_init(int device);
 int64_t noalloc_max_points();
 oc_status donor_noalloc_run(oc_ctx *ctx, Grid &g, const double *pose_host, const double *pts, int64_t n,
                             int32_t *donor, double *ref);
+// caller memory: device (or managed) memory, else host memory staged
+bool device_memory(const void *p);
+// the context's staging area, at least bytes (synchronises when it grows)
+oc_status stage_reserve(oc_ctx *ctx, size_t bytes, char **base);
+// rigid pose of a surface in a grid's frame (host)
+void pose_relative(const double *grid, const double *surf, double *out);
+// the same for device poses: out[k] = inverse(grid) after surfs[k]
+oc_status compose_poses_run(oc_slot *sl, const double *grid_dev, const double *surfs_dev, int n, Pose *out);
 // the refined cut of level k (the curved faces split k x k, the near
 // elements k^3 times) of g by the surfaces at poses_dev into iblank;
 // synchronises; *n_near (may be null) receives the number of near

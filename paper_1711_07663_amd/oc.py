@@ -37,7 +37,7 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points", "oc_ab_faces", "oc_face_points",
            "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered", "oc_slot_unblank", "oc_slot_element_points",
            "oc_submit", "oc_wait", "oc_service_info", "oc_donor_search_noalloc", "oc_noalloc_max_points",
-           "oc_cut_refined", "oc_cancel"]
+           "oc_cut_refined", "oc_cancel", "oc_cut_posed", "oc_slot_cut_posed"]
 
 
 class OcError(RuntimeError):
@@ -119,6 +119,8 @@ def load(path=LIB_PATH):
         "oc_submit": ([vp, C.POINTER(oc_cut_req), C.POINTER(C.c_uint64)]),
         "oc_wait": ([vp, C.c_uint64, C.c_int32]),
         "oc_cancel": ([vp, C.c_uint64]),
+        "oc_cut_posed": ([vp, C.c_int32, dp, i32p, dp, C.c_int32, vp]),
+        "oc_slot_cut_posed": ([vp, C.c_int32, vp, i32p, vp, C.c_int32, vp]),
         "oc_service_info": ([vp, C.POINTER(oc_service_stats)]),
         "oc_unblank": ([vp, C.c_int32, i32p, C.c_int32, dp, dp, vp, vp, vp, C.c_int64, i64p]),
         "oc_element_points": ([vp, C.c_int32, dp, vp, C.c_int64, vp, vp]),
@@ -169,6 +171,30 @@ def _dptr(t, dtype, n=None):
     if n is not None and t.numel() < n:
         raise ValueError("tensor too small: %d < %d" % (t.numel(), n))
     return C.c_void_p(t.data_ptr())
+
+
+_NP = {"int8": np.int8, "int32": np.int32, "float64": np.float64}
+
+
+def _aptr(t, dtype, n=None):
+    """Pointer of a contiguous array in host or device memory: a torch
+    tensor (CUDA or CPU) or a numpy array of the given dtype (the library
+    tells the two memories apart by the pointer)."""
+    import torch
+    if isinstance(t, torch.Tensor):
+        if not t.is_contiguous() or t.dtype != dtype:
+            raise TypeError("expected a contiguous %s tensor" % dtype)
+        if n is not None and t.numel() < n:
+            raise ValueError("tensor too small: %d < %d" % (t.numel(), n))
+        return C.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        want = _NP[str(dtype).replace("torch.", "")]
+        if not t.flags.c_contiguous or t.dtype != want:
+            raise TypeError("expected a C-contiguous %s array" % np.dtype(want).name)
+        if n is not None and t.size < n:
+            raise ValueError("array too small: %d < %d" % (t.size, n))
+        return C.c_void_p(t.ctypes.data)
+    raise TypeError("expected a torch tensor or a numpy array")
 
 
 def _cut_reqs(ctx, reqs, device_poses):
@@ -243,35 +269,53 @@ class Context:
         _check(load().oc_set_stream(self._h, C.c_void_p(handle)))
 
     # -------------------------------------------------------- registration --
+    @staticmethod
+    def _reg_array(a, np_dtype, torch_dtype, width):
+        """(pointer, rows, keep-alive) of a registration array: a torch
+        tensor (CUDA or CPU, used in place) or anything numpy takes."""
+        import torch
+        if isinstance(a, torch.Tensor):
+            a = a.contiguous().to(torch_dtype)
+            if a.is_cuda:
+                torch.cuda.synchronize(a.device)   # written by torch on its own streams
+            return C.c_void_p(a.data_ptr()), a.numel() // width, a
+        a = np.ascontiguousarray(a, dtype=np_dtype)
+        return C.c_void_p(a.ctypes.data), a.size // width, a
+
     def register_grid(self, nodes, conn, face_tags=None):
-        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
-        conn = np.ascontiguousarray(conn, dtype=np.int32)
-        tags_p = None
+        """nodes [n,3] FP64, conn [e,27] int32, face_tags [e,6] int8 (may be
+        None): numpy arrays or torch tensors in host or device memory."""
+        import torch
+        pn, n_nodes, kn = self._reg_array(nodes, np.float64, torch.float64, 3)
+        pc, n_elem, kc = self._reg_array(conn, np.int32, torch.int32, 27)
+        pt, kt = None, None
         if face_tags is not None:
-            face_tags = np.ascontiguousarray(face_tags, dtype=np.int8)
-            tags_p = face_tags.ctypes.data_as(C.POINTER(C.c_int8))
+            pt, _, kt = self._reg_array(face_tags, np.int8, torch.int8, 6)
         gid = C.c_int32(-1)
-        _check(load().oc_register_grid(self._h, nodes.ctypes.data_as(C.POINTER(C.c_double)), nodes.shape[0],
-                                       conn.ctypes.data_as(C.POINTER(C.c_int32)), conn.shape[0], tags_p,
-                                       C.byref(gid)))
-        self.grids[gid.value] = int(conn.shape[0])
+        _check(load().oc_register_grid(self._h, C.cast(pn, C.POINTER(C.c_double)), n_nodes,
+                                       C.cast(pc, C.POINTER(C.c_int32)), n_elem,
+                                       None if pt is None else C.cast(pt, C.POINTER(C.c_int8)), C.byref(gid)))
+        self.grids[gid.value] = int(n_elem)
         return gid.value
 
     def register_cut_surface(self, nodes, conn, kind=OC_SURF_WALL):
-        nodes = np.ascontiguousarray(nodes, dtype=np.float64)
-        conn = np.ascontiguousarray(conn, dtype=np.int32)
+        """nodes [n,3] FP64, conn [f,9] int32: numpy arrays or torch tensors
+        in host or device memory."""
+        import torch
+        pn, n_nodes, kn = self._reg_array(nodes, np.float64, torch.float64, 3)
+        pc, n_face, kc = self._reg_array(conn, np.int32, torch.int32, 9)
         sid = C.c_int32(-1)
-        _check(load().oc_register_cut_surface(self._h, nodes.ctypes.data_as(C.POINTER(C.c_double)), nodes.shape[0],
-                                              conn.ctypes.data_as(C.POINTER(C.c_int32)), conn.shape[0], int(kind),
-                                              C.byref(sid)))
-        self.surfs[sid.value] = int(conn.shape[0])
+        _check(load().oc_register_cut_surface(self._h, C.cast(pn, C.POINTER(C.c_double)), n_nodes,
+                                              C.cast(pc, C.POINTER(C.c_int32)), n_face, int(kind), C.byref(sid)))
+        self.surfs[sid.value] = int(n_face)
         return sid.value
 
     # -------------------------------------------------------------- compute --
     def cut(self, grid_id, surf_id, pose, iblank):
+        """iblank: int8 tensor (CUDA or CPU) or numpy array."""
         import torch
         _, pp = _pose(pose)
-        _check(load().oc_cut(self._h, grid_id, surf_id, pp, _dptr(iblank, torch.int8, self.grids[grid_id])))
+        _check(load().oc_cut(self._h, grid_id, surf_id, pp, _aptr(iblank, torch.int8, self.grids[grid_id])))
         return iblank
 
     def cut_multi(self, grid_id, surf_ids, poses, iblank):
@@ -279,7 +323,17 @@ class Context:
         ids = np.ascontiguousarray(surf_ids, dtype=np.int32)
         pa, pp = _pose(np.asarray(poses, dtype=np.float64).reshape(-1) if len(ids) else np.zeros(12))
         _check(load().oc_cut_multi(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
-                                   _dptr(iblank, torch.int8, self.grids[grid_id])))
+                                   _aptr(iblank, torch.int8, self.grids[grid_id])))
+        return iblank
+
+    def cut_posed(self, grid_id, grid_pose, surf_ids, poses, iblank):
+        """oc_cut_posed: grid and surfaces at world-frame poses (host)."""
+        import torch
+        ids = np.ascontiguousarray(surf_ids, dtype=np.int32)
+        _, gp = _pose(grid_pose)
+        pa, pp = _pose(np.asarray(poses, dtype=np.float64).reshape(-1) if len(ids) else np.zeros(12))
+        _check(load().oc_cut_posed(self._h, grid_id, gp, ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
+                                   _aptr(iblank, torch.int8, self.grids[grid_id])))
         return iblank
 
     def cut_batch(self, reqs):
@@ -427,9 +481,10 @@ class Context:
         import torch
         _, pp = _pose(pose)
         n = C.c_int64(0)
-        cap = points.numel() // 3
-        _check(load().oc_fringe_points(self._h, grid_id, pp, _dptr(iblank, torch.int8), _dptr(points, torch.float64),
-                                       cap, C.byref(n), None if src is None else _dptr(src, torch.int32, cap)))
+        cap = (points.numel() if isinstance(points, torch.Tensor) else points.size) // 3
+        _check(load().oc_fringe_points(self._h, grid_id, pp, _aptr(iblank, torch.int8, self.grids[grid_id]),
+                                       _aptr(points, torch.float64), cap, C.byref(n),
+                                       None if src is None else _aptr(src, torch.int32, cap)))
         return n.value
 
     def donor_search(self, grid_id, pose, points, n, donor, ref):
@@ -437,8 +492,8 @@ class Context:
         _, pp = _pose(pose)
         if n == 0:
             return
-        _check(load().oc_donor_search(self._h, grid_id, pp, _dptr(points, torch.float64, 3 * n), int(n),
-                                      _dptr(donor, torch.int32, n), _dptr(ref, torch.float64, 3 * n)))
+        _check(load().oc_donor_search(self._h, grid_id, pp, _aptr(points, torch.float64, 3 * n), int(n),
+                                      _aptr(donor, torch.int32, n), _aptr(ref, torch.float64, 3 * n)))
 
     def donor_search_noalloc(self, grid_id, pose, points, n, donor, ref):
         """oc_donor_search_noalloc: the donor search on the library's fixed
@@ -539,6 +594,16 @@ class Slot:
         pp = _dptr(poses_dev, torch.float64, 12 * len(ids)) if len(ids) else None
         _check(load().oc_slot_cut(self._h, grid_id, ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
                                   _dptr(iblank, torch.int8, self.ctx.grids[grid_id])))
+
+    def cut_posed(self, grid_id, grid_pose_dev, surf_ids, poses_dev, iblank):
+        """oc_slot_cut_posed: world-frame device poses (grid [12], surfaces
+        [k,12]), composed on the slot stream."""
+        import torch
+        ids = np.ascontiguousarray(surf_ids, dtype=np.int32)
+        pp = _dptr(poses_dev, torch.float64, 12 * len(ids)) if len(ids) else None
+        _check(load().oc_slot_cut_posed(self._h, grid_id, _dptr(grid_pose_dev, torch.float64, 12),
+                                        ids.ctypes.data_as(C.POINTER(C.c_int32)), pp, len(ids),
+                                        _dptr(iblank, torch.int8, self.ctx.grids[grid_id])))
 
     def cut_batch(self, reqs):
         """reqs: [(grid_id, surf_ids, device poses [k,12] tensor, iblank)]."""

@@ -22,19 +22,6 @@ import torch
 from . import oc as _oc
 
 
-def pose_inverse(p):
-    R = np.asarray(p[:9], dtype=np.float64).reshape(3, 3)
-    t = np.asarray(p[9:12], dtype=np.float64)
-    return np.concatenate([R.T.ravel(), -R.T @ t])
-
-
-def pose_compose(a, b):
-    """x -> a(b(x))"""
-    Ra = np.asarray(a[:9]).reshape(3, 3)
-    Rb = np.asarray(b[:9]).reshape(3, 3)
-    return np.concatenate([(Ra @ Rb).ravel(), Ra @ np.asarray(b[9:12]) + np.asarray(a[9:12])])
-
-
 IDENTITY = np.array([1, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0], dtype=np.float64)
 
 
@@ -95,10 +82,11 @@ class OversetSystem:
         ctx.cut_multi(self.bg_id, self.bg_cutters(), np.concatenate(poses), self.ib_bg)
         st = dict(bg_cut=ctx.last_cut_info(), donor_bg=[], donor_shell=[]) if stats else None
         for i, b in enumerate(self.bodies):
+            # the shell moves with its body: the library composes the other
+            # walls' world poses into the shell's frame
             others = [j for j in range(len(self.bodies)) if j != i]
-            inv = pose_inverse(poses[i])
-            rel = [pose_compose(inv, poses[j]) for j in others]
-            ctx.cut_multi(b["shell"], [sids[j] for j in others], np.concatenate(rel) if rel else np.zeros(12), b["ib"])
+            ctx.cut_posed(b["shell"], poses[i], [sids[j] for j in others],
+                          np.concatenate([poses[j] for j in others]) if others else np.zeros(12), b["ib"])
         n_bg = ctx.fringe_points(self.bg_id, IDENTITY, self.ib_bg, self.pts_bg, self.src_bg)
         counts = dict(n_bg_points=n_bg, n_shell_points=[])
         for i, b in enumerate(self.bodies):
@@ -177,9 +165,10 @@ class SlotStep:
     end, so the latency-bound cut kernels of A overlap B's donor search (also
     inside a captured graph).  Chain A, the longer one, is issued first.
 
-    Device pose table rows: [0, nb) body poses (background cut; shell receptor
-    points and bg->shell searches); then for body i the poses of the other
-    bodies in body i's frame (shell cuts); the last row is the identity.
+    Device pose table rows (world frame): [0, nb) body poses (background
+    cut; shell receptor points and bg->shell searches); then for body i the
+    poses of the other bodies, in order (shell cuts: the library composes
+    them into body i's frame on the device); the last row is the identity.
 
     ``warm``: (one body) the background cut of step k starts from the iblank
     of step k-1 with the sweep bound ``sweep`` (a bound on how far any wall
@@ -247,8 +236,7 @@ class SlotStep:
         nb = len(self.sys.bodies)
         rows = [np.asarray(p, dtype=np.float64) for p in poses]
         for i in range(nb):
-            inv = pose_inverse(poses[i])
-            rows += [pose_compose(inv, poses[j]) for j in range(nb) if j != i]
+            rows += [rows[j] for j in range(nb) if j != i]
         rows.append(IDENTITY)
         return torch.from_numpy(np.stack(rows))
 
@@ -300,7 +288,7 @@ class SlotStep:
         for i, b in enumerate(s.bodies):
             others = [sids[j] for j in range(nb) if j != i]
             ob = o["bodies"][i]
-            sb.cut(b["shell"], others, self.poses_dev[r:r + nb - 1], ob["ib"])
+            sb.cut_posed(b["shell"], self.poses_dev[i], others, self.poses_dev[r:r + nb - 1], ob["ib"])
             r += nb - 1
             cap = ob["pts"].shape[0]
             nd = self.n_dev[1 + i:2 + i]
