@@ -312,6 +312,20 @@ __global__ __launch_bounds__(kT) void k_dbin_sort(const int32_t *__restrict__ st
     }
 }
 
+// each bin entry as a 32-byte record: the element's control-net box and its
+// id (lo xyz + id bits, hi xyz + 0), so a bin walk reads its entries'
+// boxes contiguously instead of through the id
+__global__ __launch_bounds__(kT) void k_dbin_records(const int32_t *__restrict__ items, int64_t n_items,
+                                                    const float *__restrict__ cbox, float4 *__restrict__ rec)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_items) return;
+    const int e = items[j];
+    const float *c = cbox + (int64_t)e * 6;
+    rec[2 * j] = make_float4(c[0], c[1], c[2], __int_as_float(e));
+    rec[2 * j + 1] = make_float4(c[3], c[4], c[5], 0.f);
+}
+
 // ----------------------------------------------- fringe compaction --------
 constexpr int kFrItems = 16;
 constexpr int kFrTile = kT * kFrItems;
@@ -381,20 +395,39 @@ __global__ __launch_bounds__(kT) void k_fr_write(const int8_t *__restrict__ ibla
 // The number of fringe elements is read from the device (nfr); at most cap
 // points are written; n_out receives 27 * nfr.  An id outside [0, n_elem)
 // gives NaN points and source -1.
+// a9: 27 Gauss points per listed element.  A block takes 256 consecutive
+// points (at most 11 elements): the elements' nodes are staged in LDS with
+// coalesced loads, then every thread maps its point from LDS.
+constexpr int kPtElems = kT / 27 + 2;
+
 __global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__ enodes, int64_t n_elem,
                                                       const int32_t *__restrict__ list, const int32_t *__restrict__ nfr,
                                                       int64_t cap, const Pose *__restrict__ pose_dev,
                                                       double *__restrict__ pts, int32_t *__restrict__ src,
                                                       int32_t *__restrict__ n_out)
 {
+    __shared__ double sN[kPtElems * 81];
+    __shared__ int sE[kPtElems];
     const int64_t total = (int64_t)(*nfr) * 27;
     if (blockIdx.x == 0 && threadIdx.x == 0 && n_out) *n_out = (int32_t)total;
     const int64_t n = total < cap ? total : cap;
     const Pose pose = *pose_dev;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i0 = (int64_t)blockIdx.x * kT; i0 < n; i0 += (int64_t)gridDim.x * kT) {
+        const int64_t q0 = i0 / 27, q1 = (i0 + kT < n ? i0 + kT - 1 : n - 1) / 27;
+        const int ne = (int)(q1 - q0 + 1);
+        __syncthreads();   // the previous round's points are mapped
+        if ((int)threadIdx.x < ne) sE[threadIdx.x] = list[q0 + threadIdx.x];
+        __syncthreads();
+        for (int k = threadIdx.x; k < ne * 81; k += kT) {
+            const int j = k / 81, e = sE[j];
+            sN[k] = (e >= 0 && e < n_elem) ? enodes[(int64_t)e * 81 + (k - 81 * j)] : 0.0;
+        }
+        __syncthreads();
+        const int64_t i = i0 + threadIdx.x;
+        if (i >= n) continue;
         const int64_t q = i / 27;
-        const int k = (int)(i - q * 27);
-        const int e = list[q];
+        const int k = (int)(i - q * 27), j = (int)(q - q0);
+        const int e = sE[j];
         if (e < 0 || e >= n_elem) {
             const double nan = __builtin_nan("");
             pts[3 * i] = nan;
@@ -406,7 +439,7 @@ __global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__
         const double g = 0.7745966692414834;  // sqrt(3/5), 3-point Gauss-Legendre
         const double xi[3] = {(k % 3 - 1) * g, ((k / 3) % 3 - 1) * g, (k / 9 - 1) * g};
         double x[3];
-        q2_map<false, true>(enodes + (int64_t)e * 81, xi, x, nullptr);
+        q2_map<false, true>(sN + 81 * j, xi, x, nullptr);
         const d3 w = pose_apply(pose, mk(x[0], x[1], x[2]));
         pts[3 * i] = w.x;
         pts[3 * i + 1] = w.y;
@@ -433,10 +466,15 @@ __device__ inline bool obb_has(const float *__restrict__ o, d3 p)
     return true;
 }
 
-// candidate test: axis-aligned control-net box, then the oriented one
-__device__ inline bool cand_has(const float *__restrict__ cbox, const float *__restrict__ obox, int64_t e, d3 p)
+// candidate test of bin entry j (its record): the axis-aligned control-net
+// box, then the oriented one; *e receives the entry's element
+__device__ inline bool rec_has(const float4 *__restrict__ rec, const float *__restrict__ obox, int64_t j, d3 p,
+                               int *e)
 {
-    return box_has(cbox + e * 6, p) && obb_has(obox + e * 18, p);
+    const float4 lo = rec[2 * j], hi = rec[2 * j + 1];
+    *e = __float_as_int(lo.w);
+    return p.x >= (double)lo.x && p.y >= (double)lo.y && p.z >= (double)lo.z && p.x <= (double)hi.x &&
+           p.y <= (double)hi.y && p.z <= (double)hi.z && obb_has(obox + (int64_t)*e * 18, p);
 }
 
 __device__ inline int64_t point_bin(const BinGrid &G, d3 p)
@@ -454,7 +492,7 @@ struct DonorArgs {
     const double *ediam;
     BinGrid G;
     const int32_t *bstart;
-    const int32_t *bitems;
+    const float4 *brec;    // bin entries as records (k_dbin_records)
     const Pose *pose;
     const double *pts;
     int64_t cap;           // point capacity
@@ -536,10 +574,7 @@ __global__ __launch_bounds__(kT) void k_dp_count(DonorArgs a)
                 const int j = r + sub;
                 int e = -1;
                 bool has = false;
-                if (j < j1) {
-                    e = a.bitems[j];
-                    has = cand_has(a.cbox, a.obox, e, p);
-                }
+                if (j < j1) has = rec_has(a.brec, a.obox, j, p, &e);
                 const unsigned long long m = __ballot(has) & gmask;
                 const int at = c + __popcll(m & below);
                 if (has && at < kCandCache) a.cache[i * kCandCache + at] = e;
@@ -587,10 +622,7 @@ __global__ __launch_bounds__(kT) void k_dp_fill(DonorArgs a)
             const int j = r + sub;
             int e = -1;
             bool has = false;
-            if (j < j1) {
-                e = a.bitems[j];
-                has = cand_has(a.cbox, a.obox, e, p);
-            }
+            if (j < j1) has = rec_has(a.brec, a.obox, j, p, &e);
             const unsigned long long m = __ballot(has) & gmask;
             const int64_t at = q + __popcll(m & below);
             if (has && at < a.pair_cap) {
@@ -713,8 +745,8 @@ __global__ __launch_bounds__(kT) void k_dp_final(DonorArgs a)
             const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
             const int64_t b = point_bin(a.G, p);
             for (int j = a.bstart[b]; j < a.bstart[b + 1]; ++j) {
-                const int e = a.bitems[j];
-                if (!cand_has(a.cbox, a.obox, e, p)) continue;
+                int e;
+                if (!rec_has(a.brec, a.obox, j, p, &e)) continue;
                 ++extra;
                 if (newton_q2<true>(a.enodes + (int64_t)e * 81, p, a.ediam[e], xi, scratch)) {
                     d = e;
@@ -863,6 +895,9 @@ oc_status grid_build_donor_bins(oc_ctx *ctx, Grid &g)
     OC_HIP(hipMemsetAsync(count, 0, sizeof(int32_t) * (nb + 1), st));
     LAUNCH(k_dbin_fill, dim3(blocks(g.n_elem, kT)), dim3(kT), g.cbox, g.n_elem, g.dgrid, start, count, g.dbin_items);
     LAUNCH(k_dbin_sort, dim3(blocks(nb, kT)), dim3(kT), start, nb, g.dbin_items);
+    OC_TRY(dev_alloc(ctx, g.owned, sizeof(float4) * 2 * (size_t)std::max<int64_t>(total, 1), (void **)&g.dbin_rec));
+    LAUNCH(k_dbin_records, dim3(blocks(std::max<int64_t>(total, 1), kT)), dim3(kT), g.dbin_items, (int64_t)total,
+           g.cbox, g.dbin_rec);
     g.dbin_start = start;
     // lanes per point in the donor bin walks: about four bin entries per
     // lane for the typical query (bins weighted by their entry count, since
@@ -963,7 +998,7 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     a.ediam = g.ediam;
     a.G = g.dgrid;
     a.bstart = g.dbin_start;
-    a.bitems = g.dbin_items;
+    a.brec = g.dbin_rec;
     a.pose = pose_dev;
     a.pts = pts;
     a.cap = cap;
@@ -1106,7 +1141,7 @@ oc_status donor_noalloc_run(oc_ctx *ctx, Grid &g, const double *pose_host, const
     a.ediam = g.ediam;
     a.G = g.dgrid;
     a.bstart = g.dbin_start;
-    a.bitems = g.dbin_items;
+    a.brec = g.dbin_rec;
     a.pose = reinterpret_cast<const Pose *>(base + kNaPose);
     a.pts = pts;
     a.cap = n;

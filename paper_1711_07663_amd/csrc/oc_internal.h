@@ -84,6 +84,7 @@ struct Grid {
     BinGrid dgrid{};
     int32_t *dbin_start = nullptr; // [n_dbins + 1]
     int32_t *dbin_items = nullptr; // element ids, ascending within a bin
+    float4 *dbin_rec = nullptr;    // the same entries as records: control-net box + id (2 x float4)
     int64_t n_dbins = 0, n_ditems = 0;
     int dlanes = 1;                // lanes per point in the donor bin walks
     std::vector<DevBuf> owned;
