@@ -286,10 +286,12 @@ __global__ __launch_bounds__(kThreads) void k_bin_count(const CutInst *__restric
 }
 
 // fill: the count array doubles as the per-bin cursor and ends at zero;
-// items hold face ids local to their cut
+// each entry is a 32-byte record of the face's FP32 box and its id local to
+// its cut (lo xyz + id bits, hi xyz + 0), so bin walks read the boxes
+// together with the ids
 __global__ __launch_bounds__(kThreads) void k_bin_fill(const CutInst *__restrict__ I, int n_cut,
                                                        const int32_t *__restrict__ start, int32_t *count,
-                                                       int32_t *__restrict__ items)
+                                                       float4 *__restrict__ rec)
 {
     const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].fblk0; });
     const CutInst &c = I[ci];
@@ -297,14 +299,18 @@ __global__ __launch_bounds__(kThreads) void k_bin_fill(const CutInst *__restrict
     if (f >= c.n_face) return;
     const BinGrid G = c.params->grid;
     const int off = c.params->bin_off;
+    const float *fb = c.fbox + f * 6;
+    const float4 r0 = make_float4(fb[0], fb[1], fb[2], __int_as_float((int)f));
+    const float4 r1 = make_float4(fb[3], fb[4], fb[5], 0.f);
     int lo[3], hi[3];
-    box_bins(G, c.fbox + f * 6, lo, hi);
+    box_bins(G, fb, lo, hi);
     for (int z = lo[2]; z <= hi[2]; ++z)
         for (int y = lo[1]; y <= hi[1]; ++y)
             for (int x = lo[0]; x <= hi[0]; ++x) {
                 const int b = off + x + G.n[0] * (y + G.n[1] * z);
-                const int pos = atomicSub(&count[b], 1) - 1;
-                items[start[b] + pos] = (int32_t)f;
+                const int64_t j = (int64_t)start[b] + (atomicSub(&count[b], 1) - 1);
+                rec[2 * j] = r0;
+                rec[2 * j + 1] = r1;
             }
 }
 
@@ -413,9 +419,10 @@ struct WalkLds {
 // bins is met once per bin; callers keep the first common bin).  A round
 // loads the extents of 64 bins, one per lane, prefix-sums their lengths and
 // then hands the stored faces out one per lane, so the dependent loads of a
-// round are issued by the whole wavefront at once.  fn(face, xyz) is called
-// with the same trip count on every lane (face < 0 on idle lanes) and may use
-// wavefront operations; it returns true (wave-uniformly) to stop the walk.
+// round are issued by the whole wavefront at once.  fn(face, fb, xyz) gets
+// the face's FP32 box fb from its bin record; it is called with the same
+// trip count on every lane (face < 0 on idle lanes) and may use wavefront
+// operations; it returns true (wave-uniformly) to stop the walk.
 // The walk synchronises its workgroup: every wavefront of the workgroup must
 // walk the same range R (each with its own WalkLds), and only a one-wavefront
 // workgroup may stop early.
@@ -423,7 +430,7 @@ struct WalkLds {
 // part (mod nparts) are visited, so nparts wavefronts can share one walk.
 template <class Fn>
 __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int32_t *__restrict__ bstart,
-                                  const int32_t *__restrict__ bitems, WalkLds &L, Fn &&fn, int part = 0,
+                                  const float4 *__restrict__ brec, WalkLds &L, Fn &&fn, int part = 0,
                                   int nparts = 1)
 {
     const int lane = threadIdx.x & 63;
@@ -454,6 +461,7 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
             if (chunk % nparts != part) continue;
             const int k = k0 + lane;
             int face = -1, xyz[3] = {0, 0, 0};
+            float fb[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
             if (k < total) {
                 int lo = 0, hi = 63;
                 while (lo < hi) {
@@ -461,13 +469,21 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
                     if (L.pre[mid] <= k) lo = mid;
                     else hi = mid - 1;
                 }
-                face = bitems[L.j0[lo] + (k - L.pre[lo])];
+                const int64_t j = (int64_t)L.j0[lo] + (k - L.pre[lo]);
+                const float4 r0 = brec[2 * j], r1 = brec[2 * j + 1];
+                face = __float_as_int(r0.w);
+                fb[0] = r0.x;
+                fb[1] = r0.y;
+                fb[2] = r0.z;
+                fb[3] = r1.x;
+                fb[4] = r1.y;
+                fb[5] = r1.z;
                 const int pk = L.xyz[lo];
                 xyz[0] = pk & 1023;
                 xyz[1] = (pk >> 10) & 1023;
                 xyz[2] = pk >> 20;
             }
-            if (fn(face, xyz)) return;
+            if (fn(face, fb, xyz)) return;
         }
     }
 }
@@ -476,7 +492,7 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
 // +x ray parity of its first node over the column of bins that holds the
 // ray (one wavefront).
 __device__ inline void ray_item(const CutInst &c, const int32_t *__restrict__ bin_start,
-                                const int32_t *__restrict__ bitems, int e, WalkLds &L)
+                                const float4 *__restrict__ brec, int e, WalkLds &L)
 {
     const int lane = threadIdx.x & 63;
     const SurfParams *sp = c.params;
@@ -486,7 +502,6 @@ __device__ inline void ray_item(const CutInst &c, const int32_t *__restrict__ bi
         return;
     const BinGrid G = sp->grid;
     const int32_t *bstart = bin_start + sp->bin_off;
-    const float *__restrict__ fbox = c.fbox;
     const double *__restrict__ pnodes = c.pnodes;
     int lo[3], hi[3];
     lo[0] = bin_of((float)p.x, G.o[0], G.inv[0], G.n[0]);
@@ -495,9 +510,8 @@ __device__ inline void ray_item(const CutInst &c, const int32_t *__restrict__ bi
     hi[0] = G.n[0] - 1;
     const BinRange R = make_range(lo, hi);
     int par = 0;
-    walk_faces(G, R, bstart, bitems, L, [&](int f, const int *xyz) {
+    walk_faces(G, R, bstart, brec, L, [&](int f, const float *fb, const int *xyz) {
         if (f >= 0) {
-            const float *fb = fbox + (int64_t)f * 6;
             if (first_common_bin(G, fb, xyz, lo) && (double)fb[1] <= p.y && (double)fb[4] >= p.y &&
                 (double)fb[2] <= p.z && (double)fb[5] >= p.z && (double)fb[3] >= p.x) {
                 const double *P = pnodes + (int64_t)f * 27;
@@ -524,7 +538,7 @@ __device__ inline void ray_item(const CutInst &c, const int32_t *__restrict__ bi
 // side (the surface never came near it between the two poses) and needs no
 // further test.  k_hit takes the near items by status.
 __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I, const int32_t *__restrict__ bin_start,
-                                                   const int32_t *__restrict__ bitems,
+                                                   const float4 *__restrict__ brec,
                                                    const uint64_t *__restrict__ list_inbox, uint8_t *__restrict__ stat,
                                                    int32_t *__restrict__ ncand, const CutCounters *cnt)
 {
@@ -535,7 +549,6 @@ __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I
         const uint64_t it = list_inbox[item];
         const int ci = item_cut(it), e = item_elem(it);
         const CutInst &c = I[ci];
-        const float *__restrict__ fbox = c.fbox;
         const int8_t *prev = c.prev;
         const double sweep = c.sweep;
         const BinGrid G = c.params->grid;
@@ -550,9 +563,8 @@ __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I
         box_bins(G, wb, lo, hi);
         const BinRange R = make_range(lo, hi);
         int nc = 0, nw = 0;
-        walk_faces(G, R, bstart, bitems, L, [&](int f, const int *xyz) {
+        walk_faces(G, R, bstart, brec, L, [&](int f, const float *fb, const int *xyz) {
             if (f >= 0) {
-                const float *fb = fbox + (int64_t)f * 6;
                 if (first_common_bin(G, fb, xyz, lo)) {
                     nc += box_overlap(eb, fb);
                     nw += box_overlap(wb, fb);
@@ -575,7 +587,7 @@ __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I
         }
         if (tot == 0 && totw > 0) {
             __syncthreads();   // the ray walk reuses L
-            ray_item(c, bin_start, bitems, e, L);
+            ray_item(c, bin_start, brec, e, L);
         }
     }
 }
@@ -673,7 +685,7 @@ __device__ inline void query_bins(const BinGrid &G, d3 p, double r, int *lo, int
 struct ExactArgs {
     const CutInst *insts;
     const int32_t *bin_start;
-    const int32_t *bitems;
+    const float4 *brec;         // bin records (k_bin_fill)
     const uint64_t *list_inbox;
     uint8_t *stat;              // k_hit takes ST_NEAR items and marks them ST_HIT or ST_SIDE
     CutCounters *cnt;
@@ -718,7 +730,6 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         const CutInst &c = a.insts[ci];
         const BinGrid G = c.params->grid;
         const int32_t *bstart = a.bin_start + c.params->bin_off;
-        const float *__restrict__ fboxc = c.fbox;
         const double *__restrict__ pnodes = c.pnodes;
         __syncthreads();
         for (int k = lane; k < 81; k += 64) sX[k] = c.enodes[(int64_t)e * 81 + k];
@@ -805,10 +816,9 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
             }
             nlist = 0;
         };
-        walk_faces(G, R, bstart, a.bitems, L, [&](int f, const int *xyz) {
+        walk_faces(G, R, bstart, a.brec, L, [&](int f, const float *fb, const int *xyz) {
             bool pass = false;
             if (f >= 0) {
-                const float *fb = fboxc + (int64_t)f * 6;
                 if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb)) {
                     const double fd[6] = {fb[0], fb[1], fb[2], fb[3], fb[4], fb[5]};
                     for (int q = 0; q < 6; ++q) pass |= boxes_meet(sEF + 6 * q, fd);
@@ -925,7 +935,6 @@ __device__ inline void side_items(const ExactArgs &a)
         const CutInst &c = *cp;
         const BinGrid G = c.params->grid;
         const int32_t *bstart = a.bin_start + c.params->bin_off;
-        const float *__restrict__ fboxc = c.fbox;
         const double *__restrict__ pnodes = c.pnodes;
         // stage 1: upper bound, the nearest node of the element's candidate
         // faces (every face node lies on the surface; U only sizes stage 2)
@@ -936,9 +945,8 @@ __device__ inline void side_items(const ExactArgs &a)
             int lo[3], hi[3];
             box_bins(G, eb, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, bstart, a.bitems, L[part], [&](int f, const int *xyz) {
+            walk_faces(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
                 if (f >= 0) {
-                    const float *fb = fboxc + (int64_t)f * 6;
                     if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb) && point_box_dist(p, fb) < u) {
                         const double *P = pnodes + (int64_t)f * 27;
                         double d2 = INFINITY;
@@ -965,9 +973,8 @@ __device__ inline void side_items(const ExactArgs &a)
             int lo[3], hi[3];
             query_bins(G, p, U, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, bstart, a.bitems, L[part], [&](int f, const int *xyz) {
+            walk_faces(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
                 if (f >= 0) {
-                    const float *fb = fboxc + (int64_t)f * 6;
                     if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
                         best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
                 }
@@ -988,9 +995,8 @@ __device__ inline void side_items(const ExactArgs &a)
             int lo[3], hi[3];
             query_bins(G, p, thr, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, bstart, a.bitems, L[part], [&](int f, const int *xyz) {
+            walk_faces(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
                 if (f >= 0) {
-                    const float *fb = fboxc + (int64_t)f * 6;
                     if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= thr) {
                         const double *P = pnodes + (int64_t)f * 27;
                         for (int s = 0; s < 8; ++s) {
@@ -1348,15 +1354,15 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         LAUNCH(k_bin_count, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_count);
         OC_TRY(scan_exclusive(ctx, st, sl->bin_count, sl->bin_start, need.bins, n_bins_dev, sl->bin_scan_tmp));
         LAUNCH(k_bin_fill, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_start, sl->bin_count,
-               sl->bin_items);
+               sl->bin_rec);
         LAUNCH(k_filter, dim3((unsigned)eblk), dim3((unsigned)ctx->filter_block), sl->insts, n_cut, sl->l_inbox,
                sl->counters);
-        LAUNCH(k_candidates, dim3((unsigned)ctx->exact_waves), dim3(64), sl->insts, sl->bin_start, sl->bin_items,
+        LAUNCH(k_candidates, dim3((unsigned)ctx->exact_waves), dim3(64), sl->insts, sl->bin_start, sl->bin_rec,
                sl->l_inbox, sl->l_stat, sl->l_ncand, sl->counters);
         ExactArgs ea;
         ea.insts = sl->insts;
         ea.bin_start = sl->bin_start;
-        ea.bitems = sl->bin_items;
+        ea.brec = sl->bin_rec;
         ea.list_inbox = sl->l_inbox;
         ea.stat = sl->l_stat;
         ea.cnt = sl->counters;

@@ -180,7 +180,7 @@ static oc_status slot_alloc_cut(oc_slot *sl, CutCaps c)
     OC_TRY(dev_alloc(ctx, o, sizeof(float) * 6 * (size_t)c.faces, (void **)&sl->fbox));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)(c.bins + 1), (void **)&sl->bin_count));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)(c.bins + 1), (void **)&sl->bin_start));
-    OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * 8 * (size_t)c.faces, (void **)&sl->bin_items));
+    OC_TRY(dev_alloc(ctx, o, sizeof(float4) * 2 * 8 * (size_t)c.faces, (void **)&sl->bin_rec));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)scan_tmp_ints(c.bins + 1), (void **)&sl->bin_scan_tmp));
     // bin counts start at zero; every cut returns them to zero
     OC_HIP(hipMemset(sl->bin_count, 0, sizeof(int32_t) * (size_t)(c.bins + 1)));

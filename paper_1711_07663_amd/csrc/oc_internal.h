@@ -208,7 +208,8 @@ struct oc_slot {
     oc::SurfParams *params = nullptr;
     double *pnodes = nullptr;
     float *fbox = nullptr;
-    int32_t *bin_count = nullptr, *bin_start = nullptr, *bin_items = nullptr, *bin_scan_tmp = nullptr;
+    int32_t *bin_count = nullptr, *bin_start = nullptr, *bin_scan_tmp = nullptr;
+    float4 *bin_rec = nullptr;         // bin entries: face box + id (2 x float4 each)
     std::vector<oc::DevBuf> cut_owned;   // the cut scratch above (replaced when the default slot grows)
     std::vector<oc::DevBuf> owned;
 };
