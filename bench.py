@@ -350,6 +350,24 @@ def run_dimpled(a):
         roof_filter = dict(bound="hbm", kernel="k_filter", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                            frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic("k_filter"),
                            algorithmic_bytes_per_launch=bytes_per_launch, avg_launch_us=kf["avg_us"])
+    # the classify kernels (far/near split with ray parity, exact test, side
+    # search, fringe layer) against HBM: their algorithmic bytes per launch
+    # from the cut's counts; they move a few MB and are bound by the latency
+    # of their dependent loads, not by bandwidth
+    cls_bytes = dict(
+        k_candidates=info["n_inbox"] * (8 + 24 + 1 + 4) + info["n_cand_pairs"] * 32,
+        k_hit=info["n_near"] * (8 + 1 + 648) + info["n_cand_pairs"] * (32 + 216),
+        k_side_group=info.get("n_side", 0) * (8 + 1 + 648),
+        k_fringe=info["n_inbox"] * (8 + 1) + info["n_hole"] * (24 + 6))
+    roof_classify = []
+    for kname, nbytes in cls_bytes.items():
+        kc = per_kernel.get(kname)
+        if not kc:
+            continue
+        ach = nbytes / (kc["avg_us"] * 1e-6) / 1e9
+        roof_classify.append(dict(kernel=kname, bound="latency", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s",
+                                  frac=ach / HBM_PEAK_GBS, algorithmic_bytes_per_launch=nbytes,
+                                  avg_launch_us=kc["avg_us"]))
     # dominant kernel of the step; when it is the Newton kernel of the donor
     # search (FP64 VALU bound) its algorithmic FLOP per launch is
     # NEWTON_FLOP x the Newton iterations it ran
@@ -382,7 +400,7 @@ def run_dimpled(a):
                plain_ms_per_step=ms_plain, speedup_vs_plain=ms_plain / ms, slot_equals_plain=bool(same),
                cut_info=info, donor_info=dict(bg_to_shell=st["donor_bg"], shell_to_bg=st["donor_shell"]),
                registration_s=t_reg, per_kernel=per_kernel, per_kernel_overlapped=per_kernel_overlapped,
-               roofline=roof, roofline_filter=roof_filter,
+               roofline=roof, roofline_filter=roof_filter, roofline_classify=roof_classify,
                dominant_kernel=dominant)
     if roof_filter:
         ceil = copy_ceiling_gbs()

@@ -8,8 +8,9 @@
 // a descriptor (CutInst); every stage is one launch for the whole batch:
 //   k_pose_faces                    pose the surface nodes, FP32 face boxes
 //                                   inflated by the hit tolerance, surface box
-//   k_bins_setup / k_bin_count /    uniform bins over each surface box, packed
-//   scan / k_bin_fill               one after another: count, scan, fill (CSR)
+//   k_bin_count / scan /            uniform bins over each surface box (each
+//   k_bin_fill                      cut's bins at a fixed offset, its caps
+//                                   nb_max^3): count, scan, fill (CSR)
 //   k_filter                        stream every element's FP32 box; boxes
 //                                   meeting the surface box go to a list
 //   k_candidates                    element box x binned face boxes: elements
@@ -91,8 +92,8 @@ __device__ inline int item_elem(uint64_t v) { return (int)(uint32_t)v; }
 // one node per lane (lanes 9..15 idle), so the gathers of a face's nodes are
 // issued together; the face box is reduced within the group.  Blocks hold
 // kPoseFaces faces and are flattened over the cuts (pblk0); each block writes
-// the box of its faces to part[block] (ordered ints) and k_bins_setup reduces
-// a cut's blocks (no contended atomics).
+// the box of its faces to part[block] (ordered ints) and every block of
+// k_bin_count reduces its cut's blocks (no contended atomics).
 constexpr int kPoseFaces = kThreads / 16;
 
 __global__ __launch_bounds__(kThreads) void k_pose_faces(const CutInst *__restrict__ I, int n_cut,
@@ -190,75 +191,29 @@ __device__ inline int block_scan_excl(int v, int *total)
     return off + inc - v;
 }
 
-// Bin grid over each cut's surface box, and the cut's first bin in the
-// batch's bin arrays.  The bin edge is at least the largest face box extent
-// (dmax + 2 delta, pose invariant), so a face spans at most two bins per axis
-// and at most 8 bins in total.  One block; the batch's bin total goes to
-// *total.
-__global__ __launch_bounds__(kThreads) void k_bins_setup(const CutInst *__restrict__ I, int n_cut,
-                                                         const int32_t *__restrict__ part, int *total,
-                                                         CutCounters *cnt)
+// Bin grid over a cut's surface box.  The bin edge is at least the largest
+// face box extent (dmax + 2 delta, pose invariant), so a face spans at most
+// two bins per axis and at most 8 bins in total; at most nb_max bins per
+// axis.
+__device__ inline void bin_grid(const float *sbox, float dmax, int nb_max, BinGrid &G, int *n_bins)
 {
-    if (threadIdx.x == 0) {
-        cnt->n_inbox = 0;     // k_filter appends after this kernel
-        cnt->n_sidelist = 0;  // k_hit appends after it
-    }
-    // surface box and bin grid of every cut: one wavefront per cut folds the
-    // cut's per-block partial boxes
-    const int lane = lane_id(), wid = threadIdx.x >> 6;
-    for (int i = wid; i < n_cut; i += kThreads / 64) {
-        SurfParams *sp = I[i].params;
-        const int b0 = I[i].pblk0, nblk = (int)((I[i].n_face + kPoseFaces - 1) / kPoseFaces);
-        int ob[6] = {f2ord(INFINITY), f2ord(INFINITY), f2ord(INFINITY), f2ord(-INFINITY), f2ord(-INFINITY),
-                     f2ord(-INFINITY)};
-        for (int b = b0 + lane; b < b0 + nblk; b += 64)
-            for (int k = 0; k < 6; ++k) {
-                const int v = part[(int64_t)b * 6 + k];
-                ob[k] = k < 3 ? min(ob[k], v) : max(ob[k], v);
-            }
-        for (int k = 0; k < 6; ++k)
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) {
-                const int o = __shfl_xor(ob[k], d, 64);
-                ob[k] = k < 3 ? min(ob[k], o) : max(ob[k], o);
-            }
-        if (lane == 0) {
-            const float dmax = I[i].dmax;
-            const int nb_max = I[i].nb_max;
-            float L = 0.f;
-            for (int k = 0; k < 6; ++k) {
-                sp->sbox[k] = ord2f(ob[k]);
-                L = fmaxf(L, fabsf(sp->sbox[k]));
-            }
-            const float w = (dmax + 2.0f * (1e-7f + ldexpf(L, -20)) + ldexpf(L, -18)) * 1.001f;
-            int nb = 1;
-            for (int a = 0; a < 3; ++a) {
-                float ext = sp->sbox[3 + a] - sp->sbox[a];
-                int n = 1;
-                if (ext > 0.f) {
-                    float q = fminf(floorf(ext / w), (float)nb_max);
-                    n = q < 1.f ? 1 : (int)q;
-                }
-                sp->grid.o[a] = sp->sbox[a];
-                sp->grid.n[a] = n;
-                sp->grid.inv[a] = ext > 0.f ? (float)n / ext : 0.f;
-                nb *= n;
-            }
-            sp->n_bins = nb;
+    float L = 0.f;
+    for (int k = 0; k < 6; ++k) L = fmaxf(L, fabsf(sbox[k]));
+    const float w = (dmax + 2.0f * (1e-7f + ldexpf(L, -20)) + ldexpf(L, -18)) * 1.001f;
+    int nb = 1;
+    for (int a = 0; a < 3; ++a) {
+        float ext = sbox[3 + a] - sbox[a];
+        int n = 1;
+        if (ext > 0.f) {
+            float q = fminf(floorf(ext / w), (float)nb_max);
+            n = q < 1.f ? 1 : (int)q;
         }
+        G.o[a] = sbox[a];
+        G.n[a] = n;
+        G.inv[a] = ext > 0.f ? (float)n / ext : 0.f;
+        nb *= n;
     }
-    __syncthreads();
-    // each cut's first bin in the batch's bin arrays
-    int carry = 0;
-    for (int i0 = 0; i0 < n_cut; i0 += kThreads) {
-        const int i = i0 + (int)threadIdx.x;
-        const int nb = i < n_cut ? I[i].params->n_bins : 0;
-        int tot;
-        const int off = block_scan_excl(nb, &tot);
-        if (i < n_cut) I[i].params->bin_off = carry + off;
-        carry += tot;
-    }
-    if (threadIdx.x == 0) *total = carry;
+    *n_bins = nb;
 }
 
 __device__ inline void box_bins(const BinGrid &G, const float *b, int *lo, int *hi)
@@ -269,20 +224,72 @@ __device__ inline void box_bins(const BinGrid &G, const float *b, int *lo, int *
     }
 }
 
+// Bin counts of every face, after the cut's surface box and bin grid: each
+// block folds its cut's per-pose-block partial boxes (no contended atomics;
+// every block of a cut gets the same grid) and the cut's first block stores
+// the box and grid for the later stages.  A cut's bins start at bin_off0, the
+// sum of the bin caps nb_max^3 of the cuts before it (host side).  The
+// first block also resets the batch's list counters.
 __global__ __launch_bounds__(kThreads) void k_bin_count(const CutInst *__restrict__ I, int n_cut,
-                                                        int32_t *__restrict__ count)
+                                                        const int32_t *__restrict__ part, int32_t *__restrict__ count,
+                                                        CutCounters *cnt)
 {
+    __shared__ int wb[kThreads / 64][6];
+    __shared__ BinGrid sG;
     const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].fblk0; });
     const CutInst &c = I[ci];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        cnt->n_inbox = 0;     // k_filter appends after this kernel
+        cnt->n_sidelist = 0;  // k_hit appends after it
+    }
+    {
+        const int b0 = c.pblk0, nblk = (int)((c.n_face + kPoseFaces - 1) / kPoseFaces);
+        int ob[6] = {f2ord(INFINITY), f2ord(INFINITY), f2ord(INFINITY), f2ord(-INFINITY), f2ord(-INFINITY),
+                     f2ord(-INFINITY)};
+        for (int b = b0 + (int)threadIdx.x; b < b0 + nblk; b += kThreads)
+            for (int k = 0; k < 6; ++k) {
+                const int v = part[(int64_t)b * 6 + k];
+                ob[k] = k < 3 ? min(ob[k], v) : max(ob[k], v);
+            }
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) {
+                const int o = __shfl_xor(ob[k], d, 64);
+                ob[k] = k < 3 ? min(ob[k], o) : max(ob[k], o);
+            }
+        if (lane_id() == 0)
+            for (int k = 0; k < 6; ++k) wb[threadIdx.x >> 6][k] = ob[k];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float sbox[6];
+            for (int k = 0; k < 6; ++k) {
+                int v = wb[0][k];
+                for (int w = 1; w < kThreads / 64; ++w) v = k < 3 ? min(v, wb[w][k]) : max(v, wb[w][k]);
+                sbox[k] = ord2f(v);
+            }
+            BinGrid G;
+            int nb;
+            bin_grid(sbox, c.dmax, c.nb_max, G, &nb);
+            sG = G;
+            if ((int)blockIdx.x == c.fblk0) {
+                SurfParams *sp = c.params;
+                for (int k = 0; k < 6; ++k) sp->sbox[k] = sbox[k];
+                sp->grid = G;
+                sp->n_bins = nb;
+                sp->bin_off = c.bin_off0;
+            }
+        }
+        __syncthreads();
+    }
     const int64_t f = (int64_t)(blockIdx.x - c.fblk0) * blockDim.x + threadIdx.x;
     if (f >= c.n_face) return;
-    const BinGrid G = c.params->grid;
-    int32_t *cnt = count + c.params->bin_off;
+    const BinGrid G = sG;
+    int32_t *cb = count + c.bin_off0;
     int lo[3], hi[3];
     box_bins(G, c.fbox + f * 6, lo, hi);
     for (int z = lo[2]; z <= hi[2]; ++z)
         for (int y = lo[1]; y <= hi[1]; ++y)
-            for (int x = lo[0]; x <= hi[0]; ++x) atomicAdd(&cnt[x + G.n[0] * (y + G.n[1] * z)], 1);
+            for (int x = lo[0]; x <= hi[0]; ++x) atomicAdd(&cb[x + G.n[0] * (y + G.n[1] * z)], 1);
 }
 
 // fill: the count array doubles as the per-bin cursor and ends at zero;
@@ -1280,6 +1287,7 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
     std::vector<CutInst> I;
     std::vector<CutOut> O;
     int64_t fblk = 0, pblk = 0, eblk = 0, face_off = 0, fill_blk = 0, ov_blk = 0, cnt_blk = 0, n_elem_total = 0;
+    int64_t bin_off = 0;
     for (int r = 0; r < n_req; ++r) {
         const CutReq &q = reqs[r];
         const Grid &g = *q.g;
@@ -1323,7 +1331,9 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
             c.write_field = k == 0;
             c.fblk0 = (int)fblk;
             c.pblk0 = (int)pblk;
+            c.bin_off0 = (int)bin_off;
             c.eblk0 = (int)eblk;
+            bin_off += (int64_t)s.nb_max * s.nb_max * s.nb_max;
             fblk += blocks_of(s.n_face, kThreads);
             pblk += blocks_of(s.n_face, kPoseFaces);
             eblk += blocks_of(g.n_elem, (int64_t)ctx->filter_block * 4);
@@ -1342,7 +1352,6 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
     sl->last_n_out = n_out;
     sl->last_cblk = (int)cnt_blk;
     sl->last_outs = O;
-    int32_t *n_bins_dev = sl->scalar + 4;
     if (n_cut) OC_TRY(put_bytes(sl, sl->insts, I.data(), sizeof(CutInst) * I.size()));
     if (fill_blk || ov_blk) OC_TRY(put_bytes(sl, sl->outs, O.data(), sizeof(CutOut) * O.size()));
     if (fill_blk) LAUNCH(k_fill_field, dim3((unsigned)fill_blk), dim3(kThreads), sl->outs, n_out);
@@ -1350,9 +1359,9 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         LAUNCH(k_pose_faces, dim3((unsigned)pblk), dim3(kThreads), sl->insts, n_cut, sl->sbox_part);
         // the bin counts are zero here: zeroed when the slot's arrays were
         // made, and k_bin_fill takes every count back to zero
-        LAUNCH(k_bins_setup, dim3(1), dim3(kThreads), sl->insts, n_cut, sl->sbox_part, n_bins_dev, sl->counters);
-        LAUNCH(k_bin_count, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_count);
-        OC_TRY(scan_exclusive(ctx, st, sl->bin_count, sl->bin_start, need.bins, n_bins_dev, sl->bin_scan_tmp));
+        LAUNCH(k_bin_count, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->sbox_part, sl->bin_count,
+               sl->counters);
+        OC_TRY(scan_exclusive(ctx, st, sl->bin_count, sl->bin_start, bin_off, nullptr, sl->bin_scan_tmp));
         LAUNCH(k_bin_fill, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_start, sl->bin_count,
                sl->bin_rec);
         LAUNCH(k_filter, dim3((unsigned)eblk), dim3((unsigned)ctx->filter_block), sl->insts, n_cut, sl->l_inbox,

@@ -133,7 +133,8 @@ struct CutInst {
     float dmax;
     int nb_max, kind, write_field;
     int fblk0, eblk0;           // first block in face / element flattened launches
-    int pblk0, pad;             // first block of the pose launch (16 faces per block)
+    int pblk0;                  // first block of the pose launch (16 faces per block)
+    int bin_off0;               // first bin of this cut: the bin caps nb_max^3 of the cuts before it
 };
 
 // One output of a batch: the iblank of a grid after all of its cuts.
