@@ -697,6 +697,7 @@ struct ExactArgs {
     uint8_t *stat;              // k_hit takes ST_NEAR items and marks them ST_HIT or ST_SIDE
     CutCounters *cnt;
     int32_t *sidelist;          // the ST_SIDE items, appended by k_hit (count cnt->n_sidelist)
+    double *side_u;             // per side-list entry: nearest node of the faces k_hit tested (bound U, or inf)
 };
 
 constexpr int kSideWaves = 8;        // wavefronts sharing one side item's walks (short lists)
@@ -772,6 +773,10 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
         const BinRange R = make_range(lo, hi);
         bool hit = false;
         int nlist = 0;
+        // nearest node of the faces tested to the element's first node: an
+        // upper bound on its distance to the surface for the side search
+        const double px = sX[0], py = sX[27], pz = sX[54];
+        double u2 = INFINITY;
         // exact test of the listed faces
         int round = 0;   // group size 1, 2, 4 .. kGroup, kept across flushes
         auto flush = [&]() {
@@ -784,6 +789,12 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
                     sF[k] = pnodes[(int64_t)sList[i0 + g] * 27 + (k - 27 * g)];
                 }
                 __syncthreads();
+                for (int k = lane; k < 9 * ng; k += 64) {
+                    const double *F = sF + 27 * (k / 9);
+                    const int q = k % 9;
+                    const double dx = F[q] - px, dy = F[9 + q] - py, dz = F[18 + q] - pz;
+                    u2 = fmin(u2, dx * dx + dy * dy + dz * dz);
+                }
                 if (lane < 8 * ng) {
                     d3 F[3];
                     face_tri(sF + 27 * (lane >> 3), lane & 7, F);
@@ -859,10 +870,15 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
             }
             if (__popcll(__ballot(c)) & 1) hit = true;
         }
+        if (!hit) u2 = wave_min_d(u2);
         if (lane == 0) {
             a.stat[item] = hit ? ST_HIT : ST_SIDE;
             if (hit && c.kind == OC_SURF_WALL) c.iblank[e] = OC_HOLE;
-            if (!hit) a.sidelist[atomicAdd(&a.cnt->n_sidelist, 1)] = item;
+            if (!hit) {
+                const int pos = atomicAdd(&a.cnt->n_sidelist, 1);
+                a.sidelist[pos] = item;
+                a.side_u[pos] = sqrt(u2);
+            }
         }
     }
 }
@@ -944,9 +960,13 @@ __device__ inline void side_items(const ExactArgs &a)
         const int32_t *bstart = a.bin_start + c.params->bin_off;
         const double *__restrict__ pnodes = c.pnodes;
         // stage 1: upper bound, the nearest node of the element's candidate
-        // faces (every face node lies on the surface; U only sizes stage 2)
-        double u = INFINITY;
-        {
+        // faces (every face node lies on the surface; U only sizes stage 2).
+        // k_hit leaves the nearest node of the faces it tested, a bound as
+        // good for stage 2 (B, the minimum over every face within the bound,
+        // does not depend on which bound); the walk runs only without it.
+        const double u_hit = a.side_u[si];
+        double u = u_hit;
+        if (!(u_hit < INFINITY)) {
             float eb[6];
             for (int k = 0; k < 6; ++k) eb[k] = c.ebox[(int64_t)k * c.stride + e];
             int lo[3], hi[3];
@@ -1376,6 +1396,7 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         ea.stat = sl->l_stat;
         ea.cnt = sl->counters;
         ea.sidelist = sl->l_sidelist;
+        ea.side_u = sl->l_sideu;
         LAUNCH(k_hit, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
         LAUNCH(k_side_group, dim3((unsigned)kSideGroups), dim3(64 * kSideWaves), ea);
         // a long list, a wavefront per item (a loop, so few blocks: the launch

@@ -169,6 +169,7 @@ static oc_status slot_alloc_cut(oc_slot *sl, CutCaps c)
     OC_TRY(dev_alloc(ctx, o, sizeof(uint8_t) * (size_t)c.elem_inst, (void **)&sl->l_stat));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)c.elem_inst, (void **)&sl->l_ncand));
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * (size_t)c.elem_inst, (void **)&sl->l_sidelist));
+    OC_TRY(dev_alloc(ctx, o, sizeof(double) * (size_t)c.elem_inst, (void **)&sl->l_sideu));
     // partial boxes of the pose launch: blocks of 16 faces, plus one spare
     // block per cut
     OC_TRY(dev_alloc(ctx, o, sizeof(int32_t) * 6 * (size_t)(c.faces / 16 + 2 * c.cuts + 1),

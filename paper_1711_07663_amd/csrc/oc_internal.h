@@ -201,6 +201,7 @@ struct oc_slot {
     uint8_t *l_stat = nullptr;         // status per in-box item
     int32_t *l_ncand = nullptr;        // candidate faces per in-box item
     int32_t *l_sidelist = nullptr;     // in-box items left to the side search
+    double *l_sideu = nullptr;         // per side-list entry: distance bound from k_hit
     int32_t *sbox_part = nullptr;      // per face block: partial surface box (ordered ints)
     int last_n_cut = 0, last_n_out = 0, last_cblk = 0;
     std::vector<oc::CutOut> last_outs;
