@@ -96,20 +96,44 @@ __device__ inline int item_elem(uint64_t v) { return (int)(uint32_t)v; }
 // k_bin_count reduces its cut's blocks (no contended atomics).
 constexpr int kPoseFaces = kThreads / 16;
 
+// A batch of one cut passes its descriptor by value (one, with dst the
+// slot's descriptor array): block 0 stores it for the later stages, so no
+// separate upload launch is needed.
 __global__ __launch_bounds__(kThreads) void k_pose_faces(const CutInst *__restrict__ I, int n_cut,
-                                                         int32_t *__restrict__ part)
+                                                         int32_t *__restrict__ part, CutInst one, CutInst *dst)
 {
     __shared__ float wb[kThreads / 64][6];
-    const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].pblk0; });
-    const CutInst &c = I[ci];
-    const double *__restrict__ nodes = c.snodes;
-    const int32_t *__restrict__ conn = c.conn;
-    const int64_t n_nodes = c.n_nodes, n_face = c.n_face;
-    double *__restrict__ pnodes = c.pnodes;
-    float *__restrict__ fbox = c.fbox;
-    const Pose pose = *c.pose;
+    const double *__restrict__ nodes;
+    const int32_t *__restrict__ conn;
+    int64_t n_nodes, n_face;
+    double *__restrict__ pnodes;
+    float *__restrict__ fbox;
+    const Pose *pose_p;
+    int pblk0;
+    if (dst) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *dst = one;
+        nodes = one.snodes;
+        conn = one.conn;
+        n_nodes = one.n_nodes;
+        n_face = one.n_face;
+        pnodes = one.pnodes;
+        fbox = one.fbox;
+        pose_p = one.pose;
+        pblk0 = one.pblk0;
+    } else {
+        const CutInst &c = I[block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].pblk0; })];
+        nodes = c.snodes;
+        conn = c.conn;
+        n_nodes = c.n_nodes;
+        n_face = c.n_face;
+        pnodes = c.pnodes;
+        fbox = c.fbox;
+        pose_p = c.pose;
+        pblk0 = c.pblk0;
+    }
+    const Pose pose = *pose_p;
     const int j = threadIdx.x & 15;
-    const int64_t f = (int64_t)(blockIdx.x - c.pblk0) * kPoseFaces + (threadIdx.x >> 4);
+    const int64_t f = (int64_t)(blockIdx.x - pblk0) * kPoseFaces + (threadIdx.x >> 4);
     const bool on = f < n_face && j < 9;
     double xv[3] = {0.0, 0.0, 0.0};
     if (on) {
@@ -1148,24 +1172,53 @@ __global__ void k_stats_reset(CutCounters *cnt)
 
 // outputs with no cutting surface: every element field (blocks flattened
 // over those outputs, kThreads elements per block)
-__global__ __launch_bounds__(kThreads) void k_fill_field(const CutOut *__restrict__ O, int n_out)
+// (a batch of one output passes it by value: O null; block 0 stores it at
+// dst for the later stages)
+__global__ __launch_bounds__(kThreads) void k_fill_field(const CutOut *__restrict__ O, int n_out, CutOut one,
+                                                         CutOut *dst)
 {
-    const int oi = block_owner(n_out, blockIdx.x, [&](int k) { return O[k].fblk0; });
-    const CutOut &o = O[oi];
-    const int64_t e = (int64_t)(blockIdx.x - o.fblk0) * blockDim.x + threadIdx.x;
-    if (e < o.n_elem) o.iblank[e] = OC_FIELD;
+    int8_t *iblank;
+    int64_t n_elem;
+    int fblk0;
+    if (!O) {
+        if (dst && blockIdx.x == 0 && threadIdx.x == 0) *dst = one;
+        iblank = one.iblank;
+        n_elem = one.n_elem;
+        fblk0 = one.fblk0;
+    } else {
+        const CutOut &o = O[block_owner(n_out, blockIdx.x, [&](int k) { return O[k].fblk0; })];
+        iblank = o.iblank;
+        n_elem = o.n_elem;
+        fblk0 = o.fblk0;
+    }
+    const int64_t e = (int64_t)(blockIdx.x - fblk0) * blockDim.x + threadIdx.x;
+    if (e < n_elem) iblank[e] = OC_FIELD;
 }
 
 // elements carrying an overset-tagged face are fringe unless hole (blocks
 // flattened over the outputs' overset lists)
-__global__ __launch_bounds__(kThreads) void k_overset_fringe(const CutOut *__restrict__ O, int n_out)
+__global__ __launch_bounds__(kThreads) void k_overset_fringe(const CutOut *__restrict__ O, int n_out, CutOut one)
 {
-    const int oi = block_owner(n_out, blockIdx.x, [&](int k) { return O[k].oblk0; });
-    const CutOut &o = O[oi];
-    const int64_t i = (int64_t)(blockIdx.x - o.oblk0) * blockDim.x + threadIdx.x;
-    if (i < o.n_overset) {
-        const int e = o.overset[i];
-        if (o.iblank[e] != OC_HOLE) o.iblank[e] = OC_FRINGE;
+    int8_t *iblank;
+    const int32_t *overset;
+    int64_t n_overset;
+    int oblk0;
+    if (!O) {
+        iblank = one.iblank;
+        overset = one.overset;
+        n_overset = one.n_overset;
+        oblk0 = one.oblk0;
+    } else {
+        const CutOut &o = O[block_owner(n_out, blockIdx.x, [&](int k) { return O[k].oblk0; })];
+        iblank = o.iblank;
+        overset = o.overset;
+        n_overset = o.n_overset;
+        oblk0 = o.oblk0;
+    }
+    const int64_t i = (int64_t)(blockIdx.x - oblk0) * blockDim.x + threadIdx.x;
+    if (i < n_overset) {
+        const int e = overset[i];
+        if (iblank[e] != OC_HOLE) iblank[e] = OC_FRINGE;
     }
 }
 
@@ -1372,11 +1425,18 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
     sl->last_n_out = n_out;
     sl->last_cblk = (int)cnt_blk;
     sl->last_outs = O;
-    if (n_cut) OC_TRY(put_bytes(sl, sl->insts, I.data(), sizeof(CutInst) * I.size()));
-    if (fill_blk || ov_blk) OC_TRY(put_bytes(sl, sl->outs, O.data(), sizeof(CutOut) * O.size()));
-    if (fill_blk) LAUNCH(k_fill_field, dim3((unsigned)fill_blk), dim3(kThreads), sl->outs, n_out);
+    // one cut / one output: the descriptor travels by value in the first
+    // kernel that reads it (which stores it for the others)
+    const bool one_cut = n_cut == 1, one_out = n_out == 1;
+    if (n_cut && !one_cut) OC_TRY(put_bytes(sl, sl->insts, I.data(), sizeof(CutInst) * I.size()));
+    if ((fill_blk || ov_blk) && !one_out) OC_TRY(put_bytes(sl, sl->outs, O.data(), sizeof(CutOut) * O.size()));
+    const CutOut o1 = one_out ? O[0] : CutOut{};
+    if (fill_blk)
+        LAUNCH(k_fill_field, dim3((unsigned)fill_blk), dim3(kThreads), one_out ? nullptr : sl->outs, n_out, o1,
+               one_out ? sl->outs : nullptr);
     if (n_cut) {
-        LAUNCH(k_pose_faces, dim3((unsigned)pblk), dim3(kThreads), sl->insts, n_cut, sl->sbox_part);
+        LAUNCH(k_pose_faces, dim3((unsigned)pblk), dim3(kThreads), sl->insts, n_cut, sl->sbox_part,
+               one_cut ? I[0] : CutInst{}, one_cut ? sl->insts : nullptr);
         // the bin counts are zero here: zeroed when the slot's arrays were
         // made, and k_bin_fill takes every count back to zero
         LAUNCH(k_bin_count, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->sbox_part, sl->bin_count,
@@ -1404,7 +1464,8 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         LAUNCH(k_side_solo, dim3((unsigned)std::min(ctx->exact_waves, 4096)), dim3(64), ea);
         LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_inbox, sl->counters);
     }
-    if (ov_blk) LAUNCH(k_overset_fringe, dim3((unsigned)ov_blk), dim3(kThreads), sl->outs, n_out);
+    if (ov_blk)
+        LAUNCH(k_overset_fringe, dim3((unsigned)ov_blk), dim3(kThreads), one_out ? nullptr : sl->outs, n_out, o1);
     OC_HIP(hipGetLastError());
     return OC_OK;
 }
