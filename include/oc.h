@@ -527,6 +527,16 @@ enum {
 };
 oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t *applied);
 
+/* The check word of a checked build (liboc_checked.so, compiled with
+ * OC_CHECKED): its bin walks, pair lists and candidate records validate
+ * every index against the array it reads; a violation sets a bit (1 surface
+ * bin range, 2 surface record's face, 4 donor bin range, 8 donor record's
+ * element, 16 pair's element) and the access is skipped, so the kernels
+ * report bad offsets instead of faulting.  Product builds skip the checks
+ * and leave the word at zero.  Waits for the device; clear != 0 resets the
+ * word; *checked (may be NULL) receives 1 for a checked build. */
+oc_status oc_check_word(oc_ctx *ctx, uint32_t *word, int32_t clear, int32_t *checked);
+
 /* Device bytes currently held by the context. */
 oc_status oc_memory_used(oc_ctx *ctx, int64_t *bytes);
 

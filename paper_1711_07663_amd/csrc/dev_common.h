@@ -13,6 +13,41 @@ namespace oc {
 
 constexpr double kTolHit = OC_TOL_HIT;
 
+// Checked builds (OC_CHECKED): the CSR walks validate every index they read
+// against the size of the array it indexes; a violation sets a bit of the
+// context's check word (oc_check_word) and the access is skipped, so a bad
+// offset is reported instead of faulting.  Product builds trust the indices
+// (the check folds away).
+enum : uint32_t {
+    kChkSurfBin = 1u,    // a surface bin's entry range outside the batch's records
+    kChkSurfFace = 2u,   // a surface bin record naming a face outside its cut
+    kChkDonorBin = 4u,   // a donor bin's entry range outside the grid's records
+    kChkDonorElem = 8u,  // a donor bin record naming an element outside the grid
+    kChkPairElem = 16u   // a (point, element) pair naming an element outside the grid
+};
+__device__ inline bool chk(bool ok, uint32_t *word, uint32_t code)
+{
+#ifdef OC_CHECKED
+    if (!ok && word) atomicOr(word, code);
+    return ok;
+#else
+    (void)ok;
+    (void)word;
+    (void)code;
+    return true;
+#endif
+}
+// a size read from device memory for the checks (checked builds only)
+__device__ inline int64_t chk_size(const int32_t *p)
+{
+#ifdef OC_CHECKED
+    return *p;
+#else
+    (void)p;
+    return INT64_MAX;
+#endif
+}
+
 // Round an FP64 value to the nearest FP32 value not above / not below it.
 __host__ __device__ inline float f32_down(double v)
 {

@@ -462,7 +462,8 @@ struct WalkLds {
 template <class Fn>
 __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int32_t *__restrict__ bstart,
                                   const float4 *__restrict__ brec, WalkLds &L, Fn &&fn, int part = 0,
-                                  int nparts = 1)
+                                  int nparts = 1, int64_t n_rec = INT64_MAX, int64_t n_face = INT64_MAX,
+                                  uint32_t *err = nullptr)
 {
     const int lane = threadIdx.x & 63;
     int chunk = 0;
@@ -474,6 +475,7 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
             const int b = range_bin(G, R, idx, xyz);
             j0 = bstart[b];
             cnt = bstart[b + 1] - j0;
+            if (!chk(j0 >= 0 && cnt >= 0 && (int64_t)j0 + cnt <= n_rec, err, kChkSurfBin)) cnt = 0;
             packed = xyz[0] | (xyz[1] << 10) | (xyz[2] << 20);
         }
         int inc = cnt;
@@ -503,6 +505,7 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
                 const int64_t j = (int64_t)L.j0[lo] + (k - L.pre[lo]);
                 const float4 r0 = brec[2 * j], r1 = brec[2 * j + 1];
                 face = __float_as_int(r0.w);
+                if (!chk(face >= 0 && face < n_face, err, kChkSurfFace)) face = -1;
                 fb[0] = r0.x;
                 fb[1] = r0.y;
                 fb[2] = r0.z;
@@ -523,7 +526,7 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
 // +x ray parity of its first node over the column of bins that holds the
 // ray (one wavefront).
 __device__ inline void ray_item(const CutInst &c, const int32_t *__restrict__ bin_start,
-                                const float4 *__restrict__ brec, int e, WalkLds &L)
+                                const float4 *__restrict__ brec, int e, WalkLds &L, int64_t n_rec, uint32_t *err)
 {
     const int lane = threadIdx.x & 63;
     const SurfParams *sp = c.params;
@@ -554,7 +557,7 @@ __device__ inline void ray_item(const CutInst &c, const int32_t *__restrict__ bi
             }
         }
         return false;
-    });
+    }, 0, 1, n_rec, c.n_face, err);
     const int odd = __popcll(__ballot(par)) & 1;
     if (lane == 0 && odd) c.iblank[e] = OC_HOLE;
 }
@@ -571,9 +574,11 @@ __device__ inline void ray_item(const CutInst &c, const int32_t *__restrict__ bi
 __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I, const int32_t *__restrict__ bin_start,
                                                    const float4 *__restrict__ brec,
                                                    const uint64_t *__restrict__ list_inbox, uint8_t *__restrict__ stat,
-                                                   int32_t *__restrict__ ncand, const CutCounters *cnt)
+                                                   int32_t *__restrict__ ncand, const CutCounters *cnt,
+                                                   int64_t bins_total, uint32_t *err)
 {
     __shared__ WalkLds L;
+    const int64_t n_rec = chk_size(bin_start + bins_total);
     const int n_in = cnt->n_inbox;
     const int lane = threadIdx.x;
     for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
@@ -602,7 +607,7 @@ __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I
                 }
             }
             return false;
-        });
+        }, 0, 1, n_rec, c.n_face, err);
         const long long tot = wave_sum_ll(nc);
         const long long totw = prev ? wave_sum_ll(nw) : 1;
         if (lane == 0) {
@@ -618,7 +623,7 @@ __global__ __launch_bounds__(64) void k_candidates(const CutInst *__restrict__ I
         }
         if (tot == 0 && totw > 0) {
             __syncthreads();   // the ray walk reuses L
-            ray_item(c, bin_start, brec, e, L);
+            ray_item(c, bin_start, brec, e, L, n_rec, err);
         }
     }
 }
@@ -722,6 +727,8 @@ struct ExactArgs {
     CutCounters *cnt;
     int32_t *sidelist;          // the ST_SIDE items, appended by k_hit (count cnt->n_sidelist)
     double *side_u;             // per side-list entry: nearest node of the faces k_hit tested (bound U, or inf)
+    int64_t bins_total;         // bins of the batch (bin_start[bins_total] = records)
+    uint32_t *err;              // the context's check word (checked builds)
 };
 
 constexpr int kSideWaves = 8;        // wavefronts sharing one side item's walks (short lists)
@@ -755,6 +762,7 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
     const int lane = threadIdx.x;
     const int n_in = a.cnt->n_inbox;
     const double tol = kTolHit;
+    const int64_t n_rec = chk_size(a.bin_start + a.bins_total);
     for (int item = blockIdx.x; item < n_in; item += gridDim.x) {
         if (a.stat[item] != ST_NEAR) continue;
         const uint64_t it = a.list_inbox[item];
@@ -876,7 +884,7 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
                 flush();
             }
             return hit;
-        });
+        }, 0, 1, n_rec, c.n_face, a.err);
         if (!hit && nlist > 0) {
             __syncthreads();
             flush();
@@ -972,6 +980,7 @@ __device__ inline void side_items(const ExactArgs &a)
     __shared__ TieRec rec[2 * NW];
     const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
     const int n_side = a.cnt->n_sidelist;
+    const int64_t n_rec = chk_size(a.bin_start + a.bins_total);
     if ((n_side <= kSideGroupMax) != (NW > 1)) return;   // the other kernel takes the list
     for (int si = blockIdx.x; si < n_side; si += gridDim.x) {
         const int item = a.sidelist[si];
@@ -1010,7 +1019,7 @@ __device__ inline void side_items(const ExactArgs &a)
                 }
                 u = wave_min_d(u);
                 return false;
-            }, part, NW);
+            }, part, NW, n_rec, c.n_face, a.err);
         }
         u = wave_min_d(u);
         if (lane == 0) red[part] = u;
@@ -1031,7 +1040,7 @@ __device__ inline void side_items(const ExactArgs &a)
                 }
                 best = wave_min_d(best);
                 return false;
-            }, part, NW);
+            }, part, NW, n_rec, c.n_face, a.err);
         }
         best = wave_min_d(best);
         if (lane == 0) red[part] = best;
@@ -1076,7 +1085,7 @@ __device__ inline void side_items(const ExactArgs &a)
                     }
                 }
                 return false;
-            }, part, NW);
+            }, part, NW, n_rec, c.n_face, a.err);
         }
         tie_wave_first2(b1, b2);
         if (lane == 0) {
@@ -1446,8 +1455,9 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
                sl->bin_rec);
         LAUNCH(k_filter, dim3((unsigned)eblk), dim3((unsigned)ctx->filter_block), sl->insts, n_cut, sl->l_inbox,
                sl->counters);
+        uint32_t *err = reinterpret_cast<uint32_t *>(ctx->dev_scalar) + 8;
         LAUNCH(k_candidates, dim3((unsigned)ctx->exact_waves), dim3(64), sl->insts, sl->bin_start, sl->bin_rec,
-               sl->l_inbox, sl->l_stat, sl->l_ncand, sl->counters);
+               sl->l_inbox, sl->l_stat, sl->l_ncand, sl->counters, bin_off, err);
         ExactArgs ea;
         ea.insts = sl->insts;
         ea.bin_start = sl->bin_start;
@@ -1457,6 +1467,8 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         ea.cnt = sl->counters;
         ea.sidelist = sl->l_sidelist;
         ea.side_u = sl->l_sideu;
+        ea.bins_total = bin_off;
+        ea.err = err;
         LAUNCH(k_hit, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
         LAUNCH(k_side_group, dim3((unsigned)kSideGroups), dim3(64 * kSideWaves), ea);
         // a long list, a wavefront per item (a loop, so few blocks: the launch

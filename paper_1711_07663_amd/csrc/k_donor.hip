@@ -469,10 +469,11 @@ __device__ inline bool obb_has(const float *__restrict__ o, d3 p)
 // candidate test of bin entry j (its record): the axis-aligned control-net
 // box, then the oriented one; *e receives the entry's element
 __device__ inline bool rec_has(const float4 *__restrict__ rec, const float *__restrict__ obox, int64_t j, d3 p,
-                               int *e)
+                               int *e, int64_t n_elem, uint32_t *err)
 {
     const float4 lo = rec[2 * j], hi = rec[2 * j + 1];
     *e = __float_as_int(lo.w);
+    if (!chk(*e >= 0 && *e < n_elem, err, kChkDonorElem)) return false;
     return p.x >= (double)lo.x && p.y >= (double)lo.y && p.z >= (double)lo.z && p.x <= (double)hi.x &&
            p.y <= (double)hi.y && p.z <= (double)hi.z && obb_has(obox + (int64_t)*e * 18, p);
 }
@@ -493,6 +494,9 @@ struct DonorArgs {
     BinGrid G;
     const int32_t *bstart;
     const float4 *brec;    // bin entries as records (k_dbin_records)
+    int64_t n_items;       // bin entries of the grid
+    int64_t n_elem;        // elements of the grid
+    uint32_t *err;         // the context's check word (checked builds)
     const Pose *pose;
     const double *pts;
     int64_t cap;           // point capacity
@@ -567,14 +571,16 @@ __global__ __launch_bounds__(kT) void k_dp_count(DonorArgs a)
                 a.plocal[3 * i + 2] = p.z;
             }
             const int64_t b = point_bin(a.G, p);
-            const int j0 = a.bstart[b], j1 = a.bstart[b + 1];
+            const int j0 = a.bstart[b];
+            int j1 = a.bstart[b + 1];
+            if (!chk(0 <= j0 && j0 <= j1 && j1 <= a.n_items, a.err, kChkDonorBin)) j1 = j0;
             // the group takes the bin's entries L at a time, in order, and
             // keeps the first kCandCache candidates (ascending element id)
             for (int r = j0; r < j1; r += L) {
                 const int j = r + sub;
                 int e = -1;
                 bool has = false;
-                if (j < j1) has = rec_has(a.brec, a.obox, j, p, &e);
+                if (j < j1) has = rec_has(a.brec, a.obox, j, p, &e, a.n_elem, a.err);
                 const unsigned long long m = __ballot(has) & gmask;
                 const int at = c + __popcll(m & below);
                 if (has && at < kCandCache) a.cache[i * kCandCache + at] = e;
@@ -617,12 +623,14 @@ __global__ __launch_bounds__(kT) void k_dp_fill(DonorArgs a)
         }
         const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
         const int64_t b = point_bin(a.G, p);
-        const int j0 = a.bstart[b], j1 = a.bstart[b + 1];
+        const int j0 = a.bstart[b];
+        int j1 = a.bstart[b + 1];
+        if (!chk(0 <= j0 && j0 <= j1 && j1 <= a.n_items, a.err, kChkDonorBin)) j1 = j0;
         for (int r = j0; r < j1; r += L) {
             const int j = r + sub;
             int e = -1;
             bool has = false;
-            if (j < j1) has = rec_has(a.brec, a.obox, j, p, &e);
+            if (j < j1) has = rec_has(a.brec, a.obox, j, p, &e, a.n_elem, a.err);
             const unsigned long long m = __ballot(has) & gmask;
             const int64_t at = q + __popcll(m & below);
             if (has && at < a.pair_cap) {
@@ -655,6 +663,7 @@ __global__ __launch_bounds__(kT) void k_dp_newton(DonorArgs a)
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
     for (int64_t q = wave * kNewtonGroups + grp; q < tot; q += n_waves * kNewtonGroups) {
         const int i = a.pair_pt[q], e = a.pair_el[q];
+        if (!chk(e >= 0 && e < a.n_elem, a.err, kChkPairElem)) continue;   // the whole group (same pair)
         const double *Xg = a.enodes + (int64_t)e * 81 + 27 * d;
         double C[27];
 #pragma unroll
@@ -744,9 +753,12 @@ __global__ __launch_bounds__(kT) void k_dp_final(DonorArgs a)
             ++over;
             const d3 p = mk(a.plocal[3 * i], a.plocal[3 * i + 1], a.plocal[3 * i + 2]);
             const int64_t b = point_bin(a.G, p);
-            for (int j = a.bstart[b]; j < a.bstart[b + 1]; ++j) {
+            const int j0 = a.bstart[b];
+            int j1 = a.bstart[b + 1];
+            if (!chk(0 <= j0 && j0 <= j1 && j1 <= a.n_items, a.err, kChkDonorBin)) j1 = j0;
+            for (int j = j0; j < j1; ++j) {
                 int e;
-                if (!rec_has(a.brec, a.obox, j, p, &e)) continue;
+                if (!rec_has(a.brec, a.obox, j, p, &e, a.n_elem, a.err)) continue;
                 ++extra;
                 if (newton_q2<true>(a.enodes + (int64_t)e * 81, p, a.ediam[e], xi, scratch)) {
                     d = e;
@@ -999,6 +1011,9 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     a.G = g.dgrid;
     a.bstart = g.dbin_start;
     a.brec = g.dbin_rec;
+    a.n_items = g.n_ditems;
+    a.n_elem = g.n_elem;
+    a.err = reinterpret_cast<uint32_t *>(ctx->dev_scalar) + 8;
     a.pose = pose_dev;
     a.pts = pts;
     a.cap = cap;
@@ -1142,6 +1157,9 @@ oc_status donor_noalloc_run(oc_ctx *ctx, Grid &g, const double *pose_host, const
     a.G = g.dgrid;
     a.bstart = g.dbin_start;
     a.brec = g.dbin_rec;
+    a.n_items = g.n_ditems;
+    a.n_elem = g.n_elem;
+    a.err = reinterpret_cast<uint32_t *>(ctx->dev_scalar) + 8;
     a.pose = reinterpret_cast<const Pose *>(base + kNaPose);
     a.pts = pts;
     a.cap = n;

@@ -429,6 +429,14 @@ oc_status oc_create(oc_ctx **out, const oc_config *cfg)
         set_error("oc_create: allocation failed");
         return OC_ENOMEM;
     }
+    // registration flag and the check word of checked builds start at zero
+    if (hipMemset(ctx->dev_scalar, 0, 64) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(ctx->dev_scalar);
+        delete ctx;
+        set_error("oc_create: device memset failed");
+        return OC_EDEVICE;
+    }
     ctx->dflt = new oc_slot();
     oc_status st = slot_init(ctx, ctx->dflt, true);
     if (st != OC_OK) {
@@ -1733,6 +1741,25 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
         return OC_EINVAL;
     }
     if (applied) *applied = v;
+    return OC_OK;
+}
+
+oc_status oc_check_word(oc_ctx *ctx, uint32_t *word, int32_t clear, int32_t *checked)
+{
+    if (!ctx || !word) {
+        set_error("oc_check_word: invalid arguments");
+        return OC_EINVAL;
+    }
+#ifdef OC_CHECKED
+    if (checked) *checked = 1;
+#else
+    if (checked) *checked = 0;
+#endif
+    OC_HIP(hipSetDevice(ctx->device));
+    OC_HIP(hipDeviceSynchronize());
+    uint32_t *w = reinterpret_cast<uint32_t *>(ctx->dev_scalar) + 8;
+    OC_HIP(hipMemcpy(word, w, sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (clear) OC_HIP(hipMemset(w, 0, sizeof(uint32_t)));
     return OC_OK;
 }
 

@@ -16,7 +16,9 @@ import weakref
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboc.so")
+# OC_LIB selects another build of the library (the checked variant,
+# liboc_checked.so, for the bounds-checked test runs)
+LIB_PATH = os.environ.get("OC_LIB") or os.path.join(_HERE, "liboc.so")
 
 OC_OK, OC_EINVAL, OC_ENOMEM, OC_EDEVICE, OC_ENOTFOUND, OC_EBUDGET, OC_EGEOM, OC_ECAPACITY = 0, -1, -2, -3, -4, -5, -6, -7
 OC_ETIMEDOUT = -8
@@ -37,7 +39,7 @@ EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_regi
            "oc_slot_create_batch", "oc_tune", "oc_unblank", "oc_element_points", "oc_ab_faces", "oc_face_points",
            "oc_interp_weights", "oc_slot_ab_faces", "oc_slot_face_points", "oc_slot_interp_weights", "oc_cut_filtered", "oc_slot_unblank", "oc_slot_element_points",
            "oc_submit", "oc_wait", "oc_service_info", "oc_donor_search_noalloc", "oc_noalloc_max_points",
-           "oc_cut_refined", "oc_cancel", "oc_cut_posed", "oc_slot_cut_posed"]
+           "oc_cut_refined", "oc_cancel", "oc_cut_posed", "oc_slot_cut_posed", "oc_check_word"]
 
 
 class OcError(RuntimeError):
@@ -119,6 +121,7 @@ def load(path=LIB_PATH):
         "oc_submit": ([vp, C.POINTER(oc_cut_req), C.POINTER(C.c_uint64)]),
         "oc_wait": ([vp, C.c_uint64, C.c_int32]),
         "oc_cancel": ([vp, C.c_uint64]),
+        "oc_check_word": ([vp, C.POINTER(C.c_uint32), C.c_int32, C.POINTER(C.c_int32)]),
         "oc_cut_posed": ([vp, C.c_int32, dp, i32p, dp, C.c_int32, vp]),
         "oc_slot_cut_posed": ([vp, C.c_int32, vp, i32p, vp, C.c_int32, vp]),
         "oc_service_info": ([vp, C.POINTER(oc_service_stats)]),
@@ -358,6 +361,13 @@ class Context:
             return False
         _check(st)
         return True
+
+    def check_word(self, clear=False):
+        """(word, checked): the bounds-check word of a checked build
+        (liboc_checked.so) and whether this library is one."""
+        w, c = C.c_uint32(0), C.c_int32(0)
+        _check(load().oc_check_word(self._h, C.byref(w), int(bool(clear)), C.byref(c)))
+        return w.value, bool(c.value)
 
     def cancel(self, ticket):
         """Drop a request that is still queued (True); False when it has

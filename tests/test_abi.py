@@ -27,6 +27,14 @@ def test_library_exports_every_declared_symbol():
     assert sorted(oc.EXPORTS) == _declared()
 
 
+def test_checked_library_exports_the_same_symbols():
+    """The bounds-checked variant is the same ABI."""
+    path = os.path.join(ROOT, "paper_1711_07663_amd", "liboc_checked.so")
+    lib = ctypes.CDLL(path)
+    missing = [n for n in _declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
 def test_binding_refuses_missing_library(tmp_path):
     from paper_1711_07663_amd import oc
     import pytest
