@@ -358,6 +358,42 @@ __global__ __launch_bounds__(kT) void k_fr_count(const int8_t *__restrict__ ibla
     }
 }
 
+// count and tile-local write in one pass: tile t's fringe elements in
+// ascending order at tl[t * kFrTile ...] and their number at tcount[t]; the
+// tiles concatenated in order (after a scan of the counts) are the ordered
+// list, read in place by k_fringe_points_t
+__global__ __launch_bounds__(kT) void k_fr_tiles(const int8_t *__restrict__ iblank, int64_t n_elem,
+                                                 int32_t *__restrict__ tcount, int32_t *__restrict__ tl)
+{
+    const int64_t my = (int64_t)blockIdx.x * kFrTile + (int64_t)threadIdx.x * kFrItems;
+    int c = 0;
+    for (int k = 0; k < kFrItems; ++k) {
+        const int64_t i = my + k;
+        if (i < n_elem) c += iblank[i] == OC_FRINGE;
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = c;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    __shared__ int ws[kT / 64];
+    if (lane == 63) ws[wid] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < kT / 64; ++w) {
+        if (w < wid) off += ws[w];
+        tot += ws[w];
+    }
+    if (threadIdx.x == 0) tcount[blockIdx.x] = tot;
+    int pos = (int)((int64_t)blockIdx.x * kFrTile) + off + inc - c;
+    for (int k = 0; k < kFrItems; ++k) {
+        const int64_t i = my + k;
+        if (i < n_elem && iblank[i] == OC_FRINGE) tl[pos++] = (int32_t)i;
+    }
+}
+
 // ordered write of the listed elements (at most cap)
 __global__ __launch_bounds__(kT) void k_fr_write(const int8_t *__restrict__ iblank, const int8_t *__restrict__ prev,
                                                  int64_t n_elem, const int32_t *__restrict__ toff,
@@ -397,17 +433,24 @@ __global__ __launch_bounds__(kT) void k_fr_write(const int8_t *__restrict__ ibla
 // gives NaN points and source -1.
 // a9: 27 Gauss points per listed element.  A block takes 256 consecutive
 // points (at most 11 elements): the elements' nodes are staged in LDS with
-// coalesced loads, then every thread maps its point from LDS.
+// coalesced loads, then every thread maps its point from LDS.  The list is
+// either contiguous (list[q]) or tile-major as k_fr_tiles leaves it (the
+// elements of tile t at tl[t * kFrTile ...], tile offsets toff[0..nt]).
 constexpr int kPtElems = kT / 27 + 2;
+constexpr int kToffLds = 2048;   // tile offsets staged in LDS up to this many tiles
 
-__global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__ enodes, int64_t n_elem,
-                                                      const int32_t *__restrict__ list, const int32_t *__restrict__ nfr,
-                                                      int64_t cap, const Pose *__restrict__ pose_dev,
-                                                      double *__restrict__ pts, int32_t *__restrict__ src,
-                                                      int32_t *__restrict__ n_out)
+template <bool TILED>
+__device__ inline void gauss_points(const double *__restrict__ enodes, int64_t n_elem,
+                                    const int32_t *__restrict__ list, const int32_t *__restrict__ toff, int nt,
+                                    const int32_t *__restrict__ nfr, int64_t cap, const Pose *__restrict__ pose_dev,
+                                    double *__restrict__ pts, int32_t *__restrict__ src, int32_t *__restrict__ n_out)
 {
     __shared__ double sN[kPtElems * 81];
     __shared__ int sE[kPtElems];
+    __shared__ int sT[TILED ? kToffLds : 1];
+    const bool tl_lds = TILED && nt + 1 <= kToffLds;
+    if (tl_lds)
+        for (int k = threadIdx.x; k <= nt; k += kT) sT[k] = toff[k];
     const int64_t total = (int64_t)(*nfr) * 27;
     if (blockIdx.x == 0 && threadIdx.x == 0 && n_out) *n_out = (int32_t)total;
     const int64_t n = total < cap ? total : cap;
@@ -415,8 +458,22 @@ __global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__
     for (int64_t i0 = (int64_t)blockIdx.x * kT; i0 < n; i0 += (int64_t)gridDim.x * kT) {
         const int64_t q0 = i0 / 27, q1 = (i0 + kT < n ? i0 + kT - 1 : n - 1) / 27;
         const int ne = (int)(q1 - q0 + 1);
-        __syncthreads();   // the previous round's points are mapped
-        if ((int)threadIdx.x < ne) sE[threadIdx.x] = list[q0 + threadIdx.x];
+        __syncthreads();   // the previous round's points are mapped (and the offsets staged)
+        if ((int)threadIdx.x < ne) {
+            const int q = (int)(q0 + threadIdx.x);
+            if (TILED) {
+                // the tile holding list position q: the last t with toff[t] <= q
+                int lo = 0, hi = nt - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((tl_lds ? sT[mid] : toff[mid]) <= q) lo = mid;
+                    else hi = mid - 1;
+                }
+                sE[threadIdx.x] = list[(int64_t)lo * kFrTile + (q - (tl_lds ? sT[lo] : toff[lo]))];
+            } else {
+                sE[threadIdx.x] = list[q];
+            }
+        }
         __syncthreads();
         for (int k = threadIdx.x; k < ne * 81; k += kT) {
             const int j = k / 81, e = sE[j];
@@ -446,6 +503,25 @@ __global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__
         pts[3 * i + 2] = w.z;
         if (src) src[i] = e;
     }
+}
+
+__global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__ enodes, int64_t n_elem,
+                                                      const int32_t *__restrict__ list, const int32_t *__restrict__ nfr,
+                                                      int64_t cap, const Pose *__restrict__ pose_dev,
+                                                      double *__restrict__ pts, int32_t *__restrict__ src,
+                                                      int32_t *__restrict__ n_out)
+{
+    gauss_points<false>(enodes, n_elem, list, nullptr, 0, nfr, cap, pose_dev, pts, src, n_out);
+}
+
+// the same over the tile-major list of k_fr_tiles (nfr = toff + nt)
+__global__ __launch_bounds__(kT) void k_fringe_points_t(const double *__restrict__ enodes, int64_t n_elem,
+                                                        const int32_t *__restrict__ tl, const int32_t *__restrict__ toff,
+                                                        int nt, int64_t cap, const Pose *__restrict__ pose_dev,
+                                                        double *__restrict__ pts, int32_t *__restrict__ src,
+                                                        int32_t *__restrict__ n_out)
+{
+    gauss_points<true>(enodes, n_elem, tl, toff, nt, toff + nt, cap, pose_dev, pts, src, n_out);
 }
 
 __device__ inline bool box_has(const float *__restrict__ c, d3 p)
@@ -974,11 +1050,21 @@ oc_status element_points_run(oc_slot *sl, const Grid &g, const Pose *pose_dev, c
 oc_status fringe_points_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const int8_t *iblank, double *pts,
                             int64_t cap, int32_t *n_dev, int64_t *n_host, int32_t *src)
 {
+    oc_ctx *ctx = sl->ctx;
     hipStream_t st = sl->stream;
-    const int32_t *total = nullptr;
-    OC_TRY(list_elements_run(sl, g, iblank, nullptr, nullptr, g.n_elem, &total));
+    OC_TRY(slot_reserve_grid(sl, g));
+    // tile-local lists (one pass), a scan of the tile counts, and the points
+    // read through the tile offsets: no separate ordered write
+    const int64_t nt = std::max<int64_t>((g.n_elem + kFrTile - 1) / kFrTile, 1);
+    int32_t *tcount = sl->fr_tiles, *toff = sl->fr_tiles + (nt + 1);
+    int32_t *tmp = sl->fr_tiles + 2 * (nt + 1);
+    LAUNCH(k_fr_tiles, dim3((unsigned)nt), dim3(kT), iblank, g.n_elem, tcount, sl->list_fringe);
+    OC_TRY(scan_exclusive(ctx, st, tcount, toff, nt, nullptr, tmp));
     int32_t *cnt_out = n_dev ? n_dev : sl->scalar;
-    OC_TRY(element_points_run(sl, g, pose_dev, sl->list_fringe, total, pts, cap, cnt_out, src));
+    const int64_t cap_pts = std::min<int64_t>(cap, 27 * g.n_elem);
+    LAUNCH(k_fringe_points_t, dim3(std::min<unsigned>(blocks(std::max<int64_t>(cap_pts, 1), kT), kLoopBlocks)),
+           dim3(kT), g.enodes, g.n_elem, sl->list_fringe, toff, (int)nt, cap, pose_dev, pts, src, cnt_out);
+    OC_HIP(hipGetLastError());
     if (n_host) {
         int32_t n = 0;
         OC_HIP(hipMemcpyAsync(&n, cnt_out, sizeof(int32_t), hipMemcpyDeviceToHost, st));
