@@ -168,7 +168,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply_direct(const int32_
     }
 }
 
-constexpr int kScanDirectMaxTiles = 1024;
+// the direct apply has each block add the tile sums before it (at most
+// this many: 32 KB of reads for the last block), so scans up to 32 M items
+// need two launches, not three
+constexpr int kScanDirectMaxTiles = 8192;
 
 int64_t scan_tmp_ints(int64_t cap) { return (cap + kScanTile - 1) / kScanTile + 1; }
 int64_t scan_max_items() { return (int64_t)kScanMaxTiles * kScanTile; }
