@@ -509,6 +509,11 @@ oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len);
  *   OC_TUNE_FILTER_BLOCK arg unused; value = threads per block of the
  *                        element-box filter (64, 128, 256, 512 or 1024, four
  *                        elements per thread; 0 = 256).
+ *   OC_TUNE_POINT_TILES  arg unused; value = most tiles of the fringe list
+ *                        (4096 elements each) for which every block of the
+ *                        receptor-point kernel forms the tiles' offsets
+ *                        itself from their counts (1 .. 2048, 0 = 2048);
+ *                        larger grids take a scan launch for them.
  *   OC_TUNE_HBM_BUDGET   arg unused; value = the context's HBM budget in
  *                        bytes (0 = none), as oc_config.hbm_budget; later
  *                        allocations are held to it, memory already held is
@@ -523,7 +528,8 @@ enum {
     OC_TUNE_HBM_BUDGET = 4,
     OC_TUNE_DONOR_WAVES = 5,
     OC_TUNE_DONOR_PAIRS = 6,
-    OC_TUNE_FILTER_BLOCK = 7
+    OC_TUNE_FILTER_BLOCK = 7,
+    OC_TUNE_POINT_TILES = 8
 };
 oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t *applied);
 

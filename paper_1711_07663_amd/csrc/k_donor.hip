@@ -439,7 +439,10 @@ __global__ __launch_bounds__(kT) void k_fr_write(const int8_t *__restrict__ ibla
 constexpr int kPtElems = kT / 27 + 2;
 constexpr int kToffLds = 2048;   // tile offsets staged in LDS up to this many tiles
 
-template <bool TILED>
+// MODE 0: a contiguous list; 1: tile-major with the tile offsets toff[0..nt];
+// 2: tile-major with the tile counts (nt <= kToffLds), each block forming the
+// offsets itself in LDS (no scan launch)
+template <int MODE>
 __device__ inline void gauss_points(const double *__restrict__ enodes, int64_t n_elem,
                                     const int32_t *__restrict__ list, const int32_t *__restrict__ toff, int nt,
                                     const int32_t *__restrict__ nfr, int64_t cap, const Pose *__restrict__ pose_dev,
@@ -447,11 +450,45 @@ __device__ inline void gauss_points(const double *__restrict__ enodes, int64_t n
 {
     __shared__ double sN[kPtElems * 81];
     __shared__ int sE[kPtElems];
-    __shared__ int sT[TILED ? kToffLds : 1];
-    const bool tl_lds = TILED && nt + 1 <= kToffLds;
-    if (tl_lds)
-        for (int k = threadIdx.x; k <= nt; k += kT) sT[k] = toff[k];
-    const int64_t total = (int64_t)(*nfr) * 27;
+    __shared__ int sT[MODE ? kToffLds + 1 : 1];
+    __shared__ int sW[kT / 64];
+    const bool tl_lds = MODE == 2 || (MODE == 1 && nt + 1 <= kToffLds);
+    int64_t total;
+    if (MODE == 2) {
+        // exclusive prefix of the tile counts: a contiguous run per thread,
+        // then a block scan of the runs' sums
+        const int per = (nt + kT - 1) / kT, lo = (int)threadIdx.x * per;
+        int run = 0;
+        for (int k = 0; k < per; ++k)
+            if (lo + k < nt) run += toff[lo + k];
+        const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        int inc = run;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        if (lane == 63) sW[wid] = inc;
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < kT / 64; ++w) {
+            if (w < wid) off += sW[w];
+            tot += sW[w];
+        }
+        int p = off + inc - run;
+        for (int k = 0; k < per; ++k)
+            if (lo + k < nt) {
+                const int v = toff[lo + k];
+                sT[lo + k] = p;
+                p += v;
+            }
+        if (threadIdx.x == 0) sT[nt] = tot;
+        total = (int64_t)tot * 27;
+    } else {
+        if (tl_lds)
+            for (int k = threadIdx.x; k <= nt; k += kT) sT[k] = toff[k];
+        total = (int64_t)(*nfr) * 27;
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0 && n_out) *n_out = (int32_t)total;
     const int64_t n = total < cap ? total : cap;
     const Pose pose = *pose_dev;
@@ -461,8 +498,8 @@ __device__ inline void gauss_points(const double *__restrict__ enodes, int64_t n
         __syncthreads();   // the previous round's points are mapped (and the offsets staged)
         if ((int)threadIdx.x < ne) {
             const int q = (int)(q0 + threadIdx.x);
-            if (TILED) {
-                // the tile holding list position q: the last t with toff[t] <= q
+            if (MODE) {
+                // the tile holding list position q: the last t with offset <= q
                 int lo = 0, hi = nt - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
@@ -511,17 +548,21 @@ __global__ __launch_bounds__(kT) void k_fringe_points(const double *__restrict__
                                                       double *__restrict__ pts, int32_t *__restrict__ src,
                                                       int32_t *__restrict__ n_out)
 {
-    gauss_points<false>(enodes, n_elem, list, nullptr, 0, nfr, cap, pose_dev, pts, src, n_out);
+    gauss_points<0>(enodes, n_elem, list, nullptr, 0, nfr, cap, pose_dev, pts, src, n_out);
 }
 
-// the same over the tile-major list of k_fr_tiles (nfr = toff + nt)
+// the same over the tile-major list of k_fr_tiles: MODE 1 with the tile
+// offsets toff (nfr = toff + nt), MODE 2 with the tile counts themselves
+// (nt <= kToffLds); one instance per mode keeps one mode's LDS per block
+template <int MODE>
 __global__ __launch_bounds__(kT) void k_fringe_points_t(const double *__restrict__ enodes, int64_t n_elem,
                                                         const int32_t *__restrict__ tl, const int32_t *__restrict__ toff,
                                                         int nt, int64_t cap, const Pose *__restrict__ pose_dev,
                                                         double *__restrict__ pts, int32_t *__restrict__ src,
                                                         int32_t *__restrict__ n_out)
 {
-    gauss_points<true>(enodes, n_elem, tl, toff, nt, toff + nt, cap, pose_dev, pts, src, n_out);
+    gauss_points<MODE>(enodes, n_elem, tl, toff, nt, MODE == 1 ? toff + nt : nullptr, cap, pose_dev, pts, src,
+                       n_out);
 }
 
 __device__ inline bool box_has(const float *__restrict__ c, d3 p)
@@ -1059,11 +1100,19 @@ oc_status fringe_points_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const in
     int32_t *tcount = sl->fr_tiles, *toff = sl->fr_tiles + (nt + 1);
     int32_t *tmp = sl->fr_tiles + 2 * (nt + 1);
     LAUNCH(k_fr_tiles, dim3((unsigned)nt), dim3(kT), iblank, g.n_elem, tcount, sl->list_fringe);
-    OC_TRY(scan_exclusive(ctx, st, tcount, toff, nt, nullptr, tmp));
+    // up to point_tiles (<= kToffLds) tiles every block of the points kernel
+    // forms the tile offsets from the counts itself (no scan launch)
+    const bool counts_only = nt <= std::min(ctx->point_tiles, kToffLds);
+    if (!counts_only) OC_TRY(scan_exclusive(ctx, st, tcount, toff, nt, nullptr, tmp));
     int32_t *cnt_out = n_dev ? n_dev : sl->scalar;
     const int64_t cap_pts = std::min<int64_t>(cap, 27 * g.n_elem);
-    LAUNCH(k_fringe_points_t, dim3(std::min<unsigned>(blocks(std::max<int64_t>(cap_pts, 1), kT), kLoopBlocks)),
-           dim3(kT), g.enodes, g.n_elem, sl->list_fringe, toff, (int)nt, cap, pose_dev, pts, src, cnt_out);
+    const dim3 grid_pts(std::min<unsigned>(blocks(std::max<int64_t>(cap_pts, 1), kT), kLoopBlocks));
+    if (counts_only)
+        LAUNCH(k_fringe_points_t<2>, grid_pts, dim3(kT), g.enodes, g.n_elem, sl->list_fringe, tcount, (int)nt, cap,
+               pose_dev, pts, src, cnt_out);
+    else
+        LAUNCH(k_fringe_points_t<1>, grid_pts, dim3(kT), g.enodes, g.n_elem, sl->list_fringe, toff, (int)nt, cap,
+               pose_dev, pts, src, cnt_out);
     OC_HIP(hipGetLastError());
     if (n_host) {
         int32_t n = 0;

@@ -1676,6 +1676,8 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
             v = ctx->donor_pairs;
         } else if (knob == OC_TUNE_FILTER_BLOCK) {
             v = ctx->filter_block;
+        } else if (knob == OC_TUNE_POINT_TILES) {
+            v = ctx->point_tiles;
         } else if (knob == OC_TUNE_HBM_BUDGET) {
             v = ctx->budget;
         } else {
@@ -1729,6 +1731,13 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
         }
         ctx->filter_block = value == 0 ? 256 : (int)value;
         v = ctx->filter_block;
+    } else if (knob == OC_TUNE_POINT_TILES) {
+        if (value < 0 || value > 2048) {
+            set_error("oc_tune: point tiles out of range (0 .. 2048)");
+            return OC_EINVAL;
+        }
+        ctx->point_tiles = value == 0 ? 2048 : (int)value;
+        v = ctx->point_tiles;
     } else if (knob == OC_TUNE_HBM_BUDGET) {
         if (value < 0) {
             set_error("oc_tune: negative budget");

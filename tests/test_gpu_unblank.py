@@ -174,6 +174,41 @@ def test_fringe_points_first_call_of_context(orc):
         c.close()
 
 
+def test_fringe_points_scan_and_block_offsets(ctx, orc):
+    """The receptor-point kernel locates list positions through the fringe
+    tiles' offsets, formed by every block itself (few tiles) or by a scan
+    launch (OC_TUNE_POINT_TILES below the tile count): both give the
+    oracle's points, bit-identical to each other."""
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("fringe points with block-formed and scanned tile offsets")
+    bg = M.background_grid(40, -1.3, 1.3, amp=0.03)
+    s = M.cube_sphere(6, R=0.7, dimples=24, dimple_a=0.08, dimple_k=0.02)
+    gid = ctx.register_grid(bg.nodes, bg.conn)
+    sid = ctx.register_cut_surface(s.nodes, s.conn)
+    pose = _poses(1)
+    ib = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+    ctx.cut(gid, sid, pose, ib)
+    fr = orc.fringe_elements(ib.cpu().numpy())
+    assert bg.n_elem > 8 * 4096 and fr.size > 100
+    got = []
+    try:
+        for tiles in (0, 1, 3):
+            assert ctx.tune(oc.OC_TUNE_POINT_TILES, 0, tiles) == (tiles or 2048)
+            pts = torch.full((27 * fr.size, 3), 7.0, dtype=torch.float64, device="cuda")
+            src = torch.full((27 * fr.size,), -7, dtype=torch.int32, device="cuda")
+            assert ctx.fringe_points(gid, M.IDENTITY_POSE, ib, pts, src) == 27 * fr.size
+            got.append((pts.cpu().numpy(), src.cpu().numpy()))
+    finally:
+        ctx.tune(oc.OC_TUNE_POINT_TILES, 0, 0)
+    assert np.abs(got[0][0] - orc.fringe_points(bg, fr)).max() <= PT_TOL
+    assert np.array_equal(got[0][1], np.repeat(fr, 27))
+    for p, q in got[1:]:
+        assert np.array_equal(p, got[0][0]) and np.array_equal(q, got[0][1])
+    with pytest.raises(oc.OcError):
+        ctx.tune(oc.OC_TUNE_POINT_TILES, 0, 2049)
+
+
 def test_unblank_step_eager_and_graph(ctx, orc):
     """The capturable unblank step (slot calls, device counts): three eager
     steps, then three replays of the two captured parities, each against
