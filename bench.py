@@ -52,8 +52,9 @@ FP64_VECTOR_PEAK = 78.6        # TFLOP/s, MI355X FP64 vector: 256 CU x 4 SIMD x 
 # algorithmic FLOP per Newton iteration of the donor search: the per-unit
 # figure of the method's Newton step, x(xi) and J = dx/dxi of a 27-node
 # element (27 nodes x 4 values x 3 components multiply-adds) plus the 3x3
-# solve, about 0.7 kFLOP; the axis-by-axis contraction the kernel runs does
-# the same map in 590
+# solve, about 0.7 kFLOP; the kernel evaluates the same map from its
+# monomial coefficients by nested Horner steps (49 multiply-adds per
+# coordinate)
 NEWTON_FLOP = 700
 
 

@@ -107,6 +107,21 @@ __device__ inline bool newton_q2(const double *__restrict__ Xg, d3 p, double dia
 }
 
 // ---------------------------------------------- registration kernels -----
+// per (element, coordinate): the map's monomial coefficients (q2_mono), read
+// by the Newton solves of the donor search
+__global__ __launch_bounds__(kT) void k_elem_mono(const double *__restrict__ enodes, int64_t n_elem,
+                                                  double *__restrict__ emono)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_elem * 3) return;
+    double M[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) M[k] = enodes[i * 27 + k];
+    q2_mono(M);
+#pragma unroll
+    for (int k = 0; k < 27; ++k) emono[i * 27 + k] = M[k];
+}
+
 __global__ __launch_bounds__(kT) void k_gather_nodes(const double *__restrict__ nodes,
                                                      const int32_t *__restrict__ conn, int64_t n_elem,
                                                      double *__restrict__ enodes)
@@ -605,6 +620,7 @@ __device__ inline int64_t point_bin(const BinGrid &G, d3 p)
 
 struct DonorArgs {
     const double *enodes;
+    const double *emono;   // monomial coefficients of the elements' maps (k_elem_mono)
     const float *cbox;
     const float *obox;
     const double *ediam;
@@ -760,8 +776,9 @@ __global__ __launch_bounds__(kT) void k_dp_fill(DonorArgs a)
 }
 
 // a11: Newton on every pair, three lanes each: lane d of a group holds
-// coordinate d of the element's 27 nodes and evaluates component d of x(xi)
-// and row d of J (q2_map_comp); the group shares them and every lane takes
+// coordinate d of the element's map as 27 monomial coefficients and
+// evaluates component d of the residual and row d of J (q2_mono_comp, nested
+// Horner steps); the group shares them and every lane takes
 // the same step (the steps of newton_q2), so the three stay in lock step and
 // agree bit for bit.  21 groups per wavefront, lane 63
 // idle.  A point keeps the lowest element id that contains it, and a
@@ -781,12 +798,15 @@ __global__ __launch_bounds__(kT) void k_dp_newton(DonorArgs a)
     for (int64_t q = wave * kNewtonGroups + grp; q < tot; q += n_waves * kNewtonGroups) {
         const int i = a.pair_pt[q], e = a.pair_el[q];
         if (!chk(e >= 0 && e < a.n_elem, a.err, kChkPairElem)) continue;   // the whole group (same pair)
-        const double *Xg = a.enodes + (int64_t)e * 81 + 27 * d;
-        double C[27];
+        const double *Mg = a.emono + (int64_t)e * 81 + 27 * d;
+        double M[27];
 #pragma unroll
-        for (int k = 0; k < 27; ++k) C[k] = Xg[k];
-        const double px = a.plocal[3 * (int64_t)i], py = a.plocal[3 * (int64_t)i + 1],
-                     pz = a.plocal[3 * (int64_t)i + 2];
+        for (int k = 0; k < 27; ++k) M[k] = Mg[k];
+        // this lane's coordinate taken relative to the centre node (the
+        // constant coefficient): the point's offset from the centre is formed
+        // once, and the map's value is a sum of small terms
+        const double pd = a.plocal[3 * (int64_t)i + d] - M[0];
+        M[0] = 0.0;
         const double rtol = 1e-13 * a.ediam[e], rtol2 = rtol * rtol;
         double xi[3] = {0.0, 0.0, 0.0};
         bool conv = false;
@@ -798,22 +818,23 @@ __global__ __launch_bounds__(kT) void k_dp_newton(DonorArgs a)
             if (it == 0) {
                 // xi = 0: the centre node and half the differences of the
                 // opposite face-centre nodes (as in newton_q2)
-                xd = C[13];
-                jd[0] = 0.5 * (C[14] - C[12]);
-                jd[1] = 0.5 * (C[16] - C[10]);
-                jd[2] = 0.5 * (C[22] - C[4]);
+                xd = 0.0;
+                jd[0] = M[1];
+                jd[1] = M[3];
+                jd[2] = M[9];
             } else {
-                q2_map_comp(C, xi, xd, jd);
+                q2_mono_comp(M, xi, xd, jd);
             }
-            double x[3], J[9];
+            const double rd = pd - xd;
+            double r[3], J[9];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                x[k] = __shfl(xd, base + k, 64);
+                r[k] = __shfl(rd, base + k, 64);
                 J[3 * k] = __shfl(jd[0], base + k, 64);
                 J[3 * k + 1] = __shfl(jd[1], base + k, 64);
                 J[3 * k + 2] = __shfl(jd[2], base + k, 64);
             }
-            const double r0 = px - x[0], r1 = py - x[1], r2 = pz - x[2];
+            const double r0 = r[0], r1 = r[1], r2 = r[2];
             if (r0 * r0 + r1 * r1 + r2 * r2 <= rtol2) {
                 conv = true;
                 break;
@@ -973,6 +994,7 @@ oc_status grid_build_device(oc_ctx *ctx, Grid &g, const int32_t *conn_dev, const
     LAUNCH(k_elem_boxes, dim3(blocks(g.n_elem, kT)), dim3(kT), g.enodes, g.n_elem, g.ebox_stride, g.ebox, g.cbox,
            g.ediam, bad);
     LAUNCH(k_elem_obb, dim3(blocks(g.n_elem, kT)), dim3(kT), g.enodes, g.n_elem, g.cbox, g.obox);
+    LAUNCH(k_elem_mono, dim3(blocks(g.n_elem * 3, kT)), dim3(kT), g.enodes, g.n_elem, g.emono);
     int hbad = 0;
     OC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
     OC_HIP(hipStreamSynchronize(st));
@@ -1140,6 +1162,7 @@ oc_status donor_run(oc_slot *sl, Grid &g, const Pose *pose_dev, const double *pt
     OC_TRY(slot_reserve_points(sl, cap));
     DonorArgs a;
     a.enodes = g.enodes;
+    a.emono = g.emono;
     a.cbox = g.cbox;
     a.obox = g.obox;
     a.ediam = g.ediam;
@@ -1286,6 +1309,7 @@ oc_status donor_noalloc_run(oc_ctx *ctx, Grid &g, const double *pose_host, const
     hipLaunchKernelGGL(k_na_pose, dim3(1), dim3(64), 0, st, P, reinterpret_cast<Pose *>(base + kNaPose));
     DonorArgs a;
     a.enodes = g.enodes;
+    a.emono = g.emono;
     a.cbox = g.cbox;
     a.obox = g.obox;
     a.ediam = g.ediam;

@@ -540,6 +540,7 @@ oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, co
     if ((st = upload(ctx, tmp, conn, (size_t)n_elem * 27, &conn_dev)) != OC_OK) return fail(st);
     const size_t ne = (size_t)n_elem;
     if ((st = dev_alloc(ctx, g->owned, sizeof(double) * ne * 81, (void **)&g->enodes)) != OC_OK) return fail(st);
+    if ((st = dev_alloc(ctx, g->owned, sizeof(double) * ne * 81, (void **)&g->emono)) != OC_OK) return fail(st);
     if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 6 * (size_t)g->ebox_stride, (void **)&g->ebox)) != OC_OK)
         return fail(st);
     if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 6 * ne, (void **)&g->cbox)) != OC_OK) return fail(st);

@@ -71,6 +71,7 @@ struct DevBuf {
 struct Grid {
     int64_t n_elem = 0, n_nodes = 0;
     double *enodes = nullptr;   // [n_elem][81]: x[27], y[27], z[27]
+    double *emono = nullptr;    // [n_elem][81]: the same map's monomial coefficients per coordinate
     float *ebox = nullptr;      // [6][ebox_stride] SoA: xlo ylo zlo xhi yhi zhi (outward FP32)
     int64_t ebox_stride = 0;    // plane stride, n_elem rounded up to 64
     int32_t *nbr = nullptr;     // [n_elem][6], -1 = boundary

@@ -85,6 +85,59 @@ __device__ inline void q2_map_comp(const double *C, const double *xi, double &xd
     Jd[2] = U[0] * dc[0] + U[1] * dc[1] + U[2] * dc[2];
 }
 
+// The same polynomial in the monomial basis: one coordinate's 27 node values
+// (order a + 3b + 9c) are replaced in place by the coefficients of
+// xi^a eta^b zeta^c.  Per axis, the values v0, v1, v2 at -1, 0, 1 of a
+// quadratic are v1 + s (v2 - v0) / 2 + s^2 ((v0 + v2) / 2 - v1).  The
+// constant coefficient is the centre node itself.
+__device__ inline void q2_mono(double *M)
+{
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int S = ax == 0 ? 1 : (ax == 1 ? 3 : 9);
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            // the nine lines along axis ax: offsets over the other two axes
+            const int u = l % 3, v = l / 3;
+            const int o = ax == 0 ? 3 * u + 9 * v : (ax == 1 ? u + 9 * v : u + 3 * v);
+            const double v0 = M[o], v1 = M[o + S], v2 = M[o + 2 * S];
+            M[o] = v1;
+            M[o + S] = 0.5 * (v2 - v0);
+            M[o + 2 * S] = 0.5 * (v0 + v2) - v1;
+        }
+    }
+}
+
+// Value and gradient of one coordinate from its monomial coefficients M
+// (q2_mono) by nested Horner steps along xi, eta, zeta: 49 fused
+// multiply-adds; each derivative reuses the inner Horner term
+// (p' = h + s m2 where p = m0 + s h, h = m1 + s m2).
+__device__ inline void q2_mono_comp(const double *M, const double *xi, double &xd, double *Jd)
+{
+    const double s = xi[0], t = xi[1], u = xi[2];
+    double Q[3], Qe[3], Sx[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double P[3], D[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const double *m = M + 3 * b + 9 * c;
+            const double h = fma(s, m[2], m[1]);
+            P[b] = fma(s, h, m[0]);
+            D[b] = fma(s, m[2], h);
+        }
+        const double hq = fma(t, P[2], P[1]);
+        Q[c] = fma(t, hq, P[0]);
+        Qe[c] = fma(t, P[2], hq);
+        Sx[c] = fma(t, fma(t, D[2], D[1]), D[0]);
+    }
+    const double hz = fma(u, Q[2], Q[1]);
+    xd = fma(u, hz, Q[0]);
+    Jd[0] = fma(u, fma(u, Sx[2], Sx[1]), Sx[0]);
+    Jd[1] = fma(u, fma(u, Qe[2], Qe[1]), Qe[0]);
+    Jd[2] = fma(u, Q[2], hz);
+}
+
 // x(xi) and J = dx/dxi of an element stored as x[27], y[27], z[27].  With
 // STREAM the nine node rows are read one at a time (X in global memory, the
 // 81 coordinates never resident together); otherwise X is a register copy
