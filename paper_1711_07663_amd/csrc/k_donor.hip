@@ -795,8 +795,21 @@ __global__ __launch_bounds__(kT) void k_dp_newton(DonorArgs a)
     const int grp = lane / 3, d = lane - 3 * grp, base = 3 * grp;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t q = wave * kNewtonGroups + grp; q < tot; q += n_waves * kNewtonGroups) {
-        const int i = a.pair_pt[q], e = a.pair_el[q];
+    const int64_t qstep = n_waves * kNewtonGroups;
+    int64_t q = wave * kNewtonGroups + grp;
+    // the next pair's ids are loaded while the current pair is solved, so a
+    // pair's coefficient loads start without waiting for its ids
+    int ni = 0, ne = 0;
+    if (q < tot) {
+        ni = a.pair_pt[q];
+        ne = a.pair_el[q];
+    }
+    for (; q < tot; q += qstep) {
+        const int i = ni, e = ne;
+        if (q + qstep < tot) {
+            ni = a.pair_pt[q + qstep];
+            ne = a.pair_el[q + qstep];
+        }
         if (!chk(e >= 0 && e < a.n_elem, a.err, kChkPairElem)) continue;   // the whole group (same pair)
         const double *Mg = a.emono + (int64_t)e * 81 + 27 * d;
         double M[27];
