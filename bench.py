@@ -81,6 +81,40 @@ def kernel_source_sha(kernel):
     return h.hexdigest()
 
 
+def filter_bytes(grid, surf_nodes, pose, wave=256):
+    """Bytes k_filter moves for the cut of ``grid`` by a surface at ``pose``
+    (grid frame): every wavefront of 256 consecutive elements reads their
+    union box (24 B); if it meets the surface box, the z planes of the
+    elements' FP32 boxes (8 B per element), then the y planes only if some
+    element's z range meets the surface box, the x planes only if some
+    element meets it in z and y; every element's iblank byte is written, and
+    a ragged tail reads the planes of its elements.  The boxes are the node
+    boxes and the surface box is the posed nodes' box widened by 1e-5 (the
+    kernel's FP32 boxes round outward by less), so this models the kernel's
+    early exits on the host."""
+    R = np.asarray(pose[:9], dtype=np.float64).reshape(3, 3)
+    Y = np.asarray(surf_nodes, dtype=np.float64) @ R.T + np.asarray(pose[9:12], dtype=np.float64)
+    slo, shi = Y.min(axis=0) - 1e-5, Y.max(axis=0) + 1e-5
+    n = grid.n_elem
+    nw = n // wave
+    full = nw * wave
+    lo, hi = [], []
+    for d in range(3):
+        c = grid.nodes[:, d][grid.conn[:full]]
+        lo.append(c.min(axis=1))
+        hi.append(c.max(axis=1))
+        del c
+    meets = np.ones(nw, dtype=bool)
+    for d in range(3):
+        meets &= (lo[d].reshape(nw, wave).min(axis=1) <= shi[d]) & (hi[d].reshape(nw, wave).max(axis=1) >= slo[d])
+    live = np.repeat(meets, wave)
+    nbytes = 24.0 * (nw + (n > full))
+    for d in (2, 1, 0):
+        nbytes += 8.0 * wave * int(live.reshape(nw, wave).any(axis=1).sum())
+        live &= (lo[d] <= shi[d]) & (hi[d] >= slo[d])
+    return nbytes + 24.0 * (n - full) + 1.0 * n
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of ``kernel`` from the committed profiler
     summary profiles/<kernel>_traffic_dimpled128.md (FETCH_SIZE and
@@ -341,12 +375,13 @@ def run_dimpled(a):
 
     n_pts = counts["n_bg_points"] + sum(counts["n_shell_points"])
     value = bg.n_elem / (ms / 1e3)
-    # roofline of the streaming filter (HBM bound): per element its FP32 box
-    # (24 B) is read and its iblank (1 B) written
+    # roofline of the streaming filter (HBM bound): per element the planes of
+    # its FP32 box that the wavefront's early exits leave to read (at most
+    # 24 B) and its iblank (1 B) written
     kf = per_kernel.get("k_filter")
     roof_filter = None
     if kf:
-        bytes_per_launch = 25.0 * bg.n_elem
+        bytes_per_launch = filter_bytes(bg, case["bodies"][0]["surface"].nodes, case["poses"][0])
         achieved = bytes_per_launch / (kf["avg_us"] * 1e-6) / 1e9
         roof_filter = dict(bound="hbm", kernel="k_filter", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                            frac=achieved / HBM_PEAK_GBS, traffic=measured_traffic("k_filter"),
@@ -864,7 +899,7 @@ def run_batch(a):
     torch.cuda.set_device(0)
     ctx = oc.Context(device=0)
     log("generating and registering %d instances" % len(specs))
-    reqs, plain_args, n_tot, n_face = [], [], 0, 0
+    reqs, plain_args, n_tot, n_face, f_bytes = [], [], 0, 0, 0.0
     poses = torch.zeros((len(specs), 12), dtype=torch.float64, device="cuda")
     host_poses = np.stack([np.asarray(sp["pose"], dtype=np.float64) for sp in specs])
     poses.copy_(torch.from_numpy(host_poses))
@@ -880,6 +915,7 @@ def run_batch(a):
         plain_args.append((gid, sid, host_poses[i], bgm.n_elem))
         n_tot += bgm.n_elem
         n_face += surf.n_face
+        f_bytes += filter_bytes(bgm, surf.nodes, host_poses[i])
         del bgm, surf
     log("batch of %d instances, %d elements, %d faces" % (len(specs), n_tot, n_face))
     # eager batches on the default slot, before and after autotuning
@@ -964,9 +1000,9 @@ def run_batch(a):
     kf = per_kernel.get("k_filter")
     roof = None
     if kf:
-        achieved = 25.0 * n_tot / (kf["avg_us"] * 1e-6) / 1e9
+        achieved = f_bytes / (kf["avg_us"] * 1e-6) / 1e9
         roof = dict(bound="hbm", kernel="k_filter", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=25.0 * n_tot,
+                    frac=achieved / HBM_PEAK_GBS, traffic=None, algorithmic_bytes_per_launch=f_bytes,
                     avg_launch_us=kf["avg_us"])
     out = dict(metric="elements cut+classified/s and donors/s per step; p50/p99 connectivity latency",
                value=n_tot / t_batch, unit="elements/s", n_gpus=1, steps=a.steps, warmup=a.warmup,

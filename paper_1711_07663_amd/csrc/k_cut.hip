@@ -346,54 +346,118 @@ __global__ __launch_bounds__(kThreads) void k_bin_fill(const CutInst *__restrict
 }
 
 // ---------------------------------------------------------- element stage --
+// In-box bits of the four elements e0 .. e0 + 3 (their FP32 boxes in SoA
+// planes) against the surface box sb.  The planes are read axis by axis, z
+// first: once no element of the wavefront is left along an axis it reads no
+// further planes (neighbouring elements share their slow coordinates).
+__device__ inline int filter_quad(const float *__restrict__ ebox, int64_t stride, int64_t e0, const float *sb)
+{
+    int flags = 0;
+#pragma unroll
+    for (int ax = 2; ax >= 0; --ax) {
+        if (ax < 2 && !__ballot(flags != 0)) return 0;
+        const float4 l = *reinterpret_cast<const float4 *>(ebox + ax * stride + e0);
+        const float4 h = *reinterpret_cast<const float4 *>(ebox + (3 + ax) * stride + e0);
+        const float L[4] = {l.x, l.y, l.z, l.w}, H[4] = {h.x, h.y, h.z, h.w};
+        int in = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in |= (int)(L[k] <= sb[3 + ax] && H[k] >= sb[ax]) << k;
+        flags = ax == 2 ? in : (flags & in);
+    }
+    return flags;
+}
+
 // a3, streaming part: every element's FP32 box (SoA planes, 4 elements per
 // thread) is tested against its cut's surface box.  The first cut of an
 // output also initialises its iblank to field.  Blocks are flattened over
 // the cuts, 1024 elements per block.
-__global__ __launch_bounds__(1024) void k_filter(const CutInst *__restrict__ I, int n_cut,
-                                                     uint64_t *__restrict__ list_inbox, CutCounters *cnt)
+__global__ __launch_bounds__(1024) void k_filter(const CutInst *__restrict__ I, int n_cut, CutInst one, int use_one,
+                                                 uint64_t *__restrict__ list_inbox, CutCounters *cnt)
 {
-    const int ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].eblk0; });
-    const CutInst &c = I[ci];
-    const float *__restrict__ ebox = c.ebox;
-    const int64_t stride_e = c.stride, n_elem = c.n_elem;
-    int8_t *__restrict__ iblank = c.iblank;
-    const int write_field = c.write_field;
-    const SurfParams *sp = c.params;
-    const float s0 = sp->sbox[0], s1 = sp->sbox[1], s2 = sp->sbox[2];
-    const float s3 = sp->sbox[3], s4 = sp->sbox[4], s5 = sp->sbox[5];
-    const int64_t e0 = ((int64_t)(blockIdx.x - c.eblk0) * blockDim.x + threadIdx.x) * 4;
-    if (e0 - (int64_t)lane_id() * 4 >= n_elem) return;   // whole wavefront past the end
-    int flags = 0, cn = 0;
-    if (e0 + 3 < n_elem) {
-        const float4 xl = *reinterpret_cast<const float4 *>(ebox + e0);
-        const float4 yl = *reinterpret_cast<const float4 *>(ebox + stride_e + e0);
-        const float4 zl = *reinterpret_cast<const float4 *>(ebox + 2 * stride_e + e0);
-        const float4 xh = *reinterpret_cast<const float4 *>(ebox + 3 * stride_e + e0);
-        const float4 yh = *reinterpret_cast<const float4 *>(ebox + 4 * stride_e + e0);
-        const float4 zh = *reinterpret_cast<const float4 *>(ebox + 5 * stride_e + e0);
-        const float L0[4] = {xl.x, xl.y, xl.z, xl.w}, L1[4] = {yl.x, yl.y, yl.z, yl.w};
-        const float L2[4] = {zl.x, zl.y, zl.z, zl.w}, H0[4] = {xh.x, xh.y, xh.z, xh.w};
-        const float H1[4] = {yh.x, yh.y, yh.z, yh.w}, H2[4] = {zh.x, zh.y, zh.z, zh.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            bool in = L0[k] <= s3 && H0[k] >= s0 && L1[k] <= s4 && H1[k] >= s1 && L2[k] <= s5 && H2[k] >= s2;
-            flags |= (int)in << k;
-            cn += in;
-        }
-        if (write_field) *reinterpret_cast<uint32_t *>(iblank + e0) = 0x01010101u;
+    // a batch of one cut passes its descriptor by value (no dependent load
+    // of it before the element loads)
+    int ci = 0;
+    const float *__restrict__ ebox;
+    const float *__restrict__ wbox;
+    int64_t stride_e, n_elem;
+    int8_t *__restrict__ iblank;
+    int write_field, eblk0;
+    const SurfParams *sp;
+    if (use_one) {
+        ebox = one.ebox;
+        wbox = one.wbox;
+        stride_e = one.stride;
+        n_elem = one.n_elem;
+        iblank = one.iblank;
+        write_field = one.write_field;
+        eblk0 = one.eblk0;
+        sp = one.params;
     } else {
-        for (int k = 0; k < 4; ++k) {
-            int64_t e = e0 + k;
-            if (e >= n_elem) break;
-            bool in = ebox[e] <= s3 && ebox[3 * stride_e + e] >= s0 && ebox[stride_e + e] <= s4 &&
-                      ebox[4 * stride_e + e] >= s1 && ebox[2 * stride_e + e] <= s5 && ebox[5 * stride_e + e] >= s2;
-            flags |= (int)in << k;
-            cn += in;
-            if (write_field) iblank[e] = OC_FIELD;
+        ci = block_owner(n_cut, blockIdx.x, [&](int k) { return I[k].eblk0; });
+        const CutInst &c = I[ci];
+        ebox = c.ebox;
+        wbox = c.wbox;
+        stride_e = c.stride;
+        n_elem = c.n_elem;
+        iblank = c.iblank;
+        write_field = c.write_field;
+        eblk0 = c.eblk0;
+        sp = c.params;
+    }
+    const int64_t e0 = ((int64_t)(blockIdx.x - eblk0) * blockDim.x + threadIdx.x) * 4;
+    int flags = 0, cn = 0;
+    if (e0 - (int64_t)lane_id() * 4 < n_elem) {   // the wavefront has elements
+        const float s0 = sp->sbox[0], s1 = sp->sbox[1], s2 = sp->sbox[2];
+        const float s3 = sp->sbox[3], s4 = sp->sbox[4], s5 = sp->sbox[5];
+        // the wavefront's 256 elements (e0 of its first lane is a multiple
+        // of 256) are skipped together when their union box misses the
+        // surface box
+        bool meets = true;
+        if (wbox) {
+            const float *wb = wbox + (e0 >> 8) * 6;
+            meets = wb[0] <= s3 && wb[3] >= s0 && wb[1] <= s4 && wb[4] >= s1 && wb[2] <= s5 && wb[5] >= s2;
+        }
+        if (e0 + 3 < n_elem) {
+            const float sb[6] = {s0, s1, s2, s3, s4, s5};
+            if (meets) flags = filter_quad(ebox, stride_e, e0, sb);
+            cn = __popc(flags);
+            if (write_field) *reinterpret_cast<uint32_t *>(iblank + e0) = 0x01010101u;
+        } else {
+            for (int k = 0; k < 4; ++k) {
+                int64_t e = e0 + k;
+                if (e >= n_elem) break;
+                bool in = meets && ebox[e] <= s3 && ebox[3 * stride_e + e] >= s0 && ebox[stride_e + e] <= s4 &&
+                          ebox[4 * stride_e + e] >= s1 && ebox[2 * stride_e + e] <= s5 &&
+                          ebox[5 * stride_e + e] >= s2;
+                flags |= (int)in << k;
+                cn += in;
+                if (write_field) iblank[e] = OC_FIELD;
+            }
         }
     }
-    int pos = wave_append(&cnt->n_inbox, cn);
+    // one list reservation per block: the in-box elements cluster, and
+    // appends to one counter from many wavefronts serialise
+    __shared__ int s_tot[1024 / 64 + 1];
+    const int lane = lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int inc = cn;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += t;
+    }
+    if (lane == 63) s_tot[wid] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int w = 0; w < nw; ++w) {
+            const int t = s_tot[w];
+            s_tot[w] = run;
+            run += t;
+        }
+        s_tot[nw] = run > 0 ? atomicAdd(&cnt->n_inbox, run) : 0;
+    }
+    __syncthreads();
+    int pos = s_tot[nw] + s_tot[wid] + inc - cn;
     for (int k = 0; k < 4; ++k)
         if (flags >> k & 1) list_inbox[pos++] = pack_item(ci, (int)(e0 + k));
 }
@@ -1392,6 +1456,7 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
             CutInst c{};
             c.enodes = g.enodes;
             c.ebox = g.ebox;
+            c.wbox = g.wbox;
             c.nbr = g.nbr;
             c.snodes = s.nodes;
             c.conn = s.conn;
@@ -1453,7 +1518,8 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         OC_TRY(scan_exclusive(ctx, st, sl->bin_count, sl->bin_start, bin_off, nullptr, sl->bin_scan_tmp));
         LAUNCH(k_bin_fill, dim3((unsigned)fblk), dim3(kThreads), sl->insts, n_cut, sl->bin_start, sl->bin_count,
                sl->bin_rec);
-        LAUNCH(k_filter, dim3((unsigned)eblk), dim3((unsigned)ctx->filter_block), sl->insts, n_cut, sl->l_inbox,
+        LAUNCH(k_filter, dim3((unsigned)eblk), dim3((unsigned)ctx->filter_block), sl->insts, n_cut,
+               one_cut ? I[0] : CutInst{}, (int)one_cut, sl->l_inbox,
                sl->counters);
         uint32_t *err = reinterpret_cast<uint32_t *>(ctx->dev_scalar) + 8;
         LAUNCH(k_candidates, dim3((unsigned)ctx->exact_waves), dim3(64), sl->insts, sl->bin_start, sl->bin_rec,

@@ -107,6 +107,35 @@ __device__ inline bool newton_q2(const double *__restrict__ Xg, d3 p, double dia
 }
 
 // ---------------------------------------------- registration kernels -----
+// the union of the FP32 boxes of every 256 consecutive elements (one block of
+// 64 lanes, four elements each): the element filter's wavefront skips its
+// elements' boxes when this box misses the surface box
+__global__ __launch_bounds__(64) void k_wave_boxes(const float *__restrict__ ebox, int64_t stride, int64_t n_elem,
+                                                   float *__restrict__ wbox)
+{
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t base = (int64_t)blockIdx.x * 256 + 4 * threadIdx.x;
+    for (int k = 0; k < 4; ++k) {
+        const int64_t e = base + k;
+        if (e >= n_elem) break;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fminf(lo[d], ebox[d * stride + e]);
+            hi[d] = fmaxf(hi[d], ebox[(3 + d) * stride + e]);
+        }
+    }
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fminf(lo[d], __shfl_xor(lo[d], s, 64));
+            hi[d] = fmaxf(hi[d], __shfl_xor(hi[d], s, 64));
+        }
+    if (threadIdx.x == 0)
+        for (int d = 0; d < 3; ++d) {
+            wbox[blockIdx.x * 6 + d] = lo[d];
+            wbox[blockIdx.x * 6 + 3 + d] = hi[d];
+        }
+}
+
 // per (element, coordinate): the map's monomial coefficients (q2_mono), read
 // by the Newton solves of the donor search
 __global__ __launch_bounds__(kT) void k_elem_mono(const double *__restrict__ enodes, int64_t n_elem,
@@ -1007,6 +1036,7 @@ oc_status grid_build_device(oc_ctx *ctx, Grid &g, const int32_t *conn_dev, const
     LAUNCH(k_elem_boxes, dim3(blocks(g.n_elem, kT)), dim3(kT), g.enodes, g.n_elem, g.ebox_stride, g.ebox, g.cbox,
            g.ediam, bad);
     LAUNCH(k_elem_obb, dim3(blocks(g.n_elem, kT)), dim3(kT), g.enodes, g.n_elem, g.cbox, g.obox);
+    LAUNCH(k_wave_boxes, dim3(blocks(g.n_elem, 256)), dim3(64), g.ebox, g.ebox_stride, g.n_elem, g.wbox);
     LAUNCH(k_elem_mono, dim3(blocks(g.n_elem * 3, kT)), dim3(kT), g.enodes, g.n_elem, g.emono);
     int hbad = 0;
     OC_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));

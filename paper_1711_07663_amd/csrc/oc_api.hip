@@ -543,6 +543,8 @@ oc_status oc_register_grid(oc_ctx *ctx, const double *nodes, int64_t n_nodes, co
     if ((st = dev_alloc(ctx, g->owned, sizeof(double) * ne * 81, (void **)&g->emono)) != OC_OK) return fail(st);
     if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 6 * (size_t)g->ebox_stride, (void **)&g->ebox)) != OC_OK)
         return fail(st);
+    if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 6 * ((ne + 255) / 256), (void **)&g->wbox)) != OC_OK)
+        return fail(st);
     if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 6 * ne, (void **)&g->cbox)) != OC_OK) return fail(st);
     if ((st = dev_alloc(ctx, g->owned, sizeof(float) * 18 * ne, (void **)&g->obox)) != OC_OK) return fail(st);
     if ((st = dev_alloc(ctx, g->owned, sizeof(double) * ne, (void **)&g->ediam)) != OC_OK) return fail(st);

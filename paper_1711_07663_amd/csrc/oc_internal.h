@@ -74,6 +74,7 @@ struct Grid {
     double *emono = nullptr;    // [n_elem][81]: the same map's monomial coefficients per coordinate
     float *ebox = nullptr;      // [6][ebox_stride] SoA: xlo ylo zlo xhi yhi zhi (outward FP32)
     int64_t ebox_stride = 0;    // plane stride, n_elem rounded up to 64
+    float *wbox = nullptr;      // [ceil(n_elem / 256)][6] union of the FP32 boxes of 256 consecutive elements
     int32_t *nbr = nullptr;     // [n_elem][6], -1 = boundary
     int32_t *overset = nullptr; // elements with an OVERSET-tagged face (ascending)
     int64_t n_overset = 0;
@@ -119,6 +120,7 @@ constexpr int kPoseSlots = 256;
 struct CutInst {
     const double *enodes;
     const float *ebox;
+    const float *wbox;          // box of every 256 consecutive elements (null: none)
     const int32_t *nbr;
     const double *snodes;       // surface nodes, [3][n_nodes] registration frame
     const int32_t *conn;        // [n_face][9]
