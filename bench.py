@@ -393,7 +393,7 @@ def run_dimpled(a):
     cls_bytes = dict(
         k_candidates=info["n_inbox"] * (8 + 24 + 1 + 4) + info["n_cand_pairs"] * 32,
         k_hit=info["n_near"] * (8 + 1 + 648) + info["n_cand_pairs"] * (32 + 216),
-        k_side_group=info.get("n_side", 0) * (8 + 1 + 648),
+        k_side=info.get("n_side", 0) * (8 + 1 + 648),
         k_fringe=info["n_inbox"] * (8 + 1) + info["n_hole"] * (24 + 6))
     roof_classify = []
     for kname, nbytes in cls_bytes.items():

@@ -19,7 +19,7 @@
 //                                   parity of the first node
 //   k_hit                           one wavefront per near element: FP64
 //                                   triangle-pair intersection
-//   k_side_group / k_side_solo      near elements not hit: nearest-face side of
+//   k_side                          near elements not hit: nearest-face side of
 //                                   the first node (wavefront minimum + tie rule)
 //   k_fringe / k_overset_fringe     one fringe layer around holes, overset faces
 #include <algorithm>
@@ -503,6 +503,21 @@ __device__ inline bool first_common_bin(const BinGrid &G, const float *fb, const
     return true;
 }
 
+// Orders LDS accesses between the lanes of a workgroup, or with kWave only
+// between those of one wavefront (its LDS operations complete in order, so a
+// wavefront-scope fence that the compiler keeps in place is enough).
+template <bool kWave>
+__device__ inline void group_sync()
+{
+    if constexpr (kWave) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // LDS of one wavefront for walk_faces
 struct WalkLds {
     int pre[64];
@@ -520,10 +535,11 @@ struct WalkLds {
 // operations; it returns true (wave-uniformly) to stop the walk.
 // The walk synchronises its workgroup: every wavefront of the workgroup must
 // walk the same range R (each with its own WalkLds), and only a one-wavefront
-// workgroup may stop early.
+// workgroup may stop early.  With kWave it synchronises only its own
+// wavefront, which then walks alone (nparts = 1) whatever the others do.
 // With nparts > 1 only the chunks of 64 stored faces whose running index is
 // part (mod nparts) are visited, so nparts wavefronts can share one walk.
-template <class Fn>
+template <bool kWave = false, class Fn>
 __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int32_t *__restrict__ bstart,
                                   const float4 *__restrict__ brec, WalkLds &L, Fn &&fn, int part = 0,
                                   int nparts = 1, int64_t n_rec = INT64_MAX, int64_t n_face = INT64_MAX,
@@ -549,11 +565,11 @@ __device__ inline void walk_faces(const BinGrid &G, const BinRange &R, const int
             if (lane >= d) inc += t;
         }
         const int total = __shfl(inc, 63, 64);
-        __syncthreads();
+        group_sync<kWave>();
         L.pre[lane] = inc - cnt;
         L.j0[lane] = j0;
         L.xyz[lane] = packed;
-        __syncthreads();
+        group_sync<kWave>();
         for (int k0 = 0; k0 < total; k0 += 64, ++chunk) {
             if (chunk % nparts != part) continue;
             const int k = k0 + lane;
@@ -1031,22 +1047,20 @@ __device__ inline void tie_wave_first2(TieRec &b1, TieRec &b2)
     }
 }
 
-// NW wavefronts per item.  One of the two kernels takes the whole list,
-// chosen on the device by its length: up to kSideGroupMax items
-// k_side_group (NW = kSideWaves, one workgroup per CU at a time: the
-// latency of a few items), beyond that k_side_solo (NW = 1: throughput when
-// there are many).
-template <int NW>
-__device__ inline void side_items(const ExactArgs &a)
+// The side items si0, si0 + sstep, ... of the list, NW wavefronts per item
+// (kWave: one, synchronising only itself).  Wavefront `part` of the
+// workgroup walks with WalkLds L[part] and reduces through red[part] and
+// rec[2 part], rec[2 part + 1].
+template <int NW, bool kWave>
+__device__ inline void side_items(const ExactArgs &a, int n_side, WalkLds *L, double *red, TieRec *rec, int si0,
+                                  int sstep)
 {
-    __shared__ WalkLds L[NW];
-    __shared__ double red[NW];
-    __shared__ TieRec rec[2 * NW];
+    static_assert(!kWave || NW == 1, "a wavefront alone walks its item");
     const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
-    const int n_side = a.cnt->n_sidelist;
+    const int wp = kWave ? 0 : part;          // this wavefront's share of the item's walks
+    const int r0 = kWave ? part : 0;          // first reduction slot of the item
     const int64_t n_rec = chk_size(a.bin_start + a.bins_total);
-    if ((n_side <= kSideGroupMax) != (NW > 1)) return;   // the other kernel takes the list
-    for (int si = blockIdx.x; si < n_side; si += gridDim.x) {
+    for (int si = si0; si < n_side; si += sstep) {
         const int item = a.sidelist[si];
         int e;
         const CutInst *cp;
@@ -1069,7 +1083,7 @@ __device__ inline void side_items(const ExactArgs &a)
             int lo[3], hi[3];
             box_bins(G, eb, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
+            walk_faces<kWave>(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
                 if (f >= 0) {
                     if (first_common_bin(G, fb, xyz, lo) && box_overlap(eb, fb) && point_box_dist(p, fb) < u) {
                         const double *P = pnodes + (int64_t)f * 27;
@@ -1083,34 +1097,34 @@ __device__ inline void side_items(const ExactArgs &a)
                 }
                 u = wave_min_d(u);
                 return false;
-            }, part, NW, n_rec, c.n_face, a.err);
+            }, wp, NW, n_rec, c.n_face, a.err);
         }
         u = wave_min_d(u);
         if (lane == 0) red[part] = u;
-        __syncthreads();
-        double U = red[0];
-        for (int k = 1; k < NW; ++k) U = fmin(U, red[k]);
-        __syncthreads();
+        group_sync<kWave>();
+        double U = red[r0];
+        for (int k = 1; k < NW; ++k) U = fmin(U, red[r0 + k]);
+        group_sync<kWave>();
         // stage 2: nearest distance over every face whose box is within U
         double best = U;
         {
             int lo[3], hi[3];
             query_bins(G, p, U, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
+            walk_faces<kWave>(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
                 if (f >= 0) {
                     if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
                         best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
                 }
                 best = wave_min_d(best);
                 return false;
-            }, part, NW, n_rec, c.n_face, a.err);
+            }, wp, NW, n_rec, c.n_face, a.err);
         }
         best = wave_min_d(best);
         if (lane == 0) red[part] = best;
-        __syncthreads();
-        double B = red[0];
-        for (int k = 1; k < NW; ++k) B = fmin(B, red[k]);
+        group_sync<kWave>();
+        double B = red[r0];
+        for (int k = 1; k < NW; ++k) B = fmin(B, red[r0 + k]);
         // stage 3: tie set within B * (1 + 1e-9)
         const double thr = B * (1.0 + 1e-9);
         TieRec b1, b2;
@@ -1119,7 +1133,7 @@ __device__ inline void side_items(const ExactArgs &a)
             int lo[3], hi[3];
             query_bins(G, p, thr, lo, hi);
             const BinRange R = make_range(lo, hi);
-            walk_faces(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
+            walk_faces<kWave>(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
                 if (f >= 0) {
                     if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= thr) {
                         const double *P = pnodes + (int64_t)f * 27;
@@ -1149,29 +1163,43 @@ __device__ inline void side_items(const ExactArgs &a)
                     }
                 }
                 return false;
-            }, part, NW, n_rec, c.n_face, a.err);
+            }, wp, NW, n_rec, c.n_face, a.err);
         }
         tie_wave_first2(b1, b2);
         if (lane == 0) {
             rec[2 * part] = b1;
             rec[2 * part + 1] = b2;
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
+        group_sync<kWave>();
+        if (lane == 0 && part == r0) {
             TieRec c1, c2;
             c1.valid = c2.valid = 0;
-            for (int k = 0; k < 2 * NW; ++k) tie_offer(c1, c2, rec[k]);
+            for (int k = 0; k < 2 * NW; ++k) tie_offer(c1, c2, rec[2 * r0 + k]);
             double sg = c1.dot;
             if (c2.valid && c1.absdot - c2.absdot <= 1e-9 && ((c1.dot > 0.0) != (c2.dot > 0.0)))
                 sg = c1.vx * (c1.nx + c2.nx) + c1.vy * (c1.ny + c2.ny) + c1.vz * (c1.nz + c2.nz);
             if (c1.valid && sg < 0.0) c.iblank[e] = OC_HOLE;
         }
-        __syncthreads();
+        group_sync<kWave>();
     }
 }
 
-__global__ __launch_bounds__(64 * kSideWaves) void k_side_group(ExactArgs a) { side_items<kSideWaves>(a); }
-__global__ __launch_bounds__(64) void k_side_solo(ExactArgs a) { side_items<1>(a); }
+// a5: the side list, in one launch whatever its length (known only on the
+// device): up to kSideGroupMax items the kSideWaves wavefronts of a
+// workgroup share each item (the latency of a few items), beyond that each
+// wavefront takes its own items (throughput when there are many).
+__global__ __launch_bounds__(64 * kSideWaves) void k_side(ExactArgs a)
+{
+    __shared__ WalkLds L[kSideWaves];
+    __shared__ double red[kSideWaves];
+    __shared__ TieRec rec[2 * kSideWaves];
+    const int n_side = a.cnt->n_sidelist;
+    if (n_side <= kSideGroupMax)
+        side_items<kSideWaves, false>(a, n_side, L, red, rec, blockIdx.x, gridDim.x);
+    else
+        side_items<1, true>(a, n_side, L, red, rec, blockIdx.x * kSideWaves + (threadIdx.x >> 6),
+                            gridDim.x * kSideWaves);
+}
 
 // a8: fringe layer (field elements sharing a face with a hole).  Every hole
 // is an in-box item of some cut of its output, so the scatter runs over the
@@ -1536,10 +1564,7 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         ea.bins_total = bin_off;
         ea.err = err;
         LAUNCH(k_hit, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
-        LAUNCH(k_side_group, dim3((unsigned)kSideGroups), dim3(64 * kSideWaves), ea);
-        // a long list, a wavefront per item (a loop, so few blocks: the launch
-        // costs little when the list is short)
-        LAUNCH(k_side_solo, dim3((unsigned)std::min(ctx->exact_waves, 4096)), dim3(64), ea);
+        LAUNCH(k_side, dim3((unsigned)kSideGroups), dim3(64 * kSideWaves), ea);
         LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_inbox, sl->counters);
     }
     if (ov_blk)
