@@ -58,7 +58,7 @@ FP64_VECTOR_PEAK = 78.6        # TFLOP/s, MI355X FP64 vector: 256 CU x 4 SIMD x 
 NEWTON_FLOP = 700
 
 
-KERNEL_SOURCE = {"k_dp_newton": "paper_1711_07663_amd/csrc/k_donor.hip",
+KERNEL_SOURCE = {"k_dp_newton": "paper_1711_07663_amd/csrc/k_donor.hip", "k_dp_count": "paper_1711_07663_amd/csrc/k_donor.hip",
                  "k_filter": "paper_1711_07663_amd/csrc/k_cut.hip"}
 # headers every kernel source includes (their device functions are part of the kernels)
 KERNEL_HEADERS = ["paper_1711_07663_amd/csrc/dev_common.h", "paper_1711_07663_amd/csrc/dev_geom.h",
