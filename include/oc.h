@@ -514,6 +514,10 @@ oc_status oc_timing_report(oc_ctx *ctx, char *buf, int64_t buf_len);
  *                        receptor-point kernel forms the tiles' offsets
  *                        itself from their counts (1 .. 2048, 0 = 2048);
  *                        larger grids take a scan launch for them.
+ *   OC_TUNE_SIDE_LIST    arg unused; value = most faces one wavefront of the
+ *                        side search lists in its second stage for the tie
+ *                        stage (1 .. 64, 0 = 64); an element with more faces
+ *                        within its bound walks the bins again (same result).
  *   OC_TUNE_HBM_BUDGET   arg unused; value = the context's HBM budget in
  *                        bytes (0 = none), as oc_config.hbm_budget; later
  *                        allocations are held to it, memory already held is
@@ -529,7 +533,8 @@ enum {
     OC_TUNE_DONOR_WAVES = 5,
     OC_TUNE_DONOR_PAIRS = 6,
     OC_TUNE_FILTER_BLOCK = 7,
-    OC_TUNE_POINT_TILES = 8
+    OC_TUNE_POINT_TILES = 8,
+    OC_TUNE_SIDE_LIST = 9
 };
 oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t *applied);
 

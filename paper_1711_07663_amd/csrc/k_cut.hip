@@ -809,11 +809,20 @@ struct ExactArgs {
     double *side_u;             // per side-list entry: nearest node of the faces k_hit tested (bound U, or inf)
     int64_t bins_total;         // bins of the batch (bin_start[bins_total] = records)
     uint32_t *err;              // the context's check word (checked builds)
+    int side_cap;               // faces a side-search wavefront lists (<= kSideList)
 };
 
 constexpr int kSideWaves = 8;        // wavefronts sharing one side item's walks (short lists)
 constexpr int kSideGroups = 256;     // their workgroups: one per CU
 constexpr int kSideGroupMax = 512;   // longest list taken that way (two rounds)
+constexpr int kSideList = 64;        // faces a wavefront lists in the side search's second stage
+
+// the faces (id and FP32 box) one wavefront of the side search finds within
+// its item's bound, kept for the tie stage
+struct SideList {
+    int f[kSideList];
+    float b[6][kSideList];
+};
 
 constexpr int kFaceCap = 64;    // one chunk of candidate faces
 constexpr int kGroup = 8;   // candidate faces tested together by k_hit
@@ -1049,11 +1058,12 @@ __device__ inline void tie_wave_first2(TieRec &b1, TieRec &b2)
 
 // The side items si0, si0 + sstep, ... of the list, NW wavefronts per item
 // (kWave: one, synchronising only itself).  Wavefront `part` of the
-// workgroup walks with WalkLds L[part] and reduces through red[part] and
-// rec[2 part], rec[2 part + 1].
+// workgroup walks with WalkLds L[part], lists the faces of its share of the
+// second stage in S[part] (over[part]: they did not fit) and reduces through
+// red[part] and rec[2 part], rec[2 part + 1].
 template <int NW, bool kWave>
-__device__ inline void side_items(const ExactArgs &a, int n_side, WalkLds *L, double *red, TieRec *rec, int si0,
-                                  int sstep)
+__device__ inline void side_items(const ExactArgs &a, int n_side, WalkLds *L, double *red, TieRec *rec,
+                                  SideList *S, int *over, int si0, int sstep)
 {
     static_assert(!kWave || NW == 1, "a wavefront alone walks its item");
     const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
@@ -1105,62 +1115,94 @@ __device__ inline void side_items(const ExactArgs &a, int n_side, WalkLds *L, do
         double U = red[r0];
         for (int k = 1; k < NW; ++k) U = fmin(U, red[r0 + k]);
         group_sync<kWave>();
-        // stage 2: nearest distance over every face whose box is within U
+        // stage 2: nearest distance over every face whose box is within U.
+        // The walk covers the radius Uq a little beyond U, the largest radius
+        // stage 3 can take, and each wavefront lists the faces whose boxes
+        // are within Uq, so that stage 3 reads its faces from the lists
+        // instead of walking the bins again (a face beyond U never lowers
+        // the minimum, so the wider walk leaves B unchanged).
+        const double Uq = U * (1.0 + 4e-9);
         double best = U;
+        int nlist = 0;   // faces listed by this wavefront (the same on every lane)
         {
             int lo[3], hi[3];
-            query_bins(G, p, U, lo, hi);
+            query_bins(G, p, Uq, lo, hi);
             const BinRange R = make_range(lo, hi);
             walk_faces<kWave>(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
-                if (f >= 0) {
-                    if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= best)
-                        best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
+                bool keep = false;
+                if (f >= 0 && first_common_bin(G, fb, xyz, lo)) {
+                    const double bd = point_box_dist(p, fb);
+                    keep = bd <= Uq;
+                    if (bd <= best) best = fmin(best, point_face_dist(p, pnodes + (int64_t)f * 27));
                 }
+                const unsigned long long m = __ballot(keep);
+                if (keep) {
+                    const int at = nlist + __popcll(m & ((1ull << lane) - 1ull));
+                    if (at < a.side_cap) {
+                        S[part].f[at] = f;
+                        for (int k = 0; k < 6; ++k) S[part].b[k][at] = fb[k];
+                    }
+                }
+                nlist += __popcll(m);
                 best = wave_min_d(best);
                 return false;
             }, wp, NW, n_rec, c.n_face, a.err);
         }
         best = wave_min_d(best);
-        if (lane == 0) red[part] = best;
+        if (lane == 0) {
+            red[part] = best;
+            over[part] = nlist > a.side_cap;
+        }
         group_sync<kWave>();
         double B = red[r0];
-        for (int k = 1; k < NW; ++k) B = fmin(B, red[r0 + k]);
+        bool from_lists = !over[r0];
+        for (int k = 1; k < NW; ++k) {
+            B = fmin(B, red[r0 + k]);
+            from_lists = from_lists && !over[r0 + k];
+        }
         // stage 3: tie set within B * (1 + 1e-9)
         const double thr = B * (1.0 + 1e-9);
         TieRec b1, b2;
         b1.valid = b2.valid = 0;
-        {
+        auto tie_face = [&](int f) {
+            const double *P = pnodes + (int64_t)f * 27;
+            for (int s = 0; s < 8; ++s) {
+                d3 F[3];
+                face_tri(P, s, F);
+                const d3 v = p - closest_on_tri(p, F[0], F[1], F[2]);
+                const double d = sqrt(dot(v, v));
+                if (d > thr) continue;
+                const d3 n = cross(F[1] - F[0], F[2] - F[0]);
+                const double ln = sqrt(dot(n, n));
+                TieRec rr;
+                rr.vx = v.x;
+                rr.vy = v.y;
+                rr.vz = v.z;
+                rr.nx = ln > 0 ? n.x / ln : 0.0;
+                rr.ny = ln > 0 ? n.y / ln : 0.0;
+                rr.nz = ln > 0 ? n.z / ln : 0.0;
+                rr.dot = d > 0 ? (v.x * rr.nx + v.y * rr.ny + v.z * rr.nz) / d : 0.0;
+                rr.absdot = fabs(rr.dot);
+                rr.f = f;
+                rr.s = s;
+                rr.valid = 1;
+                rr.pad = 0;
+                tie_offer(b1, b2, rr);
+            }
+        };
+        if (from_lists) {
+            if (lane < nlist) {
+                float fb[6];
+                for (int k = 0; k < 6; ++k) fb[k] = S[part].b[k][lane];
+                if (point_box_dist(p, fb) <= thr) tie_face(S[part].f[lane]);
+            }
+        } else {
             int lo[3], hi[3];
             query_bins(G, p, thr, lo, hi);
             const BinRange R = make_range(lo, hi);
             walk_faces<kWave>(G, R, bstart, a.brec, L[part], [&](int f, const float *fb, const int *xyz) {
                 if (f >= 0) {
-                    if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= thr) {
-                        const double *P = pnodes + (int64_t)f * 27;
-                        for (int s = 0; s < 8; ++s) {
-                            d3 F[3];
-                            face_tri(P, s, F);
-                            const d3 v = p - closest_on_tri(p, F[0], F[1], F[2]);
-                            const double d = sqrt(dot(v, v));
-                            if (d > thr) continue;
-                            const d3 n = cross(F[1] - F[0], F[2] - F[0]);
-                            const double ln = sqrt(dot(n, n));
-                            TieRec rr;
-                            rr.vx = v.x;
-                            rr.vy = v.y;
-                            rr.vz = v.z;
-                            rr.nx = ln > 0 ? n.x / ln : 0.0;
-                            rr.ny = ln > 0 ? n.y / ln : 0.0;
-                            rr.nz = ln > 0 ? n.z / ln : 0.0;
-                            rr.dot = d > 0 ? (v.x * rr.nx + v.y * rr.ny + v.z * rr.nz) / d : 0.0;
-                            rr.absdot = fabs(rr.dot);
-                            rr.f = f;
-                            rr.s = s;
-                            rr.valid = 1;
-                            rr.pad = 0;
-                            tie_offer(b1, b2, rr);
-                        }
-                    }
+                    if (first_common_bin(G, fb, xyz, lo) && point_box_dist(p, fb) <= thr) tie_face(f);
                 }
                 return false;
             }, wp, NW, n_rec, c.n_face, a.err);
@@ -1193,11 +1235,13 @@ __global__ __launch_bounds__(64 * kSideWaves) void k_side(ExactArgs a)
     __shared__ WalkLds L[kSideWaves];
     __shared__ double red[kSideWaves];
     __shared__ TieRec rec[2 * kSideWaves];
+    __shared__ SideList S[kSideWaves];
+    __shared__ int over[kSideWaves];
     const int n_side = a.cnt->n_sidelist;
     if (n_side <= kSideGroupMax)
-        side_items<kSideWaves, false>(a, n_side, L, red, rec, blockIdx.x, gridDim.x);
+        side_items<kSideWaves, false>(a, n_side, L, red, rec, S, over, blockIdx.x, gridDim.x);
     else
-        side_items<1, true>(a, n_side, L, red, rec, blockIdx.x * kSideWaves + (threadIdx.x >> 6),
+        side_items<1, true>(a, n_side, L, red, rec, S, over, blockIdx.x * kSideWaves + (threadIdx.x >> 6),
                             gridDim.x * kSideWaves);
 }
 
@@ -1563,6 +1607,7 @@ oc_status cut_batch_run(oc_slot *sl, const CutReq *reqs, int n_req)
         ea.side_u = sl->l_sideu;
         ea.bins_total = bin_off;
         ea.err = err;
+        ea.side_cap = std::min(ctx->side_list, kSideList);
         LAUNCH(k_hit, dim3((unsigned)ctx->exact_waves), dim3(64), ea);
         LAUNCH(k_side, dim3((unsigned)kSideGroups), dim3(64 * kSideWaves), ea);
         LAUNCH(k_fringe, dim3(1024), dim3(kThreads), sl->insts, sl->l_inbox, sl->counters);

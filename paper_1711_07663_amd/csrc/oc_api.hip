@@ -1681,6 +1681,8 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
             v = ctx->filter_block;
         } else if (knob == OC_TUNE_POINT_TILES) {
             v = ctx->point_tiles;
+        } else if (knob == OC_TUNE_SIDE_LIST) {
+            v = ctx->side_list;
         } else if (knob == OC_TUNE_HBM_BUDGET) {
             v = ctx->budget;
         } else {
@@ -1741,6 +1743,13 @@ oc_status oc_tune(oc_ctx *ctx, int32_t knob, int32_t arg, int64_t value, int64_t
         }
         ctx->point_tiles = value == 0 ? 2048 : (int)value;
         v = ctx->point_tiles;
+    } else if (knob == OC_TUNE_SIDE_LIST) {
+        if (value < 0 || value > 64) {
+            set_error("oc_tune: side list out of range (0 .. 64)");
+            return OC_EINVAL;
+        }
+        ctx->side_list = value == 0 ? 64 : (int)value;
+        v = ctx->side_list;
     } else if (knob == OC_TUNE_HBM_BUDGET) {
         if (value < 0) {
             set_error("oc_tune: negative budget");

@@ -235,6 +235,7 @@ struct oc_ctx {
     int surf_bins = 0;
     int exact_waves = 8192;                // persistent wavefronts of the exact-stage kernels
     int filter_block = 256;                // threads per block of the element-box filter
+    int side_list = 64;                    // faces a side-search wavefront lists for the tie stage
     int point_tiles = 2048;                // most fringe tiles whose offsets the point kernel forms
     std::vector<std::pair<int, double>> bin_factor;   // tuned bins factor per face-count octave
     int donor_waves = 0;                   // cap on the donor-search wavefronts (0 = none)

@@ -30,6 +30,7 @@ OC_TUNE_SURF_BINS, OC_TUNE_EXACT_WAVES, OC_TUNE_SERVICE_SLOTS, OC_TUNE_HBM_BUDGE
 OC_TUNE_DONOR_PAIRS = 6
 OC_TUNE_FILTER_BLOCK = 7
 OC_TUNE_POINT_TILES = 8
+OC_TUNE_SIDE_LIST = 9
 
 EXPORTS = ["oc_create", "oc_destroy", "oc_last_error", "oc_set_stream", "oc_register_grid",
            "oc_register_cut_surface", "oc_cut", "oc_cut_multi", "oc_last_cut_info", "oc_fringe_points",

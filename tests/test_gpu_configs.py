@@ -224,3 +224,37 @@ def test_cut_far_from_origin(orc):
     want = orc.cut(bg, [s], [pose])
     assert np.array_equal(got, want)
     assert (want == orc.HOLE).sum() > 50
+
+
+def test_side_list_and_bin_walk_agree(orc):
+    """The tie stage of the side search reads the faces its wavefronts listed
+    in the second stage; with the lists capped at one face
+    (OC_TUNE_SIDE_LIST) an element with more faces within its bound walks the
+    bins again.  Both give the oracle's iblank."""
+    import torch
+    from paper_1711_07663_amd import oc
+    _note("side search: face lists against the bin walk (48^3, m 16, 60 dimples)")
+    bg = M.background_grid(48, -1.2, 1.2, amp=0.02)
+    s = M.cube_sphere(16, R=0.5, dimples=60, dimple_a=CF.DIMPLE_A, dimple_k=CF.DIMPLE_K)
+    pose = np.asarray(M.random_pose(np.random.default_rng(4471), 0.2), dtype=np.float64)
+    ctx = _ctx()
+    got, infos = {}, {}
+    try:
+        gid = ctx.register_grid(bg.nodes, bg.conn)
+        sid = ctx.register_cut_surface(s.nodes, s.conn)
+        for cap in (1, 0):
+            assert ctx.tune(oc.OC_TUNE_SIDE_LIST, 0, cap) == (cap or 64)
+            ib = torch.empty(bg.n_elem, dtype=torch.int8, device="cuda")
+            ctx.cut_batch([(gid, [sid], pose.reshape(1, 12), ib)])
+            infos[cap] = ctx.last_cut_info()
+            got[cap] = ib.cpu().numpy()
+        assert ctx.tune(oc.OC_TUNE_SIDE_LIST, 0, -1) == 64
+    finally:
+        torch.cuda.synchronize()
+        ctx.close()
+    _note("cut info %s" % infos[0])
+    assert infos[0]["n_side"] > 0, "the side search must run on this case"
+    want = PU.band_cut(bg, [s], [pose])
+    for cap in (1, 0):
+        bad = np.nonzero(got[cap] != want)[0]
+        assert bad.size == 0, "side list cap %d: %d elements differ, first %s" % (cap, bad.size, bad[:8])
