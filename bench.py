@@ -65,9 +65,19 @@ KERNEL_HEADERS = ["paper_1711_07663_amd/csrc/dev_common.h", "paper_1711_07663_am
                   "paper_1711_07663_amd/csrc/q2.h", "paper_1711_07663_amd/csrc/oc_internal.h", "include/oc.h"]
 
 
+def _code_only(text):
+    """C/C++ source with its comments removed and its whitespace collapsed, so
+    that an edit of a comment does not count as a change of the code."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_sha(kernel):
-    """SHA-256 of everything ``kernel`` is compiled from: its source file and
-    the shared headers (so a change to a device function it calls counts)."""
+    """SHA-256 of the code ``kernel`` is compiled from, comments aside: its
+    source file and the shared headers (so a change to a device function it
+    calls counts)."""
     import hashlib
     src = KERNEL_SOURCE.get(kernel)
     if not src:
@@ -77,7 +87,7 @@ def kernel_source_sha(kernel):
         path = f if os.path.isabs(f) else os.path.join(ROOT, f)
         if not os.path.exists(path):
             return None
-        h.update(open(path, "rb").read())
+        h.update(_code_only(open(path, encoding="utf-8").read()).encode())
     return h.hexdigest()
 
 

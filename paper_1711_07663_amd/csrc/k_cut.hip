@@ -1010,13 +1010,14 @@ __global__ __launch_bounds__(64) void k_hit(ExactArgs a)
 // tie rule (largest |dot| of the unit point-to-surface vector with the
 // outward triangle normal; normals averaged only for equally visible
 // triangles of opposite sign).  Per element of the list k_hit leaves, three
-// stages that meet in LDS (or in registers, with one wavefront): an upper
-// bound U (the nearest node of the element's candidate faces), the nearest
-// distance over the faces within U, and the two first records of the tie
-// set in tie order.  In every stage each of the NW wavefronts takes every
-// NW-th chunk of the stage's bin walk.  The stages compute a
-// minimum over an exact set and the first two records of a total order, so
-// the split among wavefronts does not change any bit.
+// stages that meet in LDS: an upper bound U (the nearest node of the
+// element's candidate faces), the nearest distance over the faces within U,
+// and the two first records of the tie set in tie order, taken from the
+// faces the second stage listed (a bin walk of its own only when a list
+// overflowed).  In every walk each of the NW wavefronts takes every NW-th
+// chunk of the stage's bins.  The stages compute a minimum over an exact set
+// and the first two records of a total order, so neither the split among
+// wavefronts nor the order of the listed faces changes any bit.
 __device__ inline void side_item(const ExactArgs &a, int item, int &e, const CutInst *&cp, d3 &p)
 {
     const uint64_t it = a.list_inbox[item];
