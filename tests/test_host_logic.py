@@ -181,16 +181,23 @@ def test_bench_traffic_follows_kernel_source(tmp_path, monkeypatch):
         assert bench.kernel_source_sha(k) is not None
         t = bench.measured_traffic(k)
         assert t is None or t > 1e6
-    # a changed definition makes the stored traffic stale
-    src = tmp_path / "k.hip"
+    # an edited comment or spacing leaves the code, and the stored traffic, as
+    # they were; a changed definition makes the stored traffic stale
     text = open(os.path.join(ROOT, bench.KERNEL_SOURCE["k_filter"])).read()
+    assert "// a3, streaming part" in text and "int flags = 0, cn = 0;" in text
+    t0 = bench.measured_traffic("k_filter")
+    src = tmp_path / "k.hip"
     src.write_text(text.replace("// a3, streaming part", "// a3 (edited), streaming part", 1)
-                   .replace("const int write_field = c.write_field;", "const int write_field = c.write_field;  "))
+                   .replace("int flags = 0, cn = 0;", "int flags = 0,  cn = 0;", 1))
     monkeypatch.setitem(bench.KERNEL_SOURCE, "k_filter", str(src))
+    assert bench.measured_traffic("k_filter") == t0
+    src2 = tmp_path / "k2.hip"
+    src2.write_text(text.replace("int flags = 0, cn = 0;", "int flags = 0, cn = 1;", 1))
+    monkeypatch.setitem(bench.KERNEL_SOURCE, "k_filter", str(src2))
     assert bench.measured_traffic("k_filter") is None
     # so does a change to a device function in a shared header
     hdr = tmp_path / "q2.h"
-    hdr.write_text(open(os.path.join(ROOT, "paper_1711_07663_amd/csrc/q2.h")).read() + "\n// edited\n")
+    hdr.write_text(open(os.path.join(ROOT, "paper_1711_07663_amd/csrc/q2.h")).read() + "\n#define OC_EDITED 1\n")
     monkeypatch.setattr(bench, "KERNEL_HEADERS", [str(hdr) if h.endswith("q2.h") else h for h in bench.KERNEL_HEADERS])
     assert bench.measured_traffic("k_dp_newton") is None
 
